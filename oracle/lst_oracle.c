@@ -1,0 +1,1264 @@
+/*
+ * CPU oracle for the Line Segment Tracking object-building chain
+ * (arXiv:2207.08207, Sections 2.1-2.5).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only tests, the smoke check and the benchmark's
+ * CPU-baseline leg may load this library.  It shares no code with the HIP
+ * library; both read the same synthetic inputs.
+ *
+ * Plain serial loops, written in the order the paper builds objects:
+ *   hits -> mini-doublets (MD, 2 hits, Section 2.2)
+ *        -> line segments (LS, two MDs linked by the module map, Section 2.2)
+ *        -> triplets (T3, two LS sharing an MD, r-z line chi2, Section 2.3)
+ *        -> quintuplets (T5, two T3 sharing an MD, radius compatibility,
+ *           5-anchor circle-fit chi2, r-z pointing, Section 2.3)
+ *        -> pixel line segments (pLS, one per seed, Section 2.4)
+ *        -> pixel triplets / quintuplets (pT3 / pT5, Section 2.4)
+ *        -> duplicate removal and cross-cleaning into track candidates
+ *           in the order pT5, pT3, T5, pLS (Section 2.5).
+ * The paper prints no cut formula or value; the selections below are this
+ * project's reading of each passage (each predicate's comment says which).
+ *
+ * Arithmetic: `real` is float (compile default: the FP32 oracle) or double
+ * (-DORACLE_F64: the FP64 shadow).  Build with -O2 -ffp-contract=off and no
+ * fast-math: every + - * / sqrt is one correctly rounded IEEE operation, in the
+ * parenthesised order written here.  Per-module window constants are computed
+ * once in double (asin by its Maclaurin series, which uses only + * /) and
+ * rounded to `real`.
+ *
+ * Stage ids: 0 MD, 1 LS, 2 T3, 3 T5, 4 pLS, 5 pT3, 6 pT5, 7 TC.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef ORACLE_F64
+typedef double real;
+#define RSQRT_(x) sqrt(x)
+#else
+typedef float real;
+#define RSQRT_(x) sqrtf(x)
+#endif
+#define RL(x) ((real)(x))
+#define RABS(x) ((x) < RL(0) ? -(x) : (x))
+
+/* ------------------------------------------------------------------ constants */
+/* B = 3.8 T: |kappa| [1/cm] = K / pT [GeV]; pT threshold 0.8 GeV (Section 2.2). */
+static const double K_CURV = 0.299792458 * 3.8 / 100.0;
+static const double PT_MIN = 0.8;
+static const double Z_LUM = 20.0;   /* luminous-region half length [cm] */
+static const double D0_MAX = 0.1;   /* transverse impact parameter bound [cm] */
+/* Half pitches per module type (0 PS, 1 2S): r-phi and long coordinate [cm]. */
+static const double H_PHI[2] = {0.005, 0.0045};
+static const double H_LONG[2] = {0.075, 2.5};
+static const double TAU = 0.8;      /* sin bound of the track-to-radial angle (endcap xy error) */
+/* Cut values (chi2 in units of half-pitch errors). */
+static const double X_T3 = 10.0;
+static const double X_T5XY = 20.0;
+static const double X_T5RZ = 20.0;
+static const double X_PXY[2] = {50.0, 80.0};   /* pT3, pT5 */
+static const double X_PRZ[2] = {50.0, 80.0};
+static const double B_XY = 1.0;                /* pLS-object window in x-y [cm] */
+static const double B_Z0 = 3.0;                /* pLS-object window in z, base [cm] */
+static const double SEED_DPT = 0.02;           /* seed curvature resolution (relative) */
+static const double SEED_DDIR = 0.001;         /* seed direction resolution [rad] */
+static const double D_PT3 = 0.02, D_T5 = 0.02, D_PLS = 0.05;  /* eta-phi proximity */
+static const double X_SERIES_MAX = 0.7;        /* validity bound of the arc-length series */
+static const double BORDER_REL = 1e-6;         /* borderline band, relative */
+
+enum { ST_MD = 0, ST_LS, ST_T3, ST_T5, ST_PLS, ST_PT3, ST_PT5, ST_TC, N_ST };
+static const int TUPLE_W[N_ST] = {2, 4, 6, 10, 1, 7, 11, 0};
+static const int ATTR_W[N_ST] = {0, 2, 4, 8, 5, 3, 3, 0};
+
+/* ------------------------------------------------------------- growable arrays */
+typedef struct { int *p; size_t n, cap; } ivec;
+typedef struct { real *p; size_t n, cap; } rvec;
+static void iv_push(ivec *v, int x) {
+  if (v->n == v->cap) { v->cap = v->cap ? 2 * v->cap : 1024; v->p = (int *)realloc(v->p, v->cap * sizeof(int)); }
+  v->p[v->n++] = x;
+}
+static void rv_push(rvec *v, real x) {
+  if (v->n == v->cap) { v->cap = v->cap ? 2 * v->cap : 1024; v->p = (real *)realloc(v->p, v->cap * sizeof(real)); }
+  v->p[v->n++] = x;
+}
+static void iv_free(ivec *v) { free(v->p); v->p = NULL; v->n = v->cap = 0; }
+static void rv_free(rvec *v) { free(v->p); v->p = NULL; v->n = v->cap = 0; }
+
+/* -------------------------------------------------------------------- geometry */
+typedef struct {
+  int n_mod, n_edges;
+  int *subdet, *layer, *side, *type;
+  double *pos_lo, *pos_up, *lmin, *lmax;
+  int *map_off, *map_tgt;
+  real *W, *A1, *A2, *A3;      /* per-module MD window constants */
+  double *Wd, *A1d, *A2d, *A3d;
+} orc_geom;
+
+/* asin(x) for |x| <= 0.85 from its Maclaurin series, summed in a fixed order
+ * with + * / only: sum_n c_n x^(2n+1), c_{n+1} = c_n (2n+1)^2 / ((2n+2)(2n+3)). */
+static double ser_asin(double x) {
+  double x2 = x * x, term = x, sum = x;
+  for (int n = 0; n < 200; ++n) {
+    term = term * x2;
+    term = term * (double)((2 * n + 1) * (2 * n + 1));
+    term = term / (double)((2 * n + 2) * (2 * n + 3));
+    sum = sum + term;
+  }
+  return sum;
+}
+
+/* Mini-doublet windows of one module (Section 2.2: the two hits of a pT module
+ * must have the slope of a track from the luminous region with pT above
+ * threshold, widened by the pitch and impact-parameter error terms).
+ *   W : bound on |sin| of the azimuth difference between the two hits;
+ *   PS barrel : |z_up - A1 z_lo| <= A2 + A3 |z_lo|;
+ *   PS endcap : -A2 <= r_up - r_lo <= A1 r_lo + A2.
+ * Derivation: for a helix from the beam line the hit azimuth is
+ * phi0 + asin(kappa r / 2) and z is linear in the transverse arc length
+ * s(r) = 2 asin(kappa r / 2) / kappa, with |kappa| <= kappa_max. */
+static void module_constants(int sd, int ty, double p_lo, double p_up, double l_min, double l_max,
+                             double out[4]) {
+  const double km = K_CURV / PT_MIN;
+  const double hp = H_PHI[ty], hl = H_LONG[ty];
+  double W, A1 = 0.0, A2 = 0.0, A3 = 0.0;
+  if (sd == 0) {
+    double r1 = p_lo, r2 = p_up;
+    double a1 = ser_asin(km * r1 / 2.0), a2 = ser_asin(km * r2 / 2.0);
+    double dphi = (a2 - a1) + D0_MAX * (1.0 / r1 - 1.0 / r2) + hp / r1 + hp / r2;
+    W = dphi * (1.0 + 1e-3) + 1e-6;
+    if (ty == 0) {
+      double a = r2 / r1;
+      double s1 = 2.0 * a1 / km, s2 = 2.0 * a2 / km;
+      double ap = s2 / s1;
+      A1 = a;
+      A2 = ((ap - 1.0) * Z_LUM + hl * (1.0 + a) + (ap - a) * hl) * (1.0 + 1e-3);
+      A3 = (ap - a) * (1.0 + 1e-3);
+    }
+  } else {
+    double z1 = p_lo, z2 = p_up, rmin = l_min, rmax = l_max;
+    double xg = km * (rmax + hl) / 2.0;
+    double gmax = ser_asin(xg) / xg;
+    double k = (z2 - z1) * gmax / (z1 - Z_LUM);
+    double b1 = ser_asin(km * rmax / 2.0), b2 = ser_asin(km * rmax * (1.0 + k) / 2.0);
+    double dphi = (b2 - b1) + D0_MAX * k / rmin + 2.0 * hp / rmin;
+    W = dphi * (1.0 + 1e-3) + 1e-6;
+    if (ty == 0) {
+      A1 = k * (1.0 + 1e-3);
+      A2 = (2.0 * hl + k * hl) * (1.0 + 1e-3);
+    }
+  }
+  out[0] = W; out[1] = A1; out[2] = A2; out[3] = A3;
+}
+
+void *orc_geom_create(int n_mod, const int *subdet, const int *layer, const int *side, const int *type,
+                      const float *pos_lo, const float *pos_up, const float *lmin, const float *lmax,
+                      int n_edges, const int *map_off, const int *map_tgt) {
+  orc_geom *g = (orc_geom *)calloc(1, sizeof(orc_geom));
+  g->n_mod = n_mod; g->n_edges = n_edges;
+#define CP_I(dst, src, n) do { dst = (int *)malloc(sizeof(int) * (size_t)(n) + 4); memcpy(dst, src, sizeof(int) * (size_t)(n)); } while (0)
+  CP_I(g->subdet, subdet, n_mod); CP_I(g->layer, layer, n_mod); CP_I(g->side, side, n_mod); CP_I(g->type, type, n_mod);
+  CP_I(g->map_off, map_off, n_mod + 1); CP_I(g->map_tgt, map_tgt, n_edges);
+#undef CP_I
+  g->pos_lo = (double *)malloc(sizeof(double) * n_mod); g->pos_up = (double *)malloc(sizeof(double) * n_mod);
+  g->lmin = (double *)malloc(sizeof(double) * n_mod); g->lmax = (double *)malloc(sizeof(double) * n_mod);
+  g->W = (real *)malloc(sizeof(real) * n_mod); g->A1 = (real *)malloc(sizeof(real) * n_mod);
+  g->A2 = (real *)malloc(sizeof(real) * n_mod); g->A3 = (real *)malloc(sizeof(real) * n_mod);
+  g->Wd = (double *)malloc(sizeof(double) * n_mod); g->A1d = (double *)malloc(sizeof(double) * n_mod);
+  g->A2d = (double *)malloc(sizeof(double) * n_mod); g->A3d = (double *)malloc(sizeof(double) * n_mod);
+  for (int m = 0; m < n_mod; ++m) {
+    double c[4];
+    g->pos_lo[m] = pos_lo[m]; g->pos_up[m] = pos_up[m]; g->lmin[m] = lmin[m]; g->lmax[m] = lmax[m];
+    module_constants(subdet[m], type[m], pos_lo[m], pos_up[m], lmin[m], lmax[m], c);
+    g->Wd[m] = c[0]; g->A1d[m] = c[1]; g->A2d[m] = c[2]; g->A3d[m] = c[3];
+    g->W[m] = (real)c[0]; g->A1[m] = (real)c[1]; g->A2[m] = (real)c[2]; g->A3[m] = (real)c[3];
+  }
+  return g;
+}
+
+void orc_geom_free(void *gp) {
+  orc_geom *g = (orc_geom *)gp;
+  if (!g) return;
+  free(g->subdet); free(g->layer); free(g->side); free(g->type); free(g->map_off); free(g->map_tgt);
+  free(g->pos_lo); free(g->pos_up); free(g->lmin); free(g->lmax);
+  free(g->W); free(g->A1); free(g->A2); free(g->A3); free(g->Wd); free(g->A1d); free(g->A2d); free(g->A3d);
+  free(g);
+}
+
+/* Per-module constants as computed here (4 per module: W, A1, A2, A3), in real. */
+void orc_module_consts(void *gp, real *out) {
+  orc_geom *g = (orc_geom *)gp;
+  for (int m = 0; m < g->n_mod; ++m) {
+    out[4 * m] = g->W[m]; out[4 * m + 1] = g->A1[m]; out[4 * m + 2] = g->A2[m]; out[4 * m + 3] = g->A3[m];
+  }
+}
+void orc_module_consts_f64(void *gp, double *out) {
+  orc_geom *g = (orc_geom *)gp;
+  for (int m = 0; m < g->n_mod; ++m) {
+    out[4 * m] = g->Wd[m]; out[4 * m + 1] = g->A1d[m]; out[4 * m + 2] = g->A2d[m]; out[4 * m + 3] = g->A3d[m];
+  }
+}
+
+/* ----------------------------------------------------------------- event state */
+typedef struct {
+  int n_hits, n_seeds;
+  real *x, *y, *z, *r;
+  const int *module, *sensor;
+  /* objects */
+  ivec md_lo, md_up, md_mod;            /* MD: input hit indices of lower / upper hit, module */
+  int *md_first;                         /* per module: first MD index (n_mod + 1) */
+  ivec ls_in, ls_out; rvec ls_attr;     /* LS: inner / outer MD; beta_in, beta_out */
+  int *ls_first;                         /* per MD: first LS with that inner MD (n_md + 1) */
+  ivec t3_ls1, t3_ls2; rvec t3_attr;    /* T3: kappa, dkappa, chi2_rz, lambda */
+  int *t3_first;                         /* per MD: first T3 whose first MD it is (n_md + 1) */
+  ivec t5_in, t5_out; rvec t5_attr;     /* T5: kappa5, chi2_xy, chi2_rz, lambda5, k_in, k_out, dir x, dir y */
+  ivec t5_keep;
+  rvec pls_attr;                         /* pLS: pT, cx, cy, lambda, kappa (+ P0 from hits) */
+  ivec pt3_seed, pt3_obj, pt3_keep; rvec pt3_attr;   /* chi2_xy, chi2_rz, score */
+  ivec pt5_seed, pt5_obj, pt5_keep; rvec pt5_attr;
+  ivec pls_keep;
+  ivec tc_type, tc_obj, tc_off, tc_hits;
+  ivec border[N_ST], border_acc[N_ST];
+  const int *q, *hits4;
+  const float *px, *py, *pz;
+  int status;
+} orc_event;
+
+/* Borderline bookkeeping (a candidate is borderline when no cut fails by more
+ * than BORDER_REL relative and at least one cut is within that band). */
+typedef struct { int firm_fail, near; } cutacc;
+static int cut_le(cutacc *a, real q, real cut, real scale) {
+  /* returns q <= cut, records nearness */
+  real d = q - cut;
+  real m = RABS(q);
+  if (RABS(cut) > m) m = RABS(cut);
+  if (scale > m) m = scale;
+  int near = RABS(d) <= (real)BORDER_REL * m;
+  int pass = q <= cut;
+  if (near) a->near = 1;
+  else if (!pass) a->firm_fail = 1;
+  return pass;
+}
+static int cut_gt(cutacc *a, real q, real lo, real scale) {
+  /* returns q > lo */
+  real d = q - lo;
+  real m = RABS(q);
+  if (RABS(lo) > m) m = RABS(lo);
+  if (scale > m) m = scale;
+  int near = RABS(d) <= (real)BORDER_REL * m;
+  int pass = q > lo;
+  if (near) a->near = 1;
+  else if (!pass) a->firm_fail = 1;
+  return pass;
+}
+
+static void record_border(orc_event *e, int st, const int *tuple, int w, int accepted, cutacc *a) {
+  if (a->firm_fail || !a->near) return;
+  for (int i = 0; i < w; ++i) iv_push(&e->border[st], tuple[i]);
+  iv_push(&e->border_acc[st], accepted);
+}
+
+/* anchor of an MD = its lower-sensor hit (Section 2.3 anchor-hit reading) */
+#define AX(md) (e->x[e->md_lo.p[md]])
+#define AY(md) (e->y[e->md_lo.p[md]])
+#define AZ(md) (e->z[e->md_lo.p[md]])
+#define AR(md) (e->r[e->md_lo.p[md]])
+#define AMOD(md) (e->md_mod.p[md])
+
+static real hphi_of(const orc_geom *g, int m) { return (real)H_PHI[g->type[m]]; }
+static real hlong_of(const orc_geom *g, int m) { return (real)H_LONG[g->type[m]]; }
+static int endcap_of(const orc_geom *g, int m) { return g->subdet[m] == 1; }
+/* transverse (x-y) position error of an anchor */
+static real sig_t(const orc_geom *g, int m) {
+  return endcap_of(g, m) ? hphi_of(g, m) + (real)TAU * hlong_of(g, m) : hphi_of(g, m);
+}
+/* z error of an anchor for a track of slope lam = dz/ds */
+static real sig_z(const orc_geom *g, int m, real lam) {
+  return endcap_of(g, m) ? hlong_of(g, m) * RABS(lam) + RL(0.01) : hlong_of(g, m);
+}
+/* asin(x)/x by its Maclaurin series truncated after x^8 (a lower bound of it) */
+static real g4(real x) {
+  real x2 = x * x;
+  return RL(1) + x2 * ((real)(1.0 / 6.0) + x2 * ((real)0.075 + x2 * ((real)(5.0 / 112.0) + x2 * (real)(35.0 / 1152.0))));
+}
+
+/* --------------------------------------------------------------- MD predicate */
+/* Section 2.2: a mini-doublet is a lower/upper hit pair in one pT module whose
+ * azimuth change and (PS modules) z or r change are those of a track from the
+ * luminous region above the pT threshold, within pitch and impact-parameter
+ * error terms.  Window constants: module_constants(). */
+static int md_select(const orc_geom *g, orc_event *e, int m, int i, int j, cutacc *a) {
+  real xi = e->x[i], yi = e->y[i], zi = e->z[i], ri = e->r[i];
+  real xj = e->x[j], yj = e->y[j], zj = e->z[j], rj = e->r[j];
+  real c = xi * yj - yi * xj;
+  real d = xi * xj + yi * yj;
+  int ok = d > RL(0);
+  if (!ok) { a->firm_fail = 1; return 0; }
+  real cut = g->W[m] * (ri * rj);
+  ok = cut_le(a, RABS(c), cut, RL(0));
+  if (g->type[m] == 0) {
+    if (g->subdet[m] == 0) {
+      real t = zj - g->A1[m] * zi;
+      ok &= cut_le(a, RABS(t), g->A2[m] + g->A3[m] * RABS(zi), RL(0));
+    } else {
+      real dr = rj - ri;
+      ok &= cut_le(a, -dr, g->A2[m], RL(0));
+      ok &= cut_le(a, dr, g->A1[m] * ri + g->A2[m], RL(0));
+    }
+  }
+  return ok;
+}
+
+/* --------------------------------------------------------------- LS predicate */
+/* Section 2.2: two MDs in modules linked by the module map form a segment if
+ * (x-y) their azimuth change fits a track from the beam line with pT above
+ * threshold and (r-z) the line through the two anchors, corrected for the
+ * helix's arc length, points back to the luminous region. */
+static int ls_select(const orc_geom *g, orc_event *e, int a_md, int b_md, real *beta_in, real *beta_out,
+                     cutacc *ac) {
+  int ma = AMOD(a_md), mb = AMOD(b_md);
+  real xa = AX(a_md), ya = AY(a_md), za = AZ(a_md), ra = AR(a_md);
+  real xb = AX(b_md), yb = AY(b_md), zb = AZ(b_md), rb = AR(b_md);
+  real dr = rb - ra;
+  int ok = cut_gt(ac, dr, RL(0), rb);
+  if (!ok) return 0;
+  real ea = endcap_of(g, ma) ? hlong_of(g, ma) : RL(0);
+  real eb = endcap_of(g, mb) ? hlong_of(g, mb) : RL(0);
+  const real kh = (real)(K_CURV / PT_MIN / 2.0);
+  /* x-y */
+  real c = xa * yb - ya * xb;
+  real d = xa * xb + ya * yb;
+  if (!(d > RL(0))) { ac->firm_fail = 1; return 0; }
+  real ub = kh * (rb + eb);
+  real ua = kh * (ra - ea);
+  real w = (ub - ua) / RSQRT_(RL(1) - ub * ub) + ((real)D0_MAX * dr) / (ra * rb) + hphi_of(g, ma) / ra +
+           hphi_of(g, mb) / rb;
+  real W = w * (real)1.001 + (real)1e-6;
+  ok &= cut_le(ac, RABS(c), W * (ra * rb), RL(0));
+  /* r-z: z0 of the chord for arc-length ratios t = s_A / s_B in [t_lo, t_hi] */
+  real xa_ = kh * ra, xb_ = kh * rb;
+  real xb2 = xb_ * xb_;
+  real x10 = xb2 * xb2;
+  x10 = x10 * x10 * xb2;
+  real ghi = g4(xb_) + ((real)(63.0 / 2816.0) * x10) / (RL(1) - xb2);
+  real t_hi = ra / rb;
+  real t_lo = (ra * g4(xa_)) / (rb * ghi);
+  real z0a = (za - t_lo * zb) / (RL(1) - t_lo);
+  real z0b = (za - t_hi * zb) / (RL(1) - t_hi);
+  real zmin = z0a < z0b ? z0a : z0b;
+  real zmax = z0a < z0b ? z0b : z0a;
+  real Ez = ((endcap_of(g, ma) ? RL(0) : hlong_of(g, ma)) + t_hi * (endcap_of(g, mb) ? RL(0) : hlong_of(g, mb))) /
+            (RL(1) - t_hi);
+  real dz = zb - za;
+  real Er = ((rb * ea + ra * eb) * RABS(dz)) / (dr * dr);
+  real L = ((real)Z_LUM + (Ez + Er)) * (real)1.001;
+  ok &= cut_le(ac, zmin, L, RL(0));
+  ok &= cut_le(ac, -zmax, L, RL(0));
+  /* stub directions (Section 1: the hit pair of a pT module measures the local
+   * track direction).  For the circle through the beam line, A and B, the
+   * direction at A makes with the position vector of A the angle the chord
+   * makes at B, and vice versa; each MD's tangential displacement between its
+   * two hits must match that prediction. */
+  real sx = xb - xa, sy = yb - ya;
+  real Ls = RSQRT_(sx * sx + sy * sy);
+  real sb_out = (xb * sy - yb * sx) / (rb * Ls);
+  real sb_in = (xa * sy - ya * sx) / (ra * Ls);
+  real dzab = RABS(dz);
+  real ea2 = endcap_of(g, ma) ? hlong_of(g, ma) : hphi_of(g, ma);
+  real eb2 = endcap_of(g, mb) ? hlong_of(g, mb) : hphi_of(g, mb);
+  real eang = (ea2 + eb2) / Ls;
+  for (int side = 0; side < 2; ++side) {
+    int md = side ? b_md : a_md, m = side ? mb : ma;
+    real sb = side ? sb_in : sb_out, rp = side ? rb : ra;
+    int i = e->md_lo.p[md], j = e->md_up.p[md];
+    real tau = (e->x[i] * e->y[j] - e->y[i] * e->x[j]) / e->r[i];
+    real pred, err;
+    if (!endcap_of(g, m)) {
+      real dl = e->r[j] - e->r[i];
+      real cs2 = RL(1) - sb * sb;
+      if (!(cs2 > RL(0))) { ac->firm_fail = 1; return 0; }
+      pred = (dl * sb) / RSQRT_(cs2);
+      err = RL(2) * hphi_of(g, m) + (RL(2) * dl) * (eang + (real)D0_MAX / rp);
+    } else {
+      if (!(dzab > RL(0))) { ac->firm_fail = 1; return 0; }
+      real dl = RABS(e->z[j]) - RABS(e->z[i]);
+      real ds = (dl * Ls) / dzab;
+      pred = ds * sb;
+      err = (RL(2) * hphi_of(g, m) + (real)0.03 * RABS(pred)) + ds * (eang + (real)D0_MAX / rp);
+    }
+    real dt = tau - pred;
+    ok &= cut_le(ac, RABS(dt), err * (real)1.001 + (real)1e-6, RL(0));
+  }
+  /* reported attributes: angle of the segment to the radial direction at each end */
+#ifdef ORACLE_F64
+  *beta_in = atan2(xa * sy - ya * sx, xa * sx + ya * sy);
+  *beta_out = atan2(xb * sy - yb * sx, xb * sx + yb * sy);
+#else
+  *beta_in = atan2f(xa * sy - ya * sx, xa * sx + ya * sy);
+  *beta_out = atan2f(xb * sy - yb * sx, xb * sx + yb * sy);
+#endif
+  return ok;
+}
+
+/* weighted straight-line fit z = alpha + lambda s over n points (fixed order);
+ * returns chi2 and the slope */
+static real line_fit(int n, const real *s, const real *z, const real *w, real *lam_out) {
+  real S = RL(0), Ss = RL(0), Sz = RL(0);
+  for (int i = 0; i < n; ++i) { S = S + w[i]; Ss = Ss + w[i] * s[i]; Sz = Sz + w[i] * z[i]; }
+  real sbar = Ss / S, zbar = Sz / S;
+  real Sss = RL(0), Ssz = RL(0);
+  for (int i = 0; i < n; ++i) {
+    real ds = s[i] - sbar, dz = z[i] - zbar;
+    Sss = Sss + w[i] * ds * ds;
+    Ssz = Ssz + w[i] * ds * dz;
+  }
+  real lam = Ssz / Sss;
+  real chi2 = RL(0);
+  for (int i = 0; i < n; ++i) {
+    real r = (z[i] - zbar) - lam * (s[i] - sbar);
+    chi2 = chi2 + w[i] * r * r;
+  }
+  *lam_out = lam;
+  return chi2;
+}
+
+/* Azimuth linear in z (Sections 2.3): for a helix from the beam line the hit
+ * azimuth and z both advance linearly with the arc length, so for anchors
+ * P, Q, R: sin(phiQ - phiP) (zR - zQ) = sin(phiR - phiQ) (zQ - zP) up to the
+ * sine's curvature, the pitch and z errors and the impact-parameter term.
+ * It is the constraint that survives the coarse radius of endcap strip hits. */
+static int phiz_test(const orc_geom *g, orc_event *e, int mp, int mq, int mr, cutacc *ac) {
+  real xP = AX(mp), yP = AY(mp), zP = AZ(mp), rP = AR(mp);
+  real xQ = AX(mq), yQ = AY(mq), zQ = AZ(mq), rQ = AR(mq);
+  real xR = AX(mr), yR = AY(mr), zR = AZ(mr), rR = AR(mr);
+  int mP = AMOD(mp), mQ = AMOD(mq), mR = AMOD(mr);
+  real su = (xP * yQ - yP * xQ) / (rP * rQ);
+  real sv = (xQ * yR - yQ * xR) / (rQ * rR);
+  real dzpq = zQ - zP, dzqr = zR - zQ;
+  real res = su * dzqr - sv * dzpq;
+  real ezP = endcap_of(g, mP) ? RL(0) : hlong_of(g, mP);
+  real ezQ = endcap_of(g, mQ) ? RL(0) : hlong_of(g, mQ);
+  real ezR = endcap_of(g, mR) ? RL(0) : hlong_of(g, mR);
+  real iP = RL(1) / rP, iQ = RL(1) / rQ, iR = RL(1) / rR;
+  real dpq = iP - iQ, dqr = iQ - iR;
+  real ePQ = (hphi_of(g, mP) * iP + hphi_of(g, mQ) * iQ) + (real)D0_MAX * RABS(dpq);
+  real eQR = (hphi_of(g, mQ) * iQ + hphi_of(g, mR) * iR) + (real)D0_MAX * RABS(dqr);
+  real au = RABS(su), av = RABS(sv), adpq = RABS(dzpq), adqr = RABS(dzqr);
+  real nl = (au * au + av * av) * (real)(1.0 / 3.0);
+  real tol = ((adqr * ePQ + adpq * eQR) + (au * (ezQ + ezR) + av * (ezP + ezQ))) + nl * (au * adqr + av * adpq);
+  return cut_le(ac, RABS(res), tol * (real)1.001 + (real)1e-6, RL(0));
+}
+
+/* --------------------------------------------------------------- T3 predicate */
+/* Section 2.3: two segments sharing their middle MD; the three anchors must lie
+ * on a circle of curvature allowed by the pT threshold and on a straight line
+ * in (arc length, z) (chi2 cut). */
+static int t3_select(const orc_geom *g, orc_event *e, int ma_, int mb_, int mc_, real attr[4], cutacc *ac) {
+  real xA = AX(ma_), yA = AY(ma_), zA = AZ(ma_);
+  real xB = AX(mb_), yB = AY(mb_), zB = AZ(mb_);
+  real xC = AX(mc_), yC = AY(mc_), zC = AZ(mc_);
+  int mA = AMOD(ma_), mB = AMOD(mb_), mC = AMOD(mc_);
+  real ux = xB - xA, uy = yB - yA, wx = xC - xA, wy = yC - yA, tx = xC - xB, ty = yC - yB;
+  real k = ux * wy - uy * wx;
+  real Lu = RSQRT_(ux * ux + uy * uy), Lw = RSQRT_(wx * wx + wy * wy), Lt = RSQRT_(tx * tx + ty * ty);
+  real kap = (RL(2) * k) / ((Lu * Lw) * Lt);
+  real dk = (RL(4) * ((sig_t(g, mA) + RL(2) * sig_t(g, mB)) + sig_t(g, mC))) / (Lw * Lw);
+  int ok = cut_le(ac, RABS(kap), (real)(K_CURV / PT_MIN * 1.01) + dk, RL(0));
+  ok &= phiz_test(g, e, ma_, mb_, mc_, ac);
+  real xa = kap * Lu * RL(0.5), xb = kap * Lt * RL(0.5);
+  ok &= cut_le(ac, RABS(xa), (real)X_SERIES_MAX, RL(0));
+  ok &= cut_le(ac, RABS(xb), (real)X_SERIES_MAX, RL(0));
+  if (ac->firm_fail) return 0;
+  real s[3], z[3], w[3];
+  s[0] = RL(0);
+  s[1] = Lu * g4(xa);
+  s[2] = s[1] + Lt * g4(xb);
+  z[0] = zA; z[1] = zB; z[2] = zC;
+  real lam0 = (zC - zA) / s[2];
+  int mm[3] = {mA, mB, mC};
+  for (int i = 0; i < 3; ++i) { real sg = sig_z(g, mm[i], lam0); w[i] = RL(1) / (sg * sg); }
+  real lam;
+  real chi2 = line_fit(3, s, z, w, &lam);
+  ok &= cut_le(ac, chi2, (real)X_T3, RL(0));
+  attr[0] = kap; attr[1] = dk; attr[2] = chi2; attr[3] = lam;
+  return ok;
+}
+
+/* --------------------------------------------------------------- T5 predicate */
+/* Section 2.3: two triplets sharing an MD; the circles of the inner and outer
+ * triplet must have compatible radii, a circle fit to the five anchors must
+ * have a small chi2, and the anchors must lie on a straight line in
+ * (arc length, z) like the triplet.  The circle fit is the linear least-squares
+ * fit of v = a + b u + c (u^2 + v^2) in the frame with origin at the first
+ * anchor and u along the chord to the last, lengths in units of that chord. */
+static int t5_select(const orc_geom *g, orc_event *e, const int md[5], const real *a_in, const real *a_out,
+                     real attr[8], cutacc *ac) {
+  real k_in = a_in[0], dk_in = a_in[1], k_out = a_out[0], dk_out = a_out[1];
+  real dkk = k_in - k_out;
+  int ok = cut_le(ac, RABS(dkk), dk_in + dk_out, RL(0));
+  ok &= phiz_test(g, e, md[0], md[2], md[4], ac);
+  if (ac->firm_fail) return 0;
+  real X[5], Y[5], Z[5];
+  int M[5];
+  for (int i = 0; i < 5; ++i) { X[i] = AX(md[i]); Y[i] = AY(md[i]); Z[i] = AZ(md[i]); M[i] = AMOD(md[i]); }
+  real ex = X[4] - X[0], ey = Y[4] - Y[0];
+  real L = RSQRT_(ex * ex + ey * ey);
+  real ux = ex / L, uy = ey / L;
+  real u[5], v[5], q[5], w[5];
+  for (int i = 0; i < 5; ++i) {
+    real dx = X[i] - X[0], dy = Y[i] - Y[0];
+    u[i] = (dx * ux + dy * uy) / L;
+    v[i] = (dy * ux - dx * uy) / L;
+    q[i] = u[i] * u[i] + v[i] * v[i];
+    real t = L / sig_t(g, M[i]);
+    w[i] = t * t;
+  }
+  real S0 = RL(0), S1 = RL(0), S2 = RL(0), S11 = RL(0), S12 = RL(0), S22 = RL(0), T0 = RL(0), T1 = RL(0), T2 = RL(0);
+  for (int i = 0; i < 5; ++i) {
+    S0 = S0 + w[i];
+    S1 = S1 + w[i] * u[i];
+    S2 = S2 + w[i] * q[i];
+    S11 = S11 + w[i] * u[i] * u[i];
+    S12 = S12 + w[i] * u[i] * q[i];
+    S22 = S22 + w[i] * q[i] * q[i];
+    T0 = T0 + w[i] * v[i];
+    T1 = T1 + w[i] * u[i] * v[i];
+    T2 = T2 + w[i] * q[i] * v[i];
+  }
+  real m00 = S11 * S22 - S12 * S12;
+  real m01 = S1 * S22 - S12 * S2;
+  real m02 = S1 * S12 - S11 * S2;
+  real det = (S0 * m00 - S1 * m01) + S2 * m02;
+  if (!(det > RL(0))) { ac->firm_fail = 1; return 0; }
+  real deta = (T0 * m00 - S1 * (T1 * S22 - S12 * T2)) + S2 * (T1 * S12 - S11 * T2);
+  real detb = (S0 * (T1 * S22 - S12 * T2) - T0 * m01) + S2 * (S1 * T2 - T1 * S2);
+  real detc = (S0 * (S11 * T2 - T1 * S12) - S1 * (S1 * T2 - T1 * S2)) + T0 * m02;
+  real fa = deta / det, fb = detb / det, fc = detc / det;
+  real chi2xy = RL(0);
+  for (int i = 0; i < 5; ++i) {
+    real r = v[i] - ((fa + fb * u[i]) + fc * q[i]);
+    chi2xy = chi2xy + w[i] * r * r;
+  }
+  ok &= cut_le(ac, chi2xy, (real)X_T5XY, RL(0));
+  real disc = (RL(1) + fb * fb) - RL(4) * fa * fc;
+  if (!(disc > RL(0))) { ac->firm_fail = 1; return 0; }
+  real k5 = (RL(2) * fc) / (L * RSQRT_(disc));
+  /* r-z: arc lengths along the anchors with the mean triplet curvature */
+  real kb = (k_in + k_out) * RL(0.5);
+  real s[5], sg, lam;
+  s[0] = RL(0);
+  for (int i = 1; i < 5; ++i) {
+    real dx = X[i] - X[i - 1], dy = Y[i] - Y[i - 1];
+    real Lc = RSQRT_(dx * dx + dy * dy);
+    real xs = kb * Lc * RL(0.5);
+    ok &= cut_le(ac, RABS(xs), (real)X_SERIES_MAX, RL(0));
+    s[i] = s[i - 1] + Lc * g4(xs);
+  }
+  if (ac->firm_fail) return 0;
+  real lam0 = (Z[4] - Z[0]) / s[4];
+  for (int i = 0; i < 5; ++i) { sg = sig_z(g, M[i], lam0); w[i] = RL(1) / (sg * sg); }
+  real chi2rz = line_fit(5, s, Z, w, &lam);
+  ok &= cut_le(ac, chi2rz, (real)X_T5RZ, RL(0));
+  /* direction at the beam line: tangent at the first anchor, rotated back */
+  real nb = RSQRT_(RL(1) + fb * fb);
+  real cx = (ux - fb * uy) / nb, cy = (uy + fb * ux) / nb;
+  attr[0] = k5; attr[1] = chi2xy; attr[2] = chi2rz; attr[3] = lam;
+  attr[4] = k_in; attr[5] = k_out;
+  attr[6] = cx + k5 * Y[0];
+  attr[7] = cy - k5 * X[0];
+  return ok;
+}
+
+/* ------------------------------------------------------ pLS / pT3 / pT5 predicate */
+/* Section 2.4: the pixel seed's own circle (through its innermost hit, tangent
+ * to its direction, with its curvature) and its own r-z line are the
+ * hypothesis; the outer object's anchors are tested against it, not refitted. */
+static int pt_select(const orc_geom *g, orc_event *e, int seed, const int *md, int k, real kT, real dkT,
+                     real attr[3], cutacc *ac) {
+  const real *pa = e->pls_attr.p + 5 * (size_t)seed;
+  real cx = pa[1], cy = pa[2], lam = pa[3], ks = pa[4];
+  int h0 = e->hits4[4 * seed];
+  real x0 = e->x[h0], y0 = e->y[h0], z0 = e->z[h0];
+  real hk = ks * RL(0.5);
+  real sk = (real)SEED_DPT * RABS(ks);
+  /* window around the hypothesis at the first anchor */
+  real dx = AX(md[0]) - x0, dy = AY(md[0]) - y0;
+  real u1 = dx * cx + dy * cy, v1 = dy * cx - dx * cy;
+  real r1 = v1 - hk * (u1 * u1 + v1 * v1);
+  int ok = cut_gt(ac, u1, RL(0), RL(1));
+  ok &= cut_le(ac, RABS(r1), (real)B_XY, RL(0));
+  if (ac->firm_fail) return 0;
+  real s = RL(0), px = x0, py = y0;
+  real chi_xy = RL(0), chi_rz = RL(0);
+  for (int i = 0; i < k; ++i) {
+    real X = AX(md[i]), Y = AY(md[i]), Zz = AZ(md[i]);
+    int M = AMOD(md[i]);
+    real ddx = X - px, ddy = Y - py;
+    real Lc = RSQRT_(ddx * ddx + ddy * ddy);
+    real xs = hk * Lc;
+    ok &= cut_le(ac, RABS(xs), (real)X_SERIES_MAX, RL(0));
+    s = s + Lc * g4(xs);
+    px = X; py = Y;
+    real ex = X - x0, ey = Y - y0;
+    real u = ex * cx + ey * cy, v = ey * cx - ex * cy;
+    real qq = u * u + v * v;
+    real r = v - hk * qq;
+    real st = sig_t(g, M);
+    real sa = sk * qq * RL(0.5), sb = (real)SEED_DDIR * u;
+    real var = (st * st + sa * sa) + sb * sb;
+    chi_xy = chi_xy + (r * r) / var;
+    real sz = sig_z(g, M, lam);
+    real rz = Zz - (z0 + lam * s);
+    if (i == 0) ok &= cut_le(ac, RABS(rz), (real)B_Z0 + RL(2) * sz, RL(0));
+    chi_rz = chi_rz + (rz * rz) / (sz * sz);
+  }
+  if (ac->firm_fail) return 0;
+  int kk = k == 3 ? 0 : 1;
+  ok &= cut_le(ac, chi_xy, (real)X_PXY[kk], RL(0));
+  ok &= cut_le(ac, chi_rz, (real)X_PRZ[kk], RL(0));
+  real dks = ks - kT;
+  ok &= cut_le(ac, RABS(dks), RL(3) * sk + dkT, RL(0));
+  attr[0] = chi_xy; attr[1] = chi_rz; attr[2] = chi_xy + chi_rz;
+  return ok;
+}
+
+/* ---------------------------------------------------------------- hit tuples */
+static void md_hits(const orc_event *e, int md, int *out) { out[0] = e->md_lo.p[md]; out[1] = e->md_up.p[md]; }
+static void ls_mds(const orc_event *e, int ls, int *out) { out[0] = e->ls_in.p[ls]; out[1] = e->ls_out.p[ls]; }
+static void t3_mds(const orc_event *e, int t, int *out) {
+  out[0] = e->ls_in.p[e->t3_ls1.p[t]]; out[1] = e->ls_out.p[e->t3_ls1.p[t]]; out[2] = e->ls_out.p[e->t3_ls2.p[t]];
+}
+static void t5_mds(const orc_event *e, int t, int *out) {
+  t3_mds(e, e->t5_in.p[t], out);
+  int o[3];
+  t3_mds(e, e->t5_out.p[t], o);
+  out[3] = o[1]; out[4] = o[2];
+}
+static void mds_to_hits(const orc_event *e, const int *md, int n, int *out) {
+  for (int i = 0; i < n; ++i) md_hits(e, md[i], out + 2 * i);
+}
+/* lexicographic comparison of (score, hit tuple) */
+static int better(real s1, const int *h1, real s2, const int *h2, int n) {
+  if (s1 < s2) return 1;
+  if (s2 < s1) return 0;
+  for (int i = 0; i < n; ++i) {
+    if (h1[i] < h2[i]) return 1;
+    if (h2[i] < h1[i]) return 0;
+  }
+  return 0;
+}
+static int shared_hits(const int *a, int na, const int *b, int nb) {
+  int c = 0;
+  for (int i = 0; i < na; ++i)
+    for (int j = 0; j < nb; ++j)
+      if (a[i] == b[j]) { ++c; break; }
+  return c;
+}
+
+/* direction at the beam line and slope of an object, for eta-phi proximity */
+typedef struct { real dx, dy, lam; } odir;
+static odir seed_dir(const orc_event *e, int seed) {
+  const real *pa = e->pls_attr.p + 5 * (size_t)seed;
+  int h0 = e->hits4[4 * seed];
+  odir d;
+  d.dx = pa[1] + pa[4] * e->y[h0];
+  d.dy = pa[2] - pa[4] * e->x[h0];
+  d.lam = pa[3];
+  return d;
+}
+static odir t5_dir(const orc_event *e, int t) {
+  const real *a = e->t5_attr.p + 8 * (size_t)t;
+  odir d;
+  d.dx = a[6]; d.dy = a[7]; d.lam = a[3];
+  return d;
+}
+/* Section 2.5 "near in eta-phi": same hemisphere and
+ * sin^2(dphi) + (d lambda)^2 / (1 + mean lambda^2) < D^2 */
+static int near_dir(odir a, odir b, real D) {
+  real dot = a.dx * b.dx + a.dy * b.dy;
+  if (!(dot > RL(0))) return 0;
+  real cr = a.dx * b.dy - a.dy * b.dx;
+  real na = a.dx * a.dx + a.dy * a.dy, nb = b.dx * b.dx + b.dy * b.dy;
+  real dl = a.lam - b.lam, lm = (a.lam + b.lam) * RL(0.5);
+  real dr2 = (cr * cr) / (na * nb) + (dl * dl) / (RL(1) + lm * lm);
+  return dr2 < D * D;
+}
+
+/* ------------------------------------------------------------------- stages */
+static void stage_md(const orc_geom *g, orc_event *e) {
+  /* bucket the outer-tracker hits by (module, sensor), keeping input order */
+  int nm = g->n_mod;
+  int *cnt = (int *)calloc((size_t)2 * nm + 1, sizeof(int));
+  for (int i = 0; i < e->n_hits; ++i)
+    if (e->module[i] >= 0) cnt[2 * e->module[i] + e->sensor[i] + 1]++;
+  for (int k = 0; k < 2 * nm; ++k) cnt[k + 1] += cnt[k];
+  int *idx = (int *)malloc(sizeof(int) * ((size_t)cnt[2 * nm] + 1));
+  int *cur = (int *)malloc(sizeof(int) * (size_t)2 * nm);
+  memcpy(cur, cnt, sizeof(int) * (size_t)2 * nm);
+  for (int i = 0; i < e->n_hits; ++i)
+    if (e->module[i] >= 0) idx[cur[2 * e->module[i] + e->sensor[i]]++] = i;
+  e->md_first = (int *)malloc(sizeof(int) * ((size_t)nm + 1));
+  for (int m = 0; m < nm; ++m) {
+    e->md_first[m] = (int)e->md_lo.n;
+    for (int a = cnt[2 * m]; a < cnt[2 * m + 1]; ++a)
+      for (int b = cnt[2 * m + 1]; b < cnt[2 * m + 2]; ++b) {
+        int i = idx[a], j = idx[b];
+        cutacc ac = {0, 0};
+        int ok = md_select(g, e, m, i, j, &ac);
+        int tup[2] = {i, j};
+        record_border(e, ST_MD, tup, 2, ok, &ac);
+        if (ok) { iv_push(&e->md_lo, i); iv_push(&e->md_up, j); iv_push(&e->md_mod, m); }
+      }
+  }
+  e->md_first[nm] = (int)e->md_lo.n;
+  free(cnt); free(idx); free(cur);
+}
+
+static void stage_ls(const orc_geom *g, orc_event *e) {
+  int nmd = (int)e->md_lo.n;
+  e->ls_first = (int *)malloc(sizeof(int) * ((size_t)nmd + 1));
+  for (int a = 0; a < nmd; ++a) {
+    e->ls_first[a] = (int)e->ls_in.n;
+    int ma = AMOD(a);
+    for (int k = g->map_off[ma]; k < g->map_off[ma + 1]; ++k) {
+      int mb = g->map_tgt[k];
+      for (int b = e->md_first[mb]; b < e->md_first[mb + 1]; ++b) {
+        cutacc ac = {0, 0};
+        real bi = RL(0), bo = RL(0);
+        int ok = ls_select(g, e, a, b, &bi, &bo, &ac);
+        int tup[4];
+        md_hits(e, a, tup); md_hits(e, b, tup + 2);
+        record_border(e, ST_LS, tup, 4, ok, &ac);
+        if (ok) { iv_push(&e->ls_in, a); iv_push(&e->ls_out, b); rv_push(&e->ls_attr, bi); rv_push(&e->ls_attr, bo); }
+      }
+    }
+  }
+  e->ls_first[nmd] = (int)e->ls_in.n;
+}
+
+static void stage_t3(const orc_geom *g, orc_event *e) {
+  int nmd = (int)e->md_lo.n;
+  int nls = (int)e->ls_in.n;
+  e->t3_first = (int *)malloc(sizeof(int) * ((size_t)nmd + 1));
+  int next_md = 0;
+  for (int l1 = 0; l1 < nls; ++l1) {
+    while (next_md <= e->ls_in.p[l1]) e->t3_first[next_md++] = (int)e->t3_ls1.n;
+    int b = e->ls_out.p[l1];
+    for (int l2 = e->ls_first[b]; l2 < e->ls_first[b + 1]; ++l2) {
+      int md3[3] = {e->ls_in.p[l1], b, e->ls_out.p[l2]};
+      real attr[4];
+      cutacc ac = {0, 0};
+      int ok = t3_select(g, e, md3[0], md3[1], md3[2], attr, &ac);
+      int tup[6];
+      mds_to_hits(e, md3, 3, tup);
+      record_border(e, ST_T3, tup, 6, ok, &ac);
+      if (ok) {
+        iv_push(&e->t3_ls1, l1); iv_push(&e->t3_ls2, l2);
+        for (int i = 0; i < 4; ++i) rv_push(&e->t3_attr, attr[i]);
+      }
+    }
+  }
+  while (next_md <= nmd) e->t3_first[next_md++] = (int)e->t3_ls1.n;
+}
+
+static void stage_t5(const orc_geom *g, orc_event *e) {
+  int nt3 = (int)e->t3_ls1.n;
+  for (int t1 = 0; t1 < nt3; ++t1) {
+    int m1[3];
+    t3_mds(e, t1, m1);
+    int c = m1[2];
+    for (int t2 = e->t3_first[c]; t2 < e->t3_first[c + 1]; ++t2) {
+      int m2[3];
+      t3_mds(e, t2, m2);
+      int md5[5] = {m1[0], m1[1], m1[2], m2[1], m2[2]};
+      real attr[8];
+      cutacc ac = {0, 0};
+      int ok = t5_select(g, e, md5, e->t3_attr.p + 4 * (size_t)t1, e->t3_attr.p + 4 * (size_t)t2, attr, &ac);
+      int tup[10];
+      mds_to_hits(e, md5, 5, tup);
+      record_border(e, ST_T5, tup, 10, ok, &ac);
+      if (ok) {
+        iv_push(&e->t5_in, t1); iv_push(&e->t5_out, t2);
+        for (int i = 0; i < 8; ++i) rv_push(&e->t5_attr, attr[i]);
+      }
+    }
+  }
+}
+
+static int shared_mds(const int *a, const int *b) {
+  int c = 0;
+  for (int i = 0; i < 5; ++i)
+    for (int j = 0; j < 5; ++j)
+      if (a[i] == b[j]) { ++c; break; }
+  return c;
+}
+
+/* Section 2.5 duplicate removal among quintuplets: a T5 is dropped when another
+ * T5 sharing at least two of its five MDs has a smaller (chi2_xy, hit tuple).
+ * (Every two 5-MD windows of one track crossing up to 8 surfaces share two
+ * MDs, so one track leaves one T5.)  Candidates are found through per-MD
+ * lists of the T5s that contain the MD. */
+static void stage_t5_dedup(orc_event *e) {
+  int n = (int)e->t5_in.n;
+  int nmd = (int)e->md_lo.n;
+  int *cnt = (int *)calloc((size_t)nmd + 1, sizeof(int));
+  int *mds = (int *)malloc(sizeof(int) * 5 * ((size_t)n + 1));
+  for (int t = 0; t < n; ++t) {
+    t5_mds(e, t, mds + 5 * t);
+    for (int i = 0; i < 5; ++i) cnt[mds[5 * t + i] + 1]++;
+  }
+  for (int k = 0; k < nmd; ++k) cnt[k + 1] += cnt[k];
+  int *lst = (int *)malloc(sizeof(int) * (5 * (size_t)n + 1));
+  int *cur = (int *)malloc(sizeof(int) * ((size_t)nmd + 1));
+  memcpy(cur, cnt, sizeof(int) * ((size_t)nmd + 1));
+  for (int t = 0; t < n; ++t)
+    for (int i = 0; i < 5; ++i) lst[cur[mds[5 * t + i]]++] = t;
+  for (int t = 0; t < n; ++t) {
+    int ht[10];
+    mds_to_hits(e, mds + 5 * t, 5, ht);
+    real st = e->t5_attr.p[8 * (size_t)t + 1];
+    int keep = 1;
+    for (int i = 0; i < 5 && keep; ++i) {
+      int md = mds[5 * t + i];
+      for (int k = cnt[md]; k < cnt[md + 1] && keep; ++k) {
+        int u = lst[k];
+        if (u == t) continue;
+        if (shared_mds(mds + 5 * t, mds + 5 * u) < 2) continue;
+        int hu[10];
+        mds_to_hits(e, mds + 5 * u, 5, hu);
+        if (better(e->t5_attr.p[8 * (size_t)u + 1], hu, st, ht, 10)) keep = 0;
+      }
+    }
+    iv_push(&e->t5_keep, keep);
+  }
+  free(cnt); free(mds); free(lst); free(cur);
+}
+
+/* Section 2.4: every pixel seed is a pixel line segment. */
+static void stage_pls(orc_event *e) {
+  for (int s = 0; s < e->n_seeds; ++s) {
+    real px = e->px[s], py = e->py[s], pz = e->pz[s];
+    real pt = RSQRT_(px * px + py * py);
+    real cx = px / pt, cy = py / pt, lam = pz / pt;
+    real ks = (-(real)e->q[s] * (real)K_CURV) / pt;
+    rv_push(&e->pls_attr, pt); rv_push(&e->pls_attr, cx); rv_push(&e->pls_attr, cy);
+    rv_push(&e->pls_attr, lam); rv_push(&e->pls_attr, ks);
+  }
+}
+
+static void stage_pt(const orc_geom *g, orc_event *e, int five) {
+  int nobj = five ? (int)e->t5_in.n : (int)e->t3_ls1.n;
+  int k = five ? 5 : 3;
+  /* first anchors in contiguous arrays, for a cheap pre-test of the window
+   * around the seed at the first anchor; the pre-test is the window test
+   * itself widened by 1e-5 relative, so it never drops a candidate that the
+   * full predicate (and its borderline band) would consider */
+  real *fx = (real *)malloc(sizeof(real) * ((size_t)nobj + 1));
+  real *fy = (real *)malloc(sizeof(real) * ((size_t)nobj + 1));
+  for (int t = 0; t < nobj; ++t) {
+    int md[5];
+    if (five) t5_mds(e, t, md); else t3_mds(e, t, md);
+    fx[t] = AX(md[0]); fy[t] = AY(md[0]);
+  }
+  for (int s = 0; s < e->n_seeds; ++s) {
+    const real *pa = e->pls_attr.p + 5 * (size_t)s;
+    real cx = pa[1], cy = pa[2], hk = pa[4] * RL(0.5);
+    int h0 = e->hits4[4 * s];
+    real x0 = e->x[h0], y0 = e->y[h0];
+    for (int t = 0; t < nobj; ++t) {
+      {
+        real dx = fx[t] - x0, dy = fy[t] - y0;
+        real u1 = dx * cx + dy * cy, v1 = dy * cx - dx * cy;
+        real r1 = v1 - hk * (u1 * u1 + v1 * v1);
+        if (!(u1 > (real)-1e-5) || !(RABS(r1) <= (real)(B_XY * (1.0 + 1e-5)))) continue;
+      }
+      int md[5];
+      real kT, dkT;
+      if (five) {
+        if (!e->t5_keep.p[t]) continue;
+        t5_mds(e, t, md);
+        kT = e->t3_attr.p[4 * (size_t)e->t5_out.p[t]];
+        dkT = e->t3_attr.p[4 * (size_t)e->t5_out.p[t] + 1];
+      } else {
+        t3_mds(e, t, md);
+        kT = e->t3_attr.p[4 * (size_t)t];
+        dkT = e->t3_attr.p[4 * (size_t)t + 1];
+      }
+      real attr[3];
+      cutacc ac = {0, 0};
+      int ok = pt_select(g, e, s, md, k, kT, dkT, attr, &ac);
+      int tup[11];
+      tup[0] = s;
+      mds_to_hits(e, md, k, tup + 1);
+      record_border(e, five ? ST_PT5 : ST_PT3, tup, 1 + 2 * k, ok, &ac);
+      if (ok) {
+        if (five) {
+          iv_push(&e->pt5_seed, s); iv_push(&e->pt5_obj, t);
+          for (int i = 0; i < 3; ++i) rv_push(&e->pt5_attr, attr[i]);
+        } else {
+          iv_push(&e->pt3_seed, s); iv_push(&e->pt3_obj, t);
+          for (int i = 0; i < 3; ++i) rv_push(&e->pt3_attr, attr[i]);
+        }
+      }
+    }
+  }
+  free(fx); free(fy);
+}
+
+/* Section 2.5 duplicate removal among pT3 (pT5): drop when another with the same
+ * seed or the same outer object has a smaller (score, seed, hit tuple). */
+static void stage_pt_dedup(orc_event *e, int five) {
+  ivec *seed = five ? &e->pt5_seed : &e->pt3_seed, *obj = five ? &e->pt5_obj : &e->pt3_obj;
+  rvec *attr = five ? &e->pt5_attr : &e->pt3_attr;
+  ivec *keep = five ? &e->pt5_keep : &e->pt3_keep;
+  int n = (int)seed->n, k = five ? 5 : 3;
+  int nobj = five ? (int)e->t5_in.n : (int)e->t3_ls1.n;
+  /* per-object lists of pT entries */
+  int *cnt = (int *)calloc((size_t)nobj + 1, sizeof(int));
+  for (int i = 0; i < n; ++i) cnt[obj->p[i] + 1]++;
+  for (int t = 0; t < nobj; ++t) cnt[t + 1] += cnt[t];
+  int *lst = (int *)malloc(sizeof(int) * ((size_t)n + 1));
+  int *cur = (int *)malloc(sizeof(int) * ((size_t)nobj + 1));
+  memcpy(cur, cnt, sizeof(int) * ((size_t)nobj + 1));
+  for (int i = 0; i < n; ++i) lst[cur[obj->p[i]]++] = i;
+  /* entries are grouped by seed (built seed by seed) */
+  for (int i = 0; i < n; ++i) {
+    int md[5], ti[11];
+    ti[0] = seed->p[i];
+    if (five) t5_mds(e, obj->p[i], md); else t3_mds(e, obj->p[i], md);
+    mds_to_hits(e, md, k, ti + 1);
+    real si = attr->p[3 * (size_t)i + 2];
+    int kp = 1;
+    int lo = i, hi = i;
+    while (lo > 0 && seed->p[lo - 1] == seed->p[i]) --lo;
+    while (hi + 1 < n && seed->p[hi + 1] == seed->p[i]) ++hi;
+    for (int j = lo; j <= hi && kp; ++j) {
+      if (j == i) continue;
+      int mj[5], tj[11];
+      tj[0] = seed->p[j];
+      if (five) t5_mds(e, obj->p[j], mj); else t3_mds(e, obj->p[j], mj);
+      mds_to_hits(e, mj, k, tj + 1);
+      if (better(attr->p[3 * (size_t)j + 2], tj, si, ti, 1 + 2 * k)) kp = 0;
+    }
+    int t = obj->p[i];
+    for (int q = cnt[t]; q < cnt[t + 1] && kp; ++q) {
+      int j = lst[q];
+      if (j == i) continue;
+      int tj[11];
+      tj[0] = seed->p[j];
+      for (int z = 1; z < 1 + 2 * k; ++z) tj[z] = ti[z];
+      if (better(attr->p[3 * (size_t)j + 2], tj, si, ti, 1 + 2 * k)) kp = 0;
+    }
+    iv_push(keep, kp);
+  }
+  free(cnt); free(lst); free(cur);
+}
+
+/* Section 2.5: track candidates are pT5, then pT3, then T5, then pLS, each
+ * added only if not already used and not near (eta-phi) what was added. */
+static void stage_tc(orc_event *e) {
+  int ns = e->n_seeds;
+  int n5 = (int)e->pt5_seed.n, n3 = (int)e->pt3_seed.n, nt5 = (int)e->t5_in.n;
+  char *seed_used = (char *)calloc((size_t)ns + 1, 1);
+  char *t5_used = (char *)calloc((size_t)nt5 + 1, 1);
+  ivec tc5 = {0}, tc3 = {0}, tct5 = {0};
+  for (int i = 0; i < n5; ++i)
+    if (e->pt5_keep.p[i]) { iv_push(&tc5, i); seed_used[e->pt5_seed.p[i]] = 1; t5_used[e->pt5_obj.p[i]] = 1; }
+  for (int i = 0; i < n3; ++i) {
+    if (!e->pt3_keep.p[i]) continue;
+    int s = e->pt3_seed.p[i];
+    if (seed_used[s]) continue;
+    odir d = seed_dir(e, s);
+    int nr = 0;
+    for (size_t j = 0; j < tc5.n && !nr; ++j) nr = near_dir(d, seed_dir(e, e->pt5_seed.p[tc5.p[j]]), (real)D_PT3);
+    if (!nr) iv_push(&tc3, i);
+  }
+  for (size_t j = 0; j < tc3.n; ++j) seed_used[e->pt3_seed.p[tc3.p[j]]] = 1;
+  for (int t = 0; t < nt5; ++t) {
+    if (!e->t5_keep.p[t] || t5_used[t]) continue;
+    odir d = t5_dir(e, t);
+    int nr = 0;
+    for (size_t j = 0; j < tc5.n && !nr; ++j) nr = near_dir(d, seed_dir(e, e->pt5_seed.p[tc5.p[j]]), (real)D_T5);
+    for (size_t j = 0; j < tc3.n && !nr; ++j) nr = near_dir(d, seed_dir(e, e->pt3_seed.p[tc3.p[j]]), (real)D_T5);
+    if (!nr) iv_push(&tct5, t);
+  }
+  /* pLS duplicate removal: seeds sharing >= 3 pixel hits; the lower seed index
+   * wins.  Candidates come from per-hit lists of the seeds using the hit. */
+  {
+    int nh = e->n_hits;
+    int *hc = (int *)calloc((size_t)nh + 1, sizeof(int));
+    for (int s = 0; s < ns; ++s)
+      for (int q = 0; q < 4; ++q) hc[e->hits4[4 * s + q] + 1]++;
+    for (int h = 0; h < nh; ++h) hc[h + 1] += hc[h];
+    int *hl = (int *)malloc(sizeof(int) * (4 * (size_t)ns + 1));
+    int *hcur = (int *)malloc(sizeof(int) * ((size_t)nh + 1));
+    memcpy(hcur, hc, sizeof(int) * ((size_t)nh + 1));
+    for (int s = 0; s < ns; ++s)
+      for (int q = 0; q < 4; ++q) hl[hcur[e->hits4[4 * s + q]]++] = s;
+    for (int s = 0; s < ns; ++s) {
+      int kp = 1;
+      for (int q = 0; q < 4 && kp; ++q) {
+        int h = e->hits4[4 * s + q];
+        for (int k = hc[h]; k < hc[h + 1] && kp; ++k) {
+          int t = hl[k];
+          if (t < s && shared_hits(e->hits4 + 4 * s, 4, e->hits4 + 4 * t, 4) >= 3) kp = 0;
+        }
+      }
+      iv_push(&e->pls_keep, kp);
+    }
+    free(hc); free(hl); free(hcur);
+  }
+  ivec tcp = {0};
+  for (int s = 0; s < ns; ++s) {
+    if (!e->pls_keep.p[s] || seed_used[s]) continue;
+    odir d = seed_dir(e, s);
+    int nr = 0;
+    for (size_t j = 0; j < tc5.n && !nr; ++j) nr = near_dir(d, seed_dir(e, e->pt5_seed.p[tc5.p[j]]), (real)D_PLS);
+    for (size_t j = 0; j < tc3.n && !nr; ++j) nr = near_dir(d, seed_dir(e, e->pt3_seed.p[tc3.p[j]]), (real)D_PLS);
+    for (size_t j = 0; j < tct5.n && !nr; ++j) nr = near_dir(d, t5_dir(e, tct5.p[j]), (real)D_PLS);
+    if (!nr) iv_push(&tcp, s);
+  }
+  /* assemble: type, object, hit list (pixel hits innermost first, then the
+   * lower and upper hit of each MD from inner to outer) */
+  iv_push(&e->tc_off, 0);
+  for (size_t j = 0; j < tc5.n; ++j) {
+    int i = tc5.p[j], s = e->pt5_seed.p[i], md[5], h[10];
+    iv_push(&e->tc_type, 0); iv_push(&e->tc_obj, i);
+    for (int q = 0; q < 4; ++q) iv_push(&e->tc_hits, e->hits4[4 * s + q]);
+    t5_mds(e, e->pt5_obj.p[i], md); mds_to_hits(e, md, 5, h);
+    for (int q = 0; q < 10; ++q) iv_push(&e->tc_hits, h[q]);
+    iv_push(&e->tc_off, (int)e->tc_hits.n);
+  }
+  for (size_t j = 0; j < tc3.n; ++j) {
+    int i = tc3.p[j], s = e->pt3_seed.p[i], md[3], h[6];
+    iv_push(&e->tc_type, 1); iv_push(&e->tc_obj, i);
+    for (int q = 0; q < 4; ++q) iv_push(&e->tc_hits, e->hits4[4 * s + q]);
+    t3_mds(e, e->pt3_obj.p[i], md); mds_to_hits(e, md, 3, h);
+    for (int q = 0; q < 6; ++q) iv_push(&e->tc_hits, h[q]);
+    iv_push(&e->tc_off, (int)e->tc_hits.n);
+  }
+  for (size_t j = 0; j < tct5.n; ++j) {
+    int t = tct5.p[j], md[5], h[10];
+    iv_push(&e->tc_type, 2); iv_push(&e->tc_obj, t);
+    t5_mds(e, t, md); mds_to_hits(e, md, 5, h);
+    for (int q = 0; q < 10; ++q) iv_push(&e->tc_hits, h[q]);
+    iv_push(&e->tc_off, (int)e->tc_hits.n);
+  }
+  for (size_t j = 0; j < tcp.n; ++j) {
+    int s = tcp.p[j];
+    iv_push(&e->tc_type, 3); iv_push(&e->tc_obj, s);
+    for (int q = 0; q < 4; ++q) iv_push(&e->tc_hits, e->hits4[4 * s + q]);
+    iv_push(&e->tc_off, (int)e->tc_hits.n);
+  }
+  free(seed_used); free(t5_used);
+  iv_free(&tc5); iv_free(&tc3); iv_free(&tct5); iv_free(&tcp);
+}
+
+/* ---------------------------------------------------------------- entry points */
+static orc_event *event_new(int n_hits, const float *x, const float *y, const float *z, const int *module,
+                            const int *sensor, int n_seeds, const float *px, const float *py, const float *pz,
+                            const int *q, const int *hits4) {
+  orc_event *e = (orc_event *)calloc(1, sizeof(orc_event));
+  e->n_hits = n_hits; e->n_seeds = n_seeds;
+  e->x = (real *)malloc(sizeof(real) * ((size_t)n_hits + 1));
+  e->y = (real *)malloc(sizeof(real) * ((size_t)n_hits + 1));
+  e->z = (real *)malloc(sizeof(real) * ((size_t)n_hits + 1));
+  e->r = (real *)malloc(sizeof(real) * ((size_t)n_hits + 1));
+  for (int i = 0; i < n_hits; ++i) {
+    e->x[i] = (real)x[i]; e->y[i] = (real)y[i]; e->z[i] = (real)z[i];
+    e->r[i] = RSQRT_(e->x[i] * e->x[i] + e->y[i] * e->y[i]);
+  }
+  e->module = module; e->sensor = sensor;
+  e->px = px; e->py = py; e->pz = pz; e->q = q; e->hits4 = hits4;
+  return e;
+}
+
+/* Runs the chain up to and including stage `last` (0..7).  Inputs are read
+ * during the call only.  Returns an opaque result, freed by orc_free. */
+void *orc_run(void *gp, int n_hits, const float *x, const float *y, const float *z, const int *module,
+              const int *sensor, int n_seeds, const float *px, const float *py, const float *pz, const int *q,
+              const int *hits4, int last) {
+  const orc_geom *g = (const orc_geom *)gp;
+  orc_event *e = event_new(n_hits, x, y, z, module, sensor, n_seeds, px, py, pz, q, hits4);
+  stage_md(g, e);
+  if (last >= ST_LS) stage_ls(g, e);
+  if (last >= ST_T3) stage_t3(g, e);
+  if (last >= ST_T5) { stage_t5(g, e); stage_t5_dedup(e); }
+  if (last >= ST_PLS) stage_pls(e);
+  if (last >= ST_PT3) { stage_pt(g, e, 0); stage_pt_dedup(e, 0); }
+  if (last >= ST_PT5) { stage_pt(g, e, 1); stage_pt_dedup(e, 1); }
+  if (last >= ST_TC) stage_tc(e);
+  /* the seeds' pointers are not kept past the call */
+  e->px = e->py = e->pz = NULL;
+  if (n_seeds) {
+    int *h4 = (int *)malloc(sizeof(int) * 4 * (size_t)n_seeds);
+    memcpy(h4, hits4, sizeof(int) * 4 * (size_t)n_seeds);
+    e->hits4 = h4;
+  } else {
+    e->hits4 = NULL;
+  }
+  e->module = e->sensor = NULL;
+  e->q = NULL;
+  return e;
+}
+
+int orc_count(void *ep, int stage) {
+  orc_event *e = (orc_event *)ep;
+  switch (stage) {
+    case ST_MD: return (int)e->md_lo.n;
+    case ST_LS: return (int)e->ls_in.n;
+    case ST_T3: return (int)e->t3_ls1.n;
+    case ST_T5: return (int)e->t5_in.n;
+    case ST_PLS: return (int)(e->pls_attr.n / 5);
+    case ST_PT3: return (int)e->pt3_seed.n;
+    case ST_PT5: return (int)e->pt5_seed.n;
+    case ST_TC: return (int)e->tc_type.n;
+  }
+  return -1;
+}
+
+/* Copies stage objects: tuples [n x TUPLE_W] of input hit indices (seed index
+ * first for pLS/pT3/pT5), flags [n] (keep flags of T5/pT3/pT5/pLS, else 1),
+ * attrs [n x ATTR_W]. Any pointer may be NULL. */
+void orc_stage(void *ep, int stage, int *tuples, int *flags, real *attrs) {
+  orc_event *e = (orc_event *)ep;
+  int n = orc_count(ep, stage);
+  for (int i = 0; i < n; ++i) {
+    int md[5], t[11] = {0};
+    int flag = 1;
+    const real *a = NULL;
+    switch (stage) {
+      case ST_MD: md_hits(e, i, t); break;
+      case ST_LS: ls_mds(e, i, md); mds_to_hits(e, md, 2, t); a = e->ls_attr.p + 2 * (size_t)i; break;
+      case ST_T3: t3_mds(e, i, md); mds_to_hits(e, md, 3, t); a = e->t3_attr.p + 4 * (size_t)i; break;
+      case ST_T5: t5_mds(e, i, md); mds_to_hits(e, md, 5, t); a = e->t5_attr.p + 8 * (size_t)i; flag = e->t5_keep.p[i]; break;
+      case ST_PLS: t[0] = i; a = e->pls_attr.p + 5 * (size_t)i; flag = e->pls_keep.n ? e->pls_keep.p[i] : 1; break;
+      case ST_PT3:
+        t[0] = e->pt3_seed.p[i]; t3_mds(e, e->pt3_obj.p[i], md); mds_to_hits(e, md, 3, t + 1);
+        a = e->pt3_attr.p + 3 * (size_t)i; flag = e->pt3_keep.p[i]; break;
+      case ST_PT5:
+        t[0] = e->pt5_seed.p[i]; t5_mds(e, e->pt5_obj.p[i], md); mds_to_hits(e, md, 5, t + 1);
+        a = e->pt5_attr.p + 3 * (size_t)i; flag = e->pt5_keep.p[i]; break;
+      default: return;
+    }
+    if (tuples) for (int k = 0; k < TUPLE_W[stage]; ++k) tuples[(size_t)i * TUPLE_W[stage] + k] = t[k];
+    if (flags) flags[i] = flag;
+    if (attrs && a) for (int k = 0; k < ATTR_W[stage]; ++k) attrs[(size_t)i * ATTR_W[stage] + k] = a[k];
+  }
+}
+
+int orc_tc_hit_count(void *ep) { return (int)((orc_event *)ep)->tc_hits.n; }
+void orc_tc(void *ep, int *type, int *offsets, int *hits) {
+  orc_event *e = (orc_event *)ep;
+  if (type) memcpy(type, e->tc_type.p, sizeof(int) * e->tc_type.n);
+  if (offsets) memcpy(offsets, e->tc_off.p, sizeof(int) * e->tc_off.n);
+  if (hits) memcpy(hits, e->tc_hits.p, sizeof(int) * e->tc_hits.n);
+}
+int orc_border_count(void *ep, int stage) { return (int)((orc_event *)ep)->border_acc[stage].n; }
+void orc_border(void *ep, int stage, int *tuples, int *accepted) {
+  orc_event *e = (orc_event *)ep;
+  memcpy(tuples, e->border[stage].p, sizeof(int) * e->border[stage].n);
+  memcpy(accepted, e->border_acc[stage].p, sizeof(int) * e->border_acc[stage].n);
+}
+int orc_real_size(void) { return (int)sizeof(real); }
+
+void orc_free(void *ep) {
+  orc_event *e = (orc_event *)ep;
+  if (!e) return;
+  free(e->x); free(e->y); free(e->z); free(e->r); free(e->md_first); free(e->ls_first); free(e->t3_first);
+  free((void *)e->hits4);
+  iv_free(&e->md_lo); iv_free(&e->md_up); iv_free(&e->md_mod);
+  iv_free(&e->ls_in); iv_free(&e->ls_out); rv_free(&e->ls_attr);
+  iv_free(&e->t3_ls1); iv_free(&e->t3_ls2); rv_free(&e->t3_attr);
+  iv_free(&e->t5_in); iv_free(&e->t5_out); rv_free(&e->t5_attr); iv_free(&e->t5_keep);
+  rv_free(&e->pls_attr); iv_free(&e->pls_keep);
+  iv_free(&e->pt3_seed); iv_free(&e->pt3_obj); iv_free(&e->pt3_keep); rv_free(&e->pt3_attr);
+  iv_free(&e->pt5_seed); iv_free(&e->pt5_obj); iv_free(&e->pt5_keep); rv_free(&e->pt5_attr);
+  iv_free(&e->tc_type); iv_free(&e->tc_obj); iv_free(&e->tc_off); iv_free(&e->tc_hits);
+  for (int s = 0; s < N_ST; ++s) { iv_free(&e->border[s]); iv_free(&e->border_acc[s]); }
+  free(e);
+}
+
+/* ------------------------------------------------------------ brute force */
+/* Closure of the same predicates over all hit / object combinations, with no
+ * buckets, per-module lists or per-MD offsets: MD over all same-module
+ * lower/upper pairs, LS over all MD pairs whose modules are linked in the map,
+ * T3 over all LS pairs with outer MD of the first = inner MD of the second,
+ * T5 over all T3 pairs sharing the last/first MD, T5 duplicate removal over all
+ * T5 pairs.  For tiny events only (quadratic in every count).  Returns counts
+ * in out_counts[0..3] and the keep count in out_counts[4]; objects are
+ * retrievable with orc_stage like a staged result. */
+void *orc_run_brute(void *gp, int n_hits, const float *x, const float *y, const float *z, const int *module,
+                    const int *sensor, int *out_counts) {
+  const orc_geom *g = (const orc_geom *)gp;
+  orc_event *e = event_new(n_hits, x, y, z, module, sensor, 0, NULL, NULL, NULL, NULL, NULL);
+  /* MD: iterate modules in order, then hit pairs in input order */
+  e->md_first = (int *)malloc(sizeof(int) * ((size_t)g->n_mod + 1));
+  for (int m = 0; m < g->n_mod; ++m) {
+    e->md_first[m] = (int)e->md_lo.n;
+    for (int i = 0; i < n_hits; ++i) {
+      if (module[i] != m || sensor[i] != 0) continue;
+      for (int j = 0; j < n_hits; ++j) {
+        if (module[j] != m || sensor[j] != 1) continue;
+        cutacc ac = {0, 0};
+        if (md_select(g, e, m, i, j, &ac)) { iv_push(&e->md_lo, i); iv_push(&e->md_up, j); iv_push(&e->md_mod, m); }
+      }
+    }
+  }
+  e->md_first[g->n_mod] = (int)e->md_lo.n;
+  int nmd = (int)e->md_lo.n;
+  for (int a = 0; a < nmd; ++a)
+    for (int b = 0; b < nmd; ++b) {
+      int ma = AMOD(a), mb = AMOD(b), linked = 0;
+      for (int k = g->map_off[ma]; k < g->map_off[ma + 1] && !linked; ++k)
+        if (g->map_tgt[k] == mb) linked = 1;
+      if (!linked) continue;
+      cutacc ac = {0, 0};
+      real bi, bo;
+      if (ls_select(g, e, a, b, &bi, &bo, &ac)) {
+        iv_push(&e->ls_in, a); iv_push(&e->ls_out, b); rv_push(&e->ls_attr, bi); rv_push(&e->ls_attr, bo);
+      }
+    }
+  int nls = (int)e->ls_in.n;
+  for (int l1 = 0; l1 < nls; ++l1)
+    for (int l2 = 0; l2 < nls; ++l2) {
+      if (e->ls_out.p[l1] != e->ls_in.p[l2]) continue;
+      real attr[4];
+      cutacc ac = {0, 0};
+      if (t3_select(g, e, e->ls_in.p[l1], e->ls_out.p[l1], e->ls_out.p[l2], attr, &ac)) {
+        iv_push(&e->t3_ls1, l1); iv_push(&e->t3_ls2, l2);
+        for (int i = 0; i < 4; ++i) rv_push(&e->t3_attr, attr[i]);
+      }
+    }
+  int nt3 = (int)e->t3_ls1.n;
+  for (int t1 = 0; t1 < nt3; ++t1)
+    for (int t2 = 0; t2 < nt3; ++t2) {
+      int m1[3], m2[3];
+      t3_mds(e, t1, m1); t3_mds(e, t2, m2);
+      if (m1[2] != m2[0]) continue;
+      int md5[5] = {m1[0], m1[1], m1[2], m2[1], m2[2]};
+      real attr[8];
+      cutacc ac = {0, 0};
+      if (t5_select(g, e, md5, e->t3_attr.p + 4 * (size_t)t1, e->t3_attr.p + 4 * (size_t)t2, attr, &ac)) {
+        iv_push(&e->t5_in, t1); iv_push(&e->t5_out, t2);
+        for (int i = 0; i < 8; ++i) rv_push(&e->t5_attr, attr[i]);
+      }
+    }
+  int nt5 = (int)e->t5_in.n, nkeep = 0;
+  for (int t = 0; t < nt5; ++t) {
+    int mt[5], ht[10], keep = 1;
+    t5_mds(e, t, mt); mds_to_hits(e, mt, 5, ht);
+    for (int u = 0; u < nt5 && keep; ++u) {
+      if (u == t) continue;
+      int mu[5], hu[10];
+      t5_mds(e, u, mu); mds_to_hits(e, mu, 5, hu);
+      if (shared_mds(mt, mu) >= 2 && better(e->t5_attr.p[8 * (size_t)u + 1], hu, e->t5_attr.p[8 * (size_t)t + 1], ht, 10))
+        keep = 0;
+    }
+    iv_push(&e->t5_keep, keep);
+    nkeep += keep;
+  }
+  out_counts[0] = nmd; out_counts[1] = nls; out_counts[2] = nt3; out_counts[3] = nt5; out_counts[4] = nkeep;
+  e->module = e->sensor = NULL;
+  return e;
+}
