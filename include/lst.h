@@ -1,0 +1,179 @@
+/*
+ * lst.h -- C ABI of the MI355X (gfx950) Line Segment Tracking library.
+ *
+ * Line Segment Tracking (arXiv:2207.08207) builds track candidates bottom-up
+ * (Section 2.1): mini-doublets (MD, hit pairs of one pT module, Section 2.2),
+ * line segments (LS, two MDs in modules linked by the module map, Section
+ * 2.2), triplets and quintuplets (T3/T5, segments and triplets sharing an MD,
+ * Section 2.3), pixel line segments and pixel triplets/quintuplets (pLS,
+ * pT3/pT5, Section 2.4), then removes duplicates and cross-cleans them into
+ * track candidates in the order pT5, pT3, T5, pLS (Section 2.5).  Hits and
+ * the module map go in; lists of hit indices come out (Section 4.2, whose
+ * flowchart starts from hits in GPU memory and ends by copying the track
+ * candidates to the host).
+ *
+ * Conventions
+ *  - Every function returns lst_status: LST_OK (0) or a negative error.  On
+ *    error lst_last_error() returns a message (thread-local, valid until the
+ *    next call on the same thread).  No C++ exception crosses this boundary.
+ *  - Geometry inputs are HOST pointers, copied during lst_load_geometry.
+ *  - Event inputs are DEVICE pointers (already in HBM), read while the chain
+ *    runs on the caller's stream; they must stay valid until the event has
+ *    completed (lst_build_event returns after completion).
+ *  - Device memory for one event comes from a caller-owned workspace (for
+ *    example a torch uint8 tensor) of at least lst_workspace_bytes() bytes;
+ *    the library never allocates device memory per event.  The workspace
+ *    holds the event's objects and must outlive the lst_event that uses it.
+ *  - Hit indices in every output are 0-based positions in the caller's hit
+ *    arrays.  Stage ids: 0 MD, 1 LS, 2 T3, 3 T5, 4 pLS, 5 pT3, 6 pT5, 7 TC.
+ *  - One geometry may serve many events and threads; one lst_event must not
+ *    be used by two threads at once.
+ */
+#ifndef LST_H
+#define LST_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LST_OK = 0,
+  LST_E_INVALID = -1,   /* bad argument or invalid input data (e.g. module id out of range, NaN) */
+  LST_E_NOMEM = -2,     /* workspace too small, or a host/device allocation at setup failed */
+  LST_E_CAPACITY = -3,  /* an object count exceeded its capacity; required counts are reported */
+  LST_E_DEVICE = -4,    /* a HIP runtime call failed */
+  LST_E_STATE = -5      /* call made in the wrong state (e.g. event not complete) */
+} lst_status;
+
+typedef struct lst_geometry_s *lst_geometry; /* opaque, library-owned, device-resident */
+typedef struct lst_event_s *lst_event;       /* opaque, library-owned host handle */
+
+/* Detector description (Section 1: bi-layer pT modules) and module map
+ * (Section 2.2).  All arrays are HOST memory, length n_modules unless noted.
+ *  subdet   0 barrel, 1 endcap
+ *  layer    barrel layer 1..6 or endcap disk 1..5
+ *  side     0 barrel, -1 / +1 endcap side
+ *  type     0 PS (macro-pixel), 1 2S (strip)
+ *  pos_lo   barrel: radius of the lower sensor [cm]; endcap: |z| of the lower sensor plane
+ *  pos_up   the same for the upper sensor
+ *  lmin,lmax  range of the long coordinate: z in the barrel, r in the endcap [cm]
+ *  map_offsets  n_modules + 1 CSR offsets; map_targets  n_edges module ids,
+ *               the modules of the next surface linked to each module. */
+typedef struct {
+  int32_t n_modules;
+  const int32_t *subdet, *layer, *side, *type;
+  const float *pos_lo, *pos_up, *lmin, *lmax;
+  int32_t n_edges;
+  const int32_t *map_offsets, *map_targets;
+} lst_geometry_desc;
+
+/* One event, all arrays in DEVICE memory.
+ *  x,y,z [n_hits] hit positions [cm]; module [n_hits] module id or -1 for a
+ *  pixel hit; sensor [n_hits] 0 lower / 1 upper (ignored for pixel hits).
+ *  Seeds (Section 2.4 pixel tracks; n_seeds may be 0 and the pointers NULL):
+ *  px,py,pz [n_seeds] momentum at the innermost pixel hit [GeV]; q [n_seeds]
+ *  charge +1/-1; hits4 [n_seeds x 4] pixel-hit indices, innermost first. */
+typedef struct {
+  int32_t n_hits;
+  const float *x, *y, *z;
+  const int32_t *module, *sensor;
+  int32_t n_seeds;
+  const float *px, *py, *pz;
+  const int32_t *q, *hits4;
+} lst_event_desc;
+
+/* Object capacities of one event.  Counts beyond a capacity are never
+ * truncated silently: the build returns LST_E_CAPACITY and
+ * lst_get_stage_counts() reports the required counts. */
+typedef struct {
+  int64_t md, ls, t3, t5, pt3, pt5;
+} lst_capacity;
+
+/* Uploads the detector and module map and computes the per-module
+ * mini-doublet windows on the device.  *out is owned by the caller and freed
+ * with lst_release_geometry.  Errors: LST_E_INVALID (NULL pointer, negative
+ * size, module id or CSR out of range), LST_E_DEVICE, LST_E_NOMEM. */
+lst_status lst_load_geometry(const lst_geometry_desc *desc, lst_geometry *out);
+lst_status lst_release_geometry(lst_geometry geom);
+
+/* Default capacities for an event of n_hits hits and n_seeds seeds. */
+lst_status lst_default_capacity(int32_t n_hits, int32_t n_seeds, lst_capacity *out);
+
+/* Workspace size in bytes for an event of n_hits hits and n_seeds seeds
+ * with the given capacities (NULL = defaults). */
+lst_status lst_workspace_bytes(lst_geometry geom, int32_t n_hits, int32_t n_seeds, const lst_capacity *cap,
+                               size_t *bytes);
+
+/* Runs the whole chain for one event on `stream` (a hipStream_t; NULL = the
+ * null stream) inside the caller's workspace and waits for it.  *out is a new
+ * event handle (freed with lst_release_event) even when the status is
+ * LST_E_CAPACITY or LST_E_INVALID (so the caller can read the counts).
+ * Errors: LST_E_INVALID (arguments, or invalid hit/seed data detected on the
+ * device), LST_E_NOMEM (ws_bytes too small), LST_E_CAPACITY, LST_E_DEVICE. */
+lst_status lst_build_event(lst_geometry geom, const lst_event_desc *ev, const lst_capacity *cap, void *workspace,
+                           size_t ws_bytes, void *stream, lst_event *out);
+
+/* Asynchronous form: enqueues the chain on `stream` and returns at once.
+ * Inputs and workspace must stay valid until lst_event_wait returns (or
+ * lst_event_query reports completion).  The status of the build is returned
+ * by lst_event_wait. */
+lst_status lst_enqueue_event(lst_geometry geom, const lst_event_desc *ev, const lst_capacity *cap, void *workspace,
+                             size_t ws_bytes, void *stream, lst_event *out);
+/* 1 if the event's device work has completed, 0 if not (into *done). */
+lst_status lst_event_query(lst_event ev, int32_t *done);
+/* Blocks until the event's device work has completed; returns its status. */
+lst_status lst_event_wait(lst_event ev);
+
+/* Track candidates (Section 2.5) of a completed event, copied to HOST
+ * buffers.  Two-call protocol: pass NULL arrays to get *n_tc and
+ * *n_hits_total, then arrays of n_tc (type), n_tc + 1 (offsets) and
+ * n_hits_total (hits).  type: 0 pT5, 1 pT3, 2 T5, 3 pLS, ordered by type,
+ * then by seed index (pT5, pT3, pLS) or by the MDs' (module, lower hit,
+ * upper hit) sequence (T5).  Hit lists: the four pixel hits innermost first,
+ * then the lower and upper hit of each MD from inner to outer (14 / 10 / 10 / 4
+ * hits).  Errors: LST_E_STATE if the event failed or is not complete. */
+lst_status lst_get_track_candidates(lst_event ev, int32_t *n_tc, int32_t *n_hits_total, int32_t *type,
+                                    int32_t *offsets, int32_t *hits);
+
+/* Objects of one stage, copied to HOST buffers (two-call protocol as above;
+ * NULL arrays to query *n).  tuples [n x w] with w = 2, 4, 6, 10, 1, 7, 11 for
+ * stages 0..6: hit indices of the MDs inner to outer (lower, upper), with the
+ * seed index first for pLS/pT3/pT5.  flags [n]: 1 if the object survives
+ * duplicate removal (T5, pLS, pT3, pT5), else 1.  attrs [n x a] with a = 0, 2,
+ * 4, 8, 5, 3, 3:  LS beta_in, beta_out;  T3 kappa, dkappa, chi2_rz, lambda;
+ * T5 kappa, chi2_xy, chi2_rz, lambda, kappa_in, kappa_out, dir_x, dir_y;
+ * pLS pT, cos, sin, lambda, kappa;  pT3/pT5 chi2_xy, chi2_rz, score. */
+lst_status lst_get_stage_objects(lst_event ev, int32_t stage, int32_t *n, int32_t *tuples, int32_t *flags,
+                                 float *attrs);
+
+/* counts[0..7]: object counts per stage (MD .. TC) as built; required[0..7]:
+ * counts that would have been built without capacity limits (equal to
+ * counts unless the status was LST_E_CAPACITY).  Either may be NULL. */
+lst_status lst_get_stage_counts(lst_event ev, int64_t *counts, int64_t *required);
+
+/* Per-module mini-doublet window constants as uploaded (4 floats per module:
+ * W, A1, A2, A3), copied to a HOST buffer of 4 * n_modules floats. */
+lst_status lst_get_module_constants(lst_geometry geom, float *out);
+
+/* Live timing of one kernel launch site (for roofline measurement).  The
+ * chain is a fixed sequence of launch sites, each launched once per event:
+ * lst_kernel_site_count() of them, named by lst_kernel_site_name(i) (NULL
+ * for an invalid index).  lst_set_timed_site(i) makes every later enqueue in
+ * the process bracket site i with two HIP events on the event's stream (-1 =
+ * off); lst_get_site_time() returns that site's duration in milliseconds for
+ * a completed event (LST_E_STATE if no site was timed). */
+int32_t lst_kernel_site_count(void);
+const char *lst_kernel_site_name(int32_t site);
+lst_status lst_set_timed_site(int32_t site);
+lst_status lst_get_site_time(lst_event ev, float *ms);
+
+lst_status lst_release_event(lst_event ev);
+const char *lst_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LST_H */

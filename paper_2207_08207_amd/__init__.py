@@ -1,0 +1,333 @@
+"""Python binding of liblst (include/lst.h): the MI355X Line Segment Tracking chain.
+
+Argument marshalling only: every step of the chain runs in the library's HIP
+kernels.  PyTorch provides device memory (input tensors, the per-event
+workspace as a uint8 tensor, i.e. torch's caching allocator) and streams.
+The functions named ``lst_*`` mirror the C ABI one to one; ``Geometry``,
+``upload_event`` and ``run_event`` are thin conveniences over them.
+
+The library must have been built (``paper_2207_08207_amd.build.build()``);
+importing the binding on a machine without it raises ImportError, and there
+is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "liblst.so")
+
+LST_OK, LST_E_INVALID, LST_E_NOMEM, LST_E_CAPACITY, LST_E_DEVICE, LST_E_STATE = 0, -1, -2, -3, -4, -5
+STAGES = ["MD", "LS", "T3", "T5", "pLS", "pT3", "pT5", "TC"]
+TUPLE_W = [2, 4, 6, 10, 1, 7, 11]
+ATTR_W = [0, 2, 4, 8, 5, 3, 3]
+EXPORTED = ["lst_load_geometry", "lst_release_geometry", "lst_default_capacity", "lst_workspace_bytes",
+            "lst_build_event", "lst_enqueue_event", "lst_event_query", "lst_event_wait",
+            "lst_get_track_candidates", "lst_get_stage_objects", "lst_get_stage_counts",
+            "lst_get_module_constants", "lst_release_event", "lst_last_error", "lst_kernel_site_count",
+            "lst_kernel_site_name", "lst_set_timed_site", "lst_get_site_time"]
+
+
+class LSTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"liblst status {status}: {msg}")
+        self.status = status
+
+
+class lst_geometry_desc(ctypes.Structure):
+    _fields_ = [("n_modules", ctypes.c_int32),
+                ("subdet", ctypes.c_void_p), ("layer", ctypes.c_void_p), ("side", ctypes.c_void_p),
+                ("type", ctypes.c_void_p), ("pos_lo", ctypes.c_void_p), ("pos_up", ctypes.c_void_p),
+                ("lmin", ctypes.c_void_p), ("lmax", ctypes.c_void_p), ("n_edges", ctypes.c_int32),
+                ("map_offsets", ctypes.c_void_p), ("map_targets", ctypes.c_void_p)]
+
+
+class lst_event_desc(ctypes.Structure):
+    _fields_ = [("n_hits", ctypes.c_int32), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p), ("module", ctypes.c_void_p), ("sensor", ctypes.c_void_p),
+                ("n_seeds", ctypes.c_int32), ("px", ctypes.c_void_p), ("py", ctypes.c_void_p),
+                ("pz", ctypes.c_void_p), ("q", ctypes.c_void_p), ("hits4", ctypes.c_void_p)]
+
+
+class lst_capacity(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("md", "ls", "t3", "t5", "pt3", "pt5")]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """dlopen liblst.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"liblst.so not built ({path}); run paper_2207_08207_amd.build.build()")
+    try:
+        import torch  # noqa: F401  (loads the HIP runtime the library then shares)
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    vp, i32, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t
+    P = ctypes.POINTER
+    sig = {
+        "lst_load_geometry": [P(lst_geometry_desc), P(vp)],
+        "lst_release_geometry": [vp],
+        "lst_default_capacity": [i32, i32, P(lst_capacity)],
+        "lst_workspace_bytes": [vp, i32, i32, P(lst_capacity), P(sz)],
+        "lst_build_event": [vp, P(lst_event_desc), P(lst_capacity), vp, sz, vp, P(vp)],
+        "lst_enqueue_event": [vp, P(lst_event_desc), P(lst_capacity), vp, sz, vp, P(vp)],
+        "lst_event_query": [vp, P(i32)],
+        "lst_event_wait": [vp],
+        "lst_get_track_candidates": [vp, P(i32), P(i32), vp, vp, vp],
+        "lst_get_stage_objects": [vp, i32, P(i32), vp, vp, vp],
+        "lst_get_stage_counts": [vp, vp, vp],
+        "lst_get_module_constants": [vp, vp],
+        "lst_release_event": [vp],
+        "lst_set_timed_site": [i32],
+        "lst_get_site_time": [vp, P(ctypes.c_float)],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    lib.lst_last_error.argtypes = []
+    lib.lst_last_error.restype = ctypes.c_char_p
+    lib.lst_kernel_site_count.argtypes = []
+    lib.lst_kernel_site_count.restype = ctypes.c_int32
+    lib.lst_kernel_site_name.argtypes = [i32]
+    lib.lst_kernel_site_name.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def lst_last_error():
+    return load_library().lst_last_error().decode(errors="replace")
+
+
+def _check(status):
+    if status != LST_OK:
+        raise LSTError(status, lst_last_error())
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+# ------------------------------------------------------------- C ABI mirror
+def lst_load_geometry(subdet, layer, side, type, pos_lo, pos_up, lmin, lmax, map_offsets, map_targets):
+    """Host arrays in, opaque geometry handle (int) out."""
+    arrs = [np.ascontiguousarray(a, np.int32) for a in (subdet, layer, side, type)]
+    arrs += [np.ascontiguousarray(a, np.float32) for a in (pos_lo, pos_up, lmin, lmax)]
+    off = np.ascontiguousarray(map_offsets, np.int32)
+    tgt = np.ascontiguousarray(map_targets, np.int32)
+    d = lst_geometry_desc(int(arrs[0].size), *[_ptr(a) for a in arrs], int(tgt.size), _ptr(off), _ptr(tgt))
+    h = ctypes.c_void_p()
+    _check(load_library().lst_load_geometry(ctypes.byref(d), ctypes.byref(h)))
+    return h.value
+
+
+def lst_release_geometry(geom):
+    _check(load_library().lst_release_geometry(geom))
+
+
+def lst_default_capacity(n_hits, n_seeds):
+    c = lst_capacity()
+    _check(load_library().lst_default_capacity(int(n_hits), int(n_seeds), ctypes.byref(c)))
+    return c
+
+
+def lst_workspace_bytes(geom, n_hits, n_seeds, cap=None):
+    b = ctypes.c_size_t()
+    _check(load_library().lst_workspace_bytes(geom, int(n_hits), int(n_seeds),
+                                              ctypes.byref(cap) if cap is not None else None, ctypes.byref(b)))
+    return int(b.value)
+
+
+def _event_desc(t):
+    return lst_event_desc(int(t["x"].numel()), _ptr(t["x"]), _ptr(t["y"]), _ptr(t["z"]), _ptr(t["module"]),
+                          _ptr(t["sensor"]), int(t["px"].numel()), _ptr(t["px"]), _ptr(t["py"]), _ptr(t["pz"]),
+                          _ptr(t["q"]), _ptr(t["hits4"]))
+
+
+def lst_build_event(geom, dev_event, workspace, cap=None, stream=None):
+    """Runs the chain (synchronously) on device tensors; returns (status, event handle)."""
+    d = _event_desc(dev_event)
+    h = ctypes.c_void_p()
+    st = load_library().lst_build_event(geom, ctypes.byref(d), ctypes.byref(cap) if cap is not None else None,
+                                        _ptr(workspace), int(workspace.numel()), stream, ctypes.byref(h))
+    return st, h.value
+
+
+def lst_enqueue_event(geom, dev_event, workspace, cap=None, stream=None):
+    d = _event_desc(dev_event)
+    h = ctypes.c_void_p()
+    st = load_library().lst_enqueue_event(geom, ctypes.byref(d), ctypes.byref(cap) if cap is not None else None,
+                                          _ptr(workspace), int(workspace.numel()), stream, ctypes.byref(h))
+    return st, h.value
+
+
+def lst_event_query(ev):
+    done = ctypes.c_int32()
+    _check(load_library().lst_event_query(ev, ctypes.byref(done)))
+    return bool(done.value)
+
+
+def lst_event_wait(ev):
+    return load_library().lst_event_wait(ev)
+
+
+def lst_get_track_candidates(ev):
+    lib = load_library()
+    n, nh = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.lst_get_track_candidates(ev, ctypes.byref(n), ctypes.byref(nh), None, None, None))
+    ty = np.zeros(n.value, np.int32)
+    off = np.zeros(n.value + 1, np.int32)
+    hits = np.zeros(nh.value, np.int32)
+    _check(lib.lst_get_track_candidates(ev, ctypes.byref(n), ctypes.byref(nh), _ptr(ty), _ptr(off), _ptr(hits)))
+    return ty, off, hits
+
+
+def lst_get_stage_objects(ev, stage):
+    lib = load_library()
+    n = ctypes.c_int32()
+    _check(lib.lst_get_stage_objects(ev, int(stage), ctypes.byref(n), None, None, None))
+    t = np.zeros((n.value, TUPLE_W[stage]), np.int32)
+    f = np.zeros(n.value, np.int32)
+    a = np.zeros((n.value, ATTR_W[stage]), np.float32)
+    _check(lib.lst_get_stage_objects(ev, int(stage), ctypes.byref(n), _ptr(t), _ptr(f), _ptr(a)))
+    return t, f, a
+
+
+def lst_get_stage_counts(ev):
+    c = np.zeros(8, np.int64)
+    r = np.zeros(8, np.int64)
+    _check(load_library().lst_get_stage_counts(ev, _ptr(c), _ptr(r)))
+    return c, r
+
+
+def lst_get_module_constants(geom, n_modules):
+    out = np.zeros((n_modules, 4), np.float32)
+    _check(load_library().lst_get_module_constants(geom, _ptr(out)))
+    return out
+
+
+def lst_release_event(ev):
+    _check(load_library().lst_release_event(ev))
+
+
+def lst_kernel_sites():
+    lib = load_library()
+    return [lib.lst_kernel_site_name(i).decode() for i in range(lib.lst_kernel_site_count())]
+
+
+def lst_set_timed_site(site):
+    _check(load_library().lst_set_timed_site(int(site)))
+
+
+def lst_get_site_time(ev):
+    ms = ctypes.c_float()
+    _check(load_library().lst_get_site_time(ev, ctypes.byref(ms)))
+    return float(ms.value)
+
+
+# ------------------------------------------------------------- conveniences
+class Geometry:
+    """A detector uploaded to the device (owns the lst_geometry handle)."""
+
+    def __init__(self, geom):
+        m = geom.module_arrays()
+        self.n_modules = int(geom.n_modules)
+        self.handle = lst_load_geometry(m["subdet"], m["layer"], m["side"], m["type"], m["pos_lo"], m["pos_up"],
+                                        m["lmin"], m["lmax"], geom.map_offsets, geom.map_targets)
+
+    def module_constants(self):
+        return lst_get_module_constants(self.handle, self.n_modules)
+
+    def close(self):
+        if self.handle:
+            lst_release_geometry(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def upload_event(ev, device="cuda"):
+    """Copies an event's arrays (numpy) to device tensors in the C ABI's layout."""
+    import torch
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+    i = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.int32)).to(device)
+    return dict(x=f(ev.x), y=f(ev.y), z=f(ev.z), module=i(ev.module), sensor=i(ev.sensor),
+                px=f(ev.px), py=f(ev.py), pz=f(ev.pz), q=i(ev.q), hits4=i(np.asarray(ev.hits4).reshape(-1)))
+
+
+class EventResult:
+    """A built event: the library's handle plus the workspace it lives in."""
+
+    def __init__(self, handle, workspace, status):
+        self.handle, self.workspace, self.status = handle, workspace, status
+
+    def track_candidates(self):
+        return lst_get_track_candidates(self.handle)
+
+    def stage(self, stage):
+        return lst_get_stage_objects(self.handle, stage)
+
+    def counts(self):
+        return lst_get_stage_counts(self.handle)
+
+    def close(self):
+        if self.handle:
+            lst_release_event(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def alloc_workspace(geom, n_hits, n_seeds, cap=None, device="cuda"):
+    import torch
+    nb = lst_workspace_bytes(geom.handle, n_hits, n_seeds, cap)
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def run_event(geom, dev_event, cap=None, workspace=None, stream=None, grow=True):
+    """Builds one event; on LST_E_CAPACITY grows the capacities to the reported needs and reruns."""
+    import torch
+    n_hits, n_seeds = int(dev_event["x"].numel()), int(dev_event["px"].numel())
+    if cap is None:
+        cap = lst_default_capacity(n_hits, n_seeds)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(4):
+        need = lst_workspace_bytes(geom.handle, n_hits, n_seeds, cap)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(need, dtype=torch.uint8, device=dev_event["x"].device)
+        st, h = lst_build_event(geom.handle, dev_event, workspace, cap, stream)
+        if st == LST_E_CAPACITY and grow:
+            _, req = lst_get_stage_counts(h)
+            lst_release_event(h)
+            names = ["md", "ls", "t3", "t5", None, "pt3", "pt5"]
+            for k, nm in enumerate(names):
+                if nm and req[k] > getattr(cap, nm):
+                    setattr(cap, nm, int(req[k] * 1.25) + 1024)
+            continue
+        if st != LST_OK:
+            msg = lst_last_error()
+            if h:
+                lst_release_event(h)
+            raise LSTError(st, msg)
+        return EventResult(h, workspace, st)
+    raise LSTError(LST_E_CAPACITY, "capacities kept growing")

@@ -1,0 +1,956 @@
+// gfx950 kernels of the Line Segment Tracking chain (arXiv:2207.08207).
+//
+// Every stage follows one pattern: count objects per parent (module, MD, LS,
+// T3, seed), exclusive-scan the counts on the device, then fill each parent's
+// objects at its scanned offset in a fixed order.  No global atomics decide
+// an output position, so the object arrays are identical run to run; the
+// only atomics are histogram counts and the scatter into per-MD / per-hit
+// incidence lists, whose consumers are order-independent.  Object counts
+// stay on the device: later kernels read them and stride over them, so the
+// whole chain is enqueued without a host round trip.
+#include "lst_select.hpp"
+#include "lst_ws.hpp"
+
+namespace lst {
+
+constexpr int kBlock = 256;
+constexpr int kWaves = kBlock / 64;
+constexpr int kScanItems = 8;                       // per thread
+constexpr int kScanTile = kBlock * kScanItems;      // per block
+constexpr int kMaxScanBlocks = 4096;                // second level handled by one block
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Exclusive prefix of `flag` over the block in thread order; *total = block count.
+__device__ __forceinline__ int block_prefix(bool flag, int *s_wave, int *total) {
+  const unsigned long long m = __ballot(flag);
+  const int wid = threadIdx.x >> 6;
+  const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+  if (lane_id() == 0) s_wave[wid] = __popcll(m);
+  __syncthreads();
+  int base = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    const int c = s_wave[w];
+    base += (w < wid) ? c : 0;
+    tot += c;
+  }
+  __syncthreads();
+  *total = tot;
+  return base + pre;
+}
+
+__device__ __forceinline__ int block_sum(int v, int *s_red) {
+  // wave reduction by shuffles, then across waves in LDS
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (lane_id() == 0) s_red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) t += s_red[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ int dev_count(const int *p, int fallback) { return p ? *p : fallback; }
+
+// ------------------------------------------------------------------ fill
+__global__ void k_fill(int *p, long n, int v) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ------------------------------------------------------------------ scan
+// Exclusive scan of in[0..n) into out[0..n], out[n] = total; n = *n_dev (or
+// n_fix).  Three passes: block sums, scan of block sums, block scans.
+__global__ void k_scan_reduce(const int *in, const int *n_dev, int n_fix, int *bsum) {
+  __shared__ int s_red[kWaves];
+  const int n = dev_count(n_dev, n_fix);
+  const long base = (long)blockIdx.x * kScanTile;
+  if (base >= n && blockIdx.x > 0) return;
+  int v = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const long i = base + (long)k * kBlock + threadIdx.x;
+    if (i < n) v += in[i];
+  }
+  v = block_sum(v, s_red);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = v;
+}
+
+__global__ void k_scan_top(int *bsum, const int *n_dev, int n_fix, int *total_req, int *total_clamped, int cap,
+                           int *status) {
+  // single block of 1024 threads: exclusive scan of up to kMaxScanBlocks block sums
+  __shared__ int s[kMaxScanBlocks];
+  __shared__ int s_w[16];
+  const int n = dev_count(n_dev, n_fix);
+  const int nb = n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
+  for (int i = threadIdx.x; i < kMaxScanBlocks; i += blockDim.x) s[i] = (i < nb) ? bsum[i] : 0;
+  __syncthreads();
+  // each thread scans 4 consecutive entries
+  const int t = threadIdx.x;
+  int a0 = s[4 * t], a1 = s[4 * t + 1], a2 = s[4 * t + 2], a3 = s[4 * t + 3];
+  int sum = a0 + a1 + a2 + a3;
+  // inclusive scan of per-thread sums across the block
+  int x = sum;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane_id() >= o) x += y;
+  }
+  if (lane_id() == 63) s_w[t >> 6] = x;
+  __syncthreads();
+  int wbase = 0;
+  for (int w = 0; w < (t >> 6); ++w) wbase += s_w[w];
+  const int excl = wbase + x - sum;
+  __syncthreads();
+  s[4 * t] = excl;
+  s[4 * t + 1] = excl + a0;
+  s[4 * t + 2] = excl + a0 + a1;
+  s[4 * t + 3] = excl + a0 + a1 + a2;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nb; i += blockDim.x) bsum[i] = s[i];
+  if (threadIdx.x == blockDim.x - 1) {
+    const int tot = excl + sum;
+    if (total_req) *total_req = tot;
+    if (total_clamped) {
+      *total_clamped = tot < cap ? tot : cap;
+      if (tot > cap) atomicOr(status, (int)ST_CAPACITY);
+    }
+  }
+}
+
+__global__ void k_scan_apply(const int *in, int *out, const int *n_dev, int n_fix, const int *bsum) {
+  __shared__ int s_wave[kWaves];
+  const int n = dev_count(n_dev, n_fix);
+  const long base = (long)blockIdx.x * kScanTile;
+  if (base > n) return;
+  int run = bsum[blockIdx.x];
+  // the block's tile in kScanItems rounds of kBlock consecutive items
+  for (int k = 0; k < kScanItems; ++k) {
+    const long i = base + (long)k * kBlock + threadIdx.x;
+    const int v = (i < n) ? in[i] : 0;
+    // inclusive scan within the wave
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane_id() >= o) x += y;
+    }
+    if (lane_id() == 63) s_wave[threadIdx.x >> 6] = x;
+    __syncthreads();
+    int wb = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+      const int c = s_wave[w];
+      wb += (w < (int)(threadIdx.x >> 6)) ? c : 0;
+      tot += c;
+    }
+    if (i < n) out[i] = run + wb + x - v;
+    if (i == n) out[i] = run + wb + x - v;  // out[n] = total
+    __syncthreads();
+    run += tot;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && n == 0) out[0] = 0;
+}
+
+static inline int grid_for(long n) {
+  long g = (n + kBlock - 1) / kBlock;
+  if (g < 1) g = 1;
+  if (g > 8192) g = 8192;
+  return (int)g;
+}
+
+// out[0..n] exclusive scan of in[0..n); n on the device (n_dev) or fixed.
+static void scan(const int *in, int *out, const int *n_dev, int n_fix, int n_cap, int *tmp, int *total_req,
+                 int *total_clamped, int cap, int *status, hipStream_t st) {
+  const int nb = (n_cap + kScanTile) / kScanTile;  // tiles covering n_cap + 1 outputs
+  k_scan_reduce<<<nb, kBlock, 0, st>>>(in, n_dev, n_fix, tmp);
+  k_scan_top<<<1, 1024, 0, st>>>(tmp, n_dev, n_fix, total_req, total_clamped, cap, status);
+  k_scan_apply<<<nb, kBlock, 0, st>>>(in, out, n_dev, n_fix, tmp);
+}
+
+// ------------------------------------------------------------- windows
+__global__ void k_module_windows(const int *info, const float *pos_lo, const float *pos_up, const float *lmin,
+                                 const float *lmax, int n_mod, float4 *win) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_mod) return;
+  double w[4];
+  module_windows((info[m] >> 1) & 1, info[m] & 1, (double)pos_lo[m], (double)pos_up[m], (double)lmin[m],
+                 (double)lmax[m], w);
+  win[m] = make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
+}
+
+void launch_module_windows(const int *info, const float *pos_lo, const float *pos_up, const float *lmin,
+                           const float *lmax, int n_mod, float4 *win, hipStream_t st) {
+  k_module_windows<<<(n_mod + 127) / 128, 128, 0, st>>>(info, pos_lo, pos_up, lmin, lmax, n_mod, win);
+}
+
+// ------------------------------------------------------------- a0: hits
+// Validation of the inputs and histogram of outer-tracker hits per (module, sensor).
+__global__ void k_hits_count(Ws w, int n_mod) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < w.n_hits; i += gridDim.x * blockDim.x) {
+    const int m = w.module[i];
+    const float x = w.x[i], y = w.y[i], z = w.z[i];
+    bool bad = !(isfinite(x) && isfinite(y) && isfinite(z)) || m < -1 || m >= n_mod;
+    if (m >= 0) {
+      const int sn = w.sensor[i];
+      bad |= (sn != 0 && sn != 1);
+      if (!bad) atomicAdd(&w.bcnt[2 * m + sn], 1);
+    }
+    if (bad) atomicOr(&w.ctr[C_STATUS], (int)ST_BAD_HIT);
+  }
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
+    bool bad = !(w.q[s] == 1 || w.q[s] == -1) || !(isfinite(w.px[s]) && isfinite(w.py[s]) && isfinite(w.pz[s]));
+    bad |= !(w.px[s] * w.px[s] + w.py[s] * w.py[s] > 0.0f);
+    for (int k = 0; k < 4; ++k) {
+      const int h = w.hits4[4 * s + k];
+      bad |= (h < 0 || h >= w.n_hits);
+      if (h >= 0 && h < w.n_hits) bad |= (w.module[h] != -1);
+    }
+    if (bad) atomicOr(&w.ctr[C_STATUS], (int)ST_BAD_SEED);
+  }
+}
+
+__global__ void k_hits_scatter(Ws w, int n_mod) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < w.n_hits; i += gridDim.x * blockDim.x) {
+    const int m = w.module[i];
+    if (m < 0 || m >= n_mod) continue;
+    const int sn = w.sensor[i];
+    if (sn != 0 && sn != 1) continue;
+    const float x = w.x[i], y = w.y[i], z = w.z[i];
+    if (!(isfinite(x) && isfinite(y) && isfinite(z))) continue;
+    const int key = 2 * m + sn;
+    const int slot = atomicAdd(&w.bcur[key], 1);
+    w.hidx_tmp[w.boff[key] + slot] = i;
+  }
+}
+
+// One wave per bucket: order the bucket by input index (stable bucketing) and
+// write the hits' coordinates and radius in bucket order.
+__global__ void k_bucket_sort(Ws w, int n_buckets) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wave >= n_buckets) return;
+  const int b0 = w.boff[wave], n = w.boff[wave + 1] - b0;
+  for (int k = lane_id(); k < n; k += 64) {
+    const int me = w.hidx_tmp[b0 + k];
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += (w.hidx_tmp[b0 + j] < me) ? 1 : 0;
+    const float x = w.x[me], y = w.y[me], z = w.z[me];
+    w.hidx[b0 + rank] = me;
+    w.hpos[b0 + rank] = make_float4(x, y, z, sqrtf(x * x + y * y));
+  }
+}
+
+// ------------------------------------------------------------- a1: MD
+constexpr int kMdStage = 512;  // hits per sensor staged in LDS
+
+// One block per module; pairs (lower i, upper j) in row-major order.
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_md(Ws w, DevGeom g) {
+  __shared__ float4 s_lo[kMdStage], s_up[kMdStage];
+  __shared__ int s_wave[kWaves];
+  const int m = blockIdx.x;
+  const int lo0 = w.boff[2 * m], nlo = w.boff[2 * m + 1] - lo0;
+  const int up0 = w.boff[2 * m + 1], nup = w.boff[2 * m + 2] - up0;
+  const long npair = (long)nlo * nup;
+  if (npair == 0) {
+    if (!FILL && threadIdx.x == 0) w.md_cnt[m] = 0;
+    return;
+  }
+  for (int k = threadIdx.x; k < nlo && k < kMdStage; k += kBlock) s_lo[k] = w.hpos[lo0 + k];
+  for (int k = threadIdx.x; k < nup && k < kMdStage; k += kBlock) s_up[k] = w.hpos[up0 + k];
+  __syncthreads();
+  const float4 win = g.win[m];
+  const ModInfo mi{g.info[m]};
+  int base = FILL ? w.md_off[m] : 0;
+  int cnt = 0;
+  for (long p0 = 0; p0 < npair; p0 += kBlock) {
+    const long p = p0 + threadIdx.x;
+    bool pass = false;
+    int i = 0, j = 0;
+    float4 hi, hj;
+    if (p < npair) {
+      i = (int)(p / nup);
+      j = (int)(p - (long)i * nup);
+      hi = i < kMdStage ? s_lo[i] : w.hpos[lo0 + i];
+      hj = j < kMdStage ? s_up[j] : w.hpos[up0 + j];
+      pass = md_pass(hi, hj, win, mi);
+    }
+    if (!FILL) {
+      cnt += pass ? 1 : 0;
+    } else {
+      int tot;
+      const int pos = base + block_prefix(pass, s_wave, &tot);
+      if (pass && pos < w.cap_md) {
+        w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
+        w.md_mod[pos] = m;
+        w.md_pos[pos] = hi;
+        w.md_stub[pos] = md_stub(hi, hj, mi);
+      }
+      base += tot;
+    }
+  }
+  if (!FILL) {
+    cnt = block_sum(cnt, s_wave);
+    if (threadIdx.x == 0) w.md_cnt[m] = cnt;
+  }
+}
+
+// ------------------------------------------------------------- a2: LS
+// One thread per inner MD a; candidates: the MDs of every module linked to a's module.
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_ls(Ws w, DevGeom g) {
+  const int n_md = w.ctr[C_NMD];
+  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n_md; a += gridDim.x * blockDim.x) {
+    const int ma = w.md_mod[a];
+    const float4 A = w.md_pos[a];
+    const float2 sa = w.md_stub[a];
+    const ModInfo mia{g.info[ma]};
+    int out = FILL ? w.ls_off[a] : 0;
+    int cnt = 0;
+    const int e1 = g.map_off[ma + 1];
+    for (int e = g.map_off[ma]; e < e1; ++e) {
+      const int mb = g.map_tgt[e];
+      const ModInfo mib{g.info[mb]};
+      const int b1 = min(w.md_off[mb + 1], n_md);
+      for (int b = w.md_off[mb]; b < b1; ++b) {
+        float2 beta;
+        if (ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, mib, &beta)) {
+          if (FILL) {
+            if (out < w.cap_ls) {
+              w.ls_md[out] = make_int2(a, b);
+              w.ls_beta[out] = beta;
+            }
+            ++out;
+          } else {
+            ++cnt;
+          }
+        }
+      }
+    }
+    if (!FILL) w.ls_cnt[a] = cnt;
+  }
+}
+
+// ------------------------------------------------------------- a3: T3
+// One thread per inner segment (a, b); partners: the segments whose inner MD is b.
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_t3(Ws w, DevGeom g) {
+  const int n_ls = w.ctr[C_NLS];
+  for (int l1 = blockIdx.x * blockDim.x + threadIdx.x; l1 < n_ls; l1 += gridDim.x * blockDim.x) {
+    const int2 ab = w.ls_md[l1];
+    const float4 A = w.md_pos[ab.x], B = w.md_pos[ab.y];
+    const ModInfo mA{g.info[w.md_mod[ab.x]]}, mB{g.info[w.md_mod[ab.y]]};
+    int out = FILL ? w.t3_off[l1] : 0;
+    int cnt = 0;
+    const int l2e = min(w.ls_off[ab.y + 1], n_ls);
+    for (int l2 = w.ls_off[ab.y]; l2 < l2e; ++l2) {
+      const int c = w.ls_md[l2].y;
+      const ModInfo mC{g.info[w.md_mod[c]]};
+      float4 attr;
+      if (t3_pass(A, B, w.md_pos[c], mA, mB, mC, &attr)) {
+        if (FILL) {
+          if (out < w.cap_t3) {
+            w.t3_md[out] = make_int4(ab.x, ab.y, c, l1);
+            w.t3_attr[out] = attr;
+            w.t3_first[out] = make_float2(A.x, A.y);
+          }
+          ++out;
+        } else {
+          ++cnt;
+        }
+      }
+    }
+    if (!FILL) w.t3_cnt[l1] = cnt;
+  }
+}
+
+// ------------------------------------------------------------- a4: T5
+// One thread per inner triplet (a, b, c); partners: the triplets whose first MD is c.
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_t5(Ws w, DevGeom g) {
+  const int n_t3 = w.ctr[C_NT3];
+  const int n_ls = w.ctr[C_NLS];
+  for (int t1 = blockIdx.x * blockDim.x + threadIdx.x; t1 < n_t3; t1 += gridDim.x * blockDim.x) {
+    const int4 abc = w.t3_md[t1];
+    float4 P[5];
+    ModInfo M[5];
+    P[0] = w.md_pos[abc.x]; P[1] = w.md_pos[abc.y]; P[2] = w.md_pos[abc.z];
+    M[0].bits = g.info[w.md_mod[abc.x]]; M[1].bits = g.info[w.md_mod[abc.y]]; M[2].bits = g.info[w.md_mod[abc.z]];
+    const float4 tin = w.t3_attr[t1];
+    // triplets with first MD c: those built from segments with inner MD c
+    const int lsb = min(w.ls_off[abc.z], n_ls), lse = min(w.ls_off[abc.z + 1], n_ls);
+    const int t2b = w.t3_off[lsb], t2e = min(w.t3_off[lse], n_t3);
+    int out = FILL ? w.t5_off[t1] : 0;
+    int cnt = 0;
+    for (int t2 = t2b; t2 < t2e; ++t2) {
+      const int4 cde = w.t3_md[t2];
+      P[3] = w.md_pos[cde.y];
+      P[4] = w.md_pos[cde.z];
+      M[3].bits = g.info[w.md_mod[cde.y]];
+      M[4].bits = g.info[w.md_mod[cde.z]];
+      float at[8];
+      if (t5_pass(P, M, tin, w.t3_attr[t2], at)) {
+        if (FILL) {
+          if (out < w.cap_t5) {
+            w.t5_t3[out] = make_int2(t1, t2);
+            int *md = w.t5_md + 5 * (long)out;
+            md[0] = abc.x; md[1] = abc.y; md[2] = abc.z; md[3] = cde.y; md[4] = cde.z;
+            float *dst = w.t5_attr + 8 * (long)out;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) dst[k] = at[k];
+          }
+          ++out;
+        } else {
+          ++cnt;
+        }
+      }
+    }
+    if (!FILL) w.t5_cnt[t1] = cnt;
+  }
+}
+
+// ------------------------------------------------------------- a5: T5 dedup
+__global__ void k_t5_inc_count(Ws w) {
+  const int n = w.ctr[C_NT5];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    for (int k = 0; k < 5; ++k) atomicAdd(&w.inc_cnt[w.t5_md[5 * (long)t + k]], 1);
+}
+__global__ void k_t5_inc_scatter(Ws w) {
+  const int n = w.ctr[C_NT5];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    for (int k = 0; k < 5; ++k) {
+      const int md = w.t5_md[5 * (long)t + k];
+      w.inc_list[w.inc_off[md] + atomicAdd(&w.inc_cur[md], 1)] = t;
+    }
+}
+
+__device__ __forceinline__ void t5_hits(const Ws &w, int t, int *h) {
+  const int *md = w.t5_md + 5 * (long)t;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const int2 hh = w.md_hits[md[k]];
+    h[2 * k] = hh.x;
+    h[2 * k + 1] = hh.y;
+  }
+}
+// (score, tuple) of u strictly smaller than (score, tuple) of t
+template <int N>
+__device__ __forceinline__ bool better(float su, const int *hu, float st, const int *ht) {
+  if (su < st) return true;
+  if (st < su) return false;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    if (hu[k] < ht[k]) return true;
+    if (ht[k] < hu[k]) return false;
+  }
+  return false;
+}
+
+// A T5 is dropped when another T5 sharing at least two MDs has a smaller (chi2_xy, hit tuple).
+__global__ void k_t5_dedup(Ws w) {
+  const int n = w.ctr[C_NT5];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    int mt[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) mt[k] = w.t5_md[5 * (long)t + k];
+    int ht[10];
+    t5_hits(w, t, ht);
+    const float st = w.t5_attr[8 * (long)t + 1];
+    bool keep = true;
+    for (int k = 0; k < 5 && keep; ++k) {
+      const int md = mt[k];
+      for (int q = w.inc_off[md]; q < w.inc_off[md + 1] && keep; ++q) {
+        const int u = w.inc_list[q];
+        if (u == t) continue;
+        int shared = 0;
+        const int *mu = w.t5_md + 5 * (long)u;
+#pragma unroll
+        for (int i = 0; i < 5; ++i) {
+          const int v = mu[i];
+          shared += (v == mt[0] || v == mt[1] || v == mt[2] || v == mt[3] || v == mt[4]) ? 1 : 0;
+        }
+        if (shared < 2) continue;
+        int hu[10];
+        t5_hits(w, u, hu);
+        if (better<10>(w.t5_attr[8 * (long)u + 1], hu, st, ht)) keep = false;
+      }
+    }
+    w.t5_keep[t] = keep ? 1 : 0;
+    const int a = mt[0];
+    w.t5_first[t] = make_float2(w.md_pos[a].x, w.md_pos[a].y);
+  }
+}
+
+// ------------------------------------------------------------- a6: pLS
+__device__ __forceinline__ Seed load_seed(const Ws &w, int s) {
+  const float *p = w.pls + 8 * (long)s;
+  Seed sd;
+  sd.pt = p[0]; sd.cx = p[1]; sd.cy = p[2]; sd.lam = p[3]; sd.ks = p[4]; sd.x0 = p[5]; sd.y0 = p[6]; sd.z0 = p[7];
+  return sd;
+}
+
+__global__ void k_pls(Ws w) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
+    const float px = w.px[s], py = w.py[s], pz = w.pz[s];
+    const float pt = sqrtf(px * px + py * py);
+    float *o = w.pls + 8 * (long)s;
+    o[0] = pt;
+    o[1] = px / pt;
+    o[2] = py / pt;
+    o[3] = pz / pt;
+    o[4] = (-(float)w.q[s] * kCurv) / pt;
+    int h0 = w.hits4[4 * (long)s];
+    h0 = (h0 >= 0 && h0 < w.n_hits) ? h0 : 0;
+    o[5] = w.x[h0];
+    o[6] = w.y[h0];
+    o[7] = w.z[h0];
+    for (int k = 0; k < 4; ++k) {
+      const int h = w.hits4[4 * (long)s + k];
+      if (h >= 0 && h < w.n_hits) atomicAdd(&w.ph_cnt[h], 1);
+    }
+  }
+}
+__global__ void k_ph_scatter(Ws w) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x)
+    for (int k = 0; k < 4; ++k) {
+      const int h = w.hits4[4 * (long)s + k];
+      if (h >= 0 && h < w.n_hits) w.ph_list[w.ph_off[h] + atomicAdd(&w.ph_cur[h], 1)] = s;
+    }
+}
+// pLS duplicate removal: seeds sharing at least 3 pixel hits; the lower seed index wins.
+__global__ void k_pls_dedup(Ws w) {
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
+    int hs[4];
+    for (int k = 0; k < 4; ++k) hs[k] = w.hits4[4 * (long)s + k];
+    bool keep = true;
+    for (int k = 0; k < 4 && keep; ++k) {
+      const int h = hs[k];
+      if (h < 0 || h >= w.n_hits) continue;
+      for (int q = w.ph_off[h]; q < w.ph_off[h + 1] && keep; ++q) {
+        const int t = w.ph_list[q];
+        if (t >= s) continue;
+        int sh = 0;
+        for (int i = 0; i < 4; ++i) {
+          const int hi = hs[i];
+          bool f = false;
+          for (int j = 0; j < 4; ++j) f |= (w.hits4[4 * (long)t + j] == hi);
+          sh += f ? 1 : 0;
+        }
+        if (sh >= 3) keep = false;
+      }
+    }
+    w.pls_keep[s] = keep ? 1 : 0;
+  }
+}
+
+// ------------------------------------------------------------- a7: pT3 / pT5
+// One block per seed; the block strides over all triplets (K = 3) or
+// surviving quintuplets (K = 5) in object order, window first.
+template <int K, bool FILL>
+__global__ __launch_bounds__(kBlock) void k_pt(Ws w, DevGeom g) {
+  __shared__ int s_wave[kWaves];
+  const int s = blockIdx.x;
+  if (s >= w.n_seeds) return;
+  const Seed sd = load_seed(w, s);
+  const int n_obj = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
+  const float2 *first = K == 3 ? w.t3_first : w.t5_first;
+  int base = FILL ? (K == 3 ? w.pt3_off[s] : w.pt5_off[s]) : 0;
+  int cnt = 0;
+  for (int t0 = 0; t0 < n_obj; t0 += kBlock) {
+    const int t = t0 + threadIdx.x;
+    bool pass = false;
+    float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t < n_obj && (K == 3 || w.t5_keep[t])) {
+      const float2 f = first[t];
+      if (seed_box(sd, f.x, f.y)) {
+        float4 P[K];
+        ModInfo M[K];
+        float kT, dkT;
+        if constexpr (K == 3) {
+          const int4 abc = w.t3_md[t];
+          const int md[3] = {abc.x, abc.y, abc.z};
+#pragma unroll
+          for (int k = 0; k < K; ++k) { P[k] = w.md_pos[md[k]]; M[k].bits = g.info[w.md_mod[md[k]]]; }
+          const float4 a3 = w.t3_attr[t];
+          kT = a3.x; dkT = a3.y;
+        } else {
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const int md = w.t5_md[5 * (long)t + k];
+            P[k] = w.md_pos[md];
+            M[k].bits = g.info[w.md_mod[md]];
+          }
+          const float4 a3 = w.t3_attr[w.t5_t3[t].y];
+          kT = a3.x; dkT = a3.y;
+        }
+        pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
+      }
+    }
+    if (!FILL) {
+      cnt += pass ? 1 : 0;
+    } else {
+      int tot;
+      const int pos = base + block_prefix(pass, s_wave, &tot);
+      const int cap = K == 3 ? w.cap_pt3 : w.cap_pt5;
+      if (pass && pos < cap) {
+        (K == 3 ? w.pt3_so : w.pt5_so)[pos] = make_int2(s, t);
+        (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = attr;
+      }
+      base += tot;
+    }
+  }
+  if (!FILL) {
+    cnt = block_sum(cnt, s_wave);
+    if (threadIdx.x == 0) (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s] = cnt;
+  }
+}
+
+template <int K>
+__global__ void k_pt_obj_count(Ws w) {
+  const int n = K == 3 ? w.ctr[C_NPT3] : w.ctr[C_NPT5];
+  const int2 *so = K == 3 ? w.pt3_so : w.pt5_so;
+  int *cnt = K == 3 ? w.o3_cnt : w.o5_cnt;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) atomicAdd(&cnt[so[i].y], 1);
+}
+template <int K>
+__global__ void k_pt_obj_scatter(Ws w) {
+  const int n = K == 3 ? w.ctr[C_NPT3] : w.ctr[C_NPT5];
+  const int2 *so = K == 3 ? w.pt3_so : w.pt5_so;
+  const int *off = K == 3 ? w.o3_off : w.o5_off;
+  int *cur = K == 3 ? w.o3_cur : w.o5_cur;
+  int *lst = K == 3 ? w.o3_list : w.o5_list;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int t = so[i].y;
+    lst[off[t] + atomicAdd(&cur[t], 1)] = i;
+  }
+}
+
+template <int K>
+__device__ __forceinline__ void obj_hits(const Ws &w, int t, int *h) {
+  if constexpr (K == 3) {
+    const int4 abc = w.t3_md[t];
+    const int md[3] = {abc.x, abc.y, abc.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int2 hh = w.md_hits[md[k]];
+      h[2 * k] = hh.x;
+      h[2 * k + 1] = hh.y;
+    }
+  } else {
+    t5_hits(w, t, h);
+  }
+}
+
+// pT duplicate removal: dropped when another entry with the same seed or the
+// same outer object has a smaller (score, seed, hit tuple).
+template <int K>
+__global__ void k_pt_dedup(Ws w) {
+  const int n = K == 3 ? w.ctr[C_NPT3] : w.ctr[C_NPT5];
+  const int2 *so = K == 3 ? w.pt3_so : w.pt5_so;
+  const float4 *at = K == 3 ? w.pt3_attr : w.pt5_attr;
+  const int *soff = K == 3 ? w.pt3_off : w.pt5_off;
+  const int *ooff = K == 3 ? w.o3_off : w.o5_off;
+  const int *olst = K == 3 ? w.o3_list : w.o5_list;
+  int *keep = K == 3 ? w.pt3_keep : w.pt5_keep;
+  constexpr int H = 2 * K + 1;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int2 me = so[i];
+    int ti[H];
+    ti[0] = me.x;
+    obj_hits<K>(w, me.y, ti + 1);
+    const float si = at[i].z;
+    bool kp = true;
+    const int j1 = min(soff[me.x + 1], n);
+    for (int j = soff[me.x]; j < j1 && kp; ++j) {
+      if (j == i) continue;
+      int tj[H];
+      tj[0] = so[j].x;
+      obj_hits<K>(w, so[j].y, tj + 1);
+      if (better<H>(at[j].z, tj, si, ti)) kp = false;
+    }
+    for (int q = ooff[me.y]; q < ooff[me.y + 1] && kp; ++q) {
+      const int j = olst[q];
+      if (j == i) continue;
+      int tj[H];
+      tj[0] = so[j].x;
+#pragma unroll
+      for (int k = 1; k < H; ++k) tj[k] = ti[k];
+      if (better<H>(at[j].z, tj, si, ti)) kp = false;
+    }
+    keep[i] = kp ? 1 : 0;
+  }
+}
+
+// ------------------------------------------------------------- a8: TC
+__device__ __forceinline__ Dir dir_of_seed(const Ws &w, int s) { return seed_dir(load_seed(w, s)); }
+__device__ __forceinline__ Dir dir_of_t5(const Ws &w, int t) {
+  const float *a = w.t5_attr + 8 * (long)t;
+  Dir d;
+  d.dx = a[6]; d.dy = a[7]; d.lam = a[3];
+  return d;
+}
+
+// pT5 TCs: every surviving pT5; marks its seed and T5 as used.
+__global__ void k_tc_pt5(Ws w) {
+  const int n = w.ctr[C_NPT5];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int k = w.pt5_keep[i];
+    w.f_pt5[i] = k;
+    if (k) {
+      w.seed_used[w.pt5_so[i].x] = 1;
+      w.t5_used[w.pt5_so[i].y] = 1;
+    }
+  }
+}
+__global__ void k_tc_dirs_pt5(Ws w) {
+  const int n = w.ctr[C_NPT5];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (w.f_pt5[i]) {
+      const Dir d = dir_of_seed(w, w.pt5_so[i].x);
+      w.dir_pt5[w.p_pt5[i]] = make_float4(d.dx, d.dy, d.lam, 0.f);
+    }
+}
+
+__device__ __forceinline__ bool near_any(const Dir &d, const float4 *lst, int n, float D) {
+  for (int j = 0; j < n; ++j) {
+    const float4 e = lst[j];
+    Dir o;
+    o.dx = e.x; o.dy = e.y; o.lam = e.z;
+    if (near_dir(d, o, D)) return true;
+  }
+  return false;
+}
+
+// pT3 TCs: surviving pT3 whose seed no TC-pT5 uses and that is not near any TC-pT5.
+__global__ void k_tc_pt3(Ws w) {
+  const int n = w.ctr[C_NPT3];
+  const int n0 = w.ctr[C_NTC0];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    int f = 0;
+    if (w.pt3_keep[i]) {
+      const int s = w.pt3_so[i].x;
+      if (!w.seed_used[s]) f = near_any(dir_of_seed(w, s), w.dir_pt5, n0, kDpT3) ? 0 : 1;
+    }
+    w.f_pt3[i] = f;
+  }
+}
+__global__ void k_tc_dirs_pt3(Ws w) {
+  const int n = w.ctr[C_NPT3];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    if (w.f_pt3[i]) {
+      const int s = w.pt3_so[i].x;
+      const Dir d = dir_of_seed(w, s);
+      w.dir_pt3[w.p_pt3[i]] = make_float4(d.dx, d.dy, d.lam, 0.f);
+      w.seed_used[s] = 1;
+    }
+}
+// T5 TCs: surviving T5 not used by a TC-pT5 and not near any TC-pT5 or TC-pT3.
+__global__ void k_tc_t5(Ws w) {
+  const int n = w.ctr[C_NT5];
+  const int n0 = w.ctr[C_NTC0], n1 = w.ctr[C_NTC1];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    int f = 0;
+    if (w.t5_keep[t] && !w.t5_used[t]) {
+      const Dir d = dir_of_t5(w, t);
+      f = (near_any(d, w.dir_pt5, n0, kDT5) || near_any(d, w.dir_pt3, n1, kDT5)) ? 0 : 1;
+    }
+    w.f_t5[t] = f;
+  }
+}
+__global__ void k_tc_dirs_t5(Ws w) {
+  const int n = w.ctr[C_NT5];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    if (w.f_t5[t]) {
+      const Dir d = dir_of_t5(w, t);
+      w.dir_t5[w.p_t5[t]] = make_float4(d.dx, d.dy, d.lam, 0.f);
+    }
+}
+// pLS TCs: surviving pLS used by no TC and not near any TC.
+__global__ void k_tc_pls(Ws w) {
+  const int n0 = w.ctr[C_NTC0], n1 = w.ctr[C_NTC1], n2 = w.ctr[C_NTC2];
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
+    int f = 0;
+    if (w.pls_keep[s] && !w.seed_used[s]) {
+      const Dir d = dir_of_seed(w, s);
+      f = (near_any(d, w.dir_pt5, n0, kDpLS) || near_any(d, w.dir_pt3, n1, kDpLS) ||
+           near_any(d, w.dir_t5, n2, kDpLS)) ? 0 : 1;
+    }
+    w.f_pls[s] = f;
+  }
+}
+
+// Output: type, offsets, hit lists (pixel hits first, then MD hits inner to outer).
+__global__ void k_tc_write(Ws w) {
+  const int n0 = w.ctr[C_NTC0], n1 = w.ctr[C_NTC1], n2 = w.ctr[C_NTC2], n3 = w.ctr[C_NTC3];
+  const int np5 = w.ctr[C_NPT5], np3 = w.ctr[C_NPT3], nt5 = w.ctr[C_NT5];
+  const long h1 = 14L * n0, h2 = h1 + 10L * n1, h3 = h2 + 10L * n2;
+  const int stride = gridDim.x * blockDim.x;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0) {
+    w.ctr[C_NTC] = n0 + n1 + n2 + n3;
+    w.ctr[C_NTCHITS] = (int)(h3 + 4L * n3);
+    w.tc_off[n0 + n1 + n2 + n3] = (int)(h3 + 4L * n3);
+  }
+  for (int i = tid; i < np5; i += stride) {
+    if (!w.f_pt5[i]) continue;
+    const int k = w.p_pt5[i];
+    const int2 so = w.pt5_so[i];
+    int *h = w.tc_hits + 14L * k;
+    for (int q = 0; q < 4; ++q) h[q] = w.hits4[4 * (long)so.x + q];
+    t5_hits(w, so.y, h + 4);
+    w.tc_type[k] = 0;
+    w.tc_off[k] = 14 * k;
+  }
+  for (int i = tid; i < np3; i += stride) {
+    if (!w.f_pt3[i]) continue;
+    const int k = w.p_pt3[i];
+    const int2 so = w.pt3_so[i];
+    int *h = w.tc_hits + h1 + 10L * k;
+    for (int q = 0; q < 4; ++q) h[q] = w.hits4[4 * (long)so.x + q];
+    obj_hits<3>(w, so.y, h + 4);
+    w.tc_type[n0 + k] = 1;
+    w.tc_off[n0 + k] = (int)(h1 + 10L * k);
+  }
+  for (int t = tid; t < nt5; t += stride) {
+    if (!w.f_t5[t]) continue;
+    const int k = w.p_t5[t];
+    t5_hits(w, t, w.tc_hits + h2 + 10L * k);
+    w.tc_type[n0 + n1 + k] = 2;
+    w.tc_off[n0 + n1 + k] = (int)(h2 + 10L * k);
+  }
+  for (int s = tid; s < w.n_seeds; s += stride) {
+    if (!w.f_pls[s]) continue;
+    const int k = w.p_pls[s];
+    int *h = w.tc_hits + h3 + 4L * k;
+    for (int q = 0; q < 4; ++q) h[q] = w.hits4[4 * (long)s + q];
+    w.tc_type[n0 + n1 + n2 + k] = 3;
+    w.tc_off[n0 + n1 + n2 + k] = (int)(h3 + 4L * k);
+  }
+}
+
+// ------------------------------------------------------------- chain
+// Launch sites of the chain, in order; each is launched once per event.  One
+// of them can be bracketed by HIP events (KernelTimer) to time it live.
+const char *const kSiteNames[] = {
+    "fill_counters", "hits_count", "hits_scan", "hits_scatter", "bucket_sort",
+    "md_count", "md_scan", "md_fill", "ls_count", "ls_scan", "ls_fill",
+    "t3_count", "t3_scan", "t3_fill", "t5_count", "t5_scan", "t5_fill",
+    "t5_inc_count", "t5_inc_scan", "t5_inc_scatter", "t5_dedup",
+    "pls", "pls_hit_scan", "pls_hit_scatter", "pls_dedup",
+    "pt3_count", "pt3_scan", "pt3_fill", "pt5_count", "pt5_scan", "pt5_fill",
+    "pt_obj_count", "pt_obj_scan", "pt_obj_scatter", "pt3_dedup", "pt5_dedup",
+    "tc_pt5", "tc_pt5_scan", "tc_pt5_dirs", "tc_pt3", "tc_pt3_scan", "tc_pt3_dirs",
+    "tc_t5", "tc_t5_scan", "tc_t5_dirs", "tc_pls", "tc_pls_scan", "tc_write"};
+const int kNumSites = (int)(sizeof(kSiteNames) / sizeof(kSiteNames[0]));
+
+static void fill(int *p, long n, int v, hipStream_t st) {
+  if (n <= 0) return;
+  k_fill<<<grid_for(n), kBlock, 0, st>>>(p, n, v);
+}
+
+void enqueue_chain(const DevGeom &g, const Ws &w, hipStream_t st, const KernelTimer *kt) {
+  int site = 0;
+  // Runs one launch site; the timed site is bracketed by the timer's events.
+  auto run = [&](auto &&launch) {
+    const bool timed = kt && kt->site == site;
+    if (timed) (void)hipEventRecord(kt->beg, st);
+    launch();
+    if (timed) (void)hipEventRecord(kt->end, st);
+    ++site;
+  };
+  const int M = g.n_mod;
+  const int N = w.n_hits, S = w.n_seeds;
+  int *ctr = w.ctr;
+  int *status = ctr + C_STATUS;
+  // a0: buckets
+  run([&] {
+    fill(ctr, C_COUNT, 0, st);
+    fill(w.bcnt, 2L * M + 1, 0, st);
+    fill(w.bcur, 2L * M, 0, st);
+  });
+  run([&] { k_hits_count<<<grid_for(N > S ? N : S), kBlock, 0, st>>>(w, M); });
+  run([&] { scan(w.bcnt, w.boff, nullptr, 2 * M, 2 * M, w.scan_tmp, ctr + C_NOUTER, nullptr, 0, status, st); });
+  run([&] { k_hits_scatter<<<grid_for(N), kBlock, 0, st>>>(w, M); });
+  run([&] { k_bucket_sort<<<(2 * M * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(w, 2 * M); });
+  // a1: MD
+  run([&] { k_md<false><<<M, kBlock, 0, st>>>(w, g); });
+  run([&] { scan(w.md_cnt, w.md_off, nullptr, M, M, w.scan_tmp, ctr + C_RMD, ctr + C_NMD, w.cap_md, status, st); });
+  run([&] { k_md<true><<<M, kBlock, 0, st>>>(w, g); });
+  // a2: LS
+  run([&] { k_ls<false><<<grid_for(w.cap_md), kBlock, 0, st>>>(w, g); });
+  run([&] { scan(w.ls_cnt, w.ls_off, ctr + C_NMD, 0, w.cap_md, w.scan_tmp, ctr + C_RLS, ctr + C_NLS, w.cap_ls, status, st); });
+  run([&] { k_ls<true><<<grid_for(w.cap_md), kBlock, 0, st>>>(w, g); });
+  // a3: T3
+  run([&] { k_t3<false><<<grid_for(w.cap_ls), kBlock, 0, st>>>(w, g); });
+  run([&] { scan(w.t3_cnt, w.t3_off, ctr + C_NLS, 0, w.cap_ls, w.scan_tmp, ctr + C_RT3, ctr + C_NT3, w.cap_t3, status, st); });
+  run([&] { k_t3<true><<<grid_for(w.cap_ls), kBlock, 0, st>>>(w, g); });
+  // a4: T5
+  run([&] { k_t5<false><<<grid_for(w.cap_t3), kBlock, 0, st>>>(w, g); });
+  run([&] { scan(w.t5_cnt, w.t5_off, ctr + C_NT3, 0, w.cap_t3, w.scan_tmp, ctr + C_RT5, ctr + C_NT5, w.cap_t5, status, st); });
+  run([&] { k_t5<true><<<grid_for(w.cap_t3), kBlock, 0, st>>>(w, g); });
+  // a5: T5 duplicate removal through per-MD incidence lists
+  run([&] {
+    fill(w.inc_cnt, (long)w.cap_md + 1, 0, st);
+    fill(w.inc_cur, (long)w.cap_md + 1, 0, st);
+    k_t5_inc_count<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w);
+  });
+  run([&] { scan(w.inc_cnt, w.inc_off, ctr + C_NMD, 0, w.cap_md, w.scan_tmp, ctr + C_NINC, nullptr, 0, status, st); });
+  run([&] { k_t5_inc_scatter<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w); });
+  run([&] { k_t5_dedup<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w); });
+  // a6: pLS
+  const bool seeds = S > 0;
+  run([&] {
+    fill(w.ph_cnt, (long)N + 1, 0, st);
+    fill(w.ph_cur, (long)N + 1, 0, st);
+    if (seeds) k_pls<<<grid_for(S), kBlock, 0, st>>>(w);
+  });
+  run([&] { if (seeds) scan(w.ph_cnt, w.ph_off, nullptr, N, N, w.scan_tmp, ctr + C_NPH, nullptr, 0, status, st); });
+  run([&] { if (seeds) k_ph_scatter<<<grid_for(S), kBlock, 0, st>>>(w); });
+  run([&] { if (seeds) k_pls_dedup<<<grid_for(S), kBlock, 0, st>>>(w); });
+  // a7: pT3, pT5 (one block per seed)
+  run([&] { if (seeds) k_pt<3, false><<<S, kBlock, 0, st>>>(w, g); });
+  run([&] { if (seeds) scan(w.pt3_cnt, w.pt3_off, nullptr, S, S, w.scan_tmp, ctr + C_RPT3, ctr + C_NPT3, w.cap_pt3, status, st); });
+  run([&] { if (seeds) k_pt<3, true><<<S, kBlock, 0, st>>>(w, g); });
+  run([&] { if (seeds) k_pt<5, false><<<S, kBlock, 0, st>>>(w, g); });
+  run([&] { if (seeds) scan(w.pt5_cnt, w.pt5_off, nullptr, S, S, w.scan_tmp, ctr + C_RPT5, ctr + C_NPT5, w.cap_pt5, status, st); });
+  run([&] { if (seeds) k_pt<5, true><<<S, kBlock, 0, st>>>(w, g); });
+  run([&] {
+    if (!seeds) return;
+    fill(w.o3_cnt, (long)w.cap_t3 + 1, 0, st);
+    fill(w.o3_cur, (long)w.cap_t3 + 1, 0, st);
+    fill(w.o5_cnt, (long)w.cap_t5 + 1, 0, st);
+    fill(w.o5_cur, (long)w.cap_t5 + 1, 0, st);
+    k_pt_obj_count<3><<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w);
+    k_pt_obj_count<5><<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w);
+  });
+  run([&] {
+    if (!seeds) return;
+    scan(w.o3_cnt, w.o3_off, ctr + C_NT3, 0, w.cap_t3, w.scan_tmp, ctr + C_NO3, nullptr, 0, status, st);
+    scan(w.o5_cnt, w.o5_off, ctr + C_NT5, 0, w.cap_t5, w.scan_tmp, ctr + C_NO5, nullptr, 0, status, st);
+  });
+  run([&] {
+    if (!seeds) return;
+    k_pt_obj_scatter<3><<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w);
+    k_pt_obj_scatter<5><<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w);
+  });
+  run([&] { if (seeds) k_pt_dedup<3><<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w); });
+  run([&] { if (seeds) k_pt_dedup<5><<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w); });
+  // a8: cleaning and track candidates
+  run([&] {
+    fill(w.seed_used, (long)S + 1, 0, st);
+    fill(w.t5_used, (long)w.cap_t5 + 1, 0, st);
+    k_tc_pt5<<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w);
+  });
+  run([&] { scan(w.f_pt5, w.p_pt5, ctr + C_NPT5, 0, w.cap_pt5, w.scan_tmp, ctr + C_NTC0, nullptr, 0, status, st); });
+  run([&] { k_tc_dirs_pt5<<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w); });
+  run([&] { k_tc_pt3<<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w); });
+  run([&] { scan(w.f_pt3, w.p_pt3, ctr + C_NPT3, 0, w.cap_pt3, w.scan_tmp, ctr + C_NTC1, nullptr, 0, status, st); });
+  run([&] { k_tc_dirs_pt3<<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w); });
+  run([&] { k_tc_t5<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w); });
+  run([&] { scan(w.f_t5, w.p_t5, ctr + C_NT5, 0, w.cap_t5, w.scan_tmp, ctr + C_NTC2, nullptr, 0, status, st); });
+  run([&] { k_tc_dirs_t5<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w); });
+  run([&] { if (seeds) k_tc_pls<<<grid_for(S), kBlock, 0, st>>>(w); });
+  run([&] { if (seeds) scan(w.f_pls, w.p_pls, nullptr, S, S, w.scan_tmp, ctr + C_NTC3, nullptr, 0, status, st); });
+  run([&] { k_tc_write<<<grid_for(w.cap_tc), kBlock, 0, st>>>(w); });
+}
+
+}  // namespace lst

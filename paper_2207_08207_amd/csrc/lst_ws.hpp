@@ -1,0 +1,100 @@
+// Workspace layout and launch interface of the LST chain (host + device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace lst {
+
+// Counter slots (int32) at the start of the workspace.
+enum Ctr : int {
+  C_STATUS = 0,  // bit 0: invalid hit data, bit 1: invalid seed data, bit 2: capacity exceeded
+  C_NMD = 1, C_NLS, C_NT3, C_NT5, C_NPT3, C_NPT5, C_NTC, C_NTCHITS,   // built counts (clamped)
+  C_RMD = 9, C_RLS, C_RT3, C_RT5, C_RPT3, C_RPT5,                      // required counts
+  C_NT5KEEP = 15, C_NTC0 = 16, C_NTC1, C_NTC2, C_NTC3,                 // survivors, TCs per type
+  C_NOUTER = 20, C_NINC = 21, C_NPH = 22, C_NO3 = 23, C_NO5 = 24,      // scratch totals
+  C_COUNT = 64
+};
+enum : int { ST_BAD_HIT = 1, ST_BAD_SEED = 2, ST_CAPACITY = 4 };
+
+struct DevGeom {
+  int n_mod, n_edges;
+  const int *map_off, *map_tgt;
+  const float4 *win;  // per module: W, A1, A2, A3
+  const int *info;    // per module: bit 0 = 2S, bit 1 = endcap
+};
+
+// Device pointers of one event (all inside the caller's workspace except the inputs).
+struct Ws {
+  // inputs (device)
+  int n_hits, n_seeds;
+  const float *x, *y, *z, *px, *py, *pz;
+  const int *module, *sensor, *q, *hits4;
+  // capacities
+  int cap_md, cap_ls, cap_t3, cap_t5, cap_pt3, cap_pt5, cap_tc;
+  int *ctr;
+  // hit buckets by (module, sensor)
+  int *bcnt, *boff, *bcur, *hidx_tmp, *hidx;
+  float4 *hpos;
+  // mini-doublets
+  int *md_cnt, *md_off;
+  int2 *md_hits;    // input indices of the lower and upper hit
+  int *md_mod;
+  float4 *md_pos;   // anchor (lower hit) x, y, z, r
+  float2 *md_stub;  // tangential displacement, sensor separation
+  // segments
+  int *ls_cnt, *ls_off;
+  int2 *ls_md;
+  float2 *ls_beta;
+  // triplets
+  int *t3_cnt, *t3_off;
+  int4 *t3_md;      // a, b, c, -
+  float4 *t3_attr;  // kappa, dkappa, chi2_rz, lambda
+  float2 *t3_first; // anchor x, y of the first MD
+  // quintuplets
+  int *t5_cnt, *t5_off;
+  int2 *t5_t3;
+  int *t5_md;       // 5 per T5
+  float *t5_attr;   // 8 per T5
+  int *t5_keep;
+  float2 *t5_first;
+  int *inc_cnt, *inc_off, *inc_cur, *inc_list;  // T5s containing each MD
+  // pixel seeds
+  float *pls;       // 8 per seed: pT, cx, cy, lambda, kappa, x0, y0, z0
+  int *pls_keep;
+  int *ph_cnt, *ph_off, *ph_cur, *ph_list;      // seeds using each pixel hit
+  // pixel triplets / quintuplets
+  int *pt3_cnt, *pt3_off, *pt5_cnt, *pt5_off;
+  int2 *pt3_so, *pt5_so;      // seed, object
+  float4 *pt3_attr, *pt5_attr;
+  int *pt3_keep, *pt5_keep;
+  int *o3_cnt, *o3_off, *o3_cur, *o3_list;      // pT3 entries per T3
+  int *o5_cnt, *o5_off, *o5_cur, *o5_list;      // pT5 entries per T5
+  // track candidates
+  int *seed_used, *t5_used;
+  int *f_pt5, *f_pt3, *f_t5, *f_pls;            // TC flags
+  int *p_pt5, *p_pt3, *p_t5, *p_pls;            // their exclusive scans
+  float4 *dir_pt5, *dir_pt3, *dir_t5;           // compact directions (dx, dy, lambda)
+  int *tc_type, *tc_off, *tc_hits;
+  // scan scratch
+  int *scan_tmp;
+};
+
+// Capacities and sizes (host-side).
+struct Caps {
+  int64_t md, ls, t3, t5, pt3, pt5;
+};
+
+size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *ws, char *base);
+// Brackets launch site `site` of the chain with two recorded HIP events.
+struct KernelTimer {
+  int site;
+  hipEvent_t beg, end;
+};
+extern const char *const kSiteNames[];
+extern const int kNumSites;
+void enqueue_chain(const DevGeom &g, const Ws &ws, hipStream_t st, const KernelTimer *kt);
+void launch_module_windows(const int *info, const float *pos_lo, const float *pos_up, const float *lmin,
+                           const float *lmax, int n_mod, float4 *win, hipStream_t st);
+
+}  // namespace lst

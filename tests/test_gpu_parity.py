@@ -1,0 +1,145 @@
+"""HIP library versus the CPU oracle, through the C ABI (needs an MI355X)."""
+import numpy as np
+import pytest
+
+import oracle
+from lstgen import make_event, make_single_track_event
+from lstgen.events import Event, make_tiny_event
+
+from parity import compare_event, compare_tc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lst():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("a GPU is required for the gpu-marked tests")
+    import paper_2207_08207_amd as lst
+    lst.load_library()
+    return lst
+
+
+@pytest.fixture(scope="module")
+def gbarrel(lst, barrel):
+    return lst.Geometry(barrel)
+
+
+@pytest.fixture(scope="module")
+def gfull(lst, full):
+    return lst.Geometry(full)
+
+
+def _run(lst, g, ev, **kw):
+    print(f"[gpu] {ev.name or 'event'}: {ev.n_hits} hits, {ev.n_seeds} seeds", flush=True)
+    return lst.run_event(g, lst.upload_event(ev), **kw)
+
+
+def test_module_windows_bit_exact(gbarrel, gfull, obarrel, ofull):
+    for g, og in ((gbarrel, obarrel), (gfull, ofull)):
+        a = g.module_constants()
+        b = og.module_consts()
+        assert a.dtype == b.dtype == np.float32
+        assert np.array_equal(a.view(np.int32), b.view(np.int32))
+
+
+@pytest.mark.parametrize("ev_no", range(5))
+def test_parity_tiny(ev_no, lst, gbarrel, obarrel):
+    ev = make_event("tiny", ev_no)
+    r = _run(lst, gbarrel, ev)
+    o = oracle.run(obarrel, ev)
+    stats = compare_event(r, o, stages=range(4))
+    compare_tc(r, o)
+    assert stats["T5"]["oracle"] > 50
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_parity_tiny_seeded_ragged(seed, lst, gbarrel, obarrel, barrel):
+    """Barrel tracks with pixel seeds, unsmeared and smeared, plus noise: every stage incl. pT3/pT5/TC."""
+    rng = np.random.default_rng(seed)
+    n = 37 + 11 * seed  # not a multiple of any block size
+    ev = make_single_track_event(barrel, np.exp(rng.uniform(np.log(0.8), np.log(20.0), n)),
+                                 rng.uniform(-0.5, 0.5, n), rng.uniform(0, 2 * np.pi, n), z0=rng.normal(0, 5, n),
+                                 q=np.where(rng.uniform(size=n) < 0.5, -1, 1), smear=bool(seed % 2), seeded=True,
+                                 seed=seed, n_noise=50)
+    r = _run(lst, gbarrel, ev)
+    o = oracle.run(obarrel, ev)
+    compare_event(r, o)
+    assert compare_tc(r, o) > 0
+
+
+def test_parity_pu200_seeded_full_event(lst, gfull, ofull):
+    """The full-size PU200-like event with pixel seeds, all stages, every object."""
+    ev = make_event("pu200_seeded", 0)
+    r = _run(lst, gfull, ev)
+    o = oracle.run(ofull, ev)
+    stats = compare_event(r, o)
+    n = compare_tc(r, o)
+    print("[gpu] pu200_seeded#0", stats, "TC", n, flush=True)
+    assert stats["T5"]["oracle"] > 1000 and n > 1000
+
+
+def test_parity_pu200_unseeded(lst, gfull, ofull):
+    ev = make_event("pu200", 1)
+    r = _run(lst, gfull, ev)
+    o = oracle.run(ofull, ev)
+    compare_event(r, o, stages=range(4))
+    compare_tc(r, o)
+
+
+def test_empty_and_degenerate_events(lst, gbarrel, obarrel, barrel):
+    empty = Event(x=np.zeros(0, np.float32), y=np.zeros(0, np.float32), z=np.zeros(0, np.float32),
+                  module=np.zeros(0, np.int32), sensor=np.zeros(0, np.int32), sim=np.zeros(0, np.int32))
+    r = _run(lst, gbarrel, empty)
+    ty, off, hits = r.track_candidates()
+    assert ty.size == 0 and list(off) == [0] and hits.size == 0
+    # one track, unseeded; one bare seed; noise only
+    for ev in (make_single_track_event(barrel, 2.0, 0.2, 1.0),
+               make_single_track_event(barrel, 2.0, 0.2, 1.0, seeded=True),
+               make_tiny_event(0, n_tracks=0, n_noise=300)):
+        r = _run(lst, gbarrel, ev)
+        o = oracle.run(obarrel, ev)
+        compare_event(r, o)
+        compare_tc(r, o)
+
+
+def test_invalid_input_rejected(lst, gbarrel, barrel):
+    ev = make_single_track_event(barrel, 2.0, 0.2, 1.0)
+    bad = Event(x=ev.x, y=ev.y, z=ev.z, module=ev.module.copy(), sensor=ev.sensor, sim=ev.sim)
+    bad.module[0] = barrel.n_modules + 5
+    with pytest.raises(lst.LSTError) as e:
+        _run(lst, gbarrel, bad)
+    assert e.value.status == lst.LST_E_INVALID
+    bad2 = Event(x=ev.x.copy(), y=ev.y, z=ev.z, module=ev.module, sensor=ev.sensor, sim=ev.sim)
+    bad2.x[1] = np.nan
+    with pytest.raises(lst.LSTError):
+        _run(lst, gbarrel, bad2)
+
+
+def test_capacity_overflow_reports_and_recovers(lst, gbarrel, obarrel):
+    ev = make_event("tiny", 2)
+    cap = lst.lst_default_capacity(ev.n_hits, ev.n_seeds)
+    cap.ls = 100  # far below the ~500 segments of the event
+    dev = lst.upload_event(ev)
+    ws = lst.alloc_workspace(gbarrel, ev.n_hits, ev.n_seeds, cap)
+    st, h = lst.lst_build_event(gbarrel.handle, dev, ws, cap)
+    assert st == lst.LST_E_CAPACITY
+    counts, req = lst.lst_get_stage_counts(h)
+    assert counts[1] == 100 and req[1] > 100
+    lst.lst_release_event(h)
+    r = lst.run_event(gbarrel, dev, cap=cap)  # grows and reruns
+    compare_tc(r, oracle.run(obarrel, ev))
+
+
+def test_deterministic_repeats(lst, gfull):
+    ev = make_event("pu200_seeded", 2)
+    dev = lst.upload_event(ev)
+    ref = None
+    for _ in range(3):
+        r = lst.run_event(gfull, dev)
+        out = [r.stage(s) for s in range(7)] + [r.track_candidates()]
+        flat = [a.tobytes() for tup in out for a in tup]
+        if ref is None:
+            ref = flat
+        assert flat == ref
