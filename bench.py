@@ -44,28 +44,37 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes per launch of the main kernels: the distinct inputs a launch
+# Algorithmic bytes per launch of a launch site: the distinct inputs the launch
 # must read once and the outputs it must write once, from the record sizes of
-# the device layout (hit 16 B; MD 36 B = hits 8 + module 4 + anchor 16 + stub 8;
-# LS 16 B = MD pair 8 + angles 8; T3 40 B = MDs 16 + attrs 16 + first anchor 8;
-# T5 68 B = T3 pair 8 + MDs 20 + attrs 32 + keep 4 + first anchor 4...), and
-# the per-parent count / offset words.  c = built object counts of the event.
-def algorithmic_bytes(site, c, n_outer, n_mod, n_edges, n_seeds):
-    md, ls, t3, t5, pt3, pt5 = c["md"], c["ls"], c["t3"], c["t5"], c["pt3"], c["pt5"]
+# the device layout: hit 16 B (x, y, z, r); MD 36 B (hit pair 8, module 4,
+# anchor 16, stub 8); LS 16 B (MD pair 8, angles 8); T3 40 B (MDs 16, attrs
+# 16, first anchor 8); T5 68 B (T3 pair 8, MDs 20, attrs 32, keep 4, first
+# anchor 4 of 8); pLS 32 B; pT entry 24 B (seed/object 8, attrs 16);
+# direction 16 B; count / offset / flag words 4 B.  c = object counts.
+def algorithmic_bytes(site, c, n_outer, n_mod, n_edges, n_seeds, n_tc):
+    md, ls, t3, t5, p3, p5 = c["md"], c["ls"], c["t3"], c["t5"], c["pt3"], c["pt5"]
+    S, M, E = n_seeds, n_mod, n_edges
+    n0, n1, n2 = c.get("tc0", 0), c.get("tc1", 0), c.get("tc2", 0)
+    hit_in = 16 * n_outer + 8 * 2 * M          # bucketed hits + bucket offsets
+    md_in = 28 * md                             # anchor + stub + module of every MD
     table = {
-        "md_count": 16 * n_outer + 8 * 2 * n_mod + 16 * n_mod + 4 * n_mod,
-        "md_fill": 16 * n_outer + 8 * 2 * n_mod + 16 * n_mod + 4 * n_mod + 36 * md,
-        "ls_count": 28 * md + 4 * (n_mod + 1) + 4 * n_edges + 4 * (n_mod + 1) + 4 * md,
-        "ls_fill": 28 * md + 4 * (n_mod + 1) + 4 * n_edges + 4 * (n_mod + 1) + 4 * (md + 1) + 16 * ls,
+        "md_count": hit_in + 20 * M + 4 * M,
+        "md_fill": hit_in + 20 * M + 4 * (M + 1) + 36 * md,
+        "ls_count": md_in + 8 * (M + 1) + 4 * E + 4 * M + 4 * md,
+        "ls_fill": md_in + 8 * (M + 1) + 4 * E + 4 * M + 4 * (md + 1) + 16 * ls,
         "t3_count": 8 * ls + 20 * md + 4 * (md + 1) + 4 * ls,
         "t3_fill": 8 * ls + 20 * md + 4 * (md + 1) + 4 * (ls + 1) + 40 * t3,
         "t5_count": 32 * t3 + 20 * md + 4 * (md + 1) + 4 * (ls + 1) + 4 * t3,
         "t5_fill": 32 * t3 + 20 * md + 4 * (md + 1) + 4 * (ls + 1) + 4 * (t3 + 1) + 60 * t5,
         "t5_dedup": 60 * t5 + 8 * md + 4 * (md + 1) + 20 * t5 + 12 * t5,
-        "pt3_count": 32 * n_seeds + 8 * t3 + 4 * n_seeds,
-        "pt3_fill": 32 * n_seeds + 8 * t3 + 4 * (n_seeds + 1) + 24 * pt3,
-        "pt5_count": 32 * n_seeds + 12 * t5 + 4 * n_seeds,
-        "pt5_fill": 32 * n_seeds + 12 * t5 + 4 * (n_seeds + 1) + 24 * pt5,
+        "pt3_count": 32 * S + 8 * t3 + 4 * S,
+        "pt3_fill": 32 * S + 8 * t3 + 4 * (S + 1) + 24 * p3,
+        "pt5_count": 32 * S + 12 * t5 + 4 * S,
+        "pt5_fill": 32 * S + 12 * t5 + 4 * (S + 1) + 24 * p5,
+        "tc_pt3": 16 * p3 + 32 * S + 4 * S + 16 * n0 + 4 * p3,
+        "tc_t5": 8 * t5 + 16 * t5 + 16 * (n0 + n1) + 4 * t5,
+        "tc_pls": 8 * S + 32 * S + 16 * (n0 + n1 + n2) + 4 * S,
+        "tc_write": 4 * (p5 + p3 + t5 + S) * 2 + 4 * (14 * n0 + 10 * (n1 + n2)) + 4 * n_tc * 3,
     }
     return table.get(site)
 
@@ -144,7 +153,7 @@ def main():
     for ev, c in zip(ev_of, counts_all):
         cc = dict(md=int(c[0]), ls=int(c[1]), t3=int(c[2]), t5=int(c[3]), pt3=int(c[5]), pt5=int(c[6]))
         nb.append(algorithmic_bytes(sites[dom], cc, int((ev.module >= 0).sum()), geom.n_modules,
-                                    int(geom.map_targets.size), ev.n_seeds))
+                                    int(geom.map_targets.size), ev.n_seeds, int(c[7])))
     roof = None
     if all(b is not None for b in nb):
         avg_bytes = float(np.mean(nb))

@@ -95,6 +95,8 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.f_pt5 = I(p5 + 1); t.f_pt3 = I(p3 + 1); t.f_t5 = I(t5 + 1); t.f_pls = I(S + 1);
   t.p_pt5 = I(p5 + 1); t.p_pt3 = I(p3 + 1); t.p_t5 = I(t5 + 1); t.p_pls = I(S + 1);
   t.dir_pt5 = F4(p5); t.dir_pt3 = F4(p3); t.dir_t5 = F4(t5);
+  t.bdir_pt5 = F4(p5); t.bdir_pt3 = F4(p3); t.bdir_t5 = F4(t5);
+  t.boff_pt5 = I(129); t.boff_pt3 = I(129); t.boff_t5 = I(129);
   t.tc_type = I(tc); t.tc_off = I(tc + 1); t.tc_hits = I(14 * tc);
   t.scan_tmp = I(4096);
 #undef I
@@ -164,6 +166,9 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   }
   for (int e = 0; e < E; ++e)
     if (d->map_targets[e] < 0 || d->map_targets[e] >= M) return fail(LST_E_INVALID, "map target out of range");
+  for (int m = 0; m < M; ++m)
+    if (d->map_offsets[m + 1] - d->map_offsets[m] > 256)
+      return fail(LST_E_INVALID, "more than 256 module-map targets for one module");
   auto *g = new (std::nothrow) lst_geometry_s();
   if (!g) return fail(LST_E_NOMEM, "host allocation failed");
   std::vector<int> info(M);

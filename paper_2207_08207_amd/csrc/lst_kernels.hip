@@ -151,6 +151,14 @@ __global__ void k_scan_apply(const int *in, int *out, const int *n_dev, int n_fi
   if (blockIdx.x == 0 && threadIdx.x == 0 && n == 0) out[0] = 0;
 }
 
+// blocks for one wave per item (capped; kernels stride)
+static inline int grid_waves(long n) {
+  long g = (n + kWaves - 1) / kWaves;
+  if (g < 1) g = 1;
+  if (g > 16384) g = 16384;
+  return (int)g;
+}
+
 static inline int grid_for(long n) {
   long g = (n + kBlock - 1) / kBlock;
   if (g < 1) g = 1;
@@ -295,38 +303,84 @@ __global__ __launch_bounds__(kBlock) void k_md(Ws w, DevGeom g) {
 }
 
 // ------------------------------------------------------------- a2: LS
-// One thread per inner MD a; candidates: the MDs of every module linked to a's module.
+constexpr int kMaxEdges = 256;  // module-map targets per module handled by one wave
+
+// One wave per inner MD a.  Its candidates -- the MDs of every module linked
+// to a's module, edge by edge -- are flattened into one list that the 64
+// lanes stride over, so a wave stays full even though each linked module
+// holds few MDs; passing candidates are compacted in list order with ballot
+// and mbcnt.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_ls(Ws w, DevGeom g) {
+  __shared__ int s_pre[kWaves][kMaxEdges + 1];  // running MD count before each edge
+  __shared__ int s_first[kWaves][kMaxEdges];    // first MD of each linked module
+  __shared__ int s_info[kWaves][kMaxEdges];
   const int n_md = w.ctr[C_NMD];
-  for (int a = blockIdx.x * blockDim.x + threadIdx.x; a < n_md; a += gridDim.x * blockDim.x) {
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int waves_total = gridDim.x * kWaves;
+  for (int a = blockIdx.x * kWaves + wv; a < n_md; a += waves_total) {
     const int ma = w.md_mod[a];
     const float4 A = w.md_pos[a];
     const float2 sa = w.md_stub[a];
     const ModInfo mia{g.info[ma]};
+    const int e0 = g.map_off[ma];
+    const int ne = g.map_off[ma + 1] - e0;  // <= kMaxEdges, checked when the geometry is loaded
+    // per-edge MD ranges and their exclusive prefix over the wave
+    int run = 0;
+    for (int k0 = 0; k0 < ne; k0 += 64) {
+      const int k = k0 + lane;
+      int first = 0, cnt = 0, info = 0;
+      if (k < ne) {
+        const int mb = g.map_tgt[e0 + k];
+        first = w.md_off[mb];
+        const int last = min(w.md_off[mb + 1], n_md);
+        cnt = last > first ? last - first : 0;
+        info = g.info[mb];
+      }
+      int x = cnt;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (k < ne) {
+        s_pre[wv][k] = run + x - cnt;
+        s_first[wv][k] = first;
+        s_info[wv][k] = info;
+      }
+      run += __shfl(x, 63, 64);
+    }
+    if (lane == 0) s_pre[wv][ne] = run;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int total = run;
     int out = FILL ? w.ls_off[a] : 0;
     int cnt = 0;
-    const int e1 = g.map_off[ma + 1];
-    for (int e = g.map_off[ma]; e < e1; ++e) {
-      const int mb = g.map_tgt[e];
-      const ModInfo mib{g.info[mb]};
-      const int b1 = min(w.md_off[mb + 1], n_md);
-      for (int b = w.md_off[mb]; b < b1; ++b) {
-        float2 beta;
-        if (ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, mib, &beta)) {
-          if (FILL) {
-            if (out < w.cap_ls) {
-              w.ls_md[out] = make_int2(a, b);
-              w.ls_beta[out] = beta;
-            }
-            ++out;
-          } else {
-            ++cnt;
-          }
+    int e = 0;  // edge of this lane's candidate (candidates advance monotonically)
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      bool pass = false;
+      int b = 0;
+      float2 beta = make_float2(0.f, 0.f);
+      if (c < total) {
+        while (s_pre[wv][e + 1] <= c) ++e;
+        b = s_first[wv][e] + (c - s_pre[wv][e]);
+        pass = ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, ModInfo{s_info[wv][e]}, &beta);
+      }
+      const unsigned long long m = __ballot(pass);
+      if (FILL) {
+        const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        const int pos = out + pre;
+        if (pass && pos < w.cap_ls) {
+          w.ls_md[pos] = make_int2(a, b);
+          w.ls_beta[pos] = beta;
         }
       }
+      out += __popcll(m);
+      cnt += __popcll(m);
     }
-    if (!FILL) w.ls_cnt[a] = cnt;
+    if (!FILL && lane == 0) w.ls_cnt[a] = cnt;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -543,64 +597,100 @@ __global__ void k_pls_dedup(Ws w) {
 }
 
 // ------------------------------------------------------------- a7: pT3 / pT5
-// One block per seed; the block strides over all triplets (K = 3) or
-// surviving quintuplets (K = 5) in object order, window first.
+constexpr int kSeedTile = 8;  // seeds per block
+
+template <int K>
+__device__ __forceinline__ void load_object(const Ws &w, const DevGeom &g, int t, float4 *P, ModInfo *M, float *kT,
+                                            float *dkT) {
+  if constexpr (K == 3) {
+    const int4 abc = w.t3_md[t];
+    const int md[3] = {abc.x, abc.y, abc.z};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { P[k] = w.md_pos[md[k]]; M[k].bits = g.info[w.md_mod[md[k]]]; }
+    const float4 a3 = w.t3_attr[t];
+    *kT = a3.x; *dkT = a3.y;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int md = w.t5_md[5 * (long)t + k];
+      P[k] = w.md_pos[md];
+      M[k].bits = g.info[w.md_mod[md]];
+    }
+    const float4 a3 = w.t3_attr[w.t5_t3[t].y];
+    *kT = a3.x; *dkT = a3.y;
+  }
+}
+
+// One block per tile of kSeedTile seeds; the block streams every triplet
+// (K = 3) or surviving quintuplet (K = 5) once, in object order, and tests it
+// against the tile's seeds held in LDS: the window at the first anchor first,
+// the full selection only inside it.  Per seed the passing objects are
+// compacted in object order; chunks in which no pair passed skip the
+// compaction.
 template <int K, bool FILL>
 __global__ __launch_bounds__(kBlock) void k_pt(Ws w, DevGeom g) {
+  __shared__ Seed s_seed[kSeedTile];
+  __shared__ int s_base[kSeedTile];
   __shared__ int s_wave[kWaves];
-  const int s = blockIdx.x;
-  if (s >= w.n_seeds) return;
-  const Seed sd = load_seed(w, s);
+  const int s0 = blockIdx.x * kSeedTile;
+  const int ns = min(kSeedTile, w.n_seeds - s0);
+  if (ns <= 0) return;
+  if (threadIdx.x < ns) {
+    s_seed[threadIdx.x] = load_seed(w, s0 + threadIdx.x);
+    if (FILL) s_base[threadIdx.x] = (K == 3 ? w.pt3_off : w.pt5_off)[s0 + threadIdx.x];
+  }
+  __syncthreads();
   const int n_obj = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
   const float2 *first = K == 3 ? w.t3_first : w.t5_first;
-  int base = FILL ? (K == 3 ? w.pt3_off[s] : w.pt5_off[s]) : 0;
-  int cnt = 0;
+  const int cap = K == 3 ? w.cap_pt3 : w.cap_pt5;
+  int cnt[kSeedTile];
+#pragma unroll
+  for (int j = 0; j < kSeedTile; ++j) cnt[j] = 0;
   for (int t0 = 0; t0 < n_obj; t0 += kBlock) {
     const int t = t0 + threadIdx.x;
-    bool pass = false;
-    float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
+    unsigned mask = 0;
+    float4 P[K];
+    ModInfo M[K];
+    float kT = 0.f, dkT = 0.f;
     if (t < n_obj && (K == 3 || w.t5_keep[t])) {
       const float2 f = first[t];
-      if (seed_box(sd, f.x, f.y)) {
-        float4 P[K];
-        ModInfo M[K];
-        float kT, dkT;
-        if constexpr (K == 3) {
-          const int4 abc = w.t3_md[t];
-          const int md[3] = {abc.x, abc.y, abc.z};
 #pragma unroll
-          for (int k = 0; k < K; ++k) { P[k] = w.md_pos[md[k]]; M[k].bits = g.info[w.md_mod[md[k]]]; }
-          const float4 a3 = w.t3_attr[t];
-          kT = a3.x; dkT = a3.y;
-        } else {
+      for (int j = 0; j < kSeedTile; ++j)
+        if (j < ns && seed_box(s_seed[j], f.x, f.y)) mask |= 1u << j;
+      if (mask) {
+        load_object<K>(w, g, t, P, M, &kT, &dkT);
 #pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const int md = w.t5_md[5 * (long)t + k];
-            P[k] = w.md_pos[md];
-            M[k].bits = g.info[w.md_mod[md]];
-          }
-          const float4 a3 = w.t3_attr[w.t5_t3[t].y];
-          kT = a3.x; dkT = a3.y;
+        for (int j = 0; j < kSeedTile; ++j) {
+          float4 attr;
+          if (((mask >> j) & 1u) && !pt_pass<K>(s_seed[j], P, M, kT, dkT, &attr)) mask &= ~(1u << j);
         }
-        pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
       }
     }
     if (!FILL) {
-      cnt += pass ? 1 : 0;
-    } else {
-      int tot;
-      const int pos = base + block_prefix(pass, s_wave, &tot);
-      const int cap = K == 3 ? w.cap_pt3 : w.cap_pt5;
-      if (pass && pos < cap) {
-        (K == 3 ? w.pt3_so : w.pt5_so)[pos] = make_int2(s, t);
-        (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = attr;
+#pragma unroll
+      for (int j = 0; j < kSeedTile; ++j) cnt[j] += (mask >> j) & 1u;
+    } else if (__syncthreads_or(mask != 0u)) {
+      for (int j = 0; j < ns; ++j) {
+        const bool pass = (mask >> j) & 1u;
+        int tot;
+        const int pos = s_base[j] + block_prefix(pass, s_wave, &tot);
+        if (pass && pos < cap) {
+          float4 attr;
+          pt_pass<K>(s_seed[j], P, M, kT, dkT, &attr);
+          (K == 3 ? w.pt3_so : w.pt5_so)[pos] = make_int2(s0 + j, t);
+          (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = attr;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_base[j] += tot;
+        __syncthreads();
       }
-      base += tot;
     }
   }
   if (!FILL) {
-    cnt = block_sum(cnt, s_wave);
-    if (threadIdx.x == 0) (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s] = cnt;
+    for (int j = 0; j < ns; ++j) {
+      const int c = block_sum(cnt[j], s_wave);
+      if (threadIdx.x == 0) (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s0 + j] = c;
+    }
   }
 }
 
@@ -710,12 +800,59 @@ __global__ void k_tc_dirs_pt5(Ws w) {
     }
 }
 
-__device__ __forceinline__ bool near_any(const Dir &d, const float4 *lst, int n, float D) {
-  for (int j = 0; j < n; ++j) {
-    const float4 e = lst[j];
-    Dir o;
-    o.dx = e.x; o.dy = e.y; o.lam = e.z;
-    if (near_dir(d, o, D)) return true;
+// Direction lists of track candidates are binned by azimuth so that a
+// proximity query reads only the bins that can hold a near entry.  Near
+// entries have |dphi| < asin(D) (the test requires sin^2 dphi < D^2 and a
+// positive dot product), so with bins of width 2 pi / kDirBins the query
+// covers ceil(asin(D) / width) + 1 bins on each side, one more than needed
+// to absorb atan2f rounding.  The decision itself is near_dir, unchanged.
+constexpr int kDirBins = 128;
+
+__device__ __forceinline__ int dir_bin(float dx, float dy) {
+  const float ph = atan2f(dy, dx);
+  if (!(ph == ph)) return 0;
+  const int b = (int)floorf((ph + (float)M_PI) * (float)(kDirBins / (2.0 * M_PI)));
+  return b < 0 ? 0 : (b >= kDirBins ? kDirBins - 1 : b);
+}
+
+constexpr int bin_reach(double D) {
+  // ceil(asin(D) / (2 pi / kDirBins)) + 1 for the D values used (asin(D) < 1.0001 D for D <= 0.05)
+  return (int)(D * 1.0001 / (2.0 * 3.14159265358979 / kDirBins)) + 2;
+}
+
+// One block: counting sort of n (on the device) directions into kDirBins bins.
+__global__ __launch_bounds__(1024) void k_bin_dirs(const float4 *dirs, const int *n_ptr, int *bin_off, float4 *out) {
+  __shared__ int s_cnt[kDirBins], s_off[kDirBins + 1], s_cur[kDirBins];
+  const int n = *n_ptr;
+  for (int b = threadIdx.x; b < kDirBins; b += blockDim.x) { s_cnt[b] = 0; s_cur[b] = 0; }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&s_cnt[dir_bin(dirs[i].x, dirs[i].y)], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int r = 0;
+    for (int b = 0; b < kDirBins; ++b) { s_off[b] = r; r += s_cnt[b]; }
+    s_off[kDirBins] = r;
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b <= kDirBins; b += blockDim.x) bin_off[b] = s_off[b];
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const float4 d = dirs[i];
+    const int b = dir_bin(d.x, d.y);
+    out[s_off[b] + atomicAdd(&s_cur[b], 1)] = d;
+  }
+}
+
+__device__ __forceinline__ bool near_any(const Dir &d, const float4 *lst, const int *bin_off, float D, int reach) {
+  const int b0 = dir_bin(d.dx, d.dy);
+  for (int k = -reach; k <= reach; ++k) {
+    const int b = (b0 + k + kDirBins) % kDirBins;
+    const int j1 = bin_off[b + 1];
+    for (int j = bin_off[b]; j < j1; ++j) {
+      const float4 e = lst[j];
+      Dir o;
+      o.dx = e.x; o.dy = e.y; o.lam = e.z;
+      if (near_dir(d, o, D)) return true;
+    }
   }
   return false;
 }
@@ -723,12 +860,11 @@ __device__ __forceinline__ bool near_any(const Dir &d, const float4 *lst, int n,
 // pT3 TCs: surviving pT3 whose seed no TC-pT5 uses and that is not near any TC-pT5.
 __global__ void k_tc_pt3(Ws w) {
   const int n = w.ctr[C_NPT3];
-  const int n0 = w.ctr[C_NTC0];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     int f = 0;
     if (w.pt3_keep[i]) {
       const int s = w.pt3_so[i].x;
-      if (!w.seed_used[s]) f = near_any(dir_of_seed(w, s), w.dir_pt5, n0, kDpT3) ? 0 : 1;
+      if (!w.seed_used[s]) f = near_any(dir_of_seed(w, s), w.bdir_pt5, w.boff_pt5, kDpT3, bin_reach(0.02)) ? 0 : 1;
     }
     w.f_pt3[i] = f;
   }
@@ -746,12 +882,12 @@ __global__ void k_tc_dirs_pt3(Ws w) {
 // T5 TCs: surviving T5 not used by a TC-pT5 and not near any TC-pT5 or TC-pT3.
 __global__ void k_tc_t5(Ws w) {
   const int n = w.ctr[C_NT5];
-  const int n0 = w.ctr[C_NTC0], n1 = w.ctr[C_NTC1];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     int f = 0;
     if (w.t5_keep[t] && !w.t5_used[t]) {
       const Dir d = dir_of_t5(w, t);
-      f = (near_any(d, w.dir_pt5, n0, kDT5) || near_any(d, w.dir_pt3, n1, kDT5)) ? 0 : 1;
+      f = (near_any(d, w.bdir_pt5, w.boff_pt5, kDT5, bin_reach(0.02)) ||
+           near_any(d, w.bdir_pt3, w.boff_pt3, kDT5, bin_reach(0.02))) ? 0 : 1;
     }
     w.f_t5[t] = f;
   }
@@ -766,13 +902,13 @@ __global__ void k_tc_dirs_t5(Ws w) {
 }
 // pLS TCs: surviving pLS used by no TC and not near any TC.
 __global__ void k_tc_pls(Ws w) {
-  const int n0 = w.ctr[C_NTC0], n1 = w.ctr[C_NTC1], n2 = w.ctr[C_NTC2];
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
     int f = 0;
     if (w.pls_keep[s] && !w.seed_used[s]) {
       const Dir d = dir_of_seed(w, s);
-      f = (near_any(d, w.dir_pt5, n0, kDpLS) || near_any(d, w.dir_pt3, n1, kDpLS) ||
-           near_any(d, w.dir_t5, n2, kDpLS)) ? 0 : 1;
+      f = (near_any(d, w.bdir_pt5, w.boff_pt5, kDpLS, bin_reach(0.05)) ||
+           near_any(d, w.bdir_pt3, w.boff_pt3, kDpLS, bin_reach(0.05)) ||
+           near_any(d, w.bdir_t5, w.boff_t5, kDpLS, bin_reach(0.05))) ? 0 : 1;
     }
     w.f_pls[s] = f;
   }
@@ -876,9 +1012,9 @@ void enqueue_chain(const DevGeom &g, const Ws &w, hipStream_t st, const KernelTi
   run([&] { scan(w.md_cnt, w.md_off, nullptr, M, M, w.scan_tmp, ctr + C_RMD, ctr + C_NMD, w.cap_md, status, st); });
   run([&] { k_md<true><<<M, kBlock, 0, st>>>(w, g); });
   // a2: LS
-  run([&] { k_ls<false><<<grid_for(w.cap_md), kBlock, 0, st>>>(w, g); });
+  run([&] { k_ls<false><<<grid_waves(w.cap_md), kBlock, 0, st>>>(w, g); });
   run([&] { scan(w.ls_cnt, w.ls_off, ctr + C_NMD, 0, w.cap_md, w.scan_tmp, ctr + C_RLS, ctr + C_NLS, w.cap_ls, status, st); });
-  run([&] { k_ls<true><<<grid_for(w.cap_md), kBlock, 0, st>>>(w, g); });
+  run([&] { k_ls<true><<<grid_waves(w.cap_md), kBlock, 0, st>>>(w, g); });
   // a3: T3
   run([&] { k_t3<false><<<grid_for(w.cap_ls), kBlock, 0, st>>>(w, g); });
   run([&] { scan(w.t3_cnt, w.t3_off, ctr + C_NLS, 0, w.cap_ls, w.scan_tmp, ctr + C_RT3, ctr + C_NT3, w.cap_t3, status, st); });
@@ -907,12 +1043,12 @@ void enqueue_chain(const DevGeom &g, const Ws &w, hipStream_t st, const KernelTi
   run([&] { if (seeds) k_ph_scatter<<<grid_for(S), kBlock, 0, st>>>(w); });
   run([&] { if (seeds) k_pls_dedup<<<grid_for(S), kBlock, 0, st>>>(w); });
   // a7: pT3, pT5 (one block per seed)
-  run([&] { if (seeds) k_pt<3, false><<<S, kBlock, 0, st>>>(w, g); });
+  run([&] { if (seeds) k_pt<3, false><<<(S + kSeedTile - 1) / kSeedTile, kBlock, 0, st>>>(w, g); });
   run([&] { if (seeds) scan(w.pt3_cnt, w.pt3_off, nullptr, S, S, w.scan_tmp, ctr + C_RPT3, ctr + C_NPT3, w.cap_pt3, status, st); });
-  run([&] { if (seeds) k_pt<3, true><<<S, kBlock, 0, st>>>(w, g); });
-  run([&] { if (seeds) k_pt<5, false><<<S, kBlock, 0, st>>>(w, g); });
+  run([&] { if (seeds) k_pt<3, true><<<(S + kSeedTile - 1) / kSeedTile, kBlock, 0, st>>>(w, g); });
+  run([&] { if (seeds) k_pt<5, false><<<(S + kSeedTile - 1) / kSeedTile, kBlock, 0, st>>>(w, g); });
   run([&] { if (seeds) scan(w.pt5_cnt, w.pt5_off, nullptr, S, S, w.scan_tmp, ctr + C_RPT5, ctr + C_NPT5, w.cap_pt5, status, st); });
-  run([&] { if (seeds) k_pt<5, true><<<S, kBlock, 0, st>>>(w, g); });
+  run([&] { if (seeds) k_pt<5, true><<<(S + kSeedTile - 1) / kSeedTile, kBlock, 0, st>>>(w, g); });
   run([&] {
     if (!seeds) return;
     fill(w.o3_cnt, (long)w.cap_t3 + 1, 0, st);
@@ -941,13 +1077,22 @@ void enqueue_chain(const DevGeom &g, const Ws &w, hipStream_t st, const KernelTi
     k_tc_pt5<<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w);
   });
   run([&] { scan(w.f_pt5, w.p_pt5, ctr + C_NPT5, 0, w.cap_pt5, w.scan_tmp, ctr + C_NTC0, nullptr, 0, status, st); });
-  run([&] { k_tc_dirs_pt5<<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w); });
+  run([&] {
+    k_tc_dirs_pt5<<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w);
+    k_bin_dirs<<<1, 1024, 0, st>>>(w.dir_pt5, ctr + C_NTC0, w.boff_pt5, w.bdir_pt5);
+  });
   run([&] { k_tc_pt3<<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w); });
   run([&] { scan(w.f_pt3, w.p_pt3, ctr + C_NPT3, 0, w.cap_pt3, w.scan_tmp, ctr + C_NTC1, nullptr, 0, status, st); });
-  run([&] { k_tc_dirs_pt3<<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w); });
+  run([&] {
+    k_tc_dirs_pt3<<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w);
+    k_bin_dirs<<<1, 1024, 0, st>>>(w.dir_pt3, ctr + C_NTC1, w.boff_pt3, w.bdir_pt3);
+  });
   run([&] { k_tc_t5<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w); });
   run([&] { scan(w.f_t5, w.p_t5, ctr + C_NT5, 0, w.cap_t5, w.scan_tmp, ctr + C_NTC2, nullptr, 0, status, st); });
-  run([&] { k_tc_dirs_t5<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w); });
+  run([&] {
+    k_tc_dirs_t5<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w);
+    k_bin_dirs<<<1, 1024, 0, st>>>(w.dir_t5, ctr + C_NTC2, w.boff_t5, w.bdir_t5);
+  });
   run([&] { if (seeds) k_tc_pls<<<grid_for(S), kBlock, 0, st>>>(w); });
   run([&] { if (seeds) scan(w.f_pls, w.p_pls, nullptr, S, S, w.scan_tmp, ctr + C_NTC3, nullptr, 0, status, st); });
   run([&] { k_tc_write<<<grid_for(w.cap_tc), kBlock, 0, st>>>(w); });

@@ -75,6 +75,8 @@ struct Ws {
   int *f_pt5, *f_pt3, *f_t5, *f_pls;            // TC flags
   int *p_pt5, *p_pt3, *p_t5, *p_pls;            // their exclusive scans
   float4 *dir_pt5, *dir_pt3, *dir_t5;           // compact directions (dx, dy, lambda)
+  float4 *bdir_pt5, *bdir_pt3, *bdir_t5;        // the same, grouped by azimuth bin
+  int *boff_pt5, *boff_pt3, *boff_t5;           // bin offsets (kDirBins + 1)
   int *tc_type, *tc_off, *tc_hits;
   // scan scratch
   int *scan_tmp;
