@@ -50,6 +50,7 @@ typedef enum {
 
 typedef struct lst_geometry_s *lst_geometry; /* opaque, library-owned, device-resident */
 typedef struct lst_event_s *lst_event;       /* opaque, library-owned host handle */
+typedef struct lst_plan_s *lst_plan;         /* opaque: a captured batch chain (HIP graph) */
 
 /* Detector description (Section 1: bi-layer pT modules) and module map
  * (Section 2.2).  All arrays are HOST memory, length n_modules unless noted.
@@ -126,6 +127,37 @@ lst_status lst_enqueue_event(lst_geometry geom, const lst_event_desc *ev, const 
 lst_status lst_event_query(lst_event ev, int32_t *done);
 /* Blocks until the event's device work has completed; returns its status. */
 lst_status lst_event_wait(lst_event ev);
+
+/* Batched form: B independent events run by one launch sequence (each kernel
+ * of the chain is launched once for the whole batch, events along the grid's
+ * y dimension), inside one workspace of lst_batch_workspace_bytes() bytes
+ * (n_hits / n_seeds: B entries; cap: B entries or NULL for defaults).  `out`
+ * receives B event handles (each released with lst_release_event; waiting on
+ * any of them waits for the batch).  Per event the results are identical to
+ * lst_build_event's.  Section 4.2.2 fills the GPU with several events through
+ * streams; here events also share each launch.  Errors as lst_build_event. */
+lst_status lst_batch_workspace_bytes(lst_geometry geom, int32_t B, const int32_t *n_hits, const int32_t *n_seeds,
+                                     const lst_capacity *cap, size_t *bytes);
+lst_status lst_enqueue_batch(lst_geometry geom, int32_t B, const lst_event_desc *evs, const lst_capacity *cap,
+                             void *workspace, size_t ws_bytes, void *stream, lst_event *out);
+
+/* Captured plan: the batched chain for B slots, each sized for max_hits hits,
+ * max_seeds seeds and capacities `cap` (NULL = defaults for those sizes), is
+ * captured once into a HIP graph bound to `workspace`
+ * (lst_plan_workspace_bytes() bytes; the caller keeps it alive until
+ * lst_plan_release).  lst_plan_run(plan, n, evs, stream, out) writes the n
+ * (<= B) event descriptors into the workspace header, replays the graph on
+ * `stream` (NULL = the stream given at creation) and returns n event handles
+ * (as lst_enqueue_batch; unused slots run as empty events).  A plan runs one
+ * batch at a time: lst_plan_run returns LST_E_STATE while any event of the
+ * previous run is still held.  Errors: LST_E_INVALID (an event larger than
+ * the slots), LST_E_DEVICE (capture or launch failure), LST_E_NOMEM. */
+lst_status lst_plan_workspace_bytes(lst_geometry geom, int32_t B, int32_t max_hits, int32_t max_seeds,
+                                    const lst_capacity *cap, size_t *bytes);
+lst_status lst_plan_create(lst_geometry geom, int32_t B, int32_t max_hits, int32_t max_seeds, const lst_capacity *cap,
+                           void *workspace, size_t ws_bytes, void *stream, lst_plan *out);
+lst_status lst_plan_run(lst_plan plan, int32_t n_events, const lst_event_desc *evs, void *stream, lst_event *out);
+lst_status lst_plan_release(lst_plan plan);
 
 /* Track candidates (Section 2.5) of a completed event, copied to HOST
  * buffers.  Two-call protocol: pass NULL arrays to get *n_tc and

@@ -26,7 +26,8 @@ EXPORTED = ["lst_load_geometry", "lst_release_geometry", "lst_default_capacity",
             "lst_build_event", "lst_enqueue_event", "lst_event_query", "lst_event_wait",
             "lst_get_track_candidates", "lst_get_stage_objects", "lst_get_stage_counts",
             "lst_get_module_constants", "lst_release_event", "lst_last_error", "lst_kernel_site_count",
-            "lst_kernel_site_name", "lst_set_timed_site", "lst_get_site_time"]
+            "lst_kernel_site_name", "lst_set_timed_site", "lst_get_site_time", "lst_batch_workspace_bytes",
+            "lst_enqueue_batch", "lst_plan_workspace_bytes", "lst_plan_create", "lst_plan_run", "lst_plan_release"]
 
 
 class LSTError(RuntimeError):
@@ -87,6 +88,12 @@ def load_library(path=LIB_PATH):
         "lst_release_event": [vp],
         "lst_set_timed_site": [i32],
         "lst_get_site_time": [vp, P(ctypes.c_float)],
+        "lst_batch_workspace_bytes": [vp, i32, vp, vp, vp, P(sz)],
+        "lst_enqueue_batch": [vp, i32, vp, vp, vp, sz, vp, vp],
+        "lst_plan_workspace_bytes": [vp, i32, i32, i32, P(lst_capacity), P(sz)],
+        "lst_plan_create": [vp, i32, i32, i32, P(lst_capacity), vp, sz, vp, P(vp)],
+        "lst_plan_run": [vp, i32, vp, vp, vp],
+        "lst_plan_release": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -236,6 +243,66 @@ def lst_get_site_time(ev):
     return float(ms.value)
 
 
+def _caps_array(caps):
+    if caps is None:
+        return None
+    arr = (lst_capacity * len(caps))(*caps)
+    return arr
+
+
+def lst_batch_workspace_bytes(geom, n_hits, n_seeds, caps=None):
+    nh = np.ascontiguousarray(n_hits, np.int32)
+    ns = np.ascontiguousarray(n_seeds, np.int32)
+    ca = _caps_array(caps)
+    b = ctypes.c_size_t()
+    _check(load_library().lst_batch_workspace_bytes(geom, int(nh.size), _ptr(nh), _ptr(ns),
+                                                    ctypes.cast(ca, ctypes.c_void_p) if ca is not None else None,
+                                                    ctypes.byref(b)))
+    return int(b.value)
+
+
+def lst_enqueue_batch(geom, dev_events, workspace, caps=None, stream=None):
+    """Enqueues B events as one batch; returns (status, [event handles])."""
+    B = len(dev_events)
+    descs = (lst_event_desc * B)(*[_event_desc(t) for t in dev_events])
+    ca = _caps_array(caps)
+    outs = (ctypes.c_void_p * B)()
+    st = load_library().lst_enqueue_batch(geom, B, ctypes.cast(descs, ctypes.c_void_p),
+                                          ctypes.cast(ca, ctypes.c_void_p) if ca is not None else None,
+                                          _ptr(workspace), int(workspace.numel()), stream,
+                                          ctypes.cast(outs, ctypes.c_void_p))
+    return st, [o for o in outs]
+
+
+def lst_plan_workspace_bytes(geom, B, max_hits, max_seeds, cap=None):
+    b = ctypes.c_size_t()
+    _check(load_library().lst_plan_workspace_bytes(geom, int(B), int(max_hits), int(max_seeds),
+                                                   ctypes.byref(cap) if cap is not None else None, ctypes.byref(b)))
+    return int(b.value)
+
+
+def lst_plan_create(geom, B, max_hits, max_seeds, workspace, cap=None, stream=None):
+    h = ctypes.c_void_p()
+    _check(load_library().lst_plan_create(geom, int(B), int(max_hits), int(max_seeds),
+                                          ctypes.byref(cap) if cap is not None else None, _ptr(workspace),
+                                          int(workspace.numel()), stream, ctypes.byref(h)))
+    return h.value
+
+
+def lst_plan_run(plan, dev_events, stream=None):
+    """Replays the plan's graph for up to B events; returns (status, [event handles])."""
+    n = len(dev_events)
+    descs = (lst_event_desc * max(n, 1))(*[_event_desc(t) for t in dev_events])
+    outs = (ctypes.c_void_p * max(n, 1))()
+    st = load_library().lst_plan_run(plan, n, ctypes.cast(descs, ctypes.c_void_p), stream,
+                                     ctypes.cast(outs, ctypes.c_void_p))
+    return st, [outs[i] for i in range(n)]
+
+
+def lst_plan_release(plan):
+    _check(load_library().lst_plan_release(plan))
+
+
 # ------------------------------------------------------------- conveniences
 class Geometry:
     """A detector uploaded to the device (owns the lst_geometry handle)."""
@@ -301,6 +368,65 @@ def alloc_workspace(geom, n_hits, n_seeds, cap=None, device="cuda"):
     import torch
     nb = lst_workspace_bytes(geom.handle, n_hits, n_seeds, cap)
     return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def run_batch(geom, dev_events, caps=None, workspace=None, stream=None):
+    """Builds B events in one batch and waits; returns one EventResult per event."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    nh = [int(t["x"].numel()) for t in dev_events]
+    ns = [int(t["px"].numel()) for t in dev_events]
+    need = lst_batch_workspace_bytes(geom.handle, nh, ns, caps)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev_events[0]["x"].device)
+    st, hs = lst_enqueue_batch(geom.handle, dev_events, workspace, caps, stream)
+    _check(st)
+    out = []
+    for h in hs:
+        s = lst_event_wait(h)
+        out.append(EventResult(h, workspace, s))
+    bad = [r.status for r in out if r.status != LST_OK]
+    if bad:
+        msg = lst_last_error()
+        for r in out:
+            r.close()
+        raise LSTError(bad[0], msg)
+    return out
+
+
+class Plan:
+    """A captured batch chain (HIP graph) over B slots in its own workspace."""
+
+    def __init__(self, geom, B, max_hits, max_seeds, cap=None, device="cuda", stream=None):
+        import torch
+        self.B = B
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        self.workspace = torch.empty(lst_plan_workspace_bytes(geom.handle, B, max_hits, max_seeds, cap),
+                                     dtype=torch.uint8, device=device)
+        self.handle = lst_plan_create(geom.handle, B, max_hits, max_seeds, self.workspace, cap, stream)
+
+    def run(self, dev_events, wait=True):
+        st, hs = lst_plan_run(self.handle, dev_events, self.stream)
+        _check(st)
+        res = [EventResult(h, self.workspace, LST_OK) for h in hs]
+        if wait:
+            for r in res:
+                r.status = lst_event_wait(r.handle)
+        return res
+
+    def close(self):
+        if self.handle:
+            lst_plan_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def run_event(geom, dev_event, cap=None, workspace=None, stream=None, grow=True):

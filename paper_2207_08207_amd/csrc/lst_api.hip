@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <atomic>
 #include <cstring>
 #include <new>
@@ -42,21 +43,36 @@ struct lst_geometry_s {
   float4 *d_win = nullptr;
 };
 
-struct lst_event_s {
+// Events enqueued together share one batch: one descriptor array and one
+// counter block in the workspace header, one completion event, one pinned
+// read-back buffer.
+struct lst_batch_s {
   lst_geometry geom = nullptr;
-  lst::Ws ws{};
+  int B = 0;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  int *h_ctr = nullptr;  // pinned copy of the counters
+  lst::Ws *h_ws = nullptr;  // pinned: the descriptors uploaded to the header
+  int *h_ctr = nullptr;     // pinned: copy of the B x C_COUNT counters
+  int refs = 0;
   bool synced = false;
-  int timed_site = -1;   // launch site bracketed by beg/end, or -1
+  bool failed = false;      // a HIP call failed at enqueue
+  int timed_site = -1;      // launch site bracketed by tbeg/tend, or -1
   hipEvent_t tbeg = nullptr, tend = nullptr;
-  lst_status status = LST_OK;
+  lst_batch_s **owner = nullptr;  // a plan's pointer to its latest run, cleared when this batch is freed
+};
+
+struct lst_event_s {
+  lst_batch_s *batch = nullptr;
+  int index = 0;
+  const lst::Ws &ws() const { return batch->h_ws[index]; }
+  const int *ctr() const { return batch->h_ctr + (size_t)index * lst::C_COUNT; }
+  bool synced() const { return batch->synced; }
 };
 
 namespace lst {
 
-size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w, char *base) {
+size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w, char *base, int *ctr,
+                        int n_hits_alloc, int n_seeds_alloc) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> char * {
     off = (off + kAlign - 1) / kAlign * kAlign;
@@ -64,7 +80,8 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
     off += bytes ? bytes : 1;
     return p;
   };
-  const long N = n_hits, S = n_seeds, M = n_mod;
+  const long N = n_hits_alloc >= 0 ? n_hits_alloc : n_hits, S = n_seeds_alloc >= 0 ? n_seeds_alloc : n_seeds;
+  const long M = n_mod;
   const long md = c.md, ls = c.ls, t3 = c.t3, t5 = c.t5, p3 = c.pt3, p5 = c.pt5;
   const long tc = p5 + p3 + t5 + S;
 #define I(n) reinterpret_cast<int *>(take(sizeof(int) * (size_t)(n)))
@@ -74,7 +91,7 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
 #define F2(n) reinterpret_cast<float2 *>(take(sizeof(float2) * (size_t)(n)))
 #define F4(n) reinterpret_cast<float4 *>(take(sizeof(float4) * (size_t)(n)))
   Ws t{};
-  t.ctr = I(C_COUNT);
+  t.ctr = ctr;
   t.bcnt = I(2 * M + 1); t.boff = I(2 * M + 1); t.bcur = I(2 * M);
   t.hidx_tmp = I(N + 1); t.hidx = I(N + 1); t.hpos = F4(N + 1);
   t.md_cnt = I(M + 1); t.md_off = I(M + 1);
@@ -106,8 +123,44 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
 #undef F2
 #undef F4
   t.cap_md = (int)md; t.cap_ls = (int)ls; t.cap_t3 = (int)t3; t.cap_t5 = (int)t5;
-  t.cap_pt3 = (int)p3; t.cap_pt5 = (int)p5; t.cap_tc = (int)tc;
+  t.cap_pt3 = (int)p3; t.cap_pt5 = (int)p5;
   t.n_hits = n_hits; t.n_seeds = n_seeds;
+  t.cap_tc = (int)(p5 + p3 + t5 + n_seeds);
+  if (w && base) {
+    const long N = n_hits, S = n_seeds;  // the jobs follow the event's own sizes
+    int *ct = t.ctr;
+    auto sj = [&](int id, const int *in, int *out, const int *n_dev, long n_fix, long n_cap, int *req, int *clamped,
+                  long cap) { t.scans[id] = ScanJob{in, out, n_dev, (int)n_fix, (int)n_cap, req, clamped, (int)cap}; };
+    sj(SC_HITS, t.bcnt, t.boff, nullptr, 2 * M, 2 * M, ct + C_NOUTER, nullptr, 0);
+    sj(SC_MD, t.md_cnt, t.md_off, nullptr, M, M, ct + C_RMD, ct + C_NMD, md);
+    sj(SC_LS, t.ls_cnt, t.ls_off, ct + C_NMD, 0, md, ct + C_RLS, ct + C_NLS, ls);
+    sj(SC_T3, t.t3_cnt, t.t3_off, ct + C_NLS, 0, ls, ct + C_RT3, ct + C_NT3, t3);
+    sj(SC_T5, t.t5_cnt, t.t5_off, ct + C_NT3, 0, t3, ct + C_RT5, ct + C_NT5, t5);
+    sj(SC_INC, t.inc_cnt, t.inc_off, ct + C_NMD, 0, md, ct + C_NINC, nullptr, 0);
+    sj(SC_PH, t.ph_cnt, t.ph_off, nullptr, N, N, ct + C_NPH, nullptr, 0);
+    sj(SC_PT3, t.pt3_cnt, t.pt3_off, nullptr, S, S, ct + C_RPT3, ct + C_NPT3, p3);
+    sj(SC_PT5, t.pt5_cnt, t.pt5_off, nullptr, S, S, ct + C_RPT5, ct + C_NPT5, p5);
+    sj(SC_O3, t.o3_cnt, t.o3_off, ct + C_NT3, 0, t3, ct + C_NO3, nullptr, 0);
+    sj(SC_O5, t.o5_cnt, t.o5_off, ct + C_NT5, 0, t5, ct + C_NO5, nullptr, 0);
+    sj(SC_F5, t.f_pt5, t.p_pt5, ct + C_NPT5, 0, p5, ct + C_NTC0, nullptr, 0);
+    sj(SC_F3, t.f_pt3, t.p_pt3, ct + C_NPT3, 0, p3, ct + C_NTC1, nullptr, 0);
+    sj(SC_FT5, t.f_t5, t.p_t5, ct + C_NT5, 0, t5, ct + C_NTC2, nullptr, 0);
+    sj(SC_FPLS, t.f_pls, t.p_pls, nullptr, S, S, ct + C_NTC3, nullptr, 0);
+    auto fj = [&](int id, int *p, long n) { t.fills[id] = FillJob{p, n}; };
+    fj(FL_CTR, ct, C_COUNT);
+    fj(FL_BCNT, t.bcnt, 2 * M + 1);
+    fj(FL_BCUR, t.bcur, 2 * M);
+    fj(FL_INC_CNT, t.inc_cnt, md + 1);
+    fj(FL_INC_CUR, t.inc_cur, md + 1);
+    fj(FL_PH_CNT, t.ph_cnt, N + 1);
+    fj(FL_PH_CUR, t.ph_cur, N + 1);
+    fj(FL_O3_CNT, t.o3_cnt, t3 + 1);
+    fj(FL_O3_CUR, t.o3_cur, t3 + 1);
+    fj(FL_O5_CNT, t.o5_cnt, t5 + 1);
+    fj(FL_O5_CUR, t.o5_cur, t5 + 1);
+    fj(FL_SEED_USED, t.seed_used, S + 1);
+    fj(FL_T5_USED, t.t5_used, t5 + 1);
+  }
   if (w) *w = t;
   return (off + kAlign - 1) / kAlign * kAlign;
 }
@@ -227,17 +280,46 @@ lst_status lst_get_module_constants(lst_geometry g, float *out) {
   return LST_OK;
 }
 
-lst_status lst_workspace_bytes(lst_geometry g, int32_t n_hits, int32_t n_seeds, const lst_capacity *cap,
-                               size_t *bytes) {
-  if (!g || !bytes || n_hits < 0 || n_seeds < 0 || n_hits > kMaxCap || n_seeds > kMaxCap / 4)
-    return fail(LST_E_INVALID, "lst_workspace_bytes: bad argument");
-  lst_capacity c;
-  if (cap) c = *cap; else lst_default_capacity(n_hits, n_seeds, &c);
-  lst_status s = check_caps(c);
-  if (s != LST_OK) return s;
-  lst::Caps cc{c.md, c.ls, c.t3, c.t5, c.pt3, c.pt5};
-  *bytes = lst::workspace_layout(g->g.n_mod, n_hits, n_seeds, cc, nullptr, nullptr);
+// ---------------------------------------------------------------- batches
+// Workspace of a batch of B events: header (B descriptors, B x C_COUNT
+// counters), then one region per event.
+static size_t header_bytes(int B) {
+  const size_t d = ((sizeof(lst::Ws) * (size_t)B + kAlign - 1) / kAlign) * kAlign;
+  const size_t c = ((sizeof(int) * lst::C_COUNT * (size_t)B + kAlign - 1) / kAlign) * kAlign;
+  return d + c;
+}
+
+static lst_status resolve_caps(int B, const int32_t *nh, const int32_t *ns, const lst_capacity *cap,
+                               std::vector<lst::Caps> &out) {
+  out.resize(B);
+  for (int i = 0; i < B; ++i) {
+    if (nh[i] < 0 || ns[i] < 0 || nh[i] > kMaxCap || ns[i] > kMaxCap / 4)
+      return fail(LST_E_INVALID, "n_hits above 8e6 or n_seeds above 2e6, or negative");
+    lst_capacity c;
+    if (cap) c = cap[i]; else lst_default_capacity(nh[i], ns[i], &c);
+    lst_status s = check_caps(c);
+    if (s != LST_OK) return s;
+    out[i] = lst::Caps{c.md, c.ls, c.t3, c.t5, c.pt3, c.pt5};
+  }
   return LST_OK;
+}
+
+static size_t batch_bytes(int n_mod, int B, const int32_t *nh, const int32_t *ns, const std::vector<lst::Caps> &c) {
+  size_t off = header_bytes(B);
+  for (int i = 0; i < B; ++i) off += lst::workspace_layout(n_mod, nh[i], ns[i], c[i], nullptr, nullptr, nullptr);
+  return off;
+}
+
+static void release_batch_ref(lst_batch_s *b) {
+  if (--b->refs > 0) return;
+  if (b->owner && *b->owner == b) *b->owner = nullptr;
+  if (!b->synced && b->done) drop(hipEventSynchronize(b->done));
+  if (b->tbeg) drop(hipEventDestroy(b->tbeg));
+  if (b->tend) drop(hipEventDestroy(b->tend));
+  if (b->done) drop(hipEventDestroy(b->done));
+  if (b->h_ctr) drop(hipHostFree(b->h_ctr));
+  if (b->h_ws) drop(hipHostFree(b->h_ws));
+  delete b;
 }
 
 static lst_status map_status(int st) {
@@ -248,66 +330,123 @@ static lst_status map_status(int st) {
   return LST_OK;
 }
 
+lst_status lst_batch_workspace_bytes(lst_geometry g, int32_t B, const int32_t *n_hits, const int32_t *n_seeds,
+                                     const lst_capacity *cap, size_t *bytes) {
+  if (!g || !bytes || B < 1 || B > 65535 || !n_hits || !n_seeds)
+    return fail(LST_E_INVALID, "lst_batch_workspace_bytes: bad argument");
+  std::vector<lst::Caps> c;
+  lst_status s = resolve_caps(B, n_hits, n_seeds, cap, c);
+  if (s != LST_OK) return s;
+  *bytes = batch_bytes(g->g.n_mod, B, n_hits, n_seeds, c);
+  return LST_OK;
+}
+
+lst_status lst_workspace_bytes(lst_geometry g, int32_t n_hits, int32_t n_seeds, const lst_capacity *cap,
+                               size_t *bytes) {
+  return lst_batch_workspace_bytes(g, 1, &n_hits, &n_seeds, cap, bytes);
+}
+
+lst_status lst_enqueue_batch(lst_geometry g, int32_t B, const lst_event_desc *evs, const lst_capacity *cap,
+                             void *workspace, size_t ws_bytes, void *stream, lst_event *out) {
+  if (!out) return fail(LST_E_INVALID, "lst_enqueue_batch: NULL out");
+  if (!g || !evs || !workspace || B < 1 || B > 65535) return fail(LST_E_INVALID, "lst_enqueue_batch: bad argument");
+  for (int i = 0; i < B; ++i) out[i] = nullptr;
+  std::vector<int32_t> nh(B), ns(B);
+  for (int i = 0; i < B; ++i) {
+    const lst_event_desc &ev = evs[i];
+    if (ev.n_hits < 0 || ev.n_seeds < 0) return fail(LST_E_INVALID, "negative n_hits or n_seeds");
+    if (ev.n_hits > 0 && (!ev.x || !ev.y || !ev.z || !ev.module || !ev.sensor))
+      return fail(LST_E_INVALID, "hit arrays missing");
+    if (ev.n_seeds > 0 && (!ev.px || !ev.py || !ev.pz || !ev.q || !ev.hits4))
+      return fail(LST_E_INVALID, "seed arrays missing");
+    if (ev.n_seeds > 0 && ev.n_hits == 0) return fail(LST_E_INVALID, "seeds without hits");
+    nh[i] = ev.n_hits;
+    ns[i] = ev.n_seeds;
+  }
+  std::vector<lst::Caps> caps;
+  lst_status s = resolve_caps(B, nh.data(), ns.data(), cap, caps);
+  if (s != LST_OK) return s;
+  const size_t need = batch_bytes(g->g.n_mod, B, nh.data(), ns.data(), caps);
+  if (ws_bytes < need) return fail(LST_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return fail(LST_E_INVALID, "workspace not 256-byte aligned");
+  auto *b = new (std::nothrow) lst_batch_s();
+  if (!b) return fail(LST_E_NOMEM, "host allocation failed");
+  b->geom = g;
+  b->B = B;
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  b->refs = B;
+  if (hipHostMalloc(reinterpret_cast<void **>(&b->h_ctr), sizeof(int) * lst::C_COUNT * B, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&b->h_ws), sizeof(lst::Ws) * B, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+    b->refs = 1;
+    release_batch_ref(b);
+    return fail(LST_E_DEVICE, "lst_enqueue_batch: pinned buffers or event creation failed");
+  }
+  char *base = reinterpret_cast<char *>(workspace);
+  lst::Ws *d_ws = reinterpret_cast<lst::Ws *>(base);
+  int *d_ctr = reinterpret_cast<int *>(base + ((sizeof(lst::Ws) * (size_t)B + kAlign - 1) / kAlign) * kAlign);
+  size_t off = header_bytes(B);
+  lst::Ws bound{};
+  for (int i = 0; i < B; ++i) {
+    lst::Ws &w = b->h_ws[i];
+    off += lst::workspace_layout(g->g.n_mod, nh[i], ns[i], caps[i], &w, base + off, d_ctr + (size_t)i * lst::C_COUNT);
+    const lst_event_desc &ev = evs[i];
+    w.x = ev.x; w.y = ev.y; w.z = ev.z; w.module = ev.module; w.sensor = ev.sensor;
+    w.px = ev.px; w.py = ev.py; w.pz = ev.pz; w.q = ev.q; w.hits4 = ev.hits4;
+    bound.n_hits = std::max(bound.n_hits, w.n_hits);
+    bound.n_seeds = std::max(bound.n_seeds, w.n_seeds);
+    bound.cap_md = std::max(bound.cap_md, w.cap_md);
+    bound.cap_ls = std::max(bound.cap_ls, w.cap_ls);
+    bound.cap_t3 = std::max(bound.cap_t3, w.cap_t3);
+    bound.cap_t5 = std::max(bound.cap_t5, w.cap_t5);
+    bound.cap_pt3 = std::max(bound.cap_pt3, w.cap_pt3);
+    bound.cap_pt5 = std::max(bound.cap_pt5, w.cap_pt5);
+    bound.cap_tc = std::max(bound.cap_tc, w.cap_tc);
+  }
+  lst::KernelTimer kt{-1, nullptr, nullptr};
+  const int site = g_timed_site.load();
+  if (site >= 0 && hipEventCreate(&b->tbeg) == hipSuccess && hipEventCreate(&b->tend) == hipSuccess) {
+    kt = lst::KernelTimer{site, b->tbeg, b->tend};
+    b->timed_site = site;
+  }
+  hipError_t he = hipMemcpyAsync(d_ws, b->h_ws, sizeof(lst::Ws) * B, hipMemcpyHostToDevice, b->stream);
+  if (he == hipSuccess) {
+    lst::enqueue_chain(g->g, d_ws, B, bound, b->stream, b->timed_site >= 0 ? &kt : nullptr);
+    he = hipGetLastError();
+  }
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(b->h_ctr, d_ctr, sizeof(int) * lst::C_COUNT * B, hipMemcpyDeviceToHost, b->stream);
+  if (he == hipSuccess) he = hipEventRecord(b->done, b->stream);
+  if (he != hipSuccess) b->failed = true;
+  for (int i = 0; i < B; ++i) {
+    auto *e = new (std::nothrow) lst_event_s();
+    if (!e) {
+      for (int k = i; k < B; ++k) release_batch_ref(b);
+      return fail(LST_E_NOMEM, "host allocation failed");
+    }
+    e->batch = b;
+    e->index = i;
+    out[i] = e;
+  }
+  if (he != hipSuccess) return fail(LST_E_DEVICE, std::string("lst_enqueue_batch: ") + hipGetErrorString(he));
+  return LST_OK;
+}
+
 lst_status lst_enqueue_event(lst_geometry g, const lst_event_desc *ev, const lst_capacity *cap, void *workspace,
                              size_t ws_bytes, void *stream, lst_event *out) {
   if (!out) return fail(LST_E_INVALID, "lst_enqueue_event: NULL out");
   *out = nullptr;
-  if (!g || !ev || !workspace) return fail(LST_E_INVALID, "lst_enqueue_event: NULL argument");
-  if (ev->n_hits < 0 || ev->n_seeds < 0) return fail(LST_E_INVALID, "negative n_hits or n_seeds");
-  if (ev->n_hits > kMaxCap || ev->n_seeds > kMaxCap / 4) return fail(LST_E_INVALID, "n_hits above 8e6 or n_seeds above 2e6");
-  if (ev->n_hits > 0 && (!ev->x || !ev->y || !ev->z || !ev->module || !ev->sensor))
-    return fail(LST_E_INVALID, "hit arrays missing");
-  if (ev->n_seeds > 0 && (!ev->px || !ev->py || !ev->pz || !ev->q || !ev->hits4))
-    return fail(LST_E_INVALID, "seed arrays missing");
-  if (ev->n_seeds > 0 && ev->n_hits == 0) return fail(LST_E_INVALID, "seeds without hits");
-  lst_capacity c;
-  if (cap) c = *cap; else lst_default_capacity(ev->n_hits, ev->n_seeds, &c);
-  lst_status s = check_caps(c);
-  if (s != LST_OK) return s;
-  lst::Caps cc{c.md, c.ls, c.t3, c.t5, c.pt3, c.pt5};
-  const size_t need = lst::workspace_layout(g->g.n_mod, ev->n_hits, ev->n_seeds, cc, nullptr, nullptr);
-  if (ws_bytes < need)
-    return fail(LST_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return fail(LST_E_INVALID, "workspace not 256-byte aligned");
-  auto *e = new (std::nothrow) lst_event_s();
-  if (!e) return fail(LST_E_NOMEM, "host allocation failed");
-  e->geom = g;
-  e->stream = reinterpret_cast<hipStream_t>(stream);
-  lst::workspace_layout(g->g.n_mod, ev->n_hits, ev->n_seeds, cc, &e->ws, reinterpret_cast<char *>(workspace));
-  lst::Ws &w = e->ws;
-  w.x = ev->x; w.y = ev->y; w.z = ev->z; w.module = ev->module; w.sensor = ev->sensor;
-  w.px = ev->px; w.py = ev->py; w.pz = ev->pz; w.q = ev->q; w.hits4 = ev->hits4;
-  if (hipHostMalloc(reinterpret_cast<void **>(&e->h_ctr), sizeof(int) * lst::C_COUNT, hipHostMallocDefault) !=
-          hipSuccess ||
-      hipEventCreateWithFlags(&e->done, hipEventDisableTiming) != hipSuccess) {
-    if (e->h_ctr) drop(hipHostFree(e->h_ctr));
-    delete e;
-    return fail(LST_E_DEVICE, "lst_enqueue_event: pinned buffer or event creation failed");
-  }
-  lst::KernelTimer kt{-1, nullptr, nullptr};
-  const int site = g_timed_site.load();
-  if (site >= 0 && hipEventCreate(&e->tbeg) == hipSuccess && hipEventCreate(&e->tend) == hipSuccess) {
-    kt = lst::KernelTimer{site, e->tbeg, e->tend};
-    e->timed_site = site;
-  }
-  lst::enqueue_chain(g->g, w, e->stream, e->timed_site >= 0 ? &kt : nullptr);
-  hipError_t he = hipGetLastError();
-  if (he == hipSuccess)
-    he = hipMemcpyAsync(e->h_ctr, w.ctr, sizeof(int) * lst::C_COUNT, hipMemcpyDeviceToHost, e->stream);
-  if (he == hipSuccess) he = hipEventRecord(e->done, e->stream);
-  if (he != hipSuccess) {
-    e->status = LST_E_DEVICE;
-    *out = e;
-    return fail(LST_E_DEVICE, std::string("lst_enqueue_event: ") + hipGetErrorString(he));
-  }
-  *out = e;
-  return LST_OK;
+  if (!ev) return fail(LST_E_INVALID, "lst_enqueue_event: NULL event");
+  return lst_enqueue_batch(g, 1, ev, cap, workspace, ws_bytes, stream, out);
 }
 
 lst_status lst_event_query(lst_event e, int32_t *done) {
   if (!e || !done) return fail(LST_E_INVALID, "lst_event_query: NULL argument");
-  if (e->synced) { *done = 1; return LST_OK; }
-  hipError_t q = hipEventQuery(e->done);
+  lst_batch_s *b = e->batch;
+  if (b->synced) { *done = 1; return LST_OK; }
+  if (b->failed) return fail(LST_E_DEVICE, "event failed at enqueue");
+  hipError_t q = hipEventQuery(b->done);
   if (q == hipErrorNotReady) { *done = 0; return LST_OK; }
   if (q != hipSuccess) return fail(LST_E_DEVICE, hipGetErrorString(q));
   *done = 1;
@@ -316,14 +455,13 @@ lst_status lst_event_query(lst_event e, int32_t *done) {
 
 lst_status lst_event_wait(lst_event e) {
   if (!e) return fail(LST_E_INVALID, "lst_event_wait: NULL event");
-  if (!e->synced) {
-    if (e->status == LST_E_DEVICE) return fail(LST_E_DEVICE, "event failed at enqueue");
-    HIP_TRY(hipEventSynchronize(e->done));
-    e->synced = true;
-    e->status = map_status(e->h_ctr[lst::C_STATUS]);
+  lst_batch_s *b = e->batch;
+  if (b->failed) return fail(LST_E_DEVICE, "event failed at enqueue");
+  if (!b->synced) {
+    HIP_TRY(hipEventSynchronize(b->done));
+    b->synced = true;
   }
-  if (e->status != LST_OK) map_status(e->h_ctr[lst::C_STATUS]);
-  return e->status;
+  return map_status(e->ctr()[lst::C_STATUS]);
 }
 
 lst_status lst_build_event(lst_geometry g, const lst_event_desc *ev, const lst_capacity *cap, void *workspace,
@@ -333,14 +471,20 @@ lst_status lst_build_event(lst_geometry g, const lst_event_desc *ev, const lst_c
   return lst_event_wait(*out);
 }
 
+static lst_status event_ok(lst_event e) {
+  if (!e->synced()) return fail(LST_E_STATE, "event not complete");
+  return LST_OK;
+}
+
 lst_status lst_get_stage_counts(lst_event e, int64_t *counts, int64_t *required) {
   if (!e) return fail(LST_E_INVALID, "lst_get_stage_counts: NULL event");
-  if (!e->synced) return fail(LST_E_STATE, "event not complete");
-  const int *c = e->h_ctr;
+  if (event_ok(e) != LST_OK) return LST_E_STATE;
+  const int *c = e->ctr();
+  const int ns = e->ws().n_seeds;
   const int built[8] = {c[lst::C_NMD], c[lst::C_NLS], c[lst::C_NT3], c[lst::C_NT5],
-                        e->ws.n_seeds, c[lst::C_NPT3], c[lst::C_NPT5], c[lst::C_NTC]};
+                        ns, c[lst::C_NPT3], c[lst::C_NPT5], c[lst::C_NTC]};
   const int req[8] = {c[lst::C_RMD], c[lst::C_RLS], c[lst::C_RT3], c[lst::C_RT5],
-                      e->ws.n_seeds, c[lst::C_RPT3], c[lst::C_RPT5], c[lst::C_NTC]};
+                      ns, c[lst::C_RPT3], c[lst::C_RPT5], c[lst::C_NTC]};
   for (int i = 0; i < 8; ++i) {
     if (counts) counts[i] = built[i];
     if (required) required[i] = req[i];
@@ -351,23 +495,25 @@ lst_status lst_get_stage_counts(lst_event e, int64_t *counts, int64_t *required)
 lst_status lst_get_track_candidates(lst_event e, int32_t *n_tc, int32_t *n_hits_total, int32_t *type,
                                     int32_t *offsets, int32_t *hits) {
   if (!e || !n_tc || !n_hits_total) return fail(LST_E_INVALID, "lst_get_track_candidates: NULL argument");
-  if (!e->synced) return fail(LST_E_STATE, "event not complete");
-  if (e->status != LST_OK) return fail(LST_E_STATE, "event did not build (status " + std::to_string(e->status) + ")");
-  const int n = e->h_ctr[lst::C_NTC], nh = e->h_ctr[lst::C_NTCHITS];
+  if (event_ok(e) != LST_OK) return LST_E_STATE;
+  const int st = e->ctr()[lst::C_STATUS];
+  if (st != 0) return fail(LST_E_STATE, "event did not build (status flags " + std::to_string(st) + ")");
+  const lst::Ws &w = e->ws();
+  const int n = e->ctr()[lst::C_NTC], nh = e->ctr()[lst::C_NTCHITS];
   *n_tc = n;
   *n_hits_total = nh;
-  if (type && n > 0) HIP_TRY(hipMemcpy(type, e->ws.tc_type, sizeof(int) * n, hipMemcpyDeviceToHost));
-  if (offsets) HIP_TRY(hipMemcpy(offsets, e->ws.tc_off, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
-  if (hits && nh > 0) HIP_TRY(hipMemcpy(hits, e->ws.tc_hits, sizeof(int) * nh, hipMemcpyDeviceToHost));
+  if (type && n > 0) HIP_TRY(hipMemcpy(type, w.tc_type, sizeof(int) * n, hipMemcpyDeviceToHost));
+  if (offsets) HIP_TRY(hipMemcpy(offsets, w.tc_off, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+  if (hits && nh > 0) HIP_TRY(hipMemcpy(hits, w.tc_hits, sizeof(int) * nh, hipMemcpyDeviceToHost));
   return LST_OK;
 }
 
 lst_status lst_get_stage_objects(lst_event e, int32_t stage, int32_t *n_out, int32_t *tuples, int32_t *flags,
                                  float *attrs) {
   if (!e || !n_out || stage < 0 || stage > 6) return fail(LST_E_INVALID, "lst_get_stage_objects: bad argument");
-  if (!e->synced) return fail(LST_E_STATE, "event not complete");
-  const int *c = e->h_ctr;
-  const lst::Ws &w = e->ws;
+  if (event_ok(e) != LST_OK) return LST_E_STATE;
+  const int *c = e->ctr();
+  const lst::Ws &w = e->ws();
   const int cnt[7] = {c[lst::C_NMD], c[lst::C_NLS], c[lst::C_NT3], c[lst::C_NT5], w.n_seeds, c[lst::C_NPT3],
                       c[lst::C_NPT5]};
   const int n = cnt[stage];
@@ -387,17 +533,17 @@ lst_status lst_get_stage_objects(lst_event e, int32_t stage, int32_t *n_out, int
     mds.resize(n);
     for (int i = 0; i < n; ++i) mds[i] = i;
   } else if (stage == 1) {
-    std::vector<int2> v; std::vector<float2> b;
-    HIP_TRY(d2h(v, w.ls_md, n)); HIP_TRY(d2h(b, w.ls_beta, n));
+    std::vector<int2> v; std::vector<float2> bb;
+    HIP_TRY(d2h(v, w.ls_md, n)); HIP_TRY(d2h(bb, w.ls_beta, n));
     k = 2; mds.resize(2 * (size_t)n);
-    for (int i = 0; i < n; ++i) { mds[2 * i] = v[i].x; mds[2 * i + 1] = v[i].y; a[2 * i] = b[i].x; a[2 * i + 1] = b[i].y; }
+    for (int i = 0; i < n; ++i) { mds[2 * i] = v[i].x; mds[2 * i + 1] = v[i].y; a[2 * i] = bb[i].x; a[2 * i + 1] = bb[i].y; }
   } else if (stage == 2) {
-    std::vector<int4> v; std::vector<float4> b;
-    HIP_TRY(d2h(v, w.t3_md, n)); HIP_TRY(d2h(b, w.t3_attr, n));
+    std::vector<int4> v; std::vector<float4> bb;
+    HIP_TRY(d2h(v, w.t3_md, n)); HIP_TRY(d2h(bb, w.t3_attr, n));
     k = 3; mds.resize(3 * (size_t)n);
     for (int i = 0; i < n; ++i) {
       mds[3 * i] = v[i].x; mds[3 * i + 1] = v[i].y; mds[3 * i + 2] = v[i].z;
-      a[4 * i] = b[i].x; a[4 * i + 1] = b[i].y; a[4 * i + 2] = b[i].z; a[4 * i + 3] = b[i].w;
+      a[4 * i] = bb[i].x; a[4 * i + 1] = bb[i].y; a[4 * i + 2] = bb[i].z; a[4 * i + 3] = bb[i].w;
     }
   } else if (stage == 3) {
     k = 5;
@@ -414,9 +560,9 @@ lst_status lst_get_stage_objects(lst_event e, int32_t stage, int32_t *n_out, int
     for (int i = 0; i < n; ++i) seeds[i] = i;
   } else {
     const bool five = stage == 6;
-    std::vector<int2> so; std::vector<float4> b;
+    std::vector<int2> so; std::vector<float4> bb;
     HIP_TRY(d2h(so, five ? (const void *)w.pt5_so : (const void *)w.pt3_so, n));
-    HIP_TRY(d2h(b, five ? (const void *)w.pt5_attr : (const void *)w.pt3_attr, n));
+    HIP_TRY(d2h(bb, five ? (const void *)w.pt5_attr : (const void *)w.pt3_attr, n));
     HIP_TRY(d2h(f, five ? w.pt5_keep : w.pt3_keep, n));
     k = five ? 5 : 3;
     mds.resize((size_t)k * n);
@@ -435,7 +581,7 @@ lst_status lst_get_stage_objects(lst_event e, int32_t stage, int32_t *n_out, int
     }
     for (int i = 0; i < n; ++i) {
       seeds[i] = so[i].x;
-      a[3 * i] = b[i].x; a[3 * i + 1] = b[i].y; a[3 * i + 2] = b[i].z;
+      a[3 * i] = bb[i].x; a[3 * i + 1] = bb[i].y; a[3 * i + 2] = bb[i].z;
     }
   }
   const int tw = kTupleW[stage];
@@ -448,6 +594,158 @@ lst_status lst_get_stage_objects(lst_event e, int32_t stage, int32_t *n_out, int
   }
   if (flags && n > 0) std::memcpy(flags, f.data(), sizeof(int) * n);
   if (attrs && kAttrW[stage] && n > 0) std::memcpy(attrs, a.data(), sizeof(float) * (size_t)n * kAttrW[stage]);
+  return LST_OK;
+}
+
+lst_status lst_release_event(lst_event e);
+
+// ------------------------------------------------------------------ plans
+struct lst_plan_s {
+  lst_geometry geom = nullptr;
+  int B = 0, max_hits = 0, max_seeds = 0;
+  lst::Caps caps{};
+  char *base = nullptr;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  lst_batch_s *pending = nullptr;  // the last run, until all its events are released
+};
+
+static size_t plan_bytes(int n_mod, int B, int max_hits, int max_seeds, const lst::Caps &c) {
+  return header_bytes(B) +
+         (size_t)B * lst::workspace_layout(n_mod, max_hits, max_seeds, c, nullptr, nullptr, nullptr);
+}
+
+lst_status lst_plan_workspace_bytes(lst_geometry g, int32_t B, int32_t max_hits, int32_t max_seeds,
+                                    const lst_capacity *cap, size_t *bytes) {
+  if (!g || !bytes || B < 1 || B > 65535) return fail(LST_E_INVALID, "lst_plan_workspace_bytes: bad argument");
+  std::vector<lst::Caps> c;
+  lst_status s = resolve_caps(1, &max_hits, &max_seeds, cap, c);
+  if (s != LST_OK) return s;
+  *bytes = plan_bytes(g->g.n_mod, B, max_hits, max_seeds, c[0]);
+  return LST_OK;
+}
+
+// Descriptor of slot i of a plan holding event `ev` (NULL = empty slot).
+static void plan_slot(const lst_plan_s *p, int i, const lst_event_desc *ev, lst::Ws *w) {
+  const size_t slot = lst::workspace_layout(p->geom->g.n_mod, p->max_hits, p->max_seeds, p->caps, nullptr, nullptr,
+                                            nullptr);
+  int *d_ctr = reinterpret_cast<int *>(p->base + ((sizeof(lst::Ws) * (size_t)p->B + kAlign - 1) / kAlign) * kAlign);
+  const int nh = ev ? ev->n_hits : 0, ns = ev ? ev->n_seeds : 0;
+  lst::workspace_layout(p->geom->g.n_mod, nh, ns, p->caps, w, p->base + header_bytes(p->B) + slot * i,
+                        d_ctr + (size_t)i * lst::C_COUNT, p->max_hits, p->max_seeds);
+  if (ev) {
+    w->x = ev->x; w->y = ev->y; w->z = ev->z; w->module = ev->module; w->sensor = ev->sensor;
+    w->px = ev->px; w->py = ev->py; w->pz = ev->pz; w->q = ev->q; w->hits4 = ev->hits4;
+  }
+}
+
+lst_status lst_plan_create(lst_geometry g, int32_t B, int32_t max_hits, int32_t max_seeds, const lst_capacity *cap,
+                           void *workspace, size_t ws_bytes, void *stream, lst_plan *out) {
+  if (!out) return fail(LST_E_INVALID, "lst_plan_create: NULL out");
+  *out = nullptr;
+  if (!g || !workspace || B < 1 || B > 65535) return fail(LST_E_INVALID, "lst_plan_create: bad argument");
+  std::vector<lst::Caps> c;
+  lst_status s = resolve_caps(1, &max_hits, &max_seeds, cap, c);
+  if (s != LST_OK) return s;
+  const size_t need = plan_bytes(g->g.n_mod, B, max_hits, max_seeds, c[0]);
+  if (ws_bytes < need) return fail(LST_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return fail(LST_E_INVALID, "workspace not 256-byte aligned");
+  auto *p = new (std::nothrow) lst_plan_s();
+  if (!p) return fail(LST_E_NOMEM, "host allocation failed");
+  p->geom = g; p->B = B; p->max_hits = max_hits; p->max_seeds = max_seeds; p->caps = c[0];
+  p->base = reinterpret_cast<char *>(workspace);
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  // launch grids of the captured chain follow the slot bounds
+  lst::Ws bound{};
+  plan_slot(p, 0, nullptr, &bound);
+  bound.n_hits = max_hits;
+  bound.n_seeds = max_seeds;
+  bound.cap_tc = (int)(c[0].pt5 + c[0].pt3 + c[0].t5 + max_seeds);
+  const lst::Ws *d_ws = reinterpret_cast<const lst::Ws *>(p->base);
+  hipStream_t cs = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    lst::enqueue_chain(g->g, d_ws, B, bound, cs, nullptr);
+    hipError_t le = hipGetLastError();
+    e = hipStreamEndCapture(cs, &p->graph);
+    if (e == hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+  if (cs) drop(hipStreamDestroy(cs));
+  if (e != hipSuccess) {
+    if (p->exec) drop(hipGraphExecDestroy(p->exec));
+    if (p->graph) drop(hipGraphDestroy(p->graph));
+    delete p;
+    return fail(LST_E_DEVICE, std::string("lst_plan_create: graph capture failed: ") + hipGetErrorString(e));
+  }
+  *out = p;
+  return LST_OK;
+}
+
+lst_status lst_plan_run(lst_plan p, int32_t n_events, const lst_event_desc *evs, void *stream, lst_event *out) {
+  if (!p || !out || n_events < 0 || n_events > p->B || (n_events > 0 && !evs))
+    return fail(LST_E_INVALID, "lst_plan_run: bad argument");
+  for (int i = 0; i < n_events; ++i) {
+    out[i] = nullptr;
+    const lst_event_desc &ev = evs[i];
+    if (ev.n_hits < 0 || ev.n_seeds < 0 || ev.n_hits > p->max_hits || ev.n_seeds > p->max_seeds)
+      return fail(LST_E_INVALID, "event larger than the plan's slots");
+    if (ev.n_hits > 0 && (!ev.x || !ev.y || !ev.z || !ev.module || !ev.sensor))
+      return fail(LST_E_INVALID, "hit arrays missing");
+    if (ev.n_seeds > 0 && (!ev.px || !ev.py || !ev.pz || !ev.q || !ev.hits4))
+      return fail(LST_E_INVALID, "seed arrays missing");
+  }
+  if (p->pending) return fail(LST_E_STATE, "events of the previous run of this plan are still held");
+  auto *b = new (std::nothrow) lst_batch_s();
+  if (!b) return fail(LST_E_NOMEM, "host allocation failed");
+  b->geom = p->geom;
+  b->B = p->B;
+  b->stream = stream ? reinterpret_cast<hipStream_t>(stream) : p->stream;
+  b->refs = 1;  // creation reference, dropped at the end of this call
+  if (hipHostMalloc(reinterpret_cast<void **>(&b->h_ctr), sizeof(int) * lst::C_COUNT * p->B, hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void **>(&b->h_ws), sizeof(lst::Ws) * p->B, hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+    release_batch_ref(b);
+    return fail(LST_E_DEVICE, "lst_plan_run: pinned buffers or event creation failed");
+  }
+  for (int i = 0; i < p->B; ++i) plan_slot(p, i, i < n_events ? &evs[i] : nullptr, &b->h_ws[i]);
+  int *d_ctr = reinterpret_cast<int *>(p->base + ((sizeof(lst::Ws) * (size_t)p->B + kAlign - 1) / kAlign) * kAlign);
+  hipError_t he = hipMemcpyAsync(p->base, b->h_ws, sizeof(lst::Ws) * p->B, hipMemcpyHostToDevice, b->stream);
+  if (he == hipSuccess) he = hipGraphLaunch(p->exec, b->stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(b->h_ctr, d_ctr, sizeof(int) * lst::C_COUNT * p->B, hipMemcpyDeviceToHost, b->stream);
+  if (he == hipSuccess) he = hipEventRecord(b->done, b->stream);
+  if (he != hipSuccess) b->failed = true;
+  for (int i = 0; i < n_events; ++i) {
+    auto *e = new (std::nothrow) lst_event_s();
+    if (!e) {
+      for (int k = 0; k < i; ++k) { lst_release_event(out[k]); out[k] = nullptr; }
+      release_batch_ref(b);
+      return fail(LST_E_NOMEM, "host allocation failed");
+    }
+    e->batch = b;
+    e->index = i;
+    ++b->refs;
+    out[i] = e;
+  }
+  // The events' objects live in the plan's workspace: the next run is refused
+  // until every event of this one has been released (which waits for it).
+  b->owner = &p->pending;
+  p->pending = b;
+  release_batch_ref(b);
+  if (he != hipSuccess) return fail(LST_E_DEVICE, std::string("lst_plan_run: ") + hipGetErrorString(he));
+  return LST_OK;
+}
+
+lst_status lst_plan_release(lst_plan p) {
+  if (!p) return LST_OK;
+  if (p->pending) p->pending->owner = nullptr;
+  if (p->exec) drop(hipGraphExecDestroy(p->exec));
+  if (p->graph) drop(hipGraphDestroy(p->graph));
+  delete p;
   return LST_OK;
 }
 
@@ -465,19 +763,15 @@ lst_status lst_set_timed_site(int32_t site) {
 
 lst_status lst_get_site_time(lst_event e, float *ms) {
   if (!e || !ms) return fail(LST_E_INVALID, "lst_get_site_time: NULL argument");
-  if (!e->synced) return fail(LST_E_STATE, "event not complete");
-  if (e->timed_site < 0) return fail(LST_E_STATE, "no launch site was timed for this event");
-  HIP_TRY(hipEventElapsedTime(ms, e->tbeg, e->tend));
+  if (event_ok(e) != LST_OK) return LST_E_STATE;
+  if (e->batch->timed_site < 0) return fail(LST_E_STATE, "no launch site was timed for this event");
+  HIP_TRY(hipEventElapsedTime(ms, e->batch->tbeg, e->batch->tend));
   return LST_OK;
 }
 
 lst_status lst_release_event(lst_event e) {
   if (!e) return LST_OK;
-  if (e->tbeg) drop(hipEventDestroy(e->tbeg));
-  if (e->tend) drop(hipEventDestroy(e->tend));
-  if (!e->synced && e->done) drop(hipEventSynchronize(e->done));
-  if (e->done) drop(hipEventDestroy(e->done));
-  if (e->h_ctr) drop(hipHostFree(e->h_ctr));
+  release_batch_ref(e->batch);
   delete e;
   return LST_OK;
 }

@@ -55,34 +55,44 @@ __device__ __forceinline__ int block_sum(int v, int *s_red) {
 __device__ __forceinline__ int dev_count(const int *p, int fallback) { return p ? *p : fallback; }
 
 // ------------------------------------------------------------------ fill
-__global__ void k_fill(int *p, long n, int v) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = v;
+// Clears the arrays of fill jobs [j0, j1) of every event of the batch.
+__global__ void k_clear(const Ws *__restrict__ wb, int j0, int j1) {
+  const Ws &w = wb[blockIdx.y];
+  for (int j = j0; j < j1; ++j) {
+    int *p = w.fills[j].p;
+    const long n = w.fills[j].n;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0;
+  }
 }
 
 // ------------------------------------------------------------------ scan
 // Exclusive scan of in[0..n) into out[0..n], out[n] = total; n = *n_dev (or
 // n_fix).  Three passes: block sums, scan of block sums, block scans.
-__global__ void k_scan_reduce(const int *in, const int *n_dev, int n_fix, int *bsum) {
+__global__ void k_scan_reduce(const Ws *__restrict__ wb, int job) {
   __shared__ int s_red[kWaves];
-  const int n = dev_count(n_dev, n_fix);
+  const Ws &w = wb[blockIdx.y];
+  const ScanJob &J = w.scans[job];
+  const int n = dev_count(J.n_dev, J.n_fix);
   const long base = (long)blockIdx.x * kScanTile;
   if (base >= n && blockIdx.x > 0) return;
   int v = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const long i = base + (long)k * kBlock + threadIdx.x;
-    if (i < n) v += in[i];
+    if (i < n) v += J.in[i];
   }
   v = block_sum(v, s_red);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = v;
+  if (threadIdx.x == 0) w.scan_tmp[blockIdx.x] = v;
 }
 
-__global__ void k_scan_top(int *bsum, const int *n_dev, int n_fix, int *total_req, int *total_clamped, int cap,
-                           int *status) {
+__global__ void k_scan_top(const Ws *__restrict__ wb, int job) {
   // single block of 1024 threads: exclusive scan of up to kMaxScanBlocks block sums
   __shared__ int s[kMaxScanBlocks];
   __shared__ int s_w[16];
-  const int n = dev_count(n_dev, n_fix);
+  const Ws &w = wb[blockIdx.y];
+  const ScanJob &J = w.scans[job];
+  int *bsum = w.scan_tmp;
+  const int n = dev_count(J.n_dev, J.n_fix);
   const int nb = n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
   for (int i = threadIdx.x; i < kMaxScanBlocks; i += blockDim.x) s[i] = (i < nb) ? bsum[i] : 0;
   __syncthreads();
@@ -99,7 +109,7 @@ __global__ void k_scan_top(int *bsum, const int *n_dev, int n_fix, int *total_re
   if (lane_id() == 63) s_w[t >> 6] = x;
   __syncthreads();
   int wbase = 0;
-  for (int w = 0; w < (t >> 6); ++w) wbase += s_w[w];
+  for (int q = 0; q < (t >> 6); ++q) wbase += s_w[q];
   const int excl = wbase + x - sum;
   __syncthreads();
   s[4 * t] = excl;
@@ -110,24 +120,26 @@ __global__ void k_scan_top(int *bsum, const int *n_dev, int n_fix, int *total_re
   for (int i = threadIdx.x; i < nb; i += blockDim.x) bsum[i] = s[i];
   if (threadIdx.x == blockDim.x - 1) {
     const int tot = excl + sum;
-    if (total_req) *total_req = tot;
-    if (total_clamped) {
-      *total_clamped = tot < cap ? tot : cap;
-      if (tot > cap) atomicOr(status, (int)ST_CAPACITY);
+    if (J.tot_req) *J.tot_req = tot;
+    if (J.tot_clamped) {
+      *J.tot_clamped = tot < J.cap ? tot : J.cap;
+      if (tot > J.cap) atomicOr(w.ctr + C_STATUS, (int)ST_CAPACITY);
     }
   }
 }
 
-__global__ void k_scan_apply(const int *in, int *out, const int *n_dev, int n_fix, const int *bsum) {
+__global__ void k_scan_apply(const Ws *__restrict__ wb, int job) {
   __shared__ int s_wave[kWaves];
-  const int n = dev_count(n_dev, n_fix);
+  const Ws &w = wb[blockIdx.y];
+  const ScanJob &J = w.scans[job];
+  const int n = dev_count(J.n_dev, J.n_fix);
   const long base = (long)blockIdx.x * kScanTile;
   if (base > n) return;
-  int run = bsum[blockIdx.x];
+  int run = w.scan_tmp[blockIdx.x];
   // the block's tile in kScanItems rounds of kBlock consecutive items
   for (int k = 0; k < kScanItems; ++k) {
     const long i = base + (long)k * kBlock + threadIdx.x;
-    const int v = (i < n) ? in[i] : 0;
+    const int v = (i < n) ? J.in[i] : 0;
     // inclusive scan within the wave
     int x = v;
     for (int o = 1; o < 64; o <<= 1) {
@@ -136,19 +148,17 @@ __global__ void k_scan_apply(const int *in, int *out, const int *n_dev, int n_fi
     }
     if (lane_id() == 63) s_wave[threadIdx.x >> 6] = x;
     __syncthreads();
-    int wb = 0, tot = 0;
+    int wbs = 0, tot = 0;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) {
-      const int c = s_wave[w];
-      wb += (w < (int)(threadIdx.x >> 6)) ? c : 0;
+    for (int q = 0; q < kWaves; ++q) {
+      const int c = s_wave[q];
+      wbs += (q < (int)(threadIdx.x >> 6)) ? c : 0;
       tot += c;
     }
-    if (i < n) out[i] = run + wb + x - v;
-    if (i == n) out[i] = run + wb + x - v;  // out[n] = total
+    if (i <= n) J.out[i] = run + wbs + x - v;  // out[n] = total
     __syncthreads();
     run += tot;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0 && n == 0) out[0] = 0;
 }
 
 // blocks for one wave per item (capped; kernels stride)
@@ -166,13 +176,12 @@ static inline int grid_for(long n) {
   return (int)g;
 }
 
-// out[0..n] exclusive scan of in[0..n); n on the device (n_dev) or fixed.
-static void scan(const int *in, int *out, const int *n_dev, int n_fix, int n_cap, int *tmp, int *total_req,
-                 int *total_clamped, int cap, int *status, hipStream_t st) {
-  const int nb = (n_cap + kScanTile) / kScanTile;  // tiles covering n_cap + 1 outputs
-  k_scan_reduce<<<nb, kBlock, 0, st>>>(in, n_dev, n_fix, tmp);
-  k_scan_top<<<1, 1024, 0, st>>>(tmp, n_dev, n_fix, total_req, total_clamped, cap, status);
-  k_scan_apply<<<nb, kBlock, 0, st>>>(in, out, n_dev, n_fix, tmp);
+// Scan job `job` of every event of the batch; n_cap bounds the item count.
+static void scan(const Ws *wb, int B, int job, long n_cap, hipStream_t st) {
+  const int nb = (int)((n_cap + kScanTile) / kScanTile);  // tiles covering n_cap + 1 outputs
+  k_scan_reduce<<<dim3(nb, B), kBlock, 0, st>>>(wb, job);
+  k_scan_top<<<dim3(1, B), 1024, 0, st>>>(wb, job);
+  k_scan_apply<<<dim3(nb, B), kBlock, 0, st>>>(wb, job);
 }
 
 // ------------------------------------------------------------- windows
@@ -193,7 +202,8 @@ void launch_module_windows(const int *info, const float *pos_lo, const float *po
 
 // ------------------------------------------------------------- a0: hits
 // Validation of the inputs and histogram of outer-tracker hits per (module, sensor).
-__global__ void k_hits_count(Ws w, int n_mod) {
+__global__ void k_hits_count(const Ws *__restrict__ wb, int n_mod) {
+  const Ws &w = wb[blockIdx.y];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < w.n_hits; i += gridDim.x * blockDim.x) {
     const int m = w.module[i];
     const float x = w.x[i], y = w.y[i], z = w.z[i];
@@ -217,7 +227,8 @@ __global__ void k_hits_count(Ws w, int n_mod) {
   }
 }
 
-__global__ void k_hits_scatter(Ws w, int n_mod) {
+__global__ void k_hits_scatter(const Ws *__restrict__ wb, int n_mod) {
+  const Ws &w = wb[blockIdx.y];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < w.n_hits; i += gridDim.x * blockDim.x) {
     const int m = w.module[i];
     if (m < 0 || m >= n_mod) continue;
@@ -233,7 +244,8 @@ __global__ void k_hits_scatter(Ws w, int n_mod) {
 
 // One wave per bucket: order the bucket by input index (stable bucketing) and
 // write the hits' coordinates and radius in bucket order.
-__global__ void k_bucket_sort(Ws w, int n_buckets) {
+__global__ void k_bucket_sort(const Ws *__restrict__ wb, int n_buckets) {
+  const Ws &w = wb[blockIdx.y];
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (wave >= n_buckets) return;
   const int b0 = w.boff[wave], n = w.boff[wave + 1] - b0;
@@ -252,7 +264,8 @@ constexpr int kMdStage = 512;  // hits per sensor staged in LDS
 
 // One block per module; pairs (lower i, upper j) in row-major order.
 template <bool FILL>
-__global__ __launch_bounds__(kBlock) void k_md(Ws w, DevGeom g) {
+__global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeom g) {
+  const Ws &w = wb[blockIdx.y];
   __shared__ float4 s_lo[kMdStage], s_up[kMdStage];
   __shared__ int s_wave[kWaves];
   const int m = blockIdx.x;
@@ -311,7 +324,8 @@ constexpr int kMaxEdges = 256;  // module-map targets per module handled by one 
 // holds few MDs; passing candidates are compacted in list order with ballot
 // and mbcnt.
 template <bool FILL>
-__global__ __launch_bounds__(kBlock) void k_ls(Ws w, DevGeom g) {
+__global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeom g) {
+  const Ws &w = wb[blockIdx.y];
   __shared__ int s_pre[kWaves][kMaxEdges + 1];  // running MD count before each edge
   __shared__ int s_first[kWaves][kMaxEdges];    // first MD of each linked module
   __shared__ int s_info[kWaves][kMaxEdges];
@@ -387,7 +401,8 @@ __global__ __launch_bounds__(kBlock) void k_ls(Ws w, DevGeom g) {
 // ------------------------------------------------------------- a3: T3
 // One thread per inner segment (a, b); partners: the segments whose inner MD is b.
 template <bool FILL>
-__global__ __launch_bounds__(kBlock) void k_t3(Ws w, DevGeom g) {
+__global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeom g) {
+  const Ws &w = wb[blockIdx.y];
   const int n_ls = w.ctr[C_NLS];
   for (int l1 = blockIdx.x * blockDim.x + threadIdx.x; l1 < n_ls; l1 += gridDim.x * blockDim.x) {
     const int2 ab = w.ls_md[l1];
@@ -420,7 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_t3(Ws w, DevGeom g) {
 // ------------------------------------------------------------- a4: T5
 // One thread per inner triplet (a, b, c); partners: the triplets whose first MD is c.
 template <bool FILL>
-__global__ __launch_bounds__(kBlock) void k_t5(Ws w, DevGeom g) {
+__global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeom g) {
+  const Ws &w = wb[blockIdx.y];
   const int n_t3 = w.ctr[C_NT3];
   const int n_ls = w.ctr[C_NLS];
   for (int t1 = blockIdx.x * blockDim.x + threadIdx.x; t1 < n_t3; t1 += gridDim.x * blockDim.x) {
@@ -463,12 +479,14 @@ __global__ __launch_bounds__(kBlock) void k_t5(Ws w, DevGeom g) {
 }
 
 // ------------------------------------------------------------- a5: T5 dedup
-__global__ void k_t5_inc_count(Ws w) {
+__global__ void k_t5_inc_count(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NT5];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
     for (int k = 0; k < 5; ++k) atomicAdd(&w.inc_cnt[w.t5_md[5 * (long)t + k]], 1);
 }
-__global__ void k_t5_inc_scatter(Ws w) {
+__global__ void k_t5_inc_scatter(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NT5];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
     for (int k = 0; k < 5; ++k) {
@@ -500,7 +518,8 @@ __device__ __forceinline__ bool better(float su, const int *hu, float st, const 
 }
 
 // A T5 is dropped when another T5 sharing at least two MDs has a smaller (chi2_xy, hit tuple).
-__global__ void k_t5_dedup(Ws w) {
+__global__ void k_t5_dedup(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NT5];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     int mt[5];
@@ -542,7 +561,8 @@ __device__ __forceinline__ Seed load_seed(const Ws &w, int s) {
   return sd;
 }
 
-__global__ void k_pls(Ws w) {
+__global__ void k_pls(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
     const float px = w.px[s], py = w.py[s], pz = w.pz[s];
     const float pt = sqrtf(px * px + py * py);
@@ -563,7 +583,8 @@ __global__ void k_pls(Ws w) {
     }
   }
 }
-__global__ void k_ph_scatter(Ws w) {
+__global__ void k_ph_scatter(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x)
     for (int k = 0; k < 4; ++k) {
       const int h = w.hits4[4 * (long)s + k];
@@ -571,7 +592,8 @@ __global__ void k_ph_scatter(Ws w) {
     }
 }
 // pLS duplicate removal: seeds sharing at least 3 pixel hits; the lower seed index wins.
-__global__ void k_pls_dedup(Ws w) {
+__global__ void k_pls_dedup(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
     int hs[4];
     for (int k = 0; k < 4; ++k) hs[k] = w.hits4[4 * (long)s + k];
@@ -628,7 +650,8 @@ __device__ __forceinline__ void load_object(const Ws &w, const DevGeom &g, int t
 // compacted in object order; chunks in which no pair passed skip the
 // compaction.
 template <int K, bool FILL>
-__global__ __launch_bounds__(kBlock) void k_pt(Ws w, DevGeom g) {
+__global__ __launch_bounds__(kBlock) void k_pt(const Ws *__restrict__ wb, DevGeom g) {
+  const Ws &w = wb[blockIdx.y];
   __shared__ Seed s_seed[kSeedTile];
   __shared__ int s_base[kSeedTile];
   __shared__ int s_wave[kWaves];
@@ -695,14 +718,16 @@ __global__ __launch_bounds__(kBlock) void k_pt(Ws w, DevGeom g) {
 }
 
 template <int K>
-__global__ void k_pt_obj_count(Ws w) {
+__global__ void k_pt_obj_count(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = K == 3 ? w.ctr[C_NPT3] : w.ctr[C_NPT5];
   const int2 *so = K == 3 ? w.pt3_so : w.pt5_so;
   int *cnt = K == 3 ? w.o3_cnt : w.o5_cnt;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) atomicAdd(&cnt[so[i].y], 1);
 }
 template <int K>
-__global__ void k_pt_obj_scatter(Ws w) {
+__global__ void k_pt_obj_scatter(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = K == 3 ? w.ctr[C_NPT3] : w.ctr[C_NPT5];
   const int2 *so = K == 3 ? w.pt3_so : w.pt5_so;
   const int *off = K == 3 ? w.o3_off : w.o5_off;
@@ -733,7 +758,8 @@ __device__ __forceinline__ void obj_hits(const Ws &w, int t, int *h) {
 // pT duplicate removal: dropped when another entry with the same seed or the
 // same outer object has a smaller (score, seed, hit tuple).
 template <int K>
-__global__ void k_pt_dedup(Ws w) {
+__global__ void k_pt_dedup(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = K == 3 ? w.ctr[C_NPT3] : w.ctr[C_NPT5];
   const int2 *so = K == 3 ? w.pt3_so : w.pt5_so;
   const float4 *at = K == 3 ? w.pt3_attr : w.pt5_attr;
@@ -780,7 +806,8 @@ __device__ __forceinline__ Dir dir_of_t5(const Ws &w, int t) {
 }
 
 // pT5 TCs: every surviving pT5; marks its seed and T5 as used.
-__global__ void k_tc_pt5(Ws w) {
+__global__ void k_tc_pt5(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NPT5];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int k = w.pt5_keep[i];
@@ -791,7 +818,8 @@ __global__ void k_tc_pt5(Ws w) {
     }
   }
 }
-__global__ void k_tc_dirs_pt5(Ws w) {
+__global__ void k_tc_dirs_pt5(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NPT5];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     if (w.f_pt5[i]) {
@@ -821,9 +849,13 @@ constexpr int bin_reach(double D) {
 }
 
 // One block: counting sort of n (on the device) directions into kDirBins bins.
-__global__ __launch_bounds__(1024) void k_bin_dirs(const float4 *dirs, const int *n_ptr, int *bin_off, float4 *out) {
+__global__ __launch_bounds__(1024) void k_bin_dirs(const Ws *__restrict__ wb, int which) {
   __shared__ int s_cnt[kDirBins], s_off[kDirBins + 1], s_cur[kDirBins];
-  const int n = *n_ptr;
+  const Ws &w = wb[blockIdx.y];
+  const float4 *dirs = which == 0 ? w.dir_pt5 : (which == 1 ? w.dir_pt3 : w.dir_t5);
+  int *bin_off = which == 0 ? w.boff_pt5 : (which == 1 ? w.boff_pt3 : w.boff_t5);
+  float4 *out = which == 0 ? w.bdir_pt5 : (which == 1 ? w.bdir_pt3 : w.bdir_t5);
+  const int n = w.ctr[which == 0 ? C_NTC0 : (which == 1 ? C_NTC1 : C_NTC2)];
   for (int b = threadIdx.x; b < kDirBins; b += blockDim.x) { s_cnt[b] = 0; s_cur[b] = 0; }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&s_cnt[dir_bin(dirs[i].x, dirs[i].y)], 1);
@@ -858,7 +890,8 @@ __device__ __forceinline__ bool near_any(const Dir &d, const float4 *lst, const 
 }
 
 // pT3 TCs: surviving pT3 whose seed no TC-pT5 uses and that is not near any TC-pT5.
-__global__ void k_tc_pt3(Ws w) {
+__global__ void k_tc_pt3(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NPT3];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     int f = 0;
@@ -869,7 +902,8 @@ __global__ void k_tc_pt3(Ws w) {
     w.f_pt3[i] = f;
   }
 }
-__global__ void k_tc_dirs_pt3(Ws w) {
+__global__ void k_tc_dirs_pt3(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NPT3];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     if (w.f_pt3[i]) {
@@ -880,7 +914,8 @@ __global__ void k_tc_dirs_pt3(Ws w) {
     }
 }
 // T5 TCs: surviving T5 not used by a TC-pT5 and not near any TC-pT5 or TC-pT3.
-__global__ void k_tc_t5(Ws w) {
+__global__ void k_tc_t5(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NT5];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     int f = 0;
@@ -892,7 +927,8 @@ __global__ void k_tc_t5(Ws w) {
     w.f_t5[t] = f;
   }
 }
-__global__ void k_tc_dirs_t5(Ws w) {
+__global__ void k_tc_dirs_t5(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NT5];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
     if (w.f_t5[t]) {
@@ -901,7 +937,8 @@ __global__ void k_tc_dirs_t5(Ws w) {
     }
 }
 // pLS TCs: surviving pLS used by no TC and not near any TC.
-__global__ void k_tc_pls(Ws w) {
+__global__ void k_tc_pls(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
     int f = 0;
     if (w.pls_keep[s] && !w.seed_used[s]) {
@@ -915,7 +952,8 @@ __global__ void k_tc_pls(Ws w) {
 }
 
 // Output: type, offsets, hit lists (pixel hits first, then MD hits inner to outer).
-__global__ void k_tc_write(Ws w) {
+__global__ void k_tc_write(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
   const int n0 = w.ctr[C_NTC0], n1 = w.ctr[C_NTC1], n2 = w.ctr[C_NTC2], n3 = w.ctr[C_NTC3];
   const int np5 = w.ctr[C_NPT5], np3 = w.ctr[C_NPT3], nt5 = w.ctr[C_NT5];
   const long h1 = 14L * n0, h2 = h1 + 10L * n1, h3 = h2 + 10L * n2;
@@ -978,12 +1016,7 @@ const char *const kSiteNames[] = {
     "tc_t5", "tc_t5_scan", "tc_t5_dirs", "tc_pls", "tc_pls_scan", "tc_write"};
 const int kNumSites = (int)(sizeof(kSiteNames) / sizeof(kSiteNames[0]));
 
-static void fill(int *p, long n, int v, hipStream_t st) {
-  if (n <= 0) return;
-  k_fill<<<grid_for(n), kBlock, 0, st>>>(p, n, v);
-}
-
-void enqueue_chain(const DevGeom &g, const Ws &w, hipStream_t st, const KernelTimer *kt) {
+void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream_t st, const KernelTimer *kt) {
   int site = 0;
   // Runs one launch site; the timed site is bracketed by the timer's events.
   auto run = [&](auto &&launch) {
@@ -994,108 +1027,102 @@ void enqueue_chain(const DevGeom &g, const Ws &w, hipStream_t st, const KernelTi
     ++site;
   };
   const int M = g.n_mod;
-  const int N = w.n_hits, S = w.n_seeds;
-  int *ctr = w.ctr;
-  int *status = ctr + C_STATUS;
+  const long N = b.n_hits, S = b.n_seeds;  // largest of the batch
+  const bool seeds = S > 0;
+  auto grid = [&](long n) { return dim3(grid_for(n), B); };
+  auto gridw = [&](long n) { return dim3(grid_waves(n), B); };
+  const dim3 one(1, B);
+  const dim3 seedtiles((unsigned)((S + kSeedTile - 1) / kSeedTile > 0 ? (S + kSeedTile - 1) / kSeedTile : 1), B);
   // a0: buckets
-  run([&] {
-    fill(ctr, C_COUNT, 0, st);
-    fill(w.bcnt, 2L * M + 1, 0, st);
-    fill(w.bcur, 2L * M, 0, st);
-  });
-  run([&] { k_hits_count<<<grid_for(N > S ? N : S), kBlock, 0, st>>>(w, M); });
-  run([&] { scan(w.bcnt, w.boff, nullptr, 2 * M, 2 * M, w.scan_tmp, ctr + C_NOUTER, nullptr, 0, status, st); });
-  run([&] { k_hits_scatter<<<grid_for(N), kBlock, 0, st>>>(w, M); });
-  run([&] { k_bucket_sort<<<(2 * M * 64 + kBlock - 1) / kBlock, kBlock, 0, st>>>(w, 2 * M); });
+  run([&] { k_clear<<<grid(2L * M + 1), kBlock, 0, st>>>(wb, FL_CTR, FL_BCUR + 1); });
+  run([&] { k_hits_count<<<grid(N > S ? N : S), kBlock, 0, st>>>(wb, M); });
+  run([&] { scan(wb, B, SC_HITS, 2L * M, st); });
+  run([&] { k_hits_scatter<<<grid(N), kBlock, 0, st>>>(wb, M); });
+  run([&] { k_bucket_sort<<<dim3((2 * M * 64 + kBlock - 1) / kBlock, B), kBlock, 0, st>>>(wb, 2 * M); });
   // a1: MD
-  run([&] { k_md<false><<<M, kBlock, 0, st>>>(w, g); });
-  run([&] { scan(w.md_cnt, w.md_off, nullptr, M, M, w.scan_tmp, ctr + C_RMD, ctr + C_NMD, w.cap_md, status, st); });
-  run([&] { k_md<true><<<M, kBlock, 0, st>>>(w, g); });
+  run([&] { k_md<false><<<dim3(M, B), kBlock, 0, st>>>(wb, g); });
+  run([&] { scan(wb, B, SC_MD, M, st); });
+  run([&] { k_md<true><<<dim3(M, B), kBlock, 0, st>>>(wb, g); });
   // a2: LS
-  run([&] { k_ls<false><<<grid_waves(w.cap_md), kBlock, 0, st>>>(w, g); });
-  run([&] { scan(w.ls_cnt, w.ls_off, ctr + C_NMD, 0, w.cap_md, w.scan_tmp, ctr + C_RLS, ctr + C_NLS, w.cap_ls, status, st); });
-  run([&] { k_ls<true><<<grid_waves(w.cap_md), kBlock, 0, st>>>(w, g); });
+  run([&] { k_ls<false><<<gridw(b.cap_md), kBlock, 0, st>>>(wb, g); });
+  run([&] { scan(wb, B, SC_LS, b.cap_md, st); });
+  run([&] { k_ls<true><<<gridw(b.cap_md), kBlock, 0, st>>>(wb, g); });
   // a3: T3
-  run([&] { k_t3<false><<<grid_for(w.cap_ls), kBlock, 0, st>>>(w, g); });
-  run([&] { scan(w.t3_cnt, w.t3_off, ctr + C_NLS, 0, w.cap_ls, w.scan_tmp, ctr + C_RT3, ctr + C_NT3, w.cap_t3, status, st); });
-  run([&] { k_t3<true><<<grid_for(w.cap_ls), kBlock, 0, st>>>(w, g); });
+  run([&] { k_t3<false><<<grid(b.cap_ls), kBlock, 0, st>>>(wb, g); });
+  run([&] { scan(wb, B, SC_T3, b.cap_ls, st); });
+  run([&] { k_t3<true><<<grid(b.cap_ls), kBlock, 0, st>>>(wb, g); });
   // a4: T5
-  run([&] { k_t5<false><<<grid_for(w.cap_t3), kBlock, 0, st>>>(w, g); });
-  run([&] { scan(w.t5_cnt, w.t5_off, ctr + C_NT3, 0, w.cap_t3, w.scan_tmp, ctr + C_RT5, ctr + C_NT5, w.cap_t5, status, st); });
-  run([&] { k_t5<true><<<grid_for(w.cap_t3), kBlock, 0, st>>>(w, g); });
+  run([&] { k_t5<false><<<grid(b.cap_t3), kBlock, 0, st>>>(wb, g); });
+  run([&] { scan(wb, B, SC_T5, b.cap_t3, st); });
+  run([&] { k_t5<true><<<grid(b.cap_t3), kBlock, 0, st>>>(wb, g); });
   // a5: T5 duplicate removal through per-MD incidence lists
   run([&] {
-    fill(w.inc_cnt, (long)w.cap_md + 1, 0, st);
-    fill(w.inc_cur, (long)w.cap_md + 1, 0, st);
-    k_t5_inc_count<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w);
+    k_clear<<<grid((long)b.cap_md + 1), kBlock, 0, st>>>(wb, FL_INC_CNT, FL_INC_CUR + 1);
+    k_t5_inc_count<<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
   });
-  run([&] { scan(w.inc_cnt, w.inc_off, ctr + C_NMD, 0, w.cap_md, w.scan_tmp, ctr + C_NINC, nullptr, 0, status, st); });
-  run([&] { k_t5_inc_scatter<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w); });
-  run([&] { k_t5_dedup<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w); });
+  run([&] { scan(wb, B, SC_INC, b.cap_md, st); });
+  run([&] { k_t5_inc_scatter<<<grid(b.cap_t5), kBlock, 0, st>>>(wb); });
+  run([&] { k_t5_dedup<<<grid(b.cap_t5), kBlock, 0, st>>>(wb); });
   // a6: pLS
-  const bool seeds = S > 0;
   run([&] {
-    fill(w.ph_cnt, (long)N + 1, 0, st);
-    fill(w.ph_cur, (long)N + 1, 0, st);
-    if (seeds) k_pls<<<grid_for(S), kBlock, 0, st>>>(w);
+    k_clear<<<grid(N + 1), kBlock, 0, st>>>(wb, FL_PH_CNT, FL_PH_CUR + 1);
+    if (seeds) k_pls<<<grid(S), kBlock, 0, st>>>(wb);
   });
-  run([&] { if (seeds) scan(w.ph_cnt, w.ph_off, nullptr, N, N, w.scan_tmp, ctr + C_NPH, nullptr, 0, status, st); });
-  run([&] { if (seeds) k_ph_scatter<<<grid_for(S), kBlock, 0, st>>>(w); });
-  run([&] { if (seeds) k_pls_dedup<<<grid_for(S), kBlock, 0, st>>>(w); });
-  // a7: pT3, pT5 (one block per seed)
-  run([&] { if (seeds) k_pt<3, false><<<(S + kSeedTile - 1) / kSeedTile, kBlock, 0, st>>>(w, g); });
-  run([&] { if (seeds) scan(w.pt3_cnt, w.pt3_off, nullptr, S, S, w.scan_tmp, ctr + C_RPT3, ctr + C_NPT3, w.cap_pt3, status, st); });
-  run([&] { if (seeds) k_pt<3, true><<<(S + kSeedTile - 1) / kSeedTile, kBlock, 0, st>>>(w, g); });
-  run([&] { if (seeds) k_pt<5, false><<<(S + kSeedTile - 1) / kSeedTile, kBlock, 0, st>>>(w, g); });
-  run([&] { if (seeds) scan(w.pt5_cnt, w.pt5_off, nullptr, S, S, w.scan_tmp, ctr + C_RPT5, ctr + C_NPT5, w.cap_pt5, status, st); });
-  run([&] { if (seeds) k_pt<5, true><<<(S + kSeedTile - 1) / kSeedTile, kBlock, 0, st>>>(w, g); });
+  run([&] { if (seeds) scan(wb, B, SC_PH, N, st); });
+  run([&] { if (seeds) k_ph_scatter<<<grid(S), kBlock, 0, st>>>(wb); });
+  run([&] { if (seeds) k_pls_dedup<<<grid(S), kBlock, 0, st>>>(wb); });
+  // a7: pT3, pT5 (tiles of seeds)
+  run([&] { if (seeds) k_pt<3, false><<<seedtiles, kBlock, 0, st>>>(wb, g); });
+  run([&] { if (seeds) scan(wb, B, SC_PT3, S, st); });
+  run([&] { if (seeds) k_pt<3, true><<<seedtiles, kBlock, 0, st>>>(wb, g); });
+  run([&] { if (seeds) k_pt<5, false><<<seedtiles, kBlock, 0, st>>>(wb, g); });
+  run([&] { if (seeds) scan(wb, B, SC_PT5, S, st); });
+  run([&] { if (seeds) k_pt<5, true><<<seedtiles, kBlock, 0, st>>>(wb, g); });
   run([&] {
     if (!seeds) return;
-    fill(w.o3_cnt, (long)w.cap_t3 + 1, 0, st);
-    fill(w.o3_cur, (long)w.cap_t3 + 1, 0, st);
-    fill(w.o5_cnt, (long)w.cap_t5 + 1, 0, st);
-    fill(w.o5_cur, (long)w.cap_t5 + 1, 0, st);
-    k_pt_obj_count<3><<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w);
-    k_pt_obj_count<5><<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w);
+    const long n = (long)(b.cap_t3 > b.cap_t5 ? b.cap_t3 : b.cap_t5) + 1;
+    k_clear<<<grid(n), kBlock, 0, st>>>(wb, FL_O3_CNT, FL_O5_CUR + 1);
+    k_pt_obj_count<3><<<grid(b.cap_pt3), kBlock, 0, st>>>(wb);
+    k_pt_obj_count<5><<<grid(b.cap_pt5), kBlock, 0, st>>>(wb);
   });
   run([&] {
     if (!seeds) return;
-    scan(w.o3_cnt, w.o3_off, ctr + C_NT3, 0, w.cap_t3, w.scan_tmp, ctr + C_NO3, nullptr, 0, status, st);
-    scan(w.o5_cnt, w.o5_off, ctr + C_NT5, 0, w.cap_t5, w.scan_tmp, ctr + C_NO5, nullptr, 0, status, st);
+    scan(wb, B, SC_O3, b.cap_t3, st);
+    scan(wb, B, SC_O5, b.cap_t5, st);
   });
   run([&] {
     if (!seeds) return;
-    k_pt_obj_scatter<3><<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w);
-    k_pt_obj_scatter<5><<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w);
+    k_pt_obj_scatter<3><<<grid(b.cap_pt3), kBlock, 0, st>>>(wb);
+    k_pt_obj_scatter<5><<<grid(b.cap_pt5), kBlock, 0, st>>>(wb);
   });
-  run([&] { if (seeds) k_pt_dedup<3><<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w); });
-  run([&] { if (seeds) k_pt_dedup<5><<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w); });
+  run([&] { if (seeds) k_pt_dedup<3><<<grid(b.cap_pt3), kBlock, 0, st>>>(wb); });
+  run([&] { if (seeds) k_pt_dedup<5><<<grid(b.cap_pt5), kBlock, 0, st>>>(wb); });
   // a8: cleaning and track candidates
   run([&] {
-    fill(w.seed_used, (long)S + 1, 0, st);
-    fill(w.t5_used, (long)w.cap_t5 + 1, 0, st);
-    k_tc_pt5<<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w);
+    const long n = (long)(S > b.cap_t5 ? S : b.cap_t5) + 1;
+    k_clear<<<grid(n), kBlock, 0, st>>>(wb, FL_SEED_USED, FL_T5_USED + 1);
+    k_tc_pt5<<<grid(b.cap_pt5), kBlock, 0, st>>>(wb);
   });
-  run([&] { scan(w.f_pt5, w.p_pt5, ctr + C_NPT5, 0, w.cap_pt5, w.scan_tmp, ctr + C_NTC0, nullptr, 0, status, st); });
+  run([&] { scan(wb, B, SC_F5, b.cap_pt5, st); });
   run([&] {
-    k_tc_dirs_pt5<<<grid_for(w.cap_pt5), kBlock, 0, st>>>(w);
-    k_bin_dirs<<<1, 1024, 0, st>>>(w.dir_pt5, ctr + C_NTC0, w.boff_pt5, w.bdir_pt5);
+    k_tc_dirs_pt5<<<grid(b.cap_pt5), kBlock, 0, st>>>(wb);
+    k_bin_dirs<<<one, 1024, 0, st>>>(wb, 0);
   });
-  run([&] { k_tc_pt3<<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w); });
-  run([&] { scan(w.f_pt3, w.p_pt3, ctr + C_NPT3, 0, w.cap_pt3, w.scan_tmp, ctr + C_NTC1, nullptr, 0, status, st); });
+  run([&] { k_tc_pt3<<<grid(b.cap_pt3), kBlock, 0, st>>>(wb); });
+  run([&] { scan(wb, B, SC_F3, b.cap_pt3, st); });
   run([&] {
-    k_tc_dirs_pt3<<<grid_for(w.cap_pt3), kBlock, 0, st>>>(w);
-    k_bin_dirs<<<1, 1024, 0, st>>>(w.dir_pt3, ctr + C_NTC1, w.boff_pt3, w.bdir_pt3);
+    k_tc_dirs_pt3<<<grid(b.cap_pt3), kBlock, 0, st>>>(wb);
+    k_bin_dirs<<<one, 1024, 0, st>>>(wb, 1);
   });
-  run([&] { k_tc_t5<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w); });
-  run([&] { scan(w.f_t5, w.p_t5, ctr + C_NT5, 0, w.cap_t5, w.scan_tmp, ctr + C_NTC2, nullptr, 0, status, st); });
+  run([&] { k_tc_t5<<<grid(b.cap_t5), kBlock, 0, st>>>(wb); });
+  run([&] { scan(wb, B, SC_FT5, b.cap_t5, st); });
   run([&] {
-    k_tc_dirs_t5<<<grid_for(w.cap_t5), kBlock, 0, st>>>(w);
-    k_bin_dirs<<<1, 1024, 0, st>>>(w.dir_t5, ctr + C_NTC2, w.boff_t5, w.bdir_t5);
+    k_tc_dirs_t5<<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
+    k_bin_dirs<<<one, 1024, 0, st>>>(wb, 2);
   });
-  run([&] { if (seeds) k_tc_pls<<<grid_for(S), kBlock, 0, st>>>(w); });
-  run([&] { if (seeds) scan(w.f_pls, w.p_pls, nullptr, S, S, w.scan_tmp, ctr + C_NTC3, nullptr, 0, status, st); });
-  run([&] { k_tc_write<<<grid_for(w.cap_tc), kBlock, 0, st>>>(w); });
+  run([&] { if (seeds) k_tc_pls<<<grid(S), kBlock, 0, st>>>(wb); });
+  run([&] { if (seeds) scan(wb, B, SC_FPLS, S, st); });
+  run([&] { k_tc_write<<<grid(b.cap_tc), kBlock, 0, st>>>(wb); });
 }
 
 }  // namespace lst

@@ -24,7 +24,33 @@ struct DevGeom {
   const int *info;    // per module: bit 0 = 2S, bit 1 = endcap
 };
 
-// Device pointers of one event (all inside the caller's workspace except the inputs).
+// One exclusive scan of the chain: out[0..n] = scan of in[0..n), n = *n_dev
+// (or n_fix); the total goes to *tot_req and, clamped to cap (overflow
+// flagged), to *tot_clamped.  n_cap bounds n for the launch grid.
+struct ScanJob {
+  const int *in;
+  int *out;
+  const int *n_dev;
+  int n_fix, n_cap;
+  int *tot_req, *tot_clamped;
+  int cap;
+};
+enum ScanId : int {
+  SC_HITS, SC_MD, SC_LS, SC_T3, SC_T5, SC_INC, SC_PH, SC_PT3, SC_PT5, SC_O3, SC_O5,
+  SC_F5, SC_F3, SC_FT5, SC_FPLS, SC_COUNT
+};
+// One array cleared to zero at the start of the chain.
+struct FillJob {
+  int *p;
+  long n;
+};
+enum FillId : int {
+  FL_CTR, FL_BCNT, FL_BCUR, FL_INC_CNT, FL_INC_CUR, FL_PH_CNT, FL_PH_CUR, FL_O3_CNT, FL_O3_CUR,
+  FL_O5_CNT, FL_O5_CUR, FL_SEED_USED, FL_T5_USED, FL_COUNT
+};
+
+// Device pointers of one event (all inside the workspace except the inputs).
+// Kernels of a batch read descriptor blockIdx.y of a device array of these.
 struct Ws {
   // inputs (device)
   int n_hits, n_seeds;
@@ -78,8 +104,10 @@ struct Ws {
   float4 *bdir_pt5, *bdir_pt3, *bdir_t5;        // the same, grouped by azimuth bin
   int *boff_pt5, *boff_pt3, *boff_t5;           // bin offsets (kDirBins + 1)
   int *tc_type, *tc_off, *tc_hits;
-  // scan scratch
+  // scan scratch and the job tables of the generic scan / clear kernels
   int *scan_tmp;
+  ScanJob scans[SC_COUNT];
+  FillJob fills[FL_COUNT];
 };
 
 // Capacities and sizes (host-side).
@@ -87,7 +115,12 @@ struct Caps {
   int64_t md, ls, t3, t5, pt3, pt5;
 };
 
-size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *ws, char *base);
+// Carves one event's arrays from `base` (nullptr: size only) and fills the
+// scan / clear job tables; counters go to `ctr` (64 ints) when given.
+// Array sizes follow n_hits_alloc / n_seeds_alloc when those are >= 0 (a
+// slot of a captured plan is sized for the largest event it may hold).
+size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *ws, char *base, int *ctr,
+                        int n_hits_alloc = -1, int n_seeds_alloc = -1);
 // Brackets launch site `site` of the chain with two recorded HIP events.
 struct KernelTimer {
   int site;
@@ -95,7 +128,10 @@ struct KernelTimer {
 };
 extern const char *const kSiteNames[];
 extern const int kNumSites;
-void enqueue_chain(const DevGeom &g, const Ws &ws, hipStream_t st, const KernelTimer *kt);
+// Enqueues the whole chain for B events whose descriptors are d_ws[0..B) in
+// device memory; `bound` holds, field by field, the largest sizes and
+// capacities of the batch (it sets the launch grids).
+void enqueue_chain(const DevGeom &g, const Ws *d_ws, int B, const Ws &bound, hipStream_t st, const KernelTimer *kt);
 void launch_module_windows(const int *info, const float *pos_lo, const float *pos_up, const float *lmin,
                            const float *lmax, int n_mod, float4 *win, hipStream_t st);
 

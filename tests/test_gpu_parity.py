@@ -143,3 +143,59 @@ def test_deterministic_repeats(lst, gfull):
         if ref is None:
             ref = flat
         assert flat == ref
+
+
+# ------------------------------------------------------------------ batches
+def _tc_tuple(r):
+    return tuple(a.tobytes() for a in r.track_candidates())
+
+
+def test_batch_ragged_equals_oracle(lst, gbarrel, obarrel, barrel):
+    """Events of different sizes (incl. an empty one) in one batched launch sequence."""
+    evs = [make_event("tiny", k) for k in range(3)]
+    evs.append(make_tiny_event(11, n_tracks=3, n_noise=7))
+    rng = np.random.default_rng(5)
+    n = 23
+    evs.append(make_single_track_event(barrel, np.exp(rng.uniform(0, 2, n)), rng.uniform(-0.5, 0.5, n),
+                                       rng.uniform(0, 6.28, n), z0=rng.normal(0, 5, n), q=1, smear=True,
+                                       seeded=True, seed=5, n_noise=31))
+    evs.append(Event(x=np.zeros(0, np.float32), y=np.zeros(0, np.float32), z=np.zeros(0, np.float32),
+                     module=np.zeros(0, np.int32), sensor=np.zeros(0, np.int32), sim=np.zeros(0, np.int32)))
+    print(f"[gpu] batch of {len(evs)} events: hits {[e.n_hits for e in evs]}", flush=True)
+    res = lst.run_batch(gbarrel, [lst.upload_event(e) for e in evs])
+    for ev, r in zip(evs, res):
+        o = oracle.run(obarrel, ev)
+        compare_event(r, o)
+        compare_tc(r, o)
+
+
+def test_batch_pu200_equals_plain(lst, gfull):
+    evs = [make_event("pu200_seeded", k) for k in (3, 4, 5)]
+    dev = [lst.upload_event(e) for e in evs]
+    print("[gpu] batch of 3 pu200_seeded", flush=True)
+    plain = [_tc_tuple(lst.run_event(gfull, d)) for d in dev]
+    res = lst.run_batch(gfull, dev)
+    assert [_tc_tuple(r) for r in res] == plain
+
+
+def test_plan_replays_equal_eager(lst, gbarrel, obarrel):
+    """A captured plan replayed several times, eager work in between, every replay checked."""
+    evs = [make_event("tiny", k) for k in range(6)]
+    dev = [lst.upload_event(e) for e in evs]
+    eager = [_tc_tuple(lst.run_event(gbarrel, d)) for d in dev]
+    plan = lst.Plan(gbarrel, 4, max(e.n_hits for e in evs), 0)
+    for rep, sel in enumerate([[0, 1, 2, 3], [4, 5], [2, 0, 5, 1], [3]]):
+        print(f"[gpu] plan replay {rep}: events {sel}", flush=True)
+        res = plan.run([dev[k] for k in sel])
+        assert [_tc_tuple(r) for r in res] == [eager[k] for k in sel]
+        # the previous run's events must be released before the next run
+        if rep == 0:
+            st, _ = lst.lst_plan_run(plan.handle, [dev[0]], plan.stream)
+            assert st == lst.LST_E_STATE
+        for r in res:
+            r.close()
+        lst.run_event(gbarrel, dev[rep])  # eager work between replays
+    r = plan.run([dev[1]])[0]
+    o = oracle.run(obarrel, evs[1])
+    compare_event(r, o, stages=range(4))
+    compare_tc(r, o)
