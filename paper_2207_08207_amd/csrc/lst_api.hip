@@ -108,6 +108,9 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.pt3_keep = I(p3); t.pt5_keep = I(p5);
   t.o3_cnt = I(t3 + 1); t.o3_off = I(t3 + 1); t.o3_cur = I(t3 + 1); t.o3_list = I(p3);
   t.o5_cnt = I(t5 + 1); t.o5_off = I(t5 + 1); t.o5_cur = I(t5 + 1); t.o5_list = I(p5);
+  const long nbins = 2560;  // first-anchor bins of the seed search (10 rings x 256 azimuth bins)
+  t.b3_cnt = I(nbins + 1); t.b3_off = I(nbins + 1); t.b3_cur = I(nbins + 1); t.b3_list = I(t3);
+  t.b5_cnt = I(nbins + 1); t.b5_off = I(nbins + 1); t.b5_cur = I(nbins + 1); t.b5_list = I(t5);
   t.seed_used = I(S + 1); t.t5_used = I(t5 + 1);
   t.f_pt5 = I(p5 + 1); t.f_pt3 = I(p3 + 1); t.f_t5 = I(t5 + 1); t.f_pls = I(S + 1);
   t.p_pt5 = I(p5 + 1); t.p_pt3 = I(p3 + 1); t.p_t5 = I(t5 + 1); t.p_pls = I(S + 1);
@@ -146,6 +149,8 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
     sj(SC_F3, t.f_pt3, t.p_pt3, ct + C_NPT3, 0, p3, ct + C_NTC1, nullptr, 0);
     sj(SC_FT5, t.f_t5, t.p_t5, ct + C_NT5, 0, t5, ct + C_NTC2, nullptr, 0);
     sj(SC_FPLS, t.f_pls, t.p_pls, nullptr, S, S, ct + C_NTC3, nullptr, 0);
+    sj(SC_B3, t.b3_cnt, t.b3_off, nullptr, nbins, nbins, ct + C_NB3, nullptr, 0);
+    sj(SC_B5, t.b5_cnt, t.b5_off, nullptr, nbins, nbins, ct + C_NB5, nullptr, 0);
     auto fj = [&](int id, int *p, long n) { t.fills[id] = FillJob{p, n}; };
     fj(FL_CTR, ct, C_COUNT);
     fj(FL_BCNT, t.bcnt, 2 * M + 1);
@@ -160,6 +165,10 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
     fj(FL_O5_CUR, t.o5_cur, t5 + 1);
     fj(FL_SEED_USED, t.seed_used, S + 1);
     fj(FL_T5_USED, t.t5_used, t5 + 1);
+    fj(FL_B3_CNT, t.b3_cnt, nbins + 1);
+    fj(FL_B3_CUR, t.b3_cur, nbins + 1);
+    fj(FL_B5_CNT, t.b5_cnt, nbins + 1);
+    fj(FL_B5_CUR, t.b5_cur, nbins + 1);
   }
   if (w) *w = t;
   return (off + kAlign - 1) / kAlign * kAlign;

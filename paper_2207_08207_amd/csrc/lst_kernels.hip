@@ -619,8 +619,6 @@ __global__ void k_pls_dedup(const Ws *__restrict__ wb) {
 }
 
 // ------------------------------------------------------------- a7: pT3 / pT5
-constexpr int kSeedTile = 8;  // seeds per block
-
 template <int K>
 __device__ __forceinline__ void load_object(const Ws &w, const DevGeom &g, int t, float4 *P, ModInfo *M, float *kT,
                                             float *dkT) {
@@ -643,77 +641,211 @@ __device__ __forceinline__ void load_object(const Ws &w, const DevGeom &g, int t
   }
 }
 
-// One block per tile of kSeedTile seeds; the block streams every triplet
-// (K = 3) or surviving quintuplet (K = 5) once, in object order, and tests it
-// against the tile's seeds held in LDS: the window at the first anchor first,
-// the full selection only inside it.  Per seed the passing objects are
-// compacted in object order; chunks in which no pair passed skip the
-// compaction.
-template <int K, bool FILL>
-__global__ __launch_bounds__(kBlock) void k_pt(const Ws *__restrict__ wb, DevGeom g) {
+// ---- binned search: objects grouped by first anchor (radius ring, azimuth bin)
+constexpr int kRings = 10;
+constexpr float kRing0 = 20.0f, kRingW = 10.0f;      // rings [20, 30), ..., [110, 120) cm, ends clamped
+constexpr int kPhiBins = 256;
+constexpr int kObjBins = kRings * kPhiBins;
+constexpr int kMaskWords = kObjBins / 32;
+constexpr float kSampleStep = 2.0f;                  // trajectory sampling step [cm]
+constexpr int kMaxSamples = 112;                     // 224 cm of arc
+constexpr int kPassList = 1024;                      // passing objects sorted per seed in LDS
+
+__device__ __forceinline__ int ring_of(float r) {
+  const int k = (int)floorf((r - kRing0) / kRingW);
+  return k < 0 ? 0 : (k >= kRings ? kRings - 1 : k);
+}
+__device__ __forceinline__ int phibin_of(float ph) {
+  const int b = (int)floorf((ph + (float)M_PI) * (float)(kPhiBins / (2.0 * M_PI)));
+  return b < 0 ? 0 : (b >= kPhiBins ? kPhiBins - 1 : b);
+}
+__device__ __forceinline__ int obj_bin(float2 a) {
+  const float ph = atan2f(a.y, a.x);
+  if (!(ph == ph)) return 0;
+  return ring_of(sqrtf(a.x * a.x + a.y * a.y)) * kPhiBins + phibin_of(ph);
+}
+
+template <int K>
+__global__ void k_obj_bin_count(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  __shared__ Seed s_seed[kSeedTile];
-  __shared__ int s_base[kSeedTile];
-  __shared__ int s_wave[kWaves];
-  const int s0 = blockIdx.x * kSeedTile;
-  const int ns = min(kSeedTile, w.n_seeds - s0);
-  if (ns <= 0) return;
-  if (threadIdx.x < ns) {
-    s_seed[threadIdx.x] = load_seed(w, s0 + threadIdx.x);
-    if (FILL) s_base[threadIdx.x] = (K == 3 ? w.pt3_off : w.pt5_off)[s0 + threadIdx.x];
-  }
-  __syncthreads();
-  const int n_obj = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
+  const int n = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
   const float2 *first = K == 3 ? w.t3_first : w.t5_first;
-  const int cap = K == 3 ? w.cap_pt3 : w.cap_pt5;
-  int cnt[kSeedTile];
-#pragma unroll
-  for (int j = 0; j < kSeedTile; ++j) cnt[j] = 0;
-  for (int t0 = 0; t0 < n_obj; t0 += kBlock) {
-    const int t = t0 + threadIdx.x;
-    unsigned mask = 0;
-    float4 P[K];
-    ModInfo M[K];
-    float kT = 0.f, dkT = 0.f;
-    if (t < n_obj && (K == 3 || w.t5_keep[t])) {
-      const float2 f = first[t];
-#pragma unroll
-      for (int j = 0; j < kSeedTile; ++j)
-        if (j < ns && seed_box(s_seed[j], f.x, f.y)) mask |= 1u << j;
-      if (mask) {
-        load_object<K>(w, g, t, P, M, &kT, &dkT);
-#pragma unroll
-        for (int j = 0; j < kSeedTile; ++j) {
-          float4 attr;
-          if (((mask >> j) & 1u) && !pt_pass<K>(s_seed[j], P, M, kT, dkT, &attr)) mask &= ~(1u << j);
-        }
-      }
+  int *cnt = K == 3 ? w.b3_cnt : w.b5_cnt;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    if (K == 3 || w.t5_keep[t]) atomicAdd(&cnt[obj_bin(first[t])], 1);
+}
+template <int K>
+__global__ void k_obj_bin_scatter(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
+  const int n = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
+  const float2 *first = K == 3 ? w.t3_first : w.t5_first;
+  const int *off = K == 3 ? w.b3_off : w.b5_off;
+  int *cur = K == 3 ? w.b3_cur : w.b5_cur;
+  int *lst = K == 3 ? w.b3_list : w.b5_list;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+    if (K == 3 || w.t5_keep[t]) {
+      const int b = obj_bin(first[t]);
+      lst[off[b] + atomicAdd(&cur[b], 1)] = t;
     }
-    if (!FILL) {
-#pragma unroll
-      for (int j = 0; j < kSeedTile; ++j) cnt[j] += (mask >> j) & 1u;
-    } else if (__syncthreads_or(mask != 0u)) {
-      for (int j = 0; j < ns; ++j) {
-        const bool pass = (mask >> j) & 1u;
-        int tot;
-        const int pos = s_base[j] + block_prefix(pass, s_wave, &tot);
-        if (pass && pos < cap) {
-          float4 attr;
-          pt_pass<K>(s_seed[j], P, M, kT, dkT, &attr);
-          (K == 3 ? w.pt3_so : w.pt5_so)[pos] = make_int2(s0 + j, t);
-          (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = attr;
+}
+
+// Marks, in the wave's bin mask, every (ring, azimuth) bin that can hold the
+// first anchor of an object inside the seed's window: the anchor lies within
+// 1.01 cm of the seed circle on its forward half-turn (algebraic distance
+// <= 1 cm with |kappa| <= 0.02/cm), hence within d = 1.01 + step/2 + 0.05 cm
+// of a trajectory sample taken every `kSampleStep` of arc.
+__device__ void mark_seed_bins(const Seed &sd, unsigned *mask) {
+  const int lane = lane_id();
+  const float d = 1.01f * kBoxXY + 0.5f * kSampleStep + 0.05f;
+  const float bw = (float)(2.0 * M_PI / kPhiBins);
+  const float k = sd.ks;
+  const float ak = fabsf(k) > 1e-9f ? fabsf(k) : 1e-9f;
+  const float s_max = (float)M_PI / ak;
+  const float px = -sd.cy, py = sd.cx;  // perpendicular of the direction
+  for (int i = lane; i < kMaxSamples; i += 64) {
+    const float sarc = i * kSampleStep;
+    if (sarc > s_max + kSampleStep) continue;
+    const float a = k * sarc;
+    const float s1 = fabsf(k) > 1e-9f ? sinf(a) / k : sarc;
+    const float sh = sinf(0.5f * a);
+    const float s2 = fabsf(k) > 1e-9f ? 2.0f * sh * sh / k : 0.0f;
+    const float x = sd.x0 + sd.cx * s1 + px * s2;
+    const float y = sd.y0 + sd.cy * s1 + py * s2;
+    const float r = sqrtf(x * x + y * y);
+    if (r + d < kRing0 - 5.0f || r - d > kRing0 + kRings * kRingW + 5.0f) continue;
+    const int r0 = ring_of(r - d), r1 = ring_of(r + d);
+    const float rin = r - d;
+    int b0, b1;
+    if (rin <= 1e-3f || d / rin >= 1.0f) {
+      b0 = 0;
+      b1 = kPhiBins - 1;
+    } else {
+      const float hw = asinf(d / rin);
+      const float ph = atan2f(y, x);
+      b0 = (int)floorf((ph - hw + (float)M_PI) / bw) - 1;
+      b1 = (int)floorf((ph + hw + (float)M_PI) / bw) + 1;
+      if (b1 - b0 >= kPhiBins) { b0 = 0; b1 = kPhiBins - 1; }
+    }
+    for (int rr = r0; rr <= r1; ++rr)
+      for (int b = b0; b <= b1; ++b) {
+        const int bb = ((b % kPhiBins) + kPhiBins) % kPhiBins;
+        const int id = rr * kPhiBins + bb;
+        atomicOr(&mask[id >> 5], 1u << (id & 31));
+      }
+  }
+}
+
+// One wave per seed over the objects of the bins its trajectory can reach.
+// COUNT: number of passing objects.  FILL: passing object indices gathered in
+// LDS, ranked by object index, written at the seed's offset in object order
+// (the order of the full scan); a seed with more than kPassList passing
+// objects is filled by an ordered scan over all objects instead.
+template <int K, bool FILL>
+__global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb, DevGeom g) {
+  __shared__ unsigned s_mask[kWaves][kMaskWords];
+  __shared__ int s_list[FILL ? kWaves : 1][FILL ? kPassList : 1];
+  const Ws &w = wb[blockIdx.y];
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int s = blockIdx.x * kWaves + wv;
+  if (s >= w.n_seeds) return;
+  const Seed sd = load_seed(w, s);
+  unsigned *mask = s_mask[wv];
+  for (int i = lane; i < kMaskWords; i += 64) mask[i] = 0u;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  mark_seed_bins(sd, mask);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int *boff = K == 3 ? w.b3_off : w.b5_off;
+  const int *blst = K == 3 ? w.b3_list : w.b5_list;
+  const float2 *first = K == 3 ? w.t3_first : w.t5_first;
+  int n_pass = 0;
+  int base = FILL ? (K == 3 ? w.pt3_off : w.pt5_off)[s] : 0;
+  const int expect = FILL ? (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s] : 0;
+  const int cap = K == 3 ? w.cap_pt3 : w.cap_pt5;
+  const bool listed = !FILL || expect <= kPassList;
+  if (listed) {
+    for (int wd = 0; wd < kMaskWords; ++wd) {
+      unsigned bits = mask[wd];
+      while (bits) {
+        const int bit = __builtin_ctz(bits);
+        bits &= bits - 1u;
+        const int bin = wd * 32 + bit;
+        const int j0 = boff[bin], j1 = boff[bin + 1];
+        for (int j = j0 + lane; j - lane < j1; j += 64) {
+          bool pass = false;
+          int t = 0;
+          if (j < j1) {
+            t = blst[j];
+            const float2 f = first[t];
+            if (seed_box(sd, f.x, f.y)) {
+              float4 P[K];
+              ModInfo M[K];
+              float kT, dkT;
+              float4 attr;
+              load_object<K>(w, g, t, P, M, &kT, &dkT);
+              pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
+            }
+          }
+          const unsigned long long m = __ballot(pass);
+          if (FILL && pass) {
+            const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+            if (n_pass + pre < kPassList) s_list[wv][n_pass + pre] = t;
+          }
+          n_pass += __popcll(m);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) s_base[j] += tot;
-        __syncthreads();
       }
     }
   }
   if (!FILL) {
-    for (int j = 0; j < ns; ++j) {
-      const int c = block_sum(cnt[j], s_wave);
-      if (threadIdx.x == 0) (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s0 + j] = c;
+    if (lane == 0) (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s] = n_pass;
+    return;
+  }
+  if (listed) {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // rank by object index (indices are distinct) and write in object order
+    for (int i = lane; i < n_pass; i += 64) {
+      const int t = s_list[wv][i];
+      int rank = 0;
+      for (int q = 0; q < n_pass; ++q) rank += s_list[wv][q] < t ? 1 : 0;
+      const int pos = base + rank;
+      if (pos < cap) {
+        float4 P[K];
+        ModInfo M[K];
+        float kT, dkT;
+        float4 attr;
+        load_object<K>(w, g, t, P, M, &kT, &dkT);
+        pt_pass<K>(sd, P, M, kT, dkT, &attr);
+        (K == 3 ? w.pt3_so : w.pt5_so)[pos] = make_int2(s, t);
+        (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = attr;
+      }
     }
+    return;
+  }
+  // rare: too many passing objects for the LDS list; ordered scan of all objects
+  const int n_obj = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
+  for (int t0 = 0; t0 < n_obj; t0 += 64) {
+    const int t = t0 + lane;
+    bool pass = false;
+    float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (t < n_obj && (K == 3 || w.t5_keep[t])) {
+      const float2 f = first[t];
+      if (seed_box(sd, f.x, f.y)) {
+        float4 P[K];
+        ModInfo M[K];
+        float kT, dkT;
+        load_object<K>(w, g, t, P, M, &kT, &dkT);
+        pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
+      }
+    }
+    const unsigned long long m = __ballot(pass);
+    const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+    if (pass && base + pre < cap) {
+      (K == 3 ? w.pt3_so : w.pt5_so)[base + pre] = make_int2(s, t);
+      (K == 3 ? w.pt3_attr : w.pt5_attr)[base + pre] = attr;
+    }
+    base += __popcll(m);
   }
 }
 
@@ -1032,7 +1164,6 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   auto grid = [&](long n) { return dim3(grid_for(n), B); };
   auto gridw = [&](long n) { return dim3(grid_waves(n), B); };
   const dim3 one(1, B);
-  const dim3 seedtiles((unsigned)((S + kSeedTile - 1) / kSeedTile > 0 ? (S + kSeedTile - 1) / kSeedTile : 1), B);
   // a0: buckets
   run([&] { k_clear<<<grid(2L * M + 1), kBlock, 0, st>>>(wb, FL_CTR, FL_BCUR + 1); });
   run([&] { k_hits_count<<<grid(N > S ? N : S), kBlock, 0, st>>>(wb, M); });
@@ -1071,13 +1202,27 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { if (seeds) scan(wb, B, SC_PH, N, st); });
   run([&] { if (seeds) k_ph_scatter<<<grid(S), kBlock, 0, st>>>(wb); });
   run([&] { if (seeds) k_pls_dedup<<<grid(S), kBlock, 0, st>>>(wb); });
-  // a7: pT3, pT5 (tiles of seeds)
-  run([&] { if (seeds) k_pt<3, false><<<seedtiles, kBlock, 0, st>>>(wb, g); });
+  // a7: pT3, pT5: objects binned by first anchor, one wave per seed over its bins
+  const dim3 seedwaves((unsigned)((S + kWaves - 1) / kWaves > 0 ? (S + kWaves - 1) / kWaves : 1), B);
+  run([&] {
+    if (!seeds) return;
+    k_clear<<<grid(kObjBins + 1), kBlock, 0, st>>>(wb, FL_B3_CNT, FL_B5_CUR + 1);
+    k_obj_bin_count<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb);
+    scan(wb, B, SC_B3, kObjBins, st);
+    k_obj_bin_scatter<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb);
+    k_pt_binned<3, false><<<seedwaves, kBlock, 0, st>>>(wb, g);
+  });
   run([&] { if (seeds) scan(wb, B, SC_PT3, S, st); });
-  run([&] { if (seeds) k_pt<3, true><<<seedtiles, kBlock, 0, st>>>(wb, g); });
-  run([&] { if (seeds) k_pt<5, false><<<seedtiles, kBlock, 0, st>>>(wb, g); });
+  run([&] { if (seeds) k_pt_binned<3, true><<<seedwaves, kBlock, 0, st>>>(wb, g); });
+  run([&] {
+    if (!seeds) return;
+    k_obj_bin_count<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
+    scan(wb, B, SC_B5, kObjBins, st);
+    k_obj_bin_scatter<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
+    k_pt_binned<5, false><<<seedwaves, kBlock, 0, st>>>(wb, g);
+  });
   run([&] { if (seeds) scan(wb, B, SC_PT5, S, st); });
-  run([&] { if (seeds) k_pt<5, true><<<seedtiles, kBlock, 0, st>>>(wb, g); });
+  run([&] { if (seeds) k_pt_binned<5, true><<<seedwaves, kBlock, 0, st>>>(wb, g); });
   run([&] {
     if (!seeds) return;
     const long n = (long)(b.cap_t3 > b.cap_t5 ? b.cap_t3 : b.cap_t5) + 1;

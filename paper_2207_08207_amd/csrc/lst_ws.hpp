@@ -13,6 +13,7 @@ enum Ctr : int {
   C_RMD = 9, C_RLS, C_RT3, C_RT5, C_RPT3, C_RPT5,                      // required counts
   C_NT5KEEP = 15, C_NTC0 = 16, C_NTC1, C_NTC2, C_NTC3,                 // survivors, TCs per type
   C_NOUTER = 20, C_NINC = 21, C_NPH = 22, C_NO3 = 23, C_NO5 = 24,      // scratch totals
+  C_NB3 = 25, C_NB5 = 26,
   C_COUNT = 64
 };
 enum : int { ST_BAD_HIT = 1, ST_BAD_SEED = 2, ST_CAPACITY = 4 };
@@ -37,7 +38,7 @@ struct ScanJob {
 };
 enum ScanId : int {
   SC_HITS, SC_MD, SC_LS, SC_T3, SC_T5, SC_INC, SC_PH, SC_PT3, SC_PT5, SC_O3, SC_O5,
-  SC_F5, SC_F3, SC_FT5, SC_FPLS, SC_COUNT
+  SC_F5, SC_F3, SC_FT5, SC_FPLS, SC_B3, SC_B5, SC_COUNT
 };
 // One array cleared to zero at the start of the chain.
 struct FillJob {
@@ -46,7 +47,7 @@ struct FillJob {
 };
 enum FillId : int {
   FL_CTR, FL_BCNT, FL_BCUR, FL_INC_CNT, FL_INC_CUR, FL_PH_CNT, FL_PH_CUR, FL_O3_CNT, FL_O3_CUR,
-  FL_O5_CNT, FL_O5_CUR, FL_SEED_USED, FL_T5_USED, FL_COUNT
+  FL_O5_CNT, FL_O5_CUR, FL_SEED_USED, FL_T5_USED, FL_B3_CNT, FL_B3_CUR, FL_B5_CNT, FL_B5_CUR, FL_COUNT
 };
 
 // Device pointers of one event (all inside the workspace except the inputs).
@@ -96,6 +97,8 @@ struct Ws {
   int *pt3_keep, *pt5_keep;
   int *o3_cnt, *o3_off, *o3_cur, *o3_list;      // pT3 entries per T3
   int *o5_cnt, *o5_off, *o5_cur, *o5_list;      // pT5 entries per T5
+  int *b3_cnt, *b3_off, *b3_cur, *b3_list;      // T3s by first-anchor (ring, azimuth) bin
+  int *b5_cnt, *b5_off, *b5_cur, *b5_list;      // surviving T5s by the same bins
   // track candidates
   int *seed_used, *t5_used;
   int *f_pt5, *f_pt3, *f_t5, *f_pls;            // TC flags
