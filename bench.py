@@ -1,14 +1,20 @@
 #!/usr/bin/env python3
-"""Throughput and latency of the LST chain on one MI355X (plain per-event path).
+"""Throughput and latency of the LST chain on one MI355X: served vs plain.
 
-One step = the whole chain (hit bucketing, MD, LS, T3, T5, T5 duplicate
-removal, pLS, pT3/pT5, duplicate removal and cross-cleaning into track
-candidates) for one PU200-like event with pixel seeds, inputs already
-resident in HBM, synchronous (lst_build_event returns after the device work
-and the counter read-back).  Events cycle through a pool of distinct seeded
-events.  Prints one JSON line.
+One step = one event through the whole chain (hit bucketing, MD, LS, T3,
+T5, T5 duplicate removal, pLS, pT3/pT5, duplicate removal and cross-cleaning
+into track candidates), inputs already resident in HBM.  Forms measured:
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--pool P] [--no-cpu]
+* served (the headline `value`): the library's serving loop (streams x
+  batches) with K PU200-like seeded events available at once;
+* plain: synchronous lst_build_event per event, one at a time;
+* trace: an open-loop Poisson trace (500 events/s, pile-up U[50, 250])
+  through the server and through the plain FIFO path (1 stream, batch 1);
+* batched: a captured hipGraph plan over B slots (pile-up U[140, 250]).
+
+Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--pool P] [--no-cpu] ...
 """
 import argparse
 import json
@@ -31,9 +37,14 @@ WORKLOAD = {
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=40)
-    p.add_argument("--warmup", type=int, default=5)
-    p.add_argument("--pool", type=int, default=8, help="distinct events cycled through")
+    p.add_argument("--steps", type=int, default=256, help="events in the timed served run")
+    p.add_argument("--warmup", type=int, default=8)
+    p.add_argument("--pool", type=int, default=12, help="distinct events cycled through")
+    p.add_argument("--streams", type=int, default=4, help="server streams")
+    p.add_argument("--max-batch", type=int, default=16, help="events per server launch sequence")
+    p.add_argument("--rate", type=float, default=500.0, help="Poisson arrival rate of the trace [events/s]")
+    p.add_argument("--trace", type=int, default=1000, help="requests in the open-loop trace (0: skip)")
+    p.add_argument("--batch", type=int, default=32, help="slots of the captured batched plan (0: skip)")
     p.add_argument("--workload", default="pu200_seeded", choices=sorted(WORKLOAD))
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-events", type=int, default=1, help="events in the CPU-baseline sample")
@@ -79,6 +90,37 @@ def algorithmic_bytes(site, c, n_outer, n_mod, n_edges, n_seeds, n_tc):
     return table.get(site)
 
 
+def percentiles(x_ms):
+    import numpy as np
+    x = np.asarray(x_ms, float)
+    return {"p50": round(float(np.percentile(x, 50)), 3), "p99": round(float(np.percentile(x, 99)), 3)}
+
+
+def run_trace(lst, g, dev, n_streams, max_batch, pool_bytes, arrivals, ids):
+    """Open-loop replay: request i (event ids[i]) arrives at arrivals[i] on the server clock."""
+    srv = lst.Server(g, n_streams, max_batch, pool_bytes)
+    t0 = srv.now() + 0.05
+    for i, (a, k) in enumerate(zip(arrivals, ids)):
+        srv.submit(dev[k], i, t0 + a)
+    lat, done, first_arr = [], [], t0
+    bad = []
+
+    def take(r):
+        if r["status"] != lst.LST_OK:
+            bad.append(r["status"])
+        lat.append((r["done_s"] - r["arrival_s"]) * 1e3)
+        done.append(r["done_s"])
+        if r["event"]:
+            lst.lst_release_event(r["event"])
+
+    srv.drain(len(arrivals), take, timeout_s=300.0)
+    srv.close()
+    if bad:
+        raise RuntimeError(f"served requests failed with statuses {sorted(set(bad))}")
+    span = max(done) - first_arr
+    return lat, len(arrivals) / span
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -106,8 +148,9 @@ def main():
     n_hits_max = max(e.n_hits for e in host)
     n_seeds_max = max(e.n_seeds for e in host)
     cap = lst.lst_default_capacity(n_hits_max, n_seeds_max)
-    ws = torch.empty(lst.lst_workspace_bytes(g.handle, n_hits_max, n_seeds_max, cap), dtype=torch.uint8, device=dev)
-    log(f"bench: workspace {ws.numel() / 2**20:.1f} MiB, max hits {n_hits_max}, max seeds {n_seeds_max}")
+    ws_one = lst.lst_workspace_bytes(g.handle, n_hits_max, n_seeds_max, cap)
+    ws = torch.empty(ws_one, dtype=torch.uint8, device=dev)
+    log(f"bench: workspace {ws.numel() / 2**20:.1f} MiB per event, max hits {n_hits_max}, max seeds {n_seeds_max}")
 
     def step(i, timed_site=None):
         st, h = lst.lst_build_event(g.handle, pool[i % len(pool)], ws, cap, stream)
@@ -118,7 +161,7 @@ def main():
         lst.lst_release_event(h)
         return counts, t
 
-    # find the dominant launch site (per-site HIP-event timing on two events, outside the timed region)
+    # ---- dominant launch site: per-site HIP-event timing on two events (outside the timed regions)
     sites = lst.lst_kernel_sites()
     per_site = np.zeros(len(sites))
     for k in range(len(sites)):
@@ -129,26 +172,92 @@ def main():
     dom = int(np.argmax(per_site))
     log("bench: site ms (2 events): " + ", ".join(f"{sites[k]}={per_site[k] / 2:.3f}"
                                                   for k in np.argsort(-per_site)[:8]))
+
+    # ---- plain: synchronous per event; the dominant site bracketed by HIP events
     for i in range(args.warmup):
         step(i)
-    # timed region: K synchronous steps; the dominant site is bracketed by HIP events
     lst.lst_set_timed_site(dom)
     torch.cuda.synchronize()
     lat, dom_ms, counts_all = [], [], []
+    n_plain = max(8, min(args.steps, 32))
     t0 = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(n_plain):
         s0 = time.perf_counter()
         counts, t = step(args.warmup + i, dom)
-        lat.append(time.perf_counter() - s0)
+        lat.append((time.perf_counter() - s0) * 1e3)
         dom_ms.append(t)
         counts_all.append(counts)
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    plain_elapsed = time.perf_counter() - t0
     lst.lst_set_timed_site(-1)
+    plain = {"events_per_s": round(n_plain / plain_elapsed, 3), "latency_ms": percentiles(lat),
+             "events": n_plain}
+    log(f"bench: plain {plain}")
+
+    # ---- served at saturation (the headline): every request available at once
+    n_streams, max_batch = args.streams, args.max_batch
+    pool_bytes = int(ws_one * (n_streams * max_batch + 2))
+    srv = lst.Server(g, n_streams, max_batch, pool_bytes)
+    for i in range(args.warmup):
+        srv.submit(pool[i % len(pool)], -1 - i, 0.0)
+    srv.drain(args.warmup, lambda r: lst.lst_release_event(r["event"]))
+    torch.cuda.synchronize()
+    served_lat = []
+    t0 = time.perf_counter()
+    tnow = srv.now()
+    for i in range(args.steps):
+        srv.submit(pool[i % len(pool)], i, tnow)
+    srv.drain(args.steps, lambda r: (served_lat.append((r["done_s"] - r["arrival_s"]) * 1e3),
+                                      lst.lst_release_event(r["event"])))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    srv.close()
     value = args.steps / elapsed
-    lat_ms = np.array(lat) * 1e3
-    # roofline of the dominant kernel: algorithmic bytes per launch / measured launch time
-    ev_of = [host[(args.warmup + i) % len(host)] for i in range(args.steps)]
+    log(f"bench: served {value:.1f} events/s ({n_streams} streams x {max_batch} per batch)")
+
+    # ---- open-loop trace: Poisson arrivals, pile-up U[50, 250], served vs plain FIFO on the same trace
+    trace = None
+    if args.trace > 0:
+        spool = [lst.upload_event(make_event("serve", i), dev) for i in range(args.pool)]
+        rng = np.random.Generator(np.random.PCG64(4999))
+        arrivals = np.cumsum(rng.exponential(1.0 / args.rate, args.trace))
+        ids = rng.integers(0, len(spool), args.trace)
+        smax = max(int(t["x"].numel()) for t in spool)
+        sseed = max(int(t["px"].numel()) for t in spool)
+        s_one = lst.lst_workspace_bytes(g.handle, smax, sseed)
+        lat_s, rate_s = run_trace(lst, g, spool, n_streams, max_batch, int(s_one * (n_streams * max_batch + 2)),
+                                  arrivals, ids)
+        lat_p, rate_p = run_trace(lst, g, spool, 1, 1, int(s_one * 3), arrivals, ids)
+        trace = {"rate_offered": args.rate, "requests": args.trace, "pileup": "U[50,250]",
+                 "served": {"events_per_s": round(rate_s, 2), "latency_ms": percentiles(lat_s)},
+                 "plain_fifo": {"events_per_s": round(rate_p, 2), "latency_ms": percentiles(lat_p)}}
+        log(f"bench: trace {trace}")
+
+    # ---- batched: captured plan over B slots (pile-up U[140, 250]), graph replays
+    batched = None
+    if args.batch > 0:
+        bpool = [lst.upload_event(make_event("batch", i), dev) for i in range(min(args.pool, args.batch))]
+        bmax = max(int(t["x"].numel()) for t in bpool)
+        bseed = max(int(t["px"].numel()) for t in bpool)
+        plan = lst.Plan(g, args.batch, bmax, bseed)
+        evs = [bpool[i % len(bpool)] for i in range(args.batch)]
+        for r in plan.run(evs):
+            r.close()
+        torch.cuda.synchronize()
+        reps = max(2, args.steps // args.batch)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            for r in plan.run(evs):
+                r.close()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        plan.close()
+        batched = {"events_per_s": round(reps * args.batch / el, 2), "events_per_launch": args.batch,
+                   "ms_per_launch": round(el / reps * 1e3, 3), "pileup": "U[140,250]", "form": "hipGraph replay"}
+        log(f"bench: batched {batched}")
+
+    # ---- roofline of the dominant kernel: algorithmic bytes per launch / measured launch time (plain run)
+    ev_of = [host[(args.warmup + i) % len(host)] for i in range(n_plain)]
     nb = []
     for ev, c in zip(ev_of, counts_all):
         cc = dict(md=int(c[0]), ls=int(c[1]), t3=int(c[2]), t5=int(c[3]), pt3=int(c[5]), pt5=int(c[6]))
@@ -163,15 +272,17 @@ def main():
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
                 "bytes_per_launch": int(avg_bytes), "launch_ms": round(avg_s * 1e3, 4)}
     out = {
-        "metric": "events/s + p50/p99 event latency, PU200-like synthetic, plain per-event path, 1 GPU",
+        "metric": "events/s + p50/p99 event latency, PU200-like synthetic, served vs plain, 1 GPU",
         "value": round(value, 3), "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.workload, "description": WORKLOAD[args.workload], "events_in_pool": args.pool,
                    "mean_hits": int(np.mean([e.n_hits for e in host])),
-                   "mean_seeds": int(np.mean([e.n_seeds for e in host])), "form": "plain synchronous per event"},
-        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
-                       "p99": round(float(np.percentile(lat_ms, 99)), 3)},
+                   "mean_seeds": int(np.mean([e.n_seeds for e in host])),
+                   "form": f"served: {n_streams} streams x batches of {max_batch}, all requests available",
+                   "step": "one event through the whole chain"},
+        "latency_ms": percentiles(served_lat),
+        "plain": plain, "trace": trace, "batched": batched,
         "roofline": roof,
     }
     if not args.no_cpu:

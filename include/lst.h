@@ -51,6 +51,7 @@ typedef enum {
 typedef struct lst_geometry_s *lst_geometry; /* opaque, library-owned, device-resident */
 typedef struct lst_event_s *lst_event;       /* opaque, library-owned host handle */
 typedef struct lst_plan_s *lst_plan;         /* opaque: a captured batch chain (HIP graph) */
+typedef struct lst_server_s *lst_server;     /* opaque: a serving loop */
 
 /* Detector description (Section 1: bi-layer pT modules) and module map
  * (Section 2.2).  All arrays are HOST memory, length n_modules unless noted.
@@ -158,6 +159,45 @@ lst_status lst_plan_create(lst_geometry geom, int32_t B, int32_t max_hits, int32
                            void *workspace, size_t ws_bytes, void *stream, lst_plan *out);
 lst_status lst_plan_run(lst_plan plan, int32_t n_events, const lst_event_desc *evs, void *stream, lst_event *out);
 lst_status lst_plan_release(lst_plan plan);
+
+/* Serving form: a request loop inside the library (its own host thread and
+ * n_streams non-blocking HIP streams of default priority).  Requests arrive
+ * with a time on the server clock (seconds since lst_server_create; a time
+ * already past means "now"); arrived requests are admitted first come first
+ * served, up to max_batch per launch sequence, whenever a stream is free and
+ * the caller's device `pool` (pool_bytes, 256-byte aligned, kept alive until
+ * lst_server_destroy) has room for the batch's footprint.  Batches on
+ * different streams overlap on the device; an event's objects stay resident
+ * in the pool until its handle is released, which returns the memory.
+ * Per event the results are identical to lst_build_event's.  Section 4.2.2's
+ * multi-streaming is the paper's counterpart. */
+typedef struct {
+  int32_t n_streams; /* batches in flight, 1..64 (1 with max_batch 1 = the plain FIFO path) */
+  int32_t max_batch; /* events per launch sequence, 1..1024 */
+} lst_server_config;
+typedef struct {
+  int64_t id;        /* the caller's request id */
+  lst_event event;   /* completed event (release with lst_release_event); NULL if it could not run */
+  double arrival_s;  /* server-clock times: arrival, admission (batch enqueued), completion observed */
+  double admit_s;
+  double done_s;
+  int32_t status;    /* LST_OK, LST_E_CAPACITY, LST_E_INVALID, LST_E_DEVICE, LST_E_NOMEM */
+} lst_server_result;
+lst_status lst_server_create(lst_geometry geom, const lst_server_config *cfg, void *pool, size_t pool_bytes,
+                             lst_server *out);
+/* Seconds since the server was created, on its clock. */
+lst_status lst_server_now(lst_server srv, double *t);
+/* Queues one event (device pointers valid until its result is released).
+ * Errors: LST_E_INVALID (descriptor), LST_E_NOMEM (larger than the pool). */
+lst_status lst_server_submit(lst_server srv, const lst_event_desc *ev, int64_t id, double arrival_s);
+/* Moves up to `max` completed results to `out` (*n of them). */
+lst_status lst_server_poll(lst_server srv, lst_server_result *out, int32_t max, int32_t *n);
+/* Requests not yet admitted, and completed results not yet polled. */
+lst_status lst_server_pending(lst_server srv, int32_t *queued, int32_t *ready);
+/* Waits for the batches in flight, releases unpolled results, stops the loop.
+ * Events still held by the caller stay readable but must be released before
+ * the pool is freed. */
+lst_status lst_server_destroy(lst_server srv);
 
 /* Track candidates (Section 2.5) of a completed event, copied to HOST
  * buffers.  Two-call protocol: pass NULL arrays to get *n_tc and

@@ -27,7 +27,9 @@ EXPORTED = ["lst_load_geometry", "lst_release_geometry", "lst_default_capacity",
             "lst_get_track_candidates", "lst_get_stage_objects", "lst_get_stage_counts",
             "lst_get_module_constants", "lst_release_event", "lst_last_error", "lst_kernel_site_count",
             "lst_kernel_site_name", "lst_set_timed_site", "lst_get_site_time", "lst_batch_workspace_bytes",
-            "lst_enqueue_batch", "lst_plan_workspace_bytes", "lst_plan_create", "lst_plan_run", "lst_plan_release"]
+            "lst_enqueue_batch", "lst_plan_workspace_bytes", "lst_plan_create", "lst_plan_run", "lst_plan_release",
+            "lst_server_create", "lst_server_now", "lst_server_submit", "lst_server_poll", "lst_server_pending",
+            "lst_server_destroy"]
 
 
 class LSTError(RuntimeError):
@@ -53,6 +55,15 @@ class lst_event_desc(ctypes.Structure):
 
 class lst_capacity(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("md", "ls", "t3", "t5", "pt3", "pt5")]
+
+
+class lst_server_config(ctypes.Structure):
+    _fields_ = [("n_streams", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+class lst_server_result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int64), ("event", ctypes.c_void_p), ("arrival_s", ctypes.c_double),
+                ("admit_s", ctypes.c_double), ("done_s", ctypes.c_double), ("status", ctypes.c_int32)]
 
 
 _lib = None
@@ -94,6 +105,12 @@ def load_library(path=LIB_PATH):
         "lst_plan_create": [vp, i32, i32, i32, P(lst_capacity), vp, sz, vp, P(vp)],
         "lst_plan_run": [vp, i32, vp, vp, vp],
         "lst_plan_release": [vp],
+        "lst_server_create": [vp, P(lst_server_config), vp, sz, P(vp)],
+        "lst_server_now": [vp, P(ctypes.c_double)],
+        "lst_server_submit": [vp, P(lst_event_desc), ctypes.c_int64, ctypes.c_double],
+        "lst_server_poll": [vp, vp, i32, P(i32)],
+        "lst_server_pending": [vp, P(i32), P(i32)],
+        "lst_server_destroy": [vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -303,6 +320,43 @@ def lst_plan_release(plan):
     _check(load_library().lst_plan_release(plan))
 
 
+def lst_server_create(geom, n_streams, max_batch, pool):
+    cfg = lst_server_config(int(n_streams), int(max_batch))
+    h = ctypes.c_void_p()
+    _check(load_library().lst_server_create(geom, ctypes.byref(cfg), _ptr(pool), int(pool.numel()),
+                                            ctypes.byref(h)))
+    return h.value
+
+
+def lst_server_now(srv):
+    t = ctypes.c_double()
+    _check(load_library().lst_server_now(srv, ctypes.byref(t)))
+    return t.value
+
+
+def lst_server_submit(srv, dev_event, req_id, arrival_s):
+    d = _event_desc(dev_event)
+    _check(load_library().lst_server_submit(srv, ctypes.byref(d), int(req_id), float(arrival_s)))
+
+
+def lst_server_poll(srv, max_results=4096):
+    buf = (lst_server_result * max_results)()
+    n = ctypes.c_int32()
+    _check(load_library().lst_server_poll(srv, ctypes.cast(buf, ctypes.c_void_p), int(max_results), ctypes.byref(n)))
+    return [dict(id=buf[i].id, event=buf[i].event, arrival_s=buf[i].arrival_s, admit_s=buf[i].admit_s,
+                 done_s=buf[i].done_s, status=buf[i].status) for i in range(n.value)]
+
+
+def lst_server_pending(srv):
+    q, r = ctypes.c_int32(), ctypes.c_int32()
+    _check(load_library().lst_server_pending(srv, ctypes.byref(q), ctypes.byref(r)))
+    return q.value, r.value
+
+
+def lst_server_destroy(srv):
+    _check(load_library().lst_server_destroy(srv))
+
+
 # ------------------------------------------------------------- conveniences
 class Geometry:
     """A detector uploaded to the device (owns the lst_geometry handle)."""
@@ -420,6 +474,55 @@ class Plan:
     def close(self):
         if self.handle:
             lst_plan_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The library's serving loop with a device pool (a torch uint8 tensor) of pool_bytes."""
+
+    def __init__(self, geom, n_streams, max_batch, pool_bytes, device="cuda"):
+        import torch
+        self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=device)
+        torch.cuda.synchronize()
+        self.handle = lst_server_create(geom.handle, n_streams, max_batch, self.pool)
+
+    def now(self):
+        return lst_server_now(self.handle)
+
+    def submit(self, dev_event, req_id, arrival_s=0.0):
+        lst_server_submit(self.handle, dev_event, req_id, arrival_s)
+
+    def poll(self):
+        return lst_server_poll(self.handle)
+
+    def pending(self):
+        return lst_server_pending(self.handle)
+
+    def drain(self, n_expected, on_result, timeout_s=120.0):
+        """Polls until n_expected results arrived; on_result(result dict) must release result['event']."""
+        import time
+        got = 0
+        t_end = time.monotonic() + timeout_s
+        while got < n_expected:
+            rs = self.poll()
+            for r in rs:
+                on_result(r)
+            got += len(rs)
+            if not rs:
+                if time.monotonic() > t_end:
+                    raise TimeoutError(f"server drained {got} of {n_expected} results")
+                time.sleep(0.0005)
+        return got
+
+    def close(self):
+        if self.handle:
+            lst_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

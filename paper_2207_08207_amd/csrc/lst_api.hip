@@ -5,6 +5,11 @@
 #include <cmath>
 #include <cstdio>
 #include <algorithm>
+#include <chrono>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
 #include <atomic>
 #include <cstring>
 #include <new>
@@ -46,6 +51,8 @@ struct lst_geometry_s {
 // Events enqueued together share one batch: one descriptor array and one
 // counter block in the workspace header, one completion event, one pinned
 // read-back buffer.
+struct lst_server_s;
+
 struct lst_batch_s {
   lst_geometry geom = nullptr;
   int B = 0;
@@ -53,8 +60,10 @@ struct lst_batch_s {
   hipEvent_t done = nullptr;
   lst::Ws *h_ws = nullptr;  // pinned: the descriptors uploaded to the header
   int *h_ctr = nullptr;     // pinned: copy of the B x C_COUNT counters
-  int refs = 0;
-  bool synced = false;
+  std::atomic<int> refs{0};
+  std::atomic<bool> synced{false};
+  lst_server_s *server = nullptr;  // a server batch returns its workspace block here when freed
+  size_t block_off = 0;
   bool failed = false;      // a HIP call failed at enqueue
   int timed_site = -1;      // launch site bracketed by tbeg/tend, or -1
   hipEvent_t tbeg = nullptr, tend = nullptr;
@@ -319,9 +328,12 @@ static size_t batch_bytes(int n_mod, int B, const int32_t *nh, const int32_t *ns
   return off;
 }
 
+static void server_release_batch(lst_server_s *s, lst_batch_s *b);
+
 static void release_batch_ref(lst_batch_s *b) {
   if (--b->refs > 0) return;
   if (b->owner && *b->owner == b) *b->owner = nullptr;
+  if (b->server) server_release_batch(b->server, b);
   if (!b->synced && b->done) drop(hipEventSynchronize(b->done));
   if (b->tbeg) drop(hipEventDestroy(b->tbeg));
   if (b->tend) drop(hipEventDestroy(b->tend));
@@ -355,34 +367,27 @@ lst_status lst_workspace_bytes(lst_geometry g, int32_t n_hits, int32_t n_seeds, 
   return lst_batch_workspace_bytes(g, 1, &n_hits, &n_seeds, cap, bytes);
 }
 
-lst_status lst_enqueue_batch(lst_geometry g, int32_t B, const lst_event_desc *evs, const lst_capacity *cap,
-                             void *workspace, size_t ws_bytes, void *stream, lst_event *out) {
-  if (!out) return fail(LST_E_INVALID, "lst_enqueue_batch: NULL out");
-  if (!g || !evs || !workspace || B < 1 || B > 65535) return fail(LST_E_INVALID, "lst_enqueue_batch: bad argument");
-  for (int i = 0; i < B; ++i) out[i] = nullptr;
-  std::vector<int32_t> nh(B), ns(B);
-  for (int i = 0; i < B; ++i) {
-    const lst_event_desc &ev = evs[i];
-    if (ev.n_hits < 0 || ev.n_seeds < 0) return fail(LST_E_INVALID, "negative n_hits or n_seeds");
-    if (ev.n_hits > 0 && (!ev.x || !ev.y || !ev.z || !ev.module || !ev.sensor))
-      return fail(LST_E_INVALID, "hit arrays missing");
-    if (ev.n_seeds > 0 && (!ev.px || !ev.py || !ev.pz || !ev.q || !ev.hits4))
-      return fail(LST_E_INVALID, "seed arrays missing");
-    if (ev.n_seeds > 0 && ev.n_hits == 0) return fail(LST_E_INVALID, "seeds without hits");
-    nh[i] = ev.n_hits;
-    ns[i] = ev.n_seeds;
-  }
-  std::vector<lst::Caps> caps;
-  lst_status s = resolve_caps(B, nh.data(), ns.data(), cap, caps);
-  if (s != LST_OK) return s;
-  const size_t need = batch_bytes(g->g.n_mod, B, nh.data(), ns.data(), caps);
-  if (ws_bytes < need) return fail(LST_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
-  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return fail(LST_E_INVALID, "workspace not 256-byte aligned");
+static lst_status check_event_desc(const lst_event_desc &ev) {
+  if (ev.n_hits < 0 || ev.n_seeds < 0) return fail(LST_E_INVALID, "negative n_hits or n_seeds");
+  if (ev.n_hits > 0 && (!ev.x || !ev.y || !ev.z || !ev.module || !ev.sensor))
+    return fail(LST_E_INVALID, "hit arrays missing");
+  if (ev.n_seeds > 0 && (!ev.px || !ev.py || !ev.pz || !ev.q || !ev.hits4))
+    return fail(LST_E_INVALID, "seed arrays missing");
+  if (ev.n_seeds > 0 && ev.n_hits == 0) return fail(LST_E_INVALID, "seeds without hits");
+  return LST_OK;
+}
+
+// Lays out B events in the workspace at `base` (batch_bytes() bytes), uploads
+// their descriptors and enqueues the chain and the counter read-back on
+// `stream`.  The returned batch holds one reference per event.
+static lst_status enqueue_batch_at(lst_geometry g, int B, const lst_event_desc *evs, const std::vector<lst::Caps> &caps,
+                                   char *base, hipStream_t stream, lst_batch_s **out) {
+  *out = nullptr;
   auto *b = new (std::nothrow) lst_batch_s();
   if (!b) return fail(LST_E_NOMEM, "host allocation failed");
   b->geom = g;
   b->B = B;
-  b->stream = reinterpret_cast<hipStream_t>(stream);
+  b->stream = stream;
   b->refs = B;
   if (hipHostMalloc(reinterpret_cast<void **>(&b->h_ctr), sizeof(int) * lst::C_COUNT * B, hipHostMallocDefault) !=
           hipSuccess ||
@@ -390,17 +395,17 @@ lst_status lst_enqueue_batch(lst_geometry g, int32_t B, const lst_event_desc *ev
       hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
     b->refs = 1;
     release_batch_ref(b);
-    return fail(LST_E_DEVICE, "lst_enqueue_batch: pinned buffers or event creation failed");
+    return fail(LST_E_DEVICE, "pinned buffers or event creation failed");
   }
-  char *base = reinterpret_cast<char *>(workspace);
   lst::Ws *d_ws = reinterpret_cast<lst::Ws *>(base);
   int *d_ctr = reinterpret_cast<int *>(base + ((sizeof(lst::Ws) * (size_t)B + kAlign - 1) / kAlign) * kAlign);
   size_t off = header_bytes(B);
   lst::Ws bound{};
   for (int i = 0; i < B; ++i) {
     lst::Ws &w = b->h_ws[i];
-    off += lst::workspace_layout(g->g.n_mod, nh[i], ns[i], caps[i], &w, base + off, d_ctr + (size_t)i * lst::C_COUNT);
     const lst_event_desc &ev = evs[i];
+    off += lst::workspace_layout(g->g.n_mod, ev.n_hits, ev.n_seeds, caps[i], &w, base + off,
+                                 d_ctr + (size_t)i * lst::C_COUNT);
     w.x = ev.x; w.y = ev.y; w.z = ev.z; w.module = ev.module; w.sensor = ev.sensor;
     w.px = ev.px; w.py = ev.py; w.pz = ev.pz; w.q = ev.q; w.hits4 = ev.hits4;
     bound.n_hits = std::max(bound.n_hits, w.n_hits);
@@ -419,27 +424,61 @@ lst_status lst_enqueue_batch(lst_geometry g, int32_t B, const lst_event_desc *ev
     kt = lst::KernelTimer{site, b->tbeg, b->tend};
     b->timed_site = site;
   }
-  hipError_t he = hipMemcpyAsync(d_ws, b->h_ws, sizeof(lst::Ws) * B, hipMemcpyHostToDevice, b->stream);
+  hipError_t he = hipMemcpyAsync(d_ws, b->h_ws, sizeof(lst::Ws) * B, hipMemcpyHostToDevice, stream);
   if (he == hipSuccess) {
-    lst::enqueue_chain(g->g, d_ws, B, bound, b->stream, b->timed_site >= 0 ? &kt : nullptr);
+    lst::enqueue_chain(g->g, d_ws, B, bound, stream, b->timed_site >= 0 ? &kt : nullptr);
     he = hipGetLastError();
   }
   if (he == hipSuccess)
-    he = hipMemcpyAsync(b->h_ctr, d_ctr, sizeof(int) * lst::C_COUNT * B, hipMemcpyDeviceToHost, b->stream);
-  if (he == hipSuccess) he = hipEventRecord(b->done, b->stream);
+    he = hipMemcpyAsync(b->h_ctr, d_ctr, sizeof(int) * lst::C_COUNT * B, hipMemcpyDeviceToHost, stream);
+  if (he == hipSuccess) he = hipEventRecord(b->done, stream);
   if (he != hipSuccess) b->failed = true;
-  for (int i = 0; i < B; ++i) {
+  *out = b;
+  if (he != hipSuccess) return fail(LST_E_DEVICE, std::string("enqueue: ") + hipGetErrorString(he));
+  return LST_OK;
+}
+
+static lst_status make_events(lst_batch_s *b, int n, lst_event *out) {
+  for (int i = 0; i < n; ++i) {
     auto *e = new (std::nothrow) lst_event_s();
     if (!e) {
-      for (int k = i; k < B; ++k) release_batch_ref(b);
+      for (int k = i; k < n; ++k) release_batch_ref(b);
       return fail(LST_E_NOMEM, "host allocation failed");
     }
     e->batch = b;
     e->index = i;
     out[i] = e;
   }
-  if (he != hipSuccess) return fail(LST_E_DEVICE, std::string("lst_enqueue_batch: ") + hipGetErrorString(he));
   return LST_OK;
+}
+
+lst_status lst_enqueue_batch(lst_geometry g, int32_t B, const lst_event_desc *evs, const lst_capacity *cap,
+                             void *workspace, size_t ws_bytes, void *stream, lst_event *out) {
+  if (!out) return fail(LST_E_INVALID, "lst_enqueue_batch: NULL out");
+  if (!g || !evs || !workspace || B < 1 || B > 65535) return fail(LST_E_INVALID, "lst_enqueue_batch: bad argument");
+  for (int i = 0; i < B; ++i) out[i] = nullptr;
+  std::vector<int32_t> nh(B), ns(B);
+  for (int i = 0; i < B; ++i) {
+    lst_status s = check_event_desc(evs[i]);
+    if (s != LST_OK) return s;
+    nh[i] = evs[i].n_hits;
+    ns[i] = evs[i].n_seeds;
+  }
+  std::vector<lst::Caps> caps;
+  lst_status s = resolve_caps(B, nh.data(), ns.data(), cap, caps);
+  if (s != LST_OK) return s;
+  const size_t need = batch_bytes(g->g.n_mod, B, nh.data(), ns.data(), caps);
+  if (ws_bytes < need) return fail(LST_E_NOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return fail(LST_E_INVALID, "workspace not 256-byte aligned");
+  lst_batch_s *b = nullptr;
+  lst_status es = enqueue_batch_at(g, B, evs, caps, reinterpret_cast<char *>(workspace),
+                                   reinterpret_cast<hipStream_t>(stream), &b);
+  if (!b) return es;
+  std::string msg = g_err;
+  lst_status ms = make_events(b, B, out);
+  if (ms != LST_OK) return ms;
+  if (es != LST_OK) g_err = msg;
+  return es;
 }
 
 lst_status lst_enqueue_event(lst_geometry g, const lst_event_desc *ev, const lst_capacity *cap, void *workspace,
@@ -755,6 +794,284 @@ lst_status lst_plan_release(lst_plan p) {
   if (p->exec) drop(hipGraphExecDestroy(p->exec));
   if (p->graph) drop(hipGraphDestroy(p->graph));
   delete p;
+  return LST_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ server
+namespace {
+
+struct SrvReq {
+  int64_t id;
+  lst_event_desc ev;
+  double arrival;
+  size_t region;  // footprint of the event's region in a batch workspace
+};
+
+struct SrvFlight {
+  lst_batch_s *batch;
+  std::vector<SrvReq> reqs;
+  double admit;
+  int stream;
+};
+
+double secs_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct lst_server_s {
+  lst_geometry geom = nullptr;
+  lst_server_config cfg{};
+  int device = 0;
+  char *pool = nullptr;
+  size_t pool_bytes = 0;
+  std::map<size_t, size_t> free_blocks;  // offset -> size, coalesced
+  std::map<size_t, size_t> used_blocks;  // offset -> size
+  std::vector<hipStream_t> streams;
+  std::mutex mu;  // guards pending, results, the allocator, live, counters
+  std::deque<SrvReq> pending;
+  std::vector<lst_server_result> results;
+  std::map<lst_batch_s *, int> live;  // batches whose events are out with the client
+  std::vector<SrvFlight> flights;     // scheduler thread only
+  std::thread th;
+  std::atomic<bool> stop{false};
+  std::chrono::steady_clock::time_point t0;
+  int64_t n_batches = 0;
+};
+
+// caller holds s->mu
+static void server_free_block_locked(lst_server_s *s, size_t off) {
+  auto it = s->used_blocks.find(off);
+  if (it == s->used_blocks.end()) return;
+  size_t size = it->second;
+  s->used_blocks.erase(it);
+  auto nx = s->free_blocks.lower_bound(off);
+  if (nx != s->free_blocks.end() && off + size == nx->first) {
+    size += nx->second;
+    nx = s->free_blocks.erase(nx);
+  }
+  if (nx != s->free_blocks.begin()) {
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == off) {
+      pv->second += size;
+      return;
+    }
+  }
+  s->free_blocks.emplace(off, size);
+}
+
+static void server_free_block(lst_server_s *s, size_t off) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  server_free_block_locked(s, off);
+}
+
+// a server batch's last event was released: its workspace block returns to the pool
+static void server_release_batch(lst_server_s *s, lst_batch_s *b) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->live.erase(b);
+  server_free_block_locked(s, b->block_off);
+}
+
+// first fit; caller holds s->mu; returns SIZE_MAX when nothing fits
+static size_t server_alloc(lst_server_s *s, size_t size) {
+  size = (size + kAlign - 1) / kAlign * kAlign;
+  for (auto it = s->free_blocks.begin(); it != s->free_blocks.end(); ++it) {
+    if (it->second < size) continue;
+    const size_t off = it->first, rest = it->second - size;
+    s->free_blocks.erase(it);
+    if (rest) s->free_blocks.emplace(off + size, rest);
+    s->used_blocks.emplace(off, size);
+    return off;
+  }
+  return SIZE_MAX;
+}
+
+static void server_loop(lst_server_s *s) {
+  (void)hipSetDevice(s->device);
+  std::vector<int> busy(s->streams.size(), 0);
+  while (!s->stop.load() || !s->flights.empty()) {
+    bool worked = false;
+    // completions
+    for (size_t f = 0; f < s->flights.size();) {
+      SrvFlight &fl = s->flights[f];
+      const hipError_t q = fl.batch->failed ? hipErrorUnknown : hipEventQuery(fl.batch->done);
+      if (q == hipErrorNotReady) { ++f; continue; }
+      const double t = secs_since(s->t0);
+      fl.batch->synced = true;
+      std::vector<lst_event> evs(fl.reqs.size(), nullptr);
+      make_events(fl.batch, (int)fl.reqs.size(), evs.data());
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->live[fl.batch] = 1;
+        for (size_t i = 0; i < fl.reqs.size(); ++i) {
+          lst_server_result r{};
+          r.id = fl.reqs[i].id;
+          r.event = evs[i];
+          r.arrival_s = fl.reqs[i].arrival;
+          r.admit_s = fl.admit;
+          r.done_s = t;
+          const int st = fl.batch->h_ctr[i * lst::C_COUNT + lst::C_STATUS];
+          r.status = fl.batch->failed ? LST_E_DEVICE
+                     : (st & (lst::ST_BAD_HIT | lst::ST_BAD_SEED)) ? LST_E_INVALID
+                     : (st & lst::ST_CAPACITY) ? LST_E_CAPACITY : LST_OK;
+          s->results.push_back(r);
+        }
+      }
+      busy[fl.stream] = 0;
+      s->flights.erase(s->flights.begin() + (long)f);
+      worked = true;
+    }
+    // admission: arrived requests, FIFO, batched, as streams and pool memory allow
+    for (size_t si = 0; si < s->streams.size() && !s->stop.load(); ++si) {
+      if (busy[si]) continue;
+      const double now = secs_since(s->t0);
+      std::vector<SrvReq> take;
+      size_t off = SIZE_MAX;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        size_t k = 0;
+        while (k < s->pending.size() && (int)k < s->cfg.max_batch && s->pending[k].arrival <= now) ++k;
+        while (k > 0) {
+          size_t need = header_bytes((int)k);
+          for (size_t i = 0; i < k; ++i) need += s->pending[i].region;
+          off = server_alloc(s, need);
+          if (off != SIZE_MAX) break;
+          --k;
+        }
+        for (size_t i = 0; i < k; ++i) {
+          take.push_back(s->pending.front());
+          s->pending.pop_front();
+        }
+      }
+      if (take.empty()) break;
+      std::vector<lst_event_desc> evs(take.size());
+      std::vector<int32_t> nh(take.size()), ns(take.size());
+      for (size_t i = 0; i < take.size(); ++i) {
+        evs[i] = take[i].ev;
+        nh[i] = evs[i].n_hits;
+        ns[i] = evs[i].n_seeds;
+      }
+      std::vector<lst::Caps> caps;
+      resolve_caps((int)take.size(), nh.data(), ns.data(), nullptr, caps);
+      lst_batch_s *b = nullptr;
+      enqueue_batch_at(s->geom, (int)take.size(), evs.data(), caps, s->pool + off, s->streams[si], &b);
+      if (!b) {  // host allocation failure: report the requests as failed
+        server_free_block(s, off);
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &r : take) {
+          lst_server_result res{};
+          res.id = r.id; res.arrival_s = r.arrival; res.admit_s = now; res.done_s = now; res.status = LST_E_NOMEM;
+          s->results.push_back(res);
+        }
+        continue;
+      }
+      b->server = s;
+      b->block_off = off;
+      s->flights.push_back(SrvFlight{b, std::move(take), now, (int)si});
+      busy[si] = 1;
+      ++s->n_batches;
+      worked = true;
+    }
+    if (!worked) std::this_thread::yield();
+  }
+}
+
+extern "C" {
+
+lst_status lst_server_create(lst_geometry g, const lst_server_config *cfg, void *pool, size_t pool_bytes,
+                             lst_server *out) {
+  if (!out) return fail(LST_E_INVALID, "lst_server_create: NULL out");
+  *out = nullptr;
+  if (!g || !cfg || !pool || cfg->n_streams < 1 || cfg->n_streams > 64 || cfg->max_batch < 1 ||
+      cfg->max_batch > 1024)
+    return fail(LST_E_INVALID, "lst_server_create: bad argument");
+  if (reinterpret_cast<uintptr_t>(pool) % kAlign != 0) return fail(LST_E_INVALID, "pool not 256-byte aligned");
+  auto *s = new (std::nothrow) lst_server_s();
+  if (!s) return fail(LST_E_NOMEM, "host allocation failed");
+  s->geom = g;
+  s->cfg = *cfg;
+  s->pool = reinterpret_cast<char *>(pool);
+  s->pool_bytes = pool_bytes / kAlign * kAlign;
+  s->free_blocks.emplace(0, s->pool_bytes);
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return fail(LST_E_DEVICE, "hipGetDevice failed");
+  }
+  for (int i = 0; i < cfg->n_streams; ++i) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      for (auto x : s->streams) drop(hipStreamDestroy(x));
+      delete s;
+      return fail(LST_E_DEVICE, "stream creation failed");
+    }
+    s->streams.push_back(st);
+  }
+  s->t0 = std::chrono::steady_clock::now();
+  s->th = std::thread(server_loop, s);
+  *out = s;
+  return LST_OK;
+}
+
+lst_status lst_server_now(lst_server s, double *t) {
+  if (!s || !t) return fail(LST_E_INVALID, "lst_server_now: NULL argument");
+  *t = secs_since(s->t0);
+  return LST_OK;
+}
+
+lst_status lst_server_submit(lst_server s, const lst_event_desc *ev, int64_t id, double arrival_s) {
+  if (!s || !ev) return fail(LST_E_INVALID, "lst_server_submit: NULL argument");
+  lst_status st = check_event_desc(*ev);
+  if (st != LST_OK) return st;
+  std::vector<lst::Caps> caps;
+  st = resolve_caps(1, &ev->n_hits, &ev->n_seeds, nullptr, caps);
+  if (st != LST_OK) return st;
+  const size_t region = lst::workspace_layout(s->geom->g.n_mod, ev->n_hits, ev->n_seeds, caps[0], nullptr, nullptr,
+                                              nullptr);
+  if (region + header_bytes(1) > s->pool_bytes) return fail(LST_E_NOMEM, "event larger than the server's pool");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->pending.push_back(SrvReq{id, *ev, arrival_s, region});
+  return LST_OK;
+}
+
+lst_status lst_server_poll(lst_server s, lst_server_result *out, int32_t max, int32_t *n) {
+  if (!s || !n || (max > 0 && !out)) return fail(LST_E_INVALID, "lst_server_poll: bad argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  const int k = std::min<int>(max, (int)s->results.size());
+  for (int i = 0; i < k; ++i) out[i] = s->results[i];
+  s->results.erase(s->results.begin(), s->results.begin() + k);
+  *n = k;
+  return LST_OK;
+}
+
+lst_status lst_server_pending(lst_server s, int32_t *queued, int32_t *ready) {
+  if (!s || !queued || !ready) return fail(LST_E_INVALID, "lst_server_pending: NULL argument");
+  std::lock_guard<std::mutex> lk(s->mu);
+  *queued = (int32_t)s->pending.size();
+  *ready = (int32_t)s->results.size();
+  return LST_OK;
+}
+
+lst_status lst_server_destroy(lst_server s) {
+  if (!s) return LST_OK;
+  s->stop.store(true);
+  if (s->th.joinable()) s->th.join();  // returns once in-flight batches completed
+  std::vector<lst_server_result> left;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    left.swap(s->results);
+  }
+  for (auto &r : left)
+    if (r.event) lst_release_event(r.event);
+  {
+    // batches whose events the client still holds no longer return memory here
+    std::lock_guard<std::mutex> lk(s->mu);
+    for (auto &kv : s->live) kv.first->server = nullptr;
+  }
+  for (auto st : s->streams) drop(hipStreamDestroy(st));
+  delete s;
   return LST_OK;
 }
 

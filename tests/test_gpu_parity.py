@@ -199,3 +199,32 @@ def test_plan_replays_equal_eager(lst, gbarrel, obarrel):
     o = oracle.run(obarrel, evs[1])
     compare_event(r, o, stages=range(4))
     compare_tc(r, o)
+
+
+# ------------------------------------------------------------------ serving
+def test_served_mix_equals_alone(lst, gfull):
+    """Each result is the same alone (plain path) and in the served mix (continuous batching)."""
+    evs = [make_event("serve", k) for k in range(6)]
+    print("[gpu] serve events PU", [round(e.tracks["pu"]) for e in evs], flush=True)
+    dev = [lst.upload_event(e) for e in evs]
+    alone = [_tc_tuple(lst.run_event(gfull, d)) for d in dev]
+    one = max(lst.lst_workspace_bytes(gfull.handle, e.n_hits, e.n_seeds) for e in evs)
+    for n_streams, max_batch, pool, stagger in ((3, 4, 12 * one, 0.0), (2, 3, 2.2 * one, 0.002), (1, 1, 1.2 * one, 0.0)):
+        print(f"[gpu] server streams={n_streams} batch={max_batch} pool={pool / 2**30:.2f} GiB", flush=True)
+        srv = lst.Server(gfull, n_streams, max_batch, pool)
+        t0 = srv.now()
+        order = [3, 0, 5, 1, 4, 2, 0, 3]
+        for i, k in enumerate(order):
+            srv.submit(dev[k], i, t0 + stagger * i)
+        got = {}
+
+        def take(r):
+            assert r["status"] == lst.LST_OK, r
+            res = lst.EventResult(r["event"], None, lst.LST_OK)
+            got[r["id"]] = _tc_tuple(res)
+            assert r["done_s"] >= r["admit_s"] >= r["arrival_s"] - 1e-6
+            res.close()
+
+        srv.drain(len(order), take)
+        srv.close()
+        assert [got[i] for i in range(len(order))] == [alone[k] for k in order]
