@@ -45,6 +45,10 @@ def parse():
     p.add_argument("--rate", type=float, default=500.0, help="Poisson arrival rate of the trace [events/s]")
     p.add_argument("--trace", type=int, default=1000, help="requests in the open-loop trace (0: skip)")
     p.add_argument("--batch", type=int, default=32, help="slots of the captured batched plan (0: skip)")
+    p.add_argument("--forms", default="plain,served,trace,batched,copy",
+                   help="comma list of forms to run (served is the headline and always runs)")
+    p.add_argument("--site", default=None,
+                   help="launch site to time for the roofline (default: the largest in a per-site calibration)")
     p.add_argument("--workload", default="pu200_seeded", choices=sorted(WORKLOAD))
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     p.add_argument("--cpu-events", type=int, default=1, help="events in the CPU-baseline sample")
@@ -161,63 +165,84 @@ def main():
         lst.lst_release_event(h)
         return counts, t
 
-    # ---- dominant launch site: per-site HIP-event timing on two events (outside the timed regions)
+    forms = set(args.forms.split(","))
     sites = lst.lst_kernel_sites()
-    per_site = np.zeros(len(sites))
-    for k in range(len(sites)):
-        lst.lst_set_timed_site(k)
-        for i in range(2):
-            per_site[k] += step(i, k)[1]
-    lst.lst_set_timed_site(-1)
-    dom = int(np.argmax(per_site))
-    log("bench: site ms (2 events): " + ", ".join(f"{sites[k]}={per_site[k] / 2:.3f}"
-                                                  for k in np.argsort(-per_site)[:8]))
+    if args.site is not None:
+        dom = sites.index(args.site)
+    else:
+        # dominant launch site: per-site HIP-event timing on two events (outside the timed regions)
+        per_site = np.zeros(len(sites))
+        for k in range(len(sites)):
+            lst.lst_set_timed_site(k)
+            for i in range(2):
+                per_site[k] += step(i, k)[1]
+        lst.lst_set_timed_site(-1)
+        dom = int(np.argmax(per_site))
+        log("bench: site ms (2 events): " + ", ".join(f"{sites[k]}={per_site[k] / 2:.3f}"
+                                                      for k in np.argsort(-per_site)[:8]))
 
-    # ---- plain: synchronous per event; the dominant site bracketed by HIP events
-    for i in range(args.warmup):
-        step(i)
-    lst.lst_set_timed_site(dom)
-    torch.cuda.synchronize()
-    lat, dom_ms, counts_all = [], [], []
-    n_plain = max(8, min(args.steps, 32))
-    t0 = time.perf_counter()
-    for i in range(n_plain):
-        s0 = time.perf_counter()
-        counts, t = step(args.warmup + i, dom)
-        lat.append((time.perf_counter() - s0) * 1e3)
-        dom_ms.append(t)
-        counts_all.append(counts)
-    torch.cuda.synchronize()
-    plain_elapsed = time.perf_counter() - t0
-    lst.lst_set_timed_site(-1)
-    plain = {"events_per_s": round(n_plain / plain_elapsed, 3), "latency_ms": percentiles(lat),
-             "events": n_plain}
-    log(f"bench: plain {plain}")
+    def event_bytes(ev, c):
+        cc = dict(md=int(c[0]), ls=int(c[1]), t3=int(c[2]), t5=int(c[3]), pt3=int(c[5]), pt5=int(c[6]))
+        return algorithmic_bytes(sites[dom], cc, int((ev.module >= 0).sum()), geom.n_modules,
+                                 int(geom.map_targets.size), ev.n_seeds, int(c[7]))
 
-    # ---- served at saturation (the headline): every request available at once
+    # ---- plain: synchronous per event
+    plain = None
+    if "plain" in forms:
+        for i in range(args.warmup):
+            step(i)
+        torch.cuda.synchronize()
+        lat = []
+        n_plain = max(8, min(args.steps, 32))
+        t0 = time.perf_counter()
+        for i in range(n_plain):
+            s0 = time.perf_counter()
+            step(args.warmup + i)
+            lat.append((time.perf_counter() - s0) * 1e3)
+        torch.cuda.synchronize()
+        plain_elapsed = time.perf_counter() - t0
+        plain = {"events_per_s": round(n_plain / plain_elapsed, 3), "latency_ms": percentiles(lat),
+                 "events": n_plain}
+        log(f"bench: plain {plain}")
+
+    # ---- served at saturation (the headline): every request available at once; the dominant
+    # launch site of every batched launch sequence is bracketed by HIP events on its stream
     n_streams, max_batch = args.streams, args.max_batch
     pool_bytes = int(ws_one * (n_streams * max_batch + 2))
     srv = lst.Server(g, n_streams, max_batch, pool_bytes)
-    for i in range(args.warmup):
+    n_warm = max(args.warmup, max_batch)
+    for i in range(n_warm):
         srv.submit(pool[i % len(pool)], -1 - i, 0.0)
-    srv.drain(args.warmup, lambda r: lst.lst_release_event(r["event"]))
+    srv.drain(n_warm, lambda r: lst.lst_release_event(r["event"]))
+    lst.lst_set_timed_site(dom)
     torch.cuda.synchronize()
-    served_lat = []
+    served_lat, launches = [], {}
+
+    def take(r):
+        served_lat.append((r["done_s"] - r["arrival_s"]) * 1e3)
+        c, _ = lst.lst_get_stage_counts(r["event"])
+        ms = lst.lst_get_site_time(r["event"])
+        rec = launches.setdefault(r["admit_s"], [ms, 0.0])
+        b = event_bytes(host[r["id"] % len(host)], c)
+        rec[1] = None if (b is None or rec[1] is None) else rec[1] + b
+        lst.lst_release_event(r["event"])
+
     t0 = time.perf_counter()
     tnow = srv.now()
     for i in range(args.steps):
         srv.submit(pool[i % len(pool)], i, tnow)
-    srv.drain(args.steps, lambda r: (served_lat.append((r["done_s"] - r["arrival_s"]) * 1e3),
-                                      lst.lst_release_event(r["event"])))
+    srv.drain(args.steps, take)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    lst.lst_set_timed_site(-1)
     srv.close()
     value = args.steps / elapsed
-    log(f"bench: served {value:.1f} events/s ({n_streams} streams x {max_batch} per batch)")
+    log(f"bench: served {value:.1f} events/s ({n_streams} streams x {max_batch} per batch, "
+        f"{len(launches)} launch sequences)")
 
     # ---- open-loop trace: Poisson arrivals, pile-up U[50, 250], served vs plain FIFO on the same trace
     trace = None
-    if args.trace > 0:
+    if args.trace > 0 and "trace" in forms:
         spool = [lst.upload_event(make_event("serve", i), dev) for i in range(args.pool)]
         rng = np.random.Generator(np.random.PCG64(4999))
         arrivals = np.cumsum(rng.exponential(1.0 / args.rate, args.trace))
@@ -235,7 +260,7 @@ def main():
 
     # ---- batched: captured plan over B slots (pile-up U[140, 250]), graph replays
     batched = None
-    if args.batch > 0:
+    if args.batch > 0 and "batched" in forms:
         bpool = [lst.upload_event(make_event("batch", i), dev) for i in range(min(args.pool, args.batch))]
         bmax = max(int(t["x"].numel()) for t in bpool)
         bseed = max(int(t["px"].numel()) for t in bpool)
@@ -256,21 +281,37 @@ def main():
                    "ms_per_launch": round(el / reps * 1e3, 3), "pileup": "U[140,250]", "form": "hipGraph replay"}
         log(f"bench: batched {batched}")
 
-    # ---- roofline of the dominant kernel: algorithmic bytes per launch / measured launch time (plain run)
-    ev_of = [host[(args.warmup + i) % len(host)] for i in range(n_plain)]
-    nb = []
-    for ev, c in zip(ev_of, counts_all):
-        cc = dict(md=int(c[0]), ls=int(c[1]), t3=int(c[2]), t5=int(c[3]), pt3=int(c[5]), pt5=int(c[6]))
-        nb.append(algorithmic_bytes(sites[dom], cc, int((ev.module >= 0).sum()), geom.n_modules,
-                                    int(geom.map_targets.size), ev.n_seeds, int(c[7])))
+    # ---- device-to-device copy of a known size: achievable HBM bandwidth, and the reference
+    # dispatch for scaling the FETCH_SIZE / WRITE_SIZE counters
+    copy = None
+    if "copy" in forms:
+        nbytes = 1 << 30
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        reps = 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        copy = {"bytes_per_copy": nbytes, "read_plus_write_GBs": round(2 * nbytes * reps / el / 1e9, 1)}
+        del src, dst
+        log(f"bench: copy {copy}")
+
+    # ---- roofline of the dominant kernel: algorithmic bytes of the events of each batched launch
+    # divided by that launch's HIP-event duration, summed over the served run's launches
     roof = None
-    if all(b is not None for b in nb):
-        avg_bytes = float(np.mean(nb))
-        avg_s = float(np.mean(dom_ms)) / 1e3
-        ach = avg_bytes / avg_s / 1e9
+    if launches and all(v[1] is not None for v in launches.values()):
+        tot_b = sum(v[1] for v in launches.values())
+        tot_s = sum(v[0] for v in launches.values()) / 1e3
+        ach = tot_b / tot_s / 1e9
         roof = {"bound": "hbm", "kernel": sites[dom], "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5), "traffic": None,
-                "bytes_per_launch": int(avg_bytes), "launch_ms": round(avg_s * 1e3, 4)}
+                "launches": len(launches), "bytes_per_launch": int(tot_b / len(launches)),
+                "launch_ms": round(tot_s * 1e3 / len(launches), 4),
+                "events_per_launch": round(args.steps / len(launches), 2)}
     out = {
         "metric": "events/s + p50/p99 event latency, PU200-like synthetic, served vs plain, 1 GPU",
         "value": round(value, 3), "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -282,7 +323,7 @@ def main():
                    "form": f"served: {n_streams} streams x batches of {max_batch}, all requests available",
                    "step": "one event through the whole chain"},
         "latency_ms": percentiles(served_lat),
-        "plain": plain, "trace": trace, "batched": batched,
+        "plain": plain, "trace": trace, "batched": batched, "copy": copy,
         "roofline": roof,
     }
     if not args.no_cpu:

@@ -106,6 +106,7 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.md_cnt = I(M + 1); t.md_off = I(M + 1);
   t.md_hits = I2(md); t.md_mod = I(md); t.md_pos = F4(md); t.md_stub = F2(md);
   t.ls_cnt = I(md + 1); t.ls_off = I(md + 1); t.ls_md = I2(ls); t.ls_beta = F2(ls);
+  t.ls_cache = I(16 * md);
   t.t3_cnt = I(ls + 1); t.t3_off = I(ls + 1); t.t3_md = I4(t3); t.t3_attr = F4(t3); t.t3_first = F2(t3);
   t.t5_cnt = I(t3 + 1); t.t5_off = I(t3 + 1); t.t5_t3 = I2(t5); t.t5_md = I(5 * t5); t.t5_attr = F(8 * t5);
   t.t5_keep = I(t5); t.t5_first = F2(t5);

@@ -317,6 +317,7 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
 
 // ------------------------------------------------------------- a2: LS
 constexpr int kMaxEdges = 256;  // module-map targets per module handled by one wave
+constexpr int kLsCache = 16;    // passing partners per MD remembered between the count and fill passes
 
 // One wave per inner MD a.  Its candidates -- the MDs of every module linked
 // to a's module, edge by edge -- are flattened into one list that the 64
@@ -337,6 +338,23 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
     const float4 A = w.md_pos[a];
     const float2 sa = w.md_stub[a];
     const ModInfo mia{g.info[ma]};
+    if (FILL) {
+      // the count pass cached up to kLsCache passing partners in candidate order
+      const int n_pass = w.ls_cnt[a];
+      if (n_pass <= kLsCache) {
+        const int out0 = w.ls_off[a];
+        for (int i = lane; i < n_pass; i += 64) {
+          const int b = w.ls_cache[(long)a * kLsCache + i];
+          float2 beta = make_float2(0.f, 0.f);
+          ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, ModInfo{g.info[w.md_mod[b]]}, &beta);
+          if (out0 + i < w.cap_ls) {
+            w.ls_md[out0 + i] = make_int2(a, b);
+            w.ls_beta[out0 + i] = beta;
+          }
+        }
+        continue;
+      }
+    }
     const int e0 = g.map_off[ma];
     const int ne = g.map_off[ma + 1] - e0;  // <= kMaxEdges, checked when the geometry is loaded
     // per-edge MD ranges and their exclusive prefix over the wave
@@ -381,13 +399,15 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
         pass = ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, ModInfo{s_info[wv][e]}, &beta);
       }
       const unsigned long long m = __ballot(pass);
+      const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
       if (FILL) {
-        const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
         const int pos = out + pre;
         if (pass && pos < w.cap_ls) {
           w.ls_md[pos] = make_int2(a, b);
           w.ls_beta[pos] = beta;
         }
+      } else if (pass && cnt + pre < kLsCache) {
+        w.ls_cache[(long)a * kLsCache + cnt + pre] = b;
       }
       out += __popcll(m);
       cnt += __popcll(m);
@@ -529,7 +549,8 @@ __global__ void k_t5_dedup(const Ws *__restrict__ wb) {
     t5_hits(w, t, ht);
     const float st = w.t5_attr[8 * (long)t + 1];
     bool keep = true;
-    for (int k = 0; k < 5 && keep; ++k) {
+    // a duplicate shares two of the five MDs, hence one of the first four
+    for (int k = 0; k < 4 && keep; ++k) {
       const int md = mt[k];
       for (int q = w.inc_off[md]; q < w.inc_off[md + 1] && keep; ++q) {
         const int u = w.inc_list[q];
@@ -1006,32 +1027,42 @@ __global__ __launch_bounds__(1024) void k_bin_dirs(const Ws *__restrict__ wb, in
   }
 }
 
-__device__ __forceinline__ bool near_any(const Dir &d, const float4 *lst, const int *bin_off, float D, int reach) {
+// Wave-cooperative query: the 64 lanes stride over the entries of the bins
+// around the query's azimuth; returns (to every lane) whether any is near.
+// `d` and `active` must be wave-uniform.
+__device__ __forceinline__ bool near_any_wave(const Dir &d, bool active, const float4 *lst, const int *bin_off, float D,
+                                              int reach) {
+  if (!active) return false;
+  const int lane = lane_id();
   const int b0 = dir_bin(d.dx, d.dy);
   for (int k = -reach; k <= reach; ++k) {
     const int b = (b0 + k + kDirBins) % kDirBins;
-    const int j1 = bin_off[b + 1];
-    for (int j = bin_off[b]; j < j1; ++j) {
-      const float4 e = lst[j];
-      Dir o;
-      o.dx = e.x; o.dy = e.y; o.lam = e.z;
-      if (near_dir(d, o, D)) return true;
+    const int j0 = bin_off[b], j1 = bin_off[b + 1];
+    for (int j = j0 + lane; j - lane < j1; j += 64) {
+      bool nr = false;
+      if (j < j1) {
+        const float4 e = lst[j];
+        Dir o;
+        o.dx = e.x; o.dy = e.y; o.lam = e.z;
+        nr = near_dir(d, o, D);
+      }
+      if (__ballot(nr)) return true;
     }
   }
   return false;
 }
 
 // pT3 TCs: surviving pT3 whose seed no TC-pT5 uses and that is not near any TC-pT5.
+// One wave per candidate (the query loops over binned lists with its lanes).
 __global__ void k_tc_pt3(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NPT3];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    int f = 0;
-    if (w.pt3_keep[i]) {
-      const int s = w.pt3_so[i].x;
-      if (!w.seed_used[s]) f = near_any(dir_of_seed(w, s), w.bdir_pt5, w.boff_pt5, kDpT3, bin_reach(0.02)) ? 0 : 1;
-    }
-    w.f_pt3[i] = f;
+  const int nw = gridDim.x * kWaves;
+  for (int i = blockIdx.x * kWaves + (threadIdx.x >> 6); i < n; i += nw) {
+    const int s = w.pt3_so[i].x;
+    const bool cand = w.pt3_keep[i] && !w.seed_used[s];
+    const bool nr = near_any_wave(dir_of_seed(w, s), cand, w.bdir_pt5, w.boff_pt5, kDpT3, bin_reach(0.02));
+    if (lane_id() == 0) w.f_pt3[i] = (cand && !nr) ? 1 : 0;
   }
 }
 __global__ void k_tc_dirs_pt3(const Ws *__restrict__ wb) {
@@ -1049,14 +1080,13 @@ __global__ void k_tc_dirs_pt3(const Ws *__restrict__ wb) {
 __global__ void k_tc_t5(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NT5];
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
-    int f = 0;
-    if (w.t5_keep[t] && !w.t5_used[t]) {
-      const Dir d = dir_of_t5(w, t);
-      f = (near_any(d, w.bdir_pt5, w.boff_pt5, kDT5, bin_reach(0.02)) ||
-           near_any(d, w.bdir_pt3, w.boff_pt3, kDT5, bin_reach(0.02))) ? 0 : 1;
-    }
-    w.f_t5[t] = f;
+  const int nw = gridDim.x * kWaves;
+  for (int t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < n; t += nw) {
+    const bool cand = w.t5_keep[t] && !w.t5_used[t];
+    const Dir d = dir_of_t5(w, t);
+    const bool nr = near_any_wave(d, cand, w.bdir_pt5, w.boff_pt5, kDT5, bin_reach(0.02)) ||
+                    near_any_wave(d, cand, w.bdir_pt3, w.boff_pt3, kDT5, bin_reach(0.02));
+    if (lane_id() == 0) w.f_t5[t] = (cand && !nr) ? 1 : 0;
   }
 }
 __global__ void k_tc_dirs_t5(const Ws *__restrict__ wb) {
@@ -1071,15 +1101,14 @@ __global__ void k_tc_dirs_t5(const Ws *__restrict__ wb) {
 // pLS TCs: surviving pLS used by no TC and not near any TC.
 __global__ void k_tc_pls(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
-    int f = 0;
-    if (w.pls_keep[s] && !w.seed_used[s]) {
-      const Dir d = dir_of_seed(w, s);
-      f = (near_any(d, w.bdir_pt5, w.boff_pt5, kDpLS, bin_reach(0.05)) ||
-           near_any(d, w.bdir_pt3, w.boff_pt3, kDpLS, bin_reach(0.05)) ||
-           near_any(d, w.bdir_t5, w.boff_t5, kDpLS, bin_reach(0.05))) ? 0 : 1;
-    }
-    w.f_pls[s] = f;
+  const int nw = gridDim.x * kWaves;
+  for (int s = blockIdx.x * kWaves + (threadIdx.x >> 6); s < w.n_seeds; s += nw) {
+    const bool cand = w.pls_keep[s] && !w.seed_used[s];
+    const Dir d = dir_of_seed(w, s);
+    const bool nr = near_any_wave(d, cand, w.bdir_pt5, w.boff_pt5, kDpLS, bin_reach(0.05)) ||
+                    near_any_wave(d, cand, w.bdir_pt3, w.boff_pt3, kDpLS, bin_reach(0.05)) ||
+                    near_any_wave(d, cand, w.bdir_t5, w.boff_t5, kDpLS, bin_reach(0.05));
+    if (lane_id() == 0) w.f_pls[s] = (cand && !nr) ? 1 : 0;
   }
 }
 
@@ -1142,7 +1171,7 @@ const char *const kSiteNames[] = {
     "t3_count", "t3_scan", "t3_fill", "t5_count", "t5_scan", "t5_fill",
     "t5_inc_count", "t5_inc_scan", "t5_inc_scatter", "t5_dedup",
     "pls", "pls_hit_scan", "pls_hit_scatter", "pls_dedup",
-    "pt3_count", "pt3_scan", "pt3_fill", "pt5_count", "pt5_scan", "pt5_fill",
+    "pt3_bin", "pt3_count", "pt3_scan", "pt3_fill", "pt5_bin", "pt5_count", "pt5_scan", "pt5_fill",
     "pt_obj_count", "pt_obj_scan", "pt_obj_scatter", "pt3_dedup", "pt5_dedup",
     "tc_pt5", "tc_pt5_scan", "tc_pt5_dirs", "tc_pt3", "tc_pt3_scan", "tc_pt3_dirs",
     "tc_t5", "tc_t5_scan", "tc_t5_dirs", "tc_pls", "tc_pls_scan", "tc_write"};
@@ -1210,8 +1239,8 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
     k_obj_bin_count<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb);
     scan(wb, B, SC_B3, kObjBins, st);
     k_obj_bin_scatter<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb);
-    k_pt_binned<3, false><<<seedwaves, kBlock, 0, st>>>(wb, g);
   });
+  run([&] { if (seeds) k_pt_binned<3, false><<<seedwaves, kBlock, 0, st>>>(wb, g); });
   run([&] { if (seeds) scan(wb, B, SC_PT3, S, st); });
   run([&] { if (seeds) k_pt_binned<3, true><<<seedwaves, kBlock, 0, st>>>(wb, g); });
   run([&] {
@@ -1219,8 +1248,8 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
     k_obj_bin_count<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
     scan(wb, B, SC_B5, kObjBins, st);
     k_obj_bin_scatter<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
-    k_pt_binned<5, false><<<seedwaves, kBlock, 0, st>>>(wb, g);
   });
+  run([&] { if (seeds) k_pt_binned<5, false><<<seedwaves, kBlock, 0, st>>>(wb, g); });
   run([&] { if (seeds) scan(wb, B, SC_PT5, S, st); });
   run([&] { if (seeds) k_pt_binned<5, true><<<seedwaves, kBlock, 0, st>>>(wb, g); });
   run([&] {
@@ -1253,19 +1282,19 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
     k_tc_dirs_pt5<<<grid(b.cap_pt5), kBlock, 0, st>>>(wb);
     k_bin_dirs<<<one, 1024, 0, st>>>(wb, 0);
   });
-  run([&] { k_tc_pt3<<<grid(b.cap_pt3), kBlock, 0, st>>>(wb); });
+  run([&] { k_tc_pt3<<<gridw(b.cap_pt3), kBlock, 0, st>>>(wb); });
   run([&] { scan(wb, B, SC_F3, b.cap_pt3, st); });
   run([&] {
     k_tc_dirs_pt3<<<grid(b.cap_pt3), kBlock, 0, st>>>(wb);
     k_bin_dirs<<<one, 1024, 0, st>>>(wb, 1);
   });
-  run([&] { k_tc_t5<<<grid(b.cap_t5), kBlock, 0, st>>>(wb); });
+  run([&] { k_tc_t5<<<gridw(b.cap_t5), kBlock, 0, st>>>(wb); });
   run([&] { scan(wb, B, SC_FT5, b.cap_t5, st); });
   run([&] {
     k_tc_dirs_t5<<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
     k_bin_dirs<<<one, 1024, 0, st>>>(wb, 2);
   });
-  run([&] { if (seeds) k_tc_pls<<<grid(S), kBlock, 0, st>>>(wb); });
+  run([&] { if (seeds) k_tc_pls<<<gridw(S), kBlock, 0, st>>>(wb); });
   run([&] { if (seeds) scan(wb, B, SC_FPLS, S, st); });
   run([&] { k_tc_write<<<grid(b.cap_tc), kBlock, 0, st>>>(wb); });
 }

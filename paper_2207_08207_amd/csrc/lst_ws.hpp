@@ -71,6 +71,7 @@ struct Ws {
   float2 *md_stub;  // tangential displacement, sensor separation
   // segments
   int *ls_cnt, *ls_off;
+  int *ls_cache;    // per MD: up to 16 passing partners found by the count pass
   int2 *ls_md;
   float2 *ls_beta;
   // triplets
