@@ -8,9 +8,15 @@ into track candidates), inputs already resident in HBM.  Forms measured:
 * served (the headline `value`): the library's serving loop (streams x
   batches) with K PU200-like seeded events available at once;
 * plain: synchronous lst_build_event per event, one at a time;
+* e2e: plain, but from pinned host arrays: host-to-device copy, the chain,
+  and the track candidates copied back (the PCIe-inclusive rate);
 * trace: an open-loop Poisson trace (500 events/s, pile-up U[50, 250])
-  through the server and through the plain FIFO path (1 stream, batch 1);
+  through the server and through the plain FIFO path (1 stream, batch 1),
+  plus a sweep of offered rates;
 * batched: a captured hipGraph plan over B slots (pile-up U[140, 250]).
+
+The CPU baseline runs the serial C oracle on one event per host core, all
+cores at once.
 
 Prints one JSON line.
 
@@ -44,14 +50,17 @@ def parse():
     p.add_argument("--max-batch", type=int, default=16, help="events per server launch sequence")
     p.add_argument("--rate", type=float, default=500.0, help="Poisson arrival rate of the trace [events/s]")
     p.add_argument("--trace", type=int, default=1000, help="requests in the open-loop trace (0: skip)")
-    p.add_argument("--batch", type=int, default=32, help="slots of the captured batched plan (0: skip)")
-    p.add_argument("--forms", default="plain,served,trace,batched,copy",
+    p.add_argument("--sweep", default="100,200,500,1000,2000",
+                   help="offered rates of the served-vs-plain rate sweep [events/s] (empty: skip)")
+    p.add_argument("--batch", type=int, default=64, help="slots of the captured batched plan (0: skip)")
+    p.add_argument("--forms", default="plain,e2e,served,trace,batched,copy",
                    help="comma list of forms to run (served is the headline and always runs)")
     p.add_argument("--site", default=None,
                    help="launch site to time for the roofline (default: the largest in a per-site calibration)")
     p.add_argument("--workload", default="pu200_seeded", choices=sorted(WORKLOAD))
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    p.add_argument("--cpu-events", type=int, default=1, help="events in the CPU-baseline sample")
+    p.add_argument("--cpu-workers", type=int, default=0,
+                   help="oracle processes run side by side for the CPU baseline (0: the host's cores, at most 16)")
     return p.parse_args()
 
 
@@ -123,6 +132,50 @@ def run_trace(lst, g, dev, n_streams, max_batch, pool_bytes, arrivals, ids):
         raise RuntimeError(f"served requests failed with statuses {sorted(set(bad))}")
     span = max(done) - first_arr
     return lat, len(arrivals) / span
+
+
+def _oracle_worker(workload, ev, start, out):
+    """One CPU-baseline process: build the oracle's geometry, wait for the start signal, run one event."""
+    try:
+        import oracle
+        from lstgen.events import geometry_for
+        og = oracle.OracleGeometry(geometry_for(workload))
+        out.put(("ready", 0.0))
+        start.wait()
+        t = time.perf_counter()
+        oracle.run(og, ev)
+        out.put(("done", time.perf_counter() - t))
+    except BaseException as e:  # report instead of leaving the parent waiting
+        out.put(("error", repr(e)))
+
+
+def cpu_baseline(workload, events, n_workers):
+    """Oracle throughput on the host: n_workers processes, one event each, started together."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    start, out = ctx.Event(), ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker, args=(workload, events[i % len(events)], start, out))
+             for i in range(n_workers)]
+    for p in procs:
+        p.start()
+    def get(what):
+        m = out.get(timeout=600)
+        if m[0] != what:
+            start.set()
+            raise RuntimeError(f"oracle worker: {m}")
+        return m[1]
+
+    for _ in procs:
+        get("ready")
+    t0 = time.perf_counter()
+    start.set()
+    per_event = [get("done") for _ in procs]
+    wall = time.perf_counter() - t0
+    for p in procs:
+        p.join()
+        if p.exitcode != 0:
+            raise RuntimeError(f"oracle worker exited with {p.exitcode}")
+    return n_workers / wall, wall, sorted(per_event)
 
 
 def main():
@@ -205,6 +258,36 @@ def main():
                  "events": n_plain}
         log(f"bench: plain {plain}")
 
+    # ---- end to end from pinned host memory: H2D, the chain, track candidates to the host
+    e2e = None
+    if "e2e" in forms:
+        keys = ("x", "y", "z", "module", "sensor", "px", "py", "pz", "q", "hits4")
+        pinned = [{k: pool[i][k].cpu().pin_memory() for k in keys} for i in range(len(pool))]
+
+        def e2e_step(i):
+            h = {k: v.to(dev, non_blocking=True) for k, v in pinned[i % len(pinned)].items()}
+            st, ev = lst.lst_build_event(g.handle, h, ws, cap, stream)
+            if st != lst.LST_OK:
+                raise lst.LSTError(st, lst.lst_last_error())
+            tc = lst.lst_get_track_candidates(ev)
+            lst.lst_release_event(ev)
+            return tc
+
+        for i in range(args.warmup):
+            e2e_step(i)
+        torch.cuda.synchronize()
+        lat, n_e2e = [], max(8, min(args.steps, 32))
+        t0 = time.perf_counter()
+        for i in range(n_e2e):
+            s0 = time.perf_counter()
+            e2e_step(args.warmup + i)
+            lat.append((time.perf_counter() - s0) * 1e3)
+        el = time.perf_counter() - t0
+        e2e = {"events_per_s": round(n_e2e / el, 3), "latency_ms": percentiles(lat), "events": n_e2e,
+               "boundary": "pinned host hits+seeds -> H2D -> chain -> track candidates on the host"}
+        del pinned
+        log(f"bench: e2e {e2e}")
+
     # ---- served at saturation (the headline): every request available at once; the dominant
     # launch site of every batched launch sequence is bracketed by HIP events on its stream
     n_streams, max_batch = args.streams, args.max_batch
@@ -257,6 +340,19 @@ def main():
                  "served": {"events_per_s": round(rate_s, 2), "latency_ms": percentiles(lat_s)},
                  "plain_fifo": {"events_per_s": round(rate_p, 2), "latency_ms": percentiles(lat_p)}}
         log(f"bench: trace {trace}")
+        sweep = []
+        for rate in [float(r) for r in args.sweep.split(",") if r.strip()]:
+            n = int(min(args.trace, max(200, 2 * rate)))  # about two seconds of arrivals, at least 200
+            arr = np.cumsum(rng.exponential(1.0 / rate, n))
+            sid = rng.integers(0, len(spool), n)
+            ls_, rs_ = run_trace(lst, g, spool, n_streams, max_batch,
+                                 int(s_one * (n_streams * max_batch + 2)), arr, sid)
+            lp_, rp_ = run_trace(lst, g, spool, 1, 1, int(s_one * 3), arr, sid)
+            sweep.append({"rate_offered": rate, "requests": n,
+                          "served": {"events_per_s": round(rs_, 2), **percentiles(ls_)},
+                          "plain_fifo": {"events_per_s": round(rp_, 2), **percentiles(lp_)}})
+            log(f"bench: sweep {sweep[-1]}")
+        trace["sweep_latency_ms"] = sweep
 
     # ---- batched: captured plan over B slots (pile-up U[140, 250]), graph replays
     batched = None
@@ -323,20 +419,23 @@ def main():
                    "form": f"served: {n_streams} streams x batches of {max_batch}, all requests available",
                    "step": "one event through the whole chain"},
         "latency_ms": percentiles(served_lat),
-        "plain": plain, "trace": trace, "batched": batched, "copy": copy,
+        "plain": plain, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
         "roofline": roof,
     }
     if not args.no_cpu:
-        import oracle
-        og = oracle.OracleGeometry(geom)
-        t = time.perf_counter()
-        for i in range(args.cpu_events):
-            oracle.run(og, host[i])
-        cpu_s = time.perf_counter() - t
-        out["cpu_baseline"] = {"value": round(args.cpu_events / cpu_s, 4), "unit": "events/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"{args.cpu_events} {args.workload} event(s) (seed 3000..), full chain, "
-                                         f"serial FP32 C oracle, {cpu_s:.1f} s"}
+        n_work = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        rate, wall, per_event = cpu_baseline(args.workload, host, n_work)
+        model = "unknown CPU"
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next(l.split(":", 1)[1].strip() for l in fh if l.startswith("model name"))
+        except (OSError, StopIteration):
+            pass
+        out["cpu_baseline"] = {"value": round(rate, 4), "unit": "events/s", "cores": n_work, "kind": "oracle",
+                               "sample": f"{n_work} {args.workload} events (the first {min(n_work, len(host))} "
+                                         f"of the pool, cycled), one per process, all at once: serial FP32 C "
+                                         f"oracle, full chain, {wall:.1f} s wall; per event "
+                                         f"{per_event[len(per_event) // 2]:.2f} s median; {model}"}
     print(json.dumps(out), flush=True)
 
 

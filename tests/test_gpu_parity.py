@@ -6,6 +6,7 @@ import oracle
 from lstgen import make_event, make_single_track_event
 from lstgen.events import Event, make_tiny_event
 
+from oracle_pool import oracle_many
 from parity import compare_event, compare_tc
 
 pytestmark = pytest.mark.gpu
@@ -44,7 +45,7 @@ def test_module_windows_bit_exact(gbarrel, gfull, obarrel, ofull):
         assert np.array_equal(a.view(np.int32), b.view(np.int32))
 
 
-@pytest.mark.parametrize("ev_no", range(5))
+@pytest.mark.parametrize("ev_no", range(10))
 def test_parity_tiny(ev_no, lst, gbarrel, obarrel):
     ev = make_event("tiny", ev_no)
     r = _run(lst, gbarrel, ev)
@@ -78,6 +79,40 @@ def test_parity_pu200_seeded_full_event(lst, gfull, ofull):
     n = compare_tc(r, o)
     print("[gpu] pu200_seeded#0", stats, "TC", n, flush=True)
     assert stats["T5"]["oracle"] > 1000 and n > 1000
+
+
+# Many full-size events: the oracle runs them in parallel processes once per module.
+MANY = [("pu200_seeded", k) for k in range(1, 21)] + [("pu200", k) for k in range(2, 22)]
+BATCH = [("batch", k) for k in range(8)]
+
+
+@pytest.fixture(scope="module")
+def many_oracle():
+    print(f"[cpu] oracle on {len(MANY) + len(BATCH)} full-size events in parallel", flush=True)
+    return dict(zip(MANY + BATCH, oracle_many(MANY + BATCH)))
+
+
+@pytest.mark.parametrize("spec", MANY, ids=[f"{c}-{k}" for c, k in MANY])
+def test_parity_many_events(spec, lst, gfull, many_oracle):
+    """Twenty seeded and twenty unseeded PU200-like events, every stage and the track candidates."""
+    ev, o = many_oracle[spec]
+    r = _run(lst, gfull, ev)
+    compare_event(r, o)
+    assert compare_tc(r, o) > 1000
+
+
+def test_parity_batch_plan_events(lst, gfull, many_oracle):
+    """Eight pile-up U[140, 250] events in one captured plan, each against the oracle."""
+    evs = [many_oracle[s][0] for s in BATCH]
+    dev = [lst.upload_event(e) for e in evs]
+    print(f"[gpu] plan of {len(evs)} batch events: hits {[e.n_hits for e in evs]}", flush=True)
+    plan = lst.Plan(gfull, len(evs), max(e.n_hits for e in evs), max(e.n_seeds for e in evs))
+    for r, s in zip(plan.run(dev), BATCH):
+        o = many_oracle[s][1]
+        compare_event(r, o)
+        compare_tc(r, o)
+        r.close()
+    plan.close()
 
 
 def test_parity_pu200_unseeded(lst, gfull, ofull):
