@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+LAUNCH_SHAPES = os.path.join(ROOT, "paper_2207_08207_amd", "launch_shapes_mi355x.json")
 WORKLOAD = {
     "pu200_seeded": ("PU200-like synthetic event with pixel seeds: 6 barrel layers (|z|<120 cm) + 2x5 endcap "
                      "disks of 10x5 cm bi-layer pT modules (19,262 modules), 8,000 helices pT 0.8-50 GeV "
@@ -59,6 +60,11 @@ def parse():
                    help="launch site to time for the roofline (default: the largest in a per-site calibration)")
     p.add_argument("--workload", default="pu200_seeded", choices=sorted(WORKLOAD))
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--launch-config", default=LAUNCH_SHAPES,
+                   help="JSON launch shapes to load (the packaged MI355X tuning; 'none' for the defaults)")
+    p.add_argument("--tune", type=int, default=0,
+                   help="autotune the launch shapes on this many pool events before any form (0: load instead)")
+    p.add_argument("--save-launch-config", default=None, help="write the launch shapes used to this JSON file")
     p.add_argument("--cpu-workers", type=int, default=0,
                    help="oracle processes run side by side for the CPU baseline (0: the host's cores, at most 16)")
     return p.parse_args()
@@ -218,6 +224,19 @@ def main():
         lst.lst_release_event(h)
         return counts, t
 
+    # ---- launch shapes: autotuned on a batch of pool events, or loaded; used by every form
+    tuned = None
+    if args.tune > 0:
+        t0 = time.perf_counter()
+        res = g.autotune(pool[:min(args.tune, len(pool))], reps=2)
+        tuned = {k: v[0] for k, v in res.items()}
+        log(f"bench: autotuned in {time.perf_counter() - t0:.1f} s: {tuned}")
+    elif args.launch_config != "none" and os.path.exists(args.launch_config):
+        g.load_launch_config(args.launch_config)
+        tuned = g.launch_config()
+        log(f"bench: launch shapes from {args.launch_config}: {tuned}")
+    if args.save_launch_config:
+        g.save_launch_config(args.save_launch_config)
     forms = set(args.forms.split(","))
     sites = lst.lst_kernel_sites()
     if args.site is not None:
@@ -360,21 +379,33 @@ def main():
         bpool = [lst.upload_event(make_event("batch", i), dev) for i in range(min(args.pool, args.batch))]
         bmax = max(int(t["x"].numel()) for t in bpool)
         bseed = max(int(t["px"].numel()) for t in bpool)
-        plan = lst.Plan(g, args.batch, bmax, bseed)
         evs = [bpool[i % len(bpool)] for i in range(args.batch)]
-        for r in plan.run(evs):
-            r.close()
-        torch.cuda.synchronize()
         reps = max(2, args.steps // args.batch)
-        t0 = time.perf_counter()
-        for _ in range(reps):
+
+        def time_plan():
+            plan = lst.Plan(g, args.batch, bmax, bseed)  # captured with the geometry's launch shapes
             for r in plan.run(evs):
                 r.close()
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        plan.close()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                for r in plan.run(evs):
+                    r.close()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            plan.close()
+            del plan
+            return el
+
+        el = time_plan()
         batched = {"events_per_s": round(reps * args.batch / el, 2), "events_per_launch": args.batch,
-                   "ms_per_launch": round(el / reps * 1e3, 3), "pileup": "U[140,250]", "form": "hipGraph replay"}
+                   "ms_per_launch": round(el / reps * 1e3, 3), "pileup": "U[140,250]", "form": "hipGraph replay",
+                   "launch_shapes": "tuned" if tuned else "default"}
+        if tuned:
+            g.set_launch_config({})
+            el_d = time_plan()
+            g.set_launch_config(tuned)
+            batched["default_shapes_events_per_s"] = round(reps * args.batch / el_d, 2)
         log(f"bench: batched {batched}")
 
     # ---- device-to-device copy of a known size: achievable HBM bandwidth, and the reference
@@ -419,7 +450,7 @@ def main():
                    "form": f"served: {n_streams} streams x batches of {max_batch}, all requests available",
                    "step": "one event through the whole chain"},
         "latency_ms": percentiles(served_lat),
-        "plain": plain, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
+        "launch_shapes": tuned, "plain": plain, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
         "roofline": roof,
     }
     if not args.no_cpu:

@@ -242,6 +242,28 @@ const char *lst_kernel_site_name(int32_t site);
 lst_status lst_set_timed_site(int32_t site);
 lst_status lst_get_site_time(lst_event ev, float *ms);
 
+/* Launch shapes and autotuning.  Some launch sites (the segment, triplet,
+ * quintuplet, pixel-seed and cleaning searches) accept a block of 64, 128 or
+ * 256 threads; the geometry holds one choice per site and every later
+ * enqueue, batch, plan capture and server launch on that geometry uses it.
+ * Results do not depend on the choice.  Arrays have lst_kernel_site_count()
+ * entries, indexed by launch site.
+ *  lst_get_launch_config: threads per block of each tunable site, 0 for the
+ *    sites with a fixed shape.
+ *  lst_set_launch_config: 0 (default, 256), 64, 128 or 256 for a tunable site,
+ *    0 for the others; LST_E_INVALID otherwise (nothing is changed).
+ *  lst_autotune: runs the caller's B events (device descriptors, as
+ *    lst_enqueue_batch, in `workspace` of lst_batch_workspace_bytes() bytes)
+ *    reps times per choice of each tunable site in turn, timing that site with
+ *    HIP events on `stream`, keeps the fastest choice per site and returns in
+ *    site_ms (optional) the best time of each tuned site (-1 for the others).
+ *    It waits for the device; on any error the previous shapes are restored.
+ *    Not to be called while other calls use the same geometry. */
+lst_status lst_get_launch_config(lst_geometry geom, int32_t n, int32_t *site_block);
+lst_status lst_set_launch_config(lst_geometry geom, int32_t n, const int32_t *site_block);
+lst_status lst_autotune(lst_geometry geom, int32_t B, const lst_event_desc *evs, const lst_capacity *cap,
+                        void *workspace, size_t ws_bytes, void *stream, int32_t reps, float *site_ms);
+
 lst_status lst_release_event(lst_event ev);
 const char *lst_last_error(void);
 

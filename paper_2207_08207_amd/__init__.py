@@ -29,7 +29,7 @@ EXPORTED = ["lst_load_geometry", "lst_release_geometry", "lst_default_capacity",
             "lst_kernel_site_name", "lst_set_timed_site", "lst_get_site_time", "lst_batch_workspace_bytes",
             "lst_enqueue_batch", "lst_plan_workspace_bytes", "lst_plan_create", "lst_plan_run", "lst_plan_release",
             "lst_server_create", "lst_server_now", "lst_server_submit", "lst_server_poll", "lst_server_pending",
-            "lst_server_destroy"]
+            "lst_server_destroy", "lst_get_launch_config", "lst_set_launch_config", "lst_autotune"]
 
 
 class LSTError(RuntimeError):
@@ -111,6 +111,9 @@ def load_library(path=LIB_PATH):
         "lst_server_poll": [vp, vp, i32, P(i32)],
         "lst_server_pending": [vp, P(i32), P(i32)],
         "lst_server_destroy": [vp],
+        "lst_get_launch_config": [vp, i32, vp],
+        "lst_set_launch_config": [vp, i32, vp],
+        "lst_autotune": [vp, i32, vp, vp, vp, sz, vp, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -260,6 +263,33 @@ def lst_get_site_time(ev):
     return float(ms.value)
 
 
+def lst_get_launch_config(geom):
+    """Threads per block of every launch site (0: fixed shape), as a list indexed by site."""
+    lib = load_library()
+    n = lib.lst_kernel_site_count()
+    a = np.zeros(n, np.int32)
+    _check(lib.lst_get_launch_config(geom, n, _ptr(a)))
+    return [int(v) for v in a]
+
+
+def lst_set_launch_config(geom, site_block):
+    a = np.ascontiguousarray(site_block, np.int32)
+    _check(load_library().lst_set_launch_config(geom, int(a.size), _ptr(a)))
+
+
+def lst_autotune(geom, dev_events, workspace, caps=None, stream=None, reps=2):
+    """Tunes the launch shapes on these events; returns the best time [ms] per launch site (-1: not tuned)."""
+    lib = load_library()
+    B = len(dev_events)
+    descs = (lst_event_desc * B)(*[_event_desc(t) for t in dev_events])
+    ca = _caps_array(caps)
+    ms = np.zeros(lib.lst_kernel_site_count(), np.float32)
+    _check(lib.lst_autotune(geom, B, ctypes.cast(descs, ctypes.c_void_p),
+                            ctypes.cast(ca, ctypes.c_void_p) if ca is not None else None, _ptr(workspace),
+                            int(workspace.numel()), stream, int(reps), _ptr(ms)))
+    return ms
+
+
 def _caps_array(caps):
     if caps is None:
         return None
@@ -369,6 +399,42 @@ class Geometry:
 
     def module_constants(self):
         return lst_get_module_constants(self.handle, self.n_modules)
+
+    def launch_config(self):
+        """{site name: threads per block} of the tunable launch sites."""
+        return {n: b for n, b in zip(lst_kernel_sites(), lst_get_launch_config(self.handle)) if b}
+
+    def set_launch_config(self, cfg):
+        """Sets the launch shapes from {site name: threads per block} (other sites: default)."""
+        names = lst_kernel_sites()
+        unknown = set(cfg) - set(names)
+        if unknown:
+            raise LSTError(LST_E_INVALID, f"unknown launch sites {sorted(unknown)}")
+        lst_set_launch_config(self.handle, [int(cfg.get(n, 0)) for n in names])
+
+    def autotune(self, dev_events, reps=2, caps=None, stream=None):
+        """Chooses the fastest launch shape per tunable site on these device events (one batch)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        nh = [int(t["x"].numel()) for t in dev_events]
+        ns = [int(t["px"].numel()) for t in dev_events]
+        ws = torch.empty(lst_batch_workspace_bytes(self.handle, nh, ns, caps), dtype=torch.uint8,
+                         device=dev_events[0]["x"].device)
+        ms = lst_autotune(self.handle, dev_events, ws, caps, stream, reps)
+        del ws
+        names = lst_kernel_sites()
+        return {names[k]: (b, float(ms[k])) for k, b in enumerate(lst_get_launch_config(self.handle)) if b}
+
+    def save_launch_config(self, path):
+        import json
+        with open(path, "w") as fh:
+            json.dump(self.launch_config(), fh, indent=1, sort_keys=True)
+
+    def load_launch_config(self, path):
+        import json
+        with open(path) as fh:
+            self.set_launch_config(json.load(fh))
 
     def close(self):
         if self.handle:

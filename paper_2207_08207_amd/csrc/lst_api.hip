@@ -46,6 +46,7 @@ struct lst_geometry_s {
   lst::DevGeom g;
   int *d_off = nullptr, *d_tgt = nullptr, *d_info = nullptr;
   float4 *d_win = nullptr;
+  int site_block[lst::kMaxSites] = {};  // launch shape of each tunable site (0 = default)
 };
 
 // Events enqueued together share one batch: one descriptor array and one
@@ -104,21 +105,22 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.bcnt = I(2 * M + 1); t.boff = I(2 * M + 1); t.bcur = I(2 * M);
   t.hidx_tmp = I(N + 1); t.hidx = I(N + 1); t.hpos = F4(N + 1);
   t.md_cnt = I(M + 1); t.md_off = I(M + 1);
-  t.md_hits = I2(md); t.md_mod = I(md); t.md_pos = F4(md); t.md_stub = F2(md);
+  t.md_hits = I2(md); t.md_mod = I(md); t.md_pos = F4(md); t.md_stub = F2(md); t.mod_disc = F4(M);
   t.ls_cnt = I(md + 1); t.ls_off = I(md + 1); t.ls_md = I2(ls); t.ls_beta = F2(ls);
-  t.ls_cache = I(16 * md);
+  t.ls_cache = I(kLsCache * md);
   t.t3_cnt = I(ls + 1); t.t3_off = I(ls + 1); t.t3_md = I4(t3); t.t3_attr = F4(t3); t.t3_first = F2(t3);
   t.t5_cnt = I(t3 + 1); t.t5_off = I(t3 + 1); t.t5_t3 = I2(t5); t.t5_md = I(5 * t5); t.t5_attr = F(8 * t5);
-  t.t5_keep = I(t5); t.t5_first = F2(t5);
+  t.t5_keep = I(t5); t.t5_first = F2(t5); t.t5_cache = I(kT5Cache * t3);
   t.inc_cnt = I(md + 1); t.inc_off = I(md + 1); t.inc_cur = I(md + 1); t.inc_list = I(5 * t5);
   t.pls = F(8 * S); t.pls_keep = I(S);
   t.ph_cnt = I(N + 1); t.ph_off = I(N + 1); t.ph_cur = I(N + 1); t.ph_list = I(4 * S);
   t.pt3_cnt = I(S + 1); t.pt3_off = I(S + 1); t.pt5_cnt = I(S + 1); t.pt5_off = I(S + 1);
+  t.pt3_cache = I(kPtCache * S); t.pt5_cache = I(kPtCache * S);
   t.pt3_so = I2(p3); t.pt5_so = I2(p5); t.pt3_attr = F4(p3); t.pt5_attr = F4(p5);
   t.pt3_keep = I(p3); t.pt5_keep = I(p5);
   t.o3_cnt = I(t3 + 1); t.o3_off = I(t3 + 1); t.o3_cur = I(t3 + 1); t.o3_list = I(p3);
   t.o5_cnt = I(t5 + 1); t.o5_off = I(t5 + 1); t.o5_cur = I(t5 + 1); t.o5_list = I(p5);
-  const long nbins = 2560;  // first-anchor bins of the seed search (10 rings x 256 azimuth bins)
+  const long nbins = kSeedBins;
   t.b3_cnt = I(nbins + 1); t.b3_off = I(nbins + 1); t.b3_cur = I(nbins + 1); t.b3_list = I(t3);
   t.b5_cnt = I(nbins + 1); t.b5_off = I(nbins + 1); t.b5_cur = I(nbins + 1); t.b5_list = I(t5);
   t.seed_used = I(S + 1); t.t5_used = I(t5 + 1);
@@ -382,7 +384,7 @@ static lst_status check_event_desc(const lst_event_desc &ev) {
 // their descriptors and enqueues the chain and the counter read-back on
 // `stream`.  The returned batch holds one reference per event.
 static lst_status enqueue_batch_at(lst_geometry g, int B, const lst_event_desc *evs, const std::vector<lst::Caps> &caps,
-                                   char *base, hipStream_t stream, lst_batch_s **out) {
+                                   char *base, hipStream_t stream, lst_batch_s **out, int timed_site = -2) {
   *out = nullptr;
   auto *b = new (std::nothrow) lst_batch_s();
   if (!b) return fail(LST_E_NOMEM, "host allocation failed");
@@ -420,14 +422,14 @@ static lst_status enqueue_batch_at(lst_geometry g, int B, const lst_event_desc *
     bound.cap_tc = std::max(bound.cap_tc, w.cap_tc);
   }
   lst::KernelTimer kt{-1, nullptr, nullptr};
-  const int site = g_timed_site.load();
+  const int site = timed_site >= -1 ? timed_site : g_timed_site.load();
   if (site >= 0 && hipEventCreate(&b->tbeg) == hipSuccess && hipEventCreate(&b->tend) == hipSuccess) {
     kt = lst::KernelTimer{site, b->tbeg, b->tend};
     b->timed_site = site;
   }
   hipError_t he = hipMemcpyAsync(d_ws, b->h_ws, sizeof(lst::Ws) * B, hipMemcpyHostToDevice, stream);
   if (he == hipSuccess) {
-    lst::enqueue_chain(g->g, d_ws, B, bound, stream, b->timed_site >= 0 ? &kt : nullptr);
+    lst::enqueue_chain(g->g, d_ws, B, bound, stream, b->timed_site >= 0 ? &kt : nullptr, g->site_block);
     he = hipGetLastError();
   }
   if (he == hipSuccess)
@@ -716,7 +718,7 @@ lst_status lst_plan_create(lst_geometry g, int32_t B, int32_t max_hits, int32_t 
   hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    lst::enqueue_chain(g->g, d_ws, B, bound, cs, nullptr);
+    lst::enqueue_chain(g->g, d_ws, B, bound, cs, nullptr, g->site_block);
     hipError_t le = hipGetLastError();
     e = hipStreamEndCapture(cs, &p->graph);
     if (e == hipSuccess) e = le;
@@ -1073,6 +1075,97 @@ lst_status lst_server_destroy(lst_server s) {
   }
   for (auto st : s->streams) drop(hipStreamDestroy(st));
   delete s;
+  return LST_OK;
+}
+
+// ---------------------------------------------------------------- launch shapes
+lst_status lst_get_launch_config(lst_geometry g, int32_t n, int32_t *site_block) {
+  if (!g || !site_block || n < lst::kNumSites) return fail(LST_E_INVALID, "lst_get_launch_config: bad argument");
+  for (int s = 0; s < lst::kNumSites; ++s)
+    site_block[s] = lst::site_tunable(s) ? (g->site_block[s] > 0 ? g->site_block[s] : 256) : 0;
+  return LST_OK;
+}
+
+static bool valid_block(int s, int b) {
+  return lst::site_tunable(s) ? (b == 0 || b == 64 || b == 128 || b == 256) : b == 0;
+}
+
+lst_status lst_set_launch_config(lst_geometry g, int32_t n, const int32_t *site_block) {
+  if (!g || !site_block || n != lst::kNumSites) return fail(LST_E_INVALID, "lst_set_launch_config: bad argument");
+  for (int s = 0; s < n; ++s)
+    if (!valid_block(s, site_block[s]))
+      return fail(LST_E_INVALID, std::string("lst_set_launch_config: site ") + lst::kSiteNames[s] +
+                                     " takes 0 (default)" + (lst::site_tunable(s) ? ", 64, 128 or 256" : " only"));
+  for (int s = 0; s < n; ++s) g->site_block[s] = site_block[s];
+  return LST_OK;
+}
+
+lst_status lst_autotune(lst_geometry g, int32_t B, const lst_event_desc *evs, const lst_capacity *cap, void *workspace,
+                        size_t ws_bytes, void *stream, int32_t reps, float *site_ms) {
+  if (!g || !evs || !workspace || B < 1 || B > 65535 || reps < 1 || reps > 100)
+    return fail(LST_E_INVALID, "lst_autotune: bad argument");
+  std::vector<int32_t> nh(B), ns(B);
+  for (int i = 0; i < B; ++i) {
+    lst_status s = check_event_desc(evs[i]);
+    if (s != LST_OK) return s;
+    nh[i] = evs[i].n_hits;
+    ns[i] = evs[i].n_seeds;
+  }
+  std::vector<lst::Caps> caps;
+  lst_status s = resolve_caps(B, nh.data(), ns.data(), cap, caps);
+  if (s != LST_OK) return s;
+  if (ws_bytes < batch_bytes(g->g.n_mod, B, nh.data(), ns.data(), caps))
+    return fail(LST_E_NOMEM, "lst_autotune: workspace too small (see lst_batch_workspace_bytes)");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return fail(LST_E_INVALID, "workspace not 256-byte aligned");
+  if (site_ms)
+    for (int k = 0; k < lst::kNumSites; ++k) site_ms[k] = -1.0f;
+  int saved[lst::kMaxSites];
+  std::copy(g->site_block, g->site_block + lst::kMaxSites, saved);
+  auto restore = [&](lst_status st) {
+    std::copy(saved, saved + lst::kMaxSites, g->site_block);
+    return st;
+  };
+  // one timed batch with the current launch shapes: the site's launch time, or an error
+  auto time_site = [&](int site, float *ms) -> lst_status {
+    lst_batch_s *b = nullptr;
+    lst_status es = enqueue_batch_at(g, B, evs, caps, reinterpret_cast<char *>(workspace),
+                                     reinterpret_cast<hipStream_t>(stream), &b, site);
+    if (!b) return es;
+    lst_status rs = es;
+    if (rs == LST_OK) {
+      hipError_t e = hipEventSynchronize(b->done);
+      if (e == hipSuccess) {
+        b->synced = true;
+        e = hipEventElapsedTime(ms, b->tbeg, b->tend);
+      }
+      if (e != hipSuccess) rs = fail(LST_E_DEVICE, std::string("lst_autotune: ") + hipGetErrorString(e));
+      for (int i = 0; i < B && rs == LST_OK; ++i) rs = map_status(b->h_ctr[(size_t)i * lst::C_COUNT + lst::C_STATUS]);
+    }
+    for (int i = 0; i < B; ++i) release_batch_ref(b);
+    return rs;
+  };
+  const int choices[3] = {64, 128, 256};
+  for (int site = 0; site < lst::kNumSites; ++site) {
+    if (!lst::site_tunable(site)) continue;
+    float best = 3.0e38f;
+    int best_b = g->site_block[site];
+    for (int c : choices) {
+      g->site_block[site] = c;
+      float tmin = 3.0e38f;
+      for (int r = 0; r < reps; ++r) {
+        float ms = 0.0f;
+        lst_status ts = time_site(site, &ms);
+        if (ts != LST_OK) return restore(ts);
+        tmin = std::min(tmin, ms);
+      }
+      if (tmin < best) {
+        best = tmin;
+        best_b = c;
+      }
+    }
+    g->site_block[site] = best_b;
+    if (site_ms) site_ms[site] = best;
+  }
   return LST_OK;
 }
 

@@ -8,6 +8,8 @@
 // incidence lists, whose consumers are order-independent.  Object counts
 // stay on the device: later kernels read them and stride over them, so the
 // whole chain is enqueued without a host round trip.
+#include <cstring>
+
 #include "lst_select.hpp"
 #include "lst_ws.hpp"
 
@@ -162,15 +164,18 @@ __global__ void k_scan_apply(const Ws *__restrict__ wb, int job) {
 }
 
 // blocks for one wave per item (capped; kernels stride)
-static inline int grid_waves(long n) {
-  long g = (n + kWaves - 1) / kWaves;
+// Blocks for n items, one wave per item (grid_waves) or one thread per item
+// (grid_for), at `block` threads per block; kernels stride over the rest.
+static inline int grid_waves(long n, int block = kBlock) {
+  const int wpb = block / 64;
+  long g = (n + wpb - 1) / wpb;
   if (g < 1) g = 1;
   if (g > 16384) g = 16384;
   return (int)g;
 }
 
-static inline int grid_for(long n) {
-  long g = (n + kBlock - 1) / kBlock;
+static inline int grid_for(long n, int block = kBlock) {
+  long g = (n + block - 1) / block;
   if (g < 1) g = 1;
   if (g > 8192) g = 8192;
   return (int)g;
@@ -312,12 +317,67 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
   if (!FILL) {
     cnt = block_sum(cnt, s_wave);
     if (threadIdx.x == 0) w.md_cnt[m] = cnt;
+  } else {
+    // a disc in x-y around every anchor of this module (the lower hits' bounding box), for
+    // the segment stage's module-level azimuth pre-test
+    float x0 = 3.0e38f, x1 = -3.0e38f, y0 = 3.0e38f, y1 = -3.0e38f;
+    for (int k = threadIdx.x; k < nlo; k += kBlock) {
+      const float4 h = k < kMdStage ? s_lo[k] : w.hpos[lo0 + k];
+      x0 = fminf(x0, h.x); x1 = fmaxf(x1, h.x);
+      y0 = fminf(y0, h.y); y1 = fmaxf(y1, h.y);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      x0 = fminf(x0, __shfl_xor(x0, o, 64)); x1 = fmaxf(x1, __shfl_xor(x1, o, 64));
+      y0 = fminf(y0, __shfl_xor(y0, o, 64)); y1 = fmaxf(y1, __shfl_xor(y1, o, 64));
+    }
+    __shared__ float4 s_box[kWaves];
+    const int wv = threadIdx.x >> 6;
+    if (lane_id() == 0) s_box[wv] = make_float4(x0, x1, y0, y1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int k = 1; k < kWaves; ++k) {
+        x0 = fminf(x0, s_box[k].x); x1 = fmaxf(x1, s_box[k].y);
+        y0 = fminf(y0, s_box[k].z); y1 = fmaxf(y1, s_box[k].w);
+      }
+      const float cx = 0.5f * (x0 + x1), cy = 0.5f * (y0 + y1);
+      const float hx = 0.5f * (x1 - x0), hy = 0.5f * (y1 - y0);
+      const float rho = sqrtf(hx * hx + hy * hy) * 1.0001f + 1e-3f;
+      w.mod_disc[m] = make_float4(cx, cy, rho, sqrtf(cx * cx + cy * cy));
+    }
   }
 }
 
 // ------------------------------------------------------------- a2: LS
+// Pre-tests of the segment azimuth window that only save work.  For inner
+// anchor A and a partner module whose anchors lie in an x-y disc (centre C,
+// radius rho; written by the MD fill), every term of ls_pass's window W is at
+// most its value at the largest partner radius r_B <= |C| + rho: the
+// threshold term (ub - ua) / sqrt(1 - ub^2) and the impact-parameter term
+// D0 (1/r_A - 1/r_B) grow with r_B (the latter is below D0 / r_A) and the
+// pitch terms are below (h_A + h_B) / r_A for an outgoing segment.  With the
+// margins below (far above rounding) Wmax >= W, so a candidate failing
+// |A x B| <= Wmax r_A r_B fails ls_pass; and since |A x B| = r_A |n.B| >= r_A
+// (|n.C| - rho) for the unit normal n of A, with r_B <= |C| + rho, a module
+// failing |n.C| - rho <= Wmax (|C| + rho) has no candidate that can pass.
+__device__ __forceinline__ float ls_window_bound(const float4 &A, ModInfo ma, float4 disc, ModInfo mb) {
+  const float ub = kHalfKmax * ((disc.w + disc.z) + mb.er());
+  if (!(ub < 0.99f)) return 3.0e38f;  // no useful bound
+  const float ua = kHalfKmax * (A.w - ma.er());
+  const float w = (ub - ua) / sqrtf(1.0f - ub * ub) + (kD0Max + ma.hphi() + 0.005f) / A.w;
+  return (w * kMargin + kEps) * 1.01f + 1e-6f;
+}
+
+__device__ __forceinline__ bool ls_module_may_pass(const float4 &A, float4 disc, float wmax) {
+  const float dn = fabsf(A.x * disc.y - A.y * disc.x) / A.w;
+  return dn - disc.z <= (wmax * (disc.w + disc.z)) * 1.001f + 1e-4f;
+}
+
+__device__ __forceinline__ bool ls_window_may_pass(const float4 &A, const float4 &B, float wmax) {
+  const float c = A.x * B.y - A.y * B.x;
+  return fabsf(c) <= wmax * (A.w * B.w);
+}
+
 constexpr int kMaxEdges = 256;  // module-map targets per module handled by one wave
-constexpr int kLsCache = 16;    // passing partners per MD remembered between the count and fill passes
 
 // One wave per inner MD a.  Its candidates -- the MDs of every module linked
 // to a's module, edge by edge -- are flattened into one list that the 64
@@ -330,10 +390,12 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
   __shared__ int s_pre[kWaves][kMaxEdges + 1];  // running MD count before each edge
   __shared__ int s_first[kWaves][kMaxEdges];    // first MD of each linked module
   __shared__ int s_info[kWaves][kMaxEdges];
+  __shared__ float s_wmax[kWaves][kMaxEdges];   // window bound of each linked module
   const int n_md = w.ctr[C_NMD];
   const int wv = threadIdx.x >> 6, lane = lane_id();
-  const int waves_total = gridDim.x * kWaves;
-  for (int a = blockIdx.x * kWaves + wv; a < n_md; a += waves_total) {
+  const int wpb = blockDim.x >> 6;  // waves per block (a tuned launch may run fewer than kWaves)
+  const int waves_total = gridDim.x * wpb;
+  for (int a = blockIdx.x * wpb + wv; a < n_md; a += waves_total) {
     const int ma = w.md_mod[a];
     const float4 A = w.md_pos[a];
     const float2 sa = w.md_stub[a];
@@ -362,12 +424,18 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
     for (int k0 = 0; k0 < ne; k0 += 64) {
       const int k = k0 + lane;
       int first = 0, cnt = 0, info = 0;
+      float wm = 0.0f;
       if (k < ne) {
         const int mb = g.map_tgt[e0 + k];
         first = w.md_off[mb];
         const int last = min(w.md_off[mb + 1], n_md);
         cnt = last > first ? last - first : 0;
         info = g.info[mb];
+        if (cnt > 0) {
+          const float4 disc = w.mod_disc[mb];
+          wm = ls_window_bound(A, mia, disc, ModInfo{info});
+          if (!ls_module_may_pass(A, disc, wm)) cnt = 0;
+        }
       }
       int x = cnt;
       for (int o = 1; o < 64; o <<= 1) {
@@ -378,6 +446,7 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
         s_pre[wv][k] = run + x - cnt;
         s_first[wv][k] = first;
         s_info[wv][k] = info;
+        s_wmax[wv][k] = wm;
       }
       run += __shfl(x, 63, 64);
     }
@@ -396,7 +465,9 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
       if (c < total) {
         while (s_pre[wv][e + 1] <= c) ++e;
         b = s_first[wv][e] + (c - s_pre[wv][e]);
-        pass = ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, ModInfo{s_info[wv][e]}, &beta);
+        const float4 Bp = w.md_pos[b];
+        const ModInfo mib{s_info[wv][e]};
+        if (ls_window_may_pass(A, Bp, s_wmax[wv][e])) pass = ls_pass(A, Bp, sa, w.md_stub[b], mia, mib, &beta);
       }
       const unsigned long long m = __ballot(pass);
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -471,7 +542,13 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
     const int t2b = w.t3_off[lsb], t2e = min(w.t3_off[lse], n_t3);
     int out = FILL ? w.t5_off[t1] : 0;
     int cnt = 0;
-    for (int t2 = t2b; t2 < t2e; ++t2) {
+    int *cache = w.t5_cache + (long)t1 * kT5Cache;
+    // fill: the count pass cached the passing partners (in candidate order) unless there were too many
+    const int n_cached = FILL ? w.t5_cnt[t1] : 0;
+    const bool cached = FILL && n_cached <= kT5Cache;
+    const int n_cand = cached ? n_cached : t2e - t2b;
+    for (int i = 0; i < n_cand; ++i) {
+      const int t2 = cached ? cache[i] : t2b + i;
       const int4 cde = w.t3_md[t2];
       P[3] = w.md_pos[cde.y];
       P[4] = w.md_pos[cde.z];
@@ -487,9 +564,11 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
             float *dst = w.t5_attr + 8 * (long)out;
 #pragma unroll
             for (int k = 0; k < 8; ++k) dst[k] = at[k];
+            w.t5_keep[out] = 1;  // until a better duplicate is found
           }
           ++out;
         } else {
+          if (cnt < kT5Cache) cache[cnt] = t2;
           ++cnt;
         }
       }
@@ -538,39 +617,49 @@ __device__ __forceinline__ bool better(float su, const int *hu, float st, const 
 }
 
 // A T5 is dropped when another T5 sharing at least two MDs has a smaller (chi2_xy, hit tuple).
+// One thread per (T5 t, k < 4): the T5s u listed at t's k-th MD that share at
+// least two MDs with t and whose first MD in common with t's first four is
+// that k-th one (so each pair is judged once).  A duplicate shares two of the
+// five MDs, hence one of the first four.  t5_keep starts at 1 (written by the
+// fill) and a strictly better duplicate clears it.
 __global__ void k_t5_dedup(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NT5];
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < 4L * n; i += (long)gridDim.x * blockDim.x) {
+    const int t = (int)(i >> 2), k = (int)(i & 3);
     int mt[5];
 #pragma unroll
-    for (int k = 0; k < 5; ++k) mt[k] = w.t5_md[5 * (long)t + k];
-    int ht[10];
-    t5_hits(w, t, ht);
+    for (int j = 0; j < 5; ++j) mt[j] = w.t5_md[5 * (long)t + j];
+    if (k == 0) w.t5_first[t] = make_float2(w.md_pos[mt[0]].x, w.md_pos[mt[0]].y);
+    const int md = mt[k];
     const float st = w.t5_attr[8 * (long)t + 1];
-    bool keep = true;
-    // a duplicate shares two of the five MDs, hence one of the first four
-    for (int k = 0; k < 4 && keep; ++k) {
-      const int md = mt[k];
-      for (int q = w.inc_off[md]; q < w.inc_off[md + 1] && keep; ++q) {
-        const int u = w.inc_list[q];
-        if (u == t) continue;
-        int shared = 0;
-        const int *mu = w.t5_md + 5 * (long)u;
+    bool have_ht = false;
+    int ht[10];
+    for (int q = w.inc_off[md]; q < w.inc_off[md + 1]; ++q) {
+      const int u = w.inc_list[q];
+      if (u == t) continue;
+      int mu[5];
 #pragma unroll
-        for (int i = 0; i < 5; ++i) {
-          const int v = mu[i];
-          shared += (v == mt[0] || v == mt[1] || v == mt[2] || v == mt[3] || v == mt[4]) ? 1 : 0;
-        }
-        if (shared < 2) continue;
-        int hu[10];
-        t5_hits(w, u, hu);
-        if (better<10>(w.t5_attr[8 * (long)u + 1], hu, st, ht)) keep = false;
+      for (int j = 0; j < 5; ++j) mu[j] = w.t5_md[5 * (long)u + j];
+      int shared = 0, first = 5;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        const bool in = mt[j] == mu[0] || mt[j] == mu[1] || mt[j] == mu[2] || mt[j] == mu[3] || mt[j] == mu[4];
+        shared += in ? 1 : 0;
+        first = (in && first == 5) ? j : first;
+      }
+      if (shared < 2 || first != k) continue;
+      if (!have_ht) {
+        t5_hits(w, t, ht);
+        have_ht = true;
+      }
+      int hu[10];
+      t5_hits(w, u, hu);
+      if (better<10>(w.t5_attr[8 * (long)u + 1], hu, st, ht)) {
+        w.t5_keep[t] = 0;
+        break;
       }
     }
-    w.t5_keep[t] = keep ? 1 : 0;
-    const int a = mt[0];
-    w.t5_first[t] = make_float2(w.md_pos[a].x, w.md_pos[a].y);
   }
 }
 
@@ -662,11 +751,14 @@ __device__ __forceinline__ void load_object(const Ws &w, const DevGeom &g, int t
   }
 }
 
-// ---- binned search: objects grouped by first anchor (radius ring, azimuth bin)
+// ---- binned search: objects grouped by first anchor (radius ring, azimuth bin, z bin)
 constexpr int kRings = 10;
 constexpr float kRing0 = 20.0f, kRingW = 10.0f;      // rings [20, 30), ..., [110, 120) cm, ends clamped
 constexpr int kPhiBins = 256;
-constexpr int kObjBins = kRings * kPhiBins;
+constexpr int kObjBins = kRings * kPhiBins;          // (ring, azimuth) pairs: the bits of a seed's mask
+constexpr int kZBins = 55;
+constexpr float kZHalf = 275.0f, kZW = 10.0f;        // z bins [-275, -265), ..., ends clamped
+static_assert(kObjBins * kZBins == kSeedBins, "seed-search bin count");
 constexpr int kMaskWords = kObjBins / 32;
 constexpr float kSampleStep = 2.0f;                  // trajectory sampling step [cm]
 constexpr int kMaxSamples = 112;                     // 224 cm of arc
@@ -680,32 +772,36 @@ __device__ __forceinline__ int phibin_of(float ph) {
   const int b = (int)floorf((ph + (float)M_PI) * (float)(kPhiBins / (2.0 * M_PI)));
   return b < 0 ? 0 : (b >= kPhiBins ? kPhiBins - 1 : b);
 }
-__device__ __forceinline__ int obj_bin(float2 a) {
+__device__ __forceinline__ int zbin_of(float z) {
+  const int b = (int)floorf((z + kZHalf) / kZW);
+  return b < 0 ? 0 : (b >= kZBins ? kZBins - 1 : b);
+}
+template <int K>
+__device__ __forceinline__ int obj_bin(const Ws &w, int t) {
+  const float4 a = w.md_pos[K == 3 ? w.t3_md[t].x : w.t5_md[5 * (long)t]];
   const float ph = atan2f(a.y, a.x);
-  if (!(ph == ph)) return 0;
-  return ring_of(sqrtf(a.x * a.x + a.y * a.y)) * kPhiBins + phibin_of(ph);
+  const int rp = ph == ph ? ring_of(sqrtf(a.x * a.x + a.y * a.y)) * kPhiBins + phibin_of(ph) : 0;
+  return rp * kZBins + zbin_of(a.z);
 }
 
 template <int K>
 __global__ void k_obj_bin_count(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   const int n = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
-  const float2 *first = K == 3 ? w.t3_first : w.t5_first;
   int *cnt = K == 3 ? w.b3_cnt : w.b5_cnt;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
-    if (K == 3 || w.t5_keep[t]) atomicAdd(&cnt[obj_bin(first[t])], 1);
+    if (K == 3 || w.t5_keep[t]) atomicAdd(&cnt[obj_bin<K>(w, t)], 1);
 }
 template <int K>
 __global__ void k_obj_bin_scatter(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   const int n = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
-  const float2 *first = K == 3 ? w.t3_first : w.t5_first;
   const int *off = K == 3 ? w.b3_off : w.b5_off;
   int *cur = K == 3 ? w.b3_cur : w.b5_cur;
   int *lst = K == 3 ? w.b3_list : w.b5_list;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
     if (K == 3 || w.t5_keep[t]) {
-      const int b = obj_bin(first[t]);
+      const int b = obj_bin<K>(w, t);
       lst[off[b] + atomicAdd(&cur[b], 1)] = t;
     }
 }
@@ -715,7 +811,7 @@ __global__ void k_obj_bin_scatter(const Ws *__restrict__ wb) {
 // 1.01 cm of the seed circle on its forward half-turn (algebraic distance
 // <= 1 cm with |kappa| <= 0.02/cm), hence within d = 1.01 + step/2 + 0.05 cm
 // of a trajectory sample taken every `kSampleStep` of arc.
-__device__ void mark_seed_bins(const Seed &sd, unsigned *mask) {
+__device__ void mark_seed_bins(const Seed &sd, unsigned *mask, int *s_lo, int *s_hi) {
   const int lane = lane_id();
   const float d = 1.01f * kBoxXY + 0.5f * kSampleStep + 0.05f;
   const float bw = (float)(2.0 * M_PI / kPhiBins);
@@ -747,13 +843,31 @@ __device__ void mark_seed_bins(const Seed &sd, unsigned *mask) {
       b1 = (int)floorf((ph + hw + (float)M_PI) / bw) + 1;
       if (b1 - b0 >= kPhiBins) { b0 = 0; b1 = kPhiBins - 1; }
     }
-    for (int rr = r0; rr <= r1; ++rr)
+    for (int rr = r0; rr <= r1; ++rr) {
+      // arc lengths are >= 0, so their float bits order like ints
+      atomicMin(&s_lo[rr], __float_as_int(sarc));
+      atomicMax(&s_hi[rr], __float_as_int(sarc));
       for (int b = b0; b <= b1; ++b) {
         const int bb = ((b % kPhiBins) + kPhiBins) % kPhiBins;
         const int id = rr * kPhiBins + bb;
         atomicOr(&mask[id >> 5], 1u << (id & 31));
       }
+    }
   }
+}
+
+// z bins of ring rr that can hold the first anchor of an object inside the
+// seed's window, from the arc-length range [lo, hi] of the samples that marked
+// the ring: the anchor's arc length from the seed hit (the chord series of
+// pt_pass) is within d + step + 1.5 cm of such a sample's, and its z within
+// the first-anchor z window (3 cm + 2 sigma_z, sigma_z at most
+// max(2.5, 2.5 |lambda| + 0.01) cm) of z0 + lambda s; margins on top.
+__device__ __forceinline__ int2 seed_zbins(const Seed &sd, float lo, float hi) {
+  const float ds = 1.01f * kBoxXY + 1.5f * kSampleStep + 1.6f;
+  const float al = fabsf(sd.lam);
+  const float zw = (kBoxZ0 + 2.0f * fmaxf(2.5f, 2.5f * al + 0.01f)) * 1.01f + 0.1f;
+  const float za = sd.z0 + sd.lam * (lo - ds), zb = sd.z0 + sd.lam * (hi + ds);
+  return make_int2(zbin_of(fminf(za, zb) - zw), zbin_of(fmaxf(za, zb) + zw));
 }
 
 // One wave per seed over the objects of the bins its trajectory can reach.
@@ -764,17 +878,51 @@ __device__ void mark_seed_bins(const Seed &sd, unsigned *mask) {
 template <int K, bool FILL>
 __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb, DevGeom g) {
   __shared__ unsigned s_mask[kWaves][kMaskWords];
+  __shared__ int s_slo[kWaves][kRings], s_shi[kWaves][kRings];
+  __shared__ int2 s_zb[kWaves][kRings];
   __shared__ int s_list[FILL ? kWaves : 1][FILL ? kPassList : 1];
   const Ws &w = wb[blockIdx.y];
   const int wv = threadIdx.x >> 6, lane = lane_id();
-  const int s = blockIdx.x * kWaves + wv;
+  const int s = blockIdx.x * (int)(blockDim.x >> 6) + wv;
   if (s >= w.n_seeds) return;
   const Seed sd = load_seed(w, s);
+  int *cache = (K == 3 ? w.pt3_cache : w.pt5_cache) + (long)s * kPtCache;
+  if constexpr (FILL) {
+    // the count pass cached every passing object of this seed: rank them by index, no search
+    const int expect = (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s];
+    if (expect <= kPtCache) {
+      if (lane < expect) {
+        const int t = cache[lane];
+        int rank = 0;
+        for (int q = 0; q < expect; ++q) rank += cache[q] < t ? 1 : 0;
+        const int pos = (K == 3 ? w.pt3_off : w.pt5_off)[s] + rank;
+        if (pos < (K == 3 ? w.cap_pt3 : w.cap_pt5)) {
+          float4 P[K];
+          ModInfo M[K];
+          float kT, dkT;
+          float4 attr;
+          load_object<K>(w, g, t, P, M, &kT, &dkT);
+          pt_pass<K>(sd, P, M, kT, dkT, &attr);
+          (K == 3 ? w.pt3_so : w.pt5_so)[pos] = make_int2(s, t);
+          (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = attr;
+        }
+      }
+      return;
+    }
+  }
   unsigned *mask = s_mask[wv];
   for (int i = lane; i < kMaskWords; i += 64) mask[i] = 0u;
+  if (lane < kRings) {
+    s_slo[wv][lane] = 0x7f7fffff;  // largest finite float
+    s_shi[wv][lane] = 0;
+  }
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  mark_seed_bins(sd, mask);
+  mark_seed_bins(sd, mask, s_slo[wv], s_shi[wv]);
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane < kRings)
+    s_zb[wv][lane] = seed_zbins(sd, __int_as_float(s_slo[wv][lane]), __int_as_float(s_shi[wv][lane]));
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
   const int *boff = K == 3 ? w.b3_off : w.b5_off;
@@ -792,7 +940,8 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
         const int bit = __builtin_ctz(bits);
         bits &= bits - 1u;
         const int bin = wd * 32 + bit;
-        const int j0 = boff[bin], j1 = boff[bin + 1];
+        const int2 zb = s_zb[wv][bin / kPhiBins];
+        const int j0 = boff[bin * kZBins + zb.x], j1 = boff[bin * kZBins + zb.y + 1];
         for (int j = j0 + lane; j - lane < j1; j += 64) {
           bool pass = false;
           int t = 0;
@@ -809,9 +958,13 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
             }
           }
           const unsigned long long m = __ballot(pass);
-          if (FILL && pass) {
+          if (pass) {
             const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-            if (n_pass + pre < kPassList) s_list[wv][n_pass + pre] = t;
+            if (FILL) {
+              if (n_pass + pre < kPassList) s_list[wv][n_pass + pre] = t;
+            } else if (n_pass + pre < kPtCache) {
+              cache[n_pass + pre] = t;
+            }
           }
           n_pass += __popcll(m);
         }
@@ -1057,8 +1210,9 @@ __device__ __forceinline__ bool near_any_wave(const Dir &d, bool active, const f
 __global__ void k_tc_pt3(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NPT3];
-  const int nw = gridDim.x * kWaves;
-  for (int i = blockIdx.x * kWaves + (threadIdx.x >> 6); i < n; i += nw) {
+  const int wpb = blockDim.x >> 6;
+  const int nw = gridDim.x * wpb;
+  for (int i = blockIdx.x * wpb + (threadIdx.x >> 6); i < n; i += nw) {
     const int s = w.pt3_so[i].x;
     const bool cand = w.pt3_keep[i] && !w.seed_used[s];
     const bool nr = near_any_wave(dir_of_seed(w, s), cand, w.bdir_pt5, w.boff_pt5, kDpT3, bin_reach(0.02));
@@ -1080,8 +1234,9 @@ __global__ void k_tc_dirs_pt3(const Ws *__restrict__ wb) {
 __global__ void k_tc_t5(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NT5];
-  const int nw = gridDim.x * kWaves;
-  for (int t = blockIdx.x * kWaves + (threadIdx.x >> 6); t < n; t += nw) {
+  const int wpb = blockDim.x >> 6;
+  const int nw = gridDim.x * wpb;
+  for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n; t += nw) {
     const bool cand = w.t5_keep[t] && !w.t5_used[t];
     const Dir d = dir_of_t5(w, t);
     const bool nr = near_any_wave(d, cand, w.bdir_pt5, w.boff_pt5, kDT5, bin_reach(0.02)) ||
@@ -1101,8 +1256,9 @@ __global__ void k_tc_dirs_t5(const Ws *__restrict__ wb) {
 // pLS TCs: surviving pLS used by no TC and not near any TC.
 __global__ void k_tc_pls(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int nw = gridDim.x * kWaves;
-  for (int s = blockIdx.x * kWaves + (threadIdx.x >> 6); s < w.n_seeds; s += nw) {
+  const int wpb = blockDim.x >> 6;
+  const int nw = gridDim.x * wpb;
+  for (int s = blockIdx.x * wpb + (threadIdx.x >> 6); s < w.n_seeds; s += nw) {
     const bool cand = w.pls_keep[s] && !w.seed_used[s];
     const Dir d = dir_of_seed(w, s);
     const bool nr = near_any_wave(d, cand, w.bdir_pt5, w.boff_pt5, kDpLS, bin_reach(0.05)) ||
@@ -1176,12 +1332,30 @@ const char *const kSiteNames[] = {
     "tc_pt5", "tc_pt5_scan", "tc_pt5_dirs", "tc_pt3", "tc_pt3_scan", "tc_pt3_dirs",
     "tc_t5", "tc_t5_scan", "tc_t5_dirs", "tc_pls", "tc_pls_scan", "tc_write"};
 const int kNumSites = (int)(sizeof(kSiteNames) / sizeof(kSiteNames[0]));
+static_assert(sizeof(kSiteNames) / sizeof(kSiteNames[0]) <= kMaxSites, "launch-site table");
 
-void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream_t st, const KernelTimer *kt) {
+// Sites whose kernels take any block of 64, 128 or 256 threads (grid-stride
+// loops over threads or waves, LDS sized for the largest block): the launch
+// shape the autotuner may choose.
+static const char *const kTunableSites[] = {"ls_count", "ls_fill",   "t3_count",  "t3_fill",  "t5_count",
+                                            "t5_fill",  "t5_dedup",  "pt3_count", "pt3_fill", "pt5_count",
+                                            "pt5_fill", "tc_pt3",    "tc_t5",     "tc_pls"};
+
+bool site_tunable(int site) {
+  if (site < 0 || site >= kNumSites) return false;
+  for (const char *n : kTunableSites)
+    if (std::strcmp(n, kSiteNames[site]) == 0) return true;
+  return false;
+}
+
+void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream_t st, const KernelTimer *kt,
+                   const int *site_block) {
   int site = 0;
+  int tb = kBlock;  // block size of the current site (tunable sites only)
   // Runs one launch site; the timed site is bracketed by the timer's events.
   auto run = [&](auto &&launch) {
     const bool timed = kt && kt->site == site;
+    tb = (site_block && site_block[site] > 0) ? site_block[site] : kBlock;
     if (timed) (void)hipEventRecord(kt->beg, st);
     launch();
     if (timed) (void)hipEventRecord(kt->end, st);
@@ -1191,7 +1365,10 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   const long N = b.n_hits, S = b.n_seeds;  // largest of the batch
   const bool seeds = S > 0;
   auto grid = [&](long n) { return dim3(grid_for(n), B); };
-  auto gridw = [&](long n) { return dim3(grid_waves(n), B); };
+  auto gridt = [&](long n) { return dim3(grid_for(n, tb), B); };    // tuned thread-per-item sites
+  auto gridwt = [&](long n) { return dim3(grid_waves(n, tb), B); }; // tuned wave-per-item sites
+  // one wave per seed, every seed its own wave (the seed search does not stride)
+  auto seedwaves = [&] { return dim3((unsigned)((S + tb / 64 - 1) / (tb / 64) > 0 ? (S + tb / 64 - 1) / (tb / 64) : 1), B); };
   const dim3 one(1, B);
   // a0: buckets
   run([&] { k_clear<<<grid(2L * M + 1), kBlock, 0, st>>>(wb, FL_CTR, FL_BCUR + 1); });
@@ -1204,17 +1381,17 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { scan(wb, B, SC_MD, M, st); });
   run([&] { k_md<true><<<dim3(M, B), kBlock, 0, st>>>(wb, g); });
   // a2: LS
-  run([&] { k_ls<false><<<gridw(b.cap_md), kBlock, 0, st>>>(wb, g); });
+  run([&] { k_ls<false><<<gridwt(b.cap_md), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_LS, b.cap_md, st); });
-  run([&] { k_ls<true><<<gridw(b.cap_md), kBlock, 0, st>>>(wb, g); });
+  run([&] { k_ls<true><<<gridwt(b.cap_md), tb, 0, st>>>(wb, g); });
   // a3: T3
-  run([&] { k_t3<false><<<grid(b.cap_ls), kBlock, 0, st>>>(wb, g); });
+  run([&] { k_t3<false><<<gridt(b.cap_ls), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_T3, b.cap_ls, st); });
-  run([&] { k_t3<true><<<grid(b.cap_ls), kBlock, 0, st>>>(wb, g); });
+  run([&] { k_t3<true><<<gridt(b.cap_ls), tb, 0, st>>>(wb, g); });
   // a4: T5
-  run([&] { k_t5<false><<<grid(b.cap_t3), kBlock, 0, st>>>(wb, g); });
+  run([&] { k_t5<false><<<gridt(b.cap_t3), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_T5, b.cap_t3, st); });
-  run([&] { k_t5<true><<<grid(b.cap_t3), kBlock, 0, st>>>(wb, g); });
+  run([&] { k_t5<true><<<gridt(b.cap_t3), tb, 0, st>>>(wb, g); });
   // a5: T5 duplicate removal through per-MD incidence lists
   run([&] {
     k_clear<<<grid((long)b.cap_md + 1), kBlock, 0, st>>>(wb, FL_INC_CNT, FL_INC_CUR + 1);
@@ -1222,7 +1399,7 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   });
   run([&] { scan(wb, B, SC_INC, b.cap_md, st); });
   run([&] { k_t5_inc_scatter<<<grid(b.cap_t5), kBlock, 0, st>>>(wb); });
-  run([&] { k_t5_dedup<<<grid(b.cap_t5), kBlock, 0, st>>>(wb); });
+  run([&] { k_t5_dedup<<<gridt(4L * b.cap_t5), tb, 0, st>>>(wb); });
   // a6: pLS
   run([&] {
     k_clear<<<grid(N + 1), kBlock, 0, st>>>(wb, FL_PH_CNT, FL_PH_CUR + 1);
@@ -1232,26 +1409,25 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { if (seeds) k_ph_scatter<<<grid(S), kBlock, 0, st>>>(wb); });
   run([&] { if (seeds) k_pls_dedup<<<grid(S), kBlock, 0, st>>>(wb); });
   // a7: pT3, pT5: objects binned by first anchor, one wave per seed over its bins
-  const dim3 seedwaves((unsigned)((S + kWaves - 1) / kWaves > 0 ? (S + kWaves - 1) / kWaves : 1), B);
   run([&] {
     if (!seeds) return;
-    k_clear<<<grid(kObjBins + 1), kBlock, 0, st>>>(wb, FL_B3_CNT, FL_B5_CUR + 1);
+    k_clear<<<grid(kSeedBins + 1), kBlock, 0, st>>>(wb, FL_B3_CNT, FL_B5_CUR + 1);
     k_obj_bin_count<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb);
-    scan(wb, B, SC_B3, kObjBins, st);
+    scan(wb, B, SC_B3, kSeedBins, st);
     k_obj_bin_scatter<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb);
   });
-  run([&] { if (seeds) k_pt_binned<3, false><<<seedwaves, kBlock, 0, st>>>(wb, g); });
+  run([&] { if (seeds) k_pt_binned<3, false><<<seedwaves(), tb, 0, st>>>(wb, g); });
   run([&] { if (seeds) scan(wb, B, SC_PT3, S, st); });
-  run([&] { if (seeds) k_pt_binned<3, true><<<seedwaves, kBlock, 0, st>>>(wb, g); });
+  run([&] { if (seeds) k_pt_binned<3, true><<<seedwaves(), tb, 0, st>>>(wb, g); });
   run([&] {
     if (!seeds) return;
     k_obj_bin_count<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
-    scan(wb, B, SC_B5, kObjBins, st);
+    scan(wb, B, SC_B5, kSeedBins, st);
     k_obj_bin_scatter<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
   });
-  run([&] { if (seeds) k_pt_binned<5, false><<<seedwaves, kBlock, 0, st>>>(wb, g); });
+  run([&] { if (seeds) k_pt_binned<5, false><<<seedwaves(), tb, 0, st>>>(wb, g); });
   run([&] { if (seeds) scan(wb, B, SC_PT5, S, st); });
-  run([&] { if (seeds) k_pt_binned<5, true><<<seedwaves, kBlock, 0, st>>>(wb, g); });
+  run([&] { if (seeds) k_pt_binned<5, true><<<seedwaves(), tb, 0, st>>>(wb, g); });
   run([&] {
     if (!seeds) return;
     const long n = (long)(b.cap_t3 > b.cap_t5 ? b.cap_t3 : b.cap_t5) + 1;
@@ -1282,19 +1458,19 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
     k_tc_dirs_pt5<<<grid(b.cap_pt5), kBlock, 0, st>>>(wb);
     k_bin_dirs<<<one, 1024, 0, st>>>(wb, 0);
   });
-  run([&] { k_tc_pt3<<<gridw(b.cap_pt3), kBlock, 0, st>>>(wb); });
+  run([&] { k_tc_pt3<<<gridwt(b.cap_pt3), tb, 0, st>>>(wb); });
   run([&] { scan(wb, B, SC_F3, b.cap_pt3, st); });
   run([&] {
     k_tc_dirs_pt3<<<grid(b.cap_pt3), kBlock, 0, st>>>(wb);
     k_bin_dirs<<<one, 1024, 0, st>>>(wb, 1);
   });
-  run([&] { k_tc_t5<<<gridw(b.cap_t5), kBlock, 0, st>>>(wb); });
+  run([&] { k_tc_t5<<<gridwt(b.cap_t5), tb, 0, st>>>(wb); });
   run([&] { scan(wb, B, SC_FT5, b.cap_t5, st); });
   run([&] {
     k_tc_dirs_t5<<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
     k_bin_dirs<<<one, 1024, 0, st>>>(wb, 2);
   });
-  run([&] { if (seeds) k_tc_pls<<<gridw(S), kBlock, 0, st>>>(wb); });
+  run([&] { if (seeds) k_tc_pls<<<gridwt(S), tb, 0, st>>>(wb); });
   run([&] { if (seeds) scan(wb, B, SC_FPLS, S, st); });
   run([&] { k_tc_write<<<grid(b.cap_tc), kBlock, 0, st>>>(wb); });
 }

@@ -52,6 +52,18 @@ enum FillId : int {
 
 // Device pointers of one event (all inside the workspace except the inputs).
 // Kernels of a batch read descriptor blockIdx.y of a device array of these.
+// Passing partners remembered between a stage's count and fill passes: per MD
+// for segments, per seed for pT3 / pT5, per inner triplet for quintuplets
+// (more than this: the fill searches again).
+constexpr int kLsCache = 16;
+constexpr int kPtCache = 64;  // one wave lane per cached object in the fill
+constexpr int kT5Cache = 4;  // per triplet for quintuplets
+
+// First-anchor bins of the seed search: 10 radius rings x 256 azimuth bins x
+// 55 z bins (10 cm over |z| < 275 cm); bins of one (ring, azimuth) pair are
+// contiguous, z ascending.
+constexpr int kSeedBins = 10 * 256 * 55;
+
 struct Ws {
   // inputs (device)
   int n_hits, n_seeds;
@@ -69,6 +81,7 @@ struct Ws {
   int *md_mod;
   float4 *md_pos;   // anchor (lower hit) x, y, z, r
   float2 *md_stub;  // tangential displacement, sensor separation
+  float4 *mod_disc;  // per module with MDs: x-y disc (cx, cy, radius, |c|) around its anchors
   // segments
   int *ls_cnt, *ls_off;
   int *ls_cache;    // per MD: up to 16 passing partners found by the count pass
@@ -93,6 +106,8 @@ struct Ws {
   int *ph_cnt, *ph_off, *ph_cur, *ph_list;      // seeds using each pixel hit
   // pixel triplets / quintuplets
   int *pt3_cnt, *pt3_off, *pt5_cnt, *pt5_off;
+  int *t5_cache;               // per T3: up to kT5Cache passing outer triplets
+  int *pt3_cache, *pt5_cache;  // per seed: up to kPtCache passing objects found by the count pass
   int2 *pt3_so, *pt5_so;      // seed, object
   float4 *pt3_attr, *pt5_attr;
   int *pt3_keep, *pt5_keep;
@@ -132,10 +147,15 @@ struct KernelTimer {
 };
 extern const char *const kSiteNames[];
 extern const int kNumSites;
+constexpr int kMaxSites = 64;
+// True for the launch sites that take a block of 64, 128 or 256 threads.
+bool site_tunable(int site);
 // Enqueues the whole chain for B events whose descriptors are d_ws[0..B) in
 // device memory; `bound` holds, field by field, the largest sizes and
-// capacities of the batch (it sets the launch grids).
-void enqueue_chain(const DevGeom &g, const Ws *d_ws, int B, const Ws &bound, hipStream_t st, const KernelTimer *kt);
+// capacities of the batch (it sets the launch grids).  site_block (kMaxSites
+// entries or NULL): threads per block of each tunable site, 0 = the default.
+void enqueue_chain(const DevGeom &g, const Ws *d_ws, int B, const Ws &bound, hipStream_t st, const KernelTimer *kt,
+                   const int *site_block);
 void launch_module_windows(const int *info, const float *pos_lo, const float *pos_up, const float *lmin,
                            const float *lmax, int n_mod, float4 *win, hipStream_t st);
 
