@@ -123,6 +123,7 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   const long nbins = kSeedBins;
   t.b3_cnt = I(nbins + 1); t.b3_off = I(nbins + 1); t.b3_cur = I(nbins + 1); t.b3_list = I(t3);
   t.b5_cnt = I(nbins + 1); t.b5_off = I(nbins + 1); t.b5_cur = I(nbins + 1); t.b5_list = I(t5);
+  t.b3_pos = F4(t3); t.b5_pos = F4(t5);
   t.seed_used = I(S + 1); t.t5_used = I(t5 + 1);
   t.f_pt5 = I(p5 + 1); t.f_pt3 = I(p3 + 1); t.f_t5 = I(t5 + 1); t.f_pls = I(S + 1);
   t.p_pt5 = I(p5 + 1); t.p_pt3 = I(p3 + 1); t.p_t5 = I(t5 + 1); t.p_pls = I(S + 1);

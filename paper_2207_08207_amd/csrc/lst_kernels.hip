@@ -763,6 +763,7 @@ constexpr int kMaskWords = kObjBins / 32;
 constexpr float kSampleStep = 2.0f;                  // trajectory sampling step [cm]
 constexpr int kMaxSamples = 112;                     // 224 cm of arc
 constexpr int kPassList = 1024;                      // passing objects sorted per seed in LDS
+constexpr int kMaxSlices = 512;                      // marked bins per seed gathered in LDS (else: bin by bin)
 
 __device__ __forceinline__ int ring_of(float r) {
   const int k = (int)floorf((r - kRing0) / kRingW);
@@ -793,16 +794,21 @@ __global__ void k_obj_bin_count(const Ws *__restrict__ wb) {
     if (K == 3 || w.t5_keep[t]) atomicAdd(&cnt[obj_bin<K>(w, t)], 1);
 }
 template <int K>
-__global__ void k_obj_bin_scatter(const Ws *__restrict__ wb) {
+__global__ void k_obj_bin_scatter(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
   const int n = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
   const int *off = K == 3 ? w.b3_off : w.b5_off;
   int *cur = K == 3 ? w.b3_cur : w.b5_cur;
   int *lst = K == 3 ? w.b3_list : w.b5_list;
+  float4 *pos = K == 3 ? w.b3_pos : w.b5_pos;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
     if (K == 3 || w.t5_keep[t]) {
       const int b = obj_bin<K>(w, t);
-      lst[off[b] + atomicAdd(&cur[b], 1)] = t;
+      const int j = off[b] + atomicAdd(&cur[b], 1);
+      lst[j] = t;
+      const int md = K == 3 ? w.t3_md[t].x : w.t5_md[5 * (long)t];
+      const float4 a = w.md_pos[md];
+      pos[j] = make_float4(a.x, a.y, a.z, __int_as_float(g.info[w.md_mod[md]]));
     }
 }
 
@@ -880,6 +886,8 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   __shared__ unsigned s_mask[kWaves][kMaskWords];
   __shared__ int s_slo[kWaves][kRings], s_shi[kWaves][kRings];
   __shared__ int2 s_zb[kWaves][kRings];
+  __shared__ int s_sl_j0[kWaves][kMaxSlices];       // bin id, then first list entry, of each slice
+  __shared__ int s_sl_pre[kWaves][kMaxSlices + 1];  // candidates before each slice
   __shared__ int s_list[FILL ? kWaves : 1][FILL ? kPassList : 1];
   const Ws &w = wb[blockIdx.y];
   const int wv = threadIdx.x >> 6, lane = lane_id();
@@ -933,7 +941,99 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   const int expect = FILL ? (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s] : 0;
   const int cap = K == 3 ? w.cap_pt3 : w.cap_pt5;
   const bool listed = !FILL || expect <= kPassList;
+  // one candidate: the object at list entry j, tested against the seed; passing ones are
+  // counted in ballot order and remembered (count: the cache; fill: the LDS list)
+  const float4 *bpos = K == 3 ? w.b3_pos : w.b5_pos;
+  auto test = [&](bool active, int j) {
+    bool pass = false;
+    int t = 0;
+    if (active) {
+      t = blst[j];
+      const float4 f = bpos[j];
+      if (pt_first_anchor(sd, f, ModInfo{__float_as_int(f.w)})) {
+        float4 P[K];
+        ModInfo M[K];
+        float kT, dkT;
+        float4 attr;
+        load_object<K>(w, g, t, P, M, &kT, &dkT);
+        pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
+      }
+    }
+    const unsigned long long m = __ballot(pass);
+    if (pass) {
+      const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      if (FILL) {
+        if (n_pass + pre < kPassList) s_list[wv][n_pass + pre] = t;
+      } else if (n_pass + pre < kPtCache) {
+        cache[n_pass + pre] = t;
+      }
+    }
+    n_pass += __popcll(m);
+  };
+  bool flat = false;
   if (listed) {
+    // every marked (ring, azimuth) bin becomes a slice of the object list (its reachable
+    // z bins, possibly empty); bit ids first, ranked over the wave by a prefix of the
+    // mask words' popcounts, then converted in place, 64 at a time, to (first entry,
+    // candidates before it)
+    int n_bits = 0;
+    for (int w0 = 0; w0 < kMaskWords; w0 += 64) {
+      const unsigned bits = w0 + lane < kMaskWords ? s_mask[wv][w0 + lane] : 0u;
+      const int pc = __popc(bits);
+      int x = pc;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      const int tot = __shfl(x, 63, 64);
+      if (n_bits + tot <= kMaxSlices) {
+        int k = n_bits + x - pc;
+        for (unsigned bb = bits; bb; bb &= bb - 1u) s_sl_j0[wv][k++] = (w0 + lane) * 32 + __builtin_ctz(bb);
+      }
+      n_bits += tot;
+    }
+    flat = n_bits <= kMaxSlices;
+    if (flat) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      int run = 0;
+      for (int c0 = 0; c0 < n_bits; c0 += 64) {
+        const int k = c0 + lane;
+        int j0 = 0, len = 0;
+        if (k < n_bits) {
+          const int bin = s_sl_j0[wv][k];
+          const int2 zb = s_zb[wv][bin / kPhiBins];
+          j0 = boff[bin * kZBins + zb.x];
+          len = boff[bin * kZBins + zb.y + 1] - j0;
+        }
+        int x = len;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(x, o, 64);
+          if (lane >= o) x += y;
+        }
+        if (k < n_bits) {
+          s_sl_j0[wv][k] = j0;
+          s_sl_pre[wv][k] = run + x - len;
+        }
+        run += __shfl(x, 63, 64);
+      }
+      if (lane == 0) s_sl_pre[wv][n_bits] = run;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      int e = 0;  // slice of this lane's candidate (candidates advance monotonically)
+      for (int c0 = 0; c0 < run; c0 += 64) {
+        const int c = c0 + lane;
+        int j = 0;
+        if (c < run) {
+          while (s_sl_pre[wv][e + 1] <= c) ++e;
+          j = s_sl_j0[wv][e] + (c - s_sl_pre[wv][e]);
+        }
+        test(c < run, j);
+      }
+    }
+  }
+  if (listed && !flat) {
+    n_pass = 0;
     for (int wd = 0; wd < kMaskWords; ++wd) {
       unsigned bits = mask[wd];
       while (bits) {
@@ -942,32 +1042,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
         const int bin = wd * 32 + bit;
         const int2 zb = s_zb[wv][bin / kPhiBins];
         const int j0 = boff[bin * kZBins + zb.x], j1 = boff[bin * kZBins + zb.y + 1];
-        for (int j = j0 + lane; j - lane < j1; j += 64) {
-          bool pass = false;
-          int t = 0;
-          if (j < j1) {
-            t = blst[j];
-            const float2 f = first[t];
-            if (seed_box(sd, f.x, f.y)) {
-              float4 P[K];
-              ModInfo M[K];
-              float kT, dkT;
-              float4 attr;
-              load_object<K>(w, g, t, P, M, &kT, &dkT);
-              pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
-            }
-          }
-          const unsigned long long m = __ballot(pass);
-          if (pass) {
-            const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-            if (FILL) {
-              if (n_pass + pre < kPassList) s_list[wv][n_pass + pre] = t;
-            } else if (n_pass + pre < kPtCache) {
-              cache[n_pass + pre] = t;
-            }
-          }
-          n_pass += __popcll(m);
-        }
+        for (int j = j0 + lane; j - lane < j1; j += 64) test(j < j1, j);
       }
     }
   }
@@ -1414,7 +1489,7 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
     k_clear<<<grid(kSeedBins + 1), kBlock, 0, st>>>(wb, FL_B3_CNT, FL_B5_CUR + 1);
     k_obj_bin_count<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb);
     scan(wb, B, SC_B3, kSeedBins, st);
-    k_obj_bin_scatter<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb);
+    k_obj_bin_scatter<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb, g);
   });
   run([&] { if (seeds) k_pt_binned<3, false><<<seedwaves(), tb, 0, st>>>(wb, g); });
   run([&] { if (seeds) scan(wb, B, SC_PT3, S, st); });
@@ -1423,7 +1498,7 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
     if (!seeds) return;
     k_obj_bin_count<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
     scan(wb, B, SC_B5, kSeedBins, st);
-    k_obj_bin_scatter<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
+    k_obj_bin_scatter<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb, g);
   });
   run([&] { if (seeds) k_pt_binned<5, false><<<seedwaves(), tb, 0, st>>>(wb, g); });
   run([&] { if (seeds) scan(wb, B, SC_PT5, S, st); });

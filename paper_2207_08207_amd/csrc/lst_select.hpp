@@ -408,6 +408,22 @@ __device__ __forceinline__ bool seed_box(const Seed &sd, float ax, float ay) {
   return (u1 > 0.0f) && (fabsf(r1) <= kBoxXY);
 }
 
+// The first-anchor part of pt_pass on its own (the same operations in the
+// same order: seed window, arc-length series validity, z window), so that a
+// candidate failing it is known to fail pt_pass before its other anchors are read.
+__device__ __forceinline__ bool pt_first_anchor(const Seed &sd, float4 A, ModInfo m) {
+  if (!seed_box(sd, A.x, A.y)) return false;
+  const float hk = sd.ks * 0.5f;
+  const float ddx = A.x - sd.x0, ddy = A.y - sd.y0;
+  const float Lc = sqrtf(ddx * ddx + ddy * ddy);
+  const float xs = hk * Lc;
+  if (!(fabsf(xs) <= kXSeriesMax)) return false;
+  const float s = 0.0f + Lc * arc_over_chord(xs);
+  const float sz = m.sig_z(sd.lam);
+  const float rz = A.z - (sd.z0 + sd.lam * s);
+  return fabsf(rz) <= kBoxZ0 + 2.0f * sz;
+}
+
 template <int K>
 __device__ __forceinline__ bool pt_pass(const Seed &sd, const float4 *P, const ModInfo *M, float kT, float dkT,
                                         float4 *out) {

@@ -113,8 +113,9 @@ struct Ws {
   int *pt3_keep, *pt5_keep;
   int *o3_cnt, *o3_off, *o3_cur, *o3_list;      // pT3 entries per T3
   int *o5_cnt, *o5_off, *o5_cur, *o5_list;      // pT5 entries per T5
-  int *b3_cnt, *b3_off, *b3_cur, *b3_list;      // T3s by first-anchor (ring, azimuth) bin
+  int *b3_cnt, *b3_off, *b3_cur, *b3_list;      // T3s by first-anchor (ring, azimuth, z) bin
   int *b5_cnt, *b5_off, *b5_cur, *b5_list;      // surviving T5s by the same bins
+  float4 *b3_pos, *b5_pos;  // per list entry: the object's first anchor x, y, z and module info bits
   // track candidates
   int *seed_used, *t5_used;
   int *f_pt5, *f_pt3, *f_t5, *f_pls;            // TC flags
