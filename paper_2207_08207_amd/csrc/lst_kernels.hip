@@ -391,6 +391,7 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
   __shared__ int s_first[kWaves][kMaxEdges];    // first MD of each linked module
   __shared__ int s_info[kWaves][kMaxEdges];
   __shared__ float s_wmax[kWaves][kMaxEdges];   // window bound of each linked module
+  __shared__ int s_q[kWaves][128], s_qi[kWaves][128];  // candidates past the pre-tests, in order
   const int n_md = w.ctr[C_NMD];
   const int wv = threadIdx.x >> 6, lane = lane_id();
   const int wpb = blockDim.x >> 6;  // waves per block (a tuned launch may run fewer than kWaves)
@@ -456,18 +457,14 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
     const int total = run;
     int out = FILL ? w.ls_off[a] : 0;
     int cnt = 0;
-    int e = 0;  // edge of this lane's candidate (candidates advance monotonically)
-    for (int c0 = 0; c0 < total; c0 += 64) {
-      const int c = c0 + lane;
+    // the full selection on the first n queued candidates (n <= 64), in candidate order
+    auto select = [&](int n) {
       bool pass = false;
       int b = 0;
       float2 beta = make_float2(0.f, 0.f);
-      if (c < total) {
-        while (s_pre[wv][e + 1] <= c) ++e;
-        b = s_first[wv][e] + (c - s_pre[wv][e]);
-        const float4 Bp = w.md_pos[b];
-        const ModInfo mib{s_info[wv][e]};
-        if (ls_window_may_pass(A, Bp, s_wmax[wv][e])) pass = ls_pass(A, Bp, sa, w.md_stub[b], mia, mib, &beta);
+      if (lane < n) {
+        b = s_q[wv][lane];
+        pass = ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, ModInfo{s_qi[wv][lane]}, &beta);
       }
       const unsigned long long m = __ballot(pass);
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -482,7 +479,52 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
       }
       out += __popcll(m);
       cnt += __popcll(m);
+    };
+    // candidates past the azimuth pre-tests and the inner MD's own stub check (both
+    // necessary conditions of ls_pass) are queued in LDS, and the full selection runs
+    // on full waves of them
+    int nq = 0;
+    int e = 0;  // edge of this lane's candidate (candidates advance monotonically)
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      bool keep = false;
+      int b = 0, info = 0;
+      if (c < total) {
+        while (s_pre[wv][e + 1] <= c) ++e;
+        b = s_first[wv][e] + (c - s_pre[wv][e]);
+        const float4 Bp = w.md_pos[b];
+        info = s_info[wv][e];
+        keep = ls_window_may_pass(A, Bp, s_wmax[wv][e]) && ls_inner_stub_ok(A, Bp, sa, mia, ModInfo{info});
+      }
+      const unsigned long long m = __ballot(keep);
+      const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      if (keep) {
+        s_q[wv][nq + pre] = b;
+        s_qi[wv][nq + pre] = info;
+      }
+      nq += __popcll(m);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (nq >= 64) {
+        select(64);
+        const int rest = nq - 64;  // < 64: move the tail of the queue to its front
+        int vb = 0, vi = 0;
+        if (lane < rest) {
+          vb = s_q[wv][64 + lane];
+          vi = s_qi[wv][64 + lane];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) {
+          s_q[wv][lane] = vb;
+          s_qi[wv][lane] = vi;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        nq = rest;
+      }
     }
+    if (nq > 0) select(nq);
     if (!FILL && lane == 0) w.ls_cnt[a] = cnt;
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();

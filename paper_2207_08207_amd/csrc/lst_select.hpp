@@ -152,6 +152,26 @@ __device__ __forceinline__ float2 md_stub(const float4 &hi, const float4 &hj, Mo
 }
 
 // -------------------------------------------------------------- LS (S2.2)
+// One MD's stub direction against the chord AB (stub st = (tangential
+// displacement, sensor separation), sn = sine of the chord's angle to the
+// radial direction used for it, rp its radius).
+__device__ __forceinline__ bool ls_stub_ok(float2 st, ModInfo m, float sn, float rp, float Ls, float adz, float eang) {
+  float pred, err;
+  if (!m.endcap()) {
+    const float cs2 = 1.0f - sn * sn;
+    if (!(cs2 > 0.0f)) return false;
+    pred = (st.y * sn) / sqrtf(cs2);
+    err = 2.0f * m.hphi() + (2.0f * st.y) * (eang + kD0Max / rp);
+  } else {
+    if (!(adz > 0.0f)) return false;
+    const float ds = (st.y * Ls) / adz;
+    pred = ds * sn;
+    err = (2.0f * m.hphi() + (float)0.03 * fabsf(pred)) + ds * (eang + kD0Max / rp);
+  }
+  const float dt = st.x - pred;
+  return fabsf(dt) <= err * kMargin + kEps;
+}
+
 // MDs a (anchor A, stub sa, module ma) and b (B, sb, mb), the modules linked
 // by the map.  x-y azimuth window from the beam line, r-z pointing to the
 // luminous region, and each stub's direction against the origin-constrained
@@ -197,32 +217,27 @@ __device__ __forceinline__ bool ls_pass(const float4 &A, const float4 &B, float2
   const float ea2 = ma.endcap() ? ma.hlong() : ma.hphi();
   const float eb2 = mb.endcap() ? mb.hlong() : mb.hphi();
   const float eang = (ea2 + eb2) / Ls;
-#pragma unroll
-  for (int k = 0; k < 2; ++k) {
-    const ModInfo m = k ? mb : ma;
-    const float2 st = k ? sb : sa;
-    const float sn = k ? s_in : s_out;
-    const float rp = k ? B.w : A.w;
-    float pred, err;
-    if (!m.endcap()) {
-      const float cs2 = 1.0f - sn * sn;
-      if (!(cs2 > 0.0f)) return false;
-      pred = (st.y * sn) / sqrtf(cs2);
-      err = 2.0f * m.hphi() + (2.0f * st.y) * (eang + kD0Max / rp);
-    } else {
-      if (!(adz > 0.0f)) return false;
-      const float ds = (st.y * Ls) / adz;
-      pred = ds * sn;
-      err = (2.0f * m.hphi() + (float)0.03 * fabsf(pred)) + ds * (eang + kD0Max / rp);
-    }
-    const float dt = st.x - pred;
-    ok &= fabsf(dt) <= err * kMargin + kEps;
-  }
+  ok &= ls_stub_ok(sa, ma, s_out, A.w, Ls, adz, eang);
+  ok &= ls_stub_ok(sb, mb, s_in, B.w, Ls, adz, eang);
   if (ok) {
     beta->x = atan2f(A.x * sy - A.y * sx, A.x * sx + A.y * sy);
     beta->y = atan2f(B.x * sy - B.y * sx, B.x * sx + B.y * sy);
   }
   return ok;
+}
+
+// The inner MD's stub check of ls_pass on its own, with the same operations in
+// the same order: a candidate failing it fails ls_pass.
+__device__ __forceinline__ bool ls_inner_stub_ok(const float4 &A, const float4 &B, float2 sa, ModInfo ma, ModInfo mb) {
+  const float dz = B.z - A.z;
+  const float sx = B.x - A.x, sy = B.y - A.y;
+  const float Ls = sqrtf(sx * sx + sy * sy);
+  const float s_out = (B.x * sy - B.y * sx) / (B.w * Ls);
+  const float adz = fabsf(dz);
+  const float ea2 = ma.endcap() ? ma.hlong() : ma.hphi();
+  const float eb2 = mb.endcap() ? mb.hlong() : mb.hphi();
+  const float eang = (ea2 + eb2) / Ls;
+  return ls_stub_ok(sa, ma, s_out, A.w, Ls, adz, eang);
 }
 
 // Azimuth linear in z over three anchors P, Q, R (Section 2.3 pointing for a
