@@ -408,11 +408,9 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
         const int out0 = w.ls_off[a];
         for (int i = lane; i < n_pass; i += 64) {
           const int b = w.ls_cache[(long)a * kLsCache + i];
-          float2 beta = make_float2(0.f, 0.f);
-          ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, ModInfo{g.info[w.md_mod[b]]}, &beta);
           if (out0 + i < w.cap_ls) {
             w.ls_md[out0 + i] = make_int2(a, b);
-            w.ls_beta[out0 + i] = beta;
+            w.ls_beta[out0 + i] = ls_beta(A, w.md_pos[b]);  // as ls_pass reports them
           }
         }
         continue;
@@ -531,91 +529,177 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
   }
 }
 
+// ---- flattened pair search shared by T3 and T5: a wave takes 64 consecutive
+// parents (one per lane), stages what their pairs need in LDS, prefix-sums
+// their candidate counts and lets its 64 lanes stride over all (parent,
+// candidate) pairs in order, so a parent with many candidates does not hold
+// the wave.  The rank of an accepted pair among its parent's accepted pairs
+// (its output position after the parent's offset in the fill) is the
+// parent's count from earlier rounds plus the accepted pairs of the same
+// parent on lower lanes of this round (a parent's pairs are on consecutive
+// lanes).  COUNT writes the per-parent counts, FILL the objects.
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+__device__ __forceinline__ int pair_rank(unsigned long long m, int seg_first_lane, int before_round) {
+  return before_round + lanes_below(m) - __popcll(m & ((1ull << seg_first_lane) - 1ull));
+}
+// Exclusive prefix of n over the wave into seg[0..64] (seg[64] = total); returns the total.
+__device__ __forceinline__ int wave_segments(int n, int *seg) {
+  const int lane = lane_id();
+  int x = n;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  seg[lane] = x - n;
+  const int total = __shfl(x, 63, 64);
+  if (lane == 0) seg[64] = total;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  return total;
+}
+
 // ------------------------------------------------------------- a3: T3
-// One thread per inner segment (a, b); partners: the segments whose inner MD is b.
+// Parents: segments (a, b); candidates: the segments whose inner MD is b.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
+  __shared__ float4 s_a[kWaves][64], s_b[kWaves][64];
+  __shared__ int s_mi[kWaves][64], s_lo[kWaves][64], s_cnt[kWaves][64], s_seg[kWaves][65];
   const int n_ls = w.ctr[C_NLS];
-  for (int l1 = blockIdx.x * blockDim.x + threadIdx.x; l1 < n_ls; l1 += gridDim.x * blockDim.x) {
-    const int2 ab = w.ls_md[l1];
-    const float4 A = w.md_pos[ab.x], B = w.md_pos[ab.y];
-    const ModInfo mA{g.info[w.md_mod[ab.x]]}, mB{g.info[w.md_mod[ab.y]]};
-    int out = FILL ? w.t3_off[l1] : 0;
-    int cnt = 0;
-    const int l2e = min(w.ls_off[ab.y + 1], n_ls);
-    for (int l2 = w.ls_off[ab.y]; l2 < l2e; ++l2) {
-      const int c = w.ls_md[l2].y;
-      const ModInfo mC{g.info[w.md_mod[c]]};
-      float4 attr;
-      if (t3_pass(A, B, w.md_pos[c], mA, mB, mC, &attr)) {
-        if (FILL) {
-          if (out < w.cap_t3) {
-            w.t3_md[out] = make_int4(ab.x, ab.y, c, l1);
-            w.t3_attr[out] = attr;
-            w.t3_first[out] = make_float2(A.x, A.y);
-          }
-          ++out;
-        } else {
-          ++cnt;
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int wpb = blockDim.x >> 6;
+  for (long p0 = ((long)blockIdx.x * wpb + wv) * 64; p0 < n_ls; p0 += (long)gridDim.x * wpb * 64) {
+    const int l1 = (int)p0 + lane;
+    int n = 0;
+    if (l1 < n_ls) {
+      const int2 ab = w.ls_md[l1];
+      s_a[wv][lane] = w.md_pos[ab.x];
+      s_b[wv][lane] = w.md_pos[ab.y];
+      s_mi[wv][lane] = g.info[w.md_mod[ab.x]] | (g.info[w.md_mod[ab.y]] << 8);
+      const int lo = w.ls_off[ab.y], hi = min(w.ls_off[ab.y + 1], n_ls);
+      s_lo[wv][lane] = lo;
+      n = hi > lo ? hi - lo : 0;
+      if (FILL && w.t3_cnt[l1] == 0) n = 0;  // nothing to write for this parent
+    }
+    s_cnt[wv][lane] = 0;
+    const int total = wave_segments(n, s_seg[wv]);
+    int e = 0;  // parent of this lane's pair (pairs advance monotonically)
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      bool pass = false;
+      int cmd = 0, first = 0, before = 0;
+      float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (c < total) {
+        while (s_seg[wv][e + 1] <= c) ++e;
+        first = max(s_seg[wv][e] - c0, 0);
+        before = s_cnt[wv][e];
+        cmd = w.ls_md[s_lo[wv][e] + (c - s_seg[wv][e])].y;
+        const int mi = s_mi[wv][e];
+        pass = t3_pass(s_a[wv][e], s_b[wv][e], w.md_pos[cmd], ModInfo{mi & 0xff}, ModInfo{mi >> 8},
+                       ModInfo{g.info[w.md_mod[cmd]]}, &attr);
+      }
+      const unsigned long long m = __ballot(pass);
+      if (FILL && pass) {
+        const int pos = w.t3_off[(int)p0 + e] + pair_rank(m, first, before);
+        if (pos < w.cap_t3) {
+          const int2 ab = w.ls_md[(int)p0 + e];
+          w.t3_md[pos] = make_int4(ab.x, ab.y, cmd, (int)p0 + e);
+          w.t3_attr[pos] = attr;
+          w.t3_first[pos] = make_float2(s_a[wv][e].x, s_a[wv][e].y);
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (pass) atomicAdd(&s_cnt[wv][e], 1);  // LDS
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
-    if (!FILL) w.t3_cnt[l1] = cnt;
+    if (!FILL && l1 < n_ls) w.t3_cnt[l1] = s_cnt[wv][lane];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
 // ------------------------------------------------------------- a4: T5
-// One thread per inner triplet (a, b, c); partners: the triplets whose first MD is c.
+// Parents: triplets (a, b, c); candidates: the triplets whose first MD is c.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
+  __shared__ float4 s_p[kWaves][3][64], s_tin[kWaves][64];
+  __shared__ int s_mi[kWaves][64], s_lo[kWaves][64], s_cnt[kWaves][64], s_seg[kWaves][65];
   const int n_t3 = w.ctr[C_NT3];
   const int n_ls = w.ctr[C_NLS];
-  for (int t1 = blockIdx.x * blockDim.x + threadIdx.x; t1 < n_t3; t1 += gridDim.x * blockDim.x) {
-    const int4 abc = w.t3_md[t1];
-    float4 P[5];
-    ModInfo M[5];
-    P[0] = w.md_pos[abc.x]; P[1] = w.md_pos[abc.y]; P[2] = w.md_pos[abc.z];
-    M[0].bits = g.info[w.md_mod[abc.x]]; M[1].bits = g.info[w.md_mod[abc.y]]; M[2].bits = g.info[w.md_mod[abc.z]];
-    const float4 tin = w.t3_attr[t1];
-    // triplets with first MD c: those built from segments with inner MD c
-    const int lsb = min(w.ls_off[abc.z], n_ls), lse = min(w.ls_off[abc.z + 1], n_ls);
-    const int t2b = w.t3_off[lsb], t2e = min(w.t3_off[lse], n_t3);
-    int out = FILL ? w.t5_off[t1] : 0;
-    int cnt = 0;
-    int *cache = w.t5_cache + (long)t1 * kT5Cache;
-    // fill: the count pass cached the passing partners (in candidate order) unless there were too many
-    const int n_cached = FILL ? w.t5_cnt[t1] : 0;
-    const bool cached = FILL && n_cached <= kT5Cache;
-    const int n_cand = cached ? n_cached : t2e - t2b;
-    for (int i = 0; i < n_cand; ++i) {
-      const int t2 = cached ? cache[i] : t2b + i;
-      const int4 cde = w.t3_md[t2];
-      P[3] = w.md_pos[cde.y];
-      P[4] = w.md_pos[cde.z];
-      M[3].bits = g.info[w.md_mod[cde.y]];
-      M[4].bits = g.info[w.md_mod[cde.z]];
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int wpb = blockDim.x >> 6;
+  for (long p0 = ((long)blockIdx.x * wpb + wv) * 64; p0 < n_t3; p0 += (long)gridDim.x * wpb * 64) {
+    const int t1 = (int)p0 + lane;
+    int n = 0;
+    if (t1 < n_t3) {
+      const int4 abc = w.t3_md[t1];
+      s_p[wv][0][lane] = w.md_pos[abc.x];
+      s_p[wv][1][lane] = w.md_pos[abc.y];
+      s_p[wv][2][lane] = w.md_pos[abc.z];
+      s_mi[wv][lane] = g.info[w.md_mod[abc.x]] | (g.info[w.md_mod[abc.y]] << 8) | (g.info[w.md_mod[abc.z]] << 16);
+      s_tin[wv][lane] = w.t3_attr[t1];
+      // triplets with first MD c: those built from segments with inner MD c
+      const int lsb = min(w.ls_off[abc.z], n_ls), lse = min(w.ls_off[abc.z + 1], n_ls);
+      const int lo = w.t3_off[lsb], hi = min(w.t3_off[lse], n_t3);
+      s_lo[wv][lane] = lo;
+      n = hi > lo ? hi - lo : 0;
+      if (FILL && w.t5_cnt[t1] == 0) n = 0;
+    }
+    s_cnt[wv][lane] = 0;
+    const int total = wave_segments(n, s_seg[wv]);
+    int e = 0;
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      bool pass = false;
+      int t2 = 0, first = 0, before = 0;
+      int4 cde = make_int4(0, 0, 0, 0);
       float at[8];
-      if (t5_pass(P, M, tin, w.t3_attr[t2], at)) {
-        if (FILL) {
-          if (out < w.cap_t5) {
-            w.t5_t3[out] = make_int2(t1, t2);
-            int *md = w.t5_md + 5 * (long)out;
-            md[0] = abc.x; md[1] = abc.y; md[2] = abc.z; md[3] = cde.y; md[4] = cde.z;
-            float *dst = w.t5_attr + 8 * (long)out;
+      if (c < total) {
+        while (s_seg[wv][e + 1] <= c) ++e;
+        first = max(s_seg[wv][e] - c0, 0);
+        before = s_cnt[wv][e];
+        t2 = s_lo[wv][e] + (c - s_seg[wv][e]);
+        cde = w.t3_md[t2];
+        float4 P[5];
+        ModInfo M[5];
+        const int mi = s_mi[wv][e];
+        P[0] = s_p[wv][0][e]; P[1] = s_p[wv][1][e]; P[2] = s_p[wv][2][e];
+        M[0].bits = mi & 0xff; M[1].bits = (mi >> 8) & 0xff; M[2].bits = mi >> 16;
+        P[3] = w.md_pos[cde.y];
+        P[4] = w.md_pos[cde.z];
+        M[3].bits = g.info[w.md_mod[cde.y]];
+        M[4].bits = g.info[w.md_mod[cde.z]];
+        pass = t5_pass(P, M, s_tin[wv][e], w.t3_attr[t2], at);
+      }
+      const unsigned long long m = __ballot(pass);
+      if (FILL && pass) {
+        const int t1e = (int)p0 + e;
+        const int pos = w.t5_off[t1e] + pair_rank(m, first, before);
+        if (pos < w.cap_t5) {
+          const int4 abc = w.t3_md[t1e];
+          w.t5_t3[pos] = make_int2(t1e, t2);
+          int *md = w.t5_md + 5 * (long)pos;
+          md[0] = abc.x; md[1] = abc.y; md[2] = abc.z; md[3] = cde.y; md[4] = cde.z;
+          float *dst = w.t5_attr + 8 * (long)pos;
 #pragma unroll
-            for (int k = 0; k < 8; ++k) dst[k] = at[k];
-            w.t5_keep[out] = 1;  // until a better duplicate is found
-          }
-          ++out;
-        } else {
-          if (cnt < kT5Cache) cache[cnt] = t2;
-          ++cnt;
+          for (int k = 0; k < 8; ++k) dst[k] = at[k];
+          w.t5_keep[pos] = 1;  // until a better duplicate is found
         }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (pass) atomicAdd(&s_cnt[wv][e], 1);  // LDS
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
-    if (!FILL) w.t5_cnt[t1] = cnt;
+    if (!FILL && t1 < n_t3) w.t5_cnt[t1] = s_cnt[wv][lane];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -1502,13 +1586,13 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { scan(wb, B, SC_LS, b.cap_md, st); });
   run([&] { k_ls<true><<<gridwt(b.cap_md), tb, 0, st>>>(wb, g); });
   // a3: T3
-  run([&] { k_t3<false><<<gridt(b.cap_ls), tb, 0, st>>>(wb, g); });
+  run([&] { k_t3<false><<<gridwt((b.cap_ls + 63) / 64), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_T3, b.cap_ls, st); });
-  run([&] { k_t3<true><<<gridt(b.cap_ls), tb, 0, st>>>(wb, g); });
+  run([&] { k_t3<true><<<gridwt((b.cap_ls + 63) / 64), tb, 0, st>>>(wb, g); });
   // a4: T5
-  run([&] { k_t5<false><<<gridt(b.cap_t3), tb, 0, st>>>(wb, g); });
+  run([&] { k_t5<false><<<gridwt((b.cap_t3 + 63) / 64), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_T5, b.cap_t3, st); });
-  run([&] { k_t5<true><<<gridt(b.cap_t3), tb, 0, st>>>(wb, g); });
+  run([&] { k_t5<true><<<gridwt((b.cap_t3 + 63) / 64), tb, 0, st>>>(wb, g); });
   // a5: T5 duplicate removal through per-MD incidence lists
   run([&] {
     k_clear<<<grid((long)b.cap_md + 1), kBlock, 0, st>>>(wb, FL_INC_CNT, FL_INC_CUR + 1);

@@ -152,6 +152,13 @@ __device__ __forceinline__ float2 md_stub(const float4 &hi, const float4 &hj, Mo
 }
 
 // -------------------------------------------------------------- LS (S2.2)
+// Reported angles of a segment: the chord AB against the radial direction at A
+// and at B.
+__device__ __forceinline__ float2 ls_beta(const float4 &A, const float4 &B) {
+  const float sx = B.x - A.x, sy = B.y - A.y;
+  return make_float2(atan2f(A.x * sy - A.y * sx, A.x * sx + A.y * sy), atan2f(B.x * sy - B.y * sx, B.x * sx + B.y * sy));
+}
+
 // One MD's stub direction against the chord AB (stub st = (tangential
 // displacement, sensor separation), sn = sine of the chord's angle to the
 // radial direction used for it, rp its radius).
@@ -219,10 +226,7 @@ __device__ __forceinline__ bool ls_pass(const float4 &A, const float4 &B, float2
   const float eang = (ea2 + eb2) / Ls;
   ok &= ls_stub_ok(sa, ma, s_out, A.w, Ls, adz, eang);
   ok &= ls_stub_ok(sb, mb, s_in, B.w, Ls, adz, eang);
-  if (ok) {
-    beta->x = atan2f(A.x * sy - A.y * sx, A.x * sx + A.y * sy);
-    beta->y = atan2f(B.x * sy - B.y * sx, B.x * sx + B.y * sy);
-  }
+  if (ok) *beta = ls_beta(A, B);
   return ok;
 }
 

@@ -53,11 +53,9 @@ enum FillId : int {
 // Device pointers of one event (all inside the workspace except the inputs).
 // Kernels of a batch read descriptor blockIdx.y of a device array of these.
 // Passing partners remembered between a stage's count and fill passes: per MD
-// for segments, per seed for pT3 / pT5, per inner triplet for quintuplets
-// (more than this: the fill searches again).
+// for segments, per seed for pT3 / pT5 (more than this: the fill searches again).
 constexpr int kLsCache = 16;
 constexpr int kPtCache = 64;  // one wave lane per cached object in the fill
-constexpr int kT5Cache = 4;  // per triplet for quintuplets
 
 // First-anchor bins of the seed search: 10 radius rings x 256 azimuth bins x
 // 55 z bins (10 cm over |z| < 275 cm); bins of one (ring, azimuth) pair are
@@ -106,7 +104,6 @@ struct Ws {
   int *ph_cnt, *ph_off, *ph_cur, *ph_list;      // seeds using each pixel hit
   // pixel triplets / quintuplets
   int *pt3_cnt, *pt3_off, *pt5_cnt, *pt5_off;
-  int *t5_cache;               // per T3: up to kT5Cache passing outer triplets
   int *pt3_cache, *pt5_cache;  // per seed: up to kPtCache passing objects found by the count pass
   int2 *pt3_so, *pt5_so;      // seed, object
   float4 *pt3_attr, *pt5_attr;
