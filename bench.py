@@ -135,6 +135,11 @@ def percentiles(x_ms):
 def run_trace(lst, g, dev, n_streams, max_batch, pool_bytes, arrivals, ids):
     """Open-loop replay: request i (event ids[i]) arrives at arrivals[i] on the server clock."""
     srv = lst.Server(g, n_streams, max_batch, pool_bytes)
+    # warm-up: every stream runs full batches once before the timed trace
+    n_warm = n_streams * max_batch * 2
+    for i in range(n_warm):
+        srv.submit(dev[ids[i % len(ids)]], -1 - i, 0.0)
+    srv.drain(n_warm, lambda r: lst.lst_release_event(r["event"]) if r["event"] else None, timeout_s=300.0)
     t0 = srv.now() + 0.05
     for i, (a, k) in enumerate(zip(arrivals, ids)):
         srv.submit(dev[k], i, t0 + a)
