@@ -103,11 +103,12 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   Ws t{};
   t.ctr = ctr;
   t.bcnt = I(2 * M + 1); t.boff = I(2 * M + 1); t.bcur = I(2 * M);
-  t.hidx_tmp = I(N + 1); t.hidx = I(N + 1); t.hpos = F4(N + 1);
+  t.hidx_tmp = I(N + 1); t.hidx = I(N + 1); t.hpos = F4(N + 1); t.hslot = I(N + 1);
   t.md_cnt = I(M + 1); t.md_off = I(M + 1);
   t.md_hits = I2(md); t.md_mod = I(md); t.md_pos = F4(md); t.md_stub = F2(md); t.mod_disc = F4(M);
   t.ls_cnt = I(md + 1); t.ls_off = I(md + 1); t.ls_md = I2(ls); t.ls_beta = F2(ls);
   t.ls_cache = I(kLsCache * md);
+  t.ls_ovf_flag = I(md + 1); t.ls_ovf_off = I(md + 1); t.ls_ovf = I(md);
   t.t3_cnt = I(ls + 1); t.t3_off = I(ls + 1); t.t3_md = I4(t3); t.t3_attr = F4(t3); t.t3_first = F2(t3);
   t.t5_cnt = I(t3 + 1); t.t5_off = I(t3 + 1); t.t5_t3 = I2(t5); t.t5_md = I(5 * t5); t.t5_attr = F(8 * t5);
   t.t5_keep = I(t5); t.t5_first = F2(t5);
@@ -116,6 +117,7 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.ph_cnt = I(N + 1); t.ph_off = I(N + 1); t.ph_cur = I(N + 1); t.ph_list = I(4 * S);
   t.pt3_cnt = I(S + 1); t.pt3_off = I(S + 1); t.pt5_cnt = I(S + 1); t.pt5_off = I(S + 1);
   t.pt3_cache = I(kPtCache * S); t.pt5_cache = I(kPtCache * S);
+  t.pt3_cattr = F4(kPtCache * S); t.pt5_cattr = F4(kPtCache * S);
   t.pt3_so = I2(p3); t.pt5_so = I2(p5); t.pt3_attr = F4(p3); t.pt5_attr = F4(p5);
   t.pt3_keep = I(p3); t.pt5_keep = I(p5);
   t.o3_cnt = I(t3 + 1); t.o3_off = I(t3 + 1); t.o3_cur = I(t3 + 1); t.o3_list = I(p3);
@@ -164,6 +166,7 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
     sj(SC_FPLS, t.f_pls, t.p_pls, nullptr, S, S, ct + C_NTC3, nullptr, 0);
     sj(SC_B3, t.b3_cnt, t.b3_off, nullptr, nbins, nbins, ct + C_NB3, nullptr, 0);
     sj(SC_B5, t.b5_cnt, t.b5_off, nullptr, nbins, nbins, ct + C_NB5, nullptr, 0);
+    sj(SC_LSOVF, t.ls_ovf_flag, t.ls_ovf_off, ct + C_NMD, 0, md, ct + C_NLSOVF, nullptr, 0);
     auto fj = [&](int id, int *p, long n) { t.fills[id] = FillJob{p, n}; };
     fj(FL_CTR, ct, C_COUNT);
     fj(FL_BCNT, t.bcnt, 2 * M + 1);

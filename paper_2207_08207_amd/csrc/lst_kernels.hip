@@ -213,11 +213,13 @@ __global__ void k_hits_count(const Ws *__restrict__ wb, int n_mod) {
     const int m = w.module[i];
     const float x = w.x[i], y = w.y[i], z = w.z[i];
     bool bad = !(isfinite(x) && isfinite(y) && isfinite(z)) || m < -1 || m >= n_mod;
+    int slot = -1;
     if (m >= 0) {
       const int sn = w.sensor[i];
       bad |= (sn != 0 && sn != 1);
-      if (!bad) atomicAdd(&w.bcnt[2 * m + sn], 1);
+      if (!bad) slot = atomicAdd(&w.bcnt[2 * m + sn], 1);
     }
+    w.hslot[i] = slot;  // arrival order in the bucket; k_bucket_sort restores input order
     if (bad) atomicOr(&w.ctr[C_STATUS], (int)ST_BAD_HIT);
   }
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
@@ -235,15 +237,9 @@ __global__ void k_hits_count(const Ws *__restrict__ wb, int n_mod) {
 __global__ void k_hits_scatter(const Ws *__restrict__ wb, int n_mod) {
   const Ws &w = wb[blockIdx.y];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < w.n_hits; i += gridDim.x * blockDim.x) {
-    const int m = w.module[i];
-    if (m < 0 || m >= n_mod) continue;
-    const int sn = w.sensor[i];
-    if (sn != 0 && sn != 1) continue;
-    const float x = w.x[i], y = w.y[i], z = w.z[i];
-    if (!(isfinite(x) && isfinite(y) && isfinite(z))) continue;
-    const int key = 2 * m + sn;
-    const int slot = atomicAdd(&w.bcur[key], 1);
-    w.hidx_tmp[w.boff[key] + slot] = i;
+    const int slot = w.hslot[i];  // >= 0 only for a valid outer-tracker hit
+    if (slot < 0) continue;
+    w.hidx_tmp[w.boff[2 * w.module[i] + w.sensor[i]] + slot] = i;
   }
 }
 
@@ -254,7 +250,20 @@ __global__ void k_bucket_sort(const Ws *__restrict__ wb, int n_buckets) {
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (wave >= n_buckets) return;
   const int b0 = w.boff[wave], n = w.boff[wave + 1] - b0;
-  for (int k = lane_id(); k < n; k += 64) {
+  const int lane = lane_id();
+  if (n <= 64) {
+    // the bucket in registers, one hit per lane; ranks by shuffles
+    const int me = lane < n ? w.hidx_tmp[b0 + lane] : 0x7fffffff;
+    int rank = 0;
+    for (int j = 0; j < n; ++j) rank += __shfl(me, j, 64) < me ? 1 : 0;
+    if (lane < n) {
+      const float x = w.x[me], y = w.y[me], z = w.z[me];
+      w.hidx[b0 + rank] = me;
+      w.hpos[b0 + rank] = make_float4(x, y, z, sqrtf(x * x + y * y));
+    }
+    return;
+  }
+  for (int k = lane; k < n; k += 64) {
     const int me = w.hidx_tmp[b0 + k];
     int rank = 0;
     for (int j = 0; j < n; ++j) rank += (w.hidx_tmp[b0 + j] < me) ? 1 : 0;
@@ -396,26 +405,13 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
   const int wv = threadIdx.x >> 6, lane = lane_id();
   const int wpb = blockDim.x >> 6;  // waves per block (a tuned launch may run fewer than kWaves)
   const int waves_total = gridDim.x * wpb;
-  for (int a = blockIdx.x * wpb + wv; a < n_md; a += waves_total) {
+  // COUNT: every MD.  FILL: only the MDs with more segments than the count pass
+  // cached (k_ls_copy writes the others and lists these densely).
+  auto process = [&](const int a) {
     const int ma = w.md_mod[a];
     const float4 A = w.md_pos[a];
     const float2 sa = w.md_stub[a];
     const ModInfo mia{g.info[ma]};
-    if (FILL) {
-      // the count pass cached up to kLsCache passing partners in candidate order
-      const int n_pass = w.ls_cnt[a];
-      if (n_pass <= kLsCache) {
-        const int out0 = w.ls_off[a];
-        for (int i = lane; i < n_pass; i += 64) {
-          const int b = w.ls_cache[(long)a * kLsCache + i];
-          if (out0 + i < w.cap_ls) {
-            w.ls_md[out0 + i] = make_int2(a, b);
-            w.ls_beta[out0 + i] = ls_beta(A, w.md_pos[b]);  // as ls_pass reports them
-          }
-        }
-        continue;
-      }
-    }
     const int e0 = g.map_off[ma];
     const int ne = g.map_off[ma + 1] - e0;  // <= kMaxEdges, checked when the geometry is loaded
     // per-edge MD ranges and their exclusive prefix over the wave
@@ -523,9 +519,18 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
       }
     }
     if (nq > 0) select(nq);
-    if (!FILL && lane == 0) w.ls_cnt[a] = cnt;
+    if (!FILL && lane == 0) {
+      w.ls_cnt[a] = cnt;
+      w.ls_ovf_flag[a] = cnt > kLsCache ? 1 : 0;
+    }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
+  };
+  if constexpr (!FILL) {
+    for (int a = blockIdx.x * wpb + wv; a < n_md; a += waves_total) process(a);
+  } else {
+    const int n_ovf = w.ctr[C_NLSOVF];
+    for (int k = blockIdx.x * wpb + wv; k < n_ovf; k += waves_total) process(w.ls_ovf[k]);
   }
 }
 
@@ -558,6 +563,27 @@ __device__ __forceinline__ int wave_segments(int n, int *seg) {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
   return total;
+}
+
+// Segments of the MDs whose partners the count pass cached: one thread per
+// (MD, cache slot), in candidate order, with the angles ls_pass reports.
+__global__ void k_ls_copy(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
+  const long n = (long)w.ctr[C_NMD] * kLsCache;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const int a = (int)(i / kLsCache), k = (int)(i % kLsCache);
+    const int cnt = w.ls_cnt[a];
+    if (cnt > kLsCache) {
+      if (k == 0) w.ls_ovf[w.ls_ovf_off[a]] = a;  // searched again by k_ls<true>
+      continue;
+    }
+    if (k >= cnt) continue;
+    const int pos = w.ls_off[a] + k;
+    if (pos >= w.cap_ls) continue;
+    const int b = w.ls_cache[i];
+    w.ls_md[pos] = make_int2(a, b);
+    w.ls_beta[pos] = ls_beta(w.md_pos[a], w.md_pos[b]);
+  }
 }
 
 // ------------------------------------------------------------- a3: T3
@@ -1021,24 +1047,23 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   if (s >= w.n_seeds) return;
   const Seed sd = load_seed(w, s);
   int *cache = (K == 3 ? w.pt3_cache : w.pt5_cache) + (long)s * kPtCache;
+  float4 *cattr = (K == 3 ? w.pt3_cattr : w.pt5_cattr) + (long)s * kPtCache;
   if constexpr (FILL) {
-    // the count pass cached every passing object of this seed: rank them by index, no search
+    // the count pass cached every passing object of this seed with its attributes:
+    // rank them by object index (in LDS) and copy, no search
     const int expect = (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s];
     if (expect <= kPtCache) {
+      const int t = lane < expect ? cache[lane] : 0;
+      if (lane < expect) s_list[wv][lane] = t;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
       if (lane < expect) {
-        const int t = cache[lane];
         int rank = 0;
-        for (int q = 0; q < expect; ++q) rank += cache[q] < t ? 1 : 0;
+        for (int q = 0; q < expect; ++q) rank += s_list[wv][q] < t ? 1 : 0;
         const int pos = (K == 3 ? w.pt3_off : w.pt5_off)[s] + rank;
         if (pos < (K == 3 ? w.cap_pt3 : w.cap_pt5)) {
-          float4 P[K];
-          ModInfo M[K];
-          float kT, dkT;
-          float4 attr;
-          load_object<K>(w, g, t, P, M, &kT, &dkT);
-          pt_pass<K>(sd, P, M, kT, dkT, &attr);
           (K == 3 ? w.pt3_so : w.pt5_so)[pos] = make_int2(s, t);
-          (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = attr;
+          (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = cattr[lane];
         }
       }
       return;
@@ -1073,6 +1098,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   auto test = [&](bool active, int j) {
     bool pass = false;
     int t = 0;
+    float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
     if (active) {
       t = blst[j];
       const float4 f = bpos[j];
@@ -1080,7 +1106,6 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
         float4 P[K];
         ModInfo M[K];
         float kT, dkT;
-        float4 attr;
         load_object<K>(w, g, t, P, M, &kT, &dkT);
         pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
       }
@@ -1092,6 +1117,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
         if (n_pass + pre < kPassList) s_list[wv][n_pass + pre] = t;
       } else if (n_pass + pre < kPtCache) {
         cache[n_pass + pre] = t;
+        cattr[n_pass + pre] = attr;
       }
     }
     n_pass += __popcll(m);
@@ -1584,7 +1610,11 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   // a2: LS
   run([&] { k_ls<false><<<gridwt(b.cap_md), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_LS, b.cap_md, st); });
-  run([&] { k_ls<true><<<gridwt(b.cap_md), tb, 0, st>>>(wb, g); });
+  run([&] {
+    scan(wb, B, SC_LSOVF, b.cap_md, st);
+    k_ls_copy<<<gridt((long)b.cap_md * kLsCache), tb, 0, st>>>(wb);
+    k_ls<true><<<gridwt(b.cap_md < 16384 ? b.cap_md : 16384), tb, 0, st>>>(wb, g);  // the overflow MDs
+  });
   // a3: T3
   run([&] { k_t3<false><<<gridwt((b.cap_ls + 63) / 64), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_T3, b.cap_ls, st); });

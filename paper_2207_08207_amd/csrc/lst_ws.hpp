@@ -14,6 +14,7 @@ enum Ctr : int {
   C_NT5KEEP = 15, C_NTC0 = 16, C_NTC1, C_NTC2, C_NTC3,                 // survivors, TCs per type
   C_NOUTER = 20, C_NINC = 21, C_NPH = 22, C_NO3 = 23, C_NO5 = 24,      // scratch totals
   C_NB3 = 25, C_NB5 = 26,
+  C_NLSOVF = 27,                 // MDs with more segments than the count pass caches
   C_COUNT = 64
 };
 enum : int { ST_BAD_HIT = 1, ST_BAD_SEED = 2, ST_CAPACITY = 4 };
@@ -38,7 +39,7 @@ struct ScanJob {
 };
 enum ScanId : int {
   SC_HITS, SC_MD, SC_LS, SC_T3, SC_T5, SC_INC, SC_PH, SC_PT3, SC_PT5, SC_O3, SC_O5,
-  SC_F5, SC_F3, SC_FT5, SC_FPLS, SC_B3, SC_B5, SC_COUNT
+  SC_F5, SC_F3, SC_FT5, SC_FPLS, SC_B3, SC_B5, SC_LSOVF, SC_COUNT
 };
 // One array cleared to zero at the start of the chain.
 struct FillJob {
@@ -72,6 +73,7 @@ struct Ws {
   int *ctr;
   // hit buckets by (module, sensor)
   int *bcnt, *boff, *bcur, *hidx_tmp, *hidx;
+  int *hslot;  // per input hit: its arrival slot in its (module, sensor) bucket, -1 if none
   float4 *hpos;
   // mini-doublets
   int *md_cnt, *md_off;
@@ -83,6 +85,7 @@ struct Ws {
   // segments
   int *ls_cnt, *ls_off;
   int *ls_cache;    // per MD: up to 16 passing partners found by the count pass
+  int *ls_ovf_flag, *ls_ovf_off, *ls_ovf;  // MDs with more: flag, its scan, the dense list
   int2 *ls_md;
   float2 *ls_beta;
   // triplets
@@ -105,6 +108,7 @@ struct Ws {
   // pixel triplets / quintuplets
   int *pt3_cnt, *pt3_off, *pt5_cnt, *pt5_off;
   int *pt3_cache, *pt5_cache;  // per seed: up to kPtCache passing objects found by the count pass
+  float4 *pt3_cattr, *pt5_cattr;  // and their attributes
   int2 *pt3_so, *pt5_so;      // seed, object
   float4 *pt3_attr, *pt5_attr;
   int *pt3_keep, *pt5_keep;
