@@ -273,7 +273,8 @@ def main():
         lst.lst_set_timed_site(-1)
         dom = int(np.argmax(per_site))
         log("bench: site ms (2 events): " + ", ".join(f"{sites[k]}={per_site[k] / 2:.3f}"
-                                                      for k in np.argsort(-per_site)[:8]))
+                                                      for k in np.argsort(-per_site)))
+        log(f"bench: sum of site times {per_site.sum() / 2:.3f} ms per event")
 
     def event_bytes(ev, c):
         cc = dict(md=int(c[0]), ls=int(c[1]), t3=int(c[2]), t5=int(c[3]), pt3=int(c[5]), pt5=int(c[6]))

@@ -769,26 +769,46 @@ __device__ __forceinline__ bool better(float su, const int *hu, float st, const 
 }
 
 // A T5 is dropped when another T5 sharing at least two MDs has a smaller (chi2_xy, hit tuple).
-// One thread per (T5 t, k < 4): the T5s u listed at t's k-th MD that share at
-// least two MDs with t and whose first MD in common with t's first four is
-// that k-th one (so each pair is judged once).  A duplicate shares two of the
-// five MDs, hence one of the first four.  t5_keep starts at 1 (written by the
-// fill) and a strictly better duplicate clears it.
-__global__ void k_t5_dedup(const Ws *__restrict__ wb) {
+// Items (T5 t, k < 4); an item's candidates are the T5s u listed at t's k-th
+// MD, and u is judged there only if it shares at least two MDs with t and its
+// first MD in common with t's first four is that k-th one (so each pair is
+// judged once; a duplicate shares two of the five MDs, hence one of the first
+// four).  Flattened as in the T3/T5 searches: a wave takes 64 items, stages
+// their MDs in LDS and strides all (item, candidate) pairs with its lanes.
+// t5_keep starts at 1 (written by the fill); a strictly better duplicate
+// clears it (every writer writes 0).
+__global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
+  __shared__ int s_mt[kWaves][5][64], s_lo[kWaves][64], s_seg[kWaves][65];
+  __shared__ float s_st[kWaves][64];
   const int n = w.ctr[C_NT5];
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < 4L * n; i += (long)gridDim.x * blockDim.x) {
-    const int t = (int)(i >> 2), k = (int)(i & 3);
-    int mt[5];
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int wpb = blockDim.x >> 6;
+  for (long p0 = ((long)blockIdx.x * wpb + wv) * 64; p0 < 4L * n; p0 += (long)gridDim.x * wpb * 64) {
+    const long item = p0 + lane;
+    int cnt = 0;
+    if (item < 4L * n) {
+      const int t = (int)(item >> 2), k = (int)(item & 3);
+      int mt[5];
 #pragma unroll
-    for (int j = 0; j < 5; ++j) mt[j] = w.t5_md[5 * (long)t + j];
-    if (k == 0) w.t5_first[t] = make_float2(w.md_pos[mt[0]].x, w.md_pos[mt[0]].y);
-    const int md = mt[k];
-    const float st = w.t5_attr[8 * (long)t + 1];
-    bool have_ht = false;
-    int ht[10];
-    for (int q = w.inc_off[md]; q < w.inc_off[md + 1]; ++q) {
-      const int u = w.inc_list[q];
+      for (int j = 0; j < 5; ++j) {
+        mt[j] = w.t5_md[5 * (long)t + j];
+        s_mt[wv][j][lane] = mt[j];
+      }
+      if (k == 0) w.t5_first[t] = make_float2(w.md_pos[mt[0]].x, w.md_pos[mt[0]].y);
+      const int lo = w.inc_off[mt[k]];
+      s_lo[wv][lane] = lo;
+      cnt = w.inc_off[mt[k] + 1] - lo;
+      s_st[wv][lane] = w.t5_attr[8 * (long)t + 1];
+    }
+    const int total = wave_segments(cnt, s_seg[wv]);
+    int e = 0;
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      if (c >= total) continue;
+      while (s_seg[wv][e + 1] <= c) ++e;
+      const int t = (int)((p0 + e) >> 2), k = (int)((p0 + e) & 3);
+      const int u = w.inc_list[s_lo[wv][e] + (c - s_seg[wv][e])];
       if (u == t) continue;
       int mu[5];
 #pragma unroll
@@ -796,22 +816,19 @@ __global__ void k_t5_dedup(const Ws *__restrict__ wb) {
       int shared = 0, first = 5;
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
-        const bool in = mt[j] == mu[0] || mt[j] == mu[1] || mt[j] == mu[2] || mt[j] == mu[3] || mt[j] == mu[4];
+        const int v = s_mt[wv][j][e];
+        const bool in = v == mu[0] || v == mu[1] || v == mu[2] || v == mu[3] || v == mu[4];
         shared += in ? 1 : 0;
         first = (in && first == 5) ? j : first;
       }
       if (shared < 2 || first != k) continue;
-      if (!have_ht) {
-        t5_hits(w, t, ht);
-        have_ht = true;
-      }
-      int hu[10];
+      int ht[10], hu[10];
+      t5_hits(w, t, ht);
       t5_hits(w, u, hu);
-      if (better<10>(w.t5_attr[8 * (long)u + 1], hu, st, ht)) {
-        w.t5_keep[t] = 0;
-        break;
-      }
+      if (better<10>(w.t5_attr[8 * (long)u + 1], hu, s_st[wv][e], ht)) w.t5_keep[t] = 0;
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -1041,6 +1058,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   __shared__ int s_sl_j0[kWaves][kMaxSlices];       // bin id, then first list entry, of each slice
   __shared__ int s_sl_pre[kWaves][kMaxSlices + 1];  // candidates before each slice
   __shared__ int s_list[FILL ? kWaves : 1][FILL ? kPassList : 1];
+  __shared__ int s_pq[kWaves][128];  // candidates past the first-anchor test, awaiting the full one
   const Ws &w = wb[blockIdx.y];
   const int wv = threadIdx.x >> 6, lane = lane_id();
   const int s = blockIdx.x * (int)(blockDim.x >> 6) + wv;
@@ -1095,20 +1113,19 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   // one candidate: the object at list entry j, tested against the seed; passing ones are
   // counted in ballot order and remembered (count: the cache; fill: the LDS list)
   const float4 *bpos = K == 3 ? w.b3_pos : w.b5_pos;
-  auto test = [&](bool active, int j) {
+  // the full selection on the first n (<= 64) queued objects; passing ones are counted
+  // in ballot order and remembered (count: the cache; fill: the LDS list)
+  auto full = [&](int n) {
     bool pass = false;
     int t = 0;
     float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (active) {
-      t = blst[j];
-      const float4 f = bpos[j];
-      if (pt_first_anchor(sd, f, ModInfo{__float_as_int(f.w)})) {
-        float4 P[K];
-        ModInfo M[K];
-        float kT, dkT;
-        load_object<K>(w, g, t, P, M, &kT, &dkT);
-        pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
-      }
+    if (lane < n) {
+      t = s_pq[wv][lane];
+      float4 P[K];
+      ModInfo M[K];
+      float kT, dkT;
+      load_object<K>(w, g, t, P, M, &kT, &dkT);
+      pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
     }
     const unsigned long long m = __ballot(pass);
     if (pass) {
@@ -1121,6 +1138,36 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
       }
     }
     n_pass += __popcll(m);
+  };
+  // one candidate per lane (list entry j): the exact first-anchor part of the selection
+  // from the packed anchor; objects passing it are queued, and the full selection runs
+  // on full waves of them
+  int nq = 0;
+  auto test = [&](bool active, int j) {
+    bool keep = false;
+    int t = 0;
+    if (active) {
+      t = blst[j];
+      const float4 f = bpos[j];
+      keep = pt_first_anchor(sd, f, ModInfo{__float_as_int(f.w)});
+    }
+    const unsigned long long m = __ballot(keep);
+    if (keep)
+      s_pq[wv][nq + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = t;
+    nq += __popcll(m);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (nq >= 64) {
+      full(64);
+      const int rest = nq - 64;  // < 64: move the queue's tail to its front
+      const int v = lane < rest ? s_pq[wv][64 + lane] : 0;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (lane < rest) s_pq[wv][lane] = v;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      nq = rest;
+    }
   };
   bool flat = false;
   if (listed) {
@@ -1186,6 +1233,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   }
   if (listed && !flat) {
     n_pass = 0;
+    nq = 0;
     for (int wd = 0; wd < kMaskWords; ++wd) {
       unsigned bits = mask[wd];
       while (bits) {
@@ -1198,6 +1246,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
       }
     }
   }
+  if (listed && nq > 0) full(nq);
   if (!FILL) {
     if (lane == 0) (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s] = n_pass;
     return;
@@ -1630,7 +1679,7 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   });
   run([&] { scan(wb, B, SC_INC, b.cap_md, st); });
   run([&] { k_t5_inc_scatter<<<grid(b.cap_t5), kBlock, 0, st>>>(wb); });
-  run([&] { k_t5_dedup<<<gridt(4L * b.cap_t5), tb, 0, st>>>(wb); });
+  run([&] { k_t5_dedup<<<gridwt((4L * b.cap_t5 + 63) / 64), tb, 0, st>>>(wb); });
   // a6: pLS
   run([&] {
     k_clear<<<grid(N + 1), kBlock, 0, st>>>(wb, FL_PH_CNT, FL_PH_CUR + 1);
