@@ -22,24 +22,9 @@ constexpr int kScanTile = kBlock * kScanItems;      // per block
 constexpr int kMaxScanBlocks = 4096;                // second level handled by one block
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
-
-// Exclusive prefix of `flag` over the block in thread order; *total = block count.
-__device__ __forceinline__ int block_prefix(bool flag, int *s_wave, int *total) {
-  const unsigned long long m = __ballot(flag);
-  const int wid = threadIdx.x >> 6;
-  const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-  if (lane_id() == 0) s_wave[wid] = __popcll(m);
-  __syncthreads();
-  int base = 0, tot = 0;
-#pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    const int c = s_wave[w];
-    base += (w < wid) ? c : 0;
-    tot += c;
-  }
-  __syncthreads();
-  *total = tot;
-  return base + pre;
+// Set bits of a ballot below this lane (its rank among the set lanes).
+__device__ __forceinline__ int lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
 __device__ __forceinline__ int block_sum(int v, int *s_red) {
@@ -274,85 +259,79 @@ __global__ void k_bucket_sort(const Ws *__restrict__ wb, int n_buckets) {
 }
 
 // ------------------------------------------------------------- a1: MD
-constexpr int kMdStage = 512;  // hits per sensor staged in LDS
+constexpr int kMdStage = 128;  // hits per sensor staged in LDS per wave (more: read from HBM)
 
-// One block per module; pairs (lower i, upper j) in row-major order.
+// One wave per module; pairs (lower i, upper j) in row-major order, 64 at a
+// time, compacted in order by ballot.  The fill also writes the module's
+// anchor disc for the segment stage's module-level azimuth pre-test.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
-  __shared__ float4 s_lo[kMdStage], s_up[kMdStage];
-  __shared__ int s_wave[kWaves];
-  const int m = blockIdx.x;
-  const int lo0 = w.boff[2 * m], nlo = w.boff[2 * m + 1] - lo0;
-  const int up0 = w.boff[2 * m + 1], nup = w.boff[2 * m + 2] - up0;
-  const long npair = (long)nlo * nup;
-  if (npair == 0) {
-    if (!FILL && threadIdx.x == 0) w.md_cnt[m] = 0;
-    return;
-  }
-  for (int k = threadIdx.x; k < nlo && k < kMdStage; k += kBlock) s_lo[k] = w.hpos[lo0 + k];
-  for (int k = threadIdx.x; k < nup && k < kMdStage; k += kBlock) s_up[k] = w.hpos[up0 + k];
-  __syncthreads();
-  const float4 win = g.win[m];
-  const ModInfo mi{g.info[m]};
-  int base = FILL ? w.md_off[m] : 0;
-  int cnt = 0;
-  for (long p0 = 0; p0 < npair; p0 += kBlock) {
-    const long p = p0 + threadIdx.x;
-    bool pass = false;
-    int i = 0, j = 0;
-    float4 hi, hj;
-    if (p < npair) {
-      i = (int)(p / nup);
-      j = (int)(p - (long)i * nup);
-      hi = i < kMdStage ? s_lo[i] : w.hpos[lo0 + i];
-      hj = j < kMdStage ? s_up[j] : w.hpos[up0 + j];
-      pass = md_pass(hi, hj, win, mi);
+  __shared__ float4 s_lo[kWaves][kMdStage], s_up[kWaves][kMdStage];
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int wpb = blockDim.x >> 6;
+  for (int m = blockIdx.x * wpb + wv; m < g.n_mod; m += gridDim.x * wpb) {
+    const int lo0 = w.boff[2 * m], nlo = w.boff[2 * m + 1] - lo0;
+    const int up0 = w.boff[2 * m + 1], nup = w.boff[2 * m + 2] - up0;
+    const long npair = (long)nlo * nup;
+    if (npair == 0) {
+      if (!FILL && lane == 0) w.md_cnt[m] = 0;
+      continue;
+    }
+    for (int k = lane; k < nlo && k < kMdStage; k += 64) s_lo[wv][k] = w.hpos[lo0 + k];
+    for (int k = lane; k < nup && k < kMdStage; k += 64) s_up[wv][k] = w.hpos[up0 + k];
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const float4 win = g.win[m];
+    const ModInfo mi{g.info[m]};
+    int base = FILL ? w.md_off[m] : 0;
+    for (long p0 = 0; p0 < npair; p0 += 64) {
+      const long p = p0 + lane;
+      bool pass = false;
+      int i = 0, j = 0;
+      float4 hi, hj;
+      if (p < npair) {
+        i = (int)(p / nup);
+        j = (int)(p - (long)i * nup);
+        hi = i < kMdStage ? s_lo[wv][i] : w.hpos[lo0 + i];
+        hj = j < kMdStage ? s_up[wv][j] : w.hpos[up0 + j];
+        pass = md_pass(hi, hj, win, mi);
+      }
+      const unsigned long long bm = __ballot(pass);
+      if (FILL && pass) {
+        const int pos = base + lanes_below(bm);
+        if (pos < w.cap_md) {
+          w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
+          w.md_mod[pos] = m;
+          w.md_pos[pos] = hi;
+          w.md_stub[pos] = md_stub(hi, hj, mi);
+        }
+      }
+      base += __popcll(bm);
     }
     if (!FILL) {
-      cnt += pass ? 1 : 0;
+      if (lane == 0) w.md_cnt[m] = base;
     } else {
-      int tot;
-      const int pos = base + block_prefix(pass, s_wave, &tot);
-      if (pass && pos < w.cap_md) {
-        w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
-        w.md_mod[pos] = m;
-        w.md_pos[pos] = hi;
-        w.md_stub[pos] = md_stub(hi, hj, mi);
+      // a disc in x-y around every anchor of this module (the lower hits' bounding box)
+      float x0 = 3.0e38f, x1 = -3.0e38f, y0 = 3.0e38f, y1 = -3.0e38f;
+      for (int k = lane; k < nlo; k += 64) {
+        const float4 h = k < kMdStage ? s_lo[wv][k] : w.hpos[lo0 + k];
+        x0 = fminf(x0, h.x); x1 = fmaxf(x1, h.x);
+        y0 = fminf(y0, h.y); y1 = fmaxf(y1, h.y);
       }
-      base += tot;
-    }
-  }
-  if (!FILL) {
-    cnt = block_sum(cnt, s_wave);
-    if (threadIdx.x == 0) w.md_cnt[m] = cnt;
-  } else {
-    // a disc in x-y around every anchor of this module (the lower hits' bounding box), for
-    // the segment stage's module-level azimuth pre-test
-    float x0 = 3.0e38f, x1 = -3.0e38f, y0 = 3.0e38f, y1 = -3.0e38f;
-    for (int k = threadIdx.x; k < nlo; k += kBlock) {
-      const float4 h = k < kMdStage ? s_lo[k] : w.hpos[lo0 + k];
-      x0 = fminf(x0, h.x); x1 = fmaxf(x1, h.x);
-      y0 = fminf(y0, h.y); y1 = fmaxf(y1, h.y);
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      x0 = fminf(x0, __shfl_xor(x0, o, 64)); x1 = fmaxf(x1, __shfl_xor(x1, o, 64));
-      y0 = fminf(y0, __shfl_xor(y0, o, 64)); y1 = fmaxf(y1, __shfl_xor(y1, o, 64));
-    }
-    __shared__ float4 s_box[kWaves];
-    const int wv = threadIdx.x >> 6;
-    if (lane_id() == 0) s_box[wv] = make_float4(x0, x1, y0, y1);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int k = 1; k < kWaves; ++k) {
-        x0 = fminf(x0, s_box[k].x); x1 = fmaxf(x1, s_box[k].y);
-        y0 = fminf(y0, s_box[k].z); y1 = fmaxf(y1, s_box[k].w);
+      for (int o = 32; o > 0; o >>= 1) {
+        x0 = fminf(x0, __shfl_xor(x0, o, 64)); x1 = fmaxf(x1, __shfl_xor(x1, o, 64));
+        y0 = fminf(y0, __shfl_xor(y0, o, 64)); y1 = fmaxf(y1, __shfl_xor(y1, o, 64));
       }
-      const float cx = 0.5f * (x0 + x1), cy = 0.5f * (y0 + y1);
-      const float hx = 0.5f * (x1 - x0), hy = 0.5f * (y1 - y0);
-      const float rho = sqrtf(hx * hx + hy * hy) * 1.0001f + 1e-3f;
-      w.mod_disc[m] = make_float4(cx, cy, rho, sqrtf(cx * cx + cy * cy));
+      if (lane == 0) {
+        const float cx = 0.5f * (x0 + x1), cy = 0.5f * (y0 + y1);
+        const float hx = 0.5f * (x1 - x0), hy = 0.5f * (y1 - y0);
+        const float rho = sqrtf(hx * hx + hy * hy) * 1.0001f + 1e-3f;
+        w.mod_disc[m] = make_float4(cx, cy, rho, sqrtf(cx * cx + cy * cy));
+      }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -543,9 +522,6 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
 // parent's count from earlier rounds plus the accepted pairs of the same
 // parent on lower lanes of this round (a parent's pairs are on consecutive
 // lanes).  COUNT writes the per-parent counts, FILL the objects.
-__device__ __forceinline__ int lanes_below(unsigned long long m) {
-  return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-}
 __device__ __forceinline__ int pair_rank(unsigned long long m, int seg_first_lane, int before_round) {
   return before_round + lanes_below(m) - __popcll(m & ((1ull << seg_first_lane) - 1ull));
 }
@@ -1613,7 +1589,7 @@ static_assert(sizeof(kSiteNames) / sizeof(kSiteNames[0]) <= kMaxSites, "launch-s
 // Sites whose kernels take any block of 64, 128 or 256 threads (grid-stride
 // loops over threads or waves, LDS sized for the largest block): the launch
 // shape the autotuner may choose.
-static const char *const kTunableSites[] = {"ls_count", "ls_fill",   "t3_count",  "t3_fill",  "t5_count",
+static const char *const kTunableSites[] = {"md_count", "md_fill",   "ls_count",  "ls_fill",  "t3_count",  "t3_fill",  "t5_count",
                                             "t5_fill",  "t5_dedup",  "pt3_count", "pt3_fill", "pt5_count",
                                             "pt5_fill", "tc_pt3",    "tc_t5",     "tc_pls"};
 
@@ -1653,9 +1629,9 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { k_hits_scatter<<<grid(N), kBlock, 0, st>>>(wb, M); });
   run([&] { k_bucket_sort<<<dim3((2 * M * 64 + kBlock - 1) / kBlock, B), kBlock, 0, st>>>(wb, 2 * M); });
   // a1: MD
-  run([&] { k_md<false><<<dim3(M, B), kBlock, 0, st>>>(wb, g); });
+  run([&] { k_md<false><<<gridwt(M), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_MD, M, st); });
-  run([&] { k_md<true><<<dim3(M, B), kBlock, 0, st>>>(wb, g); });
+  run([&] { k_md<true><<<gridwt(M), tb, 0, st>>>(wb, g); });
   // a2: LS
   run([&] { k_ls<false><<<gridwt(b.cap_md), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_LS, b.cap_md, st); });

@@ -38,7 +38,7 @@ def test_launch_shapes_do_not_change_results(lst, barrel, obarrel):
     g.set_launch_config({})
     assert set(g.launch_config().values()) == {256}
     with pytest.raises(lst.LSTError):
-        g.set_launch_config({"md_count": 64})  # a fixed-shape site
+        g.set_launch_config({"hits_count": 64})  # a fixed-shape site
     with pytest.raises(lst.LSTError):
         g.set_launch_config({"ls_count": 96})
 
