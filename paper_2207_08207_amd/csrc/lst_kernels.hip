@@ -260,10 +260,21 @@ __global__ void k_bucket_sort(const Ws *__restrict__ wb, int n_buckets) {
 
 // ------------------------------------------------------------- a1: MD
 constexpr int kMdStage = 128;  // hits per sensor staged in LDS per wave (more: read from HBM)
+constexpr long kMdBig = 2048;  // modules with more pairs go to a whole block (k_md_big)
+constexpr int kMdStageBig = 512;
 
-// One wave per module; pairs (lower i, upper j) in row-major order, 64 at a
-// time, compacted in order by ballot.  The fill also writes the module's
-// anchor disc for the segment stage's module-level azimuth pre-test.
+// Anchor disc of a module for the segment stage's module-level azimuth
+// pre-test, from the lower hits' bounding box (min/max reduced by the caller).
+__device__ __forceinline__ float4 anchor_disc(float x0, float x1, float y0, float y1) {
+  const float cx = 0.5f * (x0 + x1), cy = 0.5f * (y0 + y1);
+  const float hx = 0.5f * (x1 - x0), hy = 0.5f * (y1 - y0);
+  const float rho = sqrtf(hx * hx + hy * hy) * 1.0001f + 1e-3f;
+  return make_float4(cx, cy, rho, sqrtf(cx * cx + cy * cy));
+}
+
+// One wave per module of at most kMdBig pairs; pairs (lower i, upper j) in
+// row-major order, 64 at a time, compacted in order by ballot.  The fill also
+// writes the module's anchor disc.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
@@ -274,6 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
     const int lo0 = w.boff[2 * m], nlo = w.boff[2 * m + 1] - lo0;
     const int up0 = w.boff[2 * m + 1], nup = w.boff[2 * m + 2] - up0;
     const long npair = (long)nlo * nup;
+    if (npair > kMdBig) continue;  // k_md_big's
     if (npair == 0) {
       if (!FILL && lane == 0) w.md_cnt[m] = 0;
       continue;
@@ -323,15 +335,91 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
         x0 = fminf(x0, __shfl_xor(x0, o, 64)); x1 = fmaxf(x1, __shfl_xor(x1, o, 64));
         y0 = fminf(y0, __shfl_xor(y0, o, 64)); y1 = fmaxf(y1, __shfl_xor(y1, o, 64));
       }
-      if (lane == 0) {
-        const float cx = 0.5f * (x0 + x1), cy = 0.5f * (y0 + y1);
-        const float hx = 0.5f * (x1 - x0), hy = 0.5f * (y1 - y0);
-        const float rho = sqrtf(hx * hx + hy * hy) * 1.0001f + 1e-3f;
-        w.mod_disc[m] = make_float4(cx, cy, rho, sqrtf(cx * cx + cy * cy));
-      }
+      if (lane == 0) w.mod_disc[m] = anchor_disc(x0, x1, y0, y1);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// The same for the modules with more than kMdBig pairs, one block (kBlock
+// threads) each, so that no single wave carries a dense module.
+template <bool FILL>
+__global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, DevGeom g) {
+  const Ws &w = wb[blockIdx.y];
+  __shared__ float4 s_lo[kMdStageBig], s_up[kMdStageBig];
+  __shared__ int s_wave[kWaves];
+  __shared__ float4 s_box[kWaves];
+  const int wid = threadIdx.x >> 6, lane = lane_id();
+  for (int m = blockIdx.x; m < g.n_mod; m += gridDim.x) {
+    const int lo0 = w.boff[2 * m], nlo = w.boff[2 * m + 1] - lo0;
+    const int up0 = w.boff[2 * m + 1], nup = w.boff[2 * m + 2] - up0;
+    const long npair = (long)nlo * nup;
+    if (npair <= kMdBig) continue;
+    __syncthreads();  // the previous module's LDS reads are done
+    for (int k = threadIdx.x; k < nlo && k < kMdStageBig; k += kBlock) s_lo[k] = w.hpos[lo0 + k];
+    for (int k = threadIdx.x; k < nup && k < kMdStageBig; k += kBlock) s_up[k] = w.hpos[up0 + k];
+    __syncthreads();
+    const float4 win = g.win[m];
+    const ModInfo mi{g.info[m]};
+    int base = FILL ? w.md_off[m] : 0;
+    for (long p0 = 0; p0 < npair; p0 += kBlock) {
+      const long p = p0 + threadIdx.x;
+      bool pass = false;
+      int i = 0, j = 0;
+      float4 hi, hj;
+      if (p < npair) {
+        i = (int)(p / nup);
+        j = (int)(p - (long)i * nup);
+        hi = i < kMdStageBig ? s_lo[i] : w.hpos[lo0 + i];
+        hj = j < kMdStageBig ? s_up[j] : w.hpos[up0 + j];
+        pass = md_pass(hi, hj, win, mi);
+      }
+      // ordered compaction over the block: ballot per wave, wave totals in LDS
+      const unsigned long long bm = __ballot(pass);
+      if (lane == 0) s_wave[wid] = __popcll(bm);
+      __syncthreads();
+      int before = 0, tot = 0;
+#pragma unroll
+      for (int q = 0; q < kWaves; ++q) {
+        before += q < wid ? s_wave[q] : 0;
+        tot += s_wave[q];
+      }
+      __syncthreads();
+      if (FILL && pass) {
+        const int pos = base + before + lanes_below(bm);
+        if (pos < w.cap_md) {
+          w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
+          w.md_mod[pos] = m;
+          w.md_pos[pos] = hi;
+          w.md_stub[pos] = md_stub(hi, hj, mi);
+        }
+      }
+      base += tot;
+    }
+    if (!FILL) {
+      if (threadIdx.x == 0) w.md_cnt[m] = base;
+    } else {
+      float x0 = 3.0e38f, x1 = -3.0e38f, y0 = 3.0e38f, y1 = -3.0e38f;
+      for (int k = threadIdx.x; k < nlo; k += kBlock) {
+        const float4 h = k < kMdStageBig ? s_lo[k] : w.hpos[lo0 + k];
+        x0 = fminf(x0, h.x); x1 = fmaxf(x1, h.x);
+        y0 = fminf(y0, h.y); y1 = fmaxf(y1, h.y);
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        x0 = fminf(x0, __shfl_xor(x0, o, 64)); x1 = fmaxf(x1, __shfl_xor(x1, o, 64));
+        y0 = fminf(y0, __shfl_xor(y0, o, 64)); y1 = fmaxf(y1, __shfl_xor(y1, o, 64));
+      }
+      if (lane == 0) s_box[wid] = make_float4(x0, x1, y0, y1);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int q = 1; q < kWaves; ++q) {
+          x0 = fminf(x0, s_box[q].x); x1 = fmaxf(x1, s_box[q].y);
+          y0 = fminf(y0, s_box[q].z); y1 = fmaxf(y1, s_box[q].w);
+        }
+        w.mod_disc[m] = anchor_disc(x0, x1, y0, y1);
+      }
+    }
   }
 }
 
@@ -1629,9 +1717,15 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { k_hits_scatter<<<grid(N), kBlock, 0, st>>>(wb, M); });
   run([&] { k_bucket_sort<<<dim3((2 * M * 64 + kBlock - 1) / kBlock, B), kBlock, 0, st>>>(wb, 2 * M); });
   // a1: MD
-  run([&] { k_md<false><<<gridwt(M), tb, 0, st>>>(wb, g); });
+  run([&] {
+    k_md_big<false><<<dim3(1024, B), kBlock, 0, st>>>(wb, g);
+    k_md<false><<<gridwt(M), tb, 0, st>>>(wb, g);
+  });
   run([&] { scan(wb, B, SC_MD, M, st); });
-  run([&] { k_md<true><<<gridwt(M), tb, 0, st>>>(wb, g); });
+  run([&] {
+    k_md_big<true><<<dim3(1024, B), kBlock, 0, st>>>(wb, g);
+    k_md<true><<<gridwt(M), tb, 0, st>>>(wb, g);
+  });
   // a2: LS
   run([&] { k_ls<false><<<gridwt(b.cap_md), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_LS, b.cap_md, st); });
