@@ -63,7 +63,8 @@ typedef struct lst_server_s *lst_server;     /* opaque: a serving loop */
  *  pos_up   the same for the upper sensor
  *  lmin,lmax  range of the long coordinate: z in the barrel, r in the endcap [cm]
  *  map_offsets  n_modules + 1 CSR offsets; map_targets  n_edges module ids,
- *               the modules of the next surface linked to each module. */
+ *               the modules of the next surface linked to each module (at
+ *               most 128 per module; LST_E_INVALID otherwise). */
 typedef struct {
   int32_t n_modules;
   const int32_t *subdet, *layer, *side, *type;

@@ -245,8 +245,8 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   for (int e = 0; e < E; ++e)
     if (d->map_targets[e] < 0 || d->map_targets[e] >= M) return fail(LST_E_INVALID, "map target out of range");
   for (int m = 0; m < M; ++m)
-    if (d->map_offsets[m + 1] - d->map_offsets[m] > 256)
-      return fail(LST_E_INVALID, "more than 256 module-map targets for one module");
+    if (d->map_offsets[m + 1] - d->map_offsets[m] > 128)
+      return fail(LST_E_INVALID, "more than 128 module-map targets for one module");
   auto *g = new (std::nothrow) lst_geometry_s();
   if (!g) return fail(LST_E_NOMEM, "host allocation failed");
   std::vector<int> info(M);

@@ -453,7 +453,7 @@ __device__ __forceinline__ bool ls_window_may_pass(const float4 &A, const float4
   return fabsf(c) <= wmax * (A.w * B.w);
 }
 
-constexpr int kMaxEdges = 256;  // module-map targets per module handled by one wave
+constexpr int kMaxEdges = 128;  // module-map targets per module (checked when the geometry is loaded)
 
 // One wave per inner MD a.  Its candidates -- the MDs of every module linked
 // to a's module, edge by edge -- are flattened into one list that the 64
@@ -874,6 +874,10 @@ __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) 
       const int t = (int)((p0 + e) >> 2), k = (int)((p0 + e) & 3);
       const int u = w.inc_list[s_lo[wv][e] + (c - s_seg[wv][e])];
       if (u == t) continue;
+      // only a u that is not worse can drop t: the score first, then sharing, then on a
+      // tie of scores the hit tuples (the decision of better<10>, with fewer loads)
+      const float su = w.t5_attr[8 * (long)u + 1], st = s_st[wv][e];
+      if (st < su) continue;
       int mu[5];
 #pragma unroll
       for (int j = 0; j < 5; ++j) mu[j] = w.t5_md[5 * (long)u + j];
@@ -886,10 +890,14 @@ __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) 
         first = (in && first == 5) ? j : first;
       }
       if (shared < 2 || first != k) continue;
-      int ht[10], hu[10];
-      t5_hits(w, t, ht);
-      t5_hits(w, u, hu);
-      if (better<10>(w.t5_attr[8 * (long)u + 1], hu, s_st[wv][e], ht)) w.t5_keep[t] = 0;
+      bool drop = su < st;
+      if (!drop) {
+        int ht[10], hu[10];
+        t5_hits(w, t, ht);
+        t5_hits(w, u, hu);
+        drop = better<10>(su, hu, st, ht);
+      }
+      if (drop) w.t5_keep[t] = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1414,29 +1422,36 @@ __global__ void k_pt_dedup(const Ws *__restrict__ wb) {
   const int *olst = K == 3 ? w.o3_list : w.o5_list;
   int *keep = K == 3 ? w.pt3_keep : w.pt5_keep;
   constexpr int H = 2 * K + 1;
+  // The decision of better<H> on (score, seed, object hits), with the hit
+  // tuples read only when two scores are equal.
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int2 me = so[i];
-    int ti[H];
-    ti[0] = me.x;
-    obj_hits<K>(w, me.y, ti + 1);
     const float si = at[i].z;
-    bool kp = true;
+    bool kp = true, have_ti = false;
+    int ti[H];
     const int j1 = min(soff[me.x + 1], n);
-    for (int j = soff[me.x]; j < j1 && kp; ++j) {
+    for (int j = soff[me.x]; j < j1 && kp; ++j) {  // same seed
       if (j == i) continue;
-      int tj[H];
-      tj[0] = so[j].x;
-      obj_hits<K>(w, so[j].y, tj + 1);
-      if (better<H>(at[j].z, tj, si, ti)) kp = false;
+      const float sj = at[j].z;
+      if (sj < si) {
+        kp = false;
+      } else if (!(si < sj)) {
+        if (!have_ti) {
+          ti[0] = me.x;
+          obj_hits<K>(w, me.y, ti + 1);
+          have_ti = true;
+        }
+        int tj[H];
+        tj[0] = so[j].x;
+        obj_hits<K>(w, so[j].y, tj + 1);
+        if (better<H>(sj, tj, si, ti)) kp = false;
+      }
     }
-    for (int q = ooff[me.y]; q < ooff[me.y + 1] && kp; ++q) {
+    for (int q = ooff[me.y]; q < ooff[me.y + 1] && kp; ++q) {  // same object: the tuples differ in the seed only
       const int j = olst[q];
       if (j == i) continue;
-      int tj[H];
-      tj[0] = so[j].x;
-#pragma unroll
-      for (int k = 1; k < H; ++k) tj[k] = ti[k];
-      if (better<H>(at[j].z, tj, si, ti)) kp = false;
+      const float sj = at[j].z;
+      if (sj < si || (!(si < sj) && so[j].x < me.x)) kp = false;
     }
     keep[i] = kp ? 1 : 0;
   }
