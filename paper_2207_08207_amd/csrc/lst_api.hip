@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <algorithm>
+#include <unordered_map>
 #include <chrono>
 #include <deque>
 #include <map>
@@ -69,6 +70,7 @@ struct lst_batch_s {
   int timed_site = -1;      // launch site bracketed by tbeg/tend, or -1
   hipEvent_t tbeg = nullptr, tend = nullptr;
   lst_batch_s **owner = nullptr;  // a plan's pointer to its latest run, cleared when this batch is freed
+  int device = 0;                 // device current when the batch was made (its events belong to it)
 };
 
 struct lst_event_s {
@@ -335,6 +337,93 @@ static size_t batch_bytes(int n_mod, int B, const int32_t *nh, const int32_t *ns
   return off;
 }
 
+// Pinned host buffers and HIP events of freed batches, kept for the next batch
+// (allocating pinned memory costs far more than a batch's other host work).
+// Buffers are kept by power-of-two size class, events per device; at most
+// kPoolPinnedMax bytes of buffers are kept, the rest is freed.  Nothing is
+// released at process exit.
+constexpr int kPoolClasses = 24;               // size classes 2^0 .. 2^23 bytes
+constexpr size_t kPoolPinnedMax = 64u << 20;
+struct HostPool {
+  std::mutex mu;
+  std::vector<void *> pinned[kPoolClasses];
+  size_t pinned_bytes = 0;
+  std::unordered_map<int, std::vector<hipEvent_t>> sync_events, timing_events;
+};
+static HostPool &host_pool() {
+  static HostPool *p = new HostPool();  // never destroyed: no HIP calls during static teardown
+  return *p;
+}
+static int size_class(size_t n) {
+  int k = 0;
+  while (((size_t)1 << k) < n) ++k;
+  return k;
+}
+static void *pinned_get(size_t n) {
+  const int k = size_class(n);
+  if (k < kPoolClasses) {
+    HostPool &P = host_pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    if (!P.pinned[k].empty()) {
+      void *q = P.pinned[k].back();
+      P.pinned[k].pop_back();
+      P.pinned_bytes -= (size_t)1 << k;
+      return q;
+    }
+  }
+  void *q = nullptr;
+  if (hipHostMalloc(&q, k < kPoolClasses ? (size_t)1 << k : n, hipHostMallocDefault) != hipSuccess) return nullptr;
+  return q;
+}
+static void pinned_put(void *q, size_t n) {
+  if (!q) return;
+  const int k = size_class(n);
+  if (k < kPoolClasses) {
+    HostPool &P = host_pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    if (P.pinned_bytes + ((size_t)1 << k) <= kPoolPinnedMax) {
+      P.pinned[k].push_back(q);
+      P.pinned_bytes += (size_t)1 << k;
+      return;
+    }
+  }
+  drop(hipHostFree(q));
+}
+static hipEvent_t event_get(int device, bool timing) {
+  {
+    HostPool &P = host_pool();
+    std::lock_guard<std::mutex> lk(P.mu);
+    auto &v = (timing ? P.timing_events : P.sync_events)[device];
+    if (!v.empty()) {
+      hipEvent_t e = v.back();
+      v.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if ((timing ? hipEventCreate(&e) : hipEventCreateWithFlags(&e, hipEventDisableTiming)) != hipSuccess) return nullptr;
+  return e;
+}
+static void event_put(int device, hipEvent_t e, bool timing) {
+  if (!e) return;
+  HostPool &P = host_pool();
+  std::lock_guard<std::mutex> lk(P.mu);
+  auto &v = (timing ? P.timing_events : P.sync_events)[device];
+  if (v.size() < 4096) {
+    v.push_back(e);
+    return;
+  }
+  drop(hipEventDestroy(e));
+}
+// Pinned buffers and completion event of a new batch of B events (false on failure).
+static bool batch_host_resources(lst_batch_s *b, int B) {
+  if (hipGetDevice(&b->device) != hipSuccess) return false;
+  b->h_ctr = static_cast<int *>(pinned_get(sizeof(int) * lst::C_COUNT * B));
+  b->h_ws = static_cast<lst::Ws *>(pinned_get(sizeof(lst::Ws) * B));
+  b->done = event_get(b->device, false);
+  return b->h_ctr && b->h_ws && b->done;
+}
+
 static void server_release_batch(lst_server_s *s, lst_batch_s *b);
 
 static void release_batch_ref(lst_batch_s *b) {
@@ -342,11 +431,11 @@ static void release_batch_ref(lst_batch_s *b) {
   if (b->owner && *b->owner == b) *b->owner = nullptr;
   if (b->server) server_release_batch(b->server, b);
   if (!b->synced && b->done) drop(hipEventSynchronize(b->done));
-  if (b->tbeg) drop(hipEventDestroy(b->tbeg));
-  if (b->tend) drop(hipEventDestroy(b->tend));
-  if (b->done) drop(hipEventDestroy(b->done));
-  if (b->h_ctr) drop(hipHostFree(b->h_ctr));
-  if (b->h_ws) drop(hipHostFree(b->h_ws));
+  event_put(b->device, b->tbeg, true);
+  event_put(b->device, b->tend, true);
+  event_put(b->device, b->done, false);
+  pinned_put(b->h_ctr, sizeof(int) * lst::C_COUNT * b->B);
+  pinned_put(b->h_ws, sizeof(lst::Ws) * b->B);
   delete b;
 }
 
@@ -396,10 +485,7 @@ static lst_status enqueue_batch_at(lst_geometry g, int B, const lst_event_desc *
   b->B = B;
   b->stream = stream;
   b->refs = B;
-  if (hipHostMalloc(reinterpret_cast<void **>(&b->h_ctr), sizeof(int) * lst::C_COUNT * B, hipHostMallocDefault) !=
-          hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void **>(&b->h_ws), sizeof(lst::Ws) * B, hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+  if (!batch_host_resources(b, B)) {
     b->refs = 1;
     release_batch_ref(b);
     return fail(LST_E_DEVICE, "pinned buffers or event creation failed");
@@ -427,7 +513,7 @@ static lst_status enqueue_batch_at(lst_geometry g, int B, const lst_event_desc *
   }
   lst::KernelTimer kt{-1, nullptr, nullptr};
   const int site = timed_site >= -1 ? timed_site : g_timed_site.load();
-  if (site >= 0 && hipEventCreate(&b->tbeg) == hipSuccess && hipEventCreate(&b->tend) == hipSuccess) {
+  if (site >= 0 && (b->tbeg = event_get(b->device, true)) && (b->tend = event_get(b->device, true))) {
     kt = lst::KernelTimer{site, b->tbeg, b->tend};
     b->timed_site = site;
   }
@@ -759,10 +845,7 @@ lst_status lst_plan_run(lst_plan p, int32_t n_events, const lst_event_desc *evs,
   b->B = p->B;
   b->stream = stream ? reinterpret_cast<hipStream_t>(stream) : p->stream;
   b->refs = 1;  // creation reference, dropped at the end of this call
-  if (hipHostMalloc(reinterpret_cast<void **>(&b->h_ctr), sizeof(int) * lst::C_COUNT * p->B, hipHostMallocDefault) !=
-          hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void **>(&b->h_ws), sizeof(lst::Ws) * p->B, hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess) {
+  if (!batch_host_resources(b, p->B)) {
     release_batch_ref(b);
     return fail(LST_E_DEVICE, "lst_plan_run: pinned buffers or event creation failed");
   }
