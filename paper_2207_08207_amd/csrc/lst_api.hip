@@ -118,8 +118,8 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.pls = F(8 * S); t.pls_keep = I(S);
   t.ph_cnt = I(N + 1); t.ph_off = I(N + 1); t.ph_cur = I(N + 1); t.ph_list = I(4 * S);
   t.pt3_cnt = I(S + 1); t.pt3_off = I(S + 1); t.pt5_cnt = I(S + 1); t.pt5_off = I(S + 1);
-  t.pt3_cache = I(kPtCache * S); t.pt5_cache = I(kPtCache * S);
-  t.pt3_cattr = F4(kPtCache * S); t.pt5_cattr = F4(kPtCache * S);
+  t.pt3_cache = I(kPt3Cache * S); t.pt5_cache = I(kPt5Cache * S);
+  t.pt3_cattr = F4(kPt3Cache * S); t.pt5_cattr = F4(kPt5Cache * S);
   t.pt3_so = I2(p3); t.pt5_so = I2(p5); t.pt3_attr = F4(p3); t.pt5_attr = F4(p5);
   t.pt3_keep = I(p3); t.pt5_keep = I(p5);
   t.o3_cnt = I(t3 + 1); t.o3_off = I(t3 + 1); t.o3_cur = I(t3 + 1); t.o3_list = I(p3);

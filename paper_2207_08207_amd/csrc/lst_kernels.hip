@@ -1136,24 +1136,26 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   const int s = blockIdx.x * (int)(blockDim.x >> 6) + wv;
   if (s >= w.n_seeds) return;
   const Seed sd = load_seed(w, s);
-  int *cache = (K == 3 ? w.pt3_cache : w.pt5_cache) + (long)s * kPtCache;
-  float4 *cattr = (K == 3 ? w.pt3_cattr : w.pt5_cattr) + (long)s * kPtCache;
+  constexpr int kCache = K == 3 ? kPt3Cache : kPt5Cache;
+  static_assert(kCache <= kPassList, "the fill ranks the cache in its LDS list");
+  int *cache = (K == 3 ? w.pt3_cache : w.pt5_cache) + (long)s * kCache;
+  float4 *cattr = (K == 3 ? w.pt3_cattr : w.pt5_cattr) + (long)s * kCache;
   if constexpr (FILL) {
     // the count pass cached every passing object of this seed with its attributes:
     // rank them by object index (in LDS) and copy, no search
     const int expect = (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s];
-    if (expect <= kPtCache) {
-      const int t = lane < expect ? cache[lane] : 0;
-      if (lane < expect) s_list[wv][lane] = t;
+    if (expect <= kCache) {
+      for (int i = lane; i < expect; i += 64) s_list[wv][i] = cache[i];
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      if (lane < expect) {
+      for (int i = lane; i < expect; i += 64) {
+        const int t = s_list[wv][i];
         int rank = 0;
         for (int q = 0; q < expect; ++q) rank += s_list[wv][q] < t ? 1 : 0;
         const int pos = (K == 3 ? w.pt3_off : w.pt5_off)[s] + rank;
         if (pos < (K == 3 ? w.cap_pt3 : w.cap_pt5)) {
           (K == 3 ? w.pt3_so : w.pt5_so)[pos] = make_int2(s, t);
-          (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = cattr[lane];
+          (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = cattr[i];
         }
       }
       return;
@@ -1204,7 +1206,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
       if (FILL) {
         if (n_pass + pre < kPassList) s_list[wv][n_pass + pre] = t;
-      } else if (n_pass + pre < kPtCache) {
+      } else if (n_pass + pre < kCache) {
         cache[n_pass + pre] = t;
         cattr[n_pass + pre] = attr;
       }

@@ -51,18 +51,19 @@ enum FillId : int {
   FL_O5_CNT, FL_O5_CUR, FL_SEED_USED, FL_T5_USED, FL_B3_CNT, FL_B3_CUR, FL_B5_CNT, FL_B5_CUR, FL_COUNT
 };
 
-// Device pointers of one event (all inside the workspace except the inputs).
-// Kernels of a batch read descriptor blockIdx.y of a device array of these.
 // Passing partners remembered between a stage's count and fill passes: per MD
 // for segments, per seed for pT3 / pT5 (more than this: the fill searches again).
 constexpr int kLsCache = 16;
-constexpr int kPtCache = 64;  // one wave lane per cached object in the fill
+constexpr int kPt3Cache = 256;  // pT3 per seed (PU200 maximum ~190)
+constexpr int kPt5Cache = 16;   // pT5 per seed
 
 // First-anchor bins of the seed search: 10 radius rings x 256 azimuth bins x
 // 55 z bins (10 cm over |z| < 275 cm); bins of one (ring, azimuth) pair are
 // contiguous, z ascending.
 constexpr int kSeedBins = 10 * 256 * 55;
 
+// Device pointers of one event (all inside the workspace except the inputs).
+// Kernels of a batch read descriptor blockIdx.y of a device array of these.
 struct Ws {
   // inputs (device)
   int n_hits, n_seeds;
@@ -107,7 +108,7 @@ struct Ws {
   int *ph_cnt, *ph_off, *ph_cur, *ph_list;      // seeds using each pixel hit
   // pixel triplets / quintuplets
   int *pt3_cnt, *pt3_off, *pt5_cnt, *pt5_off;
-  int *pt3_cache, *pt5_cache;  // per seed: up to kPtCache passing objects found by the count pass
+  int *pt3_cache, *pt5_cache;  // per seed: up to kPt3Cache / kPt5Cache passing objects found by the count pass
   float4 *pt3_cattr, *pt5_cattr;  // and their attributes
   int2 *pt3_so, *pt5_so;      // seed, object
   float4 *pt3_attr, *pt5_attr;
