@@ -114,9 +114,8 @@ def algorithmic_bytes(site, c, n_outer, n_mod, n_edges, n_seeds, n_tc):
         "t5_count": 32 * t3 + 20 * md + 4 * (md + 1) + 4 * (ls + 1) + 4 * t3,
         "t5_fill": 32 * t3 + 20 * md + 4 * (md + 1) + 4 * (ls + 1) + 4 * (t3 + 1) + 60 * t5,
         "t5_dedup": 60 * t5 + 8 * md + 4 * (md + 1) + 20 * t5 + 12 * t5,
-        "pt3_count": 32 * S + 8 * t3 + 4 * S,
+        "pt_count": 32 * S + 8 * t3 + 12 * t5 + 8 * S,
         "pt3_fill": 32 * S + 8 * t3 + 4 * (S + 1) + 24 * p3,
-        "pt5_count": 32 * S + 12 * t5 + 4 * S,
         "pt5_fill": 32 * S + 12 * t5 + 4 * (S + 1) + 24 * p5,
         "tc_pt3": 16 * p3 + 32 * S + 4 * S + 16 * n0 + 4 * p3,
         "tc_t5": 8 * t5 + 16 * t5 + 16 * (n0 + n1) + 4 * t5,

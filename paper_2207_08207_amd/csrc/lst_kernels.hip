@@ -9,6 +9,7 @@
 // stay on the device: later kernels read them and stride over them, so the
 // whole chain is enqueued without a host round trip.
 #include <cstring>
+#include <type_traits>
 
 #include "lst_select.hpp"
 #include "lst_ws.hpp"
@@ -297,14 +298,15 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
     const float4 win = g.win[m];
     const ModInfo mi{g.info[m]};
     int base = FILL ? w.md_off[m] : 0;
-    for (long p0 = 0; p0 < npair; p0 += 64) {
-      const long p = p0 + lane;
+    const int np = (int)npair;  // <= kMdBig here
+    for (int p0 = 0; p0 < np; p0 += 64) {
+      const int p = p0 + lane;
       bool pass = false;
       int i = 0, j = 0;
       float4 hi, hj;
-      if (p < npair) {
-        i = (int)(p / nup);
-        j = (int)(p - (long)i * nup);
+      if (p < np) {
+        i = p / nup;
+        j = p - i * nup;
         hi = i < kMdStage ? s_lo[wv][i] : w.hpos[lo0 + i];
         hj = j < kMdStage ? s_up[wv][j] : w.hpos[up0 + j];
         pass = md_pass(hi, hj, win, mi);
@@ -1122,7 +1124,7 @@ __device__ __forceinline__ int2 seed_zbins(const Seed &sd, float lo, float hi) {
 // LDS, ranked by object index, written at the seed's offset in object order
 // (the order of the full scan); a seed with more than kPassList passing
 // objects is filled by an ordered scan over all objects instead.
-template <int K, bool FILL>
+template <int K, bool FILL, bool BOTH = false>
 __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb, DevGeom g) {
   __shared__ unsigned s_mask[kWaves][kMaskWords];
   __shared__ int s_slo[kWaves][kRings], s_shi[kWaves][kRings];
@@ -1176,200 +1178,213 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
     s_zb[wv][lane] = seed_zbins(sd, __int_as_float(s_slo[wv][lane]), __int_as_float(s_shi[wv][lane]));
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  const int *boff = K == 3 ? w.b3_off : w.b5_off;
-  const int *blst = K == 3 ? w.b3_list : w.b5_list;
-  const float2 *first = K == 3 ? w.t3_first : w.t5_first;
-  int n_pass = 0;
-  int base = FILL ? (K == 3 ? w.pt3_off : w.pt5_off)[s] : 0;
-  const int expect = FILL ? (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s] : 0;
-  const int cap = K == 3 ? w.cap_pt3 : w.cap_pt5;
-  const bool listed = !FILL || expect <= kPassList;
-  // one candidate: the object at list entry j, tested against the seed; passing ones are
-  // counted in ballot order and remembered (count: the cache; fill: the LDS list)
-  const float4 *bpos = K == 3 ? w.b3_pos : w.b5_pos;
-  // the full selection on the first n (<= 64) queued objects; passing ones are counted
-  // in ballot order and remembered (count: the cache; fill: the LDS list)
-  auto full = [&](int n) {
-    bool pass = false;
-    int t = 0;
-    float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (lane < n) {
-      t = s_pq[wv][lane];
-      float4 P[K];
-      ModInfo M[K];
-      float kT, dkT;
-      load_object<K>(w, g, t, P, M, &kT, &dkT);
-      pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
-    }
-    const unsigned long long m = __ballot(pass);
-    if (pass) {
-      const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-      if (FILL) {
-        if (n_pass + pre < kPassList) s_list[wv][n_pass + pre] = t;
-      } else if (n_pass + pre < kCache) {
-        cache[n_pass + pre] = t;
-        cattr[n_pass + pre] = attr;
-      }
-    }
-    n_pass += __popcll(m);
-  };
-  // one candidate per lane (list entry j): the exact first-anchor part of the selection
-  // from the packed anchor; objects passing it are queued, and the full selection runs
-  // on full waves of them
-  int nq = 0;
-  auto test = [&](bool active, int j) {
-    bool keep = false;
-    int t = 0;
-    if (active) {
-      t = blst[j];
-      const float4 f = bpos[j];
-      keep = pt_first_anchor(sd, f, ModInfo{__float_as_int(f.w)});
-    }
-    const unsigned long long m = __ballot(keep);
-    if (keep)
-      s_pq[wv][nq + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = t;
-    nq += __popcll(m);
+  // the search over one object kind's bins (KO = 3: triplets, 5: quintuplets)
+  auto search = [&](auto kind) {
+    constexpr int KO = decltype(kind)::value;
+    constexpr int kCacheO = KO == 3 ? kPt3Cache : kPt5Cache;
+    int *cache = (KO == 3 ? w.pt3_cache : w.pt5_cache) + (long)s * kCacheO;
+    float4 *cattr = (KO == 3 ? w.pt3_cattr : w.pt5_cattr) + (long)s * kCacheO;
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (nq >= 64) {
-      full(64);
-      const int rest = nq - 64;  // < 64: move the queue's tail to its front
-      const int v = lane < rest ? s_pq[wv][64 + lane] : 0;
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      if (lane < rest) s_pq[wv][lane] = v;
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      nq = rest;
-    }
-  };
-  bool flat = false;
-  if (listed) {
-    // every marked (ring, azimuth) bin becomes a slice of the object list (its reachable
-    // z bins, possibly empty); bit ids first, ranked over the wave by a prefix of the
-    // mask words' popcounts, then converted in place, 64 at a time, to (first entry,
-    // candidates before it)
-    int n_bits = 0;
-    for (int w0 = 0; w0 < kMaskWords; w0 += 64) {
-      const unsigned bits = w0 + lane < kMaskWords ? s_mask[wv][w0 + lane] : 0u;
-      const int pc = __popc(bits);
-      int x = pc;
-      for (int o = 1; o < 64; o <<= 1) {
-        const int y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
+    const int *boff = KO == 3 ? w.b3_off : w.b5_off;
+    const int *blst = KO == 3 ? w.b3_list : w.b5_list;
+    const float2 *first = KO == 3 ? w.t3_first : w.t5_first;
+    int n_pass = 0;
+    int base = FILL ? (KO == 3 ? w.pt3_off : w.pt5_off)[s] : 0;
+    const int expect = FILL ? (KO == 3 ? w.pt3_cnt : w.pt5_cnt)[s] : 0;
+    const int cap = KO == 3 ? w.cap_pt3 : w.cap_pt5;
+    const bool listed = !FILL || expect <= kPassList;
+    const float4 *bpos = KO == 3 ? w.b3_pos : w.b5_pos;
+    // the full selection on the first n (<= 64) queued objects; passing ones are counted
+    // in ballot order and remembered (count: the cache; fill: the LDS list)
+    auto full = [&](int n) {
+      bool pass = false;
+      int t = 0;
+      float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (lane < n) {
+        t = s_pq[wv][lane];
+        float4 P[KO];
+        ModInfo M[KO];
+        float kT, dkT;
+        load_object<KO>(w, g, t, P, M, &kT, &dkT);
+        pass = pt_pass<KO>(sd, P, M, kT, dkT, &attr);
       }
-      const int tot = __shfl(x, 63, 64);
-      if (n_bits + tot <= kMaxSlices) {
-        int k = n_bits + x - pc;
-        for (unsigned bb = bits; bb; bb &= bb - 1u) s_sl_j0[wv][k++] = (w0 + lane) * 32 + __builtin_ctz(bb);
-      }
-      n_bits += tot;
-    }
-    flat = n_bits <= kMaxSlices;
-    if (flat) {
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      int run = 0;
-      for (int c0 = 0; c0 < n_bits; c0 += 64) {
-        const int k = c0 + lane;
-        int j0 = 0, len = 0;
-        if (k < n_bits) {
-          const int bin = s_sl_j0[wv][k];
-          const int2 zb = s_zb[wv][bin / kPhiBins];
-          j0 = boff[bin * kZBins + zb.x];
-          len = boff[bin * kZBins + zb.y + 1] - j0;
+      const unsigned long long m = __ballot(pass);
+      if (pass) {
+        const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+        if (FILL) {
+          if (n_pass + pre < kPassList) s_list[wv][n_pass + pre] = t;
+        } else if (n_pass + pre < kCacheO) {
+          cache[n_pass + pre] = t;
+          cattr[n_pass + pre] = attr;
         }
-        int x = len;
+      }
+      n_pass += __popcll(m);
+    };
+    // one candidate per lane (list entry j): the exact first-anchor part of the selection
+    // from the packed anchor; objects passing it are queued, and the full selection runs
+    // on full waves of them
+    int nq = 0;
+    auto test = [&](bool active, int j) {
+      bool keep = false;
+      int t = 0;
+      if (active) {
+        t = blst[j];
+        const float4 f = bpos[j];
+        keep = pt_first_anchor(sd, f, ModInfo{__float_as_int(f.w)});
+      }
+      const unsigned long long m = __ballot(keep);
+      if (keep)
+        s_pq[wv][nq + __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))] = t;
+      nq += __popcll(m);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (nq >= 64) {
+        full(64);
+        const int rest = nq - 64;  // < 64: move the queue's tail to its front
+        const int v = lane < rest ? s_pq[wv][64 + lane] : 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) s_pq[wv][lane] = v;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        nq = rest;
+      }
+    };
+    bool flat = false;
+    if (listed) {
+      // every marked (ring, azimuth) bin becomes a slice of the object list (its reachable
+      // z bins, possibly empty); bit ids first, ranked over the wave by a prefix of the
+      // mask words' popcounts, then converted in place, 64 at a time, to (first entry,
+      // candidates before it)
+      int n_bits = 0;
+      for (int w0 = 0; w0 < kMaskWords; w0 += 64) {
+        const unsigned bits = w0 + lane < kMaskWords ? s_mask[wv][w0 + lane] : 0u;
+        const int pc = __popc(bits);
+        int x = pc;
         for (int o = 1; o < 64; o <<= 1) {
           const int y = __shfl_up(x, o, 64);
           if (lane >= o) x += y;
         }
-        if (k < n_bits) {
-          s_sl_j0[wv][k] = j0;
-          s_sl_pre[wv][k] = run + x - len;
+        const int tot = __shfl(x, 63, 64);
+        if (n_bits + tot <= kMaxSlices) {
+          int k = n_bits + x - pc;
+          for (unsigned bb = bits; bb; bb &= bb - 1u) s_sl_j0[wv][k++] = (w0 + lane) * 32 + __builtin_ctz(bb);
         }
-        run += __shfl(x, 63, 64);
+        n_bits += tot;
       }
-      if (lane == 0) s_sl_pre[wv][n_bits] = run;
+      flat = n_bits <= kMaxSlices;
+      if (flat) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        int run = 0;
+        for (int c0 = 0; c0 < n_bits; c0 += 64) {
+          const int k = c0 + lane;
+          int j0 = 0, len = 0;
+          if (k < n_bits) {
+            const int bin = s_sl_j0[wv][k];
+            const int2 zb = s_zb[wv][bin / kPhiBins];
+            j0 = boff[bin * kZBins + zb.x];
+            len = boff[bin * kZBins + zb.y + 1] - j0;
+          }
+          int x = len;
+          for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+          }
+          if (k < n_bits) {
+            s_sl_j0[wv][k] = j0;
+            s_sl_pre[wv][k] = run + x - len;
+          }
+          run += __shfl(x, 63, 64);
+        }
+        if (lane == 0) s_sl_pre[wv][n_bits] = run;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        int e = 0;  // slice of this lane's candidate (candidates advance monotonically)
+        for (int c0 = 0; c0 < run; c0 += 64) {
+          const int c = c0 + lane;
+          int j = 0;
+          if (c < run) {
+            while (s_sl_pre[wv][e + 1] <= c) ++e;
+            j = s_sl_j0[wv][e] + (c - s_sl_pre[wv][e]);
+          }
+          test(c < run, j);
+        }
+      }
+    }
+    if (listed && !flat) {
+      n_pass = 0;
+      nq = 0;
+      for (int wd = 0; wd < kMaskWords; ++wd) {
+        unsigned bits = mask[wd];
+        while (bits) {
+          const int bit = __builtin_ctz(bits);
+          bits &= bits - 1u;
+          const int bin = wd * 32 + bit;
+          const int2 zb = s_zb[wv][bin / kPhiBins];
+          const int j0 = boff[bin * kZBins + zb.x], j1 = boff[bin * kZBins + zb.y + 1];
+          for (int j = j0 + lane; j - lane < j1; j += 64) test(j < j1, j);
+        }
+      }
+    }
+    if (listed && nq > 0) full(nq);
+    if (!FILL) {
+      if (lane == 0) (KO == 3 ? w.pt3_cnt : w.pt5_cnt)[s] = n_pass;
+      return;
+    }
+    if (listed) {
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      int e = 0;  // slice of this lane's candidate (candidates advance monotonically)
-      for (int c0 = 0; c0 < run; c0 += 64) {
-        const int c = c0 + lane;
-        int j = 0;
-        if (c < run) {
-          while (s_sl_pre[wv][e + 1] <= c) ++e;
-          j = s_sl_j0[wv][e] + (c - s_sl_pre[wv][e]);
+      // rank by object index (indices are distinct) and write in object order
+      for (int i = lane; i < n_pass; i += 64) {
+        const int t = s_list[wv][i];
+        int rank = 0;
+        for (int q = 0; q < n_pass; ++q) rank += s_list[wv][q] < t ? 1 : 0;
+        const int pos = base + rank;
+        if (pos < cap) {
+          float4 P[KO];
+          ModInfo M[KO];
+          float kT, dkT;
+          float4 attr;
+          load_object<KO>(w, g, t, P, M, &kT, &dkT);
+          pt_pass<KO>(sd, P, M, kT, dkT, &attr);
+          (KO == 3 ? w.pt3_so : w.pt5_so)[pos] = make_int2(s, t);
+          (KO == 3 ? w.pt3_attr : w.pt5_attr)[pos] = attr;
         }
-        test(c < run, j);
       }
+      return;
     }
-  }
-  if (listed && !flat) {
-    n_pass = 0;
-    nq = 0;
-    for (int wd = 0; wd < kMaskWords; ++wd) {
-      unsigned bits = mask[wd];
-      while (bits) {
-        const int bit = __builtin_ctz(bits);
-        bits &= bits - 1u;
-        const int bin = wd * 32 + bit;
-        const int2 zb = s_zb[wv][bin / kPhiBins];
-        const int j0 = boff[bin * kZBins + zb.x], j1 = boff[bin * kZBins + zb.y + 1];
-        for (int j = j0 + lane; j - lane < j1; j += 64) test(j < j1, j);
+    // rare: too many passing objects for the LDS list; ordered scan of all objects
+    const int n_obj = KO == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
+    for (int t0 = 0; t0 < n_obj; t0 += 64) {
+      const int t = t0 + lane;
+      bool pass = false;
+      float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (t < n_obj && (KO == 3 || w.t5_keep[t])) {
+        const float2 f = first[t];
+        if (seed_box(sd, f.x, f.y)) {
+          float4 P[KO];
+          ModInfo M[KO];
+          float kT, dkT;
+          load_object<KO>(w, g, t, P, M, &kT, &dkT);
+          pass = pt_pass<KO>(sd, P, M, kT, dkT, &attr);
+        }
       }
-    }
-  }
-  if (listed && nq > 0) full(nq);
-  if (!FILL) {
-    if (lane == 0) (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s] = n_pass;
-    return;
-  }
-  if (listed) {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    // rank by object index (indices are distinct) and write in object order
-    for (int i = lane; i < n_pass; i += 64) {
-      const int t = s_list[wv][i];
-      int rank = 0;
-      for (int q = 0; q < n_pass; ++q) rank += s_list[wv][q] < t ? 1 : 0;
-      const int pos = base + rank;
-      if (pos < cap) {
-        float4 P[K];
-        ModInfo M[K];
-        float kT, dkT;
-        float4 attr;
-        load_object<K>(w, g, t, P, M, &kT, &dkT);
-        pt_pass<K>(sd, P, M, kT, dkT, &attr);
-        (K == 3 ? w.pt3_so : w.pt5_so)[pos] = make_int2(s, t);
-        (K == 3 ? w.pt3_attr : w.pt5_attr)[pos] = attr;
+      const unsigned long long m = __ballot(pass);
+      const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+      if (pass && base + pre < cap) {
+        (KO == 3 ? w.pt3_so : w.pt5_so)[base + pre] = make_int2(s, t);
+        (KO == 3 ? w.pt3_attr : w.pt5_attr)[base + pre] = attr;
       }
+      base += __popcll(m);
     }
-    return;
-  }
-  // rare: too many passing objects for the LDS list; ordered scan of all objects
-  const int n_obj = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
-  for (int t0 = 0; t0 < n_obj; t0 += 64) {
-    const int t = t0 + lane;
-    bool pass = false;
-    float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (t < n_obj && (K == 3 || w.t5_keep[t])) {
-      const float2 f = first[t];
-      if (seed_box(sd, f.x, f.y)) {
-        float4 P[K];
-        ModInfo M[K];
-        float kT, dkT;
-        load_object<K>(w, g, t, P, M, &kT, &dkT);
-        pass = pt_pass<K>(sd, P, M, kT, dkT, &attr);
-      }
-    }
-    const unsigned long long m = __ballot(pass);
-    const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-    if (pass && base + pre < cap) {
-      (K == 3 ? w.pt3_so : w.pt5_so)[base + pre] = make_int2(s, t);
-      (K == 3 ? w.pt3_attr : w.pt5_attr)[base + pre] = attr;
-    }
-    base += __popcll(m);
+  };
+  if constexpr (BOTH) {  // count pass of both kinds on one trajectory mask
+    search(std::integral_constant<int, 3>{});
+    search(std::integral_constant<int, 5>{});
+  } else {
+    search(std::integral_constant<int, K>{});
   }
 }
 
@@ -1684,7 +1699,7 @@ const char *const kSiteNames[] = {
     "t3_count", "t3_scan", "t3_fill", "t5_count", "t5_scan", "t5_fill",
     "t5_inc_count", "t5_inc_scan", "t5_inc_scatter", "t5_dedup",
     "pls", "pls_hit_scan", "pls_hit_scatter", "pls_dedup",
-    "pt3_bin", "pt3_count", "pt3_scan", "pt3_fill", "pt5_bin", "pt5_count", "pt5_scan", "pt5_fill",
+    "pt3_bin", "pt5_bin", "pt_count", "pt3_scan", "pt3_fill", "pt5_scan", "pt5_fill",
     "pt_obj_count", "pt_obj_scan", "pt_obj_scatter", "pt3_dedup", "pt5_dedup",
     "tc_pt5", "tc_pt5_scan", "tc_pt5_dirs", "tc_pt3", "tc_pt3_scan", "tc_pt3_dirs",
     "tc_t5", "tc_t5_scan", "tc_t5_dirs", "tc_pls", "tc_pls_scan", "tc_write"};
@@ -1694,9 +1709,9 @@ static_assert(sizeof(kSiteNames) / sizeof(kSiteNames[0]) <= kMaxSites, "launch-s
 // Sites whose kernels take any block of 64, 128 or 256 threads (grid-stride
 // loops over threads or waves, LDS sized for the largest block): the launch
 // shape the autotuner may choose.
-static const char *const kTunableSites[] = {"md_count", "md_fill",   "ls_count",  "ls_fill",  "t3_count",  "t3_fill",  "t5_count",
-                                            "t5_fill",  "t5_dedup",  "pt3_count", "pt3_fill", "pt5_count",
-                                            "pt5_fill", "tc_pt3",    "tc_t5",     "tc_pls"};
+static const char *const kTunableSites[] = {"md_count", "md_fill",  "ls_count", "ls_fill",  "t3_count",
+                                            "t3_fill",  "t5_count", "t5_fill",  "t5_dedup", "pt_count",
+                                            "pt3_fill", "pt5_fill", "tc_pt3",   "tc_t5",    "tc_pls"};
 
 bool site_tunable(int site) {
   if (site < 0 || site >= kNumSites) return false;
@@ -1783,16 +1798,16 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
     scan(wb, B, SC_B3, kSeedBins, st);
     k_obj_bin_scatter<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb, g);
   });
-  run([&] { if (seeds) k_pt_binned<3, false><<<seedwaves(), tb, 0, st>>>(wb, g); });
-  run([&] { if (seeds) scan(wb, B, SC_PT3, S, st); });
-  run([&] { if (seeds) k_pt_binned<3, true><<<seedwaves(), tb, 0, st>>>(wb, g); });
   run([&] {
     if (!seeds) return;
     k_obj_bin_count<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb);
     scan(wb, B, SC_B5, kSeedBins, st);
     k_obj_bin_scatter<5><<<grid(b.cap_t5), kBlock, 0, st>>>(wb, g);
   });
-  run([&] { if (seeds) k_pt_binned<5, false><<<seedwaves(), tb, 0, st>>>(wb, g); });
+  // both counts on one trajectory mask per seed
+  run([&] { if (seeds) k_pt_binned<3, false, true><<<seedwaves(), tb, 0, st>>>(wb, g); });
+  run([&] { if (seeds) scan(wb, B, SC_PT3, S, st); });
+  run([&] { if (seeds) k_pt_binned<3, true><<<seedwaves(), tb, 0, st>>>(wb, g); });
   run([&] { if (seeds) scan(wb, B, SC_PT5, S, st); });
   run([&] { if (seeds) k_pt_binned<5, true><<<seedwaves(), tb, 0, st>>>(wb, g); });
   run([&] {
