@@ -77,6 +77,8 @@ def parse():
                    help="launch site to time for the roofline (default: the largest in a per-site calibration)")
     p.add_argument("--workload", default="pu200_seeded", choices=sorted(WORKLOAD))
     p.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    p.add_argument("--no-physics", action="store_true",
+                   help="skip the truth-matched efficiency / fake / duplicate rates of the pool events")
     p.add_argument("--launch-config", default=LAUNCH_SHAPES,
                    help="JSON launch shapes to load (the packaged MI355X tuning; 'none' for the defaults)")
     p.add_argument("--tune", type=int, default=0,
@@ -480,6 +482,23 @@ def main():
         "launch_shapes": tuned, "plain": plain, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
         "roofline": roof,
     }
+    if not args.no_physics:
+        # efficiency, fake and duplicate rates of the HIP track candidates of every pool event,
+        # against the generator's truth (outside every timed region)
+        from lstgen.truth_metrics import pooled_metrics
+        pairs = []
+        for ev, d in zip(host, pool):
+            r = lst.run_event(g, d)
+            pairs.append((ev, r.track_candidates()))
+            r.close()
+        m = pooled_metrics(pairs)
+        rnd = lambda v: {k: rnd(x) for k, x in v.items()} if isinstance(v, dict) else (
+            round(v, 5) if isinstance(v, float) else v)
+        out["physics"] = {k: rnd(m[k]) for k in ("events", "n_tracks", "n_tc", "efficiency", "fake_rate",
+                                            "duplicate_rate", "by_type")}
+        out["physics"]["match"] = "a candidate matches a track when >= 75% of its hits are the track's"
+        out["physics"]["denominator"] = "generated tracks with pT > 0.9 GeV and |eta| < 2.4"
+        log(f"bench: physics {json.dumps(m)}")
     if not args.no_cpu:
         n_work = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
         rate, wall, per_event = cpu_baseline(args.workload, host, n_work)

@@ -101,6 +101,25 @@ def test_parity_many_events(spec, lst, gfull, many_oracle):
     assert compare_tc(r, o) > 1000
 
 
+def test_physics_metrics_from_hip_candidates(lst, gfull, many_oracle):
+    """Efficiency, fake and duplicate rates of the HIP candidates equal the oracle's, pooled over events."""
+    from lstgen.truth_metrics import pooled_metrics
+    for config in ("pu200_seeded", "pu200"):
+        specs = [s for s in MANY if s[0] == config][:8]
+        hip, orc = [], []
+        for s in specs:
+            ev, o = many_oracle[s]
+            r = _run(lst, gfull, ev)
+            hip.append((ev, r.track_candidates()))
+            orc.append((ev, o.tc()))
+            r.close()
+        mh, mo = pooled_metrics(hip), pooled_metrics(orc)
+        print(f"[gpu] {config} x{len(specs)}: efficiency {mh['efficiency']:.4f} fake {mh['fake_rate']:.4f} "
+              f"duplicate {mh['duplicate_rate']:.4f}", flush=True)
+        assert mh == mo
+        assert mh["efficiency"] > (0.93 if config == "pu200_seeded" else 0.8)
+
+
 def test_parity_batch_plan_events(lst, gfull, many_oracle):
     """Eight pile-up U[140, 250] events in one captured plan, each against the oracle."""
     evs = [many_oracle[s][0] for s in BATCH]
