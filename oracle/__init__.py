@@ -55,6 +55,8 @@ def _lib(f64=False):
         lib.orc_stage.argtypes = [vp, ctypes.c_int, vp, vp, vp]
         lib.orc_tc.argtypes = [vp, vp, vp, vp]
         lib.orc_tc_hit_count.argtypes = [vp]
+        lib.orc_ext_hit_count.argtypes = [vp]
+        lib.orc_ext.argtypes = [vp, vp, vp, vp, vp, vp]
         lib.orc_border_count.argtypes = [vp, ctypes.c_int]
         lib.orc_border.argtypes = [vp, ctypes.c_int, vp, vp]
         lib.orc_free.argtypes = [vp]
@@ -126,6 +128,19 @@ class OracleResult:
         hits = np.zeros(nh, np.int32)
         self.lib.orc_tc(ctypes.c_void_p(self.handle), _p(ty), _p(off), _p(hits))
         return ty, off, hits
+
+    def extensions(self):
+        """Track extensions of the TCs, in TC order: (n_added [n], t3 index [n] (-1: none),
+        attrs [n, 3] (chi2_xy, chi2_rz, kappa), offsets [n + 1], hits) of the extended collection."""
+        n = self.count(ST_TC)
+        nh = int(self.lib.orc_ext_hit_count(ctypes.c_void_p(self.handle)))
+        na = np.zeros(n, np.int32)
+        t3 = np.zeros(n, np.int32)
+        at = np.zeros((n, 3), np.float64 if self.f64 else np.float32)
+        off = np.zeros(n + 1, np.int32)
+        hits = np.zeros(nh, np.int32)
+        self.lib.orc_ext(ctypes.c_void_p(self.handle), _p(na), _p(t3), _p(at), _p(off), _p(hits))
+        return na, t3, at, off, hits
 
     def border(self, stage):
         n = int(self.lib.orc_border_count(ctypes.c_void_p(self.handle), stage))

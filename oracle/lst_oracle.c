@@ -66,6 +66,8 @@ static const double SEED_DDIR = 0.001;         /* seed direction resolution [rad
 static const double D_PT3 = 0.02, D_T5 = 0.02, D_PLS = 0.05;  /* eta-phi proximity */
 static const double X_SERIES_MAX = 0.7;        /* validity bound of the arc-length series */
 static const double BORDER_REL = 1e-6;         /* borderline band, relative */
+static const double X_EXT_XY = 10.0;            /* extension circle-fit chi2 per degree of freedom */
+static const double X_EXT_RZ = 20.0 / 3.0;      /* extension line-fit chi2 per degree of freedom */
 
 enum { ST_MD = 0, ST_LS, ST_T3, ST_T5, ST_PLS, ST_PT3, ST_PT5, ST_TC, N_ST };
 static const int TUPLE_W[N_ST] = {2, 4, 6, 10, 1, 7, 11, 0};
@@ -218,6 +220,7 @@ typedef struct {
   ivec pt5_seed, pt5_obj, pt5_keep; rvec pt5_attr;
   ivec pls_keep;
   ivec tc_type, tc_obj, tc_off, tc_hits;
+  ivec ext_n, ext_t3, ext_off, ext_hits; rvec ext_attr;  /* track extensions, per TC */
   ivec border[N_ST], border_acc[N_ST];
   const int *q, *hits4;
   const float *px, *py, *pz;
@@ -1054,6 +1057,161 @@ static void stage_tc(orc_event *e) {
   iv_free(&tc5); iv_free(&tc3); iv_free(&tct5); iv_free(&tcp);
 }
 
+/* ------------------------------------------------------------ track extensions */
+/* Section 2.5 (last part): a track candidate with outer-tracker MDs (pT5, pT3,
+ * T5) is lengthened by a triplet that continues it outward.  The paper names
+ * no selection, so these are readings:
+ *  - the triplet's first two MDs are the candidate's last two (one MD added),
+ *    or its first MD is the candidate's last (two MDs added);
+ *  - curvatures agree: |kappa_T3 - kappa_TC| <= dkappa_T3 + dkappa_TC, with
+ *    kappa_TC the seed's (tolerance three seed resolutions) for pT5 / pT3 and
+ *    the five-anchor fit's for a T5 (tolerance its outer triplet's dkappa);
+ *  - azimuth linear in z (phiz_test) over the first anchor, the candidate's
+ *    last anchor and the last added anchor, the long lever arms the
+ *    quintuplet uses;
+ *  - the chain of all anchors passes the quintuplet's two fits extended to n
+ *    anchors: the circle fit in x-y (chi2 <= X_EXT_XY per degree of freedom,
+ *    n - 3) and the straight line in (arc length, z) (chi2 <= X_EXT_RZ per
+ *    degree of freedom, n - 2), arc lengths taken with the circle fit's
+ *    curvature.
+ * Of the passing triplets the one adding more MDs is taken, then the smaller
+ * chi2_xy + chi2_rz, then the smaller hit tuple of the added MDs. */
+
+/* Weighted circle fit v = a + b u + c (u^2 + v^2) over n anchors in the frame
+ * of the quintuplet fit (origin at the first anchor, u along the chord to the
+ * last, lengths in chord units).  Returns 0 when the normal equations or the
+ * curvature are degenerate; else chi2 in *chi2 and the curvature in *kap. */
+static int circle_fit_n(const orc_geom *g, const orc_event *e, const int *md, int n, real *chi2, real *kap) {
+  real X[7], Y[7];
+  int M[7];
+  for (int i = 0; i < n; ++i) { X[i] = AX(md[i]); Y[i] = AY(md[i]); M[i] = AMOD(md[i]); }
+  real ex = X[n - 1] - X[0], ey = Y[n - 1] - Y[0];
+  real L = RSQRT_(ex * ex + ey * ey);
+  real ux = ex / L, uy = ey / L;
+  real u[7], v[7], q[7], w[7];
+  for (int i = 0; i < n; ++i) {
+    real dx = X[i] - X[0], dy = Y[i] - Y[0];
+    u[i] = (dx * ux + dy * uy) / L;
+    v[i] = (dy * ux - dx * uy) / L;
+    q[i] = u[i] * u[i] + v[i] * v[i];
+    real t = L / sig_t(g, M[i]);
+    w[i] = t * t;
+  }
+  real S0 = RL(0), S1 = RL(0), S2 = RL(0), S11 = RL(0), S12 = RL(0), S22 = RL(0), T0 = RL(0), T1 = RL(0), T2 = RL(0);
+  for (int i = 0; i < n; ++i) {
+    S0 = S0 + w[i];
+    S1 = S1 + w[i] * u[i];
+    S2 = S2 + w[i] * q[i];
+    S11 = S11 + w[i] * u[i] * u[i];
+    S12 = S12 + w[i] * u[i] * q[i];
+    S22 = S22 + w[i] * q[i] * q[i];
+    T0 = T0 + w[i] * v[i];
+    T1 = T1 + w[i] * u[i] * v[i];
+    T2 = T2 + w[i] * q[i] * v[i];
+  }
+  real m00 = S11 * S22 - S12 * S12;
+  real m01 = S1 * S22 - S12 * S2;
+  real m02 = S1 * S12 - S11 * S2;
+  real det = (S0 * m00 - S1 * m01) + S2 * m02;
+  if (!(det > RL(0))) return 0;
+  real deta = (T0 * m00 - S1 * (T1 * S22 - S12 * T2)) + S2 * (T1 * S12 - S11 * T2);
+  real detb = (S0 * (T1 * S22 - S12 * T2) - T0 * m01) + S2 * (S1 * T2 - T1 * S2);
+  real detc = (S0 * (S11 * T2 - T1 * S12) - S1 * (S1 * T2 - T1 * S2)) + T0 * m02;
+  real fa = deta / det, fb = detb / det, fc = detc / det;
+  real c2 = RL(0);
+  for (int i = 0; i < n; ++i) {
+    real r = v[i] - ((fa + fb * u[i]) + fc * q[i]);
+    c2 = c2 + w[i] * r * r;
+  }
+  real disc = (RL(1) + fb * fb) - RL(4) * fa * fc;
+  if (!(disc > RL(0))) return 0;
+  *chi2 = c2;
+  *kap = (RL(2) * fc) / (L * RSQRT_(disc));
+  return 1;
+}
+
+/* The fits of one extended chain; returns whether it passes, with
+ * attr = {chi2_xy, chi2_rz, kappa}. */
+static int ext_select(const orc_geom *g, const orc_event *e, const int *md, int n, real attr[3]) {
+  real c2xy, kap;
+  if (!circle_fit_n(g, e, md, n, &c2xy, &kap)) return 0;
+  if (!(c2xy <= (real)(X_EXT_XY * (double)(n - 3)))) return 0;
+  real s[7], z[7], w[7];
+  s[0] = RL(0);
+  for (int i = 1; i < n; ++i) {
+    real dx = AX(md[i]) - AX(md[i - 1]), dy = AY(md[i]) - AY(md[i - 1]);
+    real Lc = RSQRT_(dx * dx + dy * dy);
+    real xs = kap * Lc * RL(0.5);
+    if (!(RABS(xs) <= (real)X_SERIES_MAX)) return 0;
+    s[i] = s[i - 1] + Lc * g4(xs);
+  }
+  for (int i = 0; i < n; ++i) z[i] = AZ(md[i]);
+  real lam0 = (z[n - 1] - z[0]) / s[n - 1];
+  for (int i = 0; i < n; ++i) { real sg = sig_z(g, AMOD(md[i]), lam0); w[i] = RL(1) / (sg * sg); }
+  real lam;
+  real c2rz = line_fit(n, s, z, w, &lam);
+  if (!(c2rz <= (real)(X_EXT_RZ * (double)(n - 2)))) return 0;
+  attr[0] = c2xy; attr[1] = c2rz; attr[2] = kap;
+  return 1;
+}
+
+static void stage_ext(const orc_geom *g, orc_event *e) {
+  int ntc = (int)e->tc_type.n;
+  iv_push(&e->ext_off, 0);
+  for (int j = 0; j < ntc; ++j) {
+    int type = e->tc_type.p[j], obj = e->tc_obj.p[j];
+    int md[7], k = 0;
+    real kT = RL(0), dkT = RL(0);
+    if (type == 0 || type == 1) {
+      int seed = type == 0 ? e->pt5_seed.p[obj] : e->pt3_seed.p[obj];
+      if (type == 0) { t5_mds(e, e->pt5_obj.p[obj], md); k = 5; }
+      else { t3_mds(e, e->pt3_obj.p[obj], md); k = 3; }
+      kT = e->pls_attr.p[5 * (size_t)seed + 4];
+      dkT = RL(3) * ((real)SEED_DPT * RABS(kT));
+    } else if (type == 2) {
+      t5_mds(e, obj, md); k = 5;
+      kT = e->t5_attr.p[8 * (size_t)obj];
+      dkT = e->t3_attr.p[4 * (size_t)e->t5_out.p[obj] + 1];
+    }
+    int best_n = 0, best_t = -1, best_h[4] = {0, 0, 0, 0};
+    real best_s = RL(0), best_a[3] = {RL(0), RL(0), RL(0)};
+    for (int ov = 2; ov >= 1 && k > 0; --ov) {
+      int first = md[k - ov];
+      for (int t = e->t3_first[first]; t < e->t3_first[first + 1]; ++t) {
+        int tm[3];
+        t3_mds(e, t, tm);
+        if (ov == 2 && tm[1] != md[k - 1]) continue;
+        int add = 3 - ov;
+        const real *ta = e->t3_attr.p + 4 * (size_t)t;
+        real dk = ta[0] - kT;
+        if (!(RABS(dk) <= ta[1] + dkT)) continue;
+        int chain[7];
+        for (int i = 0; i < k; ++i) chain[i] = md[i];
+        for (int i = 0; i < add; ++i) chain[k + i] = tm[ov + i];
+        cutacc pz = {0, 0};
+        if (!phiz_test(g, e, chain[0], chain[k - 1], chain[k + add - 1], &pz)) continue;
+        real a[3];
+        if (!ext_select(g, e, chain, k + add, a)) continue;
+        int h[4] = {0, 0, 0, 0};
+        mds_to_hits(e, tm + ov, add, h);
+        real sc = a[0] + a[1];
+        int take = best_t < 0 || add > best_n || (add == best_n && better(sc, h, best_s, best_h, 2 * add));
+        if (take) {
+          best_n = add; best_t = t; best_s = sc;
+          for (int i = 0; i < 4; ++i) best_h[i] = h[i];
+          for (int i = 0; i < 3; ++i) best_a[i] = a[i];
+        }
+      }
+    }
+    iv_push(&e->ext_n, best_n);
+    iv_push(&e->ext_t3, best_t);
+    for (int i = 0; i < 3; ++i) rv_push(&e->ext_attr, best_a[i]);
+    for (int h = e->tc_off.p[j]; h < e->tc_off.p[j + 1]; ++h) iv_push(&e->ext_hits, e->tc_hits.p[h]);
+    for (int i = 0; i < 2 * best_n; ++i) iv_push(&e->ext_hits, best_h[i]);
+    iv_push(&e->ext_off, (int)e->ext_hits.n);
+  }
+}
+
 /* ---------------------------------------------------------------- entry points */
 static orc_event *event_new(int n_hits, const float *x, const float *y, const float *z, const int *module,
                             const int *sensor, int n_seeds, const float *px, const float *py, const float *pz,
@@ -1087,7 +1245,7 @@ void *orc_run(void *gp, int n_hits, const float *x, const float *y, const float 
   if (last >= ST_PLS) stage_pls(e);
   if (last >= ST_PT3) { stage_pt(g, e, 0); stage_pt_dedup(e, 0); }
   if (last >= ST_PT5) { stage_pt(g, e, 1); stage_pt_dedup(e, 1); }
-  if (last >= ST_TC) stage_tc(e);
+  if (last >= ST_TC) { stage_tc(e); stage_ext(g, e); }
   /* the seeds' pointers are not kept past the call */
   e->px = e->py = e->pz = NULL;
   if (n_seeds) {
@@ -1154,6 +1312,20 @@ void orc_tc(void *ep, int *type, int *offsets, int *hits) {
   if (offsets) memcpy(offsets, e->tc_off.p, sizeof(int) * e->tc_off.n);
   if (hits) memcpy(hits, e->tc_hits.p, sizeof(int) * e->tc_hits.n);
 }
+/* Track extensions of the TCs (same order as orc_tc): n_added [n_tc] (0, 1
+ * or 2 MDs), t3 [n_tc] (triplet index, -1 if none), attrs [n_tc x 3]
+ * (chi2_xy, chi2_rz, kappa of the extended chain; zeros if none), and the
+ * extended collection's offsets [n_tc + 1] and hits (each TC's hits followed
+ * by the lower and upper hit of every added MD).  Any pointer may be NULL. */
+int orc_ext_hit_count(void *ep) { return (int)((orc_event *)ep)->ext_hits.n; }
+void orc_ext(void *ep, int *n_added, int *t3, real *attrs, int *offsets, int *hits) {
+  orc_event *e = (orc_event *)ep;
+  if (n_added) memcpy(n_added, e->ext_n.p, sizeof(int) * e->ext_n.n);
+  if (t3) memcpy(t3, e->ext_t3.p, sizeof(int) * e->ext_t3.n);
+  if (attrs) memcpy(attrs, e->ext_attr.p, sizeof(real) * e->ext_attr.n);
+  if (offsets) memcpy(offsets, e->ext_off.p, sizeof(int) * e->ext_off.n);
+  if (hits) memcpy(hits, e->ext_hits.p, sizeof(int) * e->ext_hits.n);
+}
 int orc_border_count(void *ep, int stage) { return (int)((orc_event *)ep)->border_acc[stage].n; }
 void orc_border(void *ep, int stage, int *tuples, int *accepted) {
   orc_event *e = (orc_event *)ep;
@@ -1175,6 +1347,7 @@ void orc_free(void *ep) {
   iv_free(&e->pt3_seed); iv_free(&e->pt3_obj); iv_free(&e->pt3_keep); rv_free(&e->pt3_attr);
   iv_free(&e->pt5_seed); iv_free(&e->pt5_obj); iv_free(&e->pt5_keep); rv_free(&e->pt5_attr);
   iv_free(&e->tc_type); iv_free(&e->tc_obj); iv_free(&e->tc_off); iv_free(&e->tc_hits);
+  iv_free(&e->ext_n); iv_free(&e->ext_t3); iv_free(&e->ext_off); iv_free(&e->ext_hits); rv_free(&e->ext_attr);
   for (int s = 0; s < N_ST; ++s) { iv_free(&e->border[s]); iv_free(&e->border_acc[s]); }
   free(e);
 }

@@ -21,6 +21,7 @@ class OracleSnapshot:
         self._stage = {st: r.stage(st) for st in range(7)}
         self._border = {st: r.border(st) for st in range(7)}
         self._tc = r.tc()
+        self._ext = r.extensions()
 
     def stage(self, st):
         return self._stage[st]
@@ -30,6 +31,9 @@ class OracleSnapshot:
 
     def tc(self):
         return self._tc
+
+    def extensions(self):
+        return self._ext
 
 
 def _run_one(spec):

@@ -100,3 +100,24 @@ def test_oracle_physics_pu200_unseeded(oracle_pu200):
     assert bt["T5"]["n"] == m["n_tc"] and bt["pT5"]["n"] == bt["pT3"]["n"] == bt["pLS"]["n"] == 0
     assert 0.8 < m["efficiency"] < 0.95
     assert m["fake_rate"] < 0.15 and m["duplicate_rate"] < 0.01
+
+
+@pytest.mark.slow
+def test_oracle_extensions_pu200_seeded(oracle_pu200):
+    """Track extensions (Section 2.5): a large share of the candidates is lengthened, mostly
+    with the matched track's own hits, and the physics figures do not get worse."""
+    ev, snap = oracle_pu200[0]
+    ty, off, hits = snap.tc()
+    na, t3, _, xo, xh = snap.extensions()
+    frac = (na > 0).mean()
+    assert 0.25 < frac < 0.6          # the paper: about half
+    assert np.all(na[ty == 3] == 0) and np.all((na >= 0) & (na <= 2))
+    assert np.array_equal(np.diff(xo) - np.diff(off), 2 * na)
+    sim = np.asarray(ev.sim)
+    m = match_candidates(sim, off, hits)
+    ok = [np.all(sim[xh[xo[j] + off[j + 1] - off[j]:xo[j + 1]]] == m[j]) for j in np.nonzero((na > 0) & (m >= 0))[0]]
+    assert np.mean(ok) > 0.9
+    base, ext = tc_metrics(ev, ty, off, hits), tc_metrics(ev, ty, xo, xh)
+    assert ext["efficiency"] >= base["efficiency"] - 0.002
+    assert ext["fake_rate"] <= base["fake_rate"] + 0.002
+    assert ext["duplicate_rate"] <= base["duplicate_rate"] + 0.002
