@@ -71,7 +71,7 @@ def parse():
     p.add_argument("--sweep", default="100,200,500,1000,2000",
                    help="offered rates of the served-vs-plain rate sweep [events/s] (empty: skip)")
     p.add_argument("--batch", type=int, default=64, help="slots of the captured batched plan (0: skip)")
-    p.add_argument("--forms", default="plain,e2e,served,trace,batched,copy",
+    p.add_argument("--forms", default="plain,ext,e2e,served,trace,batched,copy",
                    help="comma list of forms to run (served is the headline and always runs)")
     p.add_argument("--site", default=None,
                    help="launch site to time for the roofline (default: the largest in a per-site calibration)")
@@ -238,8 +238,8 @@ def main():
     ws = torch.empty(ws_one, dtype=torch.uint8, device=dev)
     log(f"bench: workspace {ws.numel() / 2**20:.1f} MiB per event, max hits {n_hits_max}, max seeds {n_seeds_max}")
 
-    def step(i, timed_site=None):
-        st, h = lst.lst_build_event(g.handle, pool[i % len(pool)], ws, cap, stream)
+    def step(i, timed_site=None, gh=None):
+        st, h = lst.lst_build_event(g.handle if gh is None else gh, pool[i % len(pool)], ws, cap, stream)
         if st != lst.LST_OK:
             raise lst.LSTError(st, lst.lst_last_error())
         t = lst.lst_get_site_time(h) if timed_site is not None else None
@@ -300,6 +300,35 @@ def main():
         plain = {"events_per_s": round(n_plain / plain_elapsed, 3), "latency_ms": percentiles(lat),
                  "events": n_plain}
         log(f"bench: plain {plain}")
+
+    # ---- plain with the track-extension step at the end of the chain
+    ext = None
+    if "ext" in forms:
+        g_ext = lst.Geometry(geom)
+        if tuned:
+            g_ext.set_launch_config(tuned)
+        g_ext.set_track_extensions(True)
+        for i in range(args.warmup):
+            step(i, gh=g_ext.handle)
+        torch.cuda.synchronize()
+        n_ext = max(8, min(args.steps, 32))
+        lat = []
+        t0 = time.perf_counter()
+        for i in range(n_ext):
+            s0 = time.perf_counter()
+            step(args.warmup + i, gh=g_ext.handle)
+            lat.append((time.perf_counter() - s0) * 1e3)
+        torch.cuda.synchronize()
+        ext = {"events_per_s": round(n_ext / (time.perf_counter() - t0), 3), "latency_ms": percentiles(lat),
+               "events": n_ext, "step": "the chain plus the track-extension step, one event at a time"}
+        site_ms = {}
+        for name in ("tc_ext", "tc_ext_scan", "tc_ext_write"):
+            k = sites.index(name)
+            lst.lst_set_timed_site(k)
+            site_ms[name] = round(sum(step(i, k, gh=g_ext.handle)[1] for i in range(2)) / 2, 4)
+        lst.lst_set_timed_site(-1)
+        ext["site_ms"] = site_ms
+        log(f"bench: plain with extensions {ext}")
 
     # ---- end to end from pinned host memory: H2D, the chain, track candidates to the host
     e2e = None
@@ -479,18 +508,24 @@ def main():
                    "form": f"served: {n_streams} streams x batches of {max_batch}, all requests available",
                    "step": "one event through the whole chain"},
         "latency_ms": percentiles(served_lat),
-        "launch_shapes": tuned, "plain": plain, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
+        "launch_shapes": tuned, "plain": plain, "extensions": ext, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
         "roofline": roof,
     }
     if not args.no_physics:
         # efficiency, fake and duplicate rates of the HIP track candidates of every pool event,
         # against the generator's truth (outside every timed region)
         from lstgen.truth_metrics import pooled_metrics
-        pairs = []
+        pairs, pairs_ext, n_ext_tc = [], [], 0
         for ev, d in zip(host, pool):
             r = lst.run_event(g, d)
             pairs.append((ev, r.track_candidates()))
             r.close()
+            if ext is not None:
+                r = lst.run_event(g_ext, d)
+                ty, off, hits, na, _, _ = r.extended_track_candidates()
+                pairs_ext.append((ev, (ty, off, hits)))
+                n_ext_tc += int((na > 0).sum())
+                r.close()
         m = pooled_metrics(pairs)
         rnd = lambda v: {k: rnd(x) for k, x in v.items()} if isinstance(v, dict) else (
             round(v, 5) if isinstance(v, float) else v)
@@ -498,6 +533,10 @@ def main():
                                             "duplicate_rate", "by_type")}
         out["physics"]["match"] = "a candidate matches a track when >= 75% of its hits are the track's"
         out["physics"]["denominator"] = "generated tracks with pT > 0.9 GeV and |eta| < 2.4"
+        if pairs_ext:
+            mx = pooled_metrics(pairs_ext)
+            out["physics"]["extended"] = {"fraction_extended": round(n_ext_tc / max(1, mx["n_tc"]), 5),
+                                          **{k: rnd(mx[k]) for k in ("efficiency", "fake_rate", "duplicate_rate")}}
         log(f"bench: physics {json.dumps(m)}")
     if not args.no_cpu:
         n_work = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))

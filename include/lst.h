@@ -211,6 +211,38 @@ lst_status lst_server_destroy(lst_server srv);
 lst_status lst_get_track_candidates(lst_event ev, int32_t *n_tc, int32_t *n_hits_total, int32_t *type,
                                     int32_t *offsets, int32_t *hits);
 
+/* Track extensions (Section 2.5, last part): the final collection in which
+ * a candidate with outer-tracker MDs (pT5, pT3, T5) is lengthened outward by
+ * one triplet that shares its last two MDs (one MD added) or its last MD
+ * (two added).  The paper gives no selection; this library takes the
+ * triplet whose curvature agrees with the candidate's (seed resolution x3
+ * for pT5 / pT3, the outer triplet's for a T5), whose anchors keep the
+ * azimuth linear in z over the chain, and whose chain of all anchors passes
+ * the quintuplet's x-y circle and (arc length, z) line fits widened to its
+ * 4..7 anchors (chi2 <= 10 and 20/3 per degree of freedom); of those, the
+ * one adding more MDs, then the smaller chi2 sum, then the smaller hit tuple
+ * of the added MDs.
+ *
+ * lst_set_track_extensions(geom, 1) makes every chain enqueued afterwards on
+ * `geom` (events, batches, servers; plans created afterwards) end with the
+ * extension step; 0 (the default) leaves it out.  Errors: LST_E_INVALID for
+ * a NULL geometry or a value other than 0 / 1. */
+lst_status lst_set_track_extensions(lst_geometry geom, int32_t enable);
+
+/* The extended collection of a completed event, copied to HOST buffers, in
+ * the order and with the types of lst_get_track_candidates (two-call
+ * protocol: NULL arrays to get *n_tc and *n_hits_total).  hits: each
+ * candidate's hits as lst_get_track_candidates gives them, then the lower
+ * and upper hit of each added MD, inner to outer; offsets [n_tc + 1];
+ * n_added [n_tc]: 0, 1 or 2 MDs; t3 [n_tc]: index of the triplet used in the
+ * stage-2 object list (-1: none); attrs [n_tc x 3]: chi2_xy, chi2_rz and
+ * curvature of the extended chain (zeros: none).  Any array may be NULL.
+ * Errors: LST_E_STATE if the event failed, is not complete, or was enqueued
+ * while the extensions were disabled. */
+lst_status lst_get_extended_track_candidates(lst_event ev, int32_t *n_tc, int32_t *n_hits_total, int32_t *type,
+                                             int32_t *offsets, int32_t *hits, int32_t *n_added, int32_t *t3,
+                                             float *attrs);
+
 /* Objects of one stage, copied to HOST buffers (two-call protocol as above;
  * NULL arrays to query *n).  tuples [n x w] with w = 2, 4, 6, 10, 1, 7, 11 for
  * stages 0..6: hit indices of the MDs inner to outer (lower, upper), with the

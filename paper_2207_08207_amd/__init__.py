@@ -29,7 +29,8 @@ EXPORTED = ["lst_load_geometry", "lst_release_geometry", "lst_default_capacity",
             "lst_kernel_site_name", "lst_set_timed_site", "lst_get_site_time", "lst_batch_workspace_bytes",
             "lst_enqueue_batch", "lst_plan_workspace_bytes", "lst_plan_create", "lst_plan_run", "lst_plan_release",
             "lst_server_create", "lst_server_now", "lst_server_submit", "lst_server_poll", "lst_server_pending",
-            "lst_server_destroy", "lst_get_launch_config", "lst_set_launch_config", "lst_autotune"]
+            "lst_server_destroy", "lst_get_launch_config", "lst_set_launch_config", "lst_autotune",
+            "lst_set_track_extensions", "lst_get_extended_track_candidates"]
 
 
 class LSTError(RuntimeError):
@@ -93,6 +94,8 @@ def load_library(path=LIB_PATH):
         "lst_event_query": [vp, P(i32)],
         "lst_event_wait": [vp],
         "lst_get_track_candidates": [vp, P(i32), P(i32), vp, vp, vp],
+        "lst_set_track_extensions": [vp, i32],
+        "lst_get_extended_track_candidates": [vp, P(i32), P(i32), vp, vp, vp, vp, vp, vp],
         "lst_get_stage_objects": [vp, i32, P(i32), vp, vp, vp],
         "lst_get_stage_counts": [vp, vp, vp],
         "lst_get_module_constants": [vp, vp],
@@ -218,6 +221,27 @@ def lst_get_track_candidates(ev):
     hits = np.zeros(nh.value, np.int32)
     _check(lib.lst_get_track_candidates(ev, ctypes.byref(n), ctypes.byref(nh), _ptr(ty), _ptr(off), _ptr(hits)))
     return ty, off, hits
+
+
+def lst_set_track_extensions(geom, enable):
+    _check(load_library().lst_set_track_extensions(geom, 1 if enable else 0))
+
+
+def lst_get_extended_track_candidates(ev):
+    """(types, offsets, hits, n_added, t3, attrs [n, 3]) of the extended collection."""
+    lib = load_library()
+    n, nh = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.lst_get_extended_track_candidates(ev, ctypes.byref(n), ctypes.byref(nh), None, None, None, None,
+                                                 None, None))
+    ty = np.zeros(n.value, np.int32)
+    off = np.zeros(n.value + 1, np.int32)
+    hits = np.zeros(nh.value, np.int32)
+    na = np.zeros(n.value, np.int32)
+    t3 = np.zeros(n.value, np.int32)
+    at = np.zeros((n.value, 3), np.float32)
+    _check(lib.lst_get_extended_track_candidates(ev, ctypes.byref(n), ctypes.byref(nh), _ptr(ty), _ptr(off),
+                                                 _ptr(hits), _ptr(na), _ptr(t3), _ptr(at)))
+    return ty, off, hits, na, t3, at
 
 
 def lst_get_stage_objects(ev, stage):
@@ -400,6 +424,10 @@ class Geometry:
     def module_constants(self):
         return lst_get_module_constants(self.handle, self.n_modules)
 
+    def set_track_extensions(self, enable=True):
+        """Chains enqueued from now on end with (or without) the track-extension step."""
+        lst_set_track_extensions(self.handle, enable)
+
     def launch_config(self):
         """{site name: threads per block} of the tunable launch sites."""
         return {n: b for n, b in zip(lst_kernel_sites(), lst_get_launch_config(self.handle)) if b}
@@ -465,6 +493,9 @@ class EventResult:
 
     def track_candidates(self):
         return lst_get_track_candidates(self.handle)
+
+    def extended_track_candidates(self):
+        return lst_get_extended_track_candidates(self.handle)
 
     def stage(self, stage):
         return lst_get_stage_objects(self.handle, stage)

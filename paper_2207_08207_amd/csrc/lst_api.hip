@@ -135,6 +135,9 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.bdir_pt5 = F4(p5); t.bdir_pt3 = F4(p3); t.bdir_t5 = F4(t5);
   t.boff_pt5 = I(129); t.boff_pt3 = I(129); t.boff_t5 = I(129);
   t.tc_type = I(tc); t.tc_off = I(tc + 1); t.tc_hits = I(14 * tc);
+  t.tc_md = I(5 * tc); t.tc_kap = F2(tc);
+  t.ext_n = I(tc); t.ext_t3 = I(tc); t.ext_cnt = I(tc + 1); t.ext_off = I(tc + 1); t.ext_hits = I(18 * tc);
+  t.ext_attr = F4(tc);
   t.scan_tmp = I(4096);
 #undef I
 #undef F
@@ -169,6 +172,7 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
     sj(SC_B3, t.b3_cnt, t.b3_off, nullptr, nbins, nbins, ct + C_NB3, nullptr, 0);
     sj(SC_B5, t.b5_cnt, t.b5_off, nullptr, nbins, nbins, ct + C_NB5, nullptr, 0);
     sj(SC_LSOVF, t.ls_ovf_flag, t.ls_ovf_off, ct + C_NMD, 0, md, ct + C_NLSOVF, nullptr, 0);
+    sj(SC_EXT, t.ext_cnt, t.ext_off, ct + C_NTC, 0, p5 + p3 + t5 + S, ct + C_NEXTHITS, nullptr, 0);
     auto fj = [&](int id, int *p, long n) { t.fills[id] = FillJob{p, n}; };
     fj(FL_CTR, ct, C_COUNT);
     fj(FL_BCNT, t.bcnt, 2 * M + 1);
@@ -290,7 +294,14 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   g->g.map_tgt = g->d_tgt;
   g->g.win = g->d_win;
   g->g.info = g->d_info;
+  g->g.ext = 0;
   *out = g;
+  return LST_OK;
+}
+
+lst_status lst_set_track_extensions(lst_geometry g, int32_t enable) {
+  if (!g || (enable != 0 && enable != 1)) return fail(LST_E_INVALID, "lst_set_track_extensions: bad argument");
+  g->g.ext = enable;
   return LST_OK;
 }
 
@@ -646,6 +657,36 @@ lst_status lst_get_track_candidates(lst_event e, int32_t *n_tc, int32_t *n_hits_
   if (type && n > 0) HIP_TRY(hipMemcpy(type, w.tc_type, sizeof(int) * n, hipMemcpyDeviceToHost));
   if (offsets) HIP_TRY(hipMemcpy(offsets, w.tc_off, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
   if (hits && nh > 0) HIP_TRY(hipMemcpy(hits, w.tc_hits, sizeof(int) * nh, hipMemcpyDeviceToHost));
+  return LST_OK;
+}
+
+lst_status lst_get_extended_track_candidates(lst_event e, int32_t *n_tc, int32_t *n_hits_total, int32_t *type,
+                                             int32_t *offsets, int32_t *hits, int32_t *n_added, int32_t *t3,
+                                             float *attrs) {
+  if (!e || !n_tc || !n_hits_total) return fail(LST_E_INVALID, "lst_get_extended_track_candidates: NULL argument");
+  if (event_ok(e) != LST_OK) return LST_E_STATE;
+  const int st = e->ctr()[lst::C_STATUS];
+  if (st != 0) return fail(LST_E_STATE, "event did not build (status flags " + std::to_string(st) + ")");
+  if (e->ctr()[lst::C_EXT] != 1)
+    return fail(LST_E_STATE, "track extensions were not enabled on the geometry when the event was enqueued");
+  const lst::Ws &w = e->ws();
+  const int n = e->ctr()[lst::C_NTC], nh = e->ctr()[lst::C_NEXTHITS];
+  *n_tc = n;
+  *n_hits_total = nh;
+  if (type && n > 0) HIP_TRY(hipMemcpy(type, w.tc_type, sizeof(int) * n, hipMemcpyDeviceToHost));
+  if (offsets) HIP_TRY(hipMemcpy(offsets, w.ext_off, sizeof(int) * (n + 1), hipMemcpyDeviceToHost));
+  if (hits && nh > 0) HIP_TRY(hipMemcpy(hits, w.ext_hits, sizeof(int) * nh, hipMemcpyDeviceToHost));
+  if (n_added && n > 0) HIP_TRY(hipMemcpy(n_added, w.ext_n, sizeof(int) * n, hipMemcpyDeviceToHost));
+  if (t3 && n > 0) HIP_TRY(hipMemcpy(t3, w.ext_t3, sizeof(int) * n, hipMemcpyDeviceToHost));
+  if (attrs && n > 0) {
+    std::vector<float4> a;
+    HIP_TRY(d2h(a, w.ext_attr, (size_t)n));
+    for (int i = 0; i < n; ++i) {
+      attrs[3 * (size_t)i] = a[i].x;
+      attrs[3 * (size_t)i + 1] = a[i].y;
+      attrs[3 * (size_t)i + 2] = a[i].z;
+    }
+  }
   return LST_OK;
 }
 

@@ -1640,6 +1640,18 @@ __global__ void k_tc_pls(const Ws *__restrict__ wb) {
   }
 }
 
+// What the track-extension step reads of a candidate: its MDs and its
+// curvature with tolerance (the seed's, three resolutions, for pT5 / pT3;
+// the five-anchor fit's and the outer triplet's resolution for a T5).
+__device__ __forceinline__ float2 seed_kappa(const Ws &w, int seed) {
+  const float ks = w.pls[8 * (long)seed + 4];
+  return make_float2(ks, 3.0f * (kSeedDpt * fabsf(ks)));
+}
+__device__ __forceinline__ void ext_record(const Ws &w, int k, const int *md, int K, float2 kap) {
+  for (int i = 0; i < K; ++i) w.tc_md[5 * (long)k + i] = md[i];
+  w.tc_kap[k] = kap;
+}
+
 // Output: type, offsets, hit lists (pixel hits first, then MD hits inner to outer).
 __global__ void k_tc_write(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
@@ -1661,6 +1673,7 @@ __global__ void k_tc_write(const Ws *__restrict__ wb) {
     for (int q = 0; q < 4; ++q) h[q] = w.hits4[4 * (long)so.x + q];
     t5_hits(w, so.y, h + 4);
     w.tc_type[k] = 0;
+    ext_record(w, k, w.t5_md + 5 * (long)so.y, 5, seed_kappa(w, so.x));
     w.tc_off[k] = 14 * k;
   }
   for (int i = tid; i < np3; i += stride) {
@@ -1671,6 +1684,11 @@ __global__ void k_tc_write(const Ws *__restrict__ wb) {
     for (int q = 0; q < 4; ++q) h[q] = w.hits4[4 * (long)so.x + q];
     obj_hits<3>(w, so.y, h + 4);
     w.tc_type[n0 + k] = 1;
+    {
+      const int4 abc = w.t3_md[so.y];
+      const int md[3] = {abc.x, abc.y, abc.z};
+      ext_record(w, n0 + k, md, 3, seed_kappa(w, so.x));
+    }
     w.tc_off[n0 + k] = (int)(h1 + 10L * k);
   }
   for (int t = tid; t < nt5; t += stride) {
@@ -1678,6 +1696,8 @@ __global__ void k_tc_write(const Ws *__restrict__ wb) {
     const int k = w.p_t5[t];
     t5_hits(w, t, w.tc_hits + h2 + 10L * k);
     w.tc_type[n0 + n1 + k] = 2;
+    ext_record(w, n0 + n1 + k, w.t5_md + 5 * (long)t, 5,
+               make_float2(w.t5_attr[8 * (long)t], w.t3_attr[w.t5_t3[t].y].y));
     w.tc_off[n0 + n1 + k] = (int)(h2 + 10L * k);
   }
   for (int s = tid; s < w.n_seeds; s += stride) {
@@ -1687,6 +1707,221 @@ __global__ void k_tc_write(const Ws *__restrict__ wb) {
     for (int q = 0; q < 4; ++q) h[q] = w.hits4[4 * (long)s + q];
     w.tc_type[n0 + n1 + n2 + k] = 3;
     w.tc_off[n0 + n1 + n2 + k] = (int)(h3 + 4L * k);
+  }
+}
+
+// ------------------------------------------------- track extensions (S2.5)
+// A candidate with outer MDs (pT5, pT3, T5) is tested against the triplets
+// whose first two MDs are its last two (one MD added) and those whose first
+// MD is its last (two added): curvatures within their resolutions (the
+// seed's for pT5 / pT3, three resolutions; the outer triplet's for a T5),
+// azimuth linear in z over the first, the candidate's last and the last
+// added anchor, and the widened quintuplet fits (ext_fit).  The passing
+// triplet adding more MDs wins, then the smaller chi2_xy + chi2_rz, then the
+// smaller hit tuple of the added MDs.
+//
+// A wave takes kExtPerWave candidates; their (candidate, triplet) pairs are
+// laid out flat (wave_segments) so the lanes test one pair each, and every
+// candidate's lane then merges the passing pairs of its segment from LDS.  (A thread per
+// candidate walking its own triplets is bound by the longest such walk.)
+// (add, score, hits) of a strictly better than those of b
+__device__ __forceinline__ bool ext_better(int add_a, float sc_a, int4 h_a, int add_b, float sc_b, int4 h_b) {
+  if (add_a != add_b) return add_a > add_b;
+  if (sc_a < sc_b) return true;
+  if (sc_b < sc_a) return false;
+  const int ha[4] = {h_a.x, h_a.y, h_a.z, h_a.w}, hb[4] = {h_b.x, h_b.y, h_b.z, h_b.w};
+  for (int i = 0; i < 2 * add_a; ++i)
+    if (ha[i] != hb[i]) return ha[i] < hb[i];
+  return false;
+}
+
+// The K anchors of a candidate (K = 3 or 5; sP / sM [0..K)[e], staged in
+// LDS) followed by the ADD MDs of triplet abc in the kExtMax slots of ext_fit
+// (the slots past the chain repeat its last anchor), tested with the
+// lever-arm azimuth-z check and ext_fit; the added MDs' hits come back in h.
+template <int C>
+__device__ __forceinline__ bool ext_eval(const Ws &w, const DevGeom &g, const float4 (*sP)[C], const int (*sM)[C],
+                                         int e, int K, int add, int4 abc, float3 *a, int4 *h) {
+  const int nm0 = add == 1 ? abc.z : abc.y;
+  const float4 A0 = w.md_pos[nm0];
+  const int mod0 = w.md_mod[nm0];
+  const int2 h0 = w.md_hits[nm0];
+  float4 A1 = A0;
+  int mod1 = mod0;
+  int2 h1 = make_int2(0, 0);
+  if (add == 2) {
+    A1 = w.md_pos[abc.z];
+    mod1 = w.md_mod[abc.z];
+    h1 = w.md_hits[abc.z];
+  }
+  ModInfo I0, I1;
+  I0.bits = g.info[mod0];
+  I1.bits = g.info[mod1];
+  float4 P[kExtMax];
+  ModInfo M[kExtMax];
+#pragma unroll
+  for (int i = 0; i < kExtMax; ++i) {
+    if (i < 5 && i < K) {
+      P[i] = sP[i][e];
+      M[i].bits = sM[i][e];
+    } else {
+      P[i] = i == K ? A0 : A1;
+      M[i] = i == K ? I0 : I1;
+    }
+  }
+  *h = make_int4(h0.x, h0.y, h1.x, h1.y);
+  const float4 PK = K == 5 ? P[4] : P[2];
+  const ModInfo MK = K == 5 ? M[4] : M[2];
+  return phiz_pass(P[0], PK, A1, M[0], MK, I1) && ext_fit(P, M, K + add, a);
+}
+
+// Candidates per wave: few enough that their (candidate, triplet) pairs
+// (about 1.3 per candidate) spread over many waves.
+constexpr int kExtPerWave = 8;
+
+__global__ __launch_bounds__(kBlock) void k_tc_ext(const Ws *__restrict__ wb, DevGeom g) {
+  const Ws &w = wb[blockIdx.y];
+  constexpr int C = kExtPerWave;
+  __shared__ float4 s_P[kWaves][5][C];  // the candidates' anchors
+  __shared__ int s_M[kWaves][5][C], s_md[kWaves][C], s_k[kWaves][C], s_lo2[kWaves][C], s_n2[kWaves][C],
+      s_lo1[kWaves][C];  // module info bits, last MD, MD count, triplet ranges
+  __shared__ int s_seg[kWaves][65];
+  __shared__ float s_kt[kWaves][C], s_dkt[kWaves][C];
+  __shared__ int s_rt[kWaves][64], s_radd[kWaves][64];  // per pair of the round: triplet (-1: fails), MDs added
+  __shared__ float s_rsc[kWaves][64];
+  __shared__ int4 s_rh[kWaves][64];
+  __shared__ float4 s_ra[kWaves][64];
+  const int n = w.ctr[C_NTC];
+  const int n_ls = w.ctr[C_NLS], n_t3 = w.ctr[C_NT3];
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int wpb = blockDim.x >> 6;
+  for (long p0 = ((long)blockIdx.x * wpb + wv) * kExtPerWave; p0 < n; p0 += (long)gridDim.x * wpb * kExtPerWave) {
+    const int k = (int)p0 + lane;
+    const bool mine = lane < kExtPerWave && k < n;
+    int cnt = 0;
+    if (mine) {
+      const int type = w.tc_type[k];
+      const int K = type == 3 ? 0 : (type == 1 ? 3 : 5);
+      s_k[wv][lane] = K;
+      if (K > 0) {
+        int md[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) md[i] = i < K ? w.tc_md[5 * (long)k + i] : 0;
+        const float2 kap = w.tc_kap[k];
+        s_kt[wv][lane] = kap.x;
+        s_dkt[wv][lane] = kap.y;
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+          if (i < K) {
+            s_P[wv][i][lane] = w.md_pos[md[i]];
+            s_M[wv][i][lane] = g.info[w.md_mod[md[i]]];
+          }
+        // triplets with first MD m: those built from segments with inner MD m
+        const int m2 = K == 5 ? md[3] : md[1], m1 = K == 5 ? md[4] : md[2];
+        s_md[wv][lane] = m1;
+        const int l2b = min(w.ls_off[m2], n_ls), l2e = min(w.ls_off[m2 + 1], n_ls);
+        const int l1b = min(w.ls_off[m1], n_ls), l1e = min(w.ls_off[m1 + 1], n_ls);
+        const int lo2 = w.t3_off[l2b], hi2 = min(w.t3_off[l2e], n_t3);
+        const int lo1 = w.t3_off[l1b], hi1 = min(w.t3_off[l1e], n_t3);
+        const int n2 = hi2 > lo2 ? hi2 - lo2 : 0, n1 = hi1 > lo1 ? hi1 - lo1 : 0;
+        s_lo2[wv][lane] = lo2;
+        s_n2[wv][lane] = n2;
+        s_lo1[wv][lane] = lo1;
+        cnt = n2 + n1;
+      }
+    }
+    const int total = wave_segments(cnt, s_seg[wv]);
+    int best_n = 0, best_t = -1;
+    float best_s = 0.0f;
+    int4 best_h = make_int4(0, 0, 0, 0);
+    float4 best_a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    int e = 0;  // candidate of this lane's pair (pairs advance monotonically)
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      int rt = -1, radd = 0;
+      float rsc = 0.0f;
+      int4 rh = make_int4(0, 0, 0, 0);
+      float4 ra = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (c < total) {
+        while (s_seg[wv][e + 1] <= c) ++e;
+        const int idx = c - s_seg[wv][e];
+        const int K = s_k[wv][e], n2 = s_n2[wv][e];
+        const int ov = idx < n2 ? 2 : 1;
+        const int t = ov == 2 ? s_lo2[wv][e] + idx : s_lo1[wv][e] + (idx - n2);
+        const int4 abc = w.t3_md[t];
+        const float4 ta = w.t3_attr[t];
+        const int add = 3 - ov;
+        const float dk = ta.x - s_kt[wv][e];
+        bool ok = ov == 1 || abc.y == s_md[wv][e];
+        ok = ok && fabsf(dk) <= ta.y + s_dkt[wv][e];
+        if (ok) {
+          // one instantiation per chain length keeps the anchors in registers
+          float3 a;
+          int4 h;
+          if (ext_eval(w, g, s_P[wv], s_M[wv], e, K, add, abc, &a, &h)) {
+            rt = t;
+            radd = add;
+            rsc = a.x + a.y;
+            rh = h;
+            ra = make_float4(a.x, a.y, a.z, 0.0f);
+          }
+        }
+      }
+      s_rt[wv][lane] = rt;
+      s_radd[wv][lane] = radd;
+      s_rsc[wv][lane] = rsc;
+      s_rh[wv][lane] = rh;
+      s_ra[wv][lane] = ra;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // every candidate merges the pairs of its segment that fell in this round
+      const int q0 = max(s_seg[wv][lane], c0) - c0, q1 = min(s_seg[wv][lane + 1], c0 + 64) - c0;
+      for (int q = q0; q < q1; ++q) {
+        const int t = s_rt[wv][q];
+        if (t < 0) continue;
+        const int add = s_radd[wv][q];
+        const float sc = s_rsc[wv][q];
+        const int4 h = s_rh[wv][q];
+        if (best_t < 0 || ext_better(add, sc, h, best_n, best_s, best_h)) {
+          best_n = add; best_t = t; best_s = sc; best_h = h; best_a = s_ra[wv][q];
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (mine) {
+      w.ext_n[k] = best_n;
+      w.ext_t3[k] = best_t;
+      w.ext_attr[k] = best_a;
+      w.ext_cnt[k] = (w.tc_off[k + 1] - w.tc_off[k]) + 2 * best_n;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// The extended collection: each candidate's hits, then those of its added MDs.
+__global__ void k_tc_ext_write(const Ws *__restrict__ wb) {
+  const Ws &w = wb[blockIdx.y];
+  const int n = w.ctr[C_NTC];
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid == 0) w.ctr[C_EXT] = 1;
+  for (int k = tid; k < n; k += gridDim.x * blockDim.x) {
+    int *dst = w.ext_hits + w.ext_off[k];
+    const int b1 = w.tc_off[k + 1];
+    for (int h = w.tc_off[k]; h < b1; ++h) *dst++ = w.tc_hits[h];
+    const int na = w.ext_n[k];
+    if (na > 0) {
+      const int4 abc = w.t3_md[w.ext_t3[k]];
+      int2 hh = w.md_hits[na == 1 ? abc.z : abc.y];
+      dst[0] = hh.x;
+      dst[1] = hh.y;
+      if (na == 2) {
+        hh = w.md_hits[abc.z];
+        dst[2] = hh.x;
+        dst[3] = hh.y;
+      }
+    }
   }
 }
 
@@ -1702,7 +1937,8 @@ const char *const kSiteNames[] = {
     "pt3_bin", "pt5_bin", "pt_count", "pt3_scan", "pt3_fill", "pt5_scan", "pt5_fill",
     "pt_obj_count", "pt_obj_scan", "pt_obj_scatter", "pt3_dedup", "pt5_dedup",
     "tc_pt5", "tc_pt5_scan", "tc_pt5_dirs", "tc_pt3", "tc_pt3_scan", "tc_pt3_dirs",
-    "tc_t5", "tc_t5_scan", "tc_t5_dirs", "tc_pls", "tc_pls_scan", "tc_write"};
+    "tc_t5", "tc_t5_scan", "tc_t5_dirs", "tc_pls", "tc_pls_scan", "tc_write",
+    "tc_ext", "tc_ext_scan", "tc_ext_write"};
 const int kNumSites = (int)(sizeof(kSiteNames) / sizeof(kSiteNames[0]));
 static_assert(sizeof(kSiteNames) / sizeof(kSiteNames[0]) <= kMaxSites, "launch-site table");
 
@@ -1711,7 +1947,8 @@ static_assert(sizeof(kSiteNames) / sizeof(kSiteNames[0]) <= kMaxSites, "launch-s
 // shape the autotuner may choose.
 static const char *const kTunableSites[] = {"md_count", "md_fill",  "ls_count", "ls_fill",  "t3_count",
                                             "t3_fill",  "t5_count", "t5_fill",  "t5_dedup", "pt_count",
-                                            "pt3_fill", "pt5_fill", "tc_pt3",   "tc_t5",    "tc_pls"};
+                                            "pt3_fill", "pt5_fill", "tc_pt3",   "tc_t5",    "tc_pls",
+                                            "tc_ext"};
 
 bool site_tunable(int site) {
   if (site < 0 || site >= kNumSites) return false;
@@ -1855,6 +2092,10 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { if (seeds) k_tc_pls<<<gridwt(S), tb, 0, st>>>(wb); });
   run([&] { if (seeds) scan(wb, B, SC_FPLS, S, st); });
   run([&] { k_tc_write<<<grid(b.cap_tc), kBlock, 0, st>>>(wb); });
+  // track extensions (when the geometry enables them)
+  run([&] { if (g.ext) k_tc_ext<<<gridwt((b.cap_tc + kExtPerWave - 1) / kExtPerWave), tb, 0, st>>>(wb, g); });
+  run([&] { if (g.ext) scan(wb, B, SC_EXT, b.cap_tc, st); });
+  run([&] { if (g.ext) k_tc_ext_write<<<grid(b.cap_tc), kBlock, 0, st>>>(wb); });
 }
 
 }  // namespace lst

@@ -412,6 +412,125 @@ __device__ __forceinline__ bool t5_pass(const float4 *P, const ModInfo *M, float
   return true;
 }
 
+// ------------------------------------------------- track extensions (S2.5)
+// A candidate's MD chain lengthened by one triplet (its last one or two MDs
+// shared) is tested with the quintuplet's fits widened to the n = 4..7
+// anchors of the chain: the circle in x-y (chi2 <= 10 per degree of freedom,
+// N - 3) and the straight line in (arc length, z) (chi2 <= 20/3 per degree
+// of freedom, N - 2), arc lengths taken with the fitted circle's curvature.
+// out = (chi2_xy, chi2_rz, kappa).
+constexpr double kXExtXyD = 10.0, kXExtRzD = 20.0 / 3.0;
+
+// Room for the longest chain (a five-MD candidate plus two MDs); a chain of
+// n < kExtMax anchors occupies P[0..n) and every sum skips the slots past it,
+// so each term enters in the order a fit over exactly n anchors adds it.
+constexpr int kExtMax = 7;
+
+__device__ __forceinline__ bool ext_fit(const float4 *P, const ModInfo *M, int n, float3 *out) {
+  float4 PL = P[0];
+#pragma unroll
+  for (int i = 1; i < kExtMax; ++i)
+    if (i == n - 1) PL = P[i];
+  const float ex = PL.x - P[0].x, ey = PL.y - P[0].y;
+  const float L = sqrtf(ex * ex + ey * ey);
+  const float ux = ex / L, uy = ey / L;
+  float u[kExtMax], v[kExtMax], q[kExtMax], w[kExtMax];
+#pragma unroll
+  for (int i = 0; i < kExtMax; ++i) {
+    const float dx = P[i].x - P[0].x, dy = P[i].y - P[0].y;
+    u[i] = (dx * ux + dy * uy) / L;
+    v[i] = (dy * ux - dx * uy) / L;
+    q[i] = u[i] * u[i] + v[i] * v[i];
+    const float t = L / M[i].sig_t();
+    w[i] = t * t;
+  }
+  float S0 = 0.0f, S1 = 0.0f, S2 = 0.0f, S11 = 0.0f, S12 = 0.0f, S22 = 0.0f, T0 = 0.0f, T1 = 0.0f, T2 = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kExtMax; ++i) {
+    if (i < n) {
+      S0 = S0 + w[i];
+      S1 = S1 + w[i] * u[i];
+      S2 = S2 + w[i] * q[i];
+      S11 = S11 + (w[i] * u[i]) * u[i];
+      S12 = S12 + (w[i] * u[i]) * q[i];
+      S22 = S22 + (w[i] * q[i]) * q[i];
+      T0 = T0 + w[i] * v[i];
+      T1 = T1 + (w[i] * u[i]) * v[i];
+      T2 = T2 + (w[i] * q[i]) * v[i];
+    }
+  }
+  const float m00 = S11 * S22 - S12 * S12;
+  const float m01 = S1 * S22 - S12 * S2;
+  const float m02 = S1 * S12 - S11 * S2;
+  const float det = (S0 * m00 - S1 * m01) + S2 * m02;
+  if (!(det > 0.0f)) return false;
+  const float n1 = T1 * S22 - S12 * T2;
+  const float n2 = T1 * S12 - S11 * T2;
+  const float n3 = S1 * T2 - T1 * S2;
+  const float deta = (T0 * m00 - S1 * n1) + S2 * n2;
+  const float detb = (S0 * n1 - T0 * m01) + S2 * n3;
+  const float detc = (S0 * (S11 * T2 - T1 * S12) - S1 * n3) + T0 * m02;
+  const float fa = deta / det, fb = detb / det, fc = detc / det;
+  float chi2xy = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kExtMax; ++i) {
+    const float r = v[i] - ((fa + fb * u[i]) + fc * q[i]);
+    if (i < n) chi2xy = chi2xy + (w[i] * r) * r;
+  }
+  const float disc = (1.0f + fb * fb) - (4.0f * fa) * fc;
+  if (!(disc > 0.0f)) return false;
+  const float kap = (2.0f * fc) / (L * sqrtf(disc));
+  if (!(chi2xy <= (float)(kXExtXyD * (double)(n - 3)))) return false;
+  float s[kExtMax];
+  s[0] = 0.0f;
+  bool series_ok = true;
+#pragma unroll
+  for (int i = 1; i < kExtMax; ++i) {
+    const float dx = P[i].x - P[i - 1].x, dy = P[i].y - P[i - 1].y;
+    const float Lc = sqrtf(dx * dx + dy * dy);
+    const float xs = (kap * Lc) * 0.5f;
+    if (i < n && !(fabsf(xs) <= kXSeriesMax)) series_ok = false;
+    s[i] = s[i - 1] + Lc * arc_over_chord(xs);
+  }
+  if (!series_ok) return false;
+  float sL = s[0];
+#pragma unroll
+  for (int i = 1; i < kExtMax; ++i)
+    if (i == n - 1) sL = s[i];
+  const float lam0 = (PL.z - P[0].z) / sL;
+  float S = 0.0f, Ss = 0.0f, Sz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kExtMax; ++i) {
+    const float sg = M[i].sig_z(lam0);
+    w[i] = 1.0f / (sg * sg);
+    if (i < n) {
+      S = S + w[i];
+      Ss = Ss + w[i] * s[i];
+      Sz = Sz + w[i] * P[i].z;
+    }
+  }
+  const float sbar = Ss / S, zbar = Sz / S;
+  float Sss = 0.0f, Ssz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kExtMax; ++i) {
+    const float ds = s[i] - sbar, dzz = P[i].z - zbar;
+    if (i < n) {
+      Sss = Sss + (w[i] * ds) * ds;
+      Ssz = Ssz + (w[i] * ds) * dzz;
+    }
+  }
+  const float lam = Ssz / Sss;
+  float chi2rz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kExtMax; ++i) {
+    const float r = (P[i].z - zbar) - lam * (s[i] - sbar);
+    if (i < n) chi2rz = chi2rz + (w[i] * r) * r;
+  }
+  if (!(chi2rz <= (float)(kXExtRzD * (double)(n - 2)))) return false;
+  *out = make_float3(chi2xy, chi2rz, kap);
+  return true;
+}
+
 // ------------------------------------------------------- pT3 / pT5 (S2.4)
 // Seed: sd = (pT, cx, cy, lambda, kappa, x0, y0, z0).  Anchors P[0..K-1].
 struct Seed {

@@ -15,6 +15,8 @@ enum Ctr : int {
   C_NOUTER = 20, C_NINC = 21, C_NPH = 22, C_NO3 = 23, C_NO5 = 24,      // scratch totals
   C_NB3 = 25, C_NB5 = 26,
   C_NLSOVF = 27,                 // MDs with more segments than the count pass caches
+  C_NEXTHITS = 28,               // hits of the extended track-candidate collection
+  C_EXT = 29,                    // 1 once the track extensions of the event are written
   C_COUNT = 64
 };
 enum : int { ST_BAD_HIT = 1, ST_BAD_SEED = 2, ST_CAPACITY = 4 };
@@ -24,6 +26,7 @@ struct DevGeom {
   const int *map_off, *map_tgt;
   const float4 *win;  // per module: W, A1, A2, A3
   const int *info;    // per module: bit 0 = 2S, bit 1 = endcap
+  int ext;            // 1: the chain ends with the track extensions
 };
 
 // One exclusive scan of the chain: out[0..n] = scan of in[0..n), n = *n_dev
@@ -39,7 +42,7 @@ struct ScanJob {
 };
 enum ScanId : int {
   SC_HITS, SC_MD, SC_LS, SC_T3, SC_T5, SC_INC, SC_PH, SC_PT3, SC_PT5, SC_O3, SC_O5,
-  SC_F5, SC_F3, SC_FT5, SC_FPLS, SC_B3, SC_B5, SC_LSOVF, SC_COUNT
+  SC_F5, SC_F3, SC_FT5, SC_FPLS, SC_B3, SC_B5, SC_LSOVF, SC_EXT, SC_COUNT
 };
 // One array cleared to zero at the start of the chain.
 struct FillJob {
@@ -126,6 +129,12 @@ struct Ws {
   float4 *bdir_pt5, *bdir_pt3, *bdir_t5;        // the same, grouped by azimuth bin
   int *boff_pt5, *boff_pt3, *boff_t5;           // bin offsets (kDirBins + 1)
   int *tc_type, *tc_off, *tc_hits;
+  int *tc_md;                                   // its outer-tracker MDs, inner to outer (5 per TC)
+  float2 *tc_kap;                               // its curvature and curvature tolerance
+  // track extensions, per TC: MDs added (0-2), triplet (-1: none), (chi2_xy, chi2_rz, kappa),
+  // hit count of the extended TC, its exclusive scan, the extended hit lists
+  int *ext_n, *ext_t3, *ext_cnt, *ext_off, *ext_hits;
+  float4 *ext_attr;
   // scan scratch and the job tables of the generic scan / clear kernels
   int *scan_tmp;
   ScanJob scans[SC_COUNT];

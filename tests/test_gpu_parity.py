@@ -120,6 +120,87 @@ def test_physics_metrics_from_hip_candidates(lst, gfull, many_oracle):
         assert mh["efficiency"] > (0.93 if config == "pu200_seeded" else 0.8)
 
 
+@pytest.fixture(scope="module")
+def gfull_ext(lst, full):
+    g = lst.Geometry(full)
+    g.set_track_extensions(True)
+    return g
+
+
+def _compare_ext(r, o):
+    """Extended collection, added-MD counts, triplet indices and fit attributes: all bit-exact."""
+    tg, og_, hg, ng, t3g, ag = r.extended_track_candidates()
+    na, t3, at, oo, ho = o.extensions()
+    to, _, _ = o.tc()
+    assert np.array_equal(tg, to), "types differ"
+    assert np.array_equal(ng, na), "added-MD counts differ"
+    assert np.array_equal(t3g, t3), "extension triplets differ"
+    assert np.array_equal(og_, oo) and np.array_equal(hg, ho), "extended hit lists differ"
+    assert np.array_equal(ag.view(np.int32), at.astype(np.float32).view(np.int32)), "extension attributes differ"
+    return int((ng > 0).sum()), len(tg)
+
+
+def test_extensions_equal_oracle(lst, gfull_ext, many_oracle):
+    """Track extensions of seeded and unseeded PU200-like events against the oracle, the base
+    candidates unchanged by the extra step."""
+    n_ext = n_tc = 0
+    for s in [x for x in MANY if x[0] == "pu200_seeded"][:6] + [x for x in MANY if x[0] == "pu200"][:3]:
+        ev, o = many_oracle[s]
+        r = _run(lst, gfull_ext, ev)
+        compare_tc(r, o)
+        a, b = _compare_ext(r, o)
+        n_ext += a
+        n_tc += b
+        r.close()
+    print(f"[gpu] extensions: {n_ext} of {n_tc} candidates extended", flush=True)
+    assert 0.25 * n_tc < n_ext < 0.6 * n_tc
+
+
+def test_extensions_small_and_empty_events(lst, barrel, obarrel):
+    g = lst.Geometry(barrel)
+    g.set_track_extensions(True)
+    for seed in range(3):
+        rng = np.random.default_rng(100 + seed)
+        n = 23 + 17 * seed
+        ev = make_single_track_event(barrel, np.exp(rng.uniform(np.log(0.8), np.log(20.0), n)),
+                                     rng.uniform(-0.5, 0.5, n), rng.uniform(0, 2 * np.pi, n), z0=rng.normal(0, 5, n),
+                                     q=np.where(rng.uniform(size=n) < 0.5, -1, 1), smear=bool(seed % 2),
+                                     seeded=seed != 1, seed=seed, n_noise=30)
+        r = _run(lst, g, ev)
+        _compare_ext(r, oracle.run(obarrel, ev))
+        r.close()
+    empty = Event(x=np.zeros(0, np.float32), y=np.zeros(0, np.float32), z=np.zeros(0, np.float32),
+                  module=np.zeros(0, np.int32), sensor=np.zeros(0, np.int32), sim=np.zeros(0, np.int32))
+    r = _run(lst, g, empty)
+    ty, off, hits, na, t3, at = r.extended_track_candidates()
+    assert len(ty) == 0 and list(off) == [0] and len(hits) == 0
+    r.close()
+
+
+def test_extensions_disabled_is_an_error(lst, gbarrel):
+    ev = make_event("tiny", 0)
+    r = _run(lst, gbarrel, ev)
+    with pytest.raises(lst.LSTError) as ei:
+        r.extended_track_candidates()
+    assert ei.value.status == lst.LST_E_STATE
+    r.close()
+    lib = lst.load_library()
+    assert lib.lst_set_track_extensions(gbarrel.handle, 2) == lst.LST_E_INVALID
+    assert lib.lst_set_track_extensions(None, 1) == lst.LST_E_INVALID
+
+
+def test_extensions_in_captured_plan(lst, gfull_ext, many_oracle):
+    """The extension step inside a captured batch plan, event by event against the oracle."""
+    evs = [many_oracle[s][0] for s in BATCH[:4]]
+    dev = [lst.upload_event(e) for e in evs]
+    plan = lst.Plan(gfull_ext, len(evs), max(e.n_hits for e in evs), max(e.n_seeds for e in evs))
+    for _ in range(2):  # two replays
+        for r, s in zip(plan.run(dev), BATCH[:4]):
+            _compare_ext(r, many_oracle[s][1])
+            r.close()
+    plan.close()
+
+
 def test_parity_batch_plan_events(lst, gfull, many_oracle):
     """Eight pile-up U[140, 250] events in one captured plan, each against the oracle."""
     evs = [many_oracle[s][0] for s in BATCH]
