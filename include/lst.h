@@ -211,6 +211,17 @@ lst_status lst_server_destroy(lst_server srv);
 lst_status lst_get_track_candidates(lst_event ev, int32_t *n_tc, int32_t *n_hits_total, int32_t *type,
                                     int32_t *offsets, int32_t *hits);
 
+/* Transverse impact-parameter bound d0_max [cm] that every selection allows
+ * for (MD windows, segment azimuth window and stub directions, the
+ * azimuth-z pointing of triplets, quintuplets and extensions).  0.1 cm from
+ * lst_load_geometry; Section 3 runs the same chain on displaced muons, for
+ * which the bound is widened to their largest displacement.  Recomputes the
+ * per-module MD windows on the device (synchronous) and applies to chains
+ * enqueued afterwards (plans created afterwards); call it while no chain of
+ * this geometry is in flight.  Errors: LST_E_INVALID for
+ * a NULL geometry or a bound outside (0, 10]; LST_E_DEVICE. */
+lst_status lst_set_impact_bound(lst_geometry geom, double d0_max);
+
 /* Track extensions (Section 2.5, last part): the final collection in which
  * a candidate with outer-tracker MDs (pT5, pT3, T5) is lengthened outward by
  * one triplet that shares its last two MDs (one MD added) or its last MD

@@ -14,6 +14,11 @@ Workloads (cm, GeV, B = 3.8 T):
 * ``serve``     as ``pu200_seeded`` with pile-up PU ~ U[50, 250] (tracks and
                 loopers scaled by PU / 200).
 * ``batch``     as ``pu200_seeded`` with PU ~ U[140, 250].
+* ``cube``      full geometry; 50 muons per event from production vertices
+                uniform in a 5 cm cube centred on the origin (|x|, |y|, |z|
+                <= 2.5 cm; transverse displacement up to 3.5 cm), pT
+                log-uniform in [0.8, 50], eta uniform in [-2.4, 2.4]; 200
+                noise hits; no pixel seeds.
 
 Hits are the exact sensor crossings of ideal helices (no material, no
 inefficiency), taken on the outgoing half-turn only, plus a uniform smear
@@ -40,8 +45,9 @@ CONFIGS = {
                   pu_range=(50.0, 250.0)),
     "batch": dict(geom="full", n_trk=8000, eta=2.4, n_loop=40000, noise_frac=0.05, seeds=True,
                   pu_range=(140.0, 250.0)),
+    "cube": dict(geom="full", n_trk=50, eta=2.4, n_loop=0, noise_abs=200, seeds=False, cube=5.0),
 }
-CONFIG_NUMBER = {"tiny": 1, "pu200": 2, "pu200_seeded": 3, "serve": 4, "batch": 5}
+CONFIG_NUMBER = {"tiny": 1, "pu200": 2, "pu200_seeded": 3, "serve": 4, "batch": 5, "cube": 6}
 
 
 @dataclass
@@ -158,6 +164,37 @@ def _draw_tracks(rng, n, eta_max, pt_lo, pt_hi, log_pt):
     return dict(pt=pt, eta=eta, phi=phi, z0=z0, d0=d0, q=q)
 
 
+def helix_from_vertex(vx, vy, vz, psi, kappa, lam):
+    """(phi0, d0, z0, s_v) of the helix that passes the vertex (vx, vy, vz) with
+    azimuthal direction psi there, in helix_point's parameters, and the arc
+    length s_v of the vertex from the point of closest approach (negative:
+    the vertex lies before it)."""
+    rho = 1.0 / kappa
+    cx = vx - rho * np.sin(psi)
+    cy = vy + rho * np.cos(psi)
+    D = np.hypot(cx, cy)
+    sgn = np.sign(rho)
+    # the centre is (d0 + rho) (-sin phi0, cos phi0); d0 + rho = sgn * D picks the near point
+    phi0 = np.arctan2(-sgn * cx, sgn * cy)
+    d0 = sgn * D - rho
+    dpsi = np.mod(psi - phi0 + math.pi, TWO_PI) - math.pi
+    s_v = dpsi / kappa
+    return phi0, d0, vz - lam * s_v, s_v
+
+
+def _draw_displaced(rng, n, eta_max, side):
+    """Muons from vertices uniform in a cube of the given side centred on the origin."""
+    pt = np.exp(rng.uniform(math.log(0.8), math.log(50.0), n))
+    eta = rng.uniform(-eta_max, eta_max, n)
+    psi = rng.uniform(0.0, TWO_PI, n)
+    q = np.where(rng.uniform(0.0, 1.0, n) < 0.5, -1, 1)
+    v = rng.uniform(-0.5 * side, 0.5 * side, (3, n))
+    kappa = -q * K_CURV / pt
+    phi0, d0, z0, _ = helix_from_vertex(v[0], v[1], v[2], psi, kappa, np.sinh(eta))
+    return dict(pt=pt, eta=eta, phi=phi0, z0=z0, d0=d0, q=q, vx=v[0], vy=v[1], vz=v[2], psi=psi,
+                dxy=np.hypot(v[0], v[1]))
+
+
 def _assemble(geom, tracks, rng, smear, noise_abs=None, noise_frac=None, seeded=False,
               n_fake_seeds=None, fake_tracks=None, name=""):
     kappa = -tracks["q"] * K_CURV / tracks["pt"]
@@ -249,7 +286,10 @@ def make_event(config, event, pu=None, smear=True):
     scale = 1.0 if pu is None else pu / 200.0
     n_trk = int(round(cfg["n_trk"] * scale))
     n_loop = int(round(cfg["n_loop"] * scale))
-    t1 = _draw_tracks(rng, n_trk, cfg["eta"], 0.8, 50.0, True)
+    if "cube" in cfg:
+        t1 = _draw_displaced(rng, n_trk, cfg["eta"], cfg["cube"])
+    else:
+        t1 = _draw_tracks(rng, n_trk, cfg["eta"], 0.8, 50.0, True)
     if n_loop:
         t2 = _draw_tracks(rng, n_loop, cfg["eta"], 0.1, 0.8, False)
         tracks = {k: np.concatenate([t1[k], t2[k]]) for k in t1}

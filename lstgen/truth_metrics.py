@@ -7,8 +7,9 @@ own: the track id of every hit, -1 for noise and for the hits of fake seeds.
 
 * efficiency: fraction of the denominator tracks (pT above the threshold,
   |eta| inside the acceptance) that at least one candidate matches; also in
-  bins of pT, of eta and of the transverse impact parameter, as the paper
-  plots it;
+  bins of pT, of eta, of the transverse impact parameter and, for samples
+  with displaced production vertices, of the vertex's transverse distance
+  from the beam line (the paper's Delta_xy), as the paper plots it;
 * fake rate: fraction of candidates matched to no track;
 * duplicate rate: fraction of candidates whose track is matched by two or
   more candidates (all of them count, the first one too).
@@ -24,6 +25,7 @@ TC_TYPES = ("pT5", "pT3", "T5", "pLS")
 PT_BINS = (0.8, 0.9, 1.0, 1.5, 2.0, 5.0, 10.0, 50.0)
 ETA_BINS = tuple(np.round(np.linspace(-2.4, 2.4, 13), 2))
 D0_BINS = (0.0, 0.01, 0.02, 0.05, 0.5, 2.0, 5.0, 10.0)
+DXY_BINS = (0.0, 0.5, 1.0, 1.5, 2.0, 2.5, 3.0, 3.6)
 
 
 def match_candidates(sim, offsets, hits, frac=0.75):
@@ -68,7 +70,7 @@ def pooled_metrics(events, pt_min=0.9, eta_max=2.4, frac=0.75):
     Tracks and candidates of all events are pooled (a track of one event can
     only be matched by candidates of the same event).
     """
-    types, matched, pt, eta, d0 = [], [], [], [], []
+    types, matched, pt, eta, d0, dxy = [], [], [], [], [], []
     base = 0
     for ev, (ty, off, hits) in events:
         m = match_candidates(np.asarray(ev.sim), np.asarray(off), np.asarray(hits), frac)
@@ -77,9 +79,10 @@ def pooled_metrics(events, pt_min=0.9, eta_max=2.4, frac=0.75):
         pt.append(np.asarray(ev.tracks["pt"], np.float64))
         eta.append(np.asarray(ev.tracks["eta"], np.float64))
         d0.append(np.abs(np.asarray(ev.tracks["d0"], np.float64)))
+        dxy.append(np.asarray(ev.tracks["dxy"], np.float64) if "dxy" in ev.tracks else np.full(pt[-1].size, np.nan))
         base += pt[-1].size
     types, matched = np.concatenate(types), np.concatenate(matched)
-    pt, eta, d0 = np.concatenate(pt), np.concatenate(eta), np.concatenate(d0)
+    pt, eta, d0, dxy = np.concatenate(pt), np.concatenate(eta), np.concatenate(d0), np.concatenate(dxy)
 
     n_match = np.bincount(matched[matched >= 0], minlength=pt.size)
     found_all = n_match > 0
@@ -109,6 +112,9 @@ def pooled_metrics(events, pt_min=0.9, eta_max=2.4, frac=0.75):
         "efficiency_vs_eta": _binned(eta[denom], found_all[denom], ETA_BINS),
         "efficiency_vs_d0": _binned(d0[denom], found_all[denom], D0_BINS),
     }
+    if np.isfinite(dxy).any():
+        # transverse distance of the production vertex from the beam line (displaced samples)
+        out["efficiency_vs_dxy"] = _binned(dxy[denom], found_all[denom], DXY_BINS)
     for k, name in enumerate(TC_TYPES):
         sel = types == k
         out["by_type"][name] = {

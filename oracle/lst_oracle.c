@@ -48,7 +48,7 @@ typedef float real;
 static const double K_CURV = 0.299792458 * 3.8 / 100.0;
 static const double PT_MIN = 0.8;
 static const double Z_LUM = 20.0;   /* luminous-region half length [cm] */
-static const double D0_MAX = 0.1;   /* transverse impact parameter bound [cm] */
+static const double D0_MAX = 0.1;   /* default transverse impact-parameter bound [cm] */
 /* Half pitches per module type (0 PS, 1 2S): r-phi and long coordinate [cm]. */
 static const double H_PHI[2] = {0.005, 0.0045};
 static const double H_LONG[2] = {0.075, 2.5};
@@ -95,6 +95,7 @@ typedef struct {
   int *map_off, *map_tgt;
   real *W, *A1, *A2, *A3;      /* per-module MD window constants */
   double *Wd, *A1d, *A2d, *A3d;
+  double d0max;                 /* transverse impact-parameter bound of the selections [cm] */
 } orc_geom;
 
 /* asin(x) for |x| <= 0.85 from its Maclaurin series, summed in a fixed order
@@ -120,14 +121,14 @@ static double ser_asin(double x) {
  * phi0 + asin(kappa r / 2) and z is linear in the transverse arc length
  * s(r) = 2 asin(kappa r / 2) / kappa, with |kappa| <= kappa_max. */
 static void module_constants(int sd, int ty, double p_lo, double p_up, double l_min, double l_max,
-                             double out[4]) {
+                             double d0max, double out[4]) {
   const double km = K_CURV / PT_MIN;
   const double hp = H_PHI[ty], hl = H_LONG[ty];
   double W, A1 = 0.0, A2 = 0.0, A3 = 0.0;
   if (sd == 0) {
     double r1 = p_lo, r2 = p_up;
     double a1 = ser_asin(km * r1 / 2.0), a2 = ser_asin(km * r2 / 2.0);
-    double dphi = (a2 - a1) + D0_MAX * (1.0 / r1 - 1.0 / r2) + hp / r1 + hp / r2;
+    double dphi = (a2 - a1) + d0max * (1.0 / r1 - 1.0 / r2) + hp / r1 + hp / r2;
     W = dphi * (1.0 + 1e-3) + 1e-6;
     if (ty == 0) {
       double a = r2 / r1;
@@ -143,7 +144,7 @@ static void module_constants(int sd, int ty, double p_lo, double p_up, double l_
     double gmax = ser_asin(xg) / xg;
     double k = (z2 - z1) * gmax / (z1 - Z_LUM);
     double b1 = ser_asin(km * rmax / 2.0), b2 = ser_asin(km * rmax * (1.0 + k) / 2.0);
-    double dphi = (b2 - b1) + D0_MAX * k / rmin + 2.0 * hp / rmin;
+    double dphi = (b2 - b1) + d0max * k / rmin + 2.0 * hp / rmin;
     W = dphi * (1.0 + 1e-3) + 1e-6;
     if (ty == 0) {
       A1 = k * (1.0 + 1e-3);
@@ -151,6 +152,20 @@ static void module_constants(int sd, int ty, double p_lo, double p_up, double l_
     }
   }
   out[0] = W; out[1] = A1; out[2] = A2; out[3] = A3;
+}
+
+/* Sets the transverse impact-parameter bound every selection assumes
+ * (Section 3's displaced tracks: the same chain with a wider bound) and
+ * recomputes the MD windows, which depend on it. */
+void orc_geom_set_d0max(void *gp, double d0max) {
+  orc_geom *g = (orc_geom *)gp;
+  g->d0max = d0max;
+  for (int m = 0; m < g->n_mod; ++m) {
+    double c[4];
+    module_constants(g->subdet[m], g->type[m], g->pos_lo[m], g->pos_up[m], g->lmin[m], g->lmax[m], d0max, c);
+    g->Wd[m] = c[0]; g->A1d[m] = c[1]; g->A2d[m] = c[2]; g->A3d[m] = c[3];
+    g->W[m] = (real)c[0]; g->A1[m] = (real)c[1]; g->A2[m] = (real)c[2]; g->A3[m] = (real)c[3];
+  }
 }
 
 void *orc_geom_create(int n_mod, const int *subdet, const int *layer, const int *side, const int *type,
@@ -169,12 +184,9 @@ void *orc_geom_create(int n_mod, const int *subdet, const int *layer, const int 
   g->Wd = (double *)malloc(sizeof(double) * n_mod); g->A1d = (double *)malloc(sizeof(double) * n_mod);
   g->A2d = (double *)malloc(sizeof(double) * n_mod); g->A3d = (double *)malloc(sizeof(double) * n_mod);
   for (int m = 0; m < n_mod; ++m) {
-    double c[4];
     g->pos_lo[m] = pos_lo[m]; g->pos_up[m] = pos_up[m]; g->lmin[m] = lmin[m]; g->lmax[m] = lmax[m];
-    module_constants(subdet[m], type[m], pos_lo[m], pos_up[m], lmin[m], lmax[m], c);
-    g->Wd[m] = c[0]; g->A1d[m] = c[1]; g->A2d[m] = c[2]; g->A3d[m] = c[3];
-    g->W[m] = (real)c[0]; g->A1[m] = (real)c[1]; g->A2[m] = (real)c[2]; g->A3[m] = (real)c[3];
   }
+  orc_geom_set_d0max(g, D0_MAX);
   return g;
 }
 
@@ -334,7 +346,7 @@ static int ls_select(const orc_geom *g, orc_event *e, int a_md, int b_md, real *
   if (!(d > RL(0))) { ac->firm_fail = 1; return 0; }
   real ub = kh * (rb + eb);
   real ua = kh * (ra - ea);
-  real w = (ub - ua) / RSQRT_(RL(1) - ub * ub) + ((real)D0_MAX * dr) / (ra * rb) + hphi_of(g, ma) / ra +
+  real w = (ub - ua) / RSQRT_(RL(1) - ub * ub) + ((real)g->d0max * dr) / (ra * rb) + hphi_of(g, ma) / ra +
            hphi_of(g, mb) / rb;
   real W = w * (real)1.001 + (real)1e-6;
   ok &= cut_le(ac, RABS(c), W * (ra * rb), RL(0));
@@ -381,13 +393,13 @@ static int ls_select(const orc_geom *g, orc_event *e, int a_md, int b_md, real *
       real cs2 = RL(1) - sb * sb;
       if (!(cs2 > RL(0))) { ac->firm_fail = 1; return 0; }
       pred = (dl * sb) / RSQRT_(cs2);
-      err = RL(2) * hphi_of(g, m) + (RL(2) * dl) * (eang + (real)D0_MAX / rp);
+      err = RL(2) * hphi_of(g, m) + (RL(2) * dl) * (eang + (real)g->d0max / rp);
     } else {
       if (!(dzab > RL(0))) { ac->firm_fail = 1; return 0; }
       real dl = RABS(e->z[j]) - RABS(e->z[i]);
       real ds = (dl * Ls) / dzab;
       pred = ds * sb;
-      err = (RL(2) * hphi_of(g, m) + (real)0.03 * RABS(pred)) + ds * (eang + (real)D0_MAX / rp);
+      err = (RL(2) * hphi_of(g, m) + (real)0.03 * RABS(pred)) + ds * (eang + (real)g->d0max / rp);
     }
     real dt = tau - pred;
     ok &= cut_le(ac, RABS(dt), err * (real)1.001 + (real)1e-6, RL(0));
@@ -444,8 +456,8 @@ static int phiz_test(const orc_geom *g, orc_event *e, int mp, int mq, int mr, cu
   real ezR = endcap_of(g, mR) ? RL(0) : hlong_of(g, mR);
   real iP = RL(1) / rP, iQ = RL(1) / rQ, iR = RL(1) / rR;
   real dpq = iP - iQ, dqr = iQ - iR;
-  real ePQ = (hphi_of(g, mP) * iP + hphi_of(g, mQ) * iQ) + (real)D0_MAX * RABS(dpq);
-  real eQR = (hphi_of(g, mQ) * iQ + hphi_of(g, mR) * iR) + (real)D0_MAX * RABS(dqr);
+  real ePQ = (hphi_of(g, mP) * iP + hphi_of(g, mQ) * iQ) + (real)g->d0max * RABS(dpq);
+  real eQR = (hphi_of(g, mQ) * iQ + hphi_of(g, mR) * iR) + (real)g->d0max * RABS(dqr);
   real au = RABS(su), av = RABS(sv), adpq = RABS(dzpq), adqr = RABS(dzqr);
   real nl = (au * au + av * av) * (real)(1.0 / 3.0);
   real tol = ((adqr * ePQ + adpq * eQR) + (au * (ezQ + ezR) + av * (ezP + ezQ))) + nl * (au * adqr + av * adpq);

@@ -48,7 +48,11 @@ struct lst_geometry_s {
   int *d_off = nullptr, *d_tgt = nullptr, *d_info = nullptr;
   float4 *d_win = nullptr;
   int site_block[lst::kMaxSites] = {};  // launch shape of each tunable site (0 = default)
+  float *d_pos = nullptr;  // per module: pos_lo, pos_up, lmin, lmax (kept to recompute the windows)
 };
+
+// Transverse impact-parameter bound of the selections unless set otherwise [cm].
+constexpr double kD0MaxDefault = 0.1;
 
 // Events enqueued together share one batch: one descriptor array and one
 // counter block in the workspace header, one completion event, one pinned
@@ -257,12 +261,12 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   if (!g) return fail(LST_E_NOMEM, "host allocation failed");
   std::vector<int> info(M);
   for (int m = 0; m < M; ++m) info[m] = (d->type[m] & 1) | ((d->subdet[m] & 1) << 1);
-  float *d_pos = nullptr;
   auto cleanup = [&]() {
     drop(hipFree(g->d_off)); drop(hipFree(g->d_tgt)); drop(hipFree(g->d_info)); drop(hipFree(g->d_win));
-    drop(hipFree(d_pos));
+    drop(hipFree(g->d_pos));
     delete g;
   };
+  float *&d_pos = g->d_pos;
   if (hipMalloc(&g->d_off, sizeof(int) * (M + 1)) != hipSuccess ||
       hipMalloc(&g->d_tgt, sizeof(int) * (E > 0 ? E : 1)) != hipSuccess ||
       hipMalloc(&g->d_info, sizeof(int) * M) != hipSuccess || hipMalloc(&g->d_win, sizeof(float4) * M) != hipSuccess ||
@@ -279,7 +283,8 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   if (e == hipSuccess) e = hipMemcpy(d_pos + 2 * M, d->lmin, sizeof(float) * M, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_pos + 3 * M, d->lmax, sizeof(float) * M, hipMemcpyHostToDevice);
   if (e == hipSuccess) {
-    lst::launch_module_windows(g->d_info, d_pos, d_pos + M, d_pos + 2 * M, d_pos + 3 * M, M, g->d_win, nullptr);
+    lst::launch_module_windows(g->d_info, d_pos, d_pos + M, d_pos + 2 * M, d_pos + 3 * M, M, kD0MaxDefault, g->d_win,
+                               nullptr);
     e = hipGetLastError();
   }
   if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -287,7 +292,6 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
     cleanup();
     return fail(LST_E_DEVICE, std::string("lst_load_geometry: ") + hipGetErrorString(e));
   }
-  drop(hipFree(d_pos));
   g->g.n_mod = M;
   g->g.n_edges = E;
   g->g.map_off = g->d_off;
@@ -295,7 +299,20 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   g->g.win = g->d_win;
   g->g.info = g->d_info;
   g->g.ext = 0;
+  g->g.d0max = (float)kD0MaxDefault;
   *out = g;
+  return LST_OK;
+}
+
+lst_status lst_set_impact_bound(lst_geometry g, double d0_max) {
+  if (!g || !(d0_max > 0.0) || !(d0_max <= 10.0))
+    return fail(LST_E_INVALID, "lst_set_impact_bound: geometry NULL or bound outside (0, 10] cm");
+  const int M = g->g.n_mod;
+  float *p = g->d_pos;
+  lst::launch_module_windows(g->d_info, p, p + M, p + 2 * M, p + 3 * M, M, d0_max, g->d_win, nullptr);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipDeviceSynchronize());
+  g->g.d0max = (float)d0_max;
   return LST_OK;
 }
 
@@ -308,6 +325,7 @@ lst_status lst_set_track_extensions(lst_geometry g, int32_t enable) {
 lst_status lst_release_geometry(lst_geometry g) {
   if (!g) return LST_OK;
   drop(hipFree(g->d_off)); drop(hipFree(g->d_tgt)); drop(hipFree(g->d_info)); drop(hipFree(g->d_win));
+  drop(hipFree(g->d_pos));
   delete g;
   return LST_OK;
 }

@@ -177,18 +177,18 @@ static void scan(const Ws *wb, int B, int job, long n_cap, hipStream_t st) {
 
 // ------------------------------------------------------------- windows
 __global__ void k_module_windows(const int *info, const float *pos_lo, const float *pos_up, const float *lmin,
-                                 const float *lmax, int n_mod, float4 *win) {
+                                 const float *lmax, int n_mod, double d0, float4 *win) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_mod) return;
   double w[4];
   module_windows((info[m] >> 1) & 1, info[m] & 1, (double)pos_lo[m], (double)pos_up[m], (double)lmin[m],
-                 (double)lmax[m], w);
+                 (double)lmax[m], d0, w);
   win[m] = make_float4((float)w[0], (float)w[1], (float)w[2], (float)w[3]);
 }
 
 void launch_module_windows(const int *info, const float *pos_lo, const float *pos_up, const float *lmin,
-                           const float *lmax, int n_mod, float4 *win, hipStream_t st) {
-  k_module_windows<<<(n_mod + 127) / 128, 128, 0, st>>>(info, pos_lo, pos_up, lmin, lmax, n_mod, win);
+                           const float *lmax, int n_mod, double d0, float4 *win, hipStream_t st) {
+  k_module_windows<<<(n_mod + 127) / 128, 128, 0, st>>>(info, pos_lo, pos_up, lmin, lmax, n_mod, d0, win);
 }
 
 // ------------------------------------------------------------- a0: hits
@@ -437,11 +437,11 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
 // |A x B| <= Wmax r_A r_B fails ls_pass; and since |A x B| = r_A |n.B| >= r_A
 // (|n.C| - rho) for the unit normal n of A, with r_B <= |C| + rho, a module
 // failing |n.C| - rho <= Wmax (|C| + rho) has no candidate that can pass.
-__device__ __forceinline__ float ls_window_bound(const float4 &A, ModInfo ma, float4 disc, ModInfo mb) {
+__device__ __forceinline__ float ls_window_bound(const float4 &A, ModInfo ma, float4 disc, ModInfo mb, float d0) {
   const float ub = kHalfKmax * ((disc.w + disc.z) + mb.er());
   if (!(ub < 0.99f)) return 3.0e38f;  // no useful bound
   const float ua = kHalfKmax * (A.w - ma.er());
-  const float w = (ub - ua) / sqrtf(1.0f - ub * ub) + (kD0Max + ma.hphi() + 0.005f) / A.w;
+  const float w = (ub - ua) / sqrtf(1.0f - ub * ub) + (d0 + ma.hphi() + 0.005f) / A.w;
   return (w * kMargin + kEps) * 1.01f + 1e-6f;
 }
 
@@ -497,7 +497,7 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
         info = g.info[mb];
         if (cnt > 0) {
           const float4 disc = w.mod_disc[mb];
-          wm = ls_window_bound(A, mia, disc, ModInfo{info});
+          wm = ls_window_bound(A, mia, disc, ModInfo{info}, g.d0max);
           if (!ls_module_may_pass(A, disc, wm)) cnt = 0;
         }
       }
@@ -527,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
       float2 beta = make_float2(0.f, 0.f);
       if (lane < n) {
         b = s_q[wv][lane];
-        pass = ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, ModInfo{s_qi[wv][lane]}, &beta);
+        pass = ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, ModInfo{s_qi[wv][lane]}, &beta, g.d0max);
       }
       const unsigned long long m = __ballot(pass);
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -557,7 +557,7 @@ __global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeo
         b = s_first[wv][e] + (c - s_pre[wv][e]);
         const float4 Bp = w.md_pos[b];
         info = s_info[wv][e];
-        keep = ls_window_may_pass(A, Bp, s_wmax[wv][e]) && ls_inner_stub_ok(A, Bp, sa, mia, ModInfo{info});
+        keep = ls_window_may_pass(A, Bp, s_wmax[wv][e]) && ls_inner_stub_ok(A, Bp, sa, mia, ModInfo{info}, g.d0max);
       }
       const unsigned long long m = __ballot(keep);
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -690,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeo
         cmd = w.ls_md[s_lo[wv][e] + (c - s_seg[wv][e])].y;
         const int mi = s_mi[wv][e];
         pass = t3_pass(s_a[wv][e], s_b[wv][e], w.md_pos[cmd], ModInfo{mi & 0xff}, ModInfo{mi >> 8},
-                       ModInfo{g.info[w.md_mod[cmd]]}, &attr);
+                       ModInfo{g.info[w.md_mod[cmd]]}, &attr, g.d0max);
       }
       const unsigned long long m = __ballot(pass);
       if (FILL && pass) {
@@ -766,7 +766,7 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
         P[4] = w.md_pos[cde.z];
         M[3].bits = g.info[w.md_mod[cde.y]];
         M[4].bits = g.info[w.md_mod[cde.z]];
-        pass = t5_pass(P, M, s_tin[wv][e], w.t3_attr[t2], at);
+        pass = t5_pass(P, M, s_tin[wv][e], w.t3_attr[t2], at, g.d0max);
       }
       const unsigned long long m = __ballot(pass);
       if (FILL && pass) {
@@ -1772,7 +1772,7 @@ __device__ __forceinline__ bool ext_eval(const Ws &w, const DevGeom &g, const fl
   *h = make_int4(h0.x, h0.y, h1.x, h1.y);
   const float4 PK = K == 5 ? P[4] : P[2];
   const ModInfo MK = K == 5 ? M[4] : M[2];
-  return phiz_pass(P[0], PK, A1, M[0], MK, I1) && ext_fit(P, M, K + add, a);
+  return phiz_pass(P[0], PK, A1, M[0], MK, I1, g.d0max) && ext_fit(P, M, K + add, a);
 }
 
 // Candidates per wave: few enough that their (candidate, triplet) pairs

@@ -16,16 +16,17 @@
 namespace lst {
 
 // ---- physics constants (B = 3.8 T, pT threshold 0.8 GeV, Section 2.2) ----
+// (The transverse impact-parameter bound d0 of the selections is a parameter
+// of the detector description, DevGeom::d0max: 0.1 cm by default, wider for
+// displaced tracks.)
 constexpr double kCurvD = 0.299792458 * 3.8 / 100.0;  // |kappa| = kCurvD / pT  [1/cm, GeV]
 constexpr double kPtMinD = 0.8;
 constexpr double kZLumD = 20.0;   // luminous-region half length [cm]
-constexpr double kD0MaxD = 0.1;   // impact-parameter bound [cm]
 
 constexpr float kCurv = (float)kCurvD;
 constexpr float kHalfKmax = (float)(kCurvD / kPtMinD / 2.0);
 constexpr float kKmaxCut = (float)(kCurvD / kPtMinD * 1.01);
 constexpr float kZLum = (float)kZLumD;
-constexpr float kD0Max = (float)kD0MaxD;
 constexpr float kTau = (float)0.8;        // bound on sin(track-to-radial angle), endcap x-y error
 constexpr float kXT3 = (float)10.0;       // T3 r-z chi2
 constexpr float kXT5xy = (float)20.0;     // T5 circle-fit chi2
@@ -88,7 +89,7 @@ __device__ __forceinline__ double series_asin(double x) {
 //  W  bound on |sin(azimuth change)| between the two hits;
 //  PS barrel: |z_up - A1 z_lo| <= A2 + A3 |z_lo|;  PS endcap: -A2 <= r_up - r_lo <= A1 r_lo + A2.
 __device__ inline void module_windows(int endcap, int type2s, double p_lo, double p_up, double l_min, double l_max,
-                                      double w[4]) {
+                                      double d0, double w[4]) {
   const double km = kCurvD / kPtMinD;
   const double hp = type2s ? 0.0045 : 0.005;
   const double hl = type2s ? 2.5 : 0.075;
@@ -96,7 +97,7 @@ __device__ inline void module_windows(int endcap, int type2s, double p_lo, doubl
   if (!endcap) {
     const double r1 = p_lo, r2 = p_up;
     const double a1 = series_asin(km * r1 / 2.0), a2 = series_asin(km * r2 / 2.0);
-    const double dphi = (a2 - a1) + kD0MaxD * (1.0 / r1 - 1.0 / r2) + hp / r1 + hp / r2;
+    const double dphi = (a2 - a1) + d0 * (1.0 / r1 - 1.0 / r2) + hp / r1 + hp / r2;
     W = dphi * (1.0 + 1e-3) + 1e-6;
     if (!type2s) {
       const double a = r2 / r1;
@@ -112,7 +113,7 @@ __device__ inline void module_windows(int endcap, int type2s, double p_lo, doubl
     const double gmax = series_asin(xg) / xg;
     const double k = (z2 - z1) * gmax / (z1 - kZLumD);
     const double b1 = series_asin(km * rmax / 2.0), b2 = series_asin(km * rmax * (1.0 + k) / 2.0);
-    const double dphi = (b2 - b1) + kD0MaxD * k / rmin + 2.0 * hp / rmin;
+    const double dphi = (b2 - b1) + d0 * k / rmin + 2.0 * hp / rmin;
     W = dphi * (1.0 + 1e-3) + 1e-6;
     if (!type2s) {
       A1 = k * (1.0 + 1e-3);
@@ -162,18 +163,19 @@ __device__ __forceinline__ float2 ls_beta(const float4 &A, const float4 &B) {
 // One MD's stub direction against the chord AB (stub st = (tangential
 // displacement, sensor separation), sn = sine of the chord's angle to the
 // radial direction used for it, rp its radius).
-__device__ __forceinline__ bool ls_stub_ok(float2 st, ModInfo m, float sn, float rp, float Ls, float adz, float eang) {
+__device__ __forceinline__ bool ls_stub_ok(float2 st, ModInfo m, float sn, float rp, float Ls, float adz, float eang,
+                                           float d0) {
   float pred, err;
   if (!m.endcap()) {
     const float cs2 = 1.0f - sn * sn;
     if (!(cs2 > 0.0f)) return false;
     pred = (st.y * sn) / sqrtf(cs2);
-    err = 2.0f * m.hphi() + (2.0f * st.y) * (eang + kD0Max / rp);
+    err = 2.0f * m.hphi() + (2.0f * st.y) * (eang + d0 / rp);
   } else {
     if (!(adz > 0.0f)) return false;
     const float ds = (st.y * Ls) / adz;
     pred = ds * sn;
-    err = (2.0f * m.hphi() + (float)0.03 * fabsf(pred)) + ds * (eang + kD0Max / rp);
+    err = (2.0f * m.hphi() + (float)0.03 * fabsf(pred)) + ds * (eang + d0 / rp);
   }
   const float dt = st.x - pred;
   return fabsf(dt) <= err * kMargin + kEps;
@@ -184,7 +186,7 @@ __device__ __forceinline__ bool ls_stub_ok(float2 st, ModInfo m, float sn, float
 // luminous region, and each stub's direction against the origin-constrained
 // chord.  Returns the reported angles in *beta.
 __device__ __forceinline__ bool ls_pass(const float4 &A, const float4 &B, float2 sa, float2 sb, ModInfo ma,
-                                        ModInfo mb, float2 *beta) {
+                                        ModInfo mb, float2 *beta, float d0) {
   const float dr = B.w - A.w;
   if (!(dr > 0.0f)) return false;
   const float ea = ma.er(), eb = mb.er();
@@ -193,7 +195,7 @@ __device__ __forceinline__ bool ls_pass(const float4 &A, const float4 &B, float2
   if (!(d > 0.0f)) return false;
   const float ub = kHalfKmax * (B.w + eb);
   const float ua = kHalfKmax * (A.w - ea);
-  const float w = (((ub - ua) / sqrtf(1.0f - ub * ub) + (kD0Max * dr) / (A.w * B.w)) + ma.hphi() / A.w) +
+  const float w = (((ub - ua) / sqrtf(1.0f - ub * ub) + (d0 * dr) / (A.w * B.w)) + ma.hphi() / A.w) +
                   mb.hphi() / B.w;
   const float Wn = w * kMargin + kEps;
   bool ok = fabsf(c) <= Wn * (A.w * B.w);
@@ -224,15 +226,16 @@ __device__ __forceinline__ bool ls_pass(const float4 &A, const float4 &B, float2
   const float ea2 = ma.endcap() ? ma.hlong() : ma.hphi();
   const float eb2 = mb.endcap() ? mb.hlong() : mb.hphi();
   const float eang = (ea2 + eb2) / Ls;
-  ok &= ls_stub_ok(sa, ma, s_out, A.w, Ls, adz, eang);
-  ok &= ls_stub_ok(sb, mb, s_in, B.w, Ls, adz, eang);
+  ok &= ls_stub_ok(sa, ma, s_out, A.w, Ls, adz, eang, d0);
+  ok &= ls_stub_ok(sb, mb, s_in, B.w, Ls, adz, eang, d0);
   if (ok) *beta = ls_beta(A, B);
   return ok;
 }
 
 // The inner MD's stub check of ls_pass on its own, with the same operations in
 // the same order: a candidate failing it fails ls_pass.
-__device__ __forceinline__ bool ls_inner_stub_ok(const float4 &A, const float4 &B, float2 sa, ModInfo ma, ModInfo mb) {
+__device__ __forceinline__ bool ls_inner_stub_ok(const float4 &A, const float4 &B, float2 sa, ModInfo ma, ModInfo mb,
+                                                 float d0) {
   const float dz = B.z - A.z;
   const float sx = B.x - A.x, sy = B.y - A.y;
   const float Ls = sqrtf(sx * sx + sy * sy);
@@ -241,21 +244,21 @@ __device__ __forceinline__ bool ls_inner_stub_ok(const float4 &A, const float4 &
   const float ea2 = ma.endcap() ? ma.hlong() : ma.hphi();
   const float eb2 = mb.endcap() ? mb.hlong() : mb.hphi();
   const float eang = (ea2 + eb2) / Ls;
-  return ls_stub_ok(sa, ma, s_out, A.w, Ls, adz, eang);
+  return ls_stub_ok(sa, ma, s_out, A.w, Ls, adz, eang, d0);
 }
 
 // Azimuth linear in z over three anchors P, Q, R (Section 2.3 pointing for a
 // helix from the beam line): sin(phiQ-phiP)(zR-zQ) = sin(phiR-phiQ)(zQ-zP).
 __device__ __forceinline__ bool phiz_pass(const float4 &P, const float4 &Q, const float4 &R, ModInfo mp, ModInfo mq,
-                                          ModInfo mr) {
+                                          ModInfo mr, float d0) {
   const float su = (P.x * Q.y - P.y * Q.x) / (P.w * Q.w);
   const float sv = (Q.x * R.y - Q.y * R.x) / (Q.w * R.w);
   const float dzpq = Q.z - P.z, dzqr = R.z - Q.z;
   const float res = su * dzqr - sv * dzpq;
   const float iP = 1.0f / P.w, iQ = 1.0f / Q.w, iR = 1.0f / R.w;
   const float dpq = iP - iQ, dqr = iQ - iR;
-  const float ePQ = (mp.hphi() * iP + mq.hphi() * iQ) + kD0Max * fabsf(dpq);
-  const float eQR = (mq.hphi() * iQ + mr.hphi() * iR) + kD0Max * fabsf(dqr);
+  const float ePQ = (mp.hphi() * iP + mq.hphi() * iQ) + d0 * fabsf(dpq);
+  const float eQR = (mq.hphi() * iQ + mr.hphi() * iR) + d0 * fabsf(dqr);
   const float au = fabsf(su), av = fabsf(sv), adpq = fabsf(dzpq), adqr = fabsf(dzqr);
   const float nl = (au * au + av * av) * kThird;
   const float tol = ((adqr * ePQ + adpq * eQR) + (au * (mq.ez() + mr.ez()) + av * (mp.ez() + mq.ez()))) +
@@ -295,14 +298,14 @@ __device__ __forceinline__ float line_chi2(const float *s, const float *z, const
 // -------------------------------------------------------------- T3 (S2.3)
 // Anchors A, B, C of LS (a,b) + LS (b,c).  out = (kappa, dkappa, chi2_rz, lambda).
 __device__ __forceinline__ bool t3_pass(const float4 &A, const float4 &B, const float4 &C, ModInfo mA, ModInfo mB,
-                                        ModInfo mC, float4 *out) {
+                                        ModInfo mC, float4 *out, float d0) {
   const float ux = B.x - A.x, uy = B.y - A.y, wx = C.x - A.x, wy = C.y - A.y, tx = C.x - B.x, ty = C.y - B.y;
   const float k = ux * wy - uy * wx;
   const float Lu = sqrtf(ux * ux + uy * uy), Lw = sqrtf(wx * wx + wy * wy), Lt = sqrtf(tx * tx + ty * ty);
   const float kap = (2.0f * k) / ((Lu * Lw) * Lt);
   const float dk = (4.0f * ((mA.sig_t() + 2.0f * mB.sig_t()) + mC.sig_t())) / (Lw * Lw);
   if (!(fabsf(kap) <= kKmaxCut + dk)) return false;
-  if (!phiz_pass(A, B, C, mA, mB, mC)) return false;
+  if (!phiz_pass(A, B, C, mA, mB, mC, d0)) return false;
   const float xa = (kap * Lu) * 0.5f, xb = (kap * Lt) * 0.5f;
   if (!(fabsf(xa) <= kXSeriesMax) || !(fabsf(xb) <= kXSeriesMax)) return false;
   float s[3], z[3], w[3];
@@ -327,10 +330,11 @@ __device__ __forceinline__ bool t3_pass(const float4 &A, const float4 &B, const 
 // -------------------------------------------------------------- T5 (S2.3)
 // Anchors P[0..4]; tin/tout = (kappa, dkappa, ...) of the two triplets.
 // out[0..7] = kappa5, chi2_xy, chi2_rz, lambda, kappa_in, kappa_out, dir_x, dir_y.
-__device__ __forceinline__ bool t5_pass(const float4 *P, const ModInfo *M, float4 tin, float4 tout, float *out) {
+__device__ __forceinline__ bool t5_pass(const float4 *P, const ModInfo *M, float4 tin, float4 tout, float *out,
+                                        float d0) {
   const float dkk = tin.x - tout.x;
   if (!(fabsf(dkk) <= tin.y + tout.y)) return false;
-  if (!phiz_pass(P[0], P[2], P[4], M[0], M[2], M[4])) return false;
+  if (!phiz_pass(P[0], P[2], P[4], M[0], M[2], M[4], d0)) return false;
   // circle v = a + b u + c (u^2 + v^2) in the frame of the chord from P0 to P4, unit = chord
   const float ex = P[4].x - P[0].x, ey = P[4].y - P[0].y;
   const float L = sqrtf(ex * ex + ey * ey);

@@ -27,6 +27,7 @@ struct DevGeom {
   const float4 *win;  // per module: W, A1, A2, A3
   const int *info;    // per module: bit 0 = 2S, bit 1 = endcap
   int ext;            // 1: the chain ends with the track extensions
+  float d0max;        // transverse impact-parameter bound of the selections [cm]
 };
 
 // One exclusive scan of the chain: out[0..n] = scan of in[0..n), n = *n_dev
@@ -169,6 +170,6 @@ bool site_tunable(int site);
 void enqueue_chain(const DevGeom &g, const Ws *d_ws, int B, const Ws &bound, hipStream_t st, const KernelTimer *kt,
                    const int *site_block);
 void launch_module_windows(const int *info, const float *pos_lo, const float *pos_up, const float *lmin,
-                           const float *lmax, int n_mod, float4 *win, hipStream_t st);
+                           const float *lmax, int n_mod, double d0, float4 *win, hipStream_t st);
 
 }  // namespace lst

@@ -201,6 +201,36 @@ def test_extensions_in_captured_plan(lst, gfull_ext, many_oracle):
     plan.close()
 
 
+def test_displaced_bound_windows_and_cube_events(lst, full, barrel, obarrel):
+    """The displaced configuration (impact-parameter bound 3.6 cm): module windows and every stage
+    of displaced-muon events bit-exact; the barrel with a 1 cm bound on small events."""
+    g = lst.Geometry(full)
+    g.set_impact_bound(3.6)
+    og = oracle.OracleGeometry(full, d0_max=3.6)
+    assert np.array_equal(g.module_constants().view(np.int32), og.module_consts().view(np.int32))
+    n_t5 = 0
+    for k in range(12):
+        ev = make_event("cube", k)
+        r = _run(lst, g, ev)
+        o = oracle.run(og, ev)
+        stats = compare_event(r, o)
+        compare_tc(r, o)
+        n_t5 += stats["T5"]["oracle"]
+        r.close()
+    assert n_t5 > 300
+    gb = lst.Geometry(barrel)
+    gb.set_impact_bound(1.0)
+    ogb = oracle.OracleGeometry(barrel, d0_max=1.0)
+    for k in range(3):
+        ev = make_event("tiny", k)
+        r = _run(lst, gb, ev)
+        compare_event(r, oracle.run(ogb, ev), stages=range(4))
+        r.close()
+    lib = lst.load_library()
+    for bad in (0.0, -1.0, 10.5, float("nan")):
+        assert lib.lst_set_impact_bound(g.handle, bad) == lst.LST_E_INVALID
+
+
 def test_parity_batch_plan_events(lst, gfull, many_oracle):
     """Eight pile-up U[140, 250] events in one captured plan, each against the oracle."""
     evs = [many_oracle[s][0] for s in BATCH]
