@@ -299,7 +299,25 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
     const ModInfo mi{g.info[m]};
     int base = FILL ? w.md_off[m] : 0;
     const int np = (int)npair;  // <= kMdBig here
-    for (int p0 = 0; p0 < np; p0 += 64) {
+    const int n_md = FILL ? w.md_off[m + 1] - base : 0;
+    int *cache = w.md_cache + (long)kMdCache * m;
+    if (FILL && n_md <= kMdCache) {
+      // the count pass kept this module's passing pairs (row-major order): copy them
+      if (lane < n_md) {
+        const int pk = cache[lane];
+        const int i = pk >> 16, j = pk & 0xffff;
+        const int pos = base + lane;
+        if (pos < w.cap_md) {
+          const float4 hi = i < kMdStage ? s_lo[wv][i] : w.hpos[lo0 + i];
+          const float4 hj = j < kMdStage ? s_up[wv][j] : w.hpos[up0 + j];
+          w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
+          w.md_mod[pos] = m;
+          w.md_pos[pos] = hi;
+          w.md_stub[pos] = md_stub(hi, hj, mi);
+        }
+      }
+    }
+    for (int p0 = 0; p0 < np && !(FILL && n_md <= kMdCache); p0 += 64) {
       const int p = p0 + lane;
       bool pass = false;
       int i = 0, j = 0;
@@ -320,6 +338,10 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
           w.md_pos[pos] = hi;
           w.md_stub[pos] = md_stub(hi, hj, mi);
         }
+      }
+      if (!FILL && pass) {
+        const int r = base + lanes_below(bm);
+        if (r < kMdCache) cache[r] = (i << 16) | j;
       }
       base += __popcll(bm);
     }

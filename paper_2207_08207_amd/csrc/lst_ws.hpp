@@ -55,9 +55,11 @@ enum FillId : int {
   FL_O5_CNT, FL_O5_CUR, FL_SEED_USED, FL_T5_USED, FL_B3_CNT, FL_B3_CUR, FL_B5_CNT, FL_B5_CUR, FL_COUNT
 };
 
-// Passing partners remembered between a stage's count and fill passes: per MD
-// for segments, per seed for pT3 / pT5 (more than this: the fill searches again).
+// Passing partners remembered between a stage's count and fill passes: per
+// module for mini-doublets, per MD for segments, per seed for pT3 / pT5 (more
+// than this: the fill searches again).
 constexpr int kLsCache = 16;
+constexpr int kMdCache = 32;  // MDs per module whose (lower, upper) pair the MD count pass keeps
 constexpr int kPt3Cache = 256;  // pT3 per seed (PU200 maximum ~190)
 constexpr int kPt5Cache = 16;   // pT5 per seed
 
@@ -82,6 +84,7 @@ struct Ws {
   float4 *hpos;
   // mini-doublets
   int *md_cnt, *md_off;
+  int *md_cache;     // per module: up to kMdCache passing pairs (lower << 16 | upper) of the count pass
   int2 *md_hits;    // input indices of the lower and upper hit
   int *md_mod;
   float4 *md_pos;   // anchor (lower hit) x, y, z, r
