@@ -282,6 +282,42 @@ def main():
         return algorithmic_bytes(sites[dom], cc, int((ev.module >= 0).sum()), geom.n_modules,
                                  int(geom.map_targets.size), ev.n_seeds, int(c[7]))
 
+    # ---- served at saturation (the headline), measured first so that its pool is allocated like a
+    # server's at start-up: every request available at once; the dominant launch site of every
+    # batched launch sequence is bracketed by HIP events on its stream
+    n_streams, max_batch = args.streams, args.max_batch
+    pool_bytes = int(ws_one * (n_streams * max_batch + 2))
+    srv = lst.Server(g, n_streams, max_batch, pool_bytes)
+    n_warm = max(args.warmup, max_batch)
+    for i in range(n_warm):
+        srv.submit(pool[i % len(pool)], -1 - i, 0.0)
+    srv.drain(n_warm, lambda r: lst.lst_release_event(r["event"]))
+    lst.lst_set_timed_site(dom)
+    torch.cuda.synchronize()
+    served_lat, launches = [], {}
+
+    def take(r):
+        served_lat.append((r["done_s"] - r["arrival_s"]) * 1e3)
+        c, _ = lst.lst_get_stage_counts(r["event"])
+        ms = lst.lst_get_site_time(r["event"])
+        rec = launches.setdefault(r["admit_s"], [ms, 0.0])
+        b = event_bytes(host[r["id"] % len(host)], c)
+        rec[1] = None if (b is None or rec[1] is None) else rec[1] + b
+        lst.lst_release_event(r["event"])
+
+    t0 = time.perf_counter()
+    tnow = srv.now()
+    for i in range(args.steps):
+        srv.submit(pool[i % len(pool)], i, tnow)
+    srv.drain(args.steps, take)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    lst.lst_set_timed_site(-1)
+    srv.close()
+    value = args.steps / elapsed
+    log(f"bench: served {value:.1f} events/s ({n_streams} streams x {max_batch} per batch, "
+        f"{len(launches)} launch sequences)")
+
     # ---- plain: synchronous per event
     plain = None
     if "plain" in forms:
@@ -388,41 +424,6 @@ def main():
                "boundary": "pinned host hits+seeds -> H2D -> chain -> track candidates on the host"}
         del pinned
         log(f"bench: e2e {e2e}")
-
-    # ---- served at saturation (the headline): every request available at once; the dominant
-    # launch site of every batched launch sequence is bracketed by HIP events on its stream
-    n_streams, max_batch = args.streams, args.max_batch
-    pool_bytes = int(ws_one * (n_streams * max_batch + 2))
-    srv = lst.Server(g, n_streams, max_batch, pool_bytes)
-    n_warm = max(args.warmup, max_batch)
-    for i in range(n_warm):
-        srv.submit(pool[i % len(pool)], -1 - i, 0.0)
-    srv.drain(n_warm, lambda r: lst.lst_release_event(r["event"]))
-    lst.lst_set_timed_site(dom)
-    torch.cuda.synchronize()
-    served_lat, launches = [], {}
-
-    def take(r):
-        served_lat.append((r["done_s"] - r["arrival_s"]) * 1e3)
-        c, _ = lst.lst_get_stage_counts(r["event"])
-        ms = lst.lst_get_site_time(r["event"])
-        rec = launches.setdefault(r["admit_s"], [ms, 0.0])
-        b = event_bytes(host[r["id"] % len(host)], c)
-        rec[1] = None if (b is None or rec[1] is None) else rec[1] + b
-        lst.lst_release_event(r["event"])
-
-    t0 = time.perf_counter()
-    tnow = srv.now()
-    for i in range(args.steps):
-        srv.submit(pool[i % len(pool)], i, tnow)
-    srv.drain(args.steps, take)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    lst.lst_set_timed_site(-1)
-    srv.close()
-    value = args.steps / elapsed
-    log(f"bench: served {value:.1f} events/s ({n_streams} streams x {max_batch} per batch, "
-        f"{len(launches)} launch sequences)")
 
     # ---- open-loop trace: Poisson arrivals, pile-up U[50, 250], served vs plain FIFO on the same trace
     trace = None

@@ -484,8 +484,13 @@ constexpr int kMaxEdges = 128;  // module-map targets per module (checked when t
 // lanes stride over, so a wave stays full even though each linked module
 // holds few MDs; passing candidates are compacted in list order with ballot
 // and mbcnt.
+// Eight waves per SIMD (64 VGPRs; two spill): the segment search is bound by
+// the latency of its dependent gathers, and more resident waves hide more of
+// it (measured 9% faster than the 77-VGPR, six-wave build; the same for the
+// triplet and quintuplet searches made them slower).
 template <bool FILL>
-__global__ __launch_bounds__(kBlock) void k_ls(const Ws *__restrict__ wb, DevGeom g) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_ls(const Ws *__restrict__ wb,
+                                                                                        DevGeom g) {
   const Ws &w = wb[blockIdx.y];
   __shared__ int s_pre[kWaves][kMaxEdges + 1];  // running MD count before each edge
   __shared__ int s_first[kWaves][kMaxEdges];    // first MD of each linked module
