@@ -73,7 +73,8 @@ typedef struct {
   const int32_t *map_offsets, *map_targets;
 } lst_geometry_desc;
 
-/* One event, all arrays in DEVICE memory.
+/* One event, all arrays in DEVICE memory (n_hits and n_seeds at most
+ * 8,000,000 each; LST_E_INVALID beyond).
  *  x,y,z [n_hits] hit positions [cm]; module [n_hits] module id or -1 for a
  *  pixel hit; sensor [n_hits] 0 lower / 1 upper (ignored for pixel hits).
  *  Seeds (Section 2.4 pixel tracks; n_seeds may be 0 and the pointers NULL):

@@ -494,6 +494,8 @@ lst_status lst_workspace_bytes(lst_geometry g, int32_t n_hits, int32_t n_seeds, 
 
 static lst_status check_event_desc(const lst_event_desc &ev) {
   if (ev.n_hits < 0 || ev.n_seeds < 0) return fail(LST_E_INVALID, "negative n_hits or n_seeds");
+  if (ev.n_hits > kMaxCap || ev.n_seeds > kMaxCap)
+    return fail(LST_E_INVALID, "more than 8,000,000 hits or seeds in one event (the device scans' limit)");
   if (ev.n_hits > 0 && (!ev.x || !ev.y || !ev.z || !ev.module || !ev.sensor))
     return fail(LST_E_INVALID, "hit arrays missing");
   if (ev.n_seeds > 0 && (!ev.px || !ev.py || !ev.pz || !ev.q || !ev.hits4))

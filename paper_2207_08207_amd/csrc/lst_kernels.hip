@@ -20,7 +20,8 @@ constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / 64;
 constexpr int kScanItems = 8;                       // per thread
 constexpr int kScanTile = kBlock * kScanItems;      // per block
-constexpr int kMaxScanBlocks = 4096;                // second level handled by one block
+constexpr int kMaxScanBlocks = 4096;                // tile sums a scan keeps (scan_tmp): n < 8M
+static_assert((long)kMaxScanBlocks * kScanTile > 8000000L, "scan of the largest count of an event");
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 // Set bits of a ballot below this lane (its rank among the set lanes).
@@ -73,57 +74,20 @@ __global__ void k_scan_reduce(const Ws *__restrict__ wb, int job) {
   if (threadIdx.x == 0) w.scan_tmp[blockIdx.x] = v;
 }
 
-__global__ void k_scan_top(const Ws *__restrict__ wb, int job) {
-  // single block of 1024 threads: exclusive scan of up to kMaxScanBlocks block sums
-  __shared__ int s[kMaxScanBlocks];
-  __shared__ int s_w[16];
-  const Ws &w = wb[blockIdx.y];
-  const ScanJob &J = w.scans[job];
-  int *bsum = w.scan_tmp;
-  const int n = dev_count(J.n_dev, J.n_fix);
-  const int nb = n > 0 ? (n + kScanTile - 1) / kScanTile : 1;
-  for (int i = threadIdx.x; i < kMaxScanBlocks; i += blockDim.x) s[i] = (i < nb) ? bsum[i] : 0;
-  __syncthreads();
-  // each thread scans 4 consecutive entries
-  const int t = threadIdx.x;
-  int a0 = s[4 * t], a1 = s[4 * t + 1], a2 = s[4 * t + 2], a3 = s[4 * t + 3];
-  int sum = a0 + a1 + a2 + a3;
-  // inclusive scan of per-thread sums across the block
-  int x = sum;
-  for (int o = 1; o < 64; o <<= 1) {
-    const int y = __shfl_up(x, o, 64);
-    if (lane_id() >= o) x += y;
-  }
-  if (lane_id() == 63) s_w[t >> 6] = x;
-  __syncthreads();
-  int wbase = 0;
-  for (int q = 0; q < (t >> 6); ++q) wbase += s_w[q];
-  const int excl = wbase + x - sum;
-  __syncthreads();
-  s[4 * t] = excl;
-  s[4 * t + 1] = excl + a0;
-  s[4 * t + 2] = excl + a0 + a1;
-  s[4 * t + 3] = excl + a0 + a1 + a2;
-  __syncthreads();
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) bsum[i] = s[i];
-  if (threadIdx.x == blockDim.x - 1) {
-    const int tot = excl + sum;
-    if (J.tot_req) *J.tot_req = tot;
-    if (J.tot_clamped) {
-      *J.tot_clamped = tot < J.cap ? tot : J.cap;
-      if (tot > J.cap) atomicOr(w.ctr + C_STATUS, (int)ST_CAPACITY);
-    }
-  }
-}
-
+// Each block adds the tile sums of the blocks before it (at most a few hundred
+// for the chain's counts) to its own exclusive scan; the block holding index n
+// writes out[n] and the totals.  (Two launches per scan instead of a third,
+// single-block pass over the tile sums.)
 __global__ void k_scan_apply(const Ws *__restrict__ wb, int job) {
-  __shared__ int s_wave[kWaves];
+  __shared__ int s_wave[kWaves], s_red[kWaves];
   const Ws &w = wb[blockIdx.y];
   const ScanJob &J = w.scans[job];
   const int n = dev_count(J.n_dev, J.n_fix);
   const long base = (long)blockIdx.x * kScanTile;
   if (base > n) return;
-  int run = w.scan_tmp[blockIdx.x];
+  int pre = 0;
+  for (int j = threadIdx.x; j < (int)blockIdx.x; j += blockDim.x) pre += w.scan_tmp[j];
+  int run = block_sum(pre, s_red);
   // the block's tile in kScanItems rounds of kBlock consecutive items
   for (int k = 0; k < kScanItems; ++k) {
     const long i = base + (long)k * kBlock + threadIdx.x;
@@ -146,6 +110,14 @@ __global__ void k_scan_apply(const Ws *__restrict__ wb, int job) {
     if (i <= n) J.out[i] = run + wbs + x - v;  // out[n] = total
     __syncthreads();
     run += tot;
+  }
+  if (base + kScanTile > n && threadIdx.x == 0) {
+    const int tot = run;  // every item of the later tiles is past n
+    if (J.tot_req) *J.tot_req = tot;
+    if (J.tot_clamped) {
+      *J.tot_clamped = tot < J.cap ? tot : J.cap;
+      if (tot > J.cap) atomicOr(w.ctr + C_STATUS, (int)ST_CAPACITY);
+    }
   }
 }
 
@@ -171,7 +143,6 @@ static inline int grid_for(long n, int block = kBlock) {
 static void scan(const Ws *wb, int B, int job, long n_cap, hipStream_t st) {
   const int nb = (int)((n_cap + kScanTile) / kScanTile);  // tiles covering n_cap + 1 outputs
   k_scan_reduce<<<dim3(nb, B), kBlock, 0, st>>>(wb, job);
-  k_scan_top<<<dim3(1, B), 1024, 0, st>>>(wb, job);
   k_scan_apply<<<dim3(nb, B), kBlock, 0, st>>>(wb, job);
 }
 
