@@ -803,11 +803,13 @@ __global__ void k_t5_inc_count(const Ws *__restrict__ wb) {
 __global__ void k_t5_inc_scatter(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   const int n = w.ctr[C_NT5];
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
+    const int score = __float_as_int(w.t5_attr[8 * (long)t + 1]);
     for (int k = 0; k < 5; ++k) {
       const int md = w.t5_md[5 * (long)t + k];
-      w.inc_list[w.inc_off[md] + atomicAdd(&w.inc_cur[md], 1)] = t;
+      w.inc_list[w.inc_off[md] + atomicAdd(&w.inc_cur[md], 1)] = make_int2(t, score);
     }
+  }
 }
 
 __device__ __forceinline__ void t5_hits(const Ws &w, int t, int *h) {
@@ -872,11 +874,12 @@ __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) 
       if (c >= total) continue;
       while (s_seg[wv][e + 1] <= c) ++e;
       const int t = (int)((p0 + e) >> 2), k = (int)((p0 + e) & 3);
-      const int u = w.inc_list[s_lo[wv][e] + (c - s_seg[wv][e])];
+      const int2 ue = w.inc_list[s_lo[wv][e] + (c - s_seg[wv][e])];
+      const int u = ue.x;
       if (u == t) continue;
-      // only a u that is not worse can drop t: the score first, then sharing, then on a
-      // tie of scores the hit tuples (the decision of better<10>, with fewer loads)
-      const float su = w.t5_attr[8 * (long)u + 1], st = s_st[wv][e];
+      // only a u that is not worse can drop t: the score first (kept in the list entry),
+      // then sharing, then on a tie of scores the hit tuples (the decision of better<10>)
+      const float su = __int_as_float(ue.y), st = s_st[wv][e];
       if (st < su) continue;
       int mu[5];
 #pragma unroll

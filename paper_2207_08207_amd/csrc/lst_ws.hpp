@@ -108,7 +108,8 @@ struct Ws {
   float *t5_attr;   // 8 per T5
   int *t5_keep;
   float2 *t5_first;
-  int *inc_cnt, *inc_off, *inc_cur, *inc_list;  // T5s containing each MD
+  int *inc_cnt, *inc_off, *inc_cur;
+  int2 *inc_list;   // T5s containing each MD: (T5, bits of its chi2_xy score)
   // pixel seeds
   float *pls;       // 8 per seed: pT, cx, cy, lambda, kappa, x0, y0, z0
   int *pls_keep;
