@@ -280,6 +280,16 @@ def test_invalid_input_rejected(lst, gbarrel, barrel):
     bad2.x[1] = np.nan
     with pytest.raises(lst.LSTError):
         _run(lst, gbarrel, bad2)
+    # more hits than the device scans hold: rejected before any work is enqueued
+    import ctypes
+    import torch
+    d = lst._event_desc(lst.upload_event(ev))
+    d.n_hits = 8_000_001
+    h = ctypes.c_void_p()
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    st = lst.load_library().lst_build_event(gbarrel.handle, ctypes.byref(d), None, lst._ptr(ws), int(ws.numel()),
+                                            None, ctypes.byref(h))
+    assert st == lst.LST_E_INVALID and not h.value
 
 
 def test_capacity_overflow_reports_and_recovers(lst, gbarrel, obarrel):
