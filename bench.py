@@ -71,7 +71,7 @@ def parse():
     p.add_argument("--sweep", default="100,200,500,1000,2000",
                    help="offered rates of the served-vs-plain rate sweep [events/s] (empty: skip)")
     p.add_argument("--batch", type=int, default=64, help="slots of the captured batched plan (0: skip)")
-    p.add_argument("--forms", default="plain,ext,displaced,e2e,served,trace,batched,copy",
+    p.add_argument("--forms", default="plain,plain_graph,ext,displaced,e2e,served,trace,batched,copy",
                    help="comma list of forms to run (served is the headline and always runs)")
     p.add_argument("--site", default=None,
                    help="launch site to time for the roofline (default: the largest in a per-site calibration)")
@@ -210,7 +210,7 @@ def cpu_baseline(workload, events, n_workers):
 def main():
     args = parse()
     if args.gpus != 1:
-        log(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not supported "
+        log(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
             "(events are independent; multi-GPU sharding by event is described in DESIGN.md)")
         sys.exit(2)
     import numpy as np
@@ -365,6 +365,30 @@ def main():
                      "efficiency_vs_dxy": [(lo, hi, n, None if e is None else round(e, 4))
                                            for lo, hi, n, e in m["efficiency_vs_dxy"]]}
         log(f"bench: displaced {displaced}")
+
+    # ---- one event per replay of a captured one-slot plan (the chain as one HIP graph):
+    # per-event latency without the launch overhead of ~70 separate kernel launches
+    plain_graph = None
+    if "plain_graph" in forms:
+        plan1 = lst.Plan(g, 1, n_hits_max, n_seeds_max)
+        for i in range(args.warmup):
+            for r in plan1.run([pool[i % len(pool)]]):
+                r.close()
+        torch.cuda.synchronize()
+        n_pg = max(8, min(args.steps, 32))
+        lat = []
+        t0 = time.perf_counter()
+        for i in range(n_pg):
+            s0 = time.perf_counter()
+            for r in plan1.run([pool[(args.warmup + i) % len(pool)]]):
+                r.close()
+            lat.append((time.perf_counter() - s0) * 1e3)
+        torch.cuda.synchronize()
+        plain_graph = {"events_per_s": round(n_pg / (time.perf_counter() - t0), 3), "latency_ms": percentiles(lat),
+                       "events": n_pg, "form": "one event per replay of a captured one-slot plan"}
+        plan1.close()
+        del plan1
+        log(f"bench: plain graph {plain_graph}")
 
     # ---- plain with the track-extension step at the end of the chain
     ext = None
@@ -538,7 +562,7 @@ def main():
                    "form": f"served: {n_streams} streams x batches of {max_batch}, all requests available",
                    "step": "one event through the whole chain"},
         "latency_ms": percentiles(served_lat),
-        "launch_shapes": tuned, "plain": plain, "extensions": ext, "displaced": displaced, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
+        "launch_shapes": tuned, "plain": plain, "plain_graph": plain_graph, "extensions": ext, "displaced": displaced, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
         "roofline": roof,
     }
     if not args.no_physics:

@@ -156,7 +156,7 @@ def _chain_counts(geom, mds):
 
 @pytest.mark.parametrize("which,eta_max", [("barrel", 0.5), ("full", 2.4)])
 def test_single_track_closed_form(which, eta_max, barrel, full, obarrel, ofull):
-    """BJ spec: a noise-free single-track event yields exactly one quintuplet per track."""
+    """Closed form: a noise-free single-track event yields exactly one quintuplet per track."""
     geom, og = (barrel, obarrel) if which == "barrel" else (full, ofull)
     pt, eta, phi, z0, q = _closed_form_tracks(geom, eta_max, 48, 31 if which == "barrel" else 32)
     n_eligible = 0
