@@ -61,7 +61,8 @@ WORKLOAD = {
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=256, help="events in the timed served run")
+    p.add_argument("--steps", type=int, default=1024,
+                   help="events in the timed served run (256-event windows of one run vary by about 10%%)")
     p.add_argument("--warmup", type=int, default=8)
     p.add_argument("--pool", type=int, default=12, help="distinct events cycled through")
     p.add_argument("--streams", type=int, default=4, help="server streams")
