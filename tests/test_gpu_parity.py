@@ -403,3 +403,53 @@ def test_served_mix_equals_alone(lst, gfull):
         srv.drain(len(order), take)
         srv.close()
         assert [got[i] for i in range(len(order))] == [alone[k] for k in order]
+
+
+def test_server_with_extensions_and_displaced_bound(lst, full, gfull_ext, many_oracle):
+    """The serving loop on a geometry with the extension step, and on one with the displaced
+    bound: every result equal to the oracle's."""
+    specs = [s for s in MANY if s[0] == "pu200_seeded"][:4]
+    dev = [lst.upload_event(many_oracle[s][0]) for s in specs]
+    one = max(lst.lst_workspace_bytes(gfull_ext.handle, many_oracle[s][0].n_hits, many_oracle[s][0].n_seeds)
+              for s in specs)
+    srv = lst.Server(gfull_ext, 2, 2, 5 * one)
+    t0 = srv.now()
+    for i, d in enumerate(dev):
+        srv.submit(d, i, t0)
+    seen = set()
+
+    def take(r):
+        assert r["status"] == lst.LST_OK, r
+        res = lst.EventResult(r["event"], None, lst.LST_OK)
+        _compare_ext(res, many_oracle[specs[r["id"]]][1])
+        seen.add(r["id"])
+        res.close()
+
+    srv.drain(len(dev), take)
+    srv.close()
+    assert seen == set(range(len(dev)))
+
+    g = lst.Geometry(full)
+    g.set_impact_bound(3.6)
+    og = oracle.OracleGeometry(full, d0_max=3.6)
+    cube = [make_event("cube", k) for k in range(20, 26)]
+    cdev = [lst.upload_event(e) for e in cube]
+    one = max(lst.lst_workspace_bytes(g.handle, e.n_hits, e.n_seeds) for e in cube)
+    srv = lst.Server(g, 2, 3, 7 * one)
+    t0 = srv.now()
+    for i, d in enumerate(cdev):
+        srv.submit(d, i, t0)
+    got = {}
+
+    def take_c(r):
+        assert r["status"] == lst.LST_OK, r
+        res = lst.EventResult(r["event"], None, lst.LST_OK)
+        got[r["id"]] = res.track_candidates()
+        res.close()
+
+    srv.drain(len(cdev), take_c)
+    srv.close()
+    for i, e in enumerate(cube):
+        to, oo, ho = oracle.run(og, e).tc()
+        tg, og_, hg = got[i]
+        assert np.array_equal(tg, to) and np.array_equal(og_, oo) and np.array_equal(hg, ho)
