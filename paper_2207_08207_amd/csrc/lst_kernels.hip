@@ -1428,7 +1428,12 @@ __device__ __forceinline__ void obj_hits(const Ws &w, int t, int *h) {
 }
 
 // pT duplicate removal: dropped when another entry with the same seed or the
-// same outer object has a smaller (score, seed, hit tuple).
+// same outer object has a smaller (score, seed, hit tuple).  Entries of one
+// seed differ in their outer object, so of a seed's entries only the one
+// with the smallest (score, hit tuple) can survive; one wave per seed finds
+// it (a minimum over the seed's entries, the hit tuples compared only on an
+// exact tie of scores) and checks it alone against the entries sharing its
+// outer object, whose tuples differ from it in the seed only.
 template <int K>
 __global__ void k_pt_dedup(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
@@ -1440,38 +1445,52 @@ __global__ void k_pt_dedup(const Ws *__restrict__ wb) {
   const int *olst = K == 3 ? w.o3_list : w.o5_list;
   int *keep = K == 3 ? w.pt3_keep : w.pt5_keep;
   constexpr int H = 2 * K + 1;
-  // The decision of better<H> on (score, seed, object hits), with the hit
-  // tuples read only when two scores are equal.
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int2 me = so[i];
-    const float si = at[i].z;
-    bool kp = true, have_ti = false;
-    int ti[H];
-    const int j1 = min(soff[me.x + 1], n);
-    for (int j = soff[me.x]; j < j1 && kp; ++j) {  // same seed
-      if (j == i) continue;
-      const float sj = at[j].z;
-      if (sj < si) {
-        kp = false;
-      } else if (!(si < sj)) {
-        if (!have_ti) {
-          ti[0] = me.x;
-          obj_hits<K>(w, me.y, ti + 1);
-          have_ti = true;
-        }
+  const int lane = lane_id();
+  const int wpb = blockDim.x >> 6;
+  for (int s = blockIdx.x * wpb + (threadIdx.x >> 6); s < w.n_seeds; s += gridDim.x * wpb) {
+    const int j0 = min(soff[s], n), j1 = min(soff[s + 1], n);
+    if (j0 >= j1) continue;
+    // the smallest score of the seed's entries (scores of accepted entries are finite)
+    float best = 3.0e38f;
+    for (int j = j0 + lane; j < j1; j += 64) best = fminf(best, at[j].z);
+    for (int o = 32; o > 0; o >>= 1) best = fminf(best, __shfl_xor(best, o, 64));
+    // the entry of that score with the smallest hit tuple (every lane scans the ties in order)
+    int win = -1;
+    int tw[H];
+    for (int c0 = j0; c0 < j1; c0 += 64) {
+      const int j = c0 + lane;
+      const bool tie = j < j1 && !(best < at[j].z) && !(at[j].z < best);
+      unsigned long long m = __ballot(tie);
+      while (m) {
+        const int l = __builtin_ctzll(m);
+        m &= m - 1;
+        const int jt = c0 + l;
         int tj[H];
-        tj[0] = so[j].x;
-        obj_hits<K>(w, so[j].y, tj + 1);
-        if (better<H>(sj, tj, si, ti)) kp = false;
+        tj[0] = s;
+        obj_hits<K>(w, so[jt].y, tj + 1);
+        if (win < 0 || better<H>(best, tj, best, tw)) {
+          win = jt;
+#pragma unroll
+          for (int q = 0; q < H; ++q) tw[q] = tj[q];
+        }
       }
     }
-    for (int q = ooff[me.y]; q < ooff[me.y + 1] && kp; ++q) {  // same object: the tuples differ in the seed only
-      const int j = olst[q];
-      if (j == i) continue;
-      const float sj = at[j].z;
-      if (sj < si || (!(si < sj) && so[j].x < me.x)) kp = false;
+    if (win < 0) {  // no finite score (not produced by the selection): keep none
+      for (int j = j0 + lane; j < j1; j += 64) keep[j] = 0;
+      continue;
     }
-    keep[i] = kp ? 1 : 0;
+    // the winner against the entries of other seeds that share its outer object
+    bool kp = true;
+    const int ob = so[win].y;
+    const int q1 = ooff[ob + 1];
+    for (int q = ooff[ob] + lane; q < q1; q += 64) {
+      const int j = olst[q];
+      if (j == win) continue;
+      const float sj = at[j].z;
+      if (sj < best || (!(best < sj) && so[j].x < s)) kp = false;
+    }
+    kp = __ballot(!kp) == 0ull;
+    for (int j = j0 + lane; j < j1; j += 64) keep[j] = (j == win && kp) ? 1 : 0;
   }
 }
 
@@ -2065,8 +2084,8 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
     k_pt_obj_scatter<3><<<grid(b.cap_pt3), kBlock, 0, st>>>(wb);
     k_pt_obj_scatter<5><<<grid(b.cap_pt5), kBlock, 0, st>>>(wb);
   });
-  run([&] { if (seeds) k_pt_dedup<3><<<grid(b.cap_pt3), kBlock, 0, st>>>(wb); });
-  run([&] { if (seeds) k_pt_dedup<5><<<grid(b.cap_pt5), kBlock, 0, st>>>(wb); });
+  run([&] { if (seeds) k_pt_dedup<3><<<dim3(grid_waves(S), B), kBlock, 0, st>>>(wb); });
+  run([&] { if (seeds) k_pt_dedup<5><<<dim3(grid_waves(S), B), kBlock, 0, st>>>(wb); });
   // a8: cleaning and track candidates
   run([&] {
     const long n = (long)(S > b.cap_t5 ? S : b.cap_t5) + 1;
