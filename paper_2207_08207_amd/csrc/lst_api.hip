@@ -126,8 +126,8 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.pt3_cattr = F4(kPt3Cache * S); t.pt5_cattr = F4(kPt5Cache * S);
   t.pt3_so = I2(p3); t.pt5_so = I2(p5); t.pt3_attr = F4(p3); t.pt5_attr = F4(p5);
   t.pt3_keep = I(p3); t.pt5_keep = I(p5);
-  t.o3_cnt = I(t3 + 1); t.o3_off = I(t3 + 1); t.o3_cur = I(t3 + 1); t.o3_list = I(p3);
-  t.o5_cnt = I(t5 + 1); t.o5_off = I(t5 + 1); t.o5_cur = I(t5 + 1); t.o5_list = I(p5);
+  t.o3_best = reinterpret_cast<unsigned long long *>(take(8 * (size_t)(t3 + 1)));
+  t.o5_best = reinterpret_cast<unsigned long long *>(take(8 * (size_t)(t5 + 1)));
   const long nbins = kSeedBins;
   t.b3_cnt = I(nbins + 1); t.b3_off = I(nbins + 1); t.b3_cur = I(nbins + 1); t.b3_list = I(t3);
   t.b5_cnt = I(nbins + 1); t.b5_off = I(nbins + 1); t.b5_cur = I(nbins + 1); t.b5_list = I(t5);
@@ -167,8 +167,6 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
     sj(SC_PH, t.ph_cnt, t.ph_off, nullptr, N, N, ct + C_NPH, nullptr, 0);
     sj(SC_PT3, t.pt3_cnt, t.pt3_off, nullptr, S, S, ct + C_RPT3, ct + C_NPT3, p3);
     sj(SC_PT5, t.pt5_cnt, t.pt5_off, nullptr, S, S, ct + C_RPT5, ct + C_NPT5, p5);
-    sj(SC_O3, t.o3_cnt, t.o3_off, ct + C_NT3, 0, t3, ct + C_NO3, nullptr, 0);
-    sj(SC_O5, t.o5_cnt, t.o5_off, ct + C_NT5, 0, t5, ct + C_NO5, nullptr, 0);
     sj(SC_F5, t.f_pt5, t.p_pt5, ct + C_NPT5, 0, p5, ct + C_NTC0, nullptr, 0);
     sj(SC_F3, t.f_pt3, t.p_pt3, ct + C_NPT3, 0, p3, ct + C_NTC1, nullptr, 0);
     sj(SC_FT5, t.f_t5, t.p_t5, ct + C_NT5, 0, t5, ct + C_NTC2, nullptr, 0);
@@ -185,10 +183,8 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
     fj(FL_INC_CUR, t.inc_cur, md + 1);
     fj(FL_PH_CNT, t.ph_cnt, N + 1);
     fj(FL_PH_CUR, t.ph_cur, N + 1);
-    fj(FL_O3_CNT, t.o3_cnt, t3 + 1);
-    fj(FL_O3_CUR, t.o3_cur, t3 + 1);
-    fj(FL_O5_CNT, t.o5_cnt, t5 + 1);
-    fj(FL_O5_CUR, t.o5_cur, t5 + 1);
+    fj(FL_O3_BEST, reinterpret_cast<int *>(t.o3_best), 2 * (t3 + 1));
+    fj(FL_O5_BEST, reinterpret_cast<int *>(t.o5_best), 2 * (t5 + 1));
     fj(FL_SEED_USED, t.seed_used, S + 1);
     fj(FL_T5_USED, t.t5_used, t5 + 1);
     fj(FL_B3_CNT, t.b3_cnt, nbins + 1);

@@ -56,7 +56,8 @@ __global__ void k_clear(const Ws *__restrict__ wb, int j0, int j1) {
 
 // ------------------------------------------------------------------ scan
 // Exclusive scan of in[0..n) into out[0..n], out[n] = total; n = *n_dev (or
-// n_fix).  Three passes: block sums, scan of block sums, block scans.
+// n_fix).  Two passes: tile sums, then each tile's scan offset by the sum of
+// the tiles before it.
 __global__ void k_scan_reduce(const Ws *__restrict__ wb, int job) {
   __shared__ int s_red[kWaves];
   const Ws &w = wb[blockIdx.y];
@@ -1389,28 +1390,25 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   }
 }
 
+// The key that orders a pT entry for the same-object rule: smaller (score,
+// seed) is better, and since scores are >= 0 their bits order them as
+// integers; complemented so that the best is the largest, found with an
+// atomic maximum per outer object (a value, not a position: order-independent).
 template <int K>
-__global__ void k_pt_obj_count(const Ws *__restrict__ wb) {
+__device__ __forceinline__ unsigned long long pt_obj_key(const Ws &w, int i) {
+  const float4 *at = K == 3 ? w.pt3_attr : w.pt5_attr;
+  const int2 *so = K == 3 ? w.pt3_so : w.pt5_so;
+  return ~(((unsigned long long)__float_as_uint(at[i].z) << 32) | (unsigned long long)(unsigned)so[i].x);
+}
+template <int K>
+__global__ void k_pt_obj_best(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   const int n = K == 3 ? w.ctr[C_NPT3] : w.ctr[C_NPT5];
   const int2 *so = K == 3 ? w.pt3_so : w.pt5_so;
-  int *cnt = K == 3 ? w.o3_cnt : w.o5_cnt;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) atomicAdd(&cnt[so[i].y], 1);
+  unsigned long long *best = K == 3 ? w.o3_best : w.o5_best;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    atomicMax(&best[so[i].y], pt_obj_key<K>(w, i));
 }
-template <int K>
-__global__ void k_pt_obj_scatter(const Ws *__restrict__ wb) {
-  const Ws &w = wb[blockIdx.y];
-  const int n = K == 3 ? w.ctr[C_NPT3] : w.ctr[C_NPT5];
-  const int2 *so = K == 3 ? w.pt3_so : w.pt5_so;
-  const int *off = K == 3 ? w.o3_off : w.o5_off;
-  int *cur = K == 3 ? w.o3_cur : w.o5_cur;
-  int *lst = K == 3 ? w.o3_list : w.o5_list;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int t = so[i].y;
-    lst[off[t] + atomicAdd(&cur[t], 1)] = i;
-  }
-}
-
 template <int K>
 __device__ __forceinline__ void obj_hits(const Ws &w, int t, int *h) {
   if constexpr (K == 3) {
@@ -1433,7 +1431,8 @@ __device__ __forceinline__ void obj_hits(const Ws &w, int t, int *h) {
 // with the smallest (score, hit tuple) can survive; one wave per seed finds
 // it (a minimum over the seed's entries, the hit tuples compared only on an
 // exact tie of scores) and checks it alone against the entries sharing its
-// outer object, whose tuples differ from it in the seed only.
+// outer object, whose tuples differ from it in the seed only: it survives if
+// it has the object's smallest (score, seed) (k_pt_obj_best).
 template <int K>
 __global__ void k_pt_dedup(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
@@ -1441,8 +1440,7 @@ __global__ void k_pt_dedup(const Ws *__restrict__ wb) {
   const int2 *so = K == 3 ? w.pt3_so : w.pt5_so;
   const float4 *at = K == 3 ? w.pt3_attr : w.pt5_attr;
   const int *soff = K == 3 ? w.pt3_off : w.pt5_off;
-  const int *ooff = K == 3 ? w.o3_off : w.o5_off;
-  const int *olst = K == 3 ? w.o3_list : w.o5_list;
+  const unsigned long long *obest = K == 3 ? w.o3_best : w.o5_best;
   int *keep = K == 3 ? w.pt3_keep : w.pt5_keep;
   constexpr int H = 2 * K + 1;
   const int lane = lane_id();
@@ -1479,17 +1477,8 @@ __global__ void k_pt_dedup(const Ws *__restrict__ wb) {
       for (int j = j0 + lane; j < j1; j += 64) keep[j] = 0;
       continue;
     }
-    // the winner against the entries of other seeds that share its outer object
-    bool kp = true;
-    const int ob = so[win].y;
-    const int q1 = ooff[ob + 1];
-    for (int q = ooff[ob] + lane; q < q1; q += 64) {
-      const int j = olst[q];
-      if (j == win) continue;
-      const float sj = at[j].z;
-      if (sj < best || (!(best < sj) && so[j].x < s)) kp = false;
-    }
-    kp = __ballot(!kp) == 0ull;
+    // the winner survives the same-object rule if it is its object's best (score, seed)
+    const bool kp = obest[so[win].y] == pt_obj_key<K>(w, win);
     for (int j = j0 + lane; j < j1; j += 64) keep[j] = (j == win && kp) ? 1 : 0;
   }
 }
@@ -1955,7 +1944,7 @@ const char *const kSiteNames[] = {
     "t5_inc_count", "t5_inc_scan", "t5_inc_scatter", "t5_dedup",
     "pls", "pls_hit_scan", "pls_hit_scatter", "pls_dedup",
     "pt3_bin", "pt5_bin", "pt_count", "pt3_scan", "pt3_fill", "pt5_scan", "pt5_fill",
-    "pt_obj_count", "pt_obj_scan", "pt_obj_scatter", "pt3_dedup", "pt5_dedup",
+    "pt_obj_best", "pt3_dedup", "pt5_dedup",
     "tc_pt5", "tc_pt5_scan", "tc_pt5_dirs", "tc_pt3", "tc_pt3_scan", "tc_pt3_dirs",
     "tc_t5", "tc_t5_scan", "tc_t5_dirs", "tc_pls", "tc_pls_scan", "tc_write",
     "tc_ext", "tc_ext_scan", "tc_ext_write"};
@@ -2069,20 +2058,10 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { if (seeds) k_pt_binned<5, true><<<seedwaves(), tb, 0, st>>>(wb, g); });
   run([&] {
     if (!seeds) return;
-    const long n = (long)(b.cap_t3 > b.cap_t5 ? b.cap_t3 : b.cap_t5) + 1;
-    k_clear<<<grid(n), kBlock, 0, st>>>(wb, FL_O3_CNT, FL_O5_CUR + 1);
-    k_pt_obj_count<3><<<grid(b.cap_pt3), kBlock, 0, st>>>(wb);
-    k_pt_obj_count<5><<<grid(b.cap_pt5), kBlock, 0, st>>>(wb);
-  });
-  run([&] {
-    if (!seeds) return;
-    scan(wb, B, SC_O3, b.cap_t3, st);
-    scan(wb, B, SC_O5, b.cap_t5, st);
-  });
-  run([&] {
-    if (!seeds) return;
-    k_pt_obj_scatter<3><<<grid(b.cap_pt3), kBlock, 0, st>>>(wb);
-    k_pt_obj_scatter<5><<<grid(b.cap_pt5), kBlock, 0, st>>>(wb);
+    const long n = 2L * ((b.cap_t3 > b.cap_t5 ? b.cap_t3 : b.cap_t5) + 1);
+    k_clear<<<grid(n), kBlock, 0, st>>>(wb, FL_O3_BEST, FL_O5_BEST + 1);
+    k_pt_obj_best<3><<<grid(b.cap_pt3), kBlock, 0, st>>>(wb);
+    k_pt_obj_best<5><<<grid(b.cap_pt5), kBlock, 0, st>>>(wb);
   });
   run([&] { if (seeds) k_pt_dedup<3><<<dim3(grid_waves(S), B), kBlock, 0, st>>>(wb); });
   run([&] { if (seeds) k_pt_dedup<5><<<dim3(grid_waves(S), B), kBlock, 0, st>>>(wb); });

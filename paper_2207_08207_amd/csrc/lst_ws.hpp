@@ -42,7 +42,7 @@ struct ScanJob {
   int cap;
 };
 enum ScanId : int {
-  SC_HITS, SC_MD, SC_LS, SC_T3, SC_T5, SC_INC, SC_PH, SC_PT3, SC_PT5, SC_O3, SC_O5,
+  SC_HITS, SC_MD, SC_LS, SC_T3, SC_T5, SC_INC, SC_PH, SC_PT3, SC_PT5,
   SC_F5, SC_F3, SC_FT5, SC_FPLS, SC_B3, SC_B5, SC_LSOVF, SC_EXT, SC_COUNT
 };
 // One array cleared to zero at the start of the chain.
@@ -51,8 +51,8 @@ struct FillJob {
   long n;
 };
 enum FillId : int {
-  FL_CTR, FL_BCNT, FL_BCUR, FL_INC_CNT, FL_INC_CUR, FL_PH_CNT, FL_PH_CUR, FL_O3_CNT, FL_O3_CUR,
-  FL_O5_CNT, FL_O5_CUR, FL_SEED_USED, FL_T5_USED, FL_B3_CNT, FL_B3_CUR, FL_B5_CNT, FL_B5_CUR, FL_COUNT
+  FL_CTR, FL_BCNT, FL_BCUR, FL_INC_CNT, FL_INC_CUR, FL_PH_CNT, FL_PH_CUR, FL_O3_BEST,
+  FL_O5_BEST, FL_SEED_USED, FL_T5_USED, FL_B3_CNT, FL_B3_CUR, FL_B5_CNT, FL_B5_CUR, FL_COUNT
 };
 
 // Passing partners remembered between a stage's count and fill passes: per
@@ -121,8 +121,9 @@ struct Ws {
   int2 *pt3_so, *pt5_so;      // seed, object
   float4 *pt3_attr, *pt5_attr;
   int *pt3_keep, *pt5_keep;
-  int *o3_cnt, *o3_off, *o3_cur, *o3_list;      // pT3 entries per T3
-  int *o5_cnt, *o5_off, *o5_cur, *o5_list;      // pT5 entries per T5
+  // per T3 / T5: the largest ~(score bits << 32 | seed) of the pT3 / pT5 entries on it,
+  // i.e. its entry with the smallest (score, seed) (scores are >= 0, so their bits order them)
+  unsigned long long *o3_best, *o5_best;
   int *b3_cnt, *b3_off, *b3_cur, *b3_list;      // T3s by first-anchor (ring, azimuth, z) bin
   int *b5_cnt, *b5_off, *b5_cur, *b5_list;      // surviving T5s by the same bins
   float4 *b3_pos, *b5_pos;  // per list entry: the object's first anchor x, y, z and module info bits
