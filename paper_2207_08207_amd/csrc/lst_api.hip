@@ -116,6 +116,7 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.ls_cache = I(kLsCache * md);
   t.ls_ovf_flag = I(md + 1); t.ls_ovf_off = I(md + 1); t.ls_ovf = I(md);
   t.t3_cnt = I(ls + 1); t.t3_off = I(ls + 1); t.t3_md = I4(t3); t.t3_attr = F4(t3); t.t3_first = F2(t3);
+  t.t3_cache = I(kT3Cache * ls); t.t5_cache = I(kT5Cache * t3);
   t.t5_cnt = I(t3 + 1); t.t5_off = I(t3 + 1); t.t5_t3 = I2(t5); t.t5_md = I(5 * t5); t.t5_attr = F(8 * t5);
   t.t5_keep = I(t5); t.t5_first = F2(t5);
   t.inc_cnt = I(md + 1); t.inc_off = I(md + 1); t.inc_cur = I(md + 1); t.inc_list = I2(5 * t5);

@@ -657,14 +657,15 @@ template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
   __shared__ float4 s_a[kWaves][64], s_b[kWaves][64];
-  __shared__ int s_mi[kWaves][64], s_lo[kWaves][64], s_cnt[kWaves][64], s_seg[kWaves][65];
+  __shared__ int s_mi[kWaves][64], s_lo[kWaves][64], s_cnt[kWaves][64], s_seg[kWaves][65], s_cached[kWaves][64];
   const int n_ls = w.ctr[C_NLS];
   const int wv = threadIdx.x >> 6, lane = lane_id();
   const int wpb = blockDim.x >> 6;
   for (long p0 = ((long)blockIdx.x * wpb + wv) * 64; p0 < n_ls; p0 += (long)gridDim.x * wpb * 64) {
     const int l1 = (int)p0 + lane;
-    int n = 0;
-    if (l1 < n_ls) {
+    int n = 0, cached = 0;
+    // the fill reads a parent's data only if the count pass found a triplet on it
+    if (l1 < n_ls && (!FILL || w.t3_cnt[l1] > 0)) {
       const int2 ab = w.ls_md[l1];
       s_a[wv][lane] = w.md_pos[ab.x];
       s_b[wv][lane] = w.md_pos[ab.y];
@@ -672,26 +673,39 @@ __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeo
       const int lo = w.ls_off[ab.y], hi = min(w.ls_off[ab.y + 1], n_ls);
       s_lo[wv][lane] = lo;
       n = hi > lo ? hi - lo : 0;
-      if (FILL && w.t3_cnt[l1] == 0) n = 0;  // nothing to write for this parent
+      if (FILL) {
+        const int cnt = w.t3_cnt[l1];
+        if (cnt <= kT3Cache) {  // the count pass kept them all: only those are tested again
+          n = cnt;
+          cached = 1;
+        }
+      }
     }
     s_cnt[wv][lane] = 0;
+    s_cached[wv][lane] = cached;
     const int total = wave_segments(n, s_seg[wv]);
     int e = 0;  // parent of this lane's pair (pairs advance monotonically)
     for (int c0 = 0; c0 < total; c0 += 64) {
       const int c = c0 + lane;
       bool pass = false;
-      int cmd = 0, first = 0, before = 0;
+      int cmd = 0, cand = 0, first = 0, before = 0;
       float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
       if (c < total) {
         while (s_seg[wv][e + 1] <= c) ++e;
         first = max(s_seg[wv][e] - c0, 0);
         before = s_cnt[wv][e];
-        cmd = w.ls_md[s_lo[wv][e] + (c - s_seg[wv][e])].y;
+        const int idx = c - s_seg[wv][e];
+        cand = s_cached[wv][e] ? w.t3_cache[(long)((int)p0 + e) * kT3Cache + idx] : s_lo[wv][e] + idx;
+        cmd = w.ls_md[cand].y;
         const int mi = s_mi[wv][e];
         pass = t3_pass(s_a[wv][e], s_b[wv][e], w.md_pos[cmd], ModInfo{mi & 0xff}, ModInfo{mi >> 8},
                        ModInfo{g.info[w.md_mod[cmd]]}, &attr, g.d0max);
       }
       const unsigned long long m = __ballot(pass);
+      if (!FILL && pass) {
+        const int r = pair_rank(m, first, before);
+        if (r < kT3Cache) w.t3_cache[(long)((int)p0 + e) * kT3Cache + r] = cand;
+      }
       if (FILL && pass) {
         const int pos = w.t3_off[(int)p0 + e] + pair_rank(m, first, before);
         if (pos < w.cap_t3) {
@@ -719,15 +733,16 @@ template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
   __shared__ float4 s_p[kWaves][3][64], s_tin[kWaves][64];
-  __shared__ int s_mi[kWaves][64], s_lo[kWaves][64], s_cnt[kWaves][64], s_seg[kWaves][65];
+  __shared__ int s_mi[kWaves][64], s_lo[kWaves][64], s_cnt[kWaves][64], s_seg[kWaves][65], s_cached[kWaves][64];
   const int n_t3 = w.ctr[C_NT3];
   const int n_ls = w.ctr[C_NLS];
   const int wv = threadIdx.x >> 6, lane = lane_id();
   const int wpb = blockDim.x >> 6;
   for (long p0 = ((long)blockIdx.x * wpb + wv) * 64; p0 < n_t3; p0 += (long)gridDim.x * wpb * 64) {
     const int t1 = (int)p0 + lane;
-    int n = 0;
-    if (t1 < n_t3) {
+    int n = 0, cached = 0;
+    // the fill reads a parent's data only if the count pass found a quintuplet on it
+    if (t1 < n_t3 && (!FILL || w.t5_cnt[t1] > 0)) {
       const int4 abc = w.t3_md[t1];
       s_p[wv][0][lane] = w.md_pos[abc.x];
       s_p[wv][1][lane] = w.md_pos[abc.y];
@@ -739,9 +754,16 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
       const int lo = w.t3_off[lsb], hi = min(w.t3_off[lse], n_t3);
       s_lo[wv][lane] = lo;
       n = hi > lo ? hi - lo : 0;
-      if (FILL && w.t5_cnt[t1] == 0) n = 0;
+      if (FILL) {
+        const int cnt = w.t5_cnt[t1];
+        if (cnt <= kT5Cache) {  // the count pass kept them all: only those are tested again
+          n = cnt;
+          cached = 1;
+        }
+      }
     }
     s_cnt[wv][lane] = 0;
+    s_cached[wv][lane] = cached;
     const int total = wave_segments(n, s_seg[wv]);
     int e = 0;
     for (int c0 = 0; c0 < total; c0 += 64) {
@@ -754,7 +776,8 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
         while (s_seg[wv][e + 1] <= c) ++e;
         first = max(s_seg[wv][e] - c0, 0);
         before = s_cnt[wv][e];
-        t2 = s_lo[wv][e] + (c - s_seg[wv][e]);
+        const int idx = c - s_seg[wv][e];
+        t2 = s_cached[wv][e] ? w.t5_cache[(long)((int)p0 + e) * kT5Cache + idx] : s_lo[wv][e] + idx;
         cde = w.t3_md[t2];
         float4 P[5];
         ModInfo M[5];
@@ -768,6 +791,10 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
         pass = t5_pass(P, M, s_tin[wv][e], w.t3_attr[t2], at, g.d0max);
       }
       const unsigned long long m = __ballot(pass);
+      if (!FILL && pass) {
+        const int r = pair_rank(m, first, before);
+        if (r < kT5Cache) w.t5_cache[(long)((int)p0 + e) * kT5Cache + r] = t2;
+      }
       if (FILL && pass) {
         const int t1e = (int)p0 + e;
         const int pos = w.t5_off[t1e] + pair_rank(m, first, before);

@@ -60,6 +60,8 @@ enum FillId : int {
 // than this: the fill searches again).
 constexpr int kLsCache = 16;
 constexpr int kMdCache = 32;  // MDs per module whose (lower, upper) pair the MD count pass keeps
+constexpr int kT3Cache = 2;   // triplets per parent segment whose candidate the T3 count pass keeps
+constexpr int kT5Cache = 2;   // quintuplets per parent triplet whose candidate the T5 count pass keeps
 constexpr int kPt3Cache = 256;  // pT3 per seed (PU200 maximum ~190)
 constexpr int kPt5Cache = 16;   // pT5 per seed
 
@@ -101,6 +103,7 @@ struct Ws {
   int4 *t3_md;      // a, b, c, -
   float4 *t3_attr;  // kappa, dkappa, chi2_rz, lambda
   float2 *t3_first; // anchor x, y of the first MD
+  int *t3_cache;    // per segment: up to kT3Cache passing candidate segments of the count pass
   // quintuplets
   int *t5_cnt, *t5_off;
   int2 *t5_t3;
@@ -108,6 +111,7 @@ struct Ws {
   float *t5_attr;   // 8 per T5
   int *t5_keep;
   float2 *t5_first;
+  int *t5_cache;    // per triplet: up to kT5Cache passing candidate triplets of the count pass
   int *inc_cnt, *inc_off, *inc_cur;
   int2 *inc_list;   // T5s containing each MD: (T5, bits of its chi2_xy score)
   // pixel seeds
