@@ -72,7 +72,7 @@ def parse():
     p.add_argument("--sweep", default="100,200,500,1000,2000",
                    help="offered rates of the served-vs-plain rate sweep [events/s] (empty: skip)")
     p.add_argument("--batch", type=int, default=64, help="slots of the captured batched plan (0: skip)")
-    p.add_argument("--forms", default="plain,plain_graph,ext,displaced,e2e,served,trace,batched,copy",
+    p.add_argument("--forms", default="plain,plain_graph,stub16,ext,displaced,e2e,served,trace,batched,copy",
                    help="comma list of forms to run (served is the headline and always runs)")
     p.add_argument("--site", default=None,
                    help="launch site to time for the roofline (default: the largest in a per-site calibration)")
@@ -391,6 +391,32 @@ def main():
         del plan1
         log(f"bench: plain graph {plain_graph}")
 
+    # ---- plain with the MD stubs stored in binary16 (the half-precision storage variant)
+    stub16 = None
+    if "stub16" in forms:
+        g_h = lst.Geometry(geom)
+        if tuned:
+            g_h.set_launch_config(tuned)
+        g_h.set_stub_precision(16)
+        for i in range(args.warmup):
+            step(i, gh=g_h.handle)
+        torch.cuda.synchronize()
+        n_h = max(8, min(args.steps, 32))
+        lat = []
+        t0 = time.perf_counter()
+        for i in range(n_h):
+            s0 = time.perf_counter()
+            step(args.warmup + i, gh=g_h.handle)
+            lat.append((time.perf_counter() - s0) * 1e3)
+        torch.cuda.synchronize()
+        stub16 = {"events_per_s": round(n_h / (time.perf_counter() - t0), 3), "latency_ms": percentiles(lat),
+                  "events": n_h}
+        k = sites.index("ls_count")
+        lst.lst_set_timed_site(k)
+        stub16["ls_count_ms"] = round(sum(step(i, k, gh=g_h.handle)[1] for i in range(4)) / 4, 4)
+        lst.lst_set_timed_site(-1)
+        log(f"bench: plain with binary16 MD stubs {stub16}")
+
     # ---- plain with the track-extension step at the end of the chain
     ext = None
     if "ext" in forms:
@@ -563,7 +589,7 @@ def main():
                    "form": f"served: {n_streams} streams x batches of {max_batch}, all requests available",
                    "step": "one event through the whole chain"},
         "latency_ms": percentiles(served_lat),
-        "launch_shapes": tuned, "plain": plain, "plain_graph": plain_graph, "extensions": ext, "displaced": displaced, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
+        "launch_shapes": tuned, "plain": plain, "plain_graph": plain_graph, "stub16": stub16, "extensions": ext, "displaced": displaced, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
         "roofline": roof,
     }
     if not args.no_physics:

@@ -212,6 +212,16 @@ lst_status lst_server_destroy(lst_server srv);
 lst_status lst_get_track_candidates(lst_event ev, int32_t *n_tc, int32_t *n_hits_total, int32_t *type,
                                     int32_t *offsets, int32_t *hits);
 
+/* Storage precision of the MD stubs (the tangential displacement and the
+ * sensor separation of each mini-doublet, which the segment selection checks
+ * against the chord's direction): 32 (float, the default) or 16 (IEEE
+ * binary16, rounded to nearest even, read back as float) -- the
+ * half-precision types Section 5 names as future work, for the quantity
+ * whose precision the selection needs least.  Applies to chains enqueued
+ * afterwards (plans created afterwards).  Errors: LST_E_INVALID for a NULL
+ * geometry or bits other than 16 / 32. */
+lst_status lst_set_stub_precision(lst_geometry geom, int32_t bits);
+
 /* Transverse impact-parameter bound d0_max [cm] that every selection allows
  * for (MD windows, segment azimuth window and stub directions, the
  * azimuth-z pointing of triplets, quintuplets and extensions).  0.1 cm from

@@ -62,6 +62,9 @@ def _lib(f64=False):
         lib.orc_free.argtypes = [vp]
         lib.orc_geom_free.argtypes = [vp]
         lib.orc_geom_set_d0max.argtypes = [vp, ctypes.c_double]
+        lib.orc_geom_set_stub16.argtypes = [vp, ctypes.c_int]
+        lib.orc_round_half.argtypes = [ctypes.c_double]
+        lib.orc_round_half.restype = ctypes.c_double
         lib.orc_module_consts.argtypes = [vp, vp]
         lib.orc_module_consts_f64.argtypes = [vp, vp]
         _LIBS[f64] = lib
@@ -75,8 +78,9 @@ def _p(a):
 class OracleGeometry:
     """The oracle's copy of a detector (module table + module map)."""
 
-    def __init__(self, geom, f64=False, d0_max=None):
-        """d0_max: transverse impact-parameter bound of the selections [cm] (default 0.1)."""
+    def __init__(self, geom, f64=False, d0_max=None, stub16=False):
+        """d0_max: transverse impact-parameter bound of the selections [cm] (default 0.1);
+        stub16: MD stubs kept in binary16."""
         self.f64 = f64
         self.lib = _lib(f64)
         m = geom.module_arrays()
@@ -90,6 +94,8 @@ class OracleGeometry:
                                                _p(off), _p(tgt))
         if d0_max is not None:
             self.lib.orc_geom_set_d0max(ctypes.c_void_p(self.handle), ctypes.c_double(float(d0_max)))
+        if stub16:
+            self.lib.orc_geom_set_stub16(ctypes.c_void_p(self.handle), 1)
 
     def module_consts(self, as_f64=False):
         """(n_modules, 4) array of W, A1, A2, A3 (rounded to the oracle's precision unless as_f64)."""

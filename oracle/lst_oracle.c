@@ -96,6 +96,7 @@ typedef struct {
   real *W, *A1, *A2, *A3;      /* per-module MD window constants */
   double *Wd, *A1d, *A2d, *A3d;
   double d0max;                 /* transverse impact-parameter bound of the selections [cm] */
+  int stub16;                   /* MD stubs kept in binary16 (1) or in the working precision (0) */
 } orc_geom;
 
 /* asin(x) for |x| <= 0.85 from its Maclaurin series, summed in a fixed order
@@ -153,6 +154,29 @@ static void module_constants(int sd, int ty, double p_lo, double p_up, double l_
   }
   out[0] = W; out[1] = A1; out[2] = A2; out[3] = A3;
 }
+
+/* Nearest IEEE binary16 value of v, ties to even (subnormals kept,
+ * overflow to infinity), returned in double: v = f * q with the quantum q
+ * of v's binade (2^-24 below 2^-14), f rounded to an integer, ties to even. */
+static double round_half(double v) {
+  if (!(v == v)) return v;
+  double a = fabs(v);
+  if (a >= 65520.0) return copysign(INFINITY, v);
+  int e;
+  frexp(a, &e);
+  int ex = e - 1;
+  if (ex < -14) ex = -14;
+  double q = ldexp(1.0, ex - 10);
+  double r = a / q, f = floor(r), d = r - f;
+  if (d > 0.5 || (d == 0.5 && fmod(f, 2.0) != 0.0)) f += 1.0;
+  return copysign(f * q, v);
+}
+double orc_round_half(double v) { return round_half(v); }
+
+/* Keeps the MD stubs (tangential displacement and sensor separation, the two
+ * quantities of the segment stub check) in binary16: the half-precision
+ * storage the paper names as future work, as a checked variant. */
+void orc_geom_set_stub16(void *gp, int on) { ((orc_geom *)gp)->stub16 = on ? 1 : 0; }
 
 /* Sets the transverse impact-parameter bound every selection assumes
  * (Section 3's displaced tracks: the same chain with a wider bound) and
@@ -387,9 +411,11 @@ static int ls_select(const orc_geom *g, orc_event *e, int a_md, int b_md, real *
     real sb = side ? sb_in : sb_out, rp = side ? rb : ra;
     int i = e->md_lo.p[md], j = e->md_up.p[md];
     real tau = (e->x[i] * e->y[j] - e->y[i] * e->x[j]) / e->r[i];
+    if (g->stub16) tau = (real)round_half((double)tau);
     real pred, err;
     if (!endcap_of(g, m)) {
       real dl = e->r[j] - e->r[i];
+      if (g->stub16) dl = (real)round_half((double)dl);
       real cs2 = RL(1) - sb * sb;
       if (!(cs2 > RL(0))) { ac->firm_fail = 1; return 0; }
       pred = (dl * sb) / RSQRT_(cs2);
@@ -397,6 +423,7 @@ static int ls_select(const orc_geom *g, orc_event *e, int a_md, int b_md, real *
     } else {
       if (!(dzab > RL(0))) { ac->firm_fail = 1; return 0; }
       real dl = RABS(e->z[j]) - RABS(e->z[i]);
+      if (g->stub16) dl = (real)round_half((double)dl);
       real ds = (dl * Ls) / dzab;
       pred = ds * sb;
       err = (RL(2) * hphi_of(g, m) + (real)0.03 * RABS(pred)) + ds * (eang + (real)g->d0max / rp);

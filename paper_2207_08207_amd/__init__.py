@@ -30,7 +30,8 @@ EXPORTED = ["lst_load_geometry", "lst_release_geometry", "lst_default_capacity",
             "lst_enqueue_batch", "lst_plan_workspace_bytes", "lst_plan_create", "lst_plan_run", "lst_plan_release",
             "lst_server_create", "lst_server_now", "lst_server_submit", "lst_server_poll", "lst_server_pending",
             "lst_server_destroy", "lst_get_launch_config", "lst_set_launch_config", "lst_autotune",
-            "lst_set_track_extensions", "lst_get_extended_track_candidates", "lst_set_impact_bound"]
+            "lst_set_track_extensions", "lst_get_extended_track_candidates", "lst_set_impact_bound",
+            "lst_set_stub_precision"]
 
 
 class LSTError(RuntimeError):
@@ -96,6 +97,7 @@ def load_library(path=LIB_PATH):
         "lst_get_track_candidates": [vp, P(i32), P(i32), vp, vp, vp],
         "lst_set_track_extensions": [vp, i32],
         "lst_set_impact_bound": [vp, ctypes.c_double],
+        "lst_set_stub_precision": [vp, i32],
         "lst_get_extended_track_candidates": [vp, P(i32), P(i32), vp, vp, vp, vp, vp, vp],
         "lst_get_stage_objects": [vp, i32, P(i32), vp, vp, vp],
         "lst_get_stage_counts": [vp, vp, vp],
@@ -222,6 +224,10 @@ def lst_get_track_candidates(ev):
     hits = np.zeros(nh.value, np.int32)
     _check(lib.lst_get_track_candidates(ev, ctypes.byref(n), ctypes.byref(nh), _ptr(ty), _ptr(off), _ptr(hits)))
     return ty, off, hits
+
+
+def lst_set_stub_precision(geom, bits):
+    _check(load_library().lst_set_stub_precision(geom, int(bits)))
 
 
 def lst_set_impact_bound(geom, d0_max):
@@ -428,6 +434,10 @@ class Geometry:
 
     def module_constants(self):
         return lst_get_module_constants(self.handle, self.n_modules)
+
+    def set_stub_precision(self, bits):
+        """MD stubs stored in binary16 (16) or float (32, the default) by chains enqueued from now on."""
+        lst_set_stub_precision(self.handle, bits)
 
     def set_impact_bound(self, d0_max):
         """Transverse impact-parameter bound of the selections [cm] (0.1 unless set)."""

@@ -297,7 +297,14 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   g->g.info = g->d_info;
   g->g.ext = 0;
   g->g.d0max = (float)kD0MaxDefault;
+  g->g.stub16 = 0;
   *out = g;
+  return LST_OK;
+}
+
+lst_status lst_set_stub_precision(lst_geometry g, int32_t bits) {
+  if (!g || (bits != 16 && bits != 32)) return fail(LST_E_INVALID, "lst_set_stub_precision: bits must be 16 or 32");
+  g->g.stub16 = bits == 16 ? 1 : 0;
   return LST_OK;
 }
 

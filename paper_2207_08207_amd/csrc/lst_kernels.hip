@@ -8,6 +8,8 @@
 // incidence lists, whose consumers are order-independent.  Object counts
 // stay on the device: later kernels read them and stride over them, so the
 // whole chain is enqueued without a host round trip.
+#include <hip/hip_fp16.h>
+
 #include <cstring>
 #include <type_traits>
 
@@ -233,6 +235,19 @@ __global__ void k_bucket_sort(const Ws *__restrict__ wb, int n_buckets) {
 
 // ------------------------------------------------------------- a1: MD
 constexpr int kMdStage = 128;  // hits per sensor staged in LDS per wave (more: read from HBM)
+// MD stubs are stored as float2 or, with the geometry's 16-bit stub switch, as
+// a dense array of binary16 pairs (rounded to nearest even) read back as float.
+__device__ __forceinline__ void put_stub(const Ws &w, const DevGeom &g, int pos, float2 st) {
+  if (g.stub16)
+    reinterpret_cast<__half2 *>(w.md_stub)[pos] = __floats2half2_rn(st.x, st.y);
+  else
+    w.md_stub[pos] = st;
+}
+__device__ __forceinline__ float2 get_stub(const Ws &w, const DevGeom &g, int i) {
+  if (g.stub16) return __half22float2(reinterpret_cast<const __half2 *>(w.md_stub)[i]);
+  return w.md_stub[i];
+}
+
 constexpr long kMdBig = 2048;  // modules with more pairs go to a whole block (k_md_big)
 constexpr int kMdStageBig = 512;
 
@@ -285,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
           w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
           w.md_mod[pos] = m;
           w.md_pos[pos] = hi;
-          w.md_stub[pos] = md_stub(hi, hj, mi);
+          put_stub(w, g, pos, md_stub(hi, hj, mi));
         }
       }
     }
@@ -308,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
           w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
           w.md_mod[pos] = m;
           w.md_pos[pos] = hi;
-          w.md_stub[pos] = md_stub(hi, hj, mi);
+          put_stub(w, g, pos, md_stub(hi, hj, mi));
         }
       }
       if (!FILL && pass) {
@@ -388,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
           w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
           w.md_mod[pos] = m;
           w.md_pos[pos] = hi;
-          w.md_stub[pos] = md_stub(hi, hj, mi);
+          put_stub(w, g, pos, md_stub(hi, hj, mi));
         }
       }
       base += tot;
@@ -478,7 +493,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
   auto process = [&](const int a) {
     const int ma = w.md_mod[a];
     const float4 A = w.md_pos[a];
-    const float2 sa = w.md_stub[a];
+    const float2 sa = get_stub(w, g, a);
     const ModInfo mia{g.info[ma]};
     const int e0 = g.map_off[ma];
     const int ne = g.map_off[ma + 1] - e0;  // <= kMaxEdges, checked when the geometry is loaded
@@ -526,7 +541,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       float2 beta = make_float2(0.f, 0.f);
       if (lane < n) {
         b = s_q[wv][lane];
-        pass = ls_pass(A, w.md_pos[b], sa, w.md_stub[b], mia, ModInfo{s_qi[wv][lane]}, &beta, g.d0max);
+        pass = ls_pass(A, w.md_pos[b], sa, get_stub(w, g, b), mia, ModInfo{s_qi[wv][lane]}, &beta, g.d0max);
       }
       const unsigned long long m = __ballot(pass);
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));

@@ -28,6 +28,7 @@ struct DevGeom {
   const int *info;    // per module: bit 0 = 2S, bit 1 = endcap
   int ext;            // 1: the chain ends with the track extensions
   float d0max;        // transverse impact-parameter bound of the selections [cm]
+  int stub16;         // 1: MD stubs stored as binary16 pairs (dense half2), else float2
 };
 
 // One exclusive scan of the chain: out[0..n] = scan of in[0..n), n = *n_dev
@@ -90,7 +91,7 @@ struct Ws {
   int2 *md_hits;    // input indices of the lower and upper hit
   int *md_mod;
   float4 *md_pos;   // anchor (lower hit) x, y, z, r
-  float2 *md_stub;  // tangential displacement, sensor separation
+  float2 *md_stub;  // tangential displacement, sensor separation (dense half2 with DevGeom::stub16)
   float4 *mod_disc;  // per module with MDs: x-y disc (cx, cy, radius, |c|) around its anchors
   // segments
   int *ls_cnt, *ls_off;

@@ -453,3 +453,29 @@ def test_server_with_extensions_and_displaced_bound(lst, full, gfull_ext, many_o
         to, oo, ho = oracle.run(og, e).tc()
         tg, og_, hg = got[i]
         assert np.array_equal(tg, to) and np.array_equal(og_, oo) and np.array_equal(hg, ho)
+
+
+def test_half_stubs_equal_oracle(lst, full, barrel):
+    """MD stubs in binary16: every stage and the candidates bit-exact with the oracle's binary16 column."""
+    g = lst.Geometry(full)
+    g.set_stub_precision(16)
+    og = oracle.OracleGeometry(full, stub16=True)
+    ev = make_event("pu200_seeded", 5)
+    r = _run(lst, g, ev)
+    o = oracle.run(og, ev)
+    stats = compare_event(r, o)
+    compare_tc(r, o)
+    r.close()
+    assert stats["LS"]["oracle"] > 100000
+    gb = lst.Geometry(barrel)
+    gb.set_stub_precision(16)
+    ogb = oracle.OracleGeometry(barrel, stub16=True)
+    for k in range(3):
+        ev = make_event("tiny", 10 + k)
+        r = _run(lst, gb, ev)
+        o = oracle.run(ogb, ev)
+        compare_event(r, o, stages=range(4))
+        compare_tc(r, o)
+        r.close()
+    lib = lst.load_library()
+    assert lib.lst_set_stub_precision(gb.handle, 8) == lst.LST_E_INVALID
