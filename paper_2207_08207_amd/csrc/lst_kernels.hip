@@ -1906,7 +1906,7 @@ __global__ __launch_bounds__(kBlock) void k_tc_ext(const Ws *__restrict__ wb, De
         bool ok = ov == 1 || abc.y == s_md[wv][e];
         ok = ok && fabsf(dk) <= ta.y + s_dkt[wv][e];
         if (ok) {
-          // one instantiation per chain length keeps the anchors in registers
+          // the anchors fill ext_fit's fixed slots (static indices: they stay in registers)
           float3 a;
           int4 h;
           if (ext_eval(w, g, s_P[wv], s_M[wv], e, K, add, abc, &a, &h)) {
