@@ -173,8 +173,8 @@ def _oracle_worker(workload, ev, start, out):
         out.put(("ready", 0.0))
         start.wait()
         t = time.perf_counter()
-        oracle.run(og, ev)
-        out.put(("done", time.perf_counter() - t))
+        r = oracle.run(og, ev)
+        out.put(("done", (time.perf_counter() - t, r.step_seconds())))
     except BaseException as e:  # report instead of leaving the parent waiting
         out.put(("error", repr(e)))
 
@@ -189,7 +189,17 @@ def cpu_baseline(workload, events, n_workers):
     for p in procs:
         p.start()
     def get(what):
-        m = out.get(timeout=600)
+        import queue
+        t_end = time.time() + 600
+        while True:
+            try:
+                m = out.get(timeout=2)
+                break
+            except queue.Empty:
+                dead = [p.exitcode for p in procs if p.exitcode not in (None, 0)]
+                if dead or time.time() > t_end:
+                    start.set()
+                    raise RuntimeError(f"oracle worker exited with {dead[0]}" if dead else "oracle workers timed out")
         if m[0] != what:
             start.set()
             raise RuntimeError(f"oracle worker: {m}")
@@ -199,13 +209,16 @@ def cpu_baseline(workload, events, n_workers):
         get("ready")
     t0 = time.perf_counter()
     start.set()
-    per_event = [get("done") for _ in procs]
+    done = [get("done") for _ in procs]
     wall = time.perf_counter() - t0
     for p in procs:
         p.join()
         if p.exitcode != 0:
             raise RuntimeError(f"oracle worker exited with {p.exitcode}")
-    return n_workers / wall, wall, sorted(per_event)
+    # each worker is one serial event on one core: median wall seconds of every step
+    import numpy as np
+    steps = {k: round(float(np.median([d[1][k] for d in done])), 4) for k in done[0][1]}
+    return n_workers / wall, wall, sorted(d[0] for d in done), steps
 
 
 def main():
@@ -621,7 +634,7 @@ def main():
         log(f"bench: physics {json.dumps(m)}")
     if not args.no_cpu:
         n_work = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
-        rate, wall, per_event = cpu_baseline(args.workload, host, n_work)
+        rate, wall, per_event, steps = cpu_baseline(args.workload, host, n_work)
         model = "unknown CPU"
         try:
             with open("/proc/cpuinfo") as fh:
@@ -632,7 +645,8 @@ def main():
                                "sample": f"{n_work} {args.workload} events (the first {min(n_work, len(host))} "
                                          f"of the pool, cycled), one per process, all at once: serial FP32 C "
                                          f"oracle, full chain, {wall:.1f} s wall; per event "
-                                         f"{per_event[len(per_event) // 2]:.2f} s median; {model}"}
+                                         f"{per_event[len(per_event) // 2]:.2f} s median; {model}",
+                               "serial_stage_s": steps}
     print(json.dumps(out), flush=True)
 
 

@@ -22,6 +22,9 @@ ST_MD, ST_LS, ST_T3, ST_T5, ST_PLS, ST_PT3, ST_PT5, ST_TC = range(8)
 STAGE_NAMES = ["MD", "LS", "T3", "T5", "pLS", "pT3", "pT5", "TC"]
 TUPLE_W = [2, 4, 6, 10, 1, 7, 11, 0]
 ATTR_W = [0, 2, 4, 8, 5, 3, 3, 0]
+# timed steps of a run: set-up, the eight stages (with their duplicate removal
+# and cross-cleaning), track extensions
+STEP_NAMES = ["setup"] + STAGE_NAMES + ["ext"]
 
 
 def build(force=True):
@@ -57,6 +60,8 @@ def _lib(f64=False):
         lib.orc_tc_hit_count.argtypes = [vp]
         lib.orc_ext_hit_count.argtypes = [vp]
         lib.orc_ext.argtypes = [vp, vp, vp, vp, vp, vp]
+        lib.orc_step_seconds.argtypes = [vp, ctypes.c_int]
+        lib.orc_step_seconds.restype = ctypes.c_double
         lib.orc_border_count.argtypes = [vp, ctypes.c_int]
         lib.orc_border.argtypes = [vp, ctypes.c_int, vp, vp]
         lib.orc_free.argtypes = [vp]
@@ -151,6 +156,11 @@ class OracleResult:
         hits = np.zeros(nh, np.int32)
         self.lib.orc_ext(ctypes.c_void_p(self.handle), _p(na), _p(t3), _p(at), _p(off), _p(hits))
         return na, t3, at, off, hits
+
+    def step_seconds(self):
+        """{step name: wall seconds} of the run, measured by the oracle on its own thread."""
+        return {n: float(self.lib.orc_step_seconds(ctypes.c_void_p(self.handle), k))
+                for k, n in enumerate(STEP_NAMES)}
 
     def border(self, stage):
         n = int(self.lib.orc_border_count(ctypes.c_void_p(self.handle), stage))

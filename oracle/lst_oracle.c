@@ -27,11 +27,15 @@
  * rounded to `real`.
  *
  * Stage ids: 0 MD, 1 LS, 2 T3, 3 T5, 4 pLS, 5 pT3, 6 pT5, 7 TC.
+ * Each run also records the wall time of every step on the calling thread
+ * (orc_step_seconds), so the oracle's serial cost per stage can be reported.
  */
+#define _POSIX_C_SOURCE 199309L
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 
 #ifdef ORACLE_F64
 typedef double real;
@@ -70,6 +74,9 @@ static const double X_EXT_XY = 10.0;            /* extension circle-fit chi2 per
 static const double X_EXT_RZ = 20.0 / 3.0;      /* extension line-fit chi2 per degree of freedom */
 
 enum { ST_MD = 0, ST_LS, ST_T3, ST_T5, ST_PLS, ST_PT3, ST_PT5, ST_TC, N_ST };
+/* timed steps: event set-up (hit radii), the eight stages (T5, pT3 and pT5
+ * with their duplicate removal; TC with cross-cleaning), track extensions */
+enum { N_STEP = N_ST + 2 };
 static const int TUPLE_W[N_ST] = {2, 4, 6, 10, 1, 7, 11, 0};
 static const int ATTR_W[N_ST] = {0, 2, 4, 8, 5, 3, 3, 0};
 
@@ -261,6 +268,7 @@ typedef struct {
   const int *q, *hits4;
   const float *px, *py, *pz;
   int status;
+  double step_s[N_STEP];                 /* wall seconds of each step of the run */
 } orc_event;
 
 /* Borderline bookkeeping (a candidate is borderline when no cut fails by more
@@ -1270,21 +1278,40 @@ static orc_event *event_new(int n_hits, const float *x, const float *y, const fl
   return e;
 }
 
+static double now_s(void) {
+  struct timespec ts;
+  clock_gettime(CLOCK_MONOTONIC, &ts);
+  return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* books the time since *t to step k and restarts the clock */
+static void lap(orc_event *e, int k, double *t) {
+  double u = now_s();
+  e->step_s[k] = u - *t;
+  *t = u;
+}
+
 /* Runs the chain up to and including stage `last` (0..7).  Inputs are read
  * during the call only.  Returns an opaque result, freed by orc_free. */
 void *orc_run(void *gp, int n_hits, const float *x, const float *y, const float *z, const int *module,
               const int *sensor, int n_seeds, const float *px, const float *py, const float *pz, const int *q,
               const int *hits4, int last) {
   const orc_geom *g = (const orc_geom *)gp;
+  double t = now_s();
   orc_event *e = event_new(n_hits, x, y, z, module, sensor, n_seeds, px, py, pz, q, hits4);
+  lap(e, 0, &t);
   stage_md(g, e);
-  if (last >= ST_LS) stage_ls(g, e);
-  if (last >= ST_T3) stage_t3(g, e);
-  if (last >= ST_T5) { stage_t5(g, e); stage_t5_dedup(e); }
-  if (last >= ST_PLS) stage_pls(e);
-  if (last >= ST_PT3) { stage_pt(g, e, 0); stage_pt_dedup(e, 0); }
-  if (last >= ST_PT5) { stage_pt(g, e, 1); stage_pt_dedup(e, 1); }
-  if (last >= ST_TC) { stage_tc(e); stage_ext(g, e); }
+  lap(e, 1 + ST_MD, &t);
+  if (last >= ST_LS) { stage_ls(g, e); lap(e, 1 + ST_LS, &t); }
+  if (last >= ST_T3) { stage_t3(g, e); lap(e, 1 + ST_T3, &t); }
+  if (last >= ST_T5) { stage_t5(g, e); stage_t5_dedup(e); lap(e, 1 + ST_T5, &t); }
+  if (last >= ST_PLS) { stage_pls(e); lap(e, 1 + ST_PLS, &t); }
+  if (last >= ST_PT3) { stage_pt(g, e, 0); stage_pt_dedup(e, 0); lap(e, 1 + ST_PT3, &t); }
+  if (last >= ST_PT5) { stage_pt(g, e, 1); stage_pt_dedup(e, 1); lap(e, 1 + ST_PT5, &t); }
+  if (last >= ST_TC) {
+    stage_tc(e); lap(e, 1 + ST_TC, &t);
+    stage_ext(g, e); lap(e, N_STEP - 1, &t);
+  }
   /* the seeds' pointers are not kept past the call */
   e->px = e->py = e->pz = NULL;
   if (n_seeds) {
@@ -1297,6 +1324,13 @@ void *orc_run(void *gp, int n_hits, const float *x, const float *y, const float 
   e->module = e->sensor = NULL;
   e->q = NULL;
   return e;
+}
+
+/* Wall seconds of step k of the run (0: set-up, 1..8: stages 0..7, 9: track
+ * extensions); 0 for a step the run did not reach or k out of range. */
+double orc_step_seconds(void *ep, int k) {
+  const orc_event *e = (const orc_event *)ep;
+  return (k >= 0 && k < N_STEP) ? e->step_s[k] : 0.0;
 }
 
 int orc_count(void *ep, int stage) {
