@@ -128,6 +128,24 @@ def algorithmic_bytes(site, c, n_outer, n_mod, n_edges, n_seeds, n_tc):
     return table.get(site)
 
 
+# The stages of the whole chain, each reading its inputs once and writing its
+# outputs once (the fills, which read what their count pass read and write the
+# objects; duplicate removal; cleaning; the TC write).  Their sum plus the hit
+# bucketing (16 B raw read + 20 B bucketed write per hit) is the chain's
+# algorithmic bytes per event; the count passes' re-reads are not counted.
+CHAIN_SITES = ("md_fill", "ls_fill", "t3_fill", "t5_fill", "t5_dedup", "pt3_fill", "pt5_fill",
+               "tc_pt3", "tc_t5", "tc_pls", "tc_write")
+
+
+def chain_bytes(c, n_hits, n_outer, n_mod, n_edges, n_seeds):
+    """Algorithmic bytes of one event through the whole chain (c = stage counts MD..TC)."""
+    cc = dict(md=int(c[0]), ls=int(c[1]), t3=int(c[2]), t5=int(c[3]), pt3=int(c[5]), pt5=int(c[6]))
+    tot = 16 * n_hits + 20 * n_outer
+    for site in CHAIN_SITES:
+        tot += algorithmic_bytes(site, cc, n_outer, n_mod, n_edges, n_seeds, int(c[7]))
+    return tot
+
+
 def percentiles(x_ms):
     import numpy as np
     x = np.asarray(x_ms, float)
@@ -308,15 +326,18 @@ def main():
     srv.drain(n_warm, lambda r: lst.lst_release_event(r["event"]))
     lst.lst_set_timed_site(dom)
     torch.cuda.synchronize()
-    served_lat, launches = [], {}
+    served_lat, launches, chain_served = [], {}, []
 
     def take(r):
         served_lat.append((r["done_s"] - r["arrival_s"]) * 1e3)
         c, _ = lst.lst_get_stage_counts(r["event"])
         ms = lst.lst_get_site_time(r["event"])
         rec = launches.setdefault(r["admit_s"], [ms, 0.0])
-        b = event_bytes(host[r["id"] % len(host)], c)
+        hev = host[r["id"] % len(host)]
+        b = event_bytes(hev, c)
         rec[1] = None if (b is None or rec[1] is None) else rec[1] + b
+        chain_served.append(chain_bytes(c, hev.n_hits, int((hev.module >= 0).sum()), geom.n_modules,
+                                        int(geom.map_targets.size), hev.n_seeds))
         lst.lst_release_event(r["event"])
 
     t0 = time.perf_counter()
@@ -523,7 +544,9 @@ def main():
     # ---- batched: captured plan over B slots (pile-up U[140, 250]), graph replays
     batched = None
     if args.batch > 0 and "batched" in forms:
-        bpool = [lst.upload_event(make_event("batch", i), dev) for i in range(min(args.pool, args.batch))]
+        bhost = [make_event("batch", i) for i in range(min(args.pool, args.batch))]
+        bpool = [lst.upload_event(e, dev) for e in bhost]
+        chain_batched = []
         bmax = max(int(t["x"].numel()) for t in bpool)
         bseed = max(int(t["px"].numel()) for t in bpool)
         evs = [bpool[i % len(bpool)] for i in range(args.batch)]
@@ -531,7 +554,11 @@ def main():
 
         def time_plan():
             plan = lst.Plan(g, args.batch, bmax, bseed)  # captured with the geometry's launch shapes
-            for r in plan.run(evs):
+            for i, r in enumerate(plan.run(evs)):
+                if len(chain_batched) < args.batch:  # the first replay of the first plan
+                    hev = bhost[i % len(bhost)]
+                    chain_batched.append(chain_bytes(r.counts()[0], hev.n_hits, int((hev.module >= 0).sum()),
+                                                     geom.n_modules, int(geom.map_targets.size), hev.n_seeds))
                 r.close()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -553,6 +580,9 @@ def main():
             el_d = time_plan()
             g.set_launch_config(tuned)
             batched["default_shapes_events_per_s"] = round(reps * args.batch / el_d, 2)
+        bb = float(np.mean(chain_batched))
+        batched["chain_bytes_per_event"] = int(bb)
+        batched["chain_hbm_frac"] = round(batched["events_per_s"] * bb / (HBM_PEAK_GBS * 1e9), 5)
         log(f"bench: batched {batched}")
 
     # ---- device-to-device copy of a known size: achievable HBM bandwidth, and the reference
@@ -605,6 +635,16 @@ def main():
         "launch_shapes": tuned, "plain": plain, "plain_graph": plain_graph, "stub16": stub16, "extensions": ext, "displaced": displaced, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
         "roofline": roof,
     }
+    if chain_served:
+        # the whole chain against HBM: algorithmic bytes of an event through every stage
+        cb = float(np.mean(chain_served))
+        out["chain_roofline"] = {
+            "bound": "hbm", "bytes_per_event": int(cb), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "roofline_events_per_s": round(HBM_PEAK_GBS * 1e9 / cb, 1),
+            "served_frac": round(value * cb / (HBM_PEAK_GBS * 1e9), 5),
+            "batched_frac": batched["chain_hbm_frac"] if batched else None,
+            "bytes": "hits 16 B read + 20 B bucketed per hit, plus each stage's inputs read once and outputs "
+                     "written once (" + ", ".join(CHAIN_SITES) + ")"}
     if not args.no_physics:
         # efficiency, fake and duplicate rates of the HIP track candidates of every pool event,
         # against the generator's truth (outside every timed region)
