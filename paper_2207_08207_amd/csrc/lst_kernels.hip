@@ -1104,6 +1104,20 @@ __global__ void k_obj_bin_scatter(const Ws *__restrict__ wb, DevGeom g) {
 // 1.01 cm of the seed circle on its forward half-turn (algebraic distance
 // <= 1 cm with |kappa| <= 0.02/cm), hence within d = 1.01 + step/2 + 0.05 cm
 // of a trajectory sample taken every `kSampleStep` of arc.
+static_assert(kPhiBins % 32 == 0, "a ring's row of the bin mask is whole words");
+
+// Sets bits id0 .. id0 + n - 1 of the mask, one atomic per word.
+__device__ __forceinline__ void mark_run(unsigned *mask, int id0, int n) {
+  const int end = id0 + n;
+  for (int id = id0; id < end;) {
+    const int bit = id & 31;
+    const int take = min(32 - bit, end - id);
+    const unsigned m = take == 32 ? 0xffffffffu : ((1u << take) - 1u) << bit;
+    atomicOr(&mask[id >> 5], m);
+    id += take;
+  }
+}
+
 __device__ void mark_seed_bins(const Seed &sd, unsigned *mask, int *s_lo, int *s_hi) {
   const int lane = lane_id();
   const float d = 1.01f * kBoxXY + 0.5f * kSampleStep + 0.05f;
@@ -1136,15 +1150,18 @@ __device__ void mark_seed_bins(const Seed &sd, unsigned *mask, int *s_lo, int *s
       b1 = (int)floorf((ph + hw + (float)M_PI) / bw) + 1;
       if (b1 - b0 >= kPhiBins) { b0 = 0; b1 = kPhiBins - 1; }
     }
+    // bins b0..b1 (fewer than kPhiBins, may wrap round) as at most two runs of
+    // one ring's row; a ring's row is whole mask words, so each word a run
+    // touches takes one atomic
+    const int lo = ((b0 % kPhiBins) + kPhiBins) % kPhiBins;
+    const int len = b1 - b0 + 1;
+    const int n1 = min(len, kPhiBins - lo);
     for (int rr = r0; rr <= r1; ++rr) {
       // arc lengths are >= 0, so their float bits order like ints
       atomicMin(&s_lo[rr], __float_as_int(sarc));
       atomicMax(&s_hi[rr], __float_as_int(sarc));
-      for (int b = b0; b <= b1; ++b) {
-        const int bb = ((b % kPhiBins) + kPhiBins) % kPhiBins;
-        const int id = rr * kPhiBins + bb;
-        atomicOr(&mask[id >> 5], 1u << (id & 31));
-      }
+      mark_run(mask, rr * kPhiBins + lo, n1);
+      if (len > n1) mark_run(mask, rr * kPhiBins, len - n1);
     }
   }
 }
