@@ -70,6 +70,8 @@ def _lib(f64=False):
         lib.orc_geom_set_stub16.argtypes = [vp, ctypes.c_int]
         lib.orc_round_half.argtypes = [ctypes.c_double]
         lib.orc_round_half.restype = ctypes.c_double
+        lib.orc_geom_set_t5_cuts.argtypes = [vp, vp, vp]
+        lib.orc_t5_cuts.argtypes = [vp, vp, vp]
         lib.orc_module_consts.argtypes = [vp, vp]
         lib.orc_module_consts_f64.argtypes = [vp, vp]
         _LIBS[f64] = lib
@@ -101,6 +103,20 @@ class OracleGeometry:
             self.lib.orc_geom_set_d0max(ctypes.c_void_p(self.handle), ctypes.c_double(float(d0_max)))
         if stub16:
             self.lib.orc_geom_set_stub16(ctypes.c_void_p(self.handle), 1)
+
+    def set_t5_cuts(self, xy=None, rz=None):
+        """Quintuplet chi2 cuts of the 1024 categories (None: the calibrated table)."""
+        ax = None if xy is None else np.ascontiguousarray(np.broadcast_to(xy, (1024,)), np.float64)
+        ar = None if rz is None else np.ascontiguousarray(np.broadcast_to(rz, (1024,)), np.float64)
+        self.lib.orc_geom_set_t5_cuts(ctypes.c_void_p(self.handle), None if ax is None else _p(ax),
+                                      None if ar is None else _p(ar))
+
+    def t5_cuts(self):
+        """(xy, rz): the quintuplet chi2 cuts in force, per category (1024 each)."""
+        xy = np.zeros(1024, np.float64)
+        rz = np.zeros(1024, np.float64)
+        self.lib.orc_t5_cuts(ctypes.c_void_p(self.handle), _p(xy), _p(rz))
+        return xy, rz
 
     def module_consts(self, as_f64=False):
         """(n_modules, 4) array of W, A1, A2, A3 (rounded to the oracle's precision unless as_f64)."""

@@ -59,8 +59,7 @@ static const double H_LONG[2] = {0.075, 2.5};
 static const double TAU = 0.8;      /* sin bound of the track-to-radial angle (endcap xy error) */
 /* Cut values (chi2 in units of half-pitch errors). */
 static const double X_T3 = 10.0;
-static const double X_T5XY = 20.0;
-static const double X_T5RZ = 20.0;
+/* T5 chi2 cuts: per quintuplet category, see t5_category() and T5_CUTS below. */
 static const double X_PXY[2] = {50.0, 80.0};   /* pT3, pT5 */
 static const double X_PRZ[2] = {50.0, 80.0};
 static const double B_XY = 1.0;                /* pLS-object window in x-y [cm] */
@@ -104,7 +103,45 @@ typedef struct {
   double *Wd, *A1d, *A2d, *A3d;
   double d0max;                 /* transverse impact-parameter bound of the selections [cm] */
   int stub16;                   /* MD stubs kept in binary16 (1) or in the working precision (0) */
+  double t5xy[1024], t5rz[1024]; /* T5 chi2 cuts per quintuplet category */
 } orc_geom;
+
+/* Quintuplet chi2 cuts per category (Section 2.3 sets the quintuplet cuts
+ * empirically, category by category).  Category = the ordered kinds of the
+ * five anchors, innermost first, kind = 2 * endcap + 2S (0 barrel PS,
+ * 1 barrel 2S, 2 endcap PS, 3 endcap 2S), index = sum_i kind_i 4^i.
+ * Values: the 99.5% quantile of the circle-fit and r-z chi2 of the
+ * quintuplets whose ten hits all belong to one generated track above
+ * threshold, on 20 calibration events (PU200-like, generator events 900-919,
+ * disjoint from every event the tests and the benchmark use), rounded up to
+ * three significant digits; a category with fewer than 50 such quintuplets
+ * takes the quantile pooled over all categories (T5_POOLED). */
+static const double T5_POOLED[2] = {2.25, 2.7};
+static const struct { int cat; double xy, rz; } T5_CUTS[] = {
+  { 320, 2.5, 2.83},  /* bPS bPS bPS b2S b2S */
+  { 336, 2.53, 2.5},  /* bPS bPS b2S b2S b2S */
+  { 672, 0.194, 2.55},  /* bPS bPS ePS ePS ePS */
+  { 680, 0.148, 2.58},  /* bPS ePS ePS ePS ePS */
+  { 682, 0.137, 2.77},  /* ePS ePS ePS ePS ePS */
+  { 832, 2.06, 2.87},  /* bPS bPS bPS b2S e2S */
+  { 848, 2.01, 2.49},  /* bPS bPS b2S b2S e2S */
+  { 896, 0.342, 2.74},  /* bPS bPS bPS ePS e2S */
+  { 928, 0.3, 2.76},  /* bPS bPS ePS ePS e2S */
+  { 936, 0.278, 2.7},  /* bPS ePS ePS ePS e2S */
+  { 938, 0.275, 2.91},  /* ePS ePS ePS ePS e2S */
+  { 960, 0.622, 2.88},  /* bPS bPS bPS e2S e2S */
+  { 976, 0.906, 2.45},  /* bPS bPS b2S e2S e2S */
+  { 992, 0.451, 2.87},  /* bPS bPS ePS e2S e2S */
+  {1000, 0.392, 2.62},  /* bPS ePS ePS e2S e2S */
+  {1002, 0.408, 2.8},  /* ePS ePS ePS e2S e2S */
+  {1008, 0.716, 2.5},  /* bPS bPS e2S e2S e2S */
+  {1012, 1.19, 2.67},  /* bPS b2S e2S e2S e2S */
+  {1016, 0.493, 2.52},  /* bPS ePS e2S e2S e2S */
+  {1018, 0.492, 2.57},  /* ePS ePS e2S e2S e2S */
+  {1020, 0.729, 2.68},  /* bPS e2S e2S e2S e2S */
+  {1022, 0.614, 2.64},  /* ePS e2S e2S e2S e2S */
+  {1023, 0.928, 1.75},  /* e2S e2S e2S e2S e2S */
+};
 
 /* asin(x) for |x| <= 0.85 from its Maclaurin series, summed in a fixed order
  * with + * / only: sum_n c_n x^(2n+1), c_{n+1} = c_n (2n+1)^2 / ((2n+2)(2n+3)). */
@@ -199,6 +236,26 @@ void orc_geom_set_d0max(void *gp, double d0max) {
   }
 }
 
+/* Sets the quintuplet chi2 cuts of all 1024 categories (xy[c], rz[c]); NULL
+ * restores the calibrated table.  The calibration itself runs with the cuts
+ * opened this way. */
+void orc_geom_set_t5_cuts(void *gp, const double *xy, const double *rz) {
+  orc_geom *g = (orc_geom *)gp;
+  for (int c = 0; c < 1024; ++c) { g->t5xy[c] = T5_POOLED[0]; g->t5rz[c] = T5_POOLED[1]; }
+  for (size_t k = 0; k < sizeof(T5_CUTS) / sizeof(T5_CUTS[0]); ++k) {
+    g->t5xy[T5_CUTS[k].cat] = T5_CUTS[k].xy;
+    g->t5rz[T5_CUTS[k].cat] = T5_CUTS[k].rz;
+  }
+  if (xy) memcpy(g->t5xy, xy, sizeof(g->t5xy));
+  if (rz) memcpy(g->t5rz, rz, sizeof(g->t5rz));
+}
+/* The quintuplet chi2 cuts in force (1024 each). */
+void orc_t5_cuts(void *gp, double *xy, double *rz) {
+  orc_geom *g = (orc_geom *)gp;
+  memcpy(xy, g->t5xy, sizeof(g->t5xy));
+  memcpy(rz, g->t5rz, sizeof(g->t5rz));
+}
+
 void *orc_geom_create(int n_mod, const int *subdet, const int *layer, const int *side, const int *type,
                       const float *pos_lo, const float *pos_up, const float *lmin, const float *lmax,
                       int n_edges, const int *map_off, const int *map_tgt) {
@@ -218,6 +275,7 @@ void *orc_geom_create(int n_mod, const int *subdet, const int *layer, const int 
     g->pos_lo[m] = pos_lo[m]; g->pos_up[m] = pos_up[m]; g->lmin[m] = lmin[m]; g->lmax[m] = lmax[m];
   }
   orc_geom_set_d0max(g, D0_MAX);
+  orc_geom_set_t5_cuts(g, NULL, NULL);
   return g;
 }
 
@@ -534,6 +592,14 @@ static int t3_select(const orc_geom *g, orc_event *e, int ma_, int mb_, int mc_,
   return ok;
 }
 
+/* Category of a quintuplet with anchor modules M[0..4] (innermost first):
+ * sum_i kind_i 4^i, kind = 2 * endcap + 2S. */
+static int t5_category(const orc_geom *g, const int M[5]) {
+  int c = 0;
+  for (int i = 4; i >= 0; --i) c = 4 * c + (2 * endcap_of(g, M[i]) + g->type[M[i]]);
+  return c;
+}
+
 /* --------------------------------------------------------------- T5 predicate */
 /* Section 2.3: two triplets sharing an MD; the circles of the inner and outer
  * triplet must have compatible radii, a circle fit to the five anchors must
@@ -589,7 +655,8 @@ static int t5_select(const orc_geom *g, orc_event *e, const int md[5], const rea
     real r = v[i] - ((fa + fb * u[i]) + fc * q[i]);
     chi2xy = chi2xy + w[i] * r * r;
   }
-  ok &= cut_le(ac, chi2xy, (real)X_T5XY, RL(0));
+  const int cat = t5_category(g, M);
+  ok &= cut_le(ac, chi2xy, (real)g->t5xy[cat], RL(0));
   real disc = (RL(1) + fb * fb) - RL(4) * fa * fc;
   if (!(disc > RL(0))) { ac->firm_fail = 1; return 0; }
   real k5 = (RL(2) * fc) / (L * RSQRT_(disc));
@@ -608,7 +675,7 @@ static int t5_select(const orc_geom *g, orc_event *e, const int md[5], const rea
   real lam0 = (Z[4] - Z[0]) / s[4];
   for (int i = 0; i < 5; ++i) { sg = sig_z(g, M[i], lam0); w[i] = RL(1) / (sg * sg); }
   real chi2rz = line_fit(5, s, Z, w, &lam);
-  ok &= cut_le(ac, chi2rz, (real)X_T5RZ, RL(0));
+  ok &= cut_le(ac, chi2rz, (real)g->t5rz[cat], RL(0));
   /* direction at the beam line: tangent at the first anchor, rotated back */
   real nb = RSQRT_(RL(1) + fb * fb);
   real cx = (ux - fb * uy) / nb, cy = (uy + fb * ux) / nb;
