@@ -233,6 +233,24 @@ lst_status lst_set_stub_precision(lst_geometry geom, int32_t bits);
  * a NULL geometry or a bound outside (0, 10]; LST_E_DEVICE. */
 lst_status lst_set_impact_bound(lst_geometry geom, double d0_max);
 
+/* Quintuplet chi2 cuts per category (Section 2.3 sets them empirically for
+ * each category of quintuplets).  Category index c in [0, 1024) = sum over
+ * the five anchor modules, innermost first, of kind_i * 4^i with kind
+ * 0 barrel PS, 1 barrel 2S, 2 endcap PS, 3 endcap 2S.  xy[c] bounds the
+ * five-anchor circle-fit chi2, rz[c] the r-z line chi2 (a quintuplet passes
+ * when chi2 <= cut).  lst_load_geometry installs the library's calibrated
+ * table; lst_set_t5_cuts replaces it with HOST arrays of 1024 floats (either
+ * may be NULL: that half keeps the calibrated values) and applies to every
+ * chain that starts afterwards, plans included; call it while no chain of
+ * this geometry is in flight.  lst_get_t5_cuts copies the table in force to
+ * two HOST arrays of 1024 floats; lst_get_default_t5_cuts copies the
+ * calibrated table itself (host only: no geometry, no device needed).
+ * Errors: LST_E_INVALID for a NULL geometry or output, or a NaN cut;
+ * LST_E_DEVICE. */
+lst_status lst_set_t5_cuts(lst_geometry geom, const float *xy, const float *rz);
+lst_status lst_get_t5_cuts(lst_geometry geom, float *xy, float *rz);
+lst_status lst_get_default_t5_cuts(float *xy, float *rz);
+
 /* Track extensions (Section 2.5, last part): the final collection in which
  * a candidate with outer-tracker MDs (pT5, pT3, T5) is lengthened outward by
  * one triplet that shares its last two MDs (one MD added) or its last MD

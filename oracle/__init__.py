@@ -72,6 +72,14 @@ def _lib(f64=False):
         lib.orc_round_half.restype = ctypes.c_double
         lib.orc_geom_set_t5_cuts.argtypes = [vp, vp, vp]
         lib.orc_t5_cuts.argtypes = [vp, vp, vp]
+        i32 = ctypes.c_int
+        lib.orc_probe_md.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
+        lib.orc_probe_ls.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.orc_probe_t3.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.orc_probe_t5.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        f32, f64_ = ctypes.c_float, ctypes.c_double
+        lib.orc_probe_pt.argtypes = [vp, i32, vp, vp, vp, vp, f32, f32, f32, i32, f64_, f64_, vp, vp, vp, vp, vp]
+        lib.orc_probe_near.argtypes = [f64_] * 7
         lib.orc_module_consts.argtypes = [vp, vp]
         lib.orc_module_consts_f64.argtypes = [vp, vp]
         _LIBS[f64] = lib
@@ -218,3 +226,97 @@ def run_brute(ogeom, ev):
     h = ogeom.lib.orc_run_brute(ctypes.c_void_p(ogeom.handle), ctypes.c_int(ev.n_hits), _p(a["x"]), _p(a["y"]),
                                 _p(a["z"]), _p(a["module"]), _p(a["sensor"]), _p(counts))
     return OracleResult(ogeom.lib, h, ogeom.f64, ev.n_hits), counts
+
+
+# --------------------------------------------------------- selection probes
+class Probe:
+    """One selection evaluated on hand-placed hits (test instrumentation).
+
+    ok: the predicate's decision; cuts: every cut it evaluated, in order, as
+    (quantity, bound, kind) with kind 0 for "passes when quantity <= bound"
+    and 1 for "passes when quantity > bound"; attr: what the stage reports."""
+
+    def __init__(self, ok, q, b, kind, n, attr=None, extra=None):
+        self.ok = bool(ok)
+        self.cuts = [(float(q[k]), float(b[k]), int(kind[k])) for k in range(n)]
+        self.attr = attr
+        self.extra = extra
+
+    def passes(self, k):
+        q, b, kind = self.cuts[k]
+        return q <= b if kind == 0 else q > b
+
+    def failing(self):
+        return [k for k in range(len(self.cuts)) if not self.passes(k)]
+
+
+def _hits(xyz, n):
+    a = np.ascontiguousarray(np.asarray(xyz, np.float32).reshape(n, 3))
+    return [np.ascontiguousarray(a[:, i]) for i in range(3)]
+
+
+def _trace():
+    return np.zeros(48, np.float64), np.zeros(48, np.float64), np.zeros(48, np.int32), ctypes.c_int(0)
+
+
+def probe_md(og, module, lower, upper):
+    """MD selection of a lower and an upper hit (x, y, z) in one module."""
+    x, y, z = _hits([lower, upper], 2)
+    q, b, k, n = _trace()
+    ok = og.lib.orc_probe_md(ctypes.c_void_p(og.handle), int(module), _p(x), _p(y), _p(z), _p(q), _p(b), _p(k),
+                             ctypes.byref(n))
+    return Probe(ok, q, b, k, n.value)
+
+
+def probe_ls(og, modules, hits):
+    """Segment selection of MD 0 (hits 0, 1; inner) and MD 1 (hits 2, 3); attr = (beta_in, beta_out)."""
+    x, y, z = _hits(hits, 4)
+    m = np.ascontiguousarray(modules, np.int32)
+    beta = np.zeros(2, np.float64)
+    q, b, k, n = _trace()
+    ok = og.lib.orc_probe_ls(ctypes.c_void_p(og.handle), _p(m), _p(x), _p(y), _p(z), _p(beta), _p(q), _p(b), _p(k),
+                             ctypes.byref(n))
+    return Probe(ok, q, b, k, n.value, attr=beta)
+
+
+def probe_t3(og, modules, hits):
+    """Triplet selection of MDs 0, 1, 2 (hits 2k, 2k + 1); attr = (kappa, dkappa, chi2_rz, lambda)."""
+    x, y, z = _hits(hits, 6)
+    m = np.ascontiguousarray(modules, np.int32)
+    attr = np.zeros(4, np.float64)
+    q, b, k, n = _trace()
+    ok = og.lib.orc_probe_t3(ctypes.c_void_p(og.handle), _p(m), _p(x), _p(y), _p(z), _p(attr), _p(q), _p(b), _p(k),
+                             ctypes.byref(n))
+    return Probe(ok, q, b, k, n.value, attr=attr)
+
+
+def probe_t5(og, modules, hits):
+    """Quintuplet selection of MDs 0-4 (triplets (0, 1, 2) and (2, 3, 4)); extra = the two T3 decisions."""
+    x, y, z = _hits(hits, 10)
+    m = np.ascontiguousarray(modules, np.int32)
+    attr = np.zeros(8, np.float64)
+    t3ok = np.zeros(2, np.int32)
+    q, b, k, n = _trace()
+    ok = og.lib.orc_probe_t5(ctypes.c_void_p(og.handle), _p(m), _p(x), _p(y), _p(z), _p(t3ok), _p(attr), _p(q),
+                             _p(b), _p(k), ctypes.byref(n))
+    return Probe(ok, q, b, k, n.value, attr=attr, extra=t3ok)
+
+
+def probe_pt(og, modules, pixel_hits, md_hits, seed, kT, dkT):
+    """pT3 / pT5 selection: seed = (px, py, pz, charge) with four pixel hits, outer object on
+    len(modules) MDs (hits 2k, 2k + 1 of md_hits), its curvature kT and error dkT;
+    attr = (chi2_xy, chi2_rz, score)."""
+    kk = len(modules)
+    x, y, z = _hits(list(pixel_hits) + list(md_hits), 4 + 2 * kk)
+    m = np.ascontiguousarray(modules, np.int32)
+    attr = np.zeros(3, np.float64)
+    q, b, k, n = _trace()
+    px, py, pz, ch = seed
+    ok = og.lib.orc_probe_pt(ctypes.c_void_p(og.handle), kk, _p(m), _p(x), _p(y), _p(z), float(px), float(py),
+                             float(pz), int(ch), float(kT), float(dkT), _p(attr), _p(q), _p(b), _p(k), ctypes.byref(n))
+    return Probe(ok, q, b, k, n.value, attr=attr)
+
+
+def probe_near(og, a, b, D):
+    """Section 2.5's near test between directions a, b = (dx, dy, lambda) at distance D."""
+    return bool(og.lib.orc_probe_near(*(float(v) for v in a), *(float(v) for v in b), float(D)))

@@ -331,9 +331,19 @@ typedef struct {
 
 /* Borderline bookkeeping (a candidate is borderline when no cut fails by more
  * than BORDER_REL relative and at least one cut is within that band). */
-typedef struct { int firm_fail, near; } cutacc;
+/* Optional record of every cut a selection evaluates, in evaluation order
+ * (test instrumentation for the selection probes; never read by the chain). */
+#define TRACE_MAX 48
+typedef struct { double q[TRACE_MAX], b[TRACE_MAX]; int kind[TRACE_MAX]; int n; } cut_trace;
+typedef struct { int firm_fail, near; cut_trace *tr; } cutacc;
+static void trace_cut(cutacc *a, real q, real b, int kind) {
+  if (!a->tr || a->tr->n >= TRACE_MAX) return;
+  a->tr->q[a->tr->n] = (double)q; a->tr->b[a->tr->n] = (double)b; a->tr->kind[a->tr->n] = kind;
+  a->tr->n++;
+}
 static int cut_le(cutacc *a, real q, real cut, real scale) {
   /* returns q <= cut, records nearness */
+  trace_cut(a, q, cut, 0);
   real d = q - cut;
   real m = RABS(q);
   if (RABS(cut) > m) m = RABS(cut);
@@ -346,6 +356,7 @@ static int cut_le(cutacc *a, real q, real cut, real scale) {
 }
 static int cut_gt(cutacc *a, real q, real lo, real scale) {
   /* returns q > lo */
+  trace_cut(a, q, lo, 1);
   real d = q - lo;
   real m = RABS(q);
   if (RABS(lo) > m) m = RABS(lo);
@@ -1490,6 +1501,116 @@ void orc_free(void *ep) {
   iv_free(&e->ext_n); iv_free(&e->ext_t3); iv_free(&e->ext_off); iv_free(&e->ext_hits); rv_free(&e->ext_attr);
   for (int s = 0; s < N_ST; ++s) { iv_free(&e->border[s]); iv_free(&e->border_acc[s]); }
   free(e);
+}
+
+/* ------------------------------------------------------------ selection probes */
+/* Test instrumentation: evaluates one selection on hand-placed hits through
+ * the same predicate the chain calls, and reports every cut it evaluated, in
+ * evaluation order: quantity q[k], bound b[k], kind[k] (0: passes when
+ * q <= b, 1: passes when q > b); returns the predicate's decision.  The
+ * lower and upper hit of MD k are hits 2k and 2k + 1 of x, y, z (after the
+ * four pixel hits for the seed probe); mods[k] is MD k's module. */
+static orc_event *probe_event(int n_pix, int n_md, const float *x, const float *y, const float *z, const int *mods) {
+  orc_event *e = event_new(n_pix + 2 * n_md, x, y, z, NULL, NULL, 0, NULL, NULL, NULL, NULL, NULL);
+  for (int k = 0; k < n_md; ++k) {
+    iv_push(&e->md_lo, n_pix + 2 * k); iv_push(&e->md_up, n_pix + 2 * k + 1); iv_push(&e->md_mod, mods[k]);
+  }
+  return e;
+}
+static int probe_out(cut_trace *tr, double *q, double *b, int *kind, int *n) {
+  for (int k = 0; k < tr->n; ++k) { q[k] = tr->q[k]; b[k] = tr->b[k]; kind[k] = tr->kind[k]; }
+  *n = tr->n;
+  return tr->n;
+}
+
+/* MD: hit 0 lower, hit 1 upper, in module m. */
+int orc_probe_md(void *gp, int m, const float *x, const float *y, const float *z, double *q, double *b, int *kind,
+                 int *n) {
+  cut_trace tr = {{0}, {0}, {0}, 0};
+  cutacc ac = {0, 0, &tr};
+  orc_event *e = probe_event(0, 1, x, y, z, &m);
+  int ok = md_select((const orc_geom *)gp, e, m, 0, 1, &ac);
+  probe_out(&tr, q, b, kind, n);
+  orc_free(e);
+  return ok;
+}
+
+/* LS: MD 0 in mods[0] (inner), MD 1 in mods[1]; beta[0..1] = beta_in, beta_out. */
+int orc_probe_ls(void *gp, const int *mods, const float *x, const float *y, const float *z, double *beta, double *q,
+                 double *b, int *kind, int *n) {
+  cut_trace tr = {{0}, {0}, {0}, 0};
+  cutacc ac = {0, 0, &tr};
+  orc_event *e = probe_event(0, 2, x, y, z, mods);
+  real bi = RL(0), bo = RL(0);
+  int ok = ls_select((const orc_geom *)gp, e, 0, 1, &bi, &bo, &ac);
+  beta[0] = (double)bi; beta[1] = (double)bo;
+  probe_out(&tr, q, b, kind, n);
+  orc_free(e);
+  return ok;
+}
+
+/* T3 on MDs 0, 1, 2; attr[0..3] = kappa, dkappa, chi2_rz, lambda. */
+int orc_probe_t3(void *gp, const int *mods, const float *x, const float *y, const float *z, double *attr, double *q,
+                 double *b, int *kind, int *n) {
+  cut_trace tr = {{0}, {0}, {0}, 0};
+  cutacc ac = {0, 0, &tr};
+  orc_event *e = probe_event(0, 3, x, y, z, mods);
+  real a[4] = {RL(0), RL(0), RL(0), RL(0)};
+  int ok = t3_select((const orc_geom *)gp, e, 0, 1, 2, a, &ac);
+  for (int i = 0; i < 4; ++i) attr[i] = (double)a[i];
+  probe_out(&tr, q, b, kind, n);
+  orc_free(e);
+  return ok;
+}
+
+/* T5 on MDs 0-4 from the triplets (0, 1, 2) and (2, 3, 4), whose attributes
+ * the T3 selection computes first (t3ok[0..1] its decisions); attr[0..7] as
+ * the T5 stage reports them.  The trace holds the T5 selection's cuts only. */
+int orc_probe_t5(void *gp, const int *mods, const float *x, const float *y, const float *z, int *t3ok, double *attr,
+                 double *q, double *b, int *kind, int *n) {
+  const orc_geom *g = (const orc_geom *)gp;
+  cut_trace tr = {{0}, {0}, {0}, 0};
+  cutacc ac = {0, 0, &tr}, a1 = {0, 0, NULL}, a2 = {0, 0, NULL};
+  orc_event *e = probe_event(0, 5, x, y, z, mods);
+  real ain[4], aout[4], a[8];
+  t3ok[0] = t3_select(g, e, 0, 1, 2, ain, &a1);
+  t3ok[1] = t3_select(g, e, 2, 3, 4, aout, &a2);
+  for (int i = 0; i < 8; ++i) a[i] = RL(0);
+  int md5[5] = {0, 1, 2, 3, 4};
+  int ok = t5_select(g, e, md5, ain, aout, a, &ac);
+  for (int i = 0; i < 8; ++i) attr[i] = (double)a[i];
+  probe_out(&tr, q, b, kind, n);
+  orc_free(e);
+  return ok;
+}
+
+/* pT3 (k = 3) / pT5 (k = 5): seed (px, py, pz, charge) with pixel hits 0-3,
+ * outer object on MDs 0..k-1, object curvature kT and its error dkT;
+ * attr[0..2] = chi2_xy, chi2_rz, score. */
+int orc_probe_pt(void *gp, int k, const int *mods, const float *x, const float *y, const float *z, float px, float py,
+                 float pz, int charge, double kT, double dkT, double *attr, double *q, double *b, int *kind, int *n) {
+  if (k != 3 && k != 5) return -1;
+  cut_trace tr = {{0}, {0}, {0}, 0};
+  cutacc ac = {0, 0, &tr};
+  orc_event *e = probe_event(4, k, x, y, z, mods);
+  int h4[4] = {0, 1, 2, 3};
+  e->n_seeds = 1; e->px = &px; e->py = &py; e->pz = &pz; e->q = &charge; e->hits4 = h4;
+  stage_pls(e);
+  int md[5] = {0, 1, 2, 3, 4};
+  real a[3] = {RL(0), RL(0), RL(0)};
+  int ok = pt_select((const orc_geom *)gp, e, 0, md, k, (real)kT, (real)dkT, a, &ac);
+  for (int i = 0; i < 3; ++i) attr[i] = (double)a[i];
+  probe_out(&tr, q, b, kind, n);
+  e->px = e->py = e->pz = NULL; e->q = NULL; e->hits4 = NULL;
+  orc_free(e);
+  return ok;
+}
+
+/* Near test of Section 2.5's cleaning between two directions (dx, dy,
+ * lambda) at distance D (the test the cross-cleaning applies). */
+int orc_probe_near(double ax, double ay, double al, double bx, double by, double bl, double D) {
+  odir a = {(real)ax, (real)ay, (real)al}, c = {(real)bx, (real)by, (real)bl};
+  return near_dir(a, c, (real)D);
 }
 
 /* ------------------------------------------------------------ brute force */

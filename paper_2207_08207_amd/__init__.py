@@ -31,7 +31,8 @@ EXPORTED = ["lst_load_geometry", "lst_release_geometry", "lst_default_capacity",
             "lst_server_create", "lst_server_now", "lst_server_submit", "lst_server_poll", "lst_server_pending",
             "lst_server_destroy", "lst_get_launch_config", "lst_set_launch_config", "lst_autotune",
             "lst_set_track_extensions", "lst_get_extended_track_candidates", "lst_set_impact_bound",
-            "lst_set_stub_precision"]
+            "lst_set_stub_precision", "lst_set_t5_cuts", "lst_get_t5_cuts",
+            "lst_get_default_t5_cuts"]
 
 
 class LSTError(RuntimeError):
@@ -98,6 +99,9 @@ def load_library(path=LIB_PATH):
         "lst_set_track_extensions": [vp, i32],
         "lst_set_impact_bound": [vp, ctypes.c_double],
         "lst_set_stub_precision": [vp, i32],
+        "lst_set_t5_cuts": [vp, vp, vp],
+        "lst_get_t5_cuts": [vp, vp, vp],
+        "lst_get_default_t5_cuts": [vp, vp],
         "lst_get_extended_track_candidates": [vp, P(i32), P(i32), vp, vp, vp, vp, vp, vp],
         "lst_get_stage_objects": [vp, i32, P(i32), vp, vp, vp],
         "lst_get_stage_counts": [vp, vp, vp],
@@ -232,6 +236,29 @@ def lst_set_stub_precision(geom, bits):
 
 def lst_set_impact_bound(geom, d0_max):
     _check(load_library().lst_set_impact_bound(geom, float(d0_max)))
+
+
+def lst_set_t5_cuts(geom, xy=None, rz=None):
+    """Quintuplet chi2 cuts of the 1024 categories (None: that half keeps the calibrated table)."""
+    ax = None if xy is None else np.ascontiguousarray(np.broadcast_to(xy, (1024,)), np.float32)
+    ar = None if rz is None else np.ascontiguousarray(np.broadcast_to(rz, (1024,)), np.float32)
+    _check(load_library().lst_set_t5_cuts(geom, None if ax is None else _ptr(ax), None if ar is None else _ptr(ar)))
+
+
+def lst_get_t5_cuts(geom):
+    """(xy, rz) float32 arrays of 1024: the quintuplet chi2 cuts in force per category."""
+    xy = np.zeros(1024, np.float32)
+    rz = np.zeros(1024, np.float32)
+    _check(load_library().lst_get_t5_cuts(geom, _ptr(xy), _ptr(rz)))
+    return xy, rz
+
+
+def lst_t5_chi2_cuts():
+    """(xy, rz) float32 arrays of 1024: the library's calibrated quintuplet cuts (host only)."""
+    xy = np.zeros(1024, np.float32)
+    rz = np.zeros(1024, np.float32)
+    _check(load_library().lst_get_default_t5_cuts(_ptr(xy), _ptr(rz)))
+    return xy, rz
 
 
 def lst_set_track_extensions(geom, enable):
@@ -442,6 +469,14 @@ class Geometry:
     def set_impact_bound(self, d0_max):
         """Transverse impact-parameter bound of the selections [cm] (0.1 unless set)."""
         lst_set_impact_bound(self.handle, d0_max)
+
+    def set_t5_cuts(self, xy=None, rz=None):
+        """Quintuplet chi2 cuts per category for chains enqueued from now on (None: calibrated table)."""
+        lst_set_t5_cuts(self.handle, xy, rz)
+
+    def t5_cuts(self):
+        """(xy, rz): the quintuplet chi2 cuts in force, 1024 categories each."""
+        return lst_get_t5_cuts(self.handle)
 
     def set_track_extensions(self, enable=True):
         """Chains enqueued from now on end with (or without) the track-extension step."""

@@ -47,12 +47,38 @@ struct lst_geometry_s {
   lst::DevGeom g;
   int *d_off = nullptr, *d_tgt = nullptr, *d_info = nullptr;
   float4 *d_win = nullptr;
+  float2 *d_t5cut = nullptr;  // per quintuplet category: chi2_xy, chi2_rz bounds
   int site_block[lst::kMaxSites] = {};  // launch shape of each tunable site (0 = default)
   float *d_pos = nullptr;  // per module: pos_lo, pos_up, lmin, lmax (kept to recompute the windows)
 };
 
 // Transverse impact-parameter bound of the selections unless set otherwise [cm].
 constexpr double kD0MaxDefault = 0.1;
+
+namespace {
+// Quintuplet chi2 cuts per category (Section 2.3: set empirically for each
+// category of quintuplets).  Category = the ordered kinds of the five anchor
+// modules, innermost first, kind 0 barrel PS, 1 barrel 2S, 2 endcap PS,
+// 3 endcap 2S; index sum_i kind_i 4^i.  The values are the 99.5% quantile of
+// the circle-fit and r-z chi2 of quintuplets whose ten hits come from one
+// generated track, on 20 calibration events (PU200-like, generator events
+// 900-919, disjoint from the test and benchmark events), rounded up to three
+// significant digits; categories with fewer than 50 such quintuplets take the
+// quantile pooled over all categories.
+constexpr double kT5Pooled[2] = {2.25, 2.7};
+constexpr struct { int cat; double xy, rz; } kT5Cuts[] = {
+    {320, 2.5, 2.83},    {336, 2.53, 2.5},    {672, 0.194, 2.55},  {680, 0.148, 2.58},  {682, 0.137, 2.77},
+    {832, 2.06, 2.87},   {848, 2.01, 2.49},   {896, 0.342, 2.74},  {928, 0.3, 2.76},    {936, 0.278, 2.7},
+    {938, 0.275, 2.91},  {960, 0.622, 2.88},  {976, 0.906, 2.45},  {992, 0.451, 2.87},  {1000, 0.392, 2.62},
+    {1002, 0.408, 2.8},  {1008, 0.716, 2.5},  {1012, 1.19, 2.67},  {1016, 0.493, 2.52}, {1018, 0.492, 2.57},
+    {1020, 0.729, 2.68}, {1022, 0.614, 2.64}, {1023, 0.928, 1.75},
+};
+// The calibrated table as float pairs (each value rounded once from double).
+void t5_default_cuts(float2 *out) {
+  for (int c = 0; c < 1024; ++c) out[c] = make_float2((float)kT5Pooled[0], (float)kT5Pooled[1]);
+  for (const auto &e : kT5Cuts) out[e.cat] = make_float2((float)e.xy, (float)e.rz);
+}
+}  // namespace
 
 // Events enqueued together share one batch: one descriptor array and one
 // counter block in the workspace header, one completion event, one pinned
@@ -260,14 +286,14 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   for (int m = 0; m < M; ++m) info[m] = (d->type[m] & 1) | ((d->subdet[m] & 1) << 1);
   auto cleanup = [&]() {
     drop(hipFree(g->d_off)); drop(hipFree(g->d_tgt)); drop(hipFree(g->d_info)); drop(hipFree(g->d_win));
-    drop(hipFree(g->d_pos));
+    drop(hipFree(g->d_pos)); drop(hipFree(g->d_t5cut));
     delete g;
   };
   float *&d_pos = g->d_pos;
   if (hipMalloc(&g->d_off, sizeof(int) * (M + 1)) != hipSuccess ||
       hipMalloc(&g->d_tgt, sizeof(int) * (E > 0 ? E : 1)) != hipSuccess ||
       hipMalloc(&g->d_info, sizeof(int) * M) != hipSuccess || hipMalloc(&g->d_win, sizeof(float4) * M) != hipSuccess ||
-      hipMalloc(&d_pos, sizeof(float) * 4 * M) != hipSuccess) {
+      hipMalloc(&d_pos, sizeof(float) * 4 * M) != hipSuccess || hipMalloc(&g->d_t5cut, sizeof(float2) * 1024) != hipSuccess) {
     cleanup();
     return fail(LST_E_NOMEM, "lst_load_geometry: device allocation failed");
   }
@@ -279,6 +305,11 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   if (e == hipSuccess) e = hipMemcpy(d_pos + M, d->pos_up, sizeof(float) * M, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_pos + 2 * M, d->lmin, sizeof(float) * M, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(d_pos + 3 * M, d->lmax, sizeof(float) * M, hipMemcpyHostToDevice);
+  if (e == hipSuccess) {
+    std::vector<float2> cuts(1024);
+    t5_default_cuts(cuts.data());
+    e = hipMemcpy(g->d_t5cut, cuts.data(), sizeof(float2) * 1024, hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) {
     lst::launch_module_windows(g->d_info, d_pos, d_pos + M, d_pos + 2 * M, d_pos + 3 * M, M, kD0MaxDefault, g->d_win,
                                nullptr);
@@ -298,7 +329,37 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   g->g.ext = 0;
   g->g.d0max = (float)kD0MaxDefault;
   g->g.stub16 = 0;
+  g->g.t5cut = g->d_t5cut;
   *out = g;
+  return LST_OK;
+}
+
+lst_status lst_set_t5_cuts(lst_geometry g, const float *xy, const float *rz) {
+  if (!g) return fail(LST_E_INVALID, "lst_set_t5_cuts: NULL geometry");
+  std::vector<float2> cuts(1024);
+  t5_default_cuts(cuts.data());
+  for (int c = 0; c < 1024; ++c) {
+    if (xy) cuts[c].x = xy[c];
+    if (rz) cuts[c].y = rz[c];
+    if (std::isnan(cuts[c].x) || std::isnan(cuts[c].y)) return fail(LST_E_INVALID, "lst_set_t5_cuts: NaN cut");
+  }
+  HIP_TRY(hipMemcpy(g->d_t5cut, cuts.data(), sizeof(float2) * 1024, hipMemcpyHostToDevice));
+  return LST_OK;
+}
+
+lst_status lst_get_default_t5_cuts(float *xy, float *rz) {
+  if (!xy || !rz) return fail(LST_E_INVALID, "lst_get_default_t5_cuts: NULL argument");
+  float2 cuts[1024];
+  t5_default_cuts(cuts);
+  for (int c = 0; c < 1024; ++c) { xy[c] = cuts[c].x; rz[c] = cuts[c].y; }
+  return LST_OK;
+}
+
+lst_status lst_get_t5_cuts(lst_geometry g, float *xy, float *rz) {
+  if (!g || !xy || !rz) return fail(LST_E_INVALID, "lst_get_t5_cuts: NULL argument");
+  std::vector<float2> cuts(1024);
+  HIP_TRY(hipMemcpy(cuts.data(), g->d_t5cut, sizeof(float2) * 1024, hipMemcpyDeviceToHost));
+  for (int c = 0; c < 1024; ++c) { xy[c] = cuts[c].x; rz[c] = cuts[c].y; }
   return LST_OK;
 }
 
@@ -329,7 +390,7 @@ lst_status lst_set_track_extensions(lst_geometry g, int32_t enable) {
 lst_status lst_release_geometry(lst_geometry g) {
   if (!g) return LST_OK;
   drop(hipFree(g->d_off)); drop(hipFree(g->d_tgt)); drop(hipFree(g->d_info)); drop(hipFree(g->d_win));
-  drop(hipFree(g->d_pos));
+  drop(hipFree(g->d_pos)); drop(hipFree(g->d_t5cut));
   delete g;
   return LST_OK;
 }

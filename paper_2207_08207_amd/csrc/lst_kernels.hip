@@ -803,7 +803,7 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
         P[4] = w.md_pos[cde.z];
         M[3].bits = g.info[w.md_mod[cde.y]];
         M[4].bits = g.info[w.md_mod[cde.z]];
-        pass = t5_pass(P, M, s_tin[wv][e], w.t3_attr[t2], at, g.d0max);
+        pass = t5_pass(P, M, s_tin[wv][e], w.t3_attr[t2], at, g.d0max, g.t5cut);
       }
       const unsigned long long m = __ballot(pass);
       if (!FILL && pass) {

@@ -29,8 +29,7 @@ constexpr float kKmaxCut = (float)(kCurvD / kPtMinD * 1.01);
 constexpr float kZLum = (float)kZLumD;
 constexpr float kTau = (float)0.8;        // bound on sin(track-to-radial angle), endcap x-y error
 constexpr float kXT3 = (float)10.0;       // T3 r-z chi2
-constexpr float kXT5xy = (float)20.0;     // T5 circle-fit chi2
-constexpr float kXT5rz = (float)20.0;     // T5 r-z chi2
+// T5 chi2 cuts: per quintuplet category, DevGeom::t5cut (t5_category below).
 constexpr float kXPxy3 = (float)50.0, kXPxy5 = (float)80.0;
 constexpr float kXPrz3 = (float)50.0, kXPrz5 = (float)80.0;
 constexpr float kBoxXY = (float)1.0;      // seed window at the first anchor, x-y [cm]
@@ -328,10 +327,18 @@ __device__ __forceinline__ bool t3_pass(const float4 &A, const float4 &B, const 
 }
 
 // -------------------------------------------------------------- T5 (S2.3)
-// Anchors P[0..4]; tin/tout = (kappa, dkappa, ...) of the two triplets.
+// Category of a quintuplet (Section 2.3 sets its chi2 cuts per category):
+// the ordered kinds of the five anchor modules, innermost first, kind = the
+// module info word (2 * endcap + 2S), index sum_i kind_i 4^i in [0, 1024).
+__device__ __forceinline__ int t5_category(const ModInfo *M) {
+  return (((M[4].bits * 4 + M[3].bits) * 4 + M[2].bits) * 4 + M[1].bits) * 4 + M[0].bits;
+}
+
+// Anchors P[0..4]; tin/tout = (kappa, dkappa, ...) of the two triplets;
+// cuts = (chi2_xy, chi2_rz) bounds of each category.
 // out[0..7] = kappa5, chi2_xy, chi2_rz, lambda, kappa_in, kappa_out, dir_x, dir_y.
 __device__ __forceinline__ bool t5_pass(const float4 *P, const ModInfo *M, float4 tin, float4 tout, float *out,
-                                        float d0) {
+                                        float d0, const float2 *__restrict__ cuts) {
   const float dkk = tin.x - tout.x;
   if (!(fabsf(dkk) <= tin.y + tout.y)) return false;
   if (!phiz_pass(P[0], P[2], P[4], M[0], M[2], M[4], d0)) return false;
@@ -380,7 +387,8 @@ __device__ __forceinline__ bool t5_pass(const float4 *P, const ModInfo *M, float
     const float r = v[i] - ((fa + fb * u[i]) + fc * q[i]);
     chi2xy = chi2xy + (w[i] * r) * r;
   }
-  if (!(chi2xy <= kXT5xy)) return false;
+  const float2 cut = cuts[t5_category(M)];
+  if (!(chi2xy <= cut.x)) return false;
   const float disc = (1.0f + fb * fb) - (4.0f * fa) * fc;
   if (!(disc > 0.0f)) return false;
   const float k5 = (2.0f * fc) / (L * sqrtf(disc));
@@ -406,7 +414,7 @@ __device__ __forceinline__ bool t5_pass(const float4 *P, const ModInfo *M, float
   }
   float lam;
   const float chi2rz = line_chi2<5>(s, z, w, &lam);
-  if (!(chi2rz <= kXT5rz)) return false;
+  if (!(chi2rz <= cut.y)) return false;
   const float nb = sqrtf(1.0f + fb * fb);
   const float cx = (ux - fb * uy) / nb, cy = (uy + fb * ux) / nb;
   out[0] = k5; out[1] = chi2xy; out[2] = chi2rz; out[3] = lam;

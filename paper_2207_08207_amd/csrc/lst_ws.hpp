@@ -29,6 +29,7 @@ struct DevGeom {
   int ext;            // 1: the chain ends with the track extensions
   float d0max;        // transverse impact-parameter bound of the selections [cm]
   int stub16;         // 1: MD stubs stored as binary16 pairs (dense half2), else float2
+  const float2 *t5cut;  // per quintuplet category (1024): chi2_xy and chi2_rz bounds
 };
 
 // One exclusive scan of the chain: out[0..n] = scan of in[0..n), n = *n_dev

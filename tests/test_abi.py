@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "lst.h")
 def declared():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lst_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(lst_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_header_declares_the_three_calls():
