@@ -71,6 +71,7 @@ def _lib(f64=False):
         lib.orc_round_half.argtypes = [ctypes.c_double]
         lib.orc_round_half.restype = ctypes.c_double
         lib.orc_geom_set_t5_cuts.argtypes = [vp, vp, vp]
+        lib.orc_geom_set_pt_plain.argtypes = [vp, ctypes.c_int]
         lib.orc_t5_cuts.argtypes = [vp, vp, vp]
         i32 = ctypes.c_int
         lib.orc_probe_md.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp]
@@ -118,6 +119,10 @@ class OracleGeometry:
         ar = None if rz is None else np.ascontiguousarray(np.broadcast_to(rz, (1024,)), np.float64)
         self.lib.orc_geom_set_t5_cuts(ctypes.c_void_p(self.handle), None if ax is None else _p(ax),
                                       None if ar is None else _p(ar))
+
+    def set_pt_plain(self, on=True):
+        """Seed search over every (seed, object) pair with no window pre-test (same results)."""
+        self.lib.orc_geom_set_pt_plain(ctypes.c_void_p(self.handle), 1 if on else 0)
 
     def t5_cuts(self):
         """(xy, rz): the quintuplet chi2 cuts in force, per category (1024 each)."""

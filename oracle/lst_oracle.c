@@ -104,6 +104,7 @@ typedef struct {
   double d0max;                 /* transverse impact-parameter bound of the selections [cm] */
   int stub16;                   /* MD stubs kept in binary16 (1) or in the working precision (0) */
   double t5xy[1024], t5rz[1024]; /* T5 chi2 cuts per quintuplet category */
+  int pt_plain;                 /* 1: the seed search tests every (seed, object) pair (no pre-test) */
 } orc_geom;
 
 /* Quintuplet chi2 cuts per category (Section 2.3 sets the quintuplet cuts
@@ -249,6 +250,11 @@ void orc_geom_set_t5_cuts(void *gp, const double *xy, const double *rz) {
   if (xy) memcpy(g->t5xy, xy, sizeof(g->t5xy));
   if (rz) memcpy(g->t5rz, rz, sizeof(g->t5rz));
 }
+/* Test switch: with on = 1 the seed search calls the full predicate on every
+ * (seed, object) pair instead of first skipping the pairs the widened window
+ * pre-test excludes (the results must not change; several times slower). */
+void orc_geom_set_pt_plain(void *gp, int on) { ((orc_geom *)gp)->pt_plain = on ? 1 : 0; }
+
 /* The quintuplet chi2 cuts in force (1024 each). */
 void orc_t5_cuts(void *gp, double *xy, double *rz) {
   orc_geom *g = (orc_geom *)gp;
@@ -994,7 +1000,7 @@ static void stage_pt(const orc_geom *g, orc_event *e, int five) {
     int h0 = e->hits4[4 * s];
     real x0 = e->x[h0], y0 = e->y[h0];
     for (int t = 0; t < nobj; ++t) {
-      {
+      if (!g->pt_plain) {
         real dx = fx[t] - x0, dy = fy[t] - y0;
         real u1 = dx * cx + dy * cy, v1 = dy * cx - dx * cy;
         real r1 = v1 - hk * (u1 * u1 + v1 * v1);
