@@ -171,7 +171,13 @@ lst_status lst_plan_release(lst_plan plan);
  * lst_server_destroy) has room for the batch's footprint.  Batches on
  * different streams overlap on the device; an event's objects stay resident
  * in the pool until its handle is released, which returns the memory.
- * Per event the results are identical to lst_build_event's.  Section 4.2.2's
+ * Per event the results are identical to lst_build_event's.  A request whose
+ * objects overflow their capacities is run again, ahead of the queue, with
+ * every capacity grown to 1.5 x the counts the overflowing run required (at
+ * most three reruns; its arrival time and so its latency are kept); it is
+ * reported LST_E_CAPACITY only after that, or LST_E_NOMEM when the grown
+ * event no longer fits the pool.  When idle the server thread sleeps until a
+ * submission, a released result or the next arrival.  Section 4.2.2's
  * multi-streaming is the paper's counterpart. */
 typedef struct {
   int32_t n_streams; /* batches in flight, 1..64 (1 with max_batch 1 = the plain FIFO path) */
@@ -192,6 +198,11 @@ lst_status lst_server_now(lst_server srv, double *t);
 /* Queues one event (device pointers valid until its result is released).
  * Errors: LST_E_INVALID (descriptor), LST_E_NOMEM (larger than the pool). */
 lst_status lst_server_submit(lst_server srv, const lst_event_desc *ev, int64_t id, double arrival_s);
+/* The same with the first attempt's capacities given (NULL: lst_default_capacity). */
+lst_status lst_server_submit_with_capacity(lst_server srv, const lst_event_desc *ev, const lst_capacity *cap,
+                                           int64_t id, double arrival_s);
+/* Requests run again after a capacity overflow since the server was created. */
+lst_status lst_server_reruns(lst_server srv, int64_t *n);
 /* Moves up to `max` completed results to `out` (*n of them). */
 lst_status lst_server_poll(lst_server srv, lst_server_result *out, int32_t max, int32_t *n);
 /* Requests not yet admitted, and completed results not yet polled. */
@@ -336,6 +347,39 @@ lst_status lst_get_launch_config(lst_geometry geom, int32_t n, int32_t *site_blo
 lst_status lst_set_launch_config(lst_geometry geom, int32_t n, const int32_t *site_block);
 lst_status lst_autotune(lst_geometry geom, int32_t B, const lst_event_desc *evs, const lst_capacity *cap,
                         void *workspace, size_t ws_bytes, void *stream, int32_t reps, float *site_ms);
+
+/* Tile choices of the chain, per geometry (applied to chains enqueued and
+ * plans created afterwards; results do not depend on them).  Tile i in
+ * [0, lst_tile_count()) is named by lst_tile_name(i):
+ *   md_cache, ls_cache, t3_cache, t5_cache: passing partners per parent that
+ *     the MD / segment / triplet / quintuplet count pass remembers (module,
+ *     MD, segment, triplet), so that its fill copies them instead of
+ *     searching again (a parent with more is searched again);
+ *   pt3_cache, pt5_cache: pT3 / pT5 per seed the seed-search count keeps with
+ *     their attributes (Section 2.4);
+ *   pass_list: passing objects of one seed ranked in on-chip memory by the
+ *     seed-search fill (a seed with more is filled by an ordered scan of all
+ *     objects);
+ *   max_slices: marked (ring, azimuth) bins of one seed gathered into one flat
+ *     candidate list (more: searched bin by bin);
+ *   ext_per_wave: track candidates per wavefront of the extension search
+ *     (4, 8 or 16).
+ * lst_tile_range gives tile i's bounds; lst_get/set_tile_config read and
+ * write all lst_tile_count() values at once (LST_E_INVALID and nothing changed
+ * if one is out of range).  lst_autotune_tiles times the whole chain over the
+ * caller's B events (as lst_autotune) for each candidate value of each tile
+ * in turn, keeps the fastest, and returns in tile_ms (optional,
+ * lst_tile_count() entries) the best chain time per tile (-1 for tiles not
+ * tuned: ext_per_wave without track extensions).  It waits for the device;
+ * on error the previous tiles are restored.  Not to be called while other
+ * calls use the same geometry. */
+int32_t lst_tile_count(void);
+const char *lst_tile_name(int32_t i);
+lst_status lst_tile_range(int32_t i, int32_t *lo, int32_t *hi);
+lst_status lst_get_tile_config(lst_geometry geom, int32_t n, int32_t *tiles);
+lst_status lst_set_tile_config(lst_geometry geom, int32_t n, const int32_t *tiles);
+lst_status lst_autotune_tiles(lst_geometry geom, int32_t B, const lst_event_desc *evs, const lst_capacity *cap,
+                              void *workspace, size_t ws_bytes, void *stream, int32_t reps, float *tile_ms);
 
 lst_status lst_release_event(lst_event ev);
 const char *lst_last_error(void);

@@ -32,7 +32,9 @@ EXPORTED = ["lst_load_geometry", "lst_release_geometry", "lst_default_capacity",
             "lst_server_destroy", "lst_get_launch_config", "lst_set_launch_config", "lst_autotune",
             "lst_set_track_extensions", "lst_get_extended_track_candidates", "lst_set_impact_bound",
             "lst_set_stub_precision", "lst_set_t5_cuts", "lst_get_t5_cuts",
-            "lst_get_default_t5_cuts"]
+            "lst_get_default_t5_cuts",
+            "lst_server_submit_with_capacity", "lst_server_reruns", "lst_tile_count", "lst_tile_name",
+            "lst_tile_range", "lst_get_tile_config", "lst_set_tile_config", "lst_autotune_tiles"]
 
 
 class LSTError(RuntimeError):
@@ -118,12 +120,19 @@ def load_library(path=LIB_PATH):
         "lst_server_create": [vp, P(lst_server_config), vp, sz, P(vp)],
         "lst_server_now": [vp, P(ctypes.c_double)],
         "lst_server_submit": [vp, P(lst_event_desc), ctypes.c_int64, ctypes.c_double],
+        "lst_server_submit_with_capacity": [vp, P(lst_event_desc), P(lst_capacity), ctypes.c_int64,
+                                            ctypes.c_double],
+        "lst_server_reruns": [vp, P(ctypes.c_int64)],
         "lst_server_poll": [vp, vp, i32, P(i32)],
         "lst_server_pending": [vp, P(i32), P(i32)],
         "lst_server_destroy": [vp],
         "lst_get_launch_config": [vp, i32, vp],
         "lst_set_launch_config": [vp, i32, vp],
         "lst_autotune": [vp, i32, vp, vp, vp, sz, vp, i32, vp],
+        "lst_autotune_tiles": [vp, i32, vp, vp, vp, sz, vp, i32, vp],
+        "lst_tile_range": [i32, P(i32), P(i32)],
+        "lst_get_tile_config": [vp, i32, vp],
+        "lst_set_tile_config": [vp, i32, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -135,6 +144,10 @@ def load_library(path=LIB_PATH):
     lib.lst_kernel_site_count.restype = ctypes.c_int32
     lib.lst_kernel_site_name.argtypes = [i32]
     lib.lst_kernel_site_name.restype = ctypes.c_char_p
+    lib.lst_tile_count.argtypes = []
+    lib.lst_tile_count.restype = ctypes.c_int32
+    lib.lst_tile_name.argtypes = [i32]
+    lib.lst_tile_name.restype = ctypes.c_char_p
     _lib = lib
     return lib
 
@@ -315,6 +328,29 @@ def lst_kernel_sites():
     return [lib.lst_kernel_site_name(i).decode() for i in range(lib.lst_kernel_site_count())]
 
 
+def lst_tiles():
+    """[(name, lo, hi)] of the chain's tiles, in the order of the tile arrays."""
+    lib = load_library()
+    out = []
+    for i in range(lib.lst_tile_count()):
+        lo, hi = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.lst_tile_range(i, ctypes.byref(lo), ctypes.byref(hi)))
+        out.append((lib.lst_tile_name(i).decode(), lo.value, hi.value))
+    return out
+
+
+def lst_get_tile_config(geom):
+    n = load_library().lst_tile_count()
+    a = np.zeros(n, np.int32)
+    _check(load_library().lst_get_tile_config(geom, n, _ptr(a)))
+    return a
+
+
+def lst_set_tile_config(geom, tiles):
+    a = np.ascontiguousarray(tiles, np.int32)
+    _check(load_library().lst_set_tile_config(geom, int(a.size), _ptr(a)))
+
+
 def lst_set_timed_site(site):
     _check(load_library().lst_set_timed_site(int(site)))
 
@@ -426,9 +462,19 @@ def lst_server_now(srv):
     return t.value
 
 
-def lst_server_submit(srv, dev_event, req_id, arrival_s):
+def lst_server_submit(srv, dev_event, req_id, arrival_s, cap=None):
     d = _event_desc(dev_event)
-    _check(load_library().lst_server_submit(srv, ctypes.byref(d), int(req_id), float(arrival_s)))
+    if cap is None:
+        _check(load_library().lst_server_submit(srv, ctypes.byref(d), int(req_id), float(arrival_s)))
+    else:
+        _check(load_library().lst_server_submit_with_capacity(srv, ctypes.byref(d), ctypes.byref(cap), int(req_id),
+                                                              float(arrival_s)))
+
+
+def lst_server_reruns(srv):
+    n = ctypes.c_int64()
+    _check(load_library().lst_server_reruns(srv, ctypes.byref(n)))
+    return int(n.value)
 
 
 def lst_server_poll(srv, max_results=4096):
@@ -508,15 +554,55 @@ class Geometry:
         names = lst_kernel_sites()
         return {names[k]: (b, float(ms[k])) for k, b in enumerate(lst_get_launch_config(self.handle)) if b}
 
+    def tile_config(self):
+        """{tile name: value} of the chain's tiles."""
+        return {n: int(v) for (n, _, _), v in zip(lst_tiles(), lst_get_tile_config(self.handle))}
+
+    def set_tile_config(self, cfg):
+        """Sets tiles from {tile name: value} (other tiles keep their values)."""
+        names = [n for n, _, _ in lst_tiles()]
+        unknown = set(cfg) - set(names)
+        if unknown:
+            raise LSTError(LST_E_INVALID, f"unknown tiles {sorted(unknown)}")
+        cur = self.tile_config()
+        cur.update({k: int(v) for k, v in cfg.items()})
+        lst_set_tile_config(self.handle, [cur[n] for n in names])
+
+    def autotune_tiles(self, dev_events, reps=2, caps=None, stream=None):
+        """Chooses the fastest value per tile (whole-chain time over these device events, one batch);
+        returns {tile: (value, ms)} of the tuned tiles."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        nh = [int(t["x"].numel()) for t in dev_events]
+        ns = [int(t["px"].numel()) for t in dev_events]
+        ws = torch.empty(lst_batch_workspace_bytes(self.handle, nh, ns, caps), dtype=torch.uint8,
+                         device=dev_events[0]["x"].device)
+        descs = (lst_event_desc * len(dev_events))(*[_event_desc(t) for t in dev_events])
+        lib = load_library()
+        ms = np.zeros(lib.lst_tile_count(), np.float32)
+        ca = _caps_array(caps)
+        _check(lib.lst_autotune_tiles(self.handle, len(dev_events), ctypes.cast(descs, ctypes.c_void_p),
+                                      ctypes.cast(ca, ctypes.c_void_p) if ca is not None else None, _ptr(ws),
+                                      int(ws.numel()), stream, int(reps), _ptr(ms)))
+        del ws
+        cfg = self.tile_config()
+        return {n: (cfg[n], float(m)) for (n, _, _), m in zip(lst_tiles(), ms) if m >= 0}
+
     def save_launch_config(self, path):
+        """Launch shapes and tiles to a JSON file ({site: threads per block, "tiles": {...}})."""
         import json
         with open(path, "w") as fh:
-            json.dump(self.launch_config(), fh, indent=1, sort_keys=True)
+            json.dump({**self.launch_config(), "tiles": self.tile_config()}, fh, indent=1, sort_keys=True)
 
     def load_launch_config(self, path):
         import json
         with open(path) as fh:
-            self.set_launch_config(json.load(fh))
+            cfg = json.load(fh)
+        tiles = cfg.pop("tiles", None)
+        self.set_launch_config(cfg)
+        if tiles:
+            self.set_tile_config(tiles)
 
     def close(self):
         if self.handle:
@@ -646,8 +732,12 @@ class Server:
     def now(self):
         return lst_server_now(self.handle)
 
-    def submit(self, dev_event, req_id, arrival_s=0.0):
-        lst_server_submit(self.handle, dev_event, req_id, arrival_s)
+    def submit(self, dev_event, req_id, arrival_s=0.0, cap=None):
+        lst_server_submit(self.handle, dev_event, req_id, arrival_s, cap)
+
+    def reruns(self):
+        """Requests run again after a capacity overflow."""
+        return lst_server_reruns(self.handle)
 
     def poll(self):
         return lst_server_poll(self.handle)

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <thread>
 #include <atomic>
+#include <condition_variable>
 #include <cstring>
 #include <new>
 #include <string>
@@ -330,6 +331,7 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   g->g.d0max = (float)kD0MaxDefault;
   g->g.stub16 = 0;
   g->g.t5cut = g->d_t5cut;
+  g->g.tiles = lst::kTilesDefault;
   *out = g;
   return LST_OK;
 }
@@ -1023,7 +1025,10 @@ struct SrvReq {
   lst_event_desc ev;
   double arrival;
   size_t region;  // footprint of the event's region in a batch workspace
+  lst::Caps caps;  // object capacities of the next attempt
+  int attempts;    // runs that overflowed a capacity so far
 };
+constexpr int kSrvMaxAttempts = 4;  // a request whose capacities grew this often is reported as failed
 
 struct SrvFlight {
   lst_batch_s *batch;
@@ -1053,9 +1058,11 @@ struct lst_server_s {
   std::map<lst_batch_s *, int> live;  // batches whose events are out with the client
   std::vector<SrvFlight> flights;     // scheduler thread only
   std::thread th;
+  std::condition_variable cv;  // wakes the idle scheduler: a submission, a released batch, stop
   std::atomic<bool> stop{false};
   std::chrono::steady_clock::time_point t0;
   int64_t n_batches = 0;
+  int64_t n_reruns = 0;  // requests run again after a capacity overflow
 };
 
 // caller holds s->mu
@@ -1086,9 +1093,30 @@ static void server_free_block(lst_server_s *s, size_t off) {
 
 // a server batch's last event was released: its workspace block returns to the pool
 static void server_release_batch(lst_server_s *s, lst_batch_s *b) {
-  std::lock_guard<std::mutex> lk(s->mu);
-  s->live.erase(b);
-  server_free_block_locked(s, b->block_off);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->live.erase(b);
+    server_free_block_locked(s, b->block_off);
+  }
+  s->cv.notify_one();  // pending requests may fit now
+}
+
+// Capacities of a rerun after an overflow: every stage at least 1.5 x its
+// required count (required counts are exact up to the stage that overflowed
+// and lower bounds after it), clamped to the device scans' limit.
+static lst::Caps grown_caps(const lst::Caps &c, const int *ctr) {
+  auto grow = [](int64_t cur, int req) {
+    const int64_t want = std::max<int64_t>(cur, (int64_t)req + req / 2 + 1024);
+    return std::min<int64_t>(want, kMaxCap);
+  };
+  lst::Caps g = c;
+  g.md = grow(c.md, ctr[lst::C_RMD]);
+  g.ls = grow(c.ls, ctr[lst::C_RLS]);
+  g.t3 = grow(c.t3, ctr[lst::C_RT3]);
+  g.t5 = grow(c.t5, ctr[lst::C_RT5]);
+  g.pt3 = grow(c.pt3, ctr[lst::C_RPT3]);
+  g.pt5 = grow(c.pt5, ctr[lst::C_RPT5]);
+  return g;
 }
 
 // first fit; caller holds s->mu; returns SIZE_MAX when nothing fits
@@ -1119,9 +1147,11 @@ static void server_loop(lst_server_s *s) {
       fl.batch->synced = true;
       std::vector<lst_event> evs(fl.reqs.size(), nullptr);
       make_events(fl.batch, (int)fl.reqs.size(), evs.data());
+      std::vector<lst_event> rerun_evs;
       {
         std::lock_guard<std::mutex> lk(s->mu);
         s->live[fl.batch] = 1;
+        std::vector<SrvReq> rerun;
         for (size_t i = 0; i < fl.reqs.size(); ++i) {
           lst_server_result r{};
           r.id = fl.reqs[i].id;
@@ -1129,13 +1159,32 @@ static void server_loop(lst_server_s *s) {
           r.arrival_s = fl.reqs[i].arrival;
           r.admit_s = fl.admit;
           r.done_s = t;
-          const int st = fl.batch->h_ctr[i * lst::C_COUNT + lst::C_STATUS];
+          const int *ctr = fl.batch->h_ctr + i * lst::C_COUNT;
+          const int st = ctr[lst::C_STATUS];
           r.status = fl.batch->failed ? LST_E_DEVICE
                      : (st & (lst::ST_BAD_HIT | lst::ST_BAD_SEED)) ? LST_E_INVALID
                      : (st & lst::ST_CAPACITY) ? LST_E_CAPACITY : LST_OK;
+          if (r.status == LST_E_CAPACITY && fl.reqs[i].attempts + 1 < kSrvMaxAttempts) {
+            // grow the capacities from the required counts and run the request again, ahead of
+            // the queue (its arrival time, hence its latency, is kept)
+            SrvReq q = fl.reqs[i];
+            q.caps = grown_caps(q.caps, ctr);
+            q.attempts += 1;
+            q.region = lst::workspace_layout(s->geom->g.n_mod, q.ev.n_hits, q.ev.n_seeds, q.caps, nullptr, nullptr,
+                                             nullptr);
+            if (q.region + header_bytes(1) <= s->pool_bytes) {
+              rerun.push_back(q);
+              rerun_evs.push_back(evs[i]);
+              ++s->n_reruns;
+              continue;
+            }
+            r.status = LST_E_NOMEM;  // the grown event no longer fits the pool
+          }
           s->results.push_back(r);
         }
+        for (auto it = rerun.rbegin(); it != rerun.rend(); ++it) s->pending.push_front(*it);
       }
+      for (lst_event e : rerun_evs) lst_release_event(e);  // may free the batch's block (takes s->mu)
       busy[fl.stream] = 0;
       s->flights.erase(s->flights.begin() + (long)f);
       worked = true;
@@ -1170,8 +1219,8 @@ static void server_loop(lst_server_s *s) {
         nh[i] = evs[i].n_hits;
         ns[i] = evs[i].n_seeds;
       }
-      std::vector<lst::Caps> caps;
-      resolve_caps((int)take.size(), nh.data(), ns.data(), nullptr, caps);
+      std::vector<lst::Caps> caps(take.size());
+      for (size_t i = 0; i < take.size(); ++i) caps[i] = take[i].caps;
       lst_batch_s *b = nullptr;
       enqueue_batch_at(s->geom, (int)take.size(), evs.data(), caps, s->pool + off, s->streams[si], &b);
       if (!b) {  // host allocation failure: report the requests as failed
@@ -1191,7 +1240,26 @@ static void server_loop(lst_server_s *s) {
       ++s->n_batches;
       worked = true;
     }
-    if (!worked) std::this_thread::yield();
+    if (!worked) {
+      if (!s->flights.empty()) {
+        std::this_thread::yield();  // batches in flight: poll their completion events
+        continue;
+      }
+      // idle: sleep until a submission, a released batch, stop, or the next arrival
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (s->stop.load()) continue;
+      double next = -1.0;
+      for (const auto &q : s->pending) next = next < 0 ? q.arrival : std::min(next, q.arrival);
+      const double now = secs_since(s->t0);
+      if (next < 0) {
+        s->cv.wait_for(lk, std::chrono::milliseconds(50));
+      } else if (next > now) {
+        s->cv.wait_for(lk, std::chrono::duration<double>(std::min(next - now, 0.05)));
+      } else if (!s->live.empty()) {
+        // arrived requests waiting for pool memory held by results the client still has
+        s->cv.wait_for(lk, std::chrono::milliseconds(1));
+      }
+    }
   }
 }
 
@@ -1237,18 +1305,33 @@ lst_status lst_server_now(lst_server s, double *t) {
   return LST_OK;
 }
 
-lst_status lst_server_submit(lst_server s, const lst_event_desc *ev, int64_t id, double arrival_s) {
+lst_status lst_server_submit_with_capacity(lst_server s, const lst_event_desc *ev, const lst_capacity *cap,
+                                           int64_t id, double arrival_s) {
   if (!s || !ev) return fail(LST_E_INVALID, "lst_server_submit: NULL argument");
   lst_status st = check_event_desc(*ev);
   if (st != LST_OK) return st;
   std::vector<lst::Caps> caps;
-  st = resolve_caps(1, &ev->n_hits, &ev->n_seeds, nullptr, caps);
+  st = resolve_caps(1, &ev->n_hits, &ev->n_seeds, cap, caps);
   if (st != LST_OK) return st;
   const size_t region = lst::workspace_layout(s->geom->g.n_mod, ev->n_hits, ev->n_seeds, caps[0], nullptr, nullptr,
                                               nullptr);
   if (region + header_bytes(1) > s->pool_bytes) return fail(LST_E_NOMEM, "event larger than the server's pool");
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->pending.push_back(SrvReq{id, *ev, arrival_s, region, caps[0], 0});
+  }
+  s->cv.notify_one();
+  return LST_OK;
+}
+
+lst_status lst_server_submit(lst_server s, const lst_event_desc *ev, int64_t id, double arrival_s) {
+  return lst_server_submit_with_capacity(s, ev, nullptr, id, arrival_s);
+}
+
+lst_status lst_server_reruns(lst_server s, int64_t *n) {
+  if (!s || !n) return fail(LST_E_INVALID, "lst_server_reruns: NULL argument");
   std::lock_guard<std::mutex> lk(s->mu);
-  s->pending.push_back(SrvReq{id, *ev, arrival_s, region});
+  *n = s->n_reruns;
   return LST_OK;
 }
 
@@ -1273,6 +1356,7 @@ lst_status lst_server_pending(lst_server s, int32_t *queued, int32_t *ready) {
 lst_status lst_server_destroy(lst_server s) {
   if (!s) return LST_OK;
   s->stop.store(true);
+  s->cv.notify_all();
   if (s->th.joinable()) s->th.join();  // returns once in-flight batches completed
   std::vector<lst_server_result> left;
   {
@@ -1378,6 +1462,132 @@ lst_status lst_autotune(lst_geometry g, int32_t B, const lst_event_desc *evs, co
     }
     g->site_block[site] = best_b;
     if (site_ms) site_ms[site] = best;
+  }
+  return LST_OK;
+}
+
+// ------------------------------------------------------------------ tiles
+namespace {
+struct TileSpec {
+  const char *name;
+  int lo, hi;
+  int choices[4];  // autotuner candidates, 0-terminated (0 may also be a choice: listed first)
+  int n_choices;
+};
+const TileSpec kTileSpecs[] = {
+    {"md_cache", 0, lst::kMdCache, {0, 16, lst::kMdCache}, 3},
+    {"ls_cache", 0, lst::kLsCache, {4, 8, lst::kLsCache}, 3},
+    {"t3_cache", 0, lst::kT3Cache, {0, 1, 2}, 3},
+    {"t5_cache", 0, lst::kT5Cache, {0, 1, 2}, 3},
+    {"pt3_cache", 0, lst::kPt3Cache, {64, 128, lst::kPt3Cache}, 3},
+    {"pt5_cache", 0, lst::kPt5Cache, {4, 8, lst::kPt5Cache}, 3},
+    {"pass_list", 1, lst::kPassList, {256, lst::kPassList}, 2},
+    {"max_slices", 1, lst::kMaxSlices, {128, lst::kMaxSlices}, 2},
+    {"ext_per_wave", 4, 16, {4, 8, 16}, 3},
+};
+constexpr int kNumTiles = (int)(sizeof(kTileSpecs) / sizeof(kTileSpecs[0]));
+int *tile_field(lst::Tiles &t, int i) {
+  int *f[kNumTiles] = {&t.md_cache, &t.ls_cache, &t.t3_cache, &t.t5_cache, &t.pt3_cache,
+                       &t.pt5_cache, &t.pass_list, &t.max_slices, &t.ext_per_wave};
+  return f[i];
+}
+bool tile_ok(int i, int v) {
+  if (v < kTileSpecs[i].lo || v > kTileSpecs[i].hi) return false;
+  return i != 8 || v == 4 || v == 8 || v == 16;  // the extension search is built for these
+}
+}  // namespace
+
+int32_t lst_tile_count(void) { return kNumTiles; }
+
+const char *lst_tile_name(int32_t i) { return (i >= 0 && i < kNumTiles) ? kTileSpecs[i].name : nullptr; }
+
+lst_status lst_tile_range(int32_t i, int32_t *lo, int32_t *hi) {
+  if (i < 0 || i >= kNumTiles || !lo || !hi) return fail(LST_E_INVALID, "lst_tile_range: bad argument");
+  *lo = kTileSpecs[i].lo;
+  *hi = kTileSpecs[i].hi;
+  return LST_OK;
+}
+
+lst_status lst_get_tile_config(lst_geometry g, int32_t n, int32_t *tiles) {
+  if (!g || !tiles || n != kNumTiles) return fail(LST_E_INVALID, "lst_get_tile_config: bad argument");
+  for (int i = 0; i < kNumTiles; ++i) tiles[i] = *tile_field(g->g.tiles, i);
+  return LST_OK;
+}
+
+lst_status lst_set_tile_config(lst_geometry g, int32_t n, const int32_t *tiles) {
+  if (!g || !tiles || n != kNumTiles) return fail(LST_E_INVALID, "lst_set_tile_config: bad argument");
+  for (int i = 0; i < kNumTiles; ++i)
+    if (!tile_ok(i, tiles[i])) {
+      char msg[160];
+      snprintf(msg, sizeof(msg), "lst_set_tile_config: %s = %d outside [%d, %d]%s", kTileSpecs[i].name, tiles[i],
+               kTileSpecs[i].lo, kTileSpecs[i].hi, i == 8 ? " or not 4, 8, 16" : "");
+      return fail(LST_E_INVALID, msg);
+    }
+  for (int i = 0; i < kNumTiles; ++i) *tile_field(g->g.tiles, i) = tiles[i];
+  return LST_OK;
+}
+
+lst_status lst_autotune_tiles(lst_geometry g, int32_t B, const lst_event_desc *evs, const lst_capacity *cap,
+                              void *workspace, size_t ws_bytes, void *stream, int32_t reps, float *tile_ms) {
+  if (!g || !evs || !workspace || B < 1 || B > 65535 || reps < 1 || reps > 100)
+    return fail(LST_E_INVALID, "lst_autotune_tiles: bad argument");
+  std::vector<int32_t> nh(B), ns(B);
+  for (int i = 0; i < B; ++i) {
+    lst_status s = check_event_desc(evs[i]);
+    if (s != LST_OK) return s;
+    nh[i] = evs[i].n_hits;
+    ns[i] = evs[i].n_seeds;
+  }
+  std::vector<lst::Caps> caps;
+  lst_status s = resolve_caps(B, nh.data(), ns.data(), cap, caps);
+  if (s != LST_OK) return s;
+  if (ws_bytes < batch_bytes(g->g.n_mod, B, nh.data(), ns.data(), caps))
+    return fail(LST_E_NOMEM, "lst_autotune_tiles: workspace too small (see lst_batch_workspace_bytes)");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return fail(LST_E_INVALID, "workspace not 256-byte aligned");
+  const lst::Tiles saved = g->g.tiles;
+  // one timed batch with the current tiles: the whole chain's time, or an error
+  auto time_chain = [&](float *ms) -> lst_status {
+    lst_batch_s *b = nullptr;
+    lst_status es = enqueue_batch_at(g, B, evs, caps, reinterpret_cast<char *>(workspace),
+                                     reinterpret_cast<hipStream_t>(stream), &b, lst::kChainSite);
+    if (!b) return es;
+    lst_status rs = es;
+    if (rs == LST_OK) {
+      hipError_t e = hipEventSynchronize(b->done);
+      if (e == hipSuccess) {
+        b->synced = true;
+        e = (b->tbeg && b->tend) ? hipEventElapsedTime(ms, b->tbeg, b->tend) : hipErrorInvalidValue;
+      }
+      if (e != hipSuccess) rs = fail(LST_E_DEVICE, std::string("lst_autotune_tiles: ") + hipGetErrorString(e));
+      for (int i = 0; i < B && rs == LST_OK; ++i) rs = map_status(b->h_ctr[(size_t)i * lst::C_COUNT + lst::C_STATUS]);
+    }
+    for (int i = 0; i < B; ++i) release_batch_ref(b);
+    return rs;
+  };
+  for (int t = 0; t < kNumTiles; ++t) {
+    if (tile_ms) tile_ms[t] = -1.0f;
+    if (t == 8 && !g->g.ext) continue;  // the extension search runs only with extensions on
+    float best = 3.0e38f;
+    int best_v = *tile_field(g->g.tiles, t);
+    for (int c = 0; c < kTileSpecs[t].n_choices; ++c) {
+      *tile_field(g->g.tiles, t) = kTileSpecs[t].choices[c];
+      float tmin = 3.0e38f;
+      for (int r = 0; r < reps; ++r) {
+        float ms = 0.0f;
+        lst_status ts = time_chain(&ms);
+        if (ts != LST_OK) {
+          g->g.tiles = saved;
+          return ts;
+        }
+        tmin = std::min(tmin, ms);
+      }
+      if (tmin < best) {
+        best = tmin;
+        best_v = kTileSpecs[t].choices[c];
+      }
+    }
+    *tile_field(g->g.tiles, t) = best_v;
+    if (tile_ms) tile_ms[t] = best;
   }
   return LST_OK;
 }

@@ -288,7 +288,8 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
     const int np = (int)npair;  // <= kMdBig here
     const int n_md = FILL ? w.md_off[m + 1] - base : 0;
     int *cache = w.md_cache + (long)kMdCache * m;
-    if (FILL && n_md <= kMdCache) {
+    const int md_keep = g.tiles.md_cache;
+    if (FILL && n_md <= md_keep) {
       // the count pass kept this module's passing pairs (row-major order): copy them
       if (lane < n_md) {
         const int pk = cache[lane];
@@ -304,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
         }
       }
     }
-    for (int p0 = 0; p0 < np && !(FILL && n_md <= kMdCache); p0 += 64) {
+    for (int p0 = 0; p0 < np && !(FILL && n_md <= md_keep); p0 += 64) {
       const int p = p0 + lane;
       bool pass = false;
       int i = 0, j = 0;
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
       }
       if (!FILL && pass) {
         const int r = base + lanes_below(bm);
-        if (r < kMdCache) cache[r] = (i << 16) | j;
+        if (r < md_keep) cache[r] = (i << 16) | j;
       }
       base += __popcll(bm);
     }
@@ -551,7 +552,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
           w.ls_md[pos] = make_int2(a, b);
           w.ls_beta[pos] = beta;
         }
-      } else if (pass && cnt + pre < kLsCache) {
+      } else if (pass && cnt + pre < g.tiles.ls_cache) {
         w.ls_cache[(long)a * kLsCache + cnt + pre] = b;
       }
       out += __popcll(m);
@@ -604,7 +605,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     if (nq > 0) select(nq);
     if (!FILL && lane == 0) {
       w.ls_cnt[a] = cnt;
-      w.ls_ovf_flag[a] = cnt > kLsCache ? 1 : 0;
+      w.ls_ovf_flag[a] = cnt > g.tiles.ls_cache ? 1 : 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -647,13 +648,13 @@ __device__ __forceinline__ int wave_segments(int n, int *seg) {
 
 // Segments of the MDs whose partners the count pass cached: one thread per
 // (MD, cache slot), in candidate order, with the angles ls_pass reports.
-__global__ void k_ls_copy(const Ws *__restrict__ wb) {
+__global__ void k_ls_copy(const Ws *__restrict__ wb, int keep) {
   const Ws &w = wb[blockIdx.y];
   const long n = (long)w.ctr[C_NMD] * kLsCache;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const int a = (int)(i / kLsCache), k = (int)(i % kLsCache);
     const int cnt = w.ls_cnt[a];
-    if (cnt > kLsCache) {
+    if (cnt > keep) {
       if (k == 0) w.ls_ovf[w.ls_ovf_off[a]] = a;  // searched again by k_ls<true>
       continue;
     }
@@ -690,7 +691,7 @@ __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeo
       n = hi > lo ? hi - lo : 0;
       if (FILL) {
         const int cnt = w.t3_cnt[l1];
-        if (cnt <= kT3Cache) {  // the count pass kept them all: only those are tested again
+        if (cnt <= g.tiles.t3_cache) {  // the count pass kept them all: only those are tested again
           n = cnt;
           cached = 1;
         }
@@ -719,7 +720,7 @@ __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeo
       const unsigned long long m = __ballot(pass);
       if (!FILL && pass) {
         const int r = pair_rank(m, first, before);
-        if (r < kT3Cache) w.t3_cache[(long)((int)p0 + e) * kT3Cache + r] = cand;
+        if (r < g.tiles.t3_cache) w.t3_cache[(long)((int)p0 + e) * kT3Cache + r] = cand;
       }
       if (FILL && pass) {
         const int pos = w.t3_off[(int)p0 + e] + pair_rank(m, first, before);
@@ -771,7 +772,7 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
       n = hi > lo ? hi - lo : 0;
       if (FILL) {
         const int cnt = w.t5_cnt[t1];
-        if (cnt <= kT5Cache) {  // the count pass kept them all: only those are tested again
+        if (cnt <= g.tiles.t5_cache) {  // the count pass kept them all: only those are tested again
           n = cnt;
           cached = 1;
         }
@@ -808,7 +809,7 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
       const unsigned long long m = __ballot(pass);
       if (!FILL && pass) {
         const int r = pair_rank(m, first, before);
-        if (r < kT5Cache) w.t5_cache[(long)((int)p0 + e) * kT5Cache + r] = t2;
+        if (r < g.tiles.t5_cache) w.t5_cache[(long)((int)p0 + e) * kT5Cache + r] = t2;
       }
       if (FILL && pass) {
         const int t1e = (int)p0 + e;
@@ -1049,8 +1050,6 @@ static_assert(kObjBins * kZBins == kSeedBins, "seed-search bin count");
 constexpr int kMaskWords = kObjBins / 32;
 constexpr float kSampleStep = 2.0f;                  // trajectory sampling step [cm]
 constexpr int kMaxSamples = 112;                     // 224 cm of arc
-constexpr int kPassList = 1024;                      // passing objects sorted per seed in LDS
-constexpr int kMaxSlices = 512;                      // marked bins per seed gathered in LDS (else: bin by bin)
 
 __device__ __forceinline__ int ring_of(float r) {
   const int k = (int)floorf((r - kRing0) / kRingW);
@@ -1183,8 +1182,11 @@ __device__ __forceinline__ int2 seed_zbins(const Seed &sd, float lo, float hi) {
 // One wave per seed over the objects of the bins its trajectory can reach.
 // COUNT: number of passing objects.  FILL: passing object indices gathered in
 // LDS, ranked by object index, written at the seed's offset in object order
-// (the order of the full scan); a seed with more than kPassList passing
-// objects is filled by an ordered scan over all objects instead.
+// (the order of the full scan); a seed with more passing objects than the
+// list holds (tile pass_list <= kPassList) is filled by an ordered scan over
+// all objects instead.  The count pass keeps up to pt3_cache / pt5_cache
+// passing objects per seed with their attributes, which the fill then ranks
+// and copies; more than max_slices marked bins are searched bin by bin.
 template <int K, bool FILL, bool BOTH = false>
 __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb, DevGeom g) {
   __shared__ unsigned s_mask[kWaves][kMaskWords];
@@ -1201,13 +1203,16 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   const Seed sd = load_seed(w, s);
   constexpr int kCache = K == 3 ? kPt3Cache : kPt5Cache;
   static_assert(kCache <= kPassList, "the fill ranks the cache in its LDS list");
+  const int keep = K == 3 ? g.tiles.pt3_cache : g.tiles.pt5_cache;  // <= kCache
+  const int pass_list = g.tiles.pass_list;                            // <= kPassList
+  const int max_slices = g.tiles.max_slices;                          // <= kMaxSlices
   int *cache = (K == 3 ? w.pt3_cache : w.pt5_cache) + (long)s * kCache;
   float4 *cattr = (K == 3 ? w.pt3_cattr : w.pt5_cattr) + (long)s * kCache;
   if constexpr (FILL) {
     // the count pass cached every passing object of this seed with its attributes:
     // rank them by object index (in LDS) and copy, no search
     const int expect = (K == 3 ? w.pt3_cnt : w.pt5_cnt)[s];
-    if (expect <= kCache) {
+    if (expect <= keep) {
       for (int i = lane; i < expect; i += 64) s_list[wv][i] = cache[i];
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -1243,6 +1248,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   auto search = [&](auto kind) {
     constexpr int KO = decltype(kind)::value;
     constexpr int kCacheO = KO == 3 ? kPt3Cache : kPt5Cache;
+    const int keepO = KO == 3 ? g.tiles.pt3_cache : g.tiles.pt5_cache;
     int *cache = (KO == 3 ? w.pt3_cache : w.pt5_cache) + (long)s * kCacheO;
     float4 *cattr = (KO == 3 ? w.pt3_cattr : w.pt5_cattr) + (long)s * kCacheO;
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1254,7 +1260,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
     int base = FILL ? (KO == 3 ? w.pt3_off : w.pt5_off)[s] : 0;
     const int expect = FILL ? (KO == 3 ? w.pt3_cnt : w.pt5_cnt)[s] : 0;
     const int cap = KO == 3 ? w.cap_pt3 : w.cap_pt5;
-    const bool listed = !FILL || expect <= kPassList;
+    const bool listed = !FILL || expect <= pass_list;
     const float4 *bpos = KO == 3 ? w.b3_pos : w.b5_pos;
     // the full selection on the first n (<= 64) queued objects; passing ones are counted
     // in ballot order and remembered (count: the cache; fill: the LDS list)
@@ -1275,7 +1281,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
         const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
         if (FILL) {
           if (n_pass + pre < kPassList) s_list[wv][n_pass + pre] = t;
-        } else if (n_pass + pre < kCacheO) {
+        } else if (n_pass + pre < keepO) {
           cache[n_pass + pre] = t;
           cattr[n_pass + pre] = attr;
         }
@@ -1328,13 +1334,13 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
           if (lane >= o) x += y;
         }
         const int tot = __shfl(x, 63, 64);
-        if (n_bits + tot <= kMaxSlices) {
+        if (n_bits + tot <= max_slices) {
           int k = n_bits + x - pc;
           for (unsigned bb = bits; bb; bb &= bb - 1u) s_sl_j0[wv][k++] = (w0 + lane) * 32 + __builtin_ctz(bb);
         }
         n_bits += tot;
       }
-      flat = n_bits <= kMaxSlices;
+      flat = n_bits <= max_slices;
       if (flat) {
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -1843,13 +1849,13 @@ __device__ __forceinline__ bool ext_eval(const Ws &w, const DevGeom &g, const fl
   return phiz_pass(P[0], PK, A1, M[0], MK, I1, g.d0max) && ext_fit(P, M, K + add, a);
 }
 
-// Candidates per wave: few enough that their (candidate, triplet) pairs
-// (about 1.3 per candidate) spread over many waves.
-constexpr int kExtPerWave = 8;
-
+// Candidates per wave, C (tile ext_per_wave: 4, 8 or 16): few enough that
+// their (candidate, triplet) pairs (about 1.3 per candidate) spread over many
+// waves.
+template <int C>
 __global__ __launch_bounds__(kBlock) void k_tc_ext(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
-  constexpr int C = kExtPerWave;
+  constexpr int kExtPerWave = C;
   __shared__ float4 s_P[kWaves][5][C];  // the candidates' anchors
   __shared__ int s_M[kWaves][5][C], s_md[kWaves][C], s_k[kWaves][C], s_lo2[kWaves][C], s_n2[kWaves][C],
       s_lo1[kWaves][C];  // module info bits, last MD, MD count, triplet ranges
@@ -2047,6 +2053,8 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   // one wave per seed, every seed its own wave (the seed search does not stride)
   auto seedwaves = [&] { return dim3((unsigned)((S + tb / 64 - 1) / (tb / 64) > 0 ? (S + tb / 64 - 1) / (tb / 64) : 1), B); };
   const dim3 one(1, B);
+  const bool whole = kt && kt->site == kChainSite;  // the timer brackets the whole chain
+  if (whole) (void)hipEventRecord(kt->beg, st);
   // a0: buckets
   run([&] { k_clear<<<grid(2L * M + 1), kBlock, 0, st>>>(wb, FL_CTR, FL_BCUR + 1); });
   run([&] { k_hits_count<<<grid(N > S ? N : S), kBlock, 0, st>>>(wb, M); });
@@ -2068,7 +2076,7 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { scan(wb, B, SC_LS, b.cap_md, st); });
   run([&] {
     scan(wb, B, SC_LSOVF, b.cap_md, st);
-    k_ls_copy<<<gridt((long)b.cap_md * kLsCache), tb, 0, st>>>(wb);
+    k_ls_copy<<<gridt((long)b.cap_md * kLsCache), tb, 0, st>>>(wb, g.tiles.ls_cache);
     k_ls<true><<<gridwt(b.cap_md < 16384 ? b.cap_md : 16384), tb, 0, st>>>(wb, g);  // the overflow MDs
   });
   // a3: T3
@@ -2151,9 +2159,16 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { if (seeds) scan(wb, B, SC_FPLS, S, st); });
   run([&] { k_tc_write<<<grid(b.cap_tc), kBlock, 0, st>>>(wb); });
   // track extensions (when the geometry enables them)
-  run([&] { if (g.ext) k_tc_ext<<<gridwt((b.cap_tc + kExtPerWave - 1) / kExtPerWave), tb, 0, st>>>(wb, g); });
+  run([&] {
+    if (!g.ext) return;
+    const int c = g.tiles.ext_per_wave;
+    if (c == 4) k_tc_ext<4><<<gridwt((b.cap_tc + 3) / 4), tb, 0, st>>>(wb, g);
+    else if (c == 16) k_tc_ext<16><<<gridwt((b.cap_tc + 15) / 16), tb, 0, st>>>(wb, g);
+    else k_tc_ext<8><<<gridwt((b.cap_tc + 7) / 8), tb, 0, st>>>(wb, g);
+  });
   run([&] { if (g.ext) scan(wb, B, SC_EXT, b.cap_tc, st); });
   run([&] { if (g.ext) k_tc_ext_write<<<grid(b.cap_tc), kBlock, 0, st>>>(wb); });
+  if (whole) (void)hipEventRecord(kt->end, st);
 }
 
 }  // namespace lst

@@ -21,6 +21,24 @@ enum Ctr : int {
 };
 enum : int { ST_BAD_HIT = 1, ST_BAD_SEED = 2, ST_CAPACITY = 4 };
 
+// Tile choices of the chain, set per geometry at run time (lst_set_tile_config,
+// lst_autotune): how many passing partners a count pass remembers per parent
+// (its fill copies them instead of searching again), the seed search's LDS
+// list and slice table, and the candidates per wave of the extension search.
+// Storage and LDS arrays are sized for the maxima (the kXxx constants below);
+// results never depend on the choice.
+struct Tiles {
+  int md_cache;      // MDs per module whose (lower, upper) pair the MD count pass keeps, 0..kMdCache
+  int ls_cache;      // segments per MD the segment count pass keeps, 0..kLsCache
+  int t3_cache;      // triplets per segment the triplet count pass keeps, 0..kT3Cache
+  int t5_cache;      // quintuplets per triplet the quintuplet count pass keeps, 0..kT5Cache
+  int pt3_cache;     // pT3 per seed the seed-search count keeps with attributes, 0..kPt3Cache
+  int pt5_cache;     // pT5 per seed, 0..kPt5Cache
+  int pass_list;     // passing objects per seed ranked in LDS by the fill, 1..kPassList (else: ordered scan)
+  int max_slices;    // marked bins per seed gathered into one flat list, 1..kMaxSlices (else: bin by bin)
+  int ext_per_wave;  // track candidates per wave of the extension search: 4, 8 or 16
+};
+
 struct DevGeom {
   int n_mod, n_edges;
   const int *map_off, *map_tgt;
@@ -30,6 +48,7 @@ struct DevGeom {
   float d0max;        // transverse impact-parameter bound of the selections [cm]
   int stub16;         // 1: MD stubs stored as binary16 pairs (dense half2), else float2
   const float2 *t5cut;  // per quintuplet category (1024): chi2_xy and chi2_rz bounds
+  Tiles tiles;
 };
 
 // One exclusive scan of the chain: out[0..n] = scan of in[0..n), n = *n_dev
@@ -66,6 +85,10 @@ constexpr int kT3Cache = 2;   // triplets per parent segment whose candidate the
 constexpr int kT5Cache = 2;   // quintuplets per parent triplet whose candidate the T5 count pass keeps
 constexpr int kPt3Cache = 256;  // pT3 per seed (PU200 maximum ~190)
 constexpr int kPt5Cache = 16;   // pT5 per seed
+constexpr int kPassList = 1024;  // passing objects of one seed ranked in LDS by the seed-search fill
+constexpr int kMaxSlices = 512;  // marked bins of one seed gathered into a flat list in LDS
+constexpr int kExtPerWaveMax = 16;
+constexpr Tiles kTilesDefault{kMdCache, kLsCache, kT3Cache, kT5Cache, kPt3Cache, kPt5Cache, kPassList, kMaxSlices, 8};
 
 // First-anchor bins of the seed search: 10 radius rings x 256 azimuth bins x
 // 55 z bins (10 cm over |z| < 275 cm); bins of one (ring, azimuth) pair are
@@ -169,6 +192,7 @@ struct KernelTimer {
   int site;
   hipEvent_t beg, end;
 };
+constexpr int kChainSite = 1000;  // KernelTimer::site that brackets the whole chain
 extern const char *const kSiteNames[];
 extern const int kNumSites;
 constexpr int kMaxSites = 64;

@@ -84,12 +84,15 @@ def test_parity_pu200_seeded_full_event(lst, gfull, ofull):
 # Many full-size events: the oracle runs them in parallel processes once per module.
 MANY = [("pu200_seeded", k) for k in range(1, 21)] + [("pu200", k) for k in range(2, 22)]
 BATCH = [("batch", k) for k in range(8)]
+PLAN64 = [("batch", k) for k in range(64)]      # the benchmark's 64-slot plan
+SERVE = [("serve", k) for k in range(8)]        # pile-up U[50, 250], the serving workload
 
 
 @pytest.fixture(scope="module")
 def many_oracle():
-    print(f"[cpu] oracle on {len(MANY) + len(BATCH)} full-size events in parallel", flush=True)
-    return dict(zip(MANY + BATCH, oracle_many(MANY + BATCH)))
+    specs = MANY + [s for s in PLAN64 if s not in MANY] + SERVE
+    print(f"[cpu] oracle on {len(specs)} full-size events in parallel", flush=True)
+    return dict(zip(specs, oracle_many(specs)))
 
 
 @pytest.mark.parametrize("spec", MANY, ids=[f"{c}-{k}" for c, k in MANY])
@@ -243,6 +246,58 @@ def test_parity_batch_plan_events(lst, gfull, many_oracle):
         compare_tc(r, o)
         r.close()
     plan.close()
+
+
+def test_parity_batch_plan_64_slots(lst, full, many_oracle):
+    """The benchmark's batched form: 64 pile-up U[140, 250] events in one captured plan with the
+    packaged MI355X launch shapes, every event against the oracle, on two replays."""
+    import os
+    g = lst.Geometry(full)
+    shapes = os.path.join(os.path.dirname(lst.__file__), "launch_shapes_mi355x.json")
+    g.load_launch_config(shapes)
+    evs = [many_oracle[s][0] for s in PLAN64]
+    dev = [lst.upload_event(e) for e in evs]
+    print(f"[gpu] plan of 64 batch events: hits {min(e.n_hits for e in evs)}..{max(e.n_hits for e in evs)}",
+          flush=True)
+    plan = lst.Plan(g, len(evs), max(e.n_hits for e in evs), max(e.n_seeds for e in evs))
+    for rep in range(2):
+        for r, s in zip(plan.run(dev), PLAN64):
+            o = many_oracle[s][1]
+            compare_event(r, o)
+            compare_tc(r, o)
+            r.close()
+    plan.close()
+
+
+@pytest.mark.parametrize("spec", SERVE, ids=[f"{c}-{k}" for c, k in SERVE])
+def test_parity_serve_events(spec, lst, gfull, many_oracle):
+    """The serving workload's events (pile-up U[50, 250]) on the default geometry, every stage."""
+    ev, o = many_oracle[spec]
+    r = _run(lst, gfull, ev)
+    compare_event(r, o)
+    assert compare_tc(r, o) > 100
+
+
+def test_parity_dense_seed_search(lst, gbarrel, obarrel, barrel):
+    """Dense seeded fixtures: seeds with 256-1,024 and more than 1,024 passing triplets and with more
+    than 16 pT5, i.e. the seed search's re-search past its per-seed caches and its ordered scan past
+    the LDS list, object by object against the oracle."""
+    from dense import dense_event, spread_event
+    for ev in (dense_event(barrel), spread_event(barrel)):
+        r = _run(lst, gbarrel, ev)
+        o = oracle.run(obarrel, ev)
+        compare_event(r, o)
+        compare_tc(r, o)
+        t3, _, _ = r.stage(oracle.ST_PT3)
+        t5, _, _ = r.stage(oracle.ST_PT5)
+        n3 = np.bincount(t3[:, 0], minlength=ev.n_seeds)
+        n5 = np.bincount(t5[:, 0], minlength=ev.n_seeds)
+        print(f"[gpu] {ev.name}: pT3 per seed {n3.tolist()}, pT5 per seed {n5.tolist()}", flush=True)
+        if ev.name == "dense":
+            assert n3.max() > 1024 and ((n3 > 256) & (n3 <= 1024)).any()
+        else:
+            assert n5.max() > 16 and n3.max() > 1024
+        r.close()
 
 
 def test_parity_pu200_unseeded(lst, gfull, ofull):
@@ -403,6 +458,34 @@ def test_served_mix_equals_alone(lst, gfull):
         srv.drain(len(order), take)
         srv.close()
         assert [got[i] for i in range(len(order))] == [alone[k] for k in order]
+
+
+def test_server_reruns_capacity_overflow(lst, gfull):
+    """A request whose first capacities are far too small is run again by the server with grown
+    capacities; its result equals the plain path's, and the requests batched with it are unaffected."""
+    evs = [make_event("serve", k) for k in (1, 2, 3)]
+    dev = [lst.upload_event(e) for e in evs]
+    alone = [_tc_tuple(lst.run_event(gfull, d)) for d in dev]
+    one = max(lst.lst_workspace_bytes(gfull.handle, e.n_hits, e.n_seeds) for e in evs)
+    srv = lst.Server(gfull, 2, 3, 6 * one)
+    small = lst.lst_default_capacity(evs[1].n_hits, evs[1].n_seeds)
+    small.ls, small.t3 = 1000, 1000          # far below the event's segments and triplets
+    t0 = srv.now()
+    srv.submit(dev[0], 0, t0)
+    srv.submit(dev[1], 1, t0, cap=small)
+    srv.submit(dev[2], 2, t0)
+    got = {}
+
+    def take(r):
+        assert r["status"] == lst.LST_OK, r
+        res = lst.EventResult(r["event"], None, lst.LST_OK)
+        got[r["id"]] = _tc_tuple(res)
+        res.close()
+
+    srv.drain(3, take)
+    assert srv.reruns() >= 1
+    srv.close()
+    assert [got[i] for i in range(3)] == alone
 
 
 def test_server_with_extensions_and_displaced_bound(lst, full, gfull_ext, many_oracle):

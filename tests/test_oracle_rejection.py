@@ -1060,3 +1060,15 @@ def test_seed_search_pretest_drops_nothing(barrel, full):
         for x, y in zip(ra.tc(), rb.tc()):
             assert np.array_equal(x, y)
     assert n_pt > 1000
+
+
+def test_dense_fixtures_reach_the_seed_search_regimes(barrel, obarrel):
+    """The dense fixtures (tests/dense.py) hold seeds with 256-1,024 and more than 1,024 compatible
+    triplets, and a seed with more than 16 pT5 (the per-seed caches and list of the HIP seed search);
+    the oracle's counts, which the GPU parity test then compares object by object."""
+    from dense import dense_event, spread_event
+    r = oracle.run(obarrel, dense_event(barrel))
+    n3 = np.bincount(r.stage(oracle.ST_PT3)[0][:, 0], minlength=3)
+    assert n3[0] > 1024 and 256 < n3[1] <= 1024
+    r = oracle.run(obarrel, spread_event(barrel))
+    assert r.count(oracle.ST_PT5) > 16 and r.count(oracle.ST_PT3) > 1024
