@@ -1,12 +1,15 @@
 #!/usr/bin/env python3
 """Throughput and latency of the LST chain on one MI355X: served vs plain.
 
-One step = one event through the whole chain (hit bucketing, MD, LS, T3,
-T5, T5 duplicate removal, pLS, pT3/pT5, duplicate removal and cross-cleaning
-into track candidates), inputs already resident in HBM.  Forms measured:
+Every event goes through the whole chain (hit bucketing, MD, LS, T3, T5, T5
+duplicate removal, pLS, pT3/pT5, duplicate removal and cross-cleaning into
+track candidates), inputs already resident in HBM.  One step = one full
+round of the server: streams x max-batch events (64 by default), so K steps
+time 64 K events.  Forms measured:
 
 * served (the headline `value`): the library's serving loop (streams x
-  batches) with K PU200-like seeded events available at once;
+  batches) with the K rounds' PU200-like seeded events available at once;
+  the headline latency is the served p50 / p99 of the Poisson trace below;
 * plain: synchronous lst_build_event per event, one at a time;
 * e2e: plain, but from pinned host arrays: host-to-device copy, the chain,
   and the track candidates copied back (the PCIe-inclusive rate);
@@ -61,9 +64,9 @@ WORKLOAD = {
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=1024,
-                   help="events in the timed served run (256-event windows of one run vary by about 10%%)")
-    p.add_argument("--warmup", type=int, default=8)
+    p.add_argument("--steps", type=int, default=16,
+                   help="server rounds timed (one round = streams x max-batch events)")
+    p.add_argument("--warmup", type=int, default=2, help="untimed server rounds before the timed ones")
     p.add_argument("--pool", type=int, default=12, help="distinct events cycled through")
     p.add_argument("--streams", type=int, default=4, help="server streams")
     p.add_argument("--max-batch", type=int, default=16, help="events per server launch sequence")
@@ -182,6 +185,20 @@ def run_trace(lst, g, dev, n_streams, max_batch, pool_bytes, arrivals, ids):
     return lat, len(arrivals) / span
 
 
+def _make(spec):
+    from lstgen import make_event
+    return make_event(*spec)
+
+
+def make_events(specs):
+    """Generated events for [(config, number), ...], made in parallel processes (CPU only)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    n = max(1, min(16, len(os.sched_getaffinity(0)), len(specs)))
+    with ProcessPoolExecutor(max_workers=n, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(_make, specs))
+
+
 def _oracle_worker(workload, ev, start, out):
     """One CPU-baseline process: build the oracle's geometry, wait for the start signal, run one event."""
     try:
@@ -258,11 +275,8 @@ def main():
     geom = geometry_for(args.workload)
     g = lst.Geometry(geom)
     log(f"bench: generating {args.pool} {args.workload} events")
-    pool, host = [], []
-    for i in range(args.pool):
-        ev = make_event(args.workload, i)
-        host.append(ev)
-        pool.append(lst.upload_event(ev, dev))
+    host = make_events([(args.workload, i) for i in range(args.pool)])
+    pool = [lst.upload_event(ev, dev) for ev in host]
     n_hits_max = max(e.n_hits for e in host)
     n_seeds_max = max(e.n_seeds for e in host)
     cap = lst.lst_default_capacity(n_hits_max, n_seeds_max)
@@ -309,62 +323,69 @@ def main():
                                                       for k in np.argsort(-per_site)))
         log(f"bench: sum of site times {per_site.sum() / 2:.3f} ms per event")
 
-    def event_bytes(ev, c):
+    n_outer = [int((ev.module >= 0).sum()) for ev in host]
+
+    def event_bytes(k, c):
         cc = dict(md=int(c[0]), ls=int(c[1]), t3=int(c[2]), t5=int(c[3]), pt3=int(c[5]), pt5=int(c[6]))
-        return algorithmic_bytes(sites[dom], cc, int((ev.module >= 0).sum()), geom.n_modules,
-                                 int(geom.map_targets.size), ev.n_seeds, int(c[7]))
+        return algorithmic_bytes(sites[dom], cc, n_outer[k], geom.n_modules, int(geom.map_targets.size),
+                                 host[k].n_seeds, int(c[7]))
 
     # ---- served at saturation (the headline), measured first so that its pool is allocated like a
     # server's at start-up: every request available at once; the dominant launch site of every
     # batched launch sequence is bracketed by HIP events on its stream
     n_streams, max_batch = args.streams, args.max_batch
-    pool_bytes = int(ws_one * (n_streams * max_batch + 2))
+    round_events = n_streams * max_batch
+    pool_bytes = int(ws_one * (round_events + 2))
     srv = lst.Server(g, n_streams, max_batch, pool_bytes)
-    n_warm = max(args.warmup, max_batch)
+    n_warm = max(1, args.warmup) * round_events
     for i in range(n_warm):
         srv.submit(pool[i % len(pool)], -1 - i, 0.0)
     srv.drain(n_warm, lambda r: lst.lst_release_event(r["event"]))
     lst.lst_set_timed_site(dom)
-    torch.cuda.synchronize()
-    served_lat, launches, chain_served = [], {}, []
+    n_served = args.steps * round_events
+    results = []
 
     def take(r):
-        served_lat.append((r["done_s"] - r["arrival_s"]) * 1e3)
+        # only what the result handle holds; the byte bookkeeping runs after the timed region
         c, _ = lst.lst_get_stage_counts(r["event"])
-        ms = lst.lst_get_site_time(r["event"])
-        rec = launches.setdefault(r["admit_s"], [ms, 0.0])
-        hev = host[r["id"] % len(host)]
-        b = event_bytes(hev, c)
-        rec[1] = None if (b is None or rec[1] is None) else rec[1] + b
-        chain_served.append(chain_bytes(c, hev.n_hits, int((hev.module >= 0).sum()), geom.n_modules,
-                                        int(geom.map_targets.size), hev.n_seeds))
+        results.append((r["id"], r["arrival_s"], r["admit_s"], r["done_s"], lst.lst_get_site_time(r["event"]), c))
         lst.lst_release_event(r["event"])
 
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     tnow = srv.now()
-    for i in range(args.steps):
+    for i in range(n_served):
         srv.submit(pool[i % len(pool)], i, tnow)
-    srv.drain(args.steps, take)
+    srv.drain(n_served, take)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     lst.lst_set_timed_site(-1)
     srv.close()
-    value = args.steps / elapsed
-    log(f"bench: served {value:.1f} events/s ({n_streams} streams x {max_batch} per batch, "
-        f"{len(launches)} launch sequences)")
+    value = n_served / elapsed
+    served_lat, launches, chain_served = [], {}, []
+    for rid, arr, adm, done, ms, c in results:
+        served_lat.append((done - arr) * 1e3)
+        k = rid % len(host)
+        rec = launches.setdefault(adm, [ms, 0.0])
+        b = event_bytes(k, c)
+        rec[1] = None if (b is None or rec[1] is None) else rec[1] + b
+        chain_served.append(chain_bytes(c, host[k].n_hits, n_outer[k], geom.n_modules, int(geom.map_targets.size),
+                                        host[k].n_seeds))
+    log(f"bench: served {value:.1f} events/s over {n_served} events ({args.steps} rounds of {n_streams} streams x "
+        f"{max_batch} per batch, {len(launches)} launch sequences)")
 
     # ---- plain: synchronous per event
     plain = None
     if "plain" in forms:
-        for i in range(args.warmup):
+        for i in range(max(args.warmup, 4)):
             step(i)
         torch.cuda.synchronize()
         lat = []
-        n_plain = max(8, min(args.steps, 32))
+        n_plain = 32
         t0 = time.perf_counter()
         for i in range(n_plain):
             s0 = time.perf_counter()
-            step(args.warmup + i)
+            step(4 + i)
             lat.append((time.perf_counter() - s0) * 1e3)
         torch.cuda.synchronize()
         plain_elapsed = time.perf_counter() - t0
@@ -406,16 +427,16 @@ def main():
     plain_graph = None
     if "plain_graph" in forms:
         plan1 = lst.Plan(g, 1, n_hits_max, n_seeds_max)
-        for i in range(args.warmup):
+        for i in range(max(args.warmup, 4)):
             for r in plan1.run([pool[i % len(pool)]]):
                 r.close()
         torch.cuda.synchronize()
-        n_pg = max(8, min(args.steps, 32))
+        n_pg = 32
         lat = []
         t0 = time.perf_counter()
         for i in range(n_pg):
             s0 = time.perf_counter()
-            for r in plan1.run([pool[(args.warmup + i) % len(pool)]]):
+            for r in plan1.run([pool[(4 + i) % len(pool)]]):
                 r.close()
             lat.append((time.perf_counter() - s0) * 1e3)
         torch.cuda.synchronize()
@@ -432,15 +453,15 @@ def main():
         if tuned:
             g_h.set_launch_config(tuned)
         g_h.set_stub_precision(16)
-        for i in range(args.warmup):
+        for i in range(max(args.warmup, 4)):
             step(i, gh=g_h.handle)
         torch.cuda.synchronize()
-        n_h = max(8, min(args.steps, 32))
+        n_h = 32
         lat = []
         t0 = time.perf_counter()
         for i in range(n_h):
             s0 = time.perf_counter()
-            step(args.warmup + i, gh=g_h.handle)
+            step(4 + i, gh=g_h.handle)
             lat.append((time.perf_counter() - s0) * 1e3)
         torch.cuda.synchronize()
         stub16 = {"events_per_s": round(n_h / (time.perf_counter() - t0), 3), "latency_ms": percentiles(lat),
@@ -458,15 +479,15 @@ def main():
         if tuned:
             g_ext.set_launch_config(tuned)
         g_ext.set_track_extensions(True)
-        for i in range(args.warmup):
+        for i in range(max(args.warmup, 4)):
             step(i, gh=g_ext.handle)
         torch.cuda.synchronize()
-        n_ext = max(8, min(args.steps, 32))
+        n_ext = 32
         lat = []
         t0 = time.perf_counter()
         for i in range(n_ext):
             s0 = time.perf_counter()
-            step(args.warmup + i, gh=g_ext.handle)
+            step(4 + i, gh=g_ext.handle)
             lat.append((time.perf_counter() - s0) * 1e3)
         torch.cuda.synchronize()
         ext = {"events_per_s": round(n_ext / (time.perf_counter() - t0), 3), "latency_ms": percentiles(lat),
@@ -495,14 +516,14 @@ def main():
             lst.lst_release_event(ev)
             return tc
 
-        for i in range(args.warmup):
+        for i in range(max(args.warmup, 4)):
             e2e_step(i)
         torch.cuda.synchronize()
-        lat, n_e2e = [], max(8, min(args.steps, 32))
+        lat, n_e2e = [], 32
         t0 = time.perf_counter()
         for i in range(n_e2e):
             s0 = time.perf_counter()
-            e2e_step(args.warmup + i)
+            e2e_step(4 + i)
             lat.append((time.perf_counter() - s0) * 1e3)
         el = time.perf_counter() - t0
         e2e = {"events_per_s": round(n_e2e / el, 3), "latency_ms": percentiles(lat), "events": n_e2e,
@@ -544,13 +565,13 @@ def main():
     # ---- batched: captured plan over B slots (pile-up U[140, 250]), graph replays
     batched = None
     if args.batch > 0 and "batched" in forms:
-        bhost = [make_event("batch", i) for i in range(min(args.pool, args.batch))]
+        bhost = make_events([("batch", i) for i in range(args.batch)])   # 64 distinct events
         bpool = [lst.upload_event(e, dev) for e in bhost]
         chain_batched = []
         bmax = max(int(t["x"].numel()) for t in bpool)
         bseed = max(int(t["px"].numel()) for t in bpool)
         evs = [bpool[i % len(bpool)] for i in range(args.batch)]
-        reps = max(2, args.steps // args.batch)
+        reps = max(4, n_served // args.batch)
 
         def time_plan():
             plan = lst.Plan(g, args.batch, bmax, bseed)  # captured with the geometry's launch shapes
@@ -613,7 +634,7 @@ def main():
         tot_s = sum(v[0] for v in launches.values()) / 1e3
         ach = tot_b / tot_s / 1e9
         tr = measured_traffic(sites[dom])
-        ev_per_launch = args.steps / len(launches)
+        ev_per_launch = n_served / len(launches)
         roof = {"bound": "hbm", "kernel": sites[dom], "achieved": round(ach, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 5),
                 "traffic": None if tr is None else int(tr["hbm_bytes_per_event"] * ev_per_launch),
@@ -630,8 +651,11 @@ def main():
                    "mean_hits": int(np.mean([e.n_hits for e in host])),
                    "mean_seeds": int(np.mean([e.n_seeds for e in host])),
                    "form": f"served: {n_streams} streams x batches of {max_batch}, all requests available",
-                   "step": "one event through the whole chain"},
-        "latency_ms": percentiles(served_lat),
+                   "step": f"one server round: {round_events} events through the whole chain",
+                   "events_timed": n_served,
+                   "latency": "served p50/p99 of the Poisson trace (500 events/s, pile-up U[50, 250])"},
+        "latency_ms": trace["served"]["latency_ms"] if trace else None,
+        "saturation_latency_ms": percentiles(served_lat),
         "launch_shapes": tuned, "plain": plain, "plain_graph": plain_graph, "stub16": stub16, "extensions": ext, "displaced": displaced, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
         "roofline": roof,
     }
