@@ -120,6 +120,31 @@ lst_status lst_workspace_bytes(lst_geometry geom, int32_t n_hits, int32_t n_seed
 lst_status lst_build_event(lst_geometry geom, const lst_event_desc *ev, const lst_capacity *cap, void *workspace,
                            size_t ws_bytes, void *stream, lst_event *out);
 
+/* Allocation-free form of lst_build_event, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The event runs in the library's static workspace: one device
+ * array of lst_static_workspace_bytes() bytes (256 MiB) per GPU, held from the
+ * first call on that GPU until the process ends.  The call validates the
+ * arguments and the event's workspace size on the host (LST_E_NOMEM, with the
+ * bytes needed, when the event with its capacities does not fit; default
+ * capacities fit events of up to about 200,000 hits), enqueues the chain on
+ * `stream` and returns without waiting; it calls no hipMalloc, hipFree or
+ * other allocating routine.  Outputs are caller DEVICE buffers: counts[0..2]
+ * = number of track candidates, their total hit count, the chain's status
+ * flags (0 = built; 1 invalid hit data, 2 invalid seed data, 4 capacity
+ * exceeded); type[max_tc], offsets[max_tc + 1] and hits[max_tc_hits] are
+ * written (as lst_get_track_candidates lays them out) only when the status
+ * is 0 and both counts fit, so a caller reads counts after synchronizing the
+ * stream and retries with larger buffers if needed.  Every call on one GPU
+ * shares that GPU's workspace: calls that overlap on one GPU (different
+ * streams or threads, or a call before the previous one's outputs were
+ * consumed) race.  Errors: LST_E_INVALID (arguments, as lst_build_event),
+ * LST_E_NOMEM (too large), LST_E_DEVICE (a HIP call failed). */
+lst_status lst_build_event_static(lst_geometry geom, const lst_event_desc *ev, const lst_capacity *cap,
+                                  void *stream, int32_t max_tc, int32_t max_tc_hits, int32_t *type,
+                                  int32_t *offsets, int32_t *hits, int32_t *counts);
+lst_status lst_static_workspace_bytes(size_t *bytes);
+
 /* Asynchronous form: enqueues the chain on `stream` and returns at once.
  * Inputs and workspace must stay valid until lst_event_wait returns (or
  * lst_event_query reports completion).  The status of the build is returned

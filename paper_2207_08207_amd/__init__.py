@@ -32,7 +32,7 @@ EXPORTED = ["lst_load_geometry", "lst_release_geometry", "lst_default_capacity",
             "lst_server_destroy", "lst_get_launch_config", "lst_set_launch_config", "lst_autotune",
             "lst_set_track_extensions", "lst_get_extended_track_candidates", "lst_set_impact_bound",
             "lst_set_stub_precision", "lst_set_t5_cuts", "lst_get_t5_cuts",
-            "lst_get_default_t5_cuts",
+            "lst_get_default_t5_cuts", "lst_build_event_static", "lst_static_workspace_bytes",
             "lst_server_submit_with_capacity", "lst_server_reruns", "lst_tile_count", "lst_tile_name",
             "lst_tile_range", "lst_get_tile_config", "lst_set_tile_config", "lst_autotune_tiles"]
 
@@ -104,6 +104,8 @@ def load_library(path=LIB_PATH):
         "lst_set_t5_cuts": [vp, vp, vp],
         "lst_get_t5_cuts": [vp, vp, vp],
         "lst_get_default_t5_cuts": [vp, vp],
+        "lst_build_event_static": [vp, P(lst_event_desc), P(lst_capacity), vp, i32, i32, vp, vp, vp, vp],
+        "lst_static_workspace_bytes": [P(sz)],
         "lst_get_extended_track_candidates": [vp, P(i32), P(i32), vp, vp, vp, vp, vp, vp],
         "lst_get_stage_objects": [vp, i32, P(i32), vp, vp, vp],
         "lst_get_stage_counts": [vp, vp, vp],
@@ -212,6 +214,29 @@ def lst_build_event(geom, dev_event, workspace, cap=None, stream=None):
     st = load_library().lst_build_event(geom, ctypes.byref(d), ctypes.byref(cap) if cap is not None else None,
                                         _ptr(workspace), int(workspace.numel()), stream, ctypes.byref(h))
     return st, h.value
+
+
+def lst_static_workspace_bytes():
+    n = ctypes.c_size_t()
+    _check(load_library().lst_static_workspace_bytes(ctypes.byref(n)))
+    return int(n.value)
+
+
+def lst_build_event_static(geom, dev_event, type_out, offsets_out, hits_out, counts_out, cap=None, stream=None):
+    """Allocation-free build: the chain runs in the library's static workspace; the track candidates
+    go to the given device int32 tensors (counts_out[0..2] = candidates, hits, status).  Returns at
+    once; synchronize the stream before reading the outputs."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    if offsets_out.numel() < type_out.numel() + 1:
+        raise ValueError("offsets_out needs one entry more than type_out")
+    d = _event_desc(dev_event)
+    c = None if cap is None else ctypes.byref(cap)
+    _check(load_library().lst_build_event_static(
+        geom, ctypes.byref(d), c, ctypes.c_void_p(stream), int(type_out.numel()), int(hits_out.numel()),
+        ctypes.c_void_p(type_out.data_ptr()), ctypes.c_void_p(offsets_out.data_ptr()),
+        ctypes.c_void_p(hits_out.data_ptr()), ctypes.c_void_p(counts_out.data_ptr())))
 
 
 def lst_enqueue_event(geom, dev_event, workspace, cap=None, stream=None):

@@ -23,12 +23,15 @@
 
 namespace {
 
-thread_local std::string g_err;
+// Last error message of the calling thread, in a fixed buffer (setting it
+// allocates nothing, which the allocation-free entry point relies on).
+thread_local char g_err[512];
 
-lst_status fail(lst_status s, const std::string &msg) {
-  g_err = msg;
+lst_status fail(lst_status s, const char *msg) {
+  snprintf(g_err, sizeof(g_err), "%s", msg);
   return s;
 }
+lst_status fail(lst_status s, const std::string &msg) { return fail(s, msg.c_str()); }
 
 #define HIP_TRY(expr)                                                                               \
   do {                                                                                              \
@@ -244,7 +247,7 @@ static lst_status check_caps(const lst_capacity &c) {
 
 extern "C" {
 
-const char *lst_last_error(void) { return g_err.c_str(); }
+const char *lst_last_error(void) { return g_err; }
 
 lst_status lst_default_capacity(int32_t n_hits, int32_t n_seeds, lst_capacity *out) {
   if (!out || n_hits < 0 || n_seeds < 0) return fail(LST_E_INVALID, "lst_default_capacity: bad argument");
@@ -665,10 +668,10 @@ lst_status lst_enqueue_batch(lst_geometry g, int32_t B, const lst_event_desc *ev
   lst_status es = enqueue_batch_at(g, B, evs, caps, reinterpret_cast<char *>(workspace),
                                    reinterpret_cast<hipStream_t>(stream), &b);
   if (!b) return es;
-  std::string msg = g_err;
+  std::string msg = g_err;  // make_events may overwrite it
   lst_status ms = make_events(b, B, out);
   if (ms != LST_OK) return ms;
-  if (es != LST_OK) g_err = msg;
+  if (es != LST_OK) snprintf(g_err, sizeof(g_err), "%s", msg.c_str());
   return es;
 }
 
@@ -708,6 +711,89 @@ lst_status lst_build_event(lst_geometry g, const lst_event_desc *ev, const lst_c
   lst_status s = lst_enqueue_event(g, ev, cap, workspace, ws_bytes, stream, out);
   if (s != LST_OK) return s;
   return lst_event_wait(*out);
+}
+
+// ------------------------------------------------ allocation-free entry point
+// The workspace of lst_build_event_static: a file-scope device array, one copy
+// per GPU, held until the process ends.  Host code never uses its name as an
+// address: the device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+// A failed HIP call, reported without allocating.
+lst_status fail_hip(const char *what, hipError_t e) {
+  snprintf(g_err, sizeof(g_err), "%s: %s", what, hipGetErrorString(e));
+  return LST_E_DEVICE;
+}
+
+// Device address of `scratch` on the current device (looked up on the first call there).
+lst_status scratch_ptr(char **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail_hip("hipGetDevice", e);
+  if (dev < 0 || dev >= kMaxDevices) return fail(LST_E_DEVICE, "lst_build_event_static: device index above 63");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return fail_hip("hipGetSymbolAddress(scratch)", e);
+    if (!p) return fail(LST_E_DEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = static_cast<char *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return LST_OK;
+}
+}  // namespace
+
+lst_status lst_static_workspace_bytes(size_t *bytes) {
+  if (!bytes) return fail(LST_E_INVALID, "lst_static_workspace_bytes: NULL argument");
+  *bytes = kScratchBytes;
+  return LST_OK;
+}
+
+lst_status lst_build_event_static(lst_geometry g, const lst_event_desc *ev, const lst_capacity *cap, void *stream,
+                                  int32_t max_tc, int32_t max_tc_hits, int32_t *type, int32_t *offsets,
+                                  int32_t *hits, int32_t *counts) {
+  if (!g || !ev || !counts || !offsets || max_tc < 0 || max_tc_hits < 0 || (max_tc > 0 && !type) ||
+      (max_tc_hits > 0 && !hits))
+    return fail(LST_E_INVALID, "lst_build_event_static: bad argument");
+  lst_status s = check_event_desc(*ev);
+  if (s != LST_OK) return s;
+  if (ev->n_seeds > kMaxCap / 4) return fail(LST_E_INVALID, "n_seeds above 2e6");
+  lst_capacity c;
+  if (cap) c = *cap; else lst_default_capacity(ev->n_hits, ev->n_seeds, &c);
+  s = check_caps(c);
+  if (s != LST_OK) return s;
+  const lst::Caps caps{c.md, c.ls, c.t3, c.t5, c.pt3, c.pt5};
+  const size_t head = header_bytes(1);
+  const size_t need = head + lst::workspace_layout(g->g.n_mod, ev->n_hits, ev->n_seeds, caps, nullptr, nullptr, nullptr);
+  if (need > kScratchBytes) {
+    char msg[200];
+    snprintf(msg, sizeof(msg), "lst_build_event_static: event needs %zu bytes, above the static workspace of %zu",
+             need, kScratchBytes);
+    return fail(LST_E_NOMEM, msg);
+  }
+  char *base = nullptr;
+  s = scratch_ptr(&base);
+  if (s != LST_OK) return s;
+  lst::Ws *d_ws = reinterpret_cast<lst::Ws *>(base);
+  int *d_ctr = reinterpret_cast<int *>(base + ((sizeof(lst::Ws) + kAlign - 1) / kAlign) * kAlign);
+  lst::Ws w{};
+  lst::workspace_layout(g->g.n_mod, ev->n_hits, ev->n_seeds, caps, &w, base + head, d_ctr);
+  w.x = ev->x; w.y = ev->y; w.z = ev->z; w.module = ev->module; w.sensor = ev->sensor;
+  w.px = ev->px; w.py = ev->py; w.pz = ev->pz; w.q = ev->q; w.hits4 = ev->hits4;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  lst::launch_put_desc(w, d_ws, st);
+  lst::enqueue_chain(g->g, d_ws, 1, w, st, nullptr, g->site_block);
+  lst::launch_tc_export(d_ws, max_tc, max_tc_hits, type, offsets, hits, counts, st);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail_hip("lst_build_event_static: launch", e);
+  return LST_OK;
 }
 
 static lst_status event_ok(lst_event e) {

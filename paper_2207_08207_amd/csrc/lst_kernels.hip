@@ -165,6 +165,39 @@ void launch_module_windows(const int *info, const float *pos_lo, const float *po
   k_module_windows<<<(n_mod + 127) / 128, 128, 0, st>>>(info, pos_lo, pos_up, lmin, lmax, n_mod, d0, win);
 }
 
+// ------------------------------------------------- allocation-free forms
+// One event descriptor written into device memory by a kernel (its argument
+// block carries it), for callers that have no host staging buffer.
+__global__ void k_put_desc(Ws w, Ws *dst) { *dst = w; }
+
+void launch_put_desc(const Ws &w, Ws *dst, hipStream_t st) { k_put_desc<<<1, 1, 0, st>>>(w, dst); }
+
+// Copies an event's track candidates to caller device buffers: counts[0] =
+// candidates, counts[1] = their hits, counts[2] = the chain's status flags;
+// the arrays are written only when the chain succeeded and both fit.
+__global__ void k_tc_export(const Ws *__restrict__ wb, int max_tc, int max_hits, int *type, int *off, int *hits,
+                            int *counts) {
+  const Ws &w = wb[0];
+  const int st = w.ctr[C_STATUS], n = w.ctr[C_NTC], nh = w.ctr[C_NTCHITS];
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  if (tid == 0) {
+    counts[0] = n;
+    counts[1] = nh;
+    counts[2] = st;
+  }
+  if (st != 0 || n > max_tc || nh > max_hits) return;
+  for (int i = tid; i <= n; i += stride) {
+    if (i < n) type[i] = w.tc_type[i];
+    off[i] = w.tc_off[i];
+  }
+  for (int i = tid; i < nh; i += stride) hits[i] = w.tc_hits[i];
+}
+
+void launch_tc_export(const Ws *d_ws, int max_tc, int max_hits, int *type, int *off, int *hits, int *counts,
+                      hipStream_t st) {
+  k_tc_export<<<256, 256, 0, st>>>(d_ws, max_tc, max_hits, type, off, hits, counts);
+}
+
 // ------------------------------------------------------------- a0: hits
 // Validation of the inputs and histogram of outer-tracker hits per (module, sensor).
 __global__ void k_hits_count(const Ws *__restrict__ wb, int n_mod) {

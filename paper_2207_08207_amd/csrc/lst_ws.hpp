@@ -206,5 +206,10 @@ void enqueue_chain(const DevGeom &g, const Ws *d_ws, int B, const Ws &bound, hip
                    const int *site_block);
 void launch_module_windows(const int *info, const float *pos_lo, const float *pos_up, const float *lmin,
                            const float *lmax, int n_mod, double d0, float4 *win, hipStream_t st);
+// Allocation-free forms: an event descriptor written by a kernel, and the
+// track candidates copied to caller device buffers (counts: n, hits, status).
+void launch_put_desc(const Ws &w, Ws *dst, hipStream_t st);
+void launch_tc_export(const Ws *d_ws, int max_tc, int max_hits, int *type, int *off, int *hits, int *counts,
+                      hipStream_t st);
 
 }  // namespace lst
