@@ -75,7 +75,7 @@ def parse():
     p.add_argument("--sweep", default="100,200,500,1000,2000",
                    help="offered rates of the served-vs-plain rate sweep [events/s] (empty: skip)")
     p.add_argument("--batch", type=int, default=64, help="slots of the captured batched plan (0: skip)")
-    p.add_argument("--forms", default="plain,plain_graph,stub16,ext,displaced,e2e,served,trace,batched,copy",
+    p.add_argument("--forms", default="plain,plain_graph,stub16,ext,displaced,e2e,served,trace,batched,copy,probe",
                    help="comma list of forms to run (served is the headline and always runs)")
     p.add_argument("--site", default=None,
                    help="launch site to time for the roofline (default: the largest in a per-site calibration)")
@@ -626,6 +626,27 @@ def main():
         del src, dst
         log(f"bench: copy {copy}")
 
+    # ---- vector-issue calibration: a kernel of 16 independent FMAs per round and nothing else, at
+    # 8 waves per SIMD; its issue rate is the ceiling the counter summaries normalise against
+    probe = None
+    if "probe" in forms:
+        n_blocks, iters = 4096, 4000
+        out_p = torch.empty(n_blocks * 256, dtype=torch.float32, device=dev)
+        lst.lst_probe_valu(n_blocks, 10, out_p)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        lst.lst_probe_valu(n_blocks, iters, out_p)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        insts = n_blocks * 4 * 16 * iters           # wave64 FMA instructions issued
+        probe = {"kernel": "16 independent FMA chains per thread, 4096 x 256 threads, 4000 rounds",
+                 "ms": round(ms, 4), "valu_insts": insts,
+                 "insts_per_cu_per_clock_at_2.4GHz": round(insts / (ms * 1e-3 * 2.4e9 * 256), 4)}
+        del out_p
+        log(f"bench: probe {probe}")
+
     # ---- roofline of the dominant kernel: algorithmic bytes of the events of each batched launch
     # divided by that launch's HIP-event duration, summed over the served run's launches
     roof = None
@@ -656,7 +677,7 @@ def main():
                    "latency": "served p50/p99 of the Poisson trace (500 events/s, pile-up U[50, 250])"},
         "latency_ms": trace["served"]["latency_ms"] if trace else None,
         "saturation_latency_ms": percentiles(served_lat),
-        "launch_shapes": tuned, "plain": plain, "plain_graph": plain_graph, "stub16": stub16, "extensions": ext, "displaced": displaced, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy,
+        "launch_shapes": tuned, "plain": plain, "plain_graph": plain_graph, "stub16": stub16, "extensions": ext, "displaced": displaced, "e2e": e2e, "trace": trace, "batched": batched, "copy": copy, "valu_probe": probe,
         "roofline": roof,
     }
     if chain_served:

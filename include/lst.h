@@ -406,6 +406,15 @@ lst_status lst_set_tile_config(lst_geometry geom, int32_t n, const int32_t *tile
 lst_status lst_autotune_tiles(lst_geometry geom, int32_t B, const lst_event_desc *evs, const lst_capacity *cap,
                               void *workspace, size_t ws_bytes, void *stream, int32_t reps, float *tile_ms);
 
+/* Counter calibration: launches n_blocks groups of 256 threads that each run
+ * `iters` rounds of 16 independent fused multiply-adds (no memory traffic;
+ * `out`, n_blocks * 256 floats of DEVICE memory, is never written in
+ * practice), on `stream`, without waiting.  Its known instruction count and
+ * stall-free issue calibrate the vector-issue counters that the profile
+ * summaries report for the chain's kernels.  LST_E_INVALID for bad arguments,
+ * LST_E_DEVICE if the launch fails. */
+lst_status lst_probe_valu(int32_t n_blocks, int32_t iters, float *out, void *stream);
+
 lst_status lst_release_event(lst_event ev);
 const char *lst_last_error(void);
 

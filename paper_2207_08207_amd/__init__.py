@@ -34,7 +34,8 @@ EXPORTED = ["lst_load_geometry", "lst_release_geometry", "lst_default_capacity",
             "lst_set_stub_precision", "lst_set_t5_cuts", "lst_get_t5_cuts",
             "lst_get_default_t5_cuts", "lst_build_event_static", "lst_static_workspace_bytes",
             "lst_server_submit_with_capacity", "lst_server_reruns", "lst_tile_count", "lst_tile_name",
-            "lst_tile_range", "lst_get_tile_config", "lst_set_tile_config", "lst_autotune_tiles"]
+            "lst_tile_range", "lst_get_tile_config", "lst_set_tile_config", "lst_autotune_tiles",
+            "lst_probe_valu"]
 
 
 class LSTError(RuntimeError):
@@ -132,6 +133,7 @@ def load_library(path=LIB_PATH):
         "lst_set_launch_config": [vp, i32, vp],
         "lst_autotune": [vp, i32, vp, vp, vp, sz, vp, i32, vp],
         "lst_autotune_tiles": [vp, i32, vp, vp, vp, sz, vp, i32, vp],
+        "lst_probe_valu": [i32, i32, vp, vp],
         "lst_tile_range": [i32, P(i32), P(i32)],
         "lst_get_tile_config": [vp, i32, vp],
         "lst_set_tile_config": [vp, i32, vp],
@@ -374,6 +376,15 @@ def lst_get_tile_config(geom):
 def lst_set_tile_config(geom, tiles):
     a = np.ascontiguousarray(tiles, np.int32)
     _check(load_library().lst_set_tile_config(geom, int(a.size), _ptr(a)))
+
+
+def lst_probe_valu(n_blocks, iters, out, stream=None):
+    """Launches the VALU calibration kernel (see include/lst.h) into `out` (device float tensor)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    _check(load_library().lst_probe_valu(int(n_blocks), int(iters), ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(stream)))
 
 
 def lst_set_timed_site(site):

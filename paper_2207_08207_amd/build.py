@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "liblst.so")
-SOURCES = ["lst_kernels.hip", "lst_api.hip"]
+SOURCES = ["lst_kernels.hip", "lst_api.hip", "lst_probe.hip"]
 ARCH = os.environ.get("LST_OFFLOAD_ARCH", "gfx950")
 
 

@@ -480,17 +480,58 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
 // |A x B| <= Wmax r_A r_B fails ls_pass; and since |A x B| = r_A |n.B| >= r_A
 // (|n.C| - rho) for the unit normal n of A, with r_B <= |C| + rho, a module
 // failing |n.C| - rho <= Wmax (|C| + rho) has no candidate that can pass.
+//
+// The pre-tests use the hardware reciprocal, reciprocal square root and
+// square root (v_rcp_f32, v_rsq_f32, v_sqrt_f32: within 1 ulp each) instead of
+// correctly rounded division and square root; their results differ from the
+// exact values by a few parts in 1e7, far inside each pre-test's margin, so
+// the pre-tests stay supersets of the exact selection that decides.
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
 __device__ __forceinline__ float ls_window_bound(const float4 &A, ModInfo ma, float4 disc, ModInfo mb, float d0) {
   const float ub = kHalfKmax * ((disc.w + disc.z) + mb.er());
   if (!(ub < 0.99f)) return 3.0e38f;  // no useful bound
   const float ua = kHalfKmax * (A.w - ma.er());
-  const float w = (ub - ua) / sqrtf(1.0f - ub * ub) + (d0 + ma.hphi() + 0.005f) / A.w;
+  const float w = (ub - ua) * frsq(1.0f - ub * ub) + (d0 + ma.hphi() + 0.005f) * frcp(A.w);
   return (w * kMargin + kEps) * 1.01f + 1e-6f;
 }
 
 __device__ __forceinline__ bool ls_module_may_pass(const float4 &A, float4 disc, float wmax) {
-  const float dn = fabsf(A.x * disc.y - A.y * disc.x) / A.w;
+  const float dn = fabsf(A.x * disc.y - A.y * disc.x) * frcp(A.w);
   return dn - disc.z <= (wmax * (disc.w + disc.z)) * 1.001f + 1e-4f;
+}
+
+// The inner MD's stub check of ls_pass (ls_stub_ok with its chord quantities),
+// evaluated with the fast operations: every quantity is within 2e-6 relative
+// of the exact one (a chain of at most six operations of <= 2 ulp), except
+// that 1 - s^2 loses relative precision as s^2 -> 1: chords within
+// asin(sqrt(0.9)) of the tangent skip the pre-test (the exact test decides),
+// which bounds the error of the predicted displacement at 4e-5 relative.  The
+// margins (1e-4 of the prediction and of the error) exceed those bounds, so
+// whatever passes the exact check passes this one.
+__device__ __forceinline__ bool ls_inner_stub_may_pass(const float4 &A, const float4 &B, float2 st, ModInfo ma,
+                                                       ModInfo mb, float d0) {
+  const float sx = B.x - A.x, sy = B.y - A.y;
+  const float il = frsq(sx * sx + sy * sy);  // 1 / |AB|
+  const float sn = (B.x * sy - B.y * sx) * frcp(B.w) * il;
+  const float ea2 = ma.endcap() ? ma.hlong() : ma.hphi();
+  const float eb2 = mb.endcap() ? mb.hlong() : mb.hphi();
+  const float eang = (ea2 + eb2) * il;
+  float pred, err;
+  if (!ma.endcap()) {
+    const float sn2 = sn * sn;
+    if (!(sn2 < 0.9f)) return true;
+    pred = (st.y * sn) * frsq(1.0f - sn2);
+    err = 2.0f * ma.hphi() + (2.0f * st.y) * (eang + d0 * frcp(A.w));
+  } else {
+    const float adz = fabsf(B.z - A.z);
+    if (!(adz > 0.0f)) return false;  // the exact check's own rejection, on the same operands
+    const float ds = st.y * (sx * sx + sy * sy) * il * frcp(adz);
+    pred = ds * sn;
+    err = (2.0f * ma.hphi() + (float)0.03 * fabsf(pred)) + ds * (eang + d0 * frcp(A.w));
+  }
+  return fabsf(st.x - pred) <= (err * kMargin) * 1.0001f + kEps + 1e-4f * fabsf(pred);
 }
 
 __device__ __forceinline__ bool ls_window_may_pass(const float4 &A, const float4 &B, float wmax) {
@@ -605,7 +646,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         b = s_first[wv][e] + (c - s_pre[wv][e]);
         const float4 Bp = w.md_pos[b];
         info = s_info[wv][e];
-        keep = ls_window_may_pass(A, Bp, s_wmax[wv][e]) && ls_inner_stub_ok(A, Bp, sa, mia, ModInfo{info}, g.d0max);
+        keep = ls_window_may_pass(A, Bp, s_wmax[wv][e]) &&
+               ls_inner_stub_may_pass(A, Bp, sa, mia, ModInfo{info}, g.d0max);
       }
       const unsigned long long m = __ballot(keep);
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
