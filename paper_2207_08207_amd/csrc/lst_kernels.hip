@@ -744,11 +744,50 @@ __global__ void k_ls_copy(const Ws *__restrict__ wb, int keep) {
 
 // ------------------------------------------------------------- a3: T3
 // Parents: segments (a, b); candidates: the segments whose inner MD is b.
+// A superset of t3_pass's curvature cut and azimuth-z test (the cuts most
+// pairs fail), in the fast operations of the segment pre-tests.  Differences
+// from the exact quantities: the curvature and its error within 1e-6
+// relative (margin 1e-5); the azimuth-z residual is a difference of two
+// products, so its error is bounded by 1e-6 of their magnitudes (margin
+// 1e-5 of them) and the tolerance's by 1e-6 relative (margin 1e-5).
+__device__ __forceinline__ bool t3_may_pass(const float4 &A, const float4 &B, const float4 &C, ModInfo mA,
+                                            ModInfo mB, ModInfo mC, float d0) {
+  const float ux = B.x - A.x, uy = B.y - A.y, wx = C.x - A.x, wy = C.y - A.y, tx = C.x - B.x, ty = C.y - B.y;
+  const float k = ux * wy - uy * wx;
+  const float Lw2 = wx * wx + wy * wy;
+  const float kap = (2.0f * k) * (frsq(ux * ux + uy * uy) * frsq(Lw2) * frsq(tx * tx + ty * ty));
+  const float dk = (4.0f * ((mA.sig_t() + 2.0f * mB.sig_t()) + mC.sig_t())) * frcp(Lw2);
+  if (!(fabsf(kap) <= (kKmaxCut + dk) * 1.00001f)) return false;
+  const float su = (A.x * B.y - A.y * B.x) * frcp(A.w * B.w);
+  const float sv = (B.x * C.y - B.y * C.x) * frcp(B.w * C.w);
+  const float dzpq = B.z - A.z, dzqr = C.z - B.z;
+  const float t1 = su * dzqr, t2 = sv * dzpq;
+  const float iP = frcp(A.w), iQ = frcp(B.w), iR = frcp(C.w);
+  const float ePQ = (mA.hphi() * iP + mB.hphi() * iQ) + d0 * fabsf(iP - iQ);
+  const float eQR = (mB.hphi() * iQ + mC.hphi() * iR) + d0 * fabsf(iQ - iR);
+  const float au = fabsf(su), av = fabsf(sv), adpq = fabsf(dzpq), adqr = fabsf(dzqr);
+  const float nl = (au * au + av * av) * kThird;
+  const float tol = ((adqr * ePQ + adpq * eQR) + (au * (mB.ez() + mC.ez()) + av * (mA.ez() + mB.ez()))) +
+                    nl * (au * adqr + av * adpq);
+  return fabsf(t1 - t2) <= (tol * kMargin + kEps) * 1.00001f + 1e-5f * (fabsf(t1) + fabsf(t2));
+}
+
+// First lane of the run of equal values v (lanes 0..n-1 of the wave, runs of
+// equal values contiguous) that holds this lane's value.
+__device__ __forceinline__ int run_first_lane(int v, int n) {
+  const int lane = lane_id();
+  const int prev = __shfl_up(v, 1, 64);
+  const unsigned long long starts = __ballot(lane < n && (lane == 0 || v != prev));
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  return 63 - __builtin_clzll(starts & upto);
+}
+
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
   __shared__ float4 s_a[kWaves][64], s_b[kWaves][64];
   __shared__ int s_mi[kWaves][64], s_lo[kWaves][64], s_cnt[kWaves][64], s_seg[kWaves][65], s_cached[kWaves][64];
+  __shared__ int s_qe[kWaves][128], s_qc[kWaves][128];  // pairs past the pre-test, in pair order
   const int n_ls = w.ctr[C_NLS];
   const int wv = threadIdx.x >> 6, lane = lane_id();
   const int wpb = blockDim.x >> 6;
@@ -775,35 +814,34 @@ __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeo
     s_cnt[wv][lane] = 0;
     s_cached[wv][lane] = cached;
     const int total = wave_segments(n, s_seg[wv]);
-    int e = 0;  // parent of this lane's pair (pairs advance monotonically)
-    for (int c0 = 0; c0 < total; c0 += 64) {
-      const int c = c0 + lane;
+    // the exact selection on the first nb (<= 64) queued pairs: ranks among each parent's
+    // passing pairs from the parent's running count and a ballot over the batch
+    auto select = [&](int nb) {
       bool pass = false;
-      int cmd = 0, cand = 0, first = 0, before = 0;
+      int e = 0, cand = 0, cmd = 0;
       float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (c < total) {
-        while (s_seg[wv][e + 1] <= c) ++e;
-        first = max(s_seg[wv][e] - c0, 0);
-        before = s_cnt[wv][e];
-        const int idx = c - s_seg[wv][e];
-        cand = s_cached[wv][e] ? w.t3_cache[(long)((int)p0 + e) * kT3Cache + idx] : s_lo[wv][e] + idx;
+      if (lane < nb) {
+        e = s_qe[wv][lane];
+        cand = s_qc[wv][lane];
         cmd = w.ls_md[cand].y;
         const int mi = s_mi[wv][e];
         pass = t3_pass(s_a[wv][e], s_b[wv][e], w.md_pos[cmd], ModInfo{mi & 0xff}, ModInfo{mi >> 8},
                        ModInfo{g.info[w.md_mod[cmd]]}, &attr, g.d0max);
       }
+      const int first = run_first_lane(e, nb);
       const unsigned long long m = __ballot(pass);
-      if (!FILL && pass) {
-        const int r = pair_rank(m, first, before);
-        if (r < g.tiles.t3_cache) w.t3_cache[(long)((int)p0 + e) * kT3Cache + r] = cand;
-      }
-      if (FILL && pass) {
-        const int pos = w.t3_off[(int)p0 + e] + pair_rank(m, first, before);
-        if (pos < w.cap_t3) {
-          const int2 ab = w.ls_md[(int)p0 + e];
-          w.t3_md[pos] = make_int4(ab.x, ab.y, cmd, (int)p0 + e);
-          w.t3_attr[pos] = attr;
-          w.t3_first[pos] = make_float2(s_a[wv][e].x, s_a[wv][e].y);
+      if (pass) {
+        const int r = pair_rank(m, first, s_cnt[wv][e]);
+        if (!FILL) {
+          if (r < g.tiles.t3_cache) w.t3_cache[(long)((int)p0 + e) * kT3Cache + r] = cand;
+        } else {
+          const int pos = w.t3_off[(int)p0 + e] + r;
+          if (pos < w.cap_t3) {
+            const int2 ab = w.ls_md[(int)p0 + e];
+            w.t3_md[pos] = make_int4(ab.x, ab.y, cmd, (int)p0 + e);
+            w.t3_attr[pos] = attr;
+            w.t3_first[pos] = make_float2(s_a[wv][e].x, s_a[wv][e].y);
+          }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -811,7 +849,51 @@ __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeo
       if (pass) atomicAdd(&s_cnt[wv][e], 1);  // LDS
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
+    };
+    int nq = 0;
+    int e = 0;  // parent of this lane's pair (pairs advance monotonically)
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      bool keep = false;
+      int cand = 0;
+      if (c < total) {
+        while (s_seg[wv][e + 1] <= c) ++e;
+        const int idx = c - s_seg[wv][e];
+        cand = s_cached[wv][e] ? w.t3_cache[(long)((int)p0 + e) * kT3Cache + idx] : s_lo[wv][e] + idx;
+        const int cmd = w.ls_md[cand].y;
+        const int mi = s_mi[wv][e];
+        keep = t3_may_pass(s_a[wv][e], s_b[wv][e], w.md_pos[cmd], ModInfo{mi & 0xff}, ModInfo{mi >> 8},
+                           ModInfo{g.info[w.md_mod[cmd]]}, g.d0max);
+      }
+      const unsigned long long m = __ballot(keep);
+      if (keep) {
+        const int q = nq + lanes_below(m);
+        s_qe[wv][q] = e;
+        s_qc[wv][q] = cand;
+      }
+      nq += __popcll(m);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (nq >= 64) {
+        select(64);
+        const int rest = nq - 64;  // < 64: move the queue's tail to its front
+        int ve = 0, vc = 0;
+        if (lane < rest) {
+          ve = s_qe[wv][64 + lane];
+          vc = s_qc[wv][64 + lane];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) {
+          s_qe[wv][lane] = ve;
+          s_qc[wv][lane] = vc;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        nq = rest;
+      }
     }
+    if (nq > 0) select(nq);
     if (!FILL && l1 < n_ls) w.t3_cnt[l1] = s_cnt[wv][lane];
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -820,11 +902,30 @@ __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeo
 
 // ------------------------------------------------------------- a4: T5
 // Parents: triplets (a, b, c); candidates: the triplets whose first MD is c.
+// A superset of the azimuth-z test of three anchors (phiz_pass), in the fast
+// operations, with the margins of t3_may_pass's azimuth-z part.
+__device__ __forceinline__ bool phiz_may_pass(const float4 &P, const float4 &Q, const float4 &R, ModInfo mp,
+                                              ModInfo mq, ModInfo mr, float d0) {
+  const float su = (P.x * Q.y - P.y * Q.x) * frcp(P.w * Q.w);
+  const float sv = (Q.x * R.y - Q.y * R.x) * frcp(Q.w * R.w);
+  const float dzpq = Q.z - P.z, dzqr = R.z - Q.z;
+  const float t1 = su * dzqr, t2 = sv * dzpq;
+  const float iP = frcp(P.w), iQ = frcp(Q.w), iR = frcp(R.w);
+  const float ePQ = (mp.hphi() * iP + mq.hphi() * iQ) + d0 * fabsf(iP - iQ);
+  const float eQR = (mq.hphi() * iQ + mr.hphi() * iR) + d0 * fabsf(iQ - iR);
+  const float au = fabsf(su), av = fabsf(sv), adpq = fabsf(dzpq), adqr = fabsf(dzqr);
+  const float nl = (au * au + av * av) * kThird;
+  const float tol = ((adqr * ePQ + adpq * eQR) + (au * (mq.ez() + mr.ez()) + av * (mp.ez() + mq.ez()))) +
+                    nl * (au * adqr + av * adpq);
+  return fabsf(t1 - t2) <= (tol * kMargin + kEps) * 1.00001f + 1e-5f * (fabsf(t1) + fabsf(t2));
+}
+
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
   __shared__ float4 s_p[kWaves][3][64], s_tin[kWaves][64];
   __shared__ int s_mi[kWaves][64], s_lo[kWaves][64], s_cnt[kWaves][64], s_seg[kWaves][65], s_cached[kWaves][64];
+  __shared__ int s_qe[kWaves][128], s_qc[kWaves][128];  // pairs past the pre-test, in pair order
   const int n_t3 = w.ctr[C_NT3];
   const int n_ls = w.ctr[C_NLS];
   const int wv = threadIdx.x >> 6, lane = lane_id();
@@ -856,19 +957,15 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
     s_cnt[wv][lane] = 0;
     s_cached[wv][lane] = cached;
     const int total = wave_segments(n, s_seg[wv]);
-    int e = 0;
-    for (int c0 = 0; c0 < total; c0 += 64) {
-      const int c = c0 + lane;
+    // the exact selection on the first nb (<= 64) queued pairs (as in k_t3)
+    auto select = [&](int nb) {
       bool pass = false;
-      int t2 = 0, first = 0, before = 0;
+      int e = 0, t2 = 0;
       int4 cde = make_int4(0, 0, 0, 0);
       float at[8];
-      if (c < total) {
-        while (s_seg[wv][e + 1] <= c) ++e;
-        first = max(s_seg[wv][e] - c0, 0);
-        before = s_cnt[wv][e];
-        const int idx = c - s_seg[wv][e];
-        t2 = s_cached[wv][e] ? w.t5_cache[(long)((int)p0 + e) * kT5Cache + idx] : s_lo[wv][e] + idx;
+      if (lane < nb) {
+        e = s_qe[wv][lane];
+        t2 = s_qc[wv][lane];
         cde = w.t3_md[t2];
         float4 P[5];
         ModInfo M[5];
@@ -881,23 +978,25 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
         M[4].bits = g.info[w.md_mod[cde.z]];
         pass = t5_pass(P, M, s_tin[wv][e], w.t3_attr[t2], at, g.d0max, g.t5cut);
       }
+      const int first = run_first_lane(e, nb);
       const unsigned long long m = __ballot(pass);
-      if (!FILL && pass) {
-        const int r = pair_rank(m, first, before);
-        if (r < g.tiles.t5_cache) w.t5_cache[(long)((int)p0 + e) * kT5Cache + r] = t2;
-      }
-      if (FILL && pass) {
-        const int t1e = (int)p0 + e;
-        const int pos = w.t5_off[t1e] + pair_rank(m, first, before);
-        if (pos < w.cap_t5) {
-          const int4 abc = w.t3_md[t1e];
-          w.t5_t3[pos] = make_int2(t1e, t2);
-          int *md = w.t5_md + 5 * (long)pos;
-          md[0] = abc.x; md[1] = abc.y; md[2] = abc.z; md[3] = cde.y; md[4] = cde.z;
-          float *dst = w.t5_attr + 8 * (long)pos;
+      if (pass) {
+        const int r = pair_rank(m, first, s_cnt[wv][e]);
+        if (!FILL) {
+          if (r < g.tiles.t5_cache) w.t5_cache[(long)((int)p0 + e) * kT5Cache + r] = t2;
+        } else {
+          const int t1e = (int)p0 + e;
+          const int pos = w.t5_off[t1e] + r;
+          if (pos < w.cap_t5) {
+            const int4 abc = w.t3_md[t1e];
+            w.t5_t3[pos] = make_int2(t1e, t2);
+            int *md = w.t5_md + 5 * (long)pos;
+            md[0] = abc.x; md[1] = abc.y; md[2] = abc.z; md[3] = cde.y; md[4] = cde.z;
+            float *dst = w.t5_attr + 8 * (long)pos;
 #pragma unroll
-          for (int k = 0; k < 8; ++k) dst[k] = at[k];
-          w.t5_keep[pos] = 1;  // until a better duplicate is found
+            for (int k = 0; k < 8; ++k) dst[k] = at[k];
+            w.t5_keep[pos] = 1;  // until a better duplicate is found
+          }
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -905,7 +1004,55 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
       if (pass) atomicAdd(&s_cnt[wv][e], 1);  // LDS
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
+    };
+    int nq = 0;
+    int e = 0;
+    for (int c0 = 0; c0 < total; c0 += 64) {
+      const int c = c0 + lane;
+      bool keep = false;
+      int t2 = 0;
+      if (c < total) {
+        while (s_seg[wv][e + 1] <= c) ++e;
+        const int idx = c - s_seg[wv][e];
+        t2 = s_cached[wv][e] ? w.t5_cache[(long)((int)p0 + e) * kT5Cache + idx] : s_lo[wv][e] + idx;
+        // the radius compatibility cut exactly (no division), then the fast azimuth-z test
+        const float4 tin = s_tin[wv][e], tout = w.t3_attr[t2];
+        if (fabsf(tin.x - tout.x) <= tin.y + tout.y) {
+          const int4 cde = w.t3_md[t2];
+          const int mi = s_mi[wv][e];
+          keep = phiz_may_pass(s_p[wv][0][e], s_p[wv][2][e], w.md_pos[cde.z], ModInfo{mi & 0xff},
+                               ModInfo{mi >> 16}, ModInfo{g.info[w.md_mod[cde.z]]}, g.d0max);
+        }
+      }
+      const unsigned long long m = __ballot(keep);
+      if (keep) {
+        const int q = nq + lanes_below(m);
+        s_qe[wv][q] = e;
+        s_qc[wv][q] = t2;
+      }
+      nq += __popcll(m);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (nq >= 64) {
+        select(64);
+        const int rest = nq - 64;
+        int ve = 0, vc = 0;
+        if (lane < rest) {
+          ve = s_qe[wv][64 + lane];
+          vc = s_qc[wv][64 + lane];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) {
+          s_qe[wv][lane] = ve;
+          s_qc[wv][lane] = vc;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        nq = rest;
+      }
     }
+    if (nq > 0) select(nq);
     if (!FILL && t1 < n_t3) w.t5_cnt[t1] = s_cnt[wv][lane];
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
