@@ -43,6 +43,7 @@ constexpr size_t kAlign = 256;
 constexpr int kTupleW[7] = {2, 4, 6, 10, 1, 7, 11};
 constexpr int kAttrW[7] = {0, 2, 4, 8, 5, 3, 3};
 constexpr int64_t kMaxCap = 8000000;  // bounded by the two-level device scan (4096 x 2048)
+constexpr int64_t kMaxTc = 4096L * 2048 - 1;  // pT5 + pT3 + T5 + pLS capacities: one scan of candidates
 std::atomic<int> g_timed_site{-1};
 
 }  // namespace
@@ -138,8 +139,9 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
 #define F4(n) reinterpret_cast<float4 *>(take(sizeof(float4) * (size_t)(n)))
   Ws t{};
   t.ctr = ctr;
-  t.bcnt = I(2 * M + 1); t.boff = I(2 * M + 1); t.bcur = I(2 * M);
-  t.hidx_tmp = I(N + 1); t.hidx = I(N + 1); t.hpos = F4(N + 1); t.hslot = I(N + 1);
+  const long tiles = (long)n_coarse((int)M) * n_hit_tiles(N);
+  t.boff = I(2 * M + 1); t.tile_hist = I(tiles + 1); t.tile_off = I(tiles + 1);
+  t.hkey = I(N + 1); t.hsrc = I(N + 1); t.hidx = I(N + 1); t.hpos = F4(N + 1);
   t.md_cnt = I(M + 1); t.md_off = I(M + 1); t.md_cache = I(kMdCache * M);
   t.md_hits = I2(md); t.md_mod = I(md); t.md_pos = F4(md); t.md_stub = F2(md); t.mod_disc = F4(M);
   t.ls_cnt = I(md + 1); t.ls_off = I(md + 1); t.ls_md = I2(ls); t.ls_beta = F2(ls);
@@ -189,7 +191,9 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
     int *ct = t.ctr;
     auto sj = [&](int id, const int *in, int *out, const int *n_dev, long n_fix, long n_cap, int *req, int *clamped,
                   long cap) { t.scans[id] = ScanJob{in, out, n_dev, (int)n_fix, (int)n_cap, req, clamped, (int)cap}; };
-    sj(SC_HITS, t.bcnt, t.boff, nullptr, 2 * M, 2 * M, ct + C_NOUTER, nullptr, 0);
+    const long nt = (long)n_coarse((int)M) * n_hit_tiles(n_hits);
+    const long nt_cap = (long)n_coarse((int)M) * n_hit_tiles(n_hits_alloc >= 0 ? n_hits_alloc : n_hits);
+    sj(SC_HITS, t.tile_hist, t.tile_off, nullptr, nt, nt_cap, ct + C_NOUTER, nullptr, 0);
     sj(SC_MD, t.md_cnt, t.md_off, nullptr, M, M, ct + C_RMD, ct + C_NMD, md);
     sj(SC_LS, t.ls_cnt, t.ls_off, ct + C_NMD, 0, md, ct + C_RLS, ct + C_NLS, ls);
     sj(SC_T3, t.t3_cnt, t.t3_off, ct + C_NLS, 0, ls, ct + C_RT3, ct + C_NT3, t3);
@@ -208,8 +212,6 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
     sj(SC_EXT, t.ext_cnt, t.ext_off, ct + C_NTC, 0, p5 + p3 + t5 + S, ct + C_NEXTHITS, nullptr, 0);
     auto fj = [&](int id, int *p, long n) { t.fills[id] = FillJob{p, n}; };
     fj(FL_CTR, ct, C_COUNT);
-    fj(FL_BCNT, t.bcnt, 2 * M + 1);
-    fj(FL_BCUR, t.bcur, 2 * M);
     fj(FL_INC_CNT, t.inc_cnt, md + 1);
     fj(FL_INC_CUR, t.inc_cur, md + 1);
     fj(FL_PH_CNT, t.ph_cnt, N + 1);
@@ -259,6 +261,14 @@ lst_status lst_default_capacity(int32_t n_hits, int32_t n_seeds, lst_capacity *o
   out->t5 = clampc(N);
   out->pt3 = clampc(64 * S);
   out->pt5 = clampc(16 * S);
+  // track candidates (pT5 + pT3 + T5 + pLS) go through one device scan: keep their sum in it
+  const int64_t room = kMaxTc - S;
+  const int64_t sum = out->pt5 + out->pt3 + out->t5;
+  if (sum > room) {
+    out->t5 = std::max<int64_t>(1, out->t5 * room / sum);
+    out->pt3 = std::max<int64_t>(1, out->pt3 * room / sum);
+    out->pt5 = std::max<int64_t>(1, out->pt5 * room / sum);
+  }
   return LST_OK;
 }
 
@@ -284,6 +294,7 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   for (int m = 0; m < M; ++m)
     if (d->map_offsets[m + 1] - d->map_offsets[m] > 128)
       return fail(LST_E_INVALID, "more than 128 module-map targets for one module");
+  if (M > lst::kMaxModules) return fail(LST_E_INVALID, "more than 32,768 modules (the hit bucketing's limit)");
   auto *g = new (std::nothrow) lst_geometry_s();
   if (!g) return fail(LST_E_NOMEM, "host allocation failed");
   std::vector<int> info(M);
@@ -425,6 +436,8 @@ static lst_status resolve_caps(int B, const int32_t *nh, const int32_t *ns, cons
     if (cap) c = cap[i]; else lst_default_capacity(nh[i], ns[i], &c);
     lst_status s = check_caps(c);
     if (s != LST_OK) return s;
+    if (c.pt5 + c.pt3 + c.t5 + ns[i] > kMaxTc)
+      return fail(LST_E_INVALID, "capacities pT5 + pT3 + T5 + seeds above 8,388,607 (one device scan)");
     out[i] = lst::Caps{c.md, c.ls, c.t3, c.t5, c.pt3, c.pt5};
   }
   return LST_OK;
@@ -562,6 +575,19 @@ lst_status lst_workspace_bytes(lst_geometry g, int32_t n_hits, int32_t n_seeds, 
   return lst_batch_workspace_bytes(g, 1, &n_hits, &n_seeds, cap, bytes);
 }
 
+// The hit bucketing scans one count per (coarse bucket, tile of input hits):
+// an event must keep that within one device scan on this geometry.
+static lst_status check_bucketing(lst_geometry g, int64_t n_hits) {
+  const int64_t items = (int64_t)lst::n_coarse(g->g.n_mod) * lst::n_hit_tiles(n_hits);
+  if (items > kMaxTc) {
+    char msg[200];
+    snprintf(msg, sizeof(msg), "%lld hits: above what the hit bucketing scans on a detector of %d modules",
+             (long long)n_hits, g->g.n_mod);
+    return fail(LST_E_INVALID, msg);
+  }
+  return LST_OK;
+}
+
 static lst_status check_event_desc(const lst_event_desc &ev) {
   if (ev.n_hits < 0 || ev.n_seeds < 0) return fail(LST_E_INVALID, "negative n_hits or n_seeds");
   if (ev.n_hits > kMaxCap || ev.n_seeds > kMaxCap)
@@ -654,6 +680,7 @@ lst_status lst_enqueue_batch(lst_geometry g, int32_t B, const lst_event_desc *ev
   std::vector<int32_t> nh(B), ns(B);
   for (int i = 0; i < B; ++i) {
     lst_status s = check_event_desc(evs[i]);
+    if (s == LST_OK) s = check_bucketing(g, evs[i].n_hits);
     if (s != LST_OK) return s;
     nh[i] = evs[i].n_hits;
     ns[i] = evs[i].n_seeds;
@@ -763,12 +790,15 @@ lst_status lst_build_event_static(lst_geometry g, const lst_event_desc *ev, cons
       (max_tc_hits > 0 && !hits))
     return fail(LST_E_INVALID, "lst_build_event_static: bad argument");
   lst_status s = check_event_desc(*ev);
+  if (s == LST_OK) s = check_bucketing(g, ev->n_hits);
   if (s != LST_OK) return s;
   if (ev->n_seeds > kMaxCap / 4) return fail(LST_E_INVALID, "n_seeds above 2e6");
   lst_capacity c;
   if (cap) c = *cap; else lst_default_capacity(ev->n_hits, ev->n_seeds, &c);
   s = check_caps(c);
   if (s != LST_OK) return s;
+  if (c.pt5 + c.pt3 + c.t5 + ev->n_seeds > kMaxTc)
+    return fail(LST_E_INVALID, "capacities pT5 + pT3 + T5 + seeds above 8,388,607 (one device scan)");
   const lst::Caps caps{c.md, c.ls, c.t3, c.t5, c.pt3, c.pt5};
   const size_t head = header_bytes(1);
   const size_t need = head + lst::workspace_layout(g->g.n_mod, ev->n_hits, ev->n_seeds, caps, nullptr, nullptr, nullptr);
@@ -1000,6 +1030,9 @@ lst_status lst_plan_create(lst_geometry g, int32_t B, int32_t max_hits, int32_t 
   if (!out) return fail(LST_E_INVALID, "lst_plan_create: NULL out");
   *out = nullptr;
   if (!g || !workspace || B < 1 || B > 65535) return fail(LST_E_INVALID, "lst_plan_create: bad argument");
+  if (max_hits < 0) return fail(LST_E_INVALID, "lst_plan_create: negative max_hits");
+  lst_status bs = check_bucketing(g, max_hits);
+  if (bs != LST_OK) return bs;
   std::vector<lst::Caps> c;
   lst_status s = resolve_caps(1, &max_hits, &max_seeds, cap, c);
   if (s != LST_OK) return s;
@@ -1258,6 +1291,11 @@ static void server_loop(lst_server_s *s) {
             q.attempts += 1;
             q.region = lst::workspace_layout(s->geom->g.n_mod, q.ev.n_hits, q.ev.n_seeds, q.caps, nullptr, nullptr,
                                              nullptr);
+            const bool scan_ok = q.caps.pt5 + q.caps.pt3 + q.caps.t5 + q.ev.n_seeds <= kMaxTc;
+            if (!scan_ok) {
+              s->results.push_back(r);  // the grown capacities would exceed the candidates' scan
+              continue;
+            }
             if (q.region + header_bytes(1) <= s->pool_bytes) {
               rerun.push_back(q);
               rerun_evs.push_back(evs[i]);
@@ -1395,6 +1433,7 @@ lst_status lst_server_submit_with_capacity(lst_server s, const lst_event_desc *e
                                            int64_t id, double arrival_s) {
   if (!s || !ev) return fail(LST_E_INVALID, "lst_server_submit: NULL argument");
   lst_status st = check_event_desc(*ev);
+  if (st == LST_OK) st = check_bucketing(s->geom, ev->n_hits);
   if (st != LST_OK) return st;
   std::vector<lst::Caps> caps;
   st = resolve_caps(1, &ev->n_hits, &ev->n_seeds, cap, caps);
@@ -1490,6 +1529,7 @@ lst_status lst_autotune(lst_geometry g, int32_t B, const lst_event_desc *evs, co
   std::vector<int32_t> nh(B), ns(B);
   for (int i = 0; i < B; ++i) {
     lst_status s = check_event_desc(evs[i]);
+    if (s == LST_OK) s = check_bucketing(g, evs[i].n_hits);
     if (s != LST_OK) return s;
     nh[i] = evs[i].n_hits;
     ns[i] = evs[i].n_seeds;
@@ -1620,6 +1660,7 @@ lst_status lst_autotune_tiles(lst_geometry g, int32_t B, const lst_event_desc *e
   std::vector<int32_t> nh(B), ns(B);
   for (int i = 0; i < B; ++i) {
     lst_status s = check_event_desc(evs[i]);
+    if (s == LST_OK) s = check_bucketing(g, evs[i].n_hits);
     if (s != LST_OK) return s;
     nh[i] = evs[i].n_hits;
     ns[i] = evs[i].n_seeds;

@@ -144,7 +144,9 @@ static inline int grid_for(long n, int block = kBlock) {
 
 // Scan job `job` of every event of the batch; n_cap bounds the item count.
 static void scan(const Ws *wb, int B, int job, long n_cap, hipStream_t st) {
-  const int nb = (int)((n_cap + kScanTile) / kScanTile);  // tiles covering n_cap + 1 outputs
+  // tiles covering n_cap + 1 outputs; capacities are checked on the host so that every scan's
+  // count stays below kMaxScanBlocks tiles, and the grid never exceeds the tile-sum array
+  const int nb = (int)std::min<long>((n_cap + kScanTile) / kScanTile, kMaxScanBlocks);
   k_scan_reduce<<<dim3(nb, B), kBlock, 0, st>>>(wb, job);
   k_scan_apply<<<dim3(nb, B), kBlock, 0, st>>>(wb, job);
 }
@@ -199,21 +201,76 @@ void launch_tc_export(const Ws *d_ws, int max_tc, int max_hits, int *type, int *
 }
 
 // ------------------------------------------------------------- a0: hits
-// Validation of the inputs and histogram of outer-tracker hits per (module, sensor).
-__global__ void k_hits_count(const Ws *__restrict__ wb, int n_mod) {
+// Hits are bucketed by key = 2 module + sensor, stably (input order within a
+// key), with no global atomic: an LSD-free two-level counting sort.
+//  1. k_hits_count: each wave counts the hits of its tile of kHitTile input
+//     hits per coarse bucket (key >> kFineBits) in LDS and writes the counts,
+//     coarse-bucket major (and validates hits and seeds);
+//  2. an exclusive scan of those counts gives every (coarse bucket, tile) its
+//     first position;
+//  3. k_hits_scatter: each wave walks its tile again in input order, 64 hits
+//     at a time; hits of one coarse bucket in a round find each other with
+//     ballots and take consecutive positions after the bucket's running
+//     position (stable), writing (key, input index);
+//  4. k_bucket_sort: one wave per coarse bucket counts its keys, writes their
+//     offsets and places every hit (input index, x, y, z, r) at its key's
+//     running position, again 64 hits at a time in order.
+
+// The bucket key of hit i, or -1 for a pixel hit or invalid data (*bad).
+__device__ __forceinline__ int hit_key(const Ws &w, int i, int n_mod, bool *bad) {
+  const int m = w.module[i];
+  const float x = w.x[i], y = w.y[i], z = w.z[i];
+  bool b = !(isfinite(x) && isfinite(y) && isfinite(z)) || m < -1 || m >= n_mod;
+  int key = -1;
+  if (m >= 0) {
+    const int sn = w.sensor[i];
+    b |= (sn != 0 && sn != 1);
+    if (!b) key = 2 * m + sn;
+  }
+  *bad = b;
+  return key;
+}
+
+// Lanes (of the active ones) whose `nbits`-bit value v equals this lane's.
+__device__ __forceinline__ unsigned long long match_value(int v, int nbits, bool active) {
+  unsigned long long m = __ballot(active);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (v >> b) & 1;
+    const unsigned long long bb = __ballot(active && bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+__device__ __forceinline__ int bits_for(int n) {  // bits of the values 0 .. n - 1
+  int b = 0;
+  while ((1 << b) < n) ++b;
+  return b;
+}
+
+// One wave per tile (four per block): the tile's coarse counts live in LDS.
+__global__ __launch_bounds__(kBlock) void k_hits_count(const Ws *__restrict__ wb, int n_mod) {
+  __shared__ int s_h[kWaves][kMaxCoarse];
   const Ws &w = wb[blockIdx.y];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < w.n_hits; i += gridDim.x * blockDim.x) {
-    const int m = w.module[i];
-    const float x = w.x[i], y = w.y[i], z = w.z[i];
-    bool bad = !(isfinite(x) && isfinite(y) && isfinite(z)) || m < -1 || m >= n_mod;
-    int slot = -1;
-    if (m >= 0) {
-      const int sn = w.sensor[i];
-      bad |= (sn != 0 && sn != 1);
-      if (!bad) slot = atomicAdd(&w.bcnt[2 * m + sn], 1);
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int nc = n_coarse(n_mod), ntw = n_hit_tiles(w.n_hits);
+  const int tw = blockIdx.x * (blockDim.x >> 6) + wv;
+  if (tw < ntw) {
+    for (int c = lane; c < nc; c += 64) s_h[wv][c] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    bool any_bad = false;
+    const int i1 = min(w.n_hits, (tw + 1) * kHitTile);
+    for (int i = tw * kHitTile + lane; i < i1; i += 64) {
+      bool bad;
+      const int key = hit_key(w, i, n_mod, &bad);
+      any_bad |= bad;
+      if (key >= 0) atomicAdd(&s_h[wv][key >> kFineBits], 1);  // LDS
     }
-    w.hslot[i] = slot;  // arrival order in the bucket; k_bucket_sort restores input order
-    if (bad) atomicOr(&w.ctr[C_STATUS], (int)ST_BAD_HIT);
+    if (any_bad) atomicOr(&w.ctr[C_STATUS], (int)ST_BAD_HIT);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int c = lane; c < nc; c += 64) w.tile_hist[(long)c * ntw + tw] = s_h[wv][c];
   }
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
     bool bad = !(w.q[s] == 1 || w.q[s] == -1) || !(isfinite(w.px[s]) && isfinite(w.py[s]) && isfinite(w.pz[s]));
@@ -227,42 +284,114 @@ __global__ void k_hits_count(const Ws *__restrict__ wb, int n_mod) {
   }
 }
 
-__global__ void k_hits_scatter(const Ws *__restrict__ wb, int n_mod) {
+__global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ wb, int n_mod) {
+  __shared__ int s_run[kWaves][kMaxCoarse];
   const Ws &w = wb[blockIdx.y];
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < w.n_hits; i += gridDim.x * blockDim.x) {
-    const int slot = w.hslot[i];  // >= 0 only for a valid outer-tracker hit
-    if (slot < 0) continue;
-    w.hidx_tmp[w.boff[2 * w.module[i] + w.sensor[i]] + slot] = i;
+  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int nc = n_coarse(n_mod), ntw = n_hit_tiles(w.n_hits);
+  const int tw = blockIdx.x * (blockDim.x >> 6) + wv;
+  if (tw >= ntw) return;
+  for (int c = lane; c < nc; c += 64) s_run[wv][c] = w.tile_off[(long)c * ntw + tw];
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int nbits = bits_for(nc);
+  const int i0 = tw * kHitTile, i1 = min(w.n_hits, i0 + kHitTile);
+  for (int r0 = i0; r0 < i1; r0 += 64) {
+    const int i = r0 + lane;
+    bool bad = true;
+    const int key = i < i1 ? hit_key(w, i, n_mod, &bad) : -1;
+    const bool act = key >= 0;
+    const int c = act ? key >> kFineBits : 0;
+    const unsigned long long peers = match_value(c, nbits, act);
+    int base = 0;
+    if (act) {
+      base = s_run[wv][c];
+      const int pos = base + lanes_below(peers);
+      w.hkey[pos] = key;
+      w.hsrc[pos] = i;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (act && lanes_below(peers) == 0) s_run[wv][c] = base + __popcll(peers);  // the bucket's first lane
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
-// One wave per bucket: order the bucket by input index (stable bucketing) and
-// write the hits' coordinates and radius in bucket order.
-__global__ void k_bucket_sort(const Ws *__restrict__ wb, int n_buckets) {
+// One block of kSortWaves waves per coarse bucket: the bucket's hits (in input
+// order) are split into kSortWaves consecutive runs; each wave counts its
+// run's keys, the block turns the counts into each (wave, key)'s first
+// position (key order, then wave order: stable), writes the keys' offsets, and
+// every wave places its run's hits 64 at a time in order.
+constexpr int kSortWaves = 8;
+__global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__restrict__ wb, int n_mod) {
+  __shared__ int s_cnt[kSortWaves][kFineKeys];
+  __shared__ int s_key0[kFineKeys];
   const Ws &w = wb[blockIdx.y];
-  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (wave >= n_buckets) return;
-  const int b0 = w.boff[wave], n = w.boff[wave + 1] - b0;
-  const int lane = lane_id();
-  if (n <= 64) {
-    // the bucket in registers, one hit per lane; ranks by shuffles
-    const int me = lane < n ? w.hidx_tmp[b0 + lane] : 0x7fffffff;
-    int rank = 0;
-    for (int j = 0; j < n; ++j) rank += __shfl(me, j, 64) < me ? 1 : 0;
-    if (lane < n) {
-      const float x = w.x[me], y = w.y[me], z = w.z[me];
-      w.hidx[b0 + rank] = me;
-      w.hpos[b0 + rank] = make_float4(x, y, z, sqrtf(x * x + y * y));
+  const int wv = threadIdx.x >> 6, lane = lane_id(), t = threadIdx.x;
+  const int nc = n_coarse(n_mod), ntw = n_hit_tiles(w.n_hits), nkeys = 2 * n_mod;
+  const int c = blockIdx.x;
+  if (c >= nc) return;  // the whole block
+  const int j0 = w.tile_off[(long)c * ntw], j1 = w.tile_off[(long)(c + 1) * ntw];
+  const long L = j1 - j0;
+  const int a = j0 + (int)(L * wv / kSortWaves), b = j0 + (int)(L * (wv + 1) / kSortWaves);
+  for (int f = lane; f < kFineKeys; f += 64) s_cnt[wv][f] = 0;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int j = a + lane; j < b; j += 64) atomicAdd(&s_cnt[wv][w.hkey[j] & (kFineKeys - 1)], 1);  // LDS
+  __syncthreads();
+  // each key's total over the waves, then the keys' first positions (wave 0: two keys per lane)
+  int tot = 0;
+  if (t < kFineKeys)
+    for (int q = 0; q < kSortWaves; ++q) tot += s_cnt[q][t];
+  if (t < kFineKeys) s_key0[t] = tot;
+  __syncthreads();
+  if (wv == 0) {
+    static_assert(kFineKeys <= 64, "one key per lane");
+    const int x0 = lane < kFineKeys ? s_key0[lane] : 0;
+    int x = x0;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int y = __shfl_up(x, o, 64);
+      if (lane >= o) x += y;
     }
-    return;
+    const int ex = j0 + x - x0;
+    const int k = c * kFineKeys + lane;
+    if (lane < kFineKeys) {
+      s_key0[lane] = ex;
+      if (k < nkeys) w.boff[k] = ex;
+    }
+    if (c == nc - 1 && lane == 0) w.boff[nkeys] = j1;
   }
-  for (int k = lane; k < n; k += 64) {
-    const int me = w.hidx_tmp[b0 + k];
-    int rank = 0;
-    for (int j = 0; j < n; ++j) rank += (w.hidx_tmp[b0 + j] < me) ? 1 : 0;
-    const float x = w.x[me], y = w.y[me], z = w.z[me];
-    w.hidx[b0 + rank] = me;
-    w.hpos[b0 + rank] = make_float4(x, y, z, sqrtf(x * x + y * y));
+  __syncthreads();
+  // first position of each (wave, key): the key's first position plus the earlier waves' counts
+  if (t < kFineKeys) {
+    int run = s_key0[t];
+    for (int q = 0; q < kSortWaves; ++q) {
+      const int v = s_cnt[q][t];
+      s_cnt[q][t] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  for (int r0 = a; r0 < b; r0 += 64) {
+    const int j = r0 + lane;
+    const bool act = j < b;
+    const int f = act ? (w.hkey[j] & (kFineKeys - 1)) : 0;
+    const unsigned long long peers = match_value(f, kFineBits, act);
+    int base = 0;
+    if (act) {
+      base = s_cnt[wv][f];
+      const int pos = base + lanes_below(peers);
+      const int i = w.hsrc[j];
+      const float xx = w.x[i], yy = w.y[i], zz = w.z[i];
+      w.hidx[pos] = i;
+      w.hpos[pos] = make_float4(xx, yy, zz, sqrtf(xx * xx + yy * yy));
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (act && lanes_below(peers) == 0) s_cnt[wv][f] = base + __popcll(peers);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -2278,11 +2407,16 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   const bool whole = kt && kt->site == kChainSite;  // the timer brackets the whole chain
   if (whole) (void)hipEventRecord(kt->beg, st);
   // a0: buckets
-  run([&] { k_clear<<<grid(2L * M + 1), kBlock, 0, st>>>(wb, FL_CTR, FL_BCUR + 1); });
-  run([&] { k_hits_count<<<grid(N > S ? N : S), kBlock, 0, st>>>(wb, M); });
-  run([&] { scan(wb, B, SC_HITS, 2L * M, st); });
-  run([&] { k_hits_scatter<<<grid(N), kBlock, 0, st>>>(wb, M); });
-  run([&] { k_bucket_sort<<<dim3((2 * M * 64 + kBlock - 1) / kBlock, B), kBlock, 0, st>>>(wb, 2 * M); });
+  run([&] { k_clear<<<grid(C_COUNT), kBlock, 0, st>>>(wb, FL_CTR, FL_CTR + 1); });
+  const long n_tiles = n_hit_tiles(N), n_co = n_coarse(M);
+  run([&] {  // one wave per hit tile, and enough threads for the seeds' validation
+    const long waves = std::max(n_tiles, (S + 63) / 64);
+    k_hits_count<<<dim3((unsigned)std::max(1L, std::min((waves + kWaves - 1) / kWaves, 65535L)), B), kBlock, 0,
+                   st>>>(wb, M);
+  });
+  run([&] { scan(wb, B, SC_HITS, n_co * n_tiles, st); });
+  run([&] { k_hits_scatter<<<dim3((unsigned)std::max(1L, (n_tiles + kWaves - 1) / kWaves), B), kBlock, 0, st>>>(wb, M); });
+  run([&] { k_bucket_sort<<<dim3((unsigned)n_co, B), 64 * kSortWaves, 0, st>>>(wb, M); });
   // a1: MD
   run([&] {
     k_md_big<false><<<dim3(1024, B), kBlock, 0, st>>>(wb, g);

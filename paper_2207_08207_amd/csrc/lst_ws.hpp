@@ -72,7 +72,7 @@ struct FillJob {
   long n;
 };
 enum FillId : int {
-  FL_CTR, FL_BCNT, FL_BCUR, FL_INC_CNT, FL_INC_CUR, FL_PH_CNT, FL_PH_CUR, FL_O3_BEST,
+  FL_CTR, FL_INC_CNT, FL_INC_CUR, FL_PH_CNT, FL_PH_CUR, FL_O3_BEST,
   FL_O5_BEST, FL_SEED_USED, FL_T5_USED, FL_B3_CNT, FL_B3_CUR, FL_B5_CNT, FL_B5_CUR, FL_COUNT
 };
 
@@ -85,6 +85,15 @@ constexpr int kT3Cache = 2;   // triplets per parent segment whose candidate the
 constexpr int kT5Cache = 2;   // quintuplets per parent triplet whose candidate the T5 count pass keeps
 constexpr int kPt3Cache = 256;  // pT3 per seed (PU200 maximum ~190)
 constexpr int kPt5Cache = 16;   // pT5 per seed
+// Hit bucketing: wave tiles of kHitTile input hits; (module, sensor) keys in
+// coarse buckets of kFineKeys consecutive keys (at most kMaxCoarse of them,
+// so 2 n_mod <= kFineKeys * kMaxCoarse).
+constexpr int kHitTile = 1024;
+constexpr int kFineBits = 5, kFineKeys = 1 << kFineBits;
+constexpr int kMaxCoarse = 2048;
+constexpr int kMaxModules = kFineKeys * kMaxCoarse / 2;
+__host__ __device__ inline int n_coarse(int n_mod) { return (2 * n_mod + kFineKeys - 1) / kFineKeys; }
+__host__ __device__ inline int n_hit_tiles(long n_hits) { return (int)((n_hits + kHitTile - 1) / kHitTile); }
 constexpr int kPassList = 1024;  // passing objects of one seed ranked in LDS by the seed-search fill
 constexpr int kMaxSlices = 512;  // marked bins of one seed gathered into a flat list in LDS
 constexpr int kExtPerWaveMax = 16;
@@ -106,8 +115,9 @@ struct Ws {
   int cap_md, cap_ls, cap_t3, cap_t5, cap_pt3, cap_pt5, cap_tc;
   int *ctr;
   // hit buckets by (module, sensor)
-  int *bcnt, *boff, *bcur, *hidx_tmp, *hidx;
-  int *hslot;  // per input hit: its arrival slot in its (module, sensor) bucket, -1 if none
+  int *boff, *hidx;  // (module, sensor) buckets: offsets (2 n_mod + 1), input index per bucketed hit
+  int *tile_hist, *tile_off;  // hits per (coarse bucket, wave tile), coarse-bucket major, and their scan
+  int *hkey, *hsrc;  // hits in coarse-bucket order (stable): bucket key, input index
   float4 *hpos;
   // mini-doublets
   int *md_cnt, *md_off;
