@@ -388,7 +388,11 @@ lst_status lst_autotune(lst_geometry geom, int32_t B, const lst_event_desc *evs,
  *   max_slices: marked (ring, azimuth) bins of one seed gathered into one flat
  *     candidate list (more: searched bin by bin);
  *   ext_per_wave: track candidates per wavefront of the extension search
- *     (4, 8 or 16).
+ *     (4, 8 or 16);
+ *   ls_group: inner MDs per wavefront of the segment count pass (1..16),
+ *     whose selections share full wavefronts; 0 (the default) chooses per
+ *     launch from its events and MD capacity (4 for one PU200-size event, 16
+ *     for launches of 16 or more).
  * lst_tile_range gives tile i's bounds; lst_get/set_tile_config read and
  * write all lst_tile_count() values at once (LST_E_INVALID and nothing changed
  * if one is out of range).  lst_autotune_tiles times the whole chain over the

@@ -1610,11 +1610,12 @@ const TileSpec kTileSpecs[] = {
     {"pass_list", 1, lst::kPassList, {256, lst::kPassList}, 2},
     {"max_slices", 1, lst::kMaxSlices, {128, lst::kMaxSlices}, 2},
     {"ext_per_wave", 4, 16, {4, 8, 16}, 3},
+    {"ls_group", 0, lst::kLsGroup, {0, 1, lst::kLsGroup}, 3},
 };
 constexpr int kNumTiles = (int)(sizeof(kTileSpecs) / sizeof(kTileSpecs[0]));
 int *tile_field(lst::Tiles &t, int i) {
   int *f[kNumTiles] = {&t.md_cache, &t.ls_cache, &t.t3_cache, &t.t5_cache, &t.pt3_cache,
-                       &t.pt5_cache, &t.pass_list, &t.max_slices, &t.ext_per_wave};
+                       &t.pt5_cache, &t.pass_list, &t.max_slices, &t.ext_per_wave, &t.ls_group};
   return f[i];
 }
 bool tile_ok(int i, int v) {

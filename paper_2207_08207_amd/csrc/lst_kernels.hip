@@ -31,6 +31,13 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
   return __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+// Wave-uniform values in scalar registers: the compiler cannot prove a value
+// derived from threadIdx.x, or loaded through a generic pointer, uniform, and
+// would otherwise keep it (and every address computed from it) in vector
+// registers.  uload is for loads whose address is the same on every lane.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+__device__ __forceinline__ int uload(const int *p) { return __builtin_amdgcn_readfirstlane(*p); }
+
 __device__ __forceinline__ int block_sum(int v, int *s_red) {
   // wave reduction by shuffles, then across waves in LDS
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -135,6 +142,10 @@ static inline int grid_waves(long n, int block = kBlock) {
   return (int)g;
 }
 
+// Waves per launch that grid-stride kernels share among the launch's events: eight
+// per wave slot of the chip (256 CUs x 32).
+constexpr long kLaunchWaves = 8L * 256 * 32;
+
 static inline int grid_for(long n, int block = kBlock) {
   long g = (n + block - 1) / block;
   if (g < 1) g = 1;
@@ -180,7 +191,7 @@ void launch_put_desc(const Ws &w, Ws *dst, hipStream_t st) { k_put_desc<<<1, 1, 
 __global__ void k_tc_export(const Ws *__restrict__ wb, int max_tc, int max_hits, int *type, int *off, int *hits,
                             int *counts) {
   const Ws &w = wb[0];
-  const int st = w.ctr[C_STATUS], n = w.ctr[C_NTC], nh = w.ctr[C_NTCHITS];
+  const int st = w.ctr[C_STATUS], n = uload(w.ctr + C_NTC), nh = uload(w.ctr + C_NTCHITS);
   const int tid = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
   if (tid == 0) {
     counts[0] = n;
@@ -252,7 +263,7 @@ __device__ __forceinline__ int bits_for(int n) {  // bits of the values 0 .. n -
 __global__ __launch_bounds__(kBlock) void k_hits_count(const Ws *__restrict__ wb, int n_mod) {
   __shared__ int s_h[kWaves][kMaxCoarse];
   const Ws &w = wb[blockIdx.y];
-  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int wv = wave_id(), lane = lane_id();
   const int nc = n_coarse(n_mod), ntw = n_hit_tiles(w.n_hits);
   const int tw = blockIdx.x * (blockDim.x >> 6) + wv;
   if (tw < ntw) {
@@ -287,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_hits_count(const Ws *__restrict__ wb
 __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ wb, int n_mod) {
   __shared__ int s_run[kWaves][kMaxCoarse];
   const Ws &w = wb[blockIdx.y];
-  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int wv = wave_id(), lane = lane_id();
   const int nc = n_coarse(n_mod), ntw = n_hit_tiles(w.n_hits);
   const int tw = blockIdx.x * (blockDim.x >> 6) + wv;
   if (tw >= ntw) return;
@@ -328,7 +339,7 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__res
   __shared__ int s_cnt[kSortWaves][kFineKeys];
   __shared__ int s_key0[kFineKeys];
   const Ws &w = wb[blockIdx.y];
-  const int wv = threadIdx.x >> 6, lane = lane_id(), t = threadIdx.x;
+  const int wv = wave_id(), lane = lane_id(), t = threadIdx.x;
   const int nc = n_coarse(n_mod), ntw = n_hit_tiles(w.n_hits), nkeys = 2 * n_mod;
   const int c = blockIdx.x;
   if (c >= nc) return;  // the whole block
@@ -429,7 +440,7 @@ template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
   __shared__ float4 s_lo[kWaves][kMdStage], s_up[kWaves][kMdStage];
-  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;
   for (int m = blockIdx.x * wpb + wv; m < g.n_mod; m += gridDim.x * wpb) {
     const int lo0 = w.boff[2 * m], nlo = w.boff[2 * m + 1] - lo0;
@@ -670,7 +681,9 @@ __device__ __forceinline__ bool ls_window_may_pass(const float4 &A, const float4
 
 constexpr int kMaxEdges = 128;  // module-map targets per module (checked when the geometry is loaded)
 
-// One wave per inner MD a.  Its candidates -- the MDs of every module linked
+// Fill pass of the segment search for the inner MDs with more segments than
+// the count pass cached (k_ls_copy writes the others and lists these densely):
+// one wave per inner MD a.  Its candidates -- the MDs of every module linked
 // to a's module, edge by edge -- are flattened into one list that the 64
 // lanes stride over, so a wave stays full even though each linked module
 // holds few MDs; passing candidates are compacted in list order with ballot
@@ -679,21 +692,18 @@ constexpr int kMaxEdges = 128;  // module-map targets per module (checked when t
 // the latency of its dependent gathers, and more resident waves hide more of
 // it (measured 9% faster than the 77-VGPR, six-wave build; the same for the
 // triplet and quintuplet searches made them slower).
-template <bool FILL>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_ls(const Ws *__restrict__ wb,
-                                                                                        DevGeom g) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_ls_fill(const Ws *__restrict__ wb,
+                                                                                             DevGeom g) {
   const Ws &w = wb[blockIdx.y];
   __shared__ int s_pre[kWaves][kMaxEdges + 1];  // running MD count before each edge
   __shared__ int s_first[kWaves][kMaxEdges];    // first MD of each linked module
   __shared__ int s_info[kWaves][kMaxEdges];
   __shared__ float s_wmax[kWaves][kMaxEdges];   // window bound of each linked module
   __shared__ int s_q[kWaves][128], s_qi[kWaves][128];  // candidates past the pre-tests, in order
-  const int n_md = w.ctr[C_NMD];
-  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int n_md = uload(w.ctr + C_NMD);
+  const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;  // waves per block (a tuned launch may run fewer than kWaves)
   const int waves_total = gridDim.x * wpb;
-  // COUNT: every MD.  FILL: only the MDs with more segments than the count pass
-  // cached (k_ls_copy writes the others and lists these densely).
   auto process = [&](const int a) {
     const int ma = w.md_mod[a];
     const float4 A = w.md_pos[a];
@@ -736,8 +746,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const int total = run;
-    int out = FILL ? w.ls_off[a] : 0;
-    int cnt = 0;
+    int out = w.ls_off[a];
     // the full selection on the first n queued candidates (n <= 64), in candidate order
     auto select = [&](int n) {
       bool pass = false;
@@ -749,17 +758,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       }
       const unsigned long long m = __ballot(pass);
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-      if (FILL) {
-        const int pos = out + pre;
-        if (pass && pos < w.cap_ls) {
-          w.ls_md[pos] = make_int2(a, b);
-          w.ls_beta[pos] = beta;
-        }
-      } else if (pass && cnt + pre < g.tiles.ls_cache) {
-        w.ls_cache[(long)a * kLsCache + cnt + pre] = b;
+      const int pos = out + pre;
+      if (pass && pos < w.cap_ls) {
+        w.ls_md[pos] = make_int2(a, b);
+        w.ls_beta[pos] = beta;
       }
       out += __popcll(m);
-      cnt += __popcll(m);
     };
     // candidates past the azimuth pre-tests and the inner MD's own stub check (both
     // necessary conditions of ls_pass) are queued in LDS, and the full selection runs
@@ -807,18 +811,193 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       }
     }
     if (nq > 0) select(nq);
-    if (!FILL && lane == 0) {
-      w.ls_cnt[a] = cnt;
-      w.ls_ovf_flag[a] = cnt > g.tiles.ls_cache ? 1 : 0;
-    }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
   };
-  if constexpr (!FILL) {
-    for (int a = blockIdx.x * wpb + wv; a < n_md; a += waves_total) process(a);
-  } else {
-    const int n_ovf = w.ctr[C_NLSOVF];
-    for (int k = blockIdx.x * wpb + wv; k < n_ovf; k += waves_total) process(w.ls_ovf[k]);
+  const int n_ovf = uload(w.ctr + C_NLSOVF);
+  for (int k = blockIdx.x * wpb + wv; k < n_ovf; k += waves_total) process(w.ls_ovf[k]);
+}
+
+
+// Count pass of the segment search: one wave per group of kLsGroup
+// consecutive inner MDs.  Each inner MD's candidates go through the pre-tests
+// as in k_ls_fill, but the queue of candidates past them is shared by the
+// group, so the full selection runs on full waves of (inner MD, candidate)
+// pairs rather than on the ~15 a single MD queues.  The pairs of one inner MD
+// are consecutive in the queue; a passing pair's rank among its MD's passing
+// pairs is the MD's count from earlier flushes plus the passing lanes of its
+// run below it.  Writes each MD's count and caches up to tiles.ls_cache
+// partners in candidate order.  The group size trades the fuller selection
+// waves against the number of waves in flight (tiles.ls_group; see
+// ls_group_for).
+
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_ls_count(
+    const Ws *__restrict__ wb, DevGeom g, int group) {
+  const Ws &w = wb[blockIdx.y];
+  // linked modules left with candidates, in map order: first MD, candidates before it,
+  // module info, window bound (bits)
+  __shared__ int4 s_edge[kWaves][kMaxEdges];
+  __shared__ int s_mark[kWaves][64];            // a linked module's candidates start here
+  __shared__ int s_q[kWaves][128], s_qi[kWaves][128], s_qg[kWaves][128];  // queued pairs, in order
+  __shared__ float4 s_A[kWaves][kLsGroup];      // the group's inner MDs
+  __shared__ float2 s_sa[kWaves][kLsGroup];
+  __shared__ int s_mia[kWaves][kLsGroup], s_cnt[kWaves][kLsGroup];
+  const int n_md = uload(w.ctr + C_NMD);
+  const int wv = wave_id(), lane = lane_id();
+  const int wpb = blockDim.x >> 6;
+  const int waves_total = gridDim.x * wpb;
+  const int n_grp = (n_md + group - 1) / group;
+  const int keep = g.tiles.ls_cache;
+  for (int gi = blockIdx.x * wpb + wv; gi < n_grp; gi += waves_total) {
+    const int a0 = gi * group;
+    const int na = min(group, n_md - a0);
+    if (lane < na) {
+      const int a = a0 + lane;
+      s_A[wv][lane] = w.md_pos[a];
+      s_sa[wv][lane] = get_stub(w, g, a);
+      s_mia[wv][lane] = g.info[w.md_mod[a]];
+      s_cnt[wv][lane] = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // the full selection on the first n queued pairs (n <= 64)
+    auto select = [&](int n) {
+      bool pass = false;
+      int b = 0, q = -1;
+      if (lane < n) {
+        b = s_q[wv][lane];
+        q = s_qg[wv][lane];
+        float2 beta;
+        pass = ls_pass(s_A[wv][q], w.md_pos[b], s_sa[wv][q], get_stub(w, g, b), ModInfo{s_mia[wv][q]},
+                       ModInfo{s_qi[wv][lane]}, &beta, g.d0max);
+      }
+      const unsigned long long m = __ballot(pass);
+      const int qp = __shfl_up(q, 1, 64), qn = __shfl_down(q, 1, 64);
+      const unsigned long long starts = __ballot(lane == 0 || q != qp);
+      const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+      const int first = 63 - __clzll(starts & upto);  // first lane of this lane's run
+      const int below = __popcll(m & ((1ull << lane) - 1ull) & ~((1ull << first) - 1ull));
+      int before = 0;
+      if (lane < n) before = s_cnt[wv][q];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (pass && before + below < keep) w.ls_cache[(long)(a0 + q) * kLsCache + before + below] = b;
+      if (lane < n && (lane == n - 1 || qn != q)) s_cnt[wv][q] = before + below + (pass ? 1 : 0);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    };
+    int nq = 0;
+    for (int k = 0; k < na; ++k) {
+      // the inner MD's data are read from LDS where they are used, after each round's
+      // fence, so that they are not held in registers across the selection
+      const int ma = uload(w.md_mod + a0 + k);
+      const int e0 = uload(g.map_off + ma);
+      const int ne = uload(g.map_off + ma + 1) - e0;  // <= kMaxEdges, checked when the geometry is loaded
+      int run = 0, n_ne = 0;
+      for (int k0 = 0; k0 < ne; k0 += 64) {
+        const int kk = k0 + lane;
+        int first = 0, cnt = 0, info = 0;
+        float wm = 0.0f;
+        const float4 A = s_A[wv][k];
+        const ModInfo mia{s_mia[wv][k]};
+        if (kk < ne) {
+          const int mb = g.map_tgt[e0 + kk];
+          first = w.md_off[mb];
+          const int last = min(w.md_off[mb + 1], n_md);
+          cnt = last > first ? last - first : 0;
+          info = g.info[mb];
+          if (cnt > 0) {
+            const float4 disc = w.mod_disc[mb];
+            wm = ls_window_bound(A, mia, disc, ModInfo{info}, g.d0max);
+            if (!ls_module_may_pass(A, disc, wm)) cnt = 0;
+          }
+        }
+        int x = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+          const int y = __shfl_up(x, o, 64);
+          if (lane >= o) x += y;
+        }
+        const unsigned long long live = __ballot(cnt > 0);
+        if (cnt > 0) s_edge[wv][n_ne + lanes_below(live)] = make_int4(first, run + x - cnt, info, __float_as_int(wm));
+        n_ne += __popcll(live);
+        run += __builtin_amdgcn_readfirstlane(__shfl(x, 63, 64));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const int total = run;
+      // Candidates go 64 per round.  The candidate c of lane L lies in the last module
+      // whose candidates start at or before c: the modules starting before the round
+      // (jlo of them) plus those starting at or below L in it, found by marking the
+      // round's starts (distinct, as every listed module has candidates) and a ballot.
+      int jlo = 0;
+      // at least one round, so that the group's last MD flushes the queue
+      for (int c0 = 0; c0 < (total > 0 ? total : 1); c0 += 64) {
+        s_mark[wv][lane] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (jlo + lane < n_ne) {
+          const int p = s_edge[wv][jlo + lane].y - c0;  // >= 0: it starts at or after c0
+          if (p < 64) s_mark[wv][p] = 1;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const unsigned long long starts = __ballot(s_mark[wv][lane] != 0);
+        const int c = c0 + lane;
+        bool keep_c = false;
+        int b = 0, info = 0;
+        if (c < total) {
+          const float4 A = s_A[wv][k];
+          const float2 sa = s_sa[wv][k];
+          const ModInfo mia{s_mia[wv][k]};
+          const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+          const int4 E = s_edge[wv][jlo - 1 + __popcll(starts & upto)];
+          b = E.x + (c - E.y);
+          const float4 Bp = w.md_pos[b];
+          info = E.z;
+          keep_c = ls_window_may_pass(A, Bp, __int_as_float(E.w)) &&
+                   ls_inner_stub_may_pass(A, Bp, sa, mia, ModInfo{info}, g.d0max);
+        }
+        jlo += __popcll(starts);
+        const unsigned long long m = __ballot(keep_c);
+        if (keep_c) {
+          const int pos = nq + lanes_below(m);
+          s_q[wv][pos] = b;
+          s_qi[wv][pos] = info;
+          s_qg[wv][pos] = k;
+        }
+        nq += __popcll(m);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const bool fin = k == na - 1 && c0 + 64 >= total;
+        while (nq >= 64 || (fin && nq > 0)) {
+          select(nq < 64 ? nq : 64);
+          const int rest = nq > 64 ? nq - 64 : 0;  // < 64: move the tail of the queue to its front
+          int vb = 0, vi = 0, vg = 0;
+          if (lane < rest) {
+            vb = s_q[wv][64 + lane];
+            vi = s_qi[wv][64 + lane];
+            vg = s_qg[wv][64 + lane];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          if (lane < rest) {
+            s_q[wv][lane] = vb;
+            s_qi[wv][lane] = vi;
+            s_qg[wv][lane] = vg;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          nq = rest;
+        }
+      }
+    }
+    if (lane < na) {
+      const int c = s_cnt[wv][lane];
+      w.ls_cnt[a0 + lane] = c;
+      w.ls_ovf_flag[a0 + lane] = c > keep ? 1 : 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
 }
 
@@ -850,6 +1029,31 @@ __device__ __forceinline__ int wave_segments(int n, int *seg) {
   return total;
 }
 
+// Parent of each lane's pair in a round of 64 consecutive pairs [c0, c0 + 64)
+// of a wave's flattened (parent, candidate) list, where lane k's parent owns
+// pairs [start, start + n) (wave_segments' prefix): every non-empty parent
+// starting in the round marks its first position (distinct positions), and a
+// lane's parent is the last mark at or below it, else `carry`, the parent of
+// the previous round's last pair (0 before the first round).  No per-lane walk
+// over the prefix.  Called by the whole wave; updates carry.
+__device__ __forceinline__ int round_parent(int start, int n, int c0, int *mark, int &carry) {
+  const int lane = lane_id();
+  mark[lane] = -1;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (n > 0 && start >= c0 && start < c0 + 64) mark[start - c0] = lane;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  const int mk = mark[lane];
+  const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+  const unsigned long long sm = __ballot(mk >= 0) & upto;
+  const int from = sm ? 63 - (int)__builtin_clzll(sm) : 0;
+  const int got = __shfl(mk, from, 64);
+  const int e = sm ? got : carry;
+  carry = __builtin_amdgcn_readfirstlane(__shfl(e, 63, 64));
+  return e;
+}
+
 // Segments of the MDs whose partners the count pass cached: one thread per
 // (MD, cache slot), in candidate order, with the angles ls_pass reports.
 __global__ void k_ls_copy(const Ws *__restrict__ wb, int keep) {
@@ -859,7 +1063,7 @@ __global__ void k_ls_copy(const Ws *__restrict__ wb, int keep) {
     const int a = (int)(i / kLsCache), k = (int)(i % kLsCache);
     const int cnt = w.ls_cnt[a];
     if (cnt > keep) {
-      if (k == 0) w.ls_ovf[w.ls_ovf_off[a]] = a;  // searched again by k_ls<true>
+      if (k == 0) w.ls_ovf[w.ls_ovf_off[a]] = a;  // searched again by k_ls_fill
       continue;
     }
     if (k >= cnt) continue;
@@ -911,14 +1115,16 @@ __device__ __forceinline__ int run_first_lane(int v, int n) {
   return 63 - __builtin_clzll(starts & upto);
 }
 
+// Seven waves per SIMD (at most 72 VGPRs, no spills).
 template <bool FILL>
-__global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeom g) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_t3(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
   __shared__ float4 s_a[kWaves][64], s_b[kWaves][64];
   __shared__ int s_mi[kWaves][64], s_lo[kWaves][64], s_cnt[kWaves][64], s_seg[kWaves][65], s_cached[kWaves][64];
   __shared__ int s_qe[kWaves][128], s_qc[kWaves][128];  // pairs past the pre-test, in pair order
-  const int n_ls = w.ctr[C_NLS];
-  const int wv = threadIdx.x >> 6, lane = lane_id();
+  __shared__ int s_mark[kWaves][64];
+  const int n_ls = uload(w.ctr + C_NLS);
+  const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;
   for (long p0 = ((long)blockIdx.x * wpb + wv) * 64; p0 < n_ls; p0 += (long)gridDim.x * wpb * 64) {
     const int l1 = (int)p0 + lane;
@@ -980,13 +1186,14 @@ __global__ __launch_bounds__(kBlock) void k_t3(const Ws *__restrict__ wb, DevGeo
       __builtin_amdgcn_wave_barrier();
     };
     int nq = 0;
-    int e = 0;  // parent of this lane's pair (pairs advance monotonically)
+    const int start = s_seg[wv][lane];
+    int carry = 0;
     for (int c0 = 0; c0 < total; c0 += 64) {
       const int c = c0 + lane;
+      const int e = round_parent(start, n, c0, s_mark[wv], carry);  // parent of this lane's pair
       bool keep = false;
       int cand = 0;
       if (c < total) {
-        while (s_seg[wv][e + 1] <= c) ++e;
         const int idx = c - s_seg[wv][e];
         cand = s_cached[wv][e] ? w.t3_cache[(long)((int)p0 + e) * kT3Cache + idx] : s_lo[wv][e] + idx;
         const int cmd = w.ls_md[cand].y;
@@ -1055,9 +1262,9 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
   __shared__ float4 s_p[kWaves][3][64], s_tin[kWaves][64];
   __shared__ int s_mi[kWaves][64], s_lo[kWaves][64], s_cnt[kWaves][64], s_seg[kWaves][65], s_cached[kWaves][64];
   __shared__ int s_qe[kWaves][128], s_qc[kWaves][128];  // pairs past the pre-test, in pair order
-  const int n_t3 = w.ctr[C_NT3];
-  const int n_ls = w.ctr[C_NLS];
-  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int n_t3 = uload(w.ctr + C_NT3);
+  const int n_ls = uload(w.ctr + C_NLS);
+  const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;
   for (long p0 = ((long)blockIdx.x * wpb + wv) * 64; p0 < n_t3; p0 += (long)gridDim.x * wpb * 64) {
     const int t1 = (int)p0 + lane;
@@ -1135,7 +1342,8 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
       __builtin_amdgcn_wave_barrier();
     };
     int nq = 0;
-    int e = 0;
+    int e = 0;  // parent of this lane's pair (pairs advance monotonically; the walk keeps registers
+                // low enough for five waves per SIMD)
     for (int c0 = 0; c0 < total; c0 += 64) {
       const int c = c0 + lane;
       bool keep = false;
@@ -1191,13 +1399,13 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
 // ------------------------------------------------------------- a5: T5 dedup
 __global__ void k_t5_inc_count(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int n = w.ctr[C_NT5];
+  const int n = uload(w.ctr + C_NT5);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
     for (int k = 0; k < 5; ++k) atomicAdd(&w.inc_cnt[w.t5_md[5 * (long)t + k]], 1);
 }
 __global__ void k_t5_inc_scatter(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int n = w.ctr[C_NT5];
+  const int n = uload(w.ctr + C_NT5);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const int score = __float_as_int(w.t5_attr[8 * (long)t + 1]);
     for (int k = 0; k < 5; ++k) {
@@ -1240,10 +1448,10 @@ __device__ __forceinline__ bool better(float su, const int *hu, float st, const 
 // clears it (every writer writes 0).
 __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  __shared__ int s_mt[kWaves][5][64], s_lo[kWaves][64], s_seg[kWaves][65];
+  __shared__ int s_mt[kWaves][5][64], s_lo[kWaves][64], s_seg[kWaves][65], s_mark[kWaves][64];
   __shared__ float s_st[kWaves][64];
-  const int n = w.ctr[C_NT5];
-  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int n = uload(w.ctr + C_NT5);
+  const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;
   for (long p0 = ((long)blockIdx.x * wpb + wv) * 64; p0 < 4L * n; p0 += (long)gridDim.x * wpb * 64) {
     const long item = p0 + lane;
@@ -1263,11 +1471,12 @@ __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) 
       s_st[wv][lane] = w.t5_attr[8 * (long)t + 1];
     }
     const int total = wave_segments(cnt, s_seg[wv]);
-    int e = 0;
+    const int start = s_seg[wv][lane];
+    int carry = 0;
     for (int c0 = 0; c0 < total; c0 += 64) {
       const int c = c0 + lane;
+      const int e = round_parent(start, cnt, c0, s_mark[wv], carry);  // item of this lane's pair
       if (c >= total) continue;
-      while (s_seg[wv][e + 1] <= c) ++e;
       const int t = (int)((p0 + e) >> 2), k = (int)((p0 + e) & 3);
       const int2 ue = w.inc_list[s_lo[wv][e] + (c - s_seg[wv][e])];
       const int u = ue.x;
@@ -1548,7 +1757,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   __shared__ int s_list[FILL ? kWaves : 1][FILL ? kPassList : 1];
   __shared__ int s_pq[kWaves][128];  // candidates past the first-anchor test, awaiting the full one
   const Ws &w = wb[blockIdx.y];
-  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int wv = wave_id(), lane = lane_id();
   const int s = blockIdx.x * (int)(blockDim.x >> 6) + wv;
   if (s >= w.n_seeds) return;
   const Seed sd = load_seed(w, s);
@@ -1911,7 +2120,7 @@ __device__ __forceinline__ Dir dir_of_t5(const Ws &w, int t) {
 // pT5 TCs: every surviving pT5; marks its seed and T5 as used.
 __global__ void k_tc_pt5(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int n = w.ctr[C_NPT5];
+  const int n = uload(w.ctr + C_NPT5);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const int k = w.pt5_keep[i];
     w.f_pt5[i] = k;
@@ -1923,7 +2132,7 @@ __global__ void k_tc_pt5(const Ws *__restrict__ wb) {
 }
 __global__ void k_tc_dirs_pt5(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int n = w.ctr[C_NPT5];
+  const int n = uload(w.ctr + C_NPT5);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     if (w.f_pt5[i]) {
       const Dir d = dir_of_seed(w, w.pt5_so[i].x);
@@ -2006,7 +2215,7 @@ __device__ __forceinline__ bool near_any_wave(const Dir &d, bool active, const f
 // One wave per candidate (the query loops over binned lists with its lanes).
 __global__ void k_tc_pt3(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int n = w.ctr[C_NPT3];
+  const int n = uload(w.ctr + C_NPT3);
   const int wpb = blockDim.x >> 6;
   const int nw = gridDim.x * wpb;
   for (int i = blockIdx.x * wpb + (threadIdx.x >> 6); i < n; i += nw) {
@@ -2018,7 +2227,7 @@ __global__ void k_tc_pt3(const Ws *__restrict__ wb) {
 }
 __global__ void k_tc_dirs_pt3(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int n = w.ctr[C_NPT3];
+  const int n = uload(w.ctr + C_NPT3);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     if (w.f_pt3[i]) {
       const int s = w.pt3_so[i].x;
@@ -2030,7 +2239,7 @@ __global__ void k_tc_dirs_pt3(const Ws *__restrict__ wb) {
 // T5 TCs: surviving T5 not used by a TC-pT5 and not near any TC-pT5 or TC-pT3.
 __global__ void k_tc_t5(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int n = w.ctr[C_NT5];
+  const int n = uload(w.ctr + C_NT5);
   const int wpb = blockDim.x >> 6;
   const int nw = gridDim.x * wpb;
   for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n; t += nw) {
@@ -2043,7 +2252,7 @@ __global__ void k_tc_t5(const Ws *__restrict__ wb) {
 }
 __global__ void k_tc_dirs_t5(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int n = w.ctr[C_NT5];
+  const int n = uload(w.ctr + C_NT5);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
     if (w.f_t5[t]) {
       const Dir d = dir_of_t5(w, t);
@@ -2080,8 +2289,8 @@ __device__ __forceinline__ void ext_record(const Ws &w, int k, const int *md, in
 // Output: type, offsets, hit lists (pixel hits first, then MD hits inner to outer).
 __global__ void k_tc_write(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int n0 = w.ctr[C_NTC0], n1 = w.ctr[C_NTC1], n2 = w.ctr[C_NTC2], n3 = w.ctr[C_NTC3];
-  const int np5 = w.ctr[C_NPT5], np3 = w.ctr[C_NPT3], nt5 = w.ctr[C_NT5];
+  const int n0 = uload(w.ctr + C_NTC0), n1 = uload(w.ctr + C_NTC1), n2 = uload(w.ctr + C_NTC2), n3 = uload(w.ctr + C_NTC3);
+  const int np5 = uload(w.ctr + C_NPT5), np3 = uload(w.ctr + C_NPT3), nt5 = uload(w.ctr + C_NT5);
   const long h1 = 14L * n0, h2 = h1 + 10L * n1, h3 = h2 + 10L * n2;
   const int stride = gridDim.x * blockDim.x;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2216,9 +2425,9 @@ __global__ __launch_bounds__(kBlock) void k_tc_ext(const Ws *__restrict__ wb, De
   __shared__ float s_rsc[kWaves][64];
   __shared__ int4 s_rh[kWaves][64];
   __shared__ float4 s_ra[kWaves][64];
-  const int n = w.ctr[C_NTC];
-  const int n_ls = w.ctr[C_NLS], n_t3 = w.ctr[C_NT3];
-  const int wv = threadIdx.x >> 6, lane = lane_id();
+  const int n = uload(w.ctr + C_NTC);
+  const int n_ls = uload(w.ctr + C_NLS), n_t3 = uload(w.ctr + C_NT3);
+  const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;
   for (long p0 = ((long)blockIdx.x * wpb + wv) * kExtPerWave; p0 < n; p0 += (long)gridDim.x * wpb * kExtPerWave) {
     const int k = (int)p0 + lane;
@@ -2328,7 +2537,7 @@ __global__ __launch_bounds__(kBlock) void k_tc_ext(const Ws *__restrict__ wb, De
 // The extended collection: each candidate's hits, then those of its added MDs.
 __global__ void k_tc_ext_write(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
-  const int n = w.ctr[C_NTC];
+  const int n = uload(w.ctr + C_NTC);
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   if (tid == 0) w.ctr[C_EXT] = 1;
   for (int k = tid; k < n; k += gridDim.x * blockDim.x) {
@@ -2382,6 +2591,16 @@ bool site_tunable(int site) {
   return false;
 }
 
+// Inner MDs per wave of the segment count pass: the tile when set, else
+// enough groups for about 32k waves over the launch's events (MDs taken as a
+// quarter of the MD capacity, which defaults to the hit count): one event
+// alone gets groups of 4, launches of 16 or more PU200-size events groups of 16.
+int ls_group_for(const Tiles &t, int B, long cap_md) {
+  if (t.ls_group > 0) return t.ls_group < kLsGroup ? t.ls_group : kLsGroup;
+  const long gsz = (long)B * (cap_md / 4) / 32768;
+  return (int)std::max(1L, std::min((long)kLsGroup, gsz));
+}
+
 void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream_t st, const KernelTimer *kt,
                    const int *site_block) {
   int site = 0;
@@ -2398,9 +2617,17 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   const int M = g.n_mod;
   const long N = b.n_hits, S = b.n_seeds;  // largest of the batch
   const bool seeds = S > 0;
-  auto grid = [&](long n) { return dim3(grid_for(n), B); };
-  auto gridt = [&](long n) { return dim3(grid_for(n, tb), B); };    // tuned thread-per-item sites
-  auto gridwt = [&](long n) { return dim3(grid_waves(n, tb), B); }; // tuned wave-per-item sites
+  // Blocks per event: what the capacity would ask for, but at most an equal share of
+  // kLaunchWaves.  The kernels launched through these stride over their device-side
+  // counts, and the counts are far below the capacities: a launch over many events
+  // would otherwise spend most of its time dispatching blocks that find no work.
+  const long ev_waves = std::max(256L, kLaunchWaves / B);
+  auto share = [&](int blocks, int threads) {
+    return (unsigned)std::max(1L, std::min((long)blocks, ev_waves / (threads / 64)));
+  };
+  auto grid = [&](long n) { return dim3(share(grid_for(n), kBlock), B); };
+  auto gridt = [&](long n) { return dim3(share(grid_for(n, tb), tb), B); };    // tuned thread-per-item sites
+  auto gridwt = [&](long n) { return dim3(share(grid_waves(n, tb), tb), B); }; // tuned wave-per-item sites
   // one wave per seed, every seed its own wave (the seed search does not stride)
   auto seedwaves = [&] { return dim3((unsigned)((S + tb / 64 - 1) / (tb / 64) > 0 ? (S + tb / 64 - 1) / (tb / 64) : 1), B); };
   const dim3 one(1, B);
@@ -2419,21 +2646,24 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { k_bucket_sort<<<dim3((unsigned)n_co, B), 64 * kSortWaves, 0, st>>>(wb, M); });
   // a1: MD
   run([&] {
-    k_md_big<false><<<dim3(1024, B), kBlock, 0, st>>>(wb, g);
+    k_md_big<false><<<dim3(share(1024, kBlock), B), kBlock, 0, st>>>(wb, g);
     k_md<false><<<gridwt(M), tb, 0, st>>>(wb, g);
   });
   run([&] { scan(wb, B, SC_MD, M, st); });
   run([&] {
-    k_md_big<true><<<dim3(1024, B), kBlock, 0, st>>>(wb, g);
+    k_md_big<true><<<dim3(share(1024, kBlock), B), kBlock, 0, st>>>(wb, g);
     k_md<true><<<gridwt(M), tb, 0, st>>>(wb, g);
   });
   // a2: LS
-  run([&] { k_ls<false><<<gridwt(b.cap_md), tb, 0, st>>>(wb, g); });
+  run([&] {
+    const int lg = ls_group_for(g.tiles, B, b.cap_md);
+    k_ls_count<<<gridwt((b.cap_md + lg - 1) / lg), tb, 0, st>>>(wb, g, lg);
+  });
   run([&] { scan(wb, B, SC_LS, b.cap_md, st); });
   run([&] {
     scan(wb, B, SC_LSOVF, b.cap_md, st);
     k_ls_copy<<<gridt((long)b.cap_md * kLsCache), tb, 0, st>>>(wb, g.tiles.ls_cache);
-    k_ls<true><<<gridwt(b.cap_md < 16384 ? b.cap_md : 16384), tb, 0, st>>>(wb, g);  // the overflow MDs
+    k_ls_fill<<<gridwt(b.cap_md < 16384 ? b.cap_md : 16384), tb, 0, st>>>(wb, g);  // the overflow MDs
   });
   // a3: T3
   run([&] { k_t3<false><<<gridwt((b.cap_ls + 63) / 64), tb, 0, st>>>(wb, g); });

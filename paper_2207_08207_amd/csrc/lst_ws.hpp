@@ -37,6 +37,7 @@ struct Tiles {
   int pass_list;     // passing objects per seed ranked in LDS by the fill, 1..kPassList (else: ordered scan)
   int max_slices;    // marked bins per seed gathered into one flat list, 1..kMaxSlices (else: bin by bin)
   int ext_per_wave;  // track candidates per wave of the extension search: 4, 8 or 16
+  int ls_group;      // inner MDs per wave of the segment count pass, 1..kLsGroup; 0: chosen per launch
 };
 
 struct DevGeom {
@@ -80,6 +81,7 @@ enum FillId : int {
 // module for mini-doublets, per MD for segments, per seed for pT3 / pT5 (more
 // than this: the fill searches again).
 constexpr int kLsCache = 16;
+constexpr int kLsGroup = 16;  // most inner MDs per wave of the segment count pass
 constexpr int kMdCache = 32;  // MDs per module whose (lower, upper) pair the MD count pass keeps
 constexpr int kT3Cache = 2;   // triplets per parent segment whose candidate the T3 count pass keeps
 constexpr int kT5Cache = 2;   // quintuplets per parent triplet whose candidate the T5 count pass keeps
@@ -97,7 +99,7 @@ __host__ __device__ inline int n_hit_tiles(long n_hits) { return (int)((n_hits +
 constexpr int kPassList = 1024;  // passing objects of one seed ranked in LDS by the seed-search fill
 constexpr int kMaxSlices = 512;  // marked bins of one seed gathered into a flat list in LDS
 constexpr int kExtPerWaveMax = 16;
-constexpr Tiles kTilesDefault{kMdCache, kLsCache, kT3Cache, kT5Cache, kPt3Cache, kPt5Cache, kPassList, kMaxSlices, 8};
+constexpr Tiles kTilesDefault{kMdCache, kLsCache, kT3Cache, kT5Cache, kPt3Cache, kPt5Cache, kPassList, kMaxSlices, 8, 0};
 
 // First-anchor bins of the seed search: 10 radius rings x 256 azimuth bins x
 // 55 z bins (10 cm over |z| < 275 cm); bins of one (ring, azimuth) pair are

@@ -70,16 +70,16 @@ def test_tile_choices_do_not_change_results(lst, full, ofull):
     g.set_track_extensions(True)
     base = g.tile_config()
     assert base == {"md_cache": 32, "ls_cache": 16, "t3_cache": 2, "t5_cache": 2, "pt3_cache": 256,
-                    "pt5_cache": 16, "pass_list": 1024, "max_slices": 512, "ext_per_wave": 8}
+                    "pt5_cache": 16, "pass_list": 1024, "max_slices": 512, "ext_per_wave": 8, "ls_group": 0}
     ev = make_event("pu200_seeded", 9)
     print(f"[cpu] oracle on {ev.n_hits} hits", flush=True)
     o = oracle.run(ofull, ev)
     d = lst.upload_event(ev)
     configs = [dict(md_cache=0, ls_cache=0, t3_cache=0, t5_cache=0, pt3_cache=0, pt5_cache=0, pass_list=1,
-                    max_slices=1, ext_per_wave=4),
+                    max_slices=1, ext_per_wave=4, ls_group=1),
                dict(md_cache=1, ls_cache=1, t3_cache=1, t5_cache=1, pt3_cache=1, pt5_cache=1, pass_list=2,
-                    max_slices=2, ext_per_wave=16),
-               dict(md_cache=16, ls_cache=8, pt3_cache=64, pt5_cache=4, pass_list=256, max_slices=128),
+                    max_slices=2, ext_per_wave=16, ls_group=16),
+               dict(md_cache=16, ls_cache=8, pt3_cache=64, pt5_cache=4, pass_list=256, max_slices=128, ls_group=3),
                dict(ls_cache=4, pt3_cache=128, pt5_cache=8)]
     for cfg in configs:
         g.set_tile_config(base)
