@@ -141,7 +141,7 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.ctr = ctr;
   const long tiles = (long)n_coarse((int)M) * n_hit_tiles(N);
   t.boff = I(2 * M + 1); t.tile_hist = I(tiles + 1); t.tile_off = I(tiles + 1);
-  t.hkey = I(N + 1); t.hsrc = I(N + 1); t.hidx = I(N + 1); t.hpos = F4(N + 1);
+  t.hkey = I(N + 1); t.hsrc = I(N + 1); t.hcp = F4(N + 1); t.hidx = I(N + 1); t.hpos = F4(N + 1);
   t.md_cnt = I(M + 1); t.md_off = I(M + 1); t.md_cache = I(kMdCache * M);
   t.md_hits = I2(md); t.md_mod = I(md); t.md_pos = F4(md); t.md_stub = F2(md); t.mod_disc = F4(M);
   t.ls_cnt = I(md + 1); t.ls_off = I(md + 1); t.ls_md = I2(ls); t.ls_beta = F2(ls);
@@ -152,7 +152,7 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.t5_cnt = I(t3 + 1); t.t5_off = I(t3 + 1); t.t5_t3 = I2(t5); t.t5_md = I(5 * t5); t.t5_attr = F(8 * t5);
   t.t5_keep = I(t5); t.t5_first = F2(t5);
   t.inc_cnt = I(md + 1); t.inc_off = I(md + 1); t.inc_cur = I(md + 1); t.inc_list = I2(5 * t5);
-  t.pls = F(8 * S); t.pls_keep = I(S);
+  t.pls = F(8 * S); t.pls_keep = I(S); t.seed_order = I(S + 1);
   t.ph_cnt = I(N + 1); t.ph_off = I(N + 1); t.ph_cur = I(N + 1); t.ph_list = I(4 * S);
   t.pt3_cnt = I(S + 1); t.pt3_off = I(S + 1); t.pt5_cnt = I(S + 1); t.pt5_off = I(S + 1);
   t.pt3_cache = I(kPt3Cache * S); t.pt5_cache = I(kPt5Cache * S);

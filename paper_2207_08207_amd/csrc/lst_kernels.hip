@@ -214,17 +214,18 @@ void launch_tc_export(const Ws *d_ws, int max_tc, int max_hits, int *type, int *
 // ------------------------------------------------------------- a0: hits
 // Hits are bucketed by key = 2 module + sensor, stably (input order within a
 // key), with no global atomic: an LSD-free two-level counting sort.
-//  1. k_hits_count: each wave counts the hits of its tile of kHitTile input
+//  1. k_hits_count: each block counts the hits of its tile of kHitTile input
 //     hits per coarse bucket (key >> kFineBits) in LDS and writes the counts,
 //     coarse-bucket major (and validates hits and seeds);
 //  2. an exclusive scan of those counts gives every (coarse bucket, tile) its
 //     first position;
-//  3. k_hits_scatter: each wave walks its tile again in input order, 64 hits
-//     at a time; hits of one coarse bucket in a round find each other with
-//     ballots and take consecutive positions after the bucket's running
-//     position (stable), writing (key, input index);
-//  4. k_bucket_sort: one wave per coarse bucket counts its keys, writes their
-//     offsets and places every hit (input index, x, y, z, r) at its key's
+//  3. k_hits_scatter: each wave walks its quarter of the tile again in input
+//     order, 64 hits at a time, after the waves before it; hits of one coarse
+//     bucket in a round find each other with ballots and take consecutive
+//     positions after the bucket's running position (stable), writing (key,
+//     input index, x, y, z, r);
+//  4. k_bucket_sort: one block per coarse bucket counts its keys, writes their
+//     offsets and moves every hit's (input index, x, y, z, r) to its key's
 //     running position, again 64 hits at a time in order.
 
 // The bucket key of hit i, or -1 for a pixel hit or invalid data (*bad).
@@ -259,29 +260,40 @@ __device__ __forceinline__ int bits_for(int n) {  // bits of the values 0 .. n -
   return b;
 }
 
-// One wave per tile (four per block): the tile's coarse counts live in LDS.
+// One block per tile of kHitTile hits, each of its four waves counting 1024
+// consecutive hits into its own LDS row; the tile's coarse counts are the rows'
+// sums (k_hits_scatter recounts the rows to rank its waves).
+static_assert(kHitTile == kWaves * 1024, "a wave's part of a tile is 1024 hits");
+__device__ __forceinline__ bool wave_coarse_counts(const Ws &w, int tb, int n_mod, int *row) {
+  const int lane = lane_id(), wv = wave_id();
+  bool any_bad = false;
+  const int i0 = tb * kHitTile + wv * 1024, i1 = min(w.n_hits, i0 + 1024);
+  for (int i = i0 + lane; i < i1; i += 64) {
+    bool bad;
+    const int key = hit_key(w, i, n_mod, &bad);
+    any_bad |= bad;
+    if (key >= 0) atomicAdd(&row[key >> kFineBits], 1);  // LDS
+  }
+  return any_bad;
+}
+
 __global__ __launch_bounds__(kBlock) void k_hits_count(const Ws *__restrict__ wb, int n_mod) {
   __shared__ int s_h[kWaves][kMaxCoarse];
   const Ws &w = wb[blockIdx.y];
-  const int wv = wave_id(), lane = lane_id();
-  const int nc = n_coarse(n_mod), ntw = n_hit_tiles(w.n_hits);
-  const int tw = blockIdx.x * (blockDim.x >> 6) + wv;
-  if (tw < ntw) {
-    for (int c = lane; c < nc; c += 64) s_h[wv][c] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    bool any_bad = false;
-    const int i1 = min(w.n_hits, (tw + 1) * kHitTile);
-    for (int i = tw * kHitTile + lane; i < i1; i += 64) {
-      bool bad;
-      const int key = hit_key(w, i, n_mod, &bad);
-      any_bad |= bad;
-      if (key >= 0) atomicAdd(&s_h[wv][key >> kFineBits], 1);  // LDS
+  const int wv = wave_id();
+  const int nc = n_coarse(n_mod), ntb = n_hit_tiles(w.n_hits);
+  const int tb = blockIdx.x;
+  if (tb < ntb) {
+    for (int c = threadIdx.x; c < kWaves * kMaxCoarse; c += blockDim.x) (&s_h[0][0])[c] = 0;
+    __syncthreads();
+    if (wave_coarse_counts(w, tb, n_mod, s_h[wv])) atomicOr(&w.ctr[C_STATUS], (int)ST_BAD_HIT);
+    __syncthreads();
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      int t = 0;
+#pragma unroll
+      for (int q = 0; q < kWaves; ++q) t += s_h[q][c];
+      w.tile_hist[(long)c * ntb + tb] = t;
     }
-    if (any_bad) atomicOr(&w.ctr[C_STATUS], (int)ST_BAD_HIT);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    for (int c = lane; c < nc; c += 64) w.tile_hist[(long)c * ntw + tw] = s_h[wv][c];
   }
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
     bool bad = !(w.q[s] == 1 || w.q[s] == -1) || !(isfinite(w.px[s]) && isfinite(w.py[s]) && isfinite(w.pz[s]));
@@ -295,18 +307,35 @@ __global__ __launch_bounds__(kBlock) void k_hits_count(const Ws *__restrict__ wb
   }
 }
 
+// Stable scatter of a tile's hits into coarse-bucket order: each wave's first
+// slot in bucket c is the tile's offset (the scan of the tile counts) plus the
+// rows of the waves before it; in each round of 64 hits, a hit's rank among
+// the round's hits of its bucket (match_value) places it.  The hit's
+// coordinates and radius travel with it, so the per-bucket sort reads them
+// contiguously.
 __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ wb, int n_mod) {
-  __shared__ int s_run[kWaves][kMaxCoarse];
+  __shared__ int s_h[kWaves][kMaxCoarse];
   const Ws &w = wb[blockIdx.y];
   const int wv = wave_id(), lane = lane_id();
-  const int nc = n_coarse(n_mod), ntw = n_hit_tiles(w.n_hits);
-  const int tw = blockIdx.x * (blockDim.x >> 6) + wv;
-  if (tw >= ntw) return;
-  for (int c = lane; c < nc; c += 64) s_run[wv][c] = w.tile_off[(long)c * ntw + tw];
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
+  const int nc = n_coarse(n_mod), ntb = n_hit_tiles(w.n_hits);
+  const int tb = blockIdx.x;
+  if (tb >= ntb) return;  // the whole block
+  for (int c = threadIdx.x; c < kWaves * kMaxCoarse; c += blockDim.x) (&s_h[0][0])[c] = 0;
+  __syncthreads();
+  (void)wave_coarse_counts(w, tb, n_mod, s_h[wv]);
+  __syncthreads();
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    int run = w.tile_off[(long)c * ntb + tb];
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      const int v = s_h[q][c];
+      s_h[q][c] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
   const int nbits = bits_for(nc);
-  const int i0 = tw * kHitTile, i1 = min(w.n_hits, i0 + kHitTile);
+  const int i0 = tb * kHitTile + wv * 1024, i1 = min(w.n_hits, i0 + 1024);
   for (int r0 = i0; r0 < i1; r0 += 64) {
     const int i = r0 + lane;
     bool bad = true;
@@ -316,14 +345,16 @@ __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ 
     const unsigned long long peers = match_value(c, nbits, act);
     int base = 0;
     if (act) {
-      base = s_run[wv][c];
+      base = s_h[wv][c];
       const int pos = base + lanes_below(peers);
+      const float x = w.x[i], y = w.y[i], z = w.z[i];
       w.hkey[pos] = key;
       w.hsrc[pos] = i;
+      w.hcp[pos] = make_float4(x, y, z, sqrtf(x * x + y * y));
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (act && lanes_below(peers) == 0) s_run[wv][c] = base + __popcll(peers);  // the bucket's first lane
+    if (act && lanes_below(peers) == 0) s_h[wv][c] = base + __popcll(peers);  // the bucket's first lane
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
@@ -340,10 +371,10 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__res
   __shared__ int s_key0[kFineKeys];
   const Ws &w = wb[blockIdx.y];
   const int wv = wave_id(), lane = lane_id(), t = threadIdx.x;
-  const int nc = n_coarse(n_mod), ntw = n_hit_tiles(w.n_hits), nkeys = 2 * n_mod;
+  const int nc = n_coarse(n_mod), ntb = n_hit_tiles(w.n_hits), nkeys = 2 * n_mod;
   const int c = blockIdx.x;
   if (c >= nc) return;  // the whole block
-  const int j0 = w.tile_off[(long)c * ntw], j1 = w.tile_off[(long)(c + 1) * ntw];
+  const int j0 = w.tile_off[(long)c * ntb], j1 = w.tile_off[(long)(c + 1) * ntb];
   const long L = j1 - j0;
   const int a = j0 + (int)(L * wv / kSortWaves), b = j0 + (int)(L * (wv + 1) / kSortWaves);
   for (int f = lane; f < kFineKeys; f += 64) s_cnt[wv][f] = 0;
@@ -351,7 +382,7 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__res
   __builtin_amdgcn_wave_barrier();
   for (int j = a + lane; j < b; j += 64) atomicAdd(&s_cnt[wv][w.hkey[j] & (kFineKeys - 1)], 1);  // LDS
   __syncthreads();
-  // each key's total over the waves, then the keys' first positions (wave 0: two keys per lane)
+  // each key's total over the waves, then the keys' first positions (wave 0: one key per lane)
   int tot = 0;
   if (t < kFineKeys)
     for (int q = 0; q < kSortWaves; ++q) tot += s_cnt[q][t];
@@ -393,10 +424,8 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__res
     if (act) {
       base = s_cnt[wv][f];
       const int pos = base + lanes_below(peers);
-      const int i = w.hsrc[j];
-      const float xx = w.x[i], yy = w.y[i], zz = w.z[i];
-      w.hidx[pos] = i;
-      w.hpos[pos] = make_float4(xx, yy, zz, sqrtf(xx * xx + yy * yy));
+      w.hidx[pos] = w.hsrc[j];
+      w.hpos[pos] = w.hcp[j];
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1658,6 +1687,47 @@ __global__ void k_obj_bin_scatter(const Ws *__restrict__ wb, DevGeom g) {
     }
 }
 
+// Processing order of the seed search: seeds grouped by direction (azimuth of
+// the seed's direction in kPhiBins sectors x 8 bins of lambda), one block of
+// 1024 threads per event.  Seeds of one group scan nearly the same bins, so
+// waves that run together (consecutive blocks) reuse each other's object
+// lists in cache.  Results do not depend on the order (each seed writes only
+// its own entries), so ranks within a group come from LDS atomics.
+constexpr int kSeedKeys = kPhiBins * 8;
+__device__ __forceinline__ int seed_key(const Ws &w, int s) {
+  const float *p = w.pls + 8 * (long)s;
+  const float ph = atan2f(p[2], p[1]);
+  const int lb = (int)floorf((p[3] + 6.0f) * (1.0f / 1.5f));
+  return (ph == ph ? phibin_of(ph) : 0) * 8 + (lb < 0 ? 0 : (lb > 7 ? 7 : lb));
+}
+__global__ __launch_bounds__(1024) void k_seed_order(const Ws *__restrict__ wb) {
+  __shared__ int s_cnt[kSeedKeys];
+  __shared__ int s_wave[16];
+  const Ws &w = wb[blockIdx.y];
+  const int S = w.n_seeds, t = threadIdx.x, lane = lane_id(), wv = t >> 6;
+  for (int k = t; k < kSeedKeys; k += 1024) s_cnt[k] = 0;
+  __syncthreads();
+  for (int s = t; s < S; s += 1024) atomicAdd(&s_cnt[seed_key(w, s)], 1);  // LDS
+  __syncthreads();
+  // exclusive scan of the key counts: two keys per thread, then over the block
+  static_assert(kSeedKeys == 2 * 1024, "two keys per thread");
+  const int c0 = s_cnt[2 * t], c1 = s_cnt[2 * t + 1];
+  int x = c0 + c1;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_wave[wv] = x;
+  __syncthreads();
+  int before = 0;
+  for (int q = 0; q < wv; ++q) before += s_wave[q];
+  const int ex = before + x - (c0 + c1);
+  s_cnt[2 * t] = ex;
+  s_cnt[2 * t + 1] = ex + c0;
+  __syncthreads();
+  for (int s = t; s < S; s += 1024) w.seed_order[atomicAdd(&s_cnt[seed_key(w, s)], 1)] = s;  // LDS rank
+}
+
 // Marks, in the wave's bin mask, every (ring, azimuth) bin that can hold the
 // first anchor of an object inside the seed's window: the anchor lies within
 // 1.01 cm of the seed circle on its forward half-turn (algebraic distance
@@ -1752,14 +1822,16 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
   __shared__ unsigned s_mask[kWaves][kMaskWords];
   __shared__ int s_slo[kWaves][kRings], s_shi[kWaves][kRings];
   __shared__ int2 s_zb[kWaves][kRings];
-  __shared__ int s_sl_j0[kWaves][kMaxSlices];       // bin id, then first list entry, of each slice
-  __shared__ int s_sl_pre[kWaves][kMaxSlices + 1];  // candidates before each slice
+  __shared__ int s_sl_j0[kWaves][kMaxSlices];       // bin id of each slice, then first list entry of each slice with candidates
+  __shared__ int s_sl_pre[kWaves][kMaxSlices];      // candidates before each slice with candidates
   __shared__ int s_list[FILL ? kWaves : 1][FILL ? kPassList : 1];
   __shared__ int s_pq[kWaves][128];  // candidates past the first-anchor test, awaiting the full one
+  __shared__ int s_mark[kWaves][64];  // a slice's candidates start here (this round)
   const Ws &w = wb[blockIdx.y];
   const int wv = wave_id(), lane = lane_id();
-  const int s = blockIdx.x * (int)(blockDim.x >> 6) + wv;
-  if (s >= w.n_seeds) return;
+  const int si = blockIdx.x * (int)(blockDim.x >> 6) + wv;
+  if (si >= w.n_seeds) return;
+  const int s = uload(w.seed_order + si);  // seeds of one direction on neighbouring waves
   const Seed sd = load_seed(w, s);
   constexpr int kCache = K == 3 ? kPt3Cache : kPt5Cache;
   static_assert(kCache <= kPassList, "the fill ranks the cache in its LDS list");
@@ -1904,7 +1976,9 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
       if (flat) {
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        int run = 0;
+        // slices with candidates only, compacted in place (an entry is read before any
+        // write of its round, and compacted positions never pass the round's own)
+        int run = 0, n_live = 0;
         for (int c0 = 0; c0 < n_bits; c0 += 64) {
           const int k = c0 + lane;
           int j0 = 0, len = 0;
@@ -1919,23 +1993,41 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
             const int y = __shfl_up(x, o, 64);
             if (lane >= o) x += y;
           }
-          if (k < n_bits) {
-            s_sl_j0[wv][k] = j0;
-            s_sl_pre[wv][k] = run + x - len;
+          const unsigned long long live = __ballot(len > 0);
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          if (len > 0) {
+            const int q = n_live + lanes_below(live);
+            s_sl_j0[wv][q] = j0;
+            s_sl_pre[wv][q] = run + x - len;
           }
-          run += __shfl(x, 63, 64);
+          n_live += __popcll(live);
+          run += __builtin_amdgcn_readfirstlane(__shfl(x, 63, 64));
         }
-        if (lane == 0) s_sl_pre[wv][n_bits] = run;
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        int e = 0;  // slice of this lane's candidate (candidates advance monotonically)
+        // the slice of each lane's candidate: the slices starting before the round (jlo)
+        // plus those starting at or below the lane in it (distinct starts, marked)
+        int jlo = 0;
         for (int c0 = 0; c0 < run; c0 += 64) {
           const int c = c0 + lane;
+          s_mark[wv][lane] = 0;
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          if (jlo + lane < n_live) {
+            const int p = s_sl_pre[wv][jlo + lane] - c0;  // >= 0
+            if (p < 64) s_mark[wv][p] = 1;
+          }
+          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          const unsigned long long starts = __ballot(s_mark[wv][lane] != 0);
           int j = 0;
           if (c < run) {
-            while (s_sl_pre[wv][e + 1] <= c) ++e;
+            const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
+            const int e = jlo - 1 + __popcll(starts & upto);
             j = s_sl_j0[wv][e] + (c - s_sl_pre[wv][e]);
           }
+          jlo += __popcll(starts);
           test(c < run, j);
         }
       }
@@ -2636,13 +2728,12 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   // a0: buckets
   run([&] { k_clear<<<grid(C_COUNT), kBlock, 0, st>>>(wb, FL_CTR, FL_CTR + 1); });
   const long n_tiles = n_hit_tiles(N), n_co = n_coarse(M);
-  run([&] {  // one wave per hit tile, and enough threads for the seeds' validation
-    const long waves = std::max(n_tiles, (S + 63) / 64);
-    k_hits_count<<<dim3((unsigned)std::max(1L, std::min((waves + kWaves - 1) / kWaves, 65535L)), B), kBlock, 0,
-                   st>>>(wb, M);
+  run([&] {  // one block per hit tile, and enough threads for the seeds' validation
+    const long blocks = std::max(n_tiles, (S + kBlock - 1) / kBlock);
+    k_hits_count<<<dim3((unsigned)std::max(1L, std::min(blocks, 65535L)), B), kBlock, 0, st>>>(wb, M);
   });
   run([&] { scan(wb, B, SC_HITS, n_co * n_tiles, st); });
-  run([&] { k_hits_scatter<<<dim3((unsigned)std::max(1L, (n_tiles + kWaves - 1) / kWaves), B), kBlock, 0, st>>>(wb, M); });
+  run([&] { k_hits_scatter<<<dim3((unsigned)std::max(1L, n_tiles), B), kBlock, 0, st>>>(wb, M); });
   run([&] { k_bucket_sort<<<dim3((unsigned)n_co, B), 64 * kSortWaves, 0, st>>>(wb, M); });
   // a1: MD
   run([&] {
@@ -2693,6 +2784,7 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] {
     if (!seeds) return;
     k_clear<<<grid(kSeedBins + 1), kBlock, 0, st>>>(wb, FL_B3_CNT, FL_B5_CUR + 1);
+    k_seed_order<<<one, 1024, 0, st>>>(wb);
     k_obj_bin_count<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb);
     scan(wb, B, SC_B3, kSeedBins, st);
     k_obj_bin_scatter<3><<<grid(b.cap_t3), kBlock, 0, st>>>(wb, g);

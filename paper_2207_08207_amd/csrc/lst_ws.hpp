@@ -87,10 +87,10 @@ constexpr int kT3Cache = 2;   // triplets per parent segment whose candidate the
 constexpr int kT5Cache = 2;   // quintuplets per parent triplet whose candidate the T5 count pass keeps
 constexpr int kPt3Cache = 256;  // pT3 per seed (PU200 maximum ~190)
 constexpr int kPt5Cache = 16;   // pT5 per seed
-// Hit bucketing: wave tiles of kHitTile input hits; (module, sensor) keys in
-// coarse buckets of kFineKeys consecutive keys (at most kMaxCoarse of them,
-// so 2 n_mod <= kFineKeys * kMaxCoarse).
-constexpr int kHitTile = 1024;
+// Hit bucketing: block tiles of kHitTile input hits (four waves of 1024);
+// (module, sensor) keys in coarse buckets of kFineKeys consecutive keys (at
+// most kMaxCoarse of them, so 2 n_mod <= kFineKeys * kMaxCoarse).
+constexpr int kHitTile = 4096;
 constexpr int kFineBits = 5, kFineKeys = 1 << kFineBits;
 constexpr int kMaxCoarse = 2048;
 constexpr int kMaxModules = kFineKeys * kMaxCoarse / 2;
@@ -120,6 +120,7 @@ struct Ws {
   int *boff, *hidx;  // (module, sensor) buckets: offsets (2 n_mod + 1), input index per bucketed hit
   int *tile_hist, *tile_off;  // hits per (coarse bucket, wave tile), coarse-bucket major, and their scan
   int *hkey, *hsrc;  // hits in coarse-bucket order (stable): bucket key, input index
+  float4 *hcp;       // and their x, y, z, r
   float4 *hpos;
   // mini-doublets
   int *md_cnt, *md_off;
@@ -154,6 +155,7 @@ struct Ws {
   // pixel seeds
   float *pls;       // 8 per seed: pT, cx, cy, lambda, kappa, x0, y0, z0
   int *pls_keep;
+  int *seed_order;  // seeds in the seed search's processing order (grouped by direction)
   int *ph_cnt, *ph_off, *ph_cur, *ph_list;      // seeds using each pixel hit
   // pixel triplets / quintuplets
   int *pt3_cnt, *pt3_off, *pt5_cnt, *pt5_off;
