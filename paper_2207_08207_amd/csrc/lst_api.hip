@@ -1602,7 +1602,7 @@ struct TileSpec {
 };
 const TileSpec kTileSpecs[] = {
     {"md_cache", 0, lst::kMdCache, {0, 16, lst::kMdCache}, 3},
-    {"ls_cache", 0, lst::kLsCache, {4, 8, lst::kLsCache}, 3},
+    {"ls_cache", 0, lst::kLsCache, {8, 16, lst::kLsCache}, 3},
     {"t3_cache", 0, lst::kT3Cache, {0, 1, 2}, 3},
     {"t5_cache", 0, lst::kT5Cache, {0, 1, 2}, 3},
     {"pt3_cache", 0, lst::kPt3Cache, {64, 128, lst::kPt3Cache}, 3},

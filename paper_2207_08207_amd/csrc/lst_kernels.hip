@@ -916,12 +916,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       __builtin_amdgcn_wave_barrier();
     };
     int nq = 0;
+    // the linked modules' data of the current inner module (one per lane, when it has
+    // at most 64 of them): consecutive inner MDs mostly share their module
+    int cur_ma = -1, e0 = 0, ne = 0;
+    int r_first = 0, r_cnt = 0, r_info = 0;
+    float4 r_disc = make_float4(0.f, 0.f, 0.f, 0.f);
+    auto linked = [&](int kk, int &first, int &cnt, int &info, float4 &disc) {
+      const int mb = g.map_tgt[e0 + kk];
+      first = w.md_off[mb];
+      const int last = min(w.md_off[mb + 1], n_md);
+      cnt = last > first ? last - first : 0;
+      info = g.info[mb];
+      disc = w.mod_disc[mb];
+    };
     for (int k = 0; k < na; ++k) {
       // the inner MD's data are read from LDS where they are used, after each round's
       // fence, so that they are not held in registers across the selection
       const int ma = uload(w.md_mod + a0 + k);
-      const int e0 = uload(g.map_off + ma);
-      const int ne = uload(g.map_off + ma + 1) - e0;  // <= kMaxEdges, checked when the geometry is loaded
+      if (ma != cur_ma) {
+        cur_ma = ma;
+        e0 = uload(g.map_off + ma);
+        ne = uload(g.map_off + ma + 1) - e0;  // <= kMaxEdges, checked when the geometry is loaded
+        if (ne <= 64 && lane < ne) linked(lane, r_first, r_cnt, r_info, r_disc);
+      }
       int run = 0, n_ne = 0;
       for (int k0 = 0; k0 < ne; k0 += 64) {
         const int kk = k0 + lane;
@@ -930,13 +947,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         const float4 A = s_A[wv][k];
         const ModInfo mia{s_mia[wv][k]};
         if (kk < ne) {
-          const int mb = g.map_tgt[e0 + kk];
-          first = w.md_off[mb];
-          const int last = min(w.md_off[mb + 1], n_md);
-          cnt = last > first ? last - first : 0;
-          info = g.info[mb];
+          float4 disc = r_disc;
+          if (ne <= 64) {
+            first = r_first;
+            cnt = r_cnt;
+            info = r_info;
+          } else {
+            linked(kk, first, cnt, info, disc);
+          }
           if (cnt > 0) {
-            const float4 disc = w.mod_disc[mb];
             wm = ls_window_bound(A, mia, disc, ModInfo{info}, g.d0max);
             if (!ls_module_may_pass(A, disc, wm)) cnt = 0;
           }
@@ -1085,22 +1104,26 @@ __device__ __forceinline__ int round_parent(int start, int n, int c0, int *mark,
 
 // Segments of the MDs whose partners the count pass cached: one thread per
 // (MD, cache slot), in candidate order, with the angles ls_pass reports.
+// kLsCopyLanes threads per MD take slots k, k + kLsCopyLanes, ... (most MDs
+// have few segments).
+constexpr int kLsCopyLanes = 8;
 __global__ void k_ls_copy(const Ws *__restrict__ wb, int keep) {
   const Ws &w = wb[blockIdx.y];
-  const long n = (long)w.ctr[C_NMD] * kLsCache;
+  const long n = (long)uload(w.ctr + C_NMD) * kLsCopyLanes;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const int a = (int)(i / kLsCache), k = (int)(i % kLsCache);
+    const int a = (int)(i / kLsCopyLanes), k0 = (int)(i % kLsCopyLanes);
     const int cnt = w.ls_cnt[a];
     if (cnt > keep) {
-      if (k == 0) w.ls_ovf[w.ls_ovf_off[a]] = a;  // searched again by k_ls_fill
+      if (k0 == 0) w.ls_ovf[w.ls_ovf_off[a]] = a;  // searched again by k_ls_fill
       continue;
     }
-    if (k >= cnt) continue;
-    const int pos = w.ls_off[a] + k;
-    if (pos >= w.cap_ls) continue;
-    const int b = w.ls_cache[i];
-    w.ls_md[pos] = make_int2(a, b);
-    w.ls_beta[pos] = ls_beta(w.md_pos[a], w.md_pos[b]);
+    for (int k = k0; k < cnt; k += kLsCopyLanes) {
+      const int pos = w.ls_off[a] + k;
+      if (pos >= w.cap_ls) break;
+      const int b = w.ls_cache[(long)a * kLsCache + k];
+      w.ls_md[pos] = make_int2(a, b);
+      w.ls_beta[pos] = ls_beta(w.md_pos[a], w.md_pos[b]);
+    }
   }
 }
 
@@ -2753,7 +2776,7 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { scan(wb, B, SC_LS, b.cap_md, st); });
   run([&] {
     scan(wb, B, SC_LSOVF, b.cap_md, st);
-    k_ls_copy<<<gridt((long)b.cap_md * kLsCache), tb, 0, st>>>(wb, g.tiles.ls_cache);
+    k_ls_copy<<<gridt((long)b.cap_md * kLsCopyLanes), tb, 0, st>>>(wb, g.tiles.ls_cache);
     k_ls_fill<<<gridwt(b.cap_md < 16384 ? b.cap_md : 16384), tb, 0, st>>>(wb, g);  // the overflow MDs
   });
   // a3: T3

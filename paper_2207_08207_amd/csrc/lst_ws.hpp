@@ -80,7 +80,7 @@ enum FillId : int {
 // Passing partners remembered between a stage's count and fill passes: per
 // module for mini-doublets, per MD for segments, per seed for pT3 / pT5 (more
 // than this: the fill searches again).
-constexpr int kLsCache = 16;
+constexpr int kLsCache = 32;
 constexpr int kLsGroup = 16;  // most inner MDs per wave of the segment count pass
 constexpr int kMdCache = 32;  // MDs per module whose (lower, upper) pair the MD count pass keeps
 constexpr int kT3Cache = 2;   // triplets per parent segment whose candidate the T3 count pass keeps

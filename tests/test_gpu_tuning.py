@@ -69,7 +69,7 @@ def test_tile_choices_do_not_change_results(lst, full, ofull):
     g = lst.Geometry(full)
     g.set_track_extensions(True)
     base = g.tile_config()
-    assert base == {"md_cache": 32, "ls_cache": 16, "t3_cache": 2, "t5_cache": 2, "pt3_cache": 256,
+    assert base == {"md_cache": 32, "ls_cache": 32, "t3_cache": 2, "t5_cache": 2, "pt3_cache": 256,
                     "pt5_cache": 16, "pass_list": 1024, "max_slices": 512, "ext_per_wave": 8, "ls_group": 0}
     ev = make_event("pu200_seeded", 9)
     print(f"[cpu] oracle on {ev.n_hits} hits", flush=True)
