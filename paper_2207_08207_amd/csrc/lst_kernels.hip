@@ -37,6 +37,40 @@ __device__ __forceinline__ int lanes_below(unsigned long long m) {
 // registers.  uload is for loads whose address is the same on every lane.
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 __device__ __forceinline__ int uload(const int *p) { return __builtin_amdgcn_readfirstlane(*p); }
+// The same pointer in the global address space: the workspace and geometry
+// pointers are read from memory, so the compiler cannot infer their address
+// space and would issue flat loads, which also count against the LDS wait
+// counter (every LDS wait then waits for the gathers in flight too) and take a
+// 64-bit address per lane.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gp(const T *p) {
+  return (const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *gp(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+// Loads and stores of vector types through the global address space (their
+// member operators take a generic `this`): by their bits, as native vectors.
+template <int N> struct NativeOf;
+template <> struct NativeOf<4> { typedef int type; };
+template <> struct NativeOf<8> { typedef int type __attribute__((ext_vector_type(2))); };
+template <> struct NativeOf<16> { typedef int type __attribute__((ext_vector_type(4))); };
+template <class T>
+__device__ __forceinline__ T gload(const T *p, long i) {
+  typedef typename NativeOf<sizeof(T)>::type N;
+  const N n = ((const __attribute__((address_space(1))) N *)p)[i];
+  T v;
+  __builtin_memcpy(&v, &n, sizeof(T));
+  return v;
+}
+template <class T>
+__device__ __forceinline__ void gstore(T *p, long i, const T &v) {
+  typedef typename NativeOf<sizeof(T)>::type N;
+  N n;
+  __builtin_memcpy(&n, &v, sizeof(T));
+  ((__attribute__((address_space(1))) N *)p)[i] = n;
+}
 
 __device__ __forceinline__ int block_sum(int v, int *s_red) {
   // wave reduction by shuffles, then across waves in LDS
@@ -222,10 +256,10 @@ void launch_tc_export(const Ws *d_ws, int max_tc, int max_hits, int *type, int *
 //  3. k_hits_scatter: each wave walks its quarter of the tile again in input
 //     order, 64 hits at a time, after the waves before it; hits of one coarse
 //     bucket in a round find each other with ballots and take consecutive
-//     positions after the bucket's running position (stable), writing (key,
-//     input index, x, y, z, r);
+//     positions after the bucket's running position (stable), writing the key
+//     and (x, y, z, input index);
 //  4. k_bucket_sort: one block per coarse bucket counts its keys, writes their
-//     offsets and moves every hit's (input index, x, y, z, r) to its key's
+//     offsets and moves every hit (input index; x, y, z, r) to its key's
 //     running position, again 64 hits at a time in order.
 
 // The bucket key of hit i, or -1 for a pixel hit or invalid data (*bad).
@@ -311,8 +345,8 @@ __global__ __launch_bounds__(kBlock) void k_hits_count(const Ws *__restrict__ wb
 // slot in bucket c is the tile's offset (the scan of the tile counts) plus the
 // rows of the waves before it; in each round of 64 hits, a hit's rank among
 // the round's hits of its bucket (match_value) places it.  The hit's
-// coordinates and radius travel with it, so the per-bucket sort reads them
-// contiguously.
+// coordinates and input index travel with it (one 16-byte store), so the
+// per-bucket sort reads them contiguously.
 __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ wb, int n_mod) {
   __shared__ int s_h[kWaves][kMaxCoarse];
   const Ws &w = wb[blockIdx.y];
@@ -347,10 +381,8 @@ __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ 
     if (act) {
       base = s_h[wv][c];
       const int pos = base + lanes_below(peers);
-      const float x = w.x[i], y = w.y[i], z = w.z[i];
       w.hkey[pos] = key;
-      w.hsrc[pos] = i;
-      w.hcp[pos] = make_float4(x, y, z, sqrtf(x * x + y * y));
+      w.hcp[pos] = make_float4(w.x[i], w.y[i], w.z[i], __int_as_float(i));
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -424,8 +456,9 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__res
     if (act) {
       base = s_cnt[wv][f];
       const int pos = base + lanes_below(peers);
-      w.hidx[pos] = w.hsrc[j];
-      w.hpos[pos] = w.hcp[j];
+      const float4 h = w.hcp[j];
+      w.hidx[pos] = __float_as_int(h.w);
+      w.hpos[pos] = make_float4(h.x, h.y, h.z, sqrtf(h.x * h.x + h.y * h.y));
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -441,13 +474,13 @@ constexpr int kMdStage = 128;  // hits per sensor staged in LDS per wave (more: 
 // a dense array of binary16 pairs (rounded to nearest even) read back as float.
 __device__ __forceinline__ void put_stub(const Ws &w, const DevGeom &g, int pos, float2 st) {
   if (g.stub16)
-    reinterpret_cast<__half2 *>(w.md_stub)[pos] = __floats2half2_rn(st.x, st.y);
+    gstore(reinterpret_cast<__half2 *>(w.md_stub), pos, __floats2half2_rn(st.x, st.y));
   else
-    w.md_stub[pos] = st;
+    gstore(w.md_stub, pos, st);
 }
 __device__ __forceinline__ float2 get_stub(const Ws &w, const DevGeom &g, int i) {
-  if (g.stub16) return __half22float2(reinterpret_cast<const __half2 *>(w.md_stub)[i]);
-  return w.md_stub[i];
+  if (g.stub16) return __half22float2(gload(reinterpret_cast<const __half2 *>(w.md_stub), i));
+  return gload(w.md_stub, i);
 }
 
 constexpr long kMdBig = 2048;  // modules with more pairs go to a whole block (k_md_big)
@@ -462,6 +495,27 @@ __device__ __forceinline__ float4 anchor_disc(float x0, float x1, float y0, floa
   return make_float4(cx, cy, rho, sqrtf(cx * cx + cy * cy));
 }
 
+// Quotient and remainder of t / n for 0 <= t < 2^22 and n >= 1 from rn, the
+// float reciprocal of n: t is exact in float and the two roundings (of 1 / n
+// and of the product) are 2^-24 relative each, so the float quotient is within
+// (t / n) 2^-23 < 1/2 of t / n; truncated, it is the quotient or one off, and
+// one correction step each way makes it exact.  (Integer division has no
+// instruction: the compiler's sequence for a variable divisor costs some 30
+// instructions, in 64 bits far more.)
+__device__ __forceinline__ int2 divmod22(int t, int n, float rn) {
+  int q = (int)((float)t * rn);
+  int r = t - q * n;
+  if (r < 0) {
+    --q;
+    r += n;
+  }
+  if (r >= n) {
+    ++q;
+    r -= n;
+  }
+  return make_int2(q, r);
+}
+
 // One wave per module of at most kMdBig pairs; pairs (lower i, upper j) in
 // row-major order, 64 at a time, compacted in order by ballot.  The fill also
 // writes the module's anchor disc.
@@ -472,24 +526,25 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
   const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;
   for (int m = blockIdx.x * wpb + wv; m < g.n_mod; m += gridDim.x * wpb) {
-    const int lo0 = w.boff[2 * m], nlo = w.boff[2 * m + 1] - lo0;
-    const int up0 = w.boff[2 * m + 1], nup = w.boff[2 * m + 2] - up0;
+    const int lo0 = gp(w.boff)[2 * m], nlo = gp(w.boff)[2 * m + 1] - lo0;
+    const int up0 = gp(w.boff)[2 * m + 1], nup = gp(w.boff)[2 * m + 2] - up0;
     const long npair = (long)nlo * nup;
     if (npair > kMdBig) continue;  // k_md_big's
     if (npair == 0) {
-      if (!FILL && lane == 0) w.md_cnt[m] = 0;
+      if (!FILL && lane == 0) gp(w.md_cnt)[m] = 0;
       continue;
     }
-    for (int k = lane; k < nlo && k < kMdStage; k += 64) s_lo[wv][k] = w.hpos[lo0 + k];
-    for (int k = lane; k < nup && k < kMdStage; k += 64) s_up[wv][k] = w.hpos[up0 + k];
+    for (int k = lane; k < nlo && k < kMdStage; k += 64) s_lo[wv][k] = gload(w.hpos, lo0 + k);
+    for (int k = lane; k < nup && k < kMdStage; k += 64) s_up[wv][k] = gload(w.hpos, up0 + k);
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    const float4 win = g.win[m];
-    const ModInfo mi{g.info[m]};
-    int base = FILL ? w.md_off[m] : 0;
+    const float4 win = gload(g.win, m);
+    const ModInfo mi{gp(g.info)[m]};
+    int base = FILL ? gp(w.md_off)[m] : 0;
     const int np = (int)npair;  // <= kMdBig here
-    const int n_md = FILL ? w.md_off[m + 1] - base : 0;
-    int *cache = w.md_cache + (long)kMdCache * m;
+    const float rnup = 1.0f / (float)nup;
+    const int n_md = FILL ? gp(w.md_off)[m + 1] - base : 0;
+    auto cache = gp(w.md_cache) + (long)kMdCache * m;
     const int md_keep = g.tiles.md_cache;
     if (FILL && n_md <= md_keep) {
       // the count pass kept this module's passing pairs (row-major order): copy them
@@ -498,11 +553,11 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
         const int i = pk >> 16, j = pk & 0xffff;
         const int pos = base + lane;
         if (pos < w.cap_md) {
-          const float4 hi = i < kMdStage ? s_lo[wv][i] : w.hpos[lo0 + i];
-          const float4 hj = j < kMdStage ? s_up[wv][j] : w.hpos[up0 + j];
-          w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
-          w.md_mod[pos] = m;
-          w.md_pos[pos] = hi;
+          const float4 hi = i < kMdStage ? s_lo[wv][i] : gload(w.hpos, lo0 + i);
+          const float4 hj = j < kMdStage ? s_up[wv][j] : gload(w.hpos, up0 + j);
+          gstore(w.md_hits, pos, make_int2(gp(w.hidx)[lo0 + i], gp(w.hidx)[up0 + j]));
+          gp(w.md_mod)[pos] = m;
+          gstore(w.md_pos, pos, hi);
           put_stub(w, g, pos, md_stub(hi, hj, mi));
         }
       }
@@ -513,19 +568,20 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
       int i = 0, j = 0;
       float4 hi, hj;
       if (p < np) {
-        i = p / nup;
-        j = p - i * nup;
-        hi = i < kMdStage ? s_lo[wv][i] : w.hpos[lo0 + i];
-        hj = j < kMdStage ? s_up[wv][j] : w.hpos[up0 + j];
+        const int2 ij = divmod22(p, nup, rnup);
+        i = ij.x;
+        j = ij.y;
+        hi = i < kMdStage ? s_lo[wv][i] : gload(w.hpos, lo0 + i);
+        hj = j < kMdStage ? s_up[wv][j] : gload(w.hpos, up0 + j);
         pass = md_pass(hi, hj, win, mi);
       }
       const unsigned long long bm = __ballot(pass);
       if (FILL && pass) {
         const int pos = base + lanes_below(bm);
         if (pos < w.cap_md) {
-          w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
-          w.md_mod[pos] = m;
-          w.md_pos[pos] = hi;
+          gstore(w.md_hits, pos, make_int2(gp(w.hidx)[lo0 + i], gp(w.hidx)[up0 + j]));
+          gp(w.md_mod)[pos] = m;
+          gstore(w.md_pos, pos, hi);
           put_stub(w, g, pos, md_stub(hi, hj, mi));
         }
       }
@@ -536,12 +592,12 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
       base += __popcll(bm);
     }
     if (!FILL) {
-      if (lane == 0) w.md_cnt[m] = base;
+      if (lane == 0) gp(w.md_cnt)[m] = base;
     } else {
       // a disc in x-y around every anchor of this module (the lower hits' bounding box)
       float x0 = 3.0e38f, x1 = -3.0e38f, y0 = 3.0e38f, y1 = -3.0e38f;
       for (int k = lane; k < nlo; k += 64) {
-        const float4 h = k < kMdStage ? s_lo[wv][k] : w.hpos[lo0 + k];
+        const float4 h = k < kMdStage ? s_lo[wv][k] : gload(w.hpos, lo0 + k);
         x0 = fminf(x0, h.x); x1 = fmaxf(x1, h.x);
         y0 = fminf(y0, h.y); y1 = fmaxf(y1, h.y);
       }
@@ -549,7 +605,7 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
         x0 = fminf(x0, __shfl_xor(x0, o, 64)); x1 = fmaxf(x1, __shfl_xor(x1, o, 64));
         y0 = fminf(y0, __shfl_xor(y0, o, 64)); y1 = fmaxf(y1, __shfl_xor(y1, o, 64));
       }
-      if (lane == 0) w.mod_disc[m] = anchor_disc(x0, x1, y0, y1);
+      if (lane == 0) gstore(w.mod_disc, m, anchor_disc(x0, x1, y0, y1));
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -557,66 +613,80 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
 }
 
 // The same for the modules with more than kMdBig pairs, one block (kBlock
-// threads) each, so that no single wave carries a dense module.
+// threads) each, so that no single wave carries a dense module: the block
+// stages both sensors' hits, and each of its four waves takes one consecutive
+// quarter of the module's row-major pairs on its own (no block barrier per
+// round).  The count pass writes each quarter's count (md_part), from which
+// the fill starts each quarter at the module's offset plus the counts of the
+// quarters before it, so the module's MDs stay in row-major order.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, DevGeom g) {
+  static_assert(kWaves == 4, "one quarter of the pairs per wave");
   const Ws &w = wb[blockIdx.y];
   __shared__ float4 s_lo[kMdStageBig], s_up[kMdStageBig];
-  __shared__ int s_wave[kWaves];
+  __shared__ int s_part[kWaves];
   __shared__ float4 s_box[kWaves];
-  const int wid = threadIdx.x >> 6, lane = lane_id();
+  const int wid = wave_id(), lane = lane_id();
   for (int m = blockIdx.x; m < g.n_mod; m += gridDim.x) {
-    const int lo0 = w.boff[2 * m], nlo = w.boff[2 * m + 1] - lo0;
-    const int up0 = w.boff[2 * m + 1], nup = w.boff[2 * m + 2] - up0;
+    const int lo0 = gp(w.boff)[2 * m], nlo = gp(w.boff)[2 * m + 1] - lo0;
+    const int up0 = gp(w.boff)[2 * m + 1], nup = gp(w.boff)[2 * m + 2] - up0;
     const long npair = (long)nlo * nup;
     if (npair <= kMdBig) continue;
     __syncthreads();  // the previous module's LDS reads are done
-    for (int k = threadIdx.x; k < nlo && k < kMdStageBig; k += kBlock) s_lo[k] = w.hpos[lo0 + k];
-    for (int k = threadIdx.x; k < nup && k < kMdStageBig; k += kBlock) s_up[k] = w.hpos[up0 + k];
+    for (int k = threadIdx.x; k < nlo && k < kMdStageBig; k += kBlock) s_lo[k] = gload(w.hpos, lo0 + k);
+    for (int k = threadIdx.x; k < nup && k < kMdStageBig; k += kBlock) s_up[k] = gload(w.hpos, up0 + k);
     __syncthreads();
-    const float4 win = g.win[m];
-    const ModInfo mi{g.info[m]};
-    int base = FILL ? w.md_off[m] : 0;
-    for (long p0 = 0; p0 < npair; p0 += kBlock) {
-      const long p = p0 + threadIdx.x;
+    const float4 win = gload(g.win, m);
+    const ModInfo mi{gp(g.info)[m]};
+    const float rnup = 1.0f / (float)nup;
+    const bool small = npair < (1L << 22);  // divmod22's range (always, below 2,048 hits per sensor)
+    const long q0 = npair * wid / kWaves, q1 = npair * (wid + 1) / kWaves;  // this wave's quarter
+    int base = 0;
+    if (FILL) {
+      base = gp(w.md_off)[m];
+      for (int q = 0; q < wid; ++q) base += gp(w.md_part)[4 * m + q];
+    }
+    for (long p0 = q0; p0 < q1; p0 += 64) {
+      const long p = p0 + lane;
       bool pass = false;
       int i = 0, j = 0;
       float4 hi, hj;
-      if (p < npair) {
-        i = (int)(p / nup);
-        j = (int)(p - (long)i * nup);
-        hi = i < kMdStageBig ? s_lo[i] : w.hpos[lo0 + i];
-        hj = j < kMdStageBig ? s_up[j] : w.hpos[up0 + j];
+      if (p < q1) {
+        if (small) {
+          const int2 ij = divmod22((int)p, nup, rnup);
+          i = ij.x;
+          j = ij.y;
+        } else {
+          i = (int)(p / nup);
+          j = (int)(p - (long)i * nup);
+        }
+        hi = i < kMdStageBig ? s_lo[i] : gload(w.hpos, lo0 + i);
+        hj = j < kMdStageBig ? s_up[j] : gload(w.hpos, up0 + j);
         pass = md_pass(hi, hj, win, mi);
       }
-      // ordered compaction over the block: ballot per wave, wave totals in LDS
       const unsigned long long bm = __ballot(pass);
-      if (lane == 0) s_wave[wid] = __popcll(bm);
-      __syncthreads();
-      int before = 0, tot = 0;
-#pragma unroll
-      for (int q = 0; q < kWaves; ++q) {
-        before += q < wid ? s_wave[q] : 0;
-        tot += s_wave[q];
-      }
-      __syncthreads();
       if (FILL && pass) {
-        const int pos = base + before + lanes_below(bm);
+        const int pos = base + lanes_below(bm);
         if (pos < w.cap_md) {
-          w.md_hits[pos] = make_int2(w.hidx[lo0 + i], w.hidx[up0 + j]);
-          w.md_mod[pos] = m;
-          w.md_pos[pos] = hi;
+          gstore(w.md_hits, pos, make_int2(gp(w.hidx)[lo0 + i], gp(w.hidx)[up0 + j]));
+          gp(w.md_mod)[pos] = m;
+          gstore(w.md_pos, pos, hi);
           put_stub(w, g, pos, md_stub(hi, hj, mi));
         }
       }
-      base += tot;
+      base += __popcll(bm);
     }
     if (!FILL) {
-      if (threadIdx.x == 0) w.md_cnt[m] = base;
+      if (lane == 0) {
+        gp(w.md_part)[4 * m + wid] = base;
+        s_part[wid] = base;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) gp(w.md_cnt)[m] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
     } else {
       float x0 = 3.0e38f, x1 = -3.0e38f, y0 = 3.0e38f, y1 = -3.0e38f;
       for (int k = threadIdx.x; k < nlo; k += kBlock) {
-        const float4 h = k < kMdStageBig ? s_lo[k] : w.hpos[lo0 + k];
+        const float4 h = k < kMdStageBig ? s_lo[k] : gload(w.hpos, lo0 + k);
         x0 = fminf(x0, h.x); x1 = fmaxf(x1, h.x);
         y0 = fminf(y0, h.y); y1 = fmaxf(y1, h.y);
       }
@@ -631,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
           x0 = fminf(x0, s_box[q].x); x1 = fmaxf(x1, s_box[q].y);
           y0 = fminf(y0, s_box[q].z); y1 = fmaxf(y1, s_box[q].w);
         }
-        w.mod_disc[m] = anchor_disc(x0, x1, y0, y1);
+        gstore(w.mod_disc, m, anchor_disc(x0, x1, y0, y1));
       }
     }
   }
@@ -882,9 +952,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const int na = min(group, n_md - a0);
     if (lane < na) {
       const int a = a0 + lane;
-      s_A[wv][lane] = w.md_pos[a];
+      s_A[wv][lane] = gload(w.md_pos, a);
       s_sa[wv][lane] = get_stub(w, g, a);
-      s_mia[wv][lane] = g.info[w.md_mod[a]];
+      s_mia[wv][lane] = gp(g.info)[gp(w.md_mod)[a]];
       s_cnt[wv][lane] = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -897,7 +967,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         b = s_q[wv][lane];
         q = s_qg[wv][lane];
         float2 beta;
-        pass = ls_pass(s_A[wv][q], w.md_pos[b], s_sa[wv][q], get_stub(w, g, b), ModInfo{s_mia[wv][q]},
+        pass = ls_pass(s_A[wv][q], gload(w.md_pos, b), s_sa[wv][q], get_stub(w, g, b), ModInfo{s_mia[wv][q]},
                        ModInfo{s_qi[wv][lane]}, &beta, g.d0max);
       }
       const unsigned long long m = __ballot(pass);
@@ -910,7 +980,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       if (lane < n) before = s_cnt[wv][q];
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      if (pass && before + below < keep) w.ls_cache[(long)(a0 + q) * kLsCache + before + below] = b;
+      if (pass && before + below < keep) gp(w.ls_cache)[(long)(a0 + q) * kLsCache + before + below] = b;
       if (lane < n && (lane == n - 1 || qn != q)) s_cnt[wv][q] = before + below + (pass ? 1 : 0);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -922,12 +992,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     int r_first = 0, r_cnt = 0, r_info = 0;
     float4 r_disc = make_float4(0.f, 0.f, 0.f, 0.f);
     auto linked = [&](int kk, int &first, int &cnt, int &info, float4 &disc) {
-      const int mb = g.map_tgt[e0 + kk];
-      first = w.md_off[mb];
-      const int last = min(w.md_off[mb + 1], n_md);
+      const int mb = gp(g.map_tgt)[e0 + kk];
+      first = gp(w.md_off)[mb];
+      const int last = min(gp(w.md_off)[mb + 1], n_md);
       cnt = last > first ? last - first : 0;
-      info = g.info[mb];
-      disc = w.mod_disc[mb];
+      info = gp(g.info)[mb];
+      disc = gload(w.mod_disc, mb);
     };
     for (int k = 0; k < na; ++k) {
       // the inner MD's data are read from LDS where they are used, after each round's
@@ -1000,7 +1070,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
           const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
           const int4 E = s_edge[wv][jlo - 1 + __popcll(starts & upto)];
           b = E.x + (c - E.y);
-          const float4 Bp = w.md_pos[b];
+          const float4 Bp = gload(w.md_pos, b);
           info = E.z;
           keep_c = ls_window_may_pass(A, Bp, __int_as_float(E.w)) &&
                    ls_inner_stub_may_pass(A, Bp, sa, mia, ModInfo{info}, g.d0max);
@@ -1041,8 +1111,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
     if (lane < na) {
       const int c = s_cnt[wv][lane];
-      w.ls_cnt[a0 + lane] = c;
-      w.ls_ovf_flag[a0 + lane] = c > keep ? 1 : 0;
+      gp(w.ls_cnt)[a0 + lane] = c;
+      gp(w.ls_ovf_flag)[a0 + lane] = c > keep ? 1 : 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();

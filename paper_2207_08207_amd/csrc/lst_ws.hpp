@@ -119,12 +119,13 @@ struct Ws {
   // hit buckets by (module, sensor)
   int *boff, *hidx;  // (module, sensor) buckets: offsets (2 n_mod + 1), input index per bucketed hit
   int *tile_hist, *tile_off;  // hits per (coarse bucket, wave tile), coarse-bucket major, and their scan
-  int *hkey, *hsrc;  // hits in coarse-bucket order (stable): bucket key, input index
-  float4 *hcp;       // and their x, y, z, r
+  int *hkey;    // hits in coarse-bucket order (stable): bucket key
+  float4 *hcp;  // and x, y, z, input index (bits)
   float4 *hpos;
   // mini-doublets
   int *md_cnt, *md_off;
   int *md_cache;     // per module: up to kMdCache passing pairs (lower << 16 | upper) of the count pass
+  int *md_part;      // per dense module: MDs of each wave's quarter of its pairs (count pass)
   int2 *md_hits;    // input indices of the lower and upper hit
   int *md_mod;
   float4 *md_pos;   // anchor (lower hit) x, y, z, r
