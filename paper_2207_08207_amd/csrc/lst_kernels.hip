@@ -264,12 +264,12 @@ void launch_tc_export(const Ws *d_ws, int max_tc, int max_hits, int *type, int *
 
 // The bucket key of hit i, or -1 for a pixel hit or invalid data (*bad).
 __device__ __forceinline__ int hit_key(const Ws &w, int i, int n_mod, bool *bad) {
-  const int m = w.module[i];
-  const float x = w.x[i], y = w.y[i], z = w.z[i];
+  const int m = gp(w.module)[i];
+  const float x = gp(w.x)[i], y = gp(w.y)[i], z = gp(w.z)[i];
   bool b = !(isfinite(x) && isfinite(y) && isfinite(z)) || m < -1 || m >= n_mod;
   int key = -1;
   if (m >= 0) {
-    const int sn = w.sensor[i];
+    const int sn = gp(w.sensor)[i];
     b |= (sn != 0 && sn != 1);
     if (!b) key = 2 * m + sn;
   }
@@ -326,14 +326,14 @@ __global__ __launch_bounds__(kBlock) void k_hits_count(const Ws *__restrict__ wb
       int t = 0;
 #pragma unroll
       for (int q = 0; q < kWaves; ++q) t += s_h[q][c];
-      w.tile_hist[(long)c * ntb + tb] = t;
+      gp(w.tile_hist)[(long)c * ntb + tb] = t;
     }
   }
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
-    bool bad = !(w.q[s] == 1 || w.q[s] == -1) || !(isfinite(w.px[s]) && isfinite(w.py[s]) && isfinite(w.pz[s]));
-    bad |= !(w.px[s] * w.px[s] + w.py[s] * w.py[s] > 0.0f);
+    bool bad = !(w.q[s] == 1 || gp(w.q)[s] == -1) || !(isfinite(w.px[s]) && isfinite(w.py[s]) && isfinite(w.pz[s]));
+    bad |= !(w.px[s] * gp(w.px)[s] + gp(w.py)[s] * gp(w.py)[s] > 0.0f);
     for (int k = 0; k < 4; ++k) {
-      const int h = w.hits4[4 * s + k];
+      const int h = gp(w.hits4)[4 * s + k];
       bad |= (h < 0 || h >= w.n_hits);
       if (h >= 0 && h < w.n_hits) bad |= (w.module[h] != -1);
     }
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ 
   (void)wave_coarse_counts(w, tb, n_mod, s_h[wv]);
   __syncthreads();
   for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-    int run = w.tile_off[(long)c * ntb + tb];
+    int run = gp(w.tile_off)[(long)c * ntb + tb];
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) {
       const int v = s_h[q][c];
@@ -381,8 +381,8 @@ __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ 
     if (act) {
       base = s_h[wv][c];
       const int pos = base + lanes_below(peers);
-      w.hkey[pos] = key;
-      w.hcp[pos] = make_float4(w.x[i], w.y[i], w.z[i], __int_as_float(i));
+      gp(w.hkey)[pos] = key;
+      gstore(w.hcp, pos, make_float4(w.x[i], gp(w.y)[i], gp(w.z)[i], __int_as_float(i)));
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -406,13 +406,13 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__res
   const int nc = n_coarse(n_mod), ntb = n_hit_tiles(w.n_hits), nkeys = 2 * n_mod;
   const int c = blockIdx.x;
   if (c >= nc) return;  // the whole block
-  const int j0 = w.tile_off[(long)c * ntb], j1 = w.tile_off[(long)(c + 1) * ntb];
+  const int j0 = gp(w.tile_off)[(long)c * ntb], j1 = gp(w.tile_off)[(long)(c + 1) * ntb];
   const long L = j1 - j0;
   const int a = j0 + (int)(L * wv / kSortWaves), b = j0 + (int)(L * (wv + 1) / kSortWaves);
   for (int f = lane; f < kFineKeys; f += 64) s_cnt[wv][f] = 0;
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  for (int j = a + lane; j < b; j += 64) atomicAdd(&s_cnt[wv][w.hkey[j] & (kFineKeys - 1)], 1);  // LDS
+  for (int j = a + lane; j < b; j += 64) atomicAdd(&s_cnt[wv][gp(w.hkey)[j] & (kFineKeys - 1)], 1);  // LDS
   __syncthreads();
   // each key's total over the waves, then the keys' first positions (wave 0: one key per lane)
   int tot = 0;
@@ -432,9 +432,9 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__res
     const int k = c * kFineKeys + lane;
     if (lane < kFineKeys) {
       s_key0[lane] = ex;
-      if (k < nkeys) w.boff[k] = ex;
+      if (k < nkeys) gp(w.boff)[k] = ex;
     }
-    if (c == nc - 1 && lane == 0) w.boff[nkeys] = j1;
+    if (c == nc - 1 && lane == 0) gp(w.boff)[nkeys] = j1;
   }
   __syncthreads();
   // first position of each (wave, key): the key's first position plus the earlier waves' counts
@@ -456,9 +456,9 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__res
     if (act) {
       base = s_cnt[wv][f];
       const int pos = base + lanes_below(peers);
-      const float4 h = w.hcp[j];
-      w.hidx[pos] = __float_as_int(h.w);
-      w.hpos[pos] = make_float4(h.x, h.y, h.z, sqrtf(h.x * h.x + h.y * h.y));
+      const float4 h = gload(w.hcp, j);
+      gp(w.hidx)[pos] = __float_as_int(h.w);
+      gstore(w.hpos, pos, make_float4(h.x, h.y, h.z, sqrtf(h.x * h.x + h.y * h.y)));
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -804,12 +804,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
   const int wpb = blockDim.x >> 6;  // waves per block (a tuned launch may run fewer than kWaves)
   const int waves_total = gridDim.x * wpb;
   auto process = [&](const int a) {
-    const int ma = w.md_mod[a];
-    const float4 A = w.md_pos[a];
+    const int ma = gp(w.md_mod)[a];
+    const float4 A = gload(w.md_pos, a);
     const float2 sa = get_stub(w, g, a);
-    const ModInfo mia{g.info[ma]};
-    const int e0 = g.map_off[ma];
-    const int ne = g.map_off[ma + 1] - e0;  // <= kMaxEdges, checked when the geometry is loaded
+    const ModInfo mia{gp(g.info)[ma]};
+    const int e0 = gp(g.map_off)[ma];
+    const int ne = gp(g.map_off)[ma + 1] - e0;  // <= kMaxEdges, checked when the geometry is loaded
     // per-edge MD ranges and their exclusive prefix over the wave
     int run = 0;
     for (int k0 = 0; k0 < ne; k0 += 64) {
@@ -817,13 +817,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       int first = 0, cnt = 0, info = 0;
       float wm = 0.0f;
       if (k < ne) {
-        const int mb = g.map_tgt[e0 + k];
-        first = w.md_off[mb];
+        const int mb = gp(g.map_tgt)[e0 + k];
+        first = gp(w.md_off)[mb];
         const int last = min(w.md_off[mb + 1], n_md);
         cnt = last > first ? last - first : 0;
-        info = g.info[mb];
+        info = gp(g.info)[mb];
         if (cnt > 0) {
-          const float4 disc = w.mod_disc[mb];
+          const float4 disc = gload(w.mod_disc, mb);
           wm = ls_window_bound(A, mia, disc, ModInfo{info}, g.d0max);
           if (!ls_module_may_pass(A, disc, wm)) cnt = 0;
         }
@@ -845,7 +845,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const int total = run;
-    int out = w.ls_off[a];
+    int out = gp(w.ls_off)[a];
     // the full selection on the first n queued candidates (n <= 64), in candidate order
     auto select = [&](int n) {
       bool pass = false;
@@ -853,14 +853,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       float2 beta = make_float2(0.f, 0.f);
       if (lane < n) {
         b = s_q[wv][lane];
-        pass = ls_pass(A, w.md_pos[b], sa, get_stub(w, g, b), mia, ModInfo{s_qi[wv][lane]}, &beta, g.d0max);
+        pass = ls_pass(A, gload(w.md_pos, b), sa, get_stub(w, g, b), mia, ModInfo{s_qi[wv][lane]}, &beta, g.d0max);
       }
       const unsigned long long m = __ballot(pass);
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
       const int pos = out + pre;
       if (pass && pos < w.cap_ls) {
-        w.ls_md[pos] = make_int2(a, b);
-        w.ls_beta[pos] = beta;
+        gstore(w.ls_md, pos, make_int2(a, b));
+        gstore(w.ls_beta, pos, beta);
       }
       out += __popcll(m);
     };
@@ -876,7 +876,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       if (c < total) {
         while (s_pre[wv][e + 1] <= c) ++e;
         b = s_first[wv][e] + (c - s_pre[wv][e]);
-        const float4 Bp = w.md_pos[b];
+        const float4 Bp = gload(w.md_pos, b);
         info = s_info[wv][e];
         keep = ls_window_may_pass(A, Bp, s_wmax[wv][e]) &&
                ls_inner_stub_may_pass(A, Bp, sa, mia, ModInfo{info}, g.d0max);
@@ -1182,17 +1182,17 @@ __global__ void k_ls_copy(const Ws *__restrict__ wb, int keep) {
   const long n = (long)uload(w.ctr + C_NMD) * kLsCopyLanes;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const int a = (int)(i / kLsCopyLanes), k0 = (int)(i % kLsCopyLanes);
-    const int cnt = w.ls_cnt[a];
+    const int cnt = gp(w.ls_cnt)[a];
     if (cnt > keep) {
-      if (k0 == 0) w.ls_ovf[w.ls_ovf_off[a]] = a;  // searched again by k_ls_fill
+      if (k0 == 0) gp(w.ls_ovf)[gp(w.ls_ovf_off)[a]] = a;  // searched again by k_ls_fill
       continue;
     }
     for (int k = k0; k < cnt; k += kLsCopyLanes) {
-      const int pos = w.ls_off[a] + k;
+      const int pos = gp(w.ls_off)[a] + k;
       if (pos >= w.cap_ls) break;
-      const int b = w.ls_cache[(long)a * kLsCache + k];
-      w.ls_md[pos] = make_int2(a, b);
-      w.ls_beta[pos] = ls_beta(w.md_pos[a], w.md_pos[b]);
+      const int b = gp(w.ls_cache)[(long)a * kLsCache + k];
+      gstore(w.ls_md, pos, make_int2(a, b));
+      gstore(w.ls_beta, pos, ls_beta(gload(w.md_pos, a), gload(w.md_pos, b)));
     }
   }
 }
@@ -1252,16 +1252,16 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
     const int l1 = (int)p0 + lane;
     int n = 0, cached = 0;
     // the fill reads a parent's data only if the count pass found a triplet on it
-    if (l1 < n_ls && (!FILL || w.t3_cnt[l1] > 0)) {
-      const int2 ab = w.ls_md[l1];
-      s_a[wv][lane] = w.md_pos[ab.x];
-      s_b[wv][lane] = w.md_pos[ab.y];
-      s_mi[wv][lane] = g.info[w.md_mod[ab.x]] | (g.info[w.md_mod[ab.y]] << 8);
-      const int lo = w.ls_off[ab.y], hi = min(w.ls_off[ab.y + 1], n_ls);
+    if (l1 < n_ls && (!FILL || gp(w.t3_cnt)[l1] > 0)) {
+      const int2 ab = gload(w.ls_md, l1);
+      s_a[wv][lane] = gload(w.md_pos, ab.x);
+      s_b[wv][lane] = gload(w.md_pos, ab.y);
+      s_mi[wv][lane] = gp(g.info)[gp(w.md_mod)[ab.x]] | (gp(g.info)[gp(w.md_mod)[ab.y]] << 8);
+      const int lo = gp(w.ls_off)[ab.y], hi = min(gp(w.ls_off)[ab.y + 1], n_ls);
       s_lo[wv][lane] = lo;
       n = hi > lo ? hi - lo : 0;
       if (FILL) {
-        const int cnt = w.t3_cnt[l1];
+        const int cnt = gp(w.t3_cnt)[l1];
         if (cnt <= g.tiles.t3_cache) {  // the count pass kept them all: only those are tested again
           n = cnt;
           cached = 1;
@@ -1280,24 +1280,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
       if (lane < nb) {
         e = s_qe[wv][lane];
         cand = s_qc[wv][lane];
-        cmd = w.ls_md[cand].y;
+        cmd = gload(w.ls_md, cand).y;
         const int mi = s_mi[wv][e];
-        pass = t3_pass(s_a[wv][e], s_b[wv][e], w.md_pos[cmd], ModInfo{mi & 0xff}, ModInfo{mi >> 8},
-                       ModInfo{g.info[w.md_mod[cmd]]}, &attr, g.d0max);
+        pass = t3_pass(s_a[wv][e], s_b[wv][e], gload(w.md_pos, cmd), ModInfo{mi & 0xff}, ModInfo{mi >> 8},
+                       ModInfo{gp(g.info)[gp(w.md_mod)[cmd]]}, &attr, g.d0max);
       }
       const int first = run_first_lane(e, nb);
       const unsigned long long m = __ballot(pass);
       if (pass) {
         const int r = pair_rank(m, first, s_cnt[wv][e]);
         if (!FILL) {
-          if (r < g.tiles.t3_cache) w.t3_cache[(long)((int)p0 + e) * kT3Cache + r] = cand;
+          if (r < g.tiles.t3_cache) gp(w.t3_cache)[(long)((int)p0 + e) * kT3Cache + r] = cand;
         } else {
-          const int pos = w.t3_off[(int)p0 + e] + r;
+          const int pos = gp(w.t3_off)[(int)p0 + e] + r;
           if (pos < w.cap_t3) {
-            const int2 ab = w.ls_md[(int)p0 + e];
-            w.t3_md[pos] = make_int4(ab.x, ab.y, cmd, (int)p0 + e);
-            w.t3_attr[pos] = attr;
-            w.t3_first[pos] = make_float2(s_a[wv][e].x, s_a[wv][e].y);
+            const int2 ab = gload(w.ls_md, (int)p0 + e);
+            gstore(w.t3_md, pos, make_int4(ab.x, ab.y, cmd, (int)p0 + e));
+            gstore(w.t3_attr, pos, attr);
+            gstore(w.t3_first, pos, make_float2(s_a[wv][e].x, s_a[wv][e].y));
           }
         }
       }
@@ -1317,11 +1317,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
       int cand = 0;
       if (c < total) {
         const int idx = c - s_seg[wv][e];
-        cand = s_cached[wv][e] ? w.t3_cache[(long)((int)p0 + e) * kT3Cache + idx] : s_lo[wv][e] + idx;
-        const int cmd = w.ls_md[cand].y;
+        cand = s_cached[wv][e] ? gp(w.t3_cache)[(long)((int)p0 + e) * kT3Cache + idx] : s_lo[wv][e] + idx;
+        const int cmd = gload(w.ls_md, cand).y;
         const int mi = s_mi[wv][e];
-        keep = t3_may_pass(s_a[wv][e], s_b[wv][e], w.md_pos[cmd], ModInfo{mi & 0xff}, ModInfo{mi >> 8},
-                           ModInfo{g.info[w.md_mod[cmd]]}, g.d0max);
+        keep = t3_may_pass(s_a[wv][e], s_b[wv][e], gload(w.md_pos, cmd), ModInfo{mi & 0xff}, ModInfo{mi >> 8},
+                           ModInfo{gp(g.info)[gp(w.md_mod)[cmd]]}, g.d0max);
       }
       const unsigned long long m = __ballot(keep);
       if (keep) {
@@ -1352,7 +1352,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
       }
     }
     if (nq > 0) select(nq);
-    if (!FILL && l1 < n_ls) w.t3_cnt[l1] = s_cnt[wv][lane];
+    if (!FILL && l1 < n_ls) gp(w.t3_cnt)[l1] = s_cnt[wv][lane];
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
@@ -1392,20 +1392,20 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
     const int t1 = (int)p0 + lane;
     int n = 0, cached = 0;
     // the fill reads a parent's data only if the count pass found a quintuplet on it
-    if (t1 < n_t3 && (!FILL || w.t5_cnt[t1] > 0)) {
-      const int4 abc = w.t3_md[t1];
-      s_p[wv][0][lane] = w.md_pos[abc.x];
-      s_p[wv][1][lane] = w.md_pos[abc.y];
-      s_p[wv][2][lane] = w.md_pos[abc.z];
-      s_mi[wv][lane] = g.info[w.md_mod[abc.x]] | (g.info[w.md_mod[abc.y]] << 8) | (g.info[w.md_mod[abc.z]] << 16);
-      s_tin[wv][lane] = w.t3_attr[t1];
+    if (t1 < n_t3 && (!FILL || gp(w.t5_cnt)[t1] > 0)) {
+      const int4 abc = gload(w.t3_md, t1);
+      s_p[wv][0][lane] = gload(w.md_pos, abc.x);
+      s_p[wv][1][lane] = gload(w.md_pos, abc.y);
+      s_p[wv][2][lane] = gload(w.md_pos, abc.z);
+      s_mi[wv][lane] = gp(g.info)[gp(w.md_mod)[abc.x]] | (g.info[gp(w.md_mod)[abc.y]] << 8) | (g.info[gp(w.md_mod)[abc.z]] << 16);
+      s_tin[wv][lane] = gload(w.t3_attr, t1);
       // triplets with first MD c: those built from segments with inner MD c
       const int lsb = min(w.ls_off[abc.z], n_ls), lse = min(w.ls_off[abc.z + 1], n_ls);
-      const int lo = w.t3_off[lsb], hi = min(w.t3_off[lse], n_t3);
+      const int lo = gp(w.t3_off)[lsb], hi = min(w.t3_off[lse], n_t3);
       s_lo[wv][lane] = lo;
       n = hi > lo ? hi - lo : 0;
       if (FILL) {
-        const int cnt = w.t5_cnt[t1];
+        const int cnt = gp(w.t5_cnt)[t1];
         if (cnt <= g.tiles.t5_cache) {  // the count pass kept them all: only those are tested again
           n = cnt;
           cached = 1;
@@ -1424,36 +1424,36 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
       if (lane < nb) {
         e = s_qe[wv][lane];
         t2 = s_qc[wv][lane];
-        cde = w.t3_md[t2];
+        cde = gload(w.t3_md, t2);
         float4 P[5];
         ModInfo M[5];
         const int mi = s_mi[wv][e];
         P[0] = s_p[wv][0][e]; P[1] = s_p[wv][1][e]; P[2] = s_p[wv][2][e];
         M[0].bits = mi & 0xff; M[1].bits = (mi >> 8) & 0xff; M[2].bits = mi >> 16;
-        P[3] = w.md_pos[cde.y];
-        P[4] = w.md_pos[cde.z];
-        M[3].bits = g.info[w.md_mod[cde.y]];
-        M[4].bits = g.info[w.md_mod[cde.z]];
-        pass = t5_pass(P, M, s_tin[wv][e], w.t3_attr[t2], at, g.d0max, g.t5cut);
+        P[3] = gload(w.md_pos, cde.y);
+        P[4] = gload(w.md_pos, cde.z);
+        M[3].bits = gp(g.info)[gp(w.md_mod)[cde.y]];
+        M[4].bits = gp(g.info)[gp(w.md_mod)[cde.z]];
+        pass = t5_pass(P, M, s_tin[wv][e], gload(w.t3_attr, t2), at, g.d0max, g.t5cut);
       }
       const int first = run_first_lane(e, nb);
       const unsigned long long m = __ballot(pass);
       if (pass) {
         const int r = pair_rank(m, first, s_cnt[wv][e]);
         if (!FILL) {
-          if (r < g.tiles.t5_cache) w.t5_cache[(long)((int)p0 + e) * kT5Cache + r] = t2;
+          if (r < g.tiles.t5_cache) gp(w.t5_cache)[(long)((int)p0 + e) * kT5Cache + r] = t2;
         } else {
           const int t1e = (int)p0 + e;
-          const int pos = w.t5_off[t1e] + r;
+          const int pos = gp(w.t5_off)[t1e] + r;
           if (pos < w.cap_t5) {
-            const int4 abc = w.t3_md[t1e];
-            w.t5_t3[pos] = make_int2(t1e, t2);
+            const int4 abc = gload(w.t3_md, t1e);
+            gstore(w.t5_t3, pos, make_int2(t1e, t2));
             int *md = w.t5_md + 5 * (long)pos;
             md[0] = abc.x; md[1] = abc.y; md[2] = abc.z; md[3] = cde.y; md[4] = cde.z;
             float *dst = w.t5_attr + 8 * (long)pos;
 #pragma unroll
             for (int k = 0; k < 8; ++k) dst[k] = at[k];
-            w.t5_keep[pos] = 1;  // until a better duplicate is found
+            gp(w.t5_keep)[pos] = 1;  // until a better duplicate is found
           }
         }
       }
@@ -1473,14 +1473,14 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
       if (c < total) {
         while (s_seg[wv][e + 1] <= c) ++e;
         const int idx = c - s_seg[wv][e];
-        t2 = s_cached[wv][e] ? w.t5_cache[(long)((int)p0 + e) * kT5Cache + idx] : s_lo[wv][e] + idx;
+        t2 = s_cached[wv][e] ? gp(w.t5_cache)[(long)((int)p0 + e) * kT5Cache + idx] : s_lo[wv][e] + idx;
         // the radius compatibility cut exactly (no division), then the fast azimuth-z test
-        const float4 tin = s_tin[wv][e], tout = w.t3_attr[t2];
+        const float4 tin = s_tin[wv][e], tout = gload(w.t3_attr, t2);
         if (fabsf(tin.x - tout.x) <= tin.y + tout.y) {
-          const int4 cde = w.t3_md[t2];
+          const int4 cde = gload(w.t3_md, t2);
           const int mi = s_mi[wv][e];
-          keep = phiz_may_pass(s_p[wv][0][e], s_p[wv][2][e], w.md_pos[cde.z], ModInfo{mi & 0xff},
-                               ModInfo{mi >> 16}, ModInfo{g.info[w.md_mod[cde.z]]}, g.d0max);
+          keep = phiz_may_pass(s_p[wv][0][e], s_p[wv][2][e], gload(w.md_pos, cde.z), ModInfo{mi & 0xff},
+                               ModInfo{mi >> 16}, ModInfo{gp(g.info)[gp(w.md_mod)[cde.z]]}, g.d0max);
         }
       }
       const unsigned long long m = __ballot(keep);
@@ -1512,7 +1512,7 @@ __global__ __launch_bounds__(kBlock) void k_t5(const Ws *__restrict__ wb, DevGeo
       }
     }
     if (nq > 0) select(nq);
-    if (!FILL && t1 < n_t3) w.t5_cnt[t1] = s_cnt[wv][lane];
+    if (!FILL && t1 < n_t3) gp(w.t5_cnt)[t1] = s_cnt[wv][lane];
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
@@ -1523,7 +1523,7 @@ __global__ void k_t5_inc_count(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   const int n = uload(w.ctr + C_NT5);
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
-    for (int k = 0; k < 5; ++k) atomicAdd(&w.inc_cnt[w.t5_md[5 * (long)t + k]], 1);
+    for (int k = 0; k < 5; ++k) atomicAdd(&w.inc_cnt[gp(w.t5_md)[5 * (long)t + k]], 1);
 }
 __global__ void k_t5_inc_scatter(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
@@ -1531,8 +1531,8 @@ __global__ void k_t5_inc_scatter(const Ws *__restrict__ wb) {
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const int score = __float_as_int(w.t5_attr[8 * (long)t + 1]);
     for (int k = 0; k < 5; ++k) {
-      const int md = w.t5_md[5 * (long)t + k];
-      w.inc_list[w.inc_off[md] + atomicAdd(&w.inc_cur[md], 1)] = make_int2(t, score);
+      const int md = gp(w.t5_md)[5 * (long)t + k];
+      w.inc_list[gp(w.inc_off)[md] + atomicAdd(&w.inc_cur[md], 1)] = make_int2(t, score);
     }
   }
 }
@@ -1583,14 +1583,14 @@ __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) 
       int mt[5];
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
-        mt[j] = w.t5_md[5 * (long)t + j];
+        mt[j] = gp(w.t5_md)[5 * (long)t + j];
         s_mt[wv][j][lane] = mt[j];
       }
-      if (k == 0) w.t5_first[t] = make_float2(w.md_pos[mt[0]].x, w.md_pos[mt[0]].y);
-      const int lo = w.inc_off[mt[k]];
+      if (k == 0) gstore(w.t5_first, t, make_float2(w.md_pos[mt[0]].x, w.md_pos[mt[0]].y));
+      const int lo = gp(w.inc_off)[mt[k]];
       s_lo[wv][lane] = lo;
-      cnt = w.inc_off[mt[k] + 1] - lo;
-      s_st[wv][lane] = w.t5_attr[8 * (long)t + 1];
+      cnt = gp(w.inc_off)[mt[k] + 1] - lo;
+      s_st[wv][lane] = gp(w.t5_attr)[8 * (long)t + 1];
     }
     const int total = wave_segments(cnt, s_seg[wv]);
     const int start = s_seg[wv][lane];
@@ -1609,7 +1609,7 @@ __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) 
       if (st < su) continue;
       int mu[5];
 #pragma unroll
-      for (int j = 0; j < 5; ++j) mu[j] = w.t5_md[5 * (long)u + j];
+      for (int j = 0; j < 5; ++j) mu[j] = gp(w.t5_md)[5 * (long)u + j];
       int shared = 0, first = 5;
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
@@ -1626,7 +1626,7 @@ __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) 
         t5_hits(w, u, hu);
         drop = better<10>(su, hu, st, ht);
       }
-      if (drop) w.t5_keep[t] = 0;
+      if (drop) gp(w.t5_keep)[t] = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -1644,21 +1644,21 @@ __device__ __forceinline__ Seed load_seed(const Ws &w, int s) {
 __global__ void k_pls(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
-    const float px = w.px[s], py = w.py[s], pz = w.pz[s];
+    const float px = gp(w.px)[s], py = gp(w.py)[s], pz = gp(w.pz)[s];
     const float pt = sqrtf(px * px + py * py);
     float *o = w.pls + 8 * (long)s;
     o[0] = pt;
     o[1] = px / pt;
     o[2] = py / pt;
     o[3] = pz / pt;
-    o[4] = (-(float)w.q[s] * kCurv) / pt;
-    int h0 = w.hits4[4 * (long)s];
+    o[4] = (-(float)gp(w.q)[s] * kCurv) / pt;
+    int h0 = gp(w.hits4)[4 * (long)s];
     h0 = (h0 >= 0 && h0 < w.n_hits) ? h0 : 0;
-    o[5] = w.x[h0];
-    o[6] = w.y[h0];
-    o[7] = w.z[h0];
+    o[5] = gp(w.x)[h0];
+    o[6] = gp(w.y)[h0];
+    o[7] = gp(w.z)[h0];
     for (int k = 0; k < 4; ++k) {
-      const int h = w.hits4[4 * (long)s + k];
+      const int h = gp(w.hits4)[4 * (long)s + k];
       if (h >= 0 && h < w.n_hits) atomicAdd(&w.ph_cnt[h], 1);
     }
   }
@@ -1667,8 +1667,8 @@ __global__ void k_ph_scatter(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x)
     for (int k = 0; k < 4; ++k) {
-      const int h = w.hits4[4 * (long)s + k];
-      if (h >= 0 && h < w.n_hits) w.ph_list[w.ph_off[h] + atomicAdd(&w.ph_cur[h], 1)] = s;
+      const int h = gp(w.hits4)[4 * (long)s + k];
+      if (h >= 0 && h < w.n_hits) gp(w.ph_list)[gp(w.ph_off)[h] + atomicAdd(&w.ph_cur[h], 1)] = s;
     }
 }
 // pLS duplicate removal: seeds sharing at least 3 pixel hits; the lower seed index wins.
@@ -1676,13 +1676,13 @@ __global__ void k_pls_dedup(const Ws *__restrict__ wb) {
   const Ws &w = wb[blockIdx.y];
   for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < w.n_seeds; s += gridDim.x * blockDim.x) {
     int hs[4];
-    for (int k = 0; k < 4; ++k) hs[k] = w.hits4[4 * (long)s + k];
+    for (int k = 0; k < 4; ++k) hs[k] = gp(w.hits4)[4 * (long)s + k];
     bool keep = true;
     for (int k = 0; k < 4 && keep; ++k) {
       const int h = hs[k];
       if (h < 0 || h >= w.n_hits) continue;
-      for (int q = w.ph_off[h]; q < w.ph_off[h + 1] && keep; ++q) {
-        const int t = w.ph_list[q];
+      for (int q = gp(w.ph_off)[h]; q < gp(w.ph_off)[h + 1] && keep; ++q) {
+        const int t = gp(w.ph_list)[q];
         if (t >= s) continue;
         int sh = 0;
         for (int i = 0; i < 4; ++i) {
@@ -1694,7 +1694,7 @@ __global__ void k_pls_dedup(const Ws *__restrict__ wb) {
         if (sh >= 3) keep = false;
       }
     }
-    w.pls_keep[s] = keep ? 1 : 0;
+    gp(w.pls_keep)[s] = keep ? 1 : 0;
   }
 }
 
@@ -1703,20 +1703,20 @@ template <int K>
 __device__ __forceinline__ void load_object(const Ws &w, const DevGeom &g, int t, float4 *P, ModInfo *M, float *kT,
                                             float *dkT) {
   if constexpr (K == 3) {
-    const int4 abc = w.t3_md[t];
+    const int4 abc = gload(w.t3_md, t);
     const int md[3] = {abc.x, abc.y, abc.z};
 #pragma unroll
-    for (int k = 0; k < 3; ++k) { P[k] = w.md_pos[md[k]]; M[k].bits = g.info[w.md_mod[md[k]]]; }
-    const float4 a3 = w.t3_attr[t];
+    for (int k = 0; k < 3; ++k) { P[k] = w.md_pos[md[k]]; M[k].bits = gp(g.info)[gp(w.md_mod)[md[k]]]; }
+    const float4 a3 = gload(w.t3_attr, t);
     *kT = a3.x; *dkT = a3.y;
   } else {
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
-      const int md = w.t5_md[5 * (long)t + k];
-      P[k] = w.md_pos[md];
-      M[k].bits = g.info[w.md_mod[md]];
+      const int md = gp(w.t5_md)[5 * (long)t + k];
+      P[k] = gload(w.md_pos, md);
+      M[k].bits = gp(g.info)[gp(w.md_mod)[md]];
     }
-    const float4 a3 = w.t3_attr[w.t5_t3[t].y];
+    const float4 a3 = w.t3_attr[gload(w.t5_t3, t).y];
     *kT = a3.x; *dkT = a3.y;
   }
 }
@@ -1747,7 +1747,7 @@ __device__ __forceinline__ int zbin_of(float z) {
 }
 template <int K>
 __device__ __forceinline__ int obj_bin(const Ws &w, int t) {
-  const float4 a = w.md_pos[K == 3 ? w.t3_md[t].x : w.t5_md[5 * (long)t]];
+  const float4 a = w.md_pos[K == 3 ? gload(w.t3_md, t).x : gp(w.t5_md)[5 * (long)t]];
   const float ph = atan2f(a.y, a.x);
   const int rp = ph == ph ? ring_of(sqrtf(a.x * a.x + a.y * a.y)) * kPhiBins + phibin_of(ph) : 0;
   return rp * kZBins + zbin_of(a.z);
@@ -1759,7 +1759,7 @@ __global__ void k_obj_bin_count(const Ws *__restrict__ wb) {
   const int n = K == 3 ? w.ctr[C_NT3] : w.ctr[C_NT5];
   int *cnt = K == 3 ? w.b3_cnt : w.b5_cnt;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
-    if (K == 3 || w.t5_keep[t]) atomicAdd(&cnt[obj_bin<K>(w, t)], 1);
+    if (K == 3 || gp(w.t5_keep)[t]) atomicAdd(&cnt[obj_bin<K>(w, t)], 1);
 }
 template <int K>
 __global__ void k_obj_bin_scatter(const Ws *__restrict__ wb, DevGeom g) {
@@ -1770,13 +1770,13 @@ __global__ void k_obj_bin_scatter(const Ws *__restrict__ wb, DevGeom g) {
   int *lst = K == 3 ? w.b3_list : w.b5_list;
   float4 *pos = K == 3 ? w.b3_pos : w.b5_pos;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x)
-    if (K == 3 || w.t5_keep[t]) {
+    if (K == 3 || gp(w.t5_keep)[t]) {
       const int b = obj_bin<K>(w, t);
       const int j = off[b] + atomicAdd(&cur[b], 1);
       lst[j] = t;
-      const int md = K == 3 ? w.t3_md[t].x : w.t5_md[5 * (long)t];
-      const float4 a = w.md_pos[md];
-      pos[j] = make_float4(a.x, a.y, a.z, __int_as_float(g.info[w.md_mod[md]]));
+      const int md = K == 3 ? gload(w.t3_md, t).x : gp(w.t5_md)[5 * (long)t];
+      const float4 a = gload(w.md_pos, md);
+      pos[j] = make_float4(a.x, a.y, a.z, __int_as_float(g.info[gp(w.md_mod)[md]]));
     }
 }
 
@@ -1818,7 +1818,7 @@ __global__ __launch_bounds__(1024) void k_seed_order(const Ws *__restrict__ wb) 
   s_cnt[2 * t] = ex;
   s_cnt[2 * t + 1] = ex + c0;
   __syncthreads();
-  for (int s = t; s < S; s += 1024) w.seed_order[atomicAdd(&s_cnt[seed_key(w, s)], 1)] = s;  // LDS rank
+  for (int s = t; s < S; s += 1024) gp(w.seed_order)[atomicAdd(&s_cnt[seed_key(w, s)], 1)] = s;  // LDS rank
 }
 
 // Marks, in the wave's bin mask, every (ring, azimuth) bin that can hold the
@@ -1910,8 +1910,9 @@ __device__ __forceinline__ int2 seed_zbins(const Seed &sd, float lo, float hi) {
 // all objects instead.  The count pass keeps up to pt3_cache / pt5_cache
 // passing objects per seed with their attributes, which the fill then ranks
 // and copies; more than max_slices marked bins are searched bin by bin.
+// (Seven waves per SIMD for the count: at most 72 VGPRs, no spills.)
 template <int K, bool FILL, bool BOTH = false>
-__global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb, DevGeom g) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) void k_pt_binned(const Ws *__restrict__ wb, DevGeom g) {
   __shared__ unsigned s_mask[kWaves][kMaskWords];
   __shared__ int s_slo[kWaves][kRings], s_shi[kWaves][kRings];
   __shared__ int2 s_zb[kWaves][kRings];
@@ -2173,7 +2174,7 @@ __global__ __launch_bounds__(kBlock) void k_pt_binned(const Ws *__restrict__ wb,
       const int t = t0 + lane;
       bool pass = false;
       float4 attr = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (t < n_obj && (KO == 3 || w.t5_keep[t])) {
+      if (t < n_obj && (KO == 3 || gp(w.t5_keep)[t])) {
         const float2 f = first[t];
         if (seed_box(sd, f.x, f.y)) {
           float4 P[KO];
@@ -2222,7 +2223,7 @@ __global__ void k_pt_obj_best(const Ws *__restrict__ wb) {
 template <int K>
 __device__ __forceinline__ void obj_hits(const Ws &w, int t, int *h) {
   if constexpr (K == 3) {
-    const int4 abc = w.t3_md[t];
+    const int4 abc = gload(w.t3_md, t);
     const int md[3] = {abc.x, abc.y, abc.z};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -2310,8 +2311,8 @@ __global__ void k_tc_pt5(const Ws *__restrict__ wb) {
     const int k = w.pt5_keep[i];
     w.f_pt5[i] = k;
     if (k) {
-      w.seed_used[w.pt5_so[i].x] = 1;
-      w.t5_used[w.pt5_so[i].y] = 1;
+      w.seed_used[gload(w.pt5_so, i).x] = 1;
+      w.t5_used[gload(w.pt5_so, i).y] = 1;
     }
   }
 }
@@ -2320,7 +2321,7 @@ __global__ void k_tc_dirs_pt5(const Ws *__restrict__ wb) {
   const int n = uload(w.ctr + C_NPT5);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     if (w.f_pt5[i]) {
-      const Dir d = dir_of_seed(w, w.pt5_so[i].x);
+      const Dir d = dir_of_seed(w, gload(w.pt5_so, i).x);
       w.dir_pt5[w.p_pt5[i]] = make_float4(d.dx, d.dy, d.lam, 0.f);
     }
 }
@@ -2404,7 +2405,7 @@ __global__ void k_tc_pt3(const Ws *__restrict__ wb) {
   const int wpb = blockDim.x >> 6;
   const int nw = gridDim.x * wpb;
   for (int i = blockIdx.x * wpb + (threadIdx.x >> 6); i < n; i += nw) {
-    const int s = w.pt3_so[i].x;
+    const int s = gload(w.pt3_so, i).x;
     const bool cand = w.pt3_keep[i] && !w.seed_used[s];
     const bool nr = near_any_wave(dir_of_seed(w, s), cand, w.bdir_pt5, w.boff_pt5, kDpT3, bin_reach(0.02));
     if (lane_id() == 0) w.f_pt3[i] = (cand && !nr) ? 1 : 0;
@@ -2415,7 +2416,7 @@ __global__ void k_tc_dirs_pt3(const Ws *__restrict__ wb) {
   const int n = uload(w.ctr + C_NPT3);
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
     if (w.f_pt3[i]) {
-      const int s = w.pt3_so[i].x;
+      const int s = gload(w.pt3_so, i).x;
       const Dir d = dir_of_seed(w, s);
       w.dir_pt3[w.p_pt3[i]] = make_float4(d.dx, d.dy, d.lam, 0.f);
       w.seed_used[s] = 1;
@@ -2428,7 +2429,7 @@ __global__ void k_tc_t5(const Ws *__restrict__ wb) {
   const int wpb = blockDim.x >> 6;
   const int nw = gridDim.x * wpb;
   for (int t = blockIdx.x * wpb + (threadIdx.x >> 6); t < n; t += nw) {
-    const bool cand = w.t5_keep[t] && !w.t5_used[t];
+    const bool cand = gp(w.t5_keep)[t] && !w.t5_used[t];
     const Dir d = dir_of_t5(w, t);
     const bool nr = near_any_wave(d, cand, w.bdir_pt5, w.boff_pt5, kDT5, bin_reach(0.02)) ||
                     near_any_wave(d, cand, w.bdir_pt3, w.boff_pt3, kDT5, bin_reach(0.02));
@@ -2450,7 +2451,7 @@ __global__ void k_tc_pls(const Ws *__restrict__ wb) {
   const int wpb = blockDim.x >> 6;
   const int nw = gridDim.x * wpb;
   for (int s = blockIdx.x * wpb + (threadIdx.x >> 6); s < w.n_seeds; s += nw) {
-    const bool cand = w.pls_keep[s] && !w.seed_used[s];
+    const bool cand = gp(w.pls_keep)[s] && !w.seed_used[s];
     const Dir d = dir_of_seed(w, s);
     const bool nr = near_any_wave(d, cand, w.bdir_pt5, w.boff_pt5, kDpLS, bin_reach(0.05)) ||
                     near_any_wave(d, cand, w.bdir_pt3, w.boff_pt3, kDpLS, bin_reach(0.05)) ||
@@ -2463,12 +2464,12 @@ __global__ void k_tc_pls(const Ws *__restrict__ wb) {
 // curvature with tolerance (the seed's, three resolutions, for pT5 / pT3;
 // the five-anchor fit's and the outer triplet's resolution for a T5).
 __device__ __forceinline__ float2 seed_kappa(const Ws &w, int seed) {
-  const float ks = w.pls[8 * (long)seed + 4];
+  const float ks = gp(w.pls)[8 * (long)seed + 4];
   return make_float2(ks, 3.0f * (kSeedDpt * fabsf(ks)));
 }
 __device__ __forceinline__ void ext_record(const Ws &w, int k, const int *md, int K, float2 kap) {
   for (int i = 0; i < K; ++i) w.tc_md[5 * (long)k + i] = md[i];
-  w.tc_kap[k] = kap;
+  gstore(w.tc_kap, k, kap);
 }
 
 // Output: type, offsets, hit lists (pixel hits first, then MD hits inner to outer).
@@ -2487,9 +2488,9 @@ __global__ void k_tc_write(const Ws *__restrict__ wb) {
   for (int i = tid; i < np5; i += stride) {
     if (!w.f_pt5[i]) continue;
     const int k = w.p_pt5[i];
-    const int2 so = w.pt5_so[i];
+    const int2 so = gload(w.pt5_so, i);
     int *h = w.tc_hits + 14L * k;
-    for (int q = 0; q < 4; ++q) h[q] = w.hits4[4 * (long)so.x + q];
+    for (int q = 0; q < 4; ++q) h[q] = gp(w.hits4)[4 * (long)so.x + q];
     t5_hits(w, so.y, h + 4);
     w.tc_type[k] = 0;
     ext_record(w, k, w.t5_md + 5 * (long)so.y, 5, seed_kappa(w, so.x));
@@ -2498,13 +2499,13 @@ __global__ void k_tc_write(const Ws *__restrict__ wb) {
   for (int i = tid; i < np3; i += stride) {
     if (!w.f_pt3[i]) continue;
     const int k = w.p_pt3[i];
-    const int2 so = w.pt3_so[i];
+    const int2 so = gload(w.pt3_so, i);
     int *h = w.tc_hits + h1 + 10L * k;
-    for (int q = 0; q < 4; ++q) h[q] = w.hits4[4 * (long)so.x + q];
+    for (int q = 0; q < 4; ++q) h[q] = gp(w.hits4)[4 * (long)so.x + q];
     obj_hits<3>(w, so.y, h + 4);
     w.tc_type[n0 + k] = 1;
     {
-      const int4 abc = w.t3_md[so.y];
+      const int4 abc = gload(w.t3_md, so.y);
       const int md[3] = {abc.x, abc.y, abc.z};
       ext_record(w, n0 + k, md, 3, seed_kappa(w, so.x));
     }
@@ -2516,14 +2517,14 @@ __global__ void k_tc_write(const Ws *__restrict__ wb) {
     t5_hits(w, t, w.tc_hits + h2 + 10L * k);
     w.tc_type[n0 + n1 + k] = 2;
     ext_record(w, n0 + n1 + k, w.t5_md + 5 * (long)t, 5,
-               make_float2(w.t5_attr[8 * (long)t], w.t3_attr[w.t5_t3[t].y].y));
+               make_float2(w.t5_attr[8 * (long)t], w.t3_attr[gload(w.t5_t3, t).y].y));
     w.tc_off[n0 + n1 + k] = (int)(h2 + 10L * k);
   }
   for (int s = tid; s < w.n_seeds; s += stride) {
     if (!w.f_pls[s]) continue;
     const int k = w.p_pls[s];
     int *h = w.tc_hits + h3 + 4L * k;
-    for (int q = 0; q < 4; ++q) h[q] = w.hits4[4 * (long)s + q];
+    for (int q = 0; q < 4; ++q) h[q] = gp(w.hits4)[4 * (long)s + q];
     w.tc_type[n0 + n1 + n2 + k] = 3;
     w.tc_off[n0 + n1 + n2 + k] = (int)(h3 + 4L * k);
   }
@@ -2562,20 +2563,20 @@ template <int C>
 __device__ __forceinline__ bool ext_eval(const Ws &w, const DevGeom &g, const float4 (*sP)[C], const int (*sM)[C],
                                          int e, int K, int add, int4 abc, float3 *a, int4 *h) {
   const int nm0 = add == 1 ? abc.z : abc.y;
-  const float4 A0 = w.md_pos[nm0];
-  const int mod0 = w.md_mod[nm0];
-  const int2 h0 = w.md_hits[nm0];
+  const float4 A0 = gload(w.md_pos, nm0);
+  const int mod0 = gp(w.md_mod)[nm0];
+  const int2 h0 = gload(w.md_hits, nm0);
   float4 A1 = A0;
   int mod1 = mod0;
   int2 h1 = make_int2(0, 0);
   if (add == 2) {
-    A1 = w.md_pos[abc.z];
-    mod1 = w.md_mod[abc.z];
-    h1 = w.md_hits[abc.z];
+    A1 = gload(w.md_pos, abc.z);
+    mod1 = gp(w.md_mod)[abc.z];
+    h1 = gload(w.md_hits, abc.z);
   }
   ModInfo I0, I1;
-  I0.bits = g.info[mod0];
-  I1.bits = g.info[mod1];
+  I0.bits = gp(g.info)[mod0];
+  I1.bits = gp(g.info)[mod1];
   float4 P[kExtMax];
   ModInfo M[kExtMax];
 #pragma unroll
@@ -2626,22 +2627,22 @@ __global__ __launch_bounds__(kBlock) void k_tc_ext(const Ws *__restrict__ wb, De
         int md[5];
 #pragma unroll
         for (int i = 0; i < 5; ++i) md[i] = i < K ? w.tc_md[5 * (long)k + i] : 0;
-        const float2 kap = w.tc_kap[k];
+        const float2 kap = gload(w.tc_kap, k);
         s_kt[wv][lane] = kap.x;
         s_dkt[wv][lane] = kap.y;
 #pragma unroll
         for (int i = 0; i < 5; ++i)
           if (i < K) {
             s_P[wv][i][lane] = w.md_pos[md[i]];
-            s_M[wv][i][lane] = g.info[w.md_mod[md[i]]];
+            s_M[wv][i][lane] = gp(g.info)[gp(w.md_mod)[md[i]]];
           }
         // triplets with first MD m: those built from segments with inner MD m
         const int m2 = K == 5 ? md[3] : md[1], m1 = K == 5 ? md[4] : md[2];
         s_md[wv][lane] = m1;
         const int l2b = min(w.ls_off[m2], n_ls), l2e = min(w.ls_off[m2 + 1], n_ls);
         const int l1b = min(w.ls_off[m1], n_ls), l1e = min(w.ls_off[m1 + 1], n_ls);
-        const int lo2 = w.t3_off[l2b], hi2 = min(w.t3_off[l2e], n_t3);
-        const int lo1 = w.t3_off[l1b], hi1 = min(w.t3_off[l1e], n_t3);
+        const int lo2 = gp(w.t3_off)[l2b], hi2 = min(w.t3_off[l2e], n_t3);
+        const int lo1 = gp(w.t3_off)[l1b], hi1 = min(w.t3_off[l1e], n_t3);
         const int n2 = hi2 > lo2 ? hi2 - lo2 : 0, n1 = hi1 > lo1 ? hi1 - lo1 : 0;
         s_lo2[wv][lane] = lo2;
         s_n2[wv][lane] = n2;
@@ -2667,8 +2668,8 @@ __global__ __launch_bounds__(kBlock) void k_tc_ext(const Ws *__restrict__ wb, De
         const int K = s_k[wv][e], n2 = s_n2[wv][e];
         const int ov = idx < n2 ? 2 : 1;
         const int t = ov == 2 ? s_lo2[wv][e] + idx : s_lo1[wv][e] + (idx - n2);
-        const int4 abc = w.t3_md[t];
-        const float4 ta = w.t3_attr[t];
+        const int4 abc = gload(w.t3_md, t);
+        const float4 ta = gload(w.t3_attr, t);
         const int add = 3 - ov;
         const float dk = ta.x - s_kt[wv][e];
         bool ok = ov == 1 || abc.y == s_md[wv][e];
@@ -2711,7 +2712,7 @@ __global__ __launch_bounds__(kBlock) void k_tc_ext(const Ws *__restrict__ wb, De
     if (mine) {
       w.ext_n[k] = best_n;
       w.ext_t3[k] = best_t;
-      w.ext_attr[k] = best_a;
+      gstore(w.ext_attr, k, best_a);
       w.ext_cnt[k] = (w.tc_off[k + 1] - w.tc_off[k]) + 2 * best_n;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -2732,11 +2733,11 @@ __global__ void k_tc_ext_write(const Ws *__restrict__ wb) {
     const int na = w.ext_n[k];
     if (na > 0) {
       const int4 abc = w.t3_md[w.ext_t3[k]];
-      int2 hh = w.md_hits[na == 1 ? abc.z : abc.y];
+      int2 hh = gload(w.md_hits, na == 1 ? abc.z : abc.y);
       dst[0] = hh.x;
       dst[1] = hh.y;
       if (na == 2) {
-        hh = w.md_hits[abc.z];
+        hh = gload(w.md_hits, abc.z);
         dst[2] = hh.x;
         dst[3] = hh.y;
       }
