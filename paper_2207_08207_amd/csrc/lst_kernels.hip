@@ -106,61 +106,65 @@ __global__ void k_scan_reduce(const Ws *__restrict__ wb, int job) {
   const Ws &w = wb[blockIdx.y];
   const ScanJob &J = w.scans[job];
   const int n = dev_count(J.n_dev, J.n_fix);
-  const long base = (long)blockIdx.x * kScanTile;
-  if (base >= n && blockIdx.x > 0) return;
-  int v = 0;
+  // tiles 0 .. n / kScanTile (the last one may be empty), strided over the grid
+  for (long t = blockIdx.x; t * kScanTile <= n; t += gridDim.x) {
+    const long base = t * kScanTile;
+    int v = 0;
 #pragma unroll
-  for (int k = 0; k < kScanItems; ++k) {
-    const long i = base + (long)k * kBlock + threadIdx.x;
-    if (i < n) v += J.in[i];
+    for (int k = 0; k < kScanItems; ++k) {
+      const long i = base + (long)k * kBlock + threadIdx.x;
+      if (i < n) v += J.in[i];
+    }
+    v = block_sum(v, s_red);
+    if (threadIdx.x == 0) w.scan_tmp[t] = v;
   }
-  v = block_sum(v, s_red);
-  if (threadIdx.x == 0) w.scan_tmp[blockIdx.x] = v;
 }
 
-// Each block adds the tile sums of the blocks before it (at most a few hundred
-// for the chain's counts) to its own exclusive scan; the block holding index n
-// writes out[n] and the totals.  (Two launches per scan instead of a third,
-// single-block pass over the tile sums.)
+// Each tile adds the tile sums before it (at most a few hundred for the
+// chain's counts) to its own exclusive scan; the tile holding index n writes
+// out[n] and the totals.  (Two launches per scan instead of a third,
+// single-block pass over the tile sums.)  Both passes stride over the tiles,
+// so the grid need not cover the capacity.
 __global__ void k_scan_apply(const Ws *__restrict__ wb, int job) {
   __shared__ int s_wave[kWaves], s_red[kWaves];
   const Ws &w = wb[blockIdx.y];
   const ScanJob &J = w.scans[job];
   const int n = dev_count(J.n_dev, J.n_fix);
-  const long base = (long)blockIdx.x * kScanTile;
-  if (base > n) return;
-  int pre = 0;
-  for (int j = threadIdx.x; j < (int)blockIdx.x; j += blockDim.x) pre += w.scan_tmp[j];
-  int run = block_sum(pre, s_red);
-  // the block's tile in kScanItems rounds of kBlock consecutive items
-  for (int k = 0; k < kScanItems; ++k) {
-    const long i = base + (long)k * kBlock + threadIdx.x;
-    const int v = (i < n) ? J.in[i] : 0;
-    // inclusive scan within the wave
-    int x = v;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int y = __shfl_up(x, o, 64);
-      if (lane_id() >= o) x += y;
-    }
-    if (lane_id() == 63) s_wave[threadIdx.x >> 6] = x;
-    __syncthreads();
-    int wbs = 0, tot = 0;
+  for (long t = blockIdx.x; t * kScanTile <= n; t += gridDim.x) {
+    const long base = t * kScanTile;
+    int pre = 0;
+    for (int j = threadIdx.x; j < (int)t; j += blockDim.x) pre += w.scan_tmp[j];
+    int run = block_sum(pre, s_red);
+    // the tile in kScanItems rounds of kBlock consecutive items
+    for (int k = 0; k < kScanItems; ++k) {
+      const long i = base + (long)k * kBlock + threadIdx.x;
+      const int v = (i < n) ? J.in[i] : 0;
+      // inclusive scan within the wave
+      int x = v;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane_id() >= o) x += y;
+      }
+      if (lane_id() == 63) s_wave[threadIdx.x >> 6] = x;
+      __syncthreads();
+      int wbs = 0, tot = 0;
 #pragma unroll
-    for (int q = 0; q < kWaves; ++q) {
-      const int c = s_wave[q];
-      wbs += (q < (int)(threadIdx.x >> 6)) ? c : 0;
-      tot += c;
+      for (int q = 0; q < kWaves; ++q) {
+        const int c = s_wave[q];
+        wbs += (q < (int)(threadIdx.x >> 6)) ? c : 0;
+        tot += c;
+      }
+      if (i <= n) J.out[i] = run + wbs + x - v;  // out[n] = total
+      __syncthreads();
+      run += tot;
     }
-    if (i <= n) J.out[i] = run + wbs + x - v;  // out[n] = total
-    __syncthreads();
-    run += tot;
-  }
-  if (base + kScanTile > n && threadIdx.x == 0) {
-    const int tot = run;  // every item of the later tiles is past n
-    if (J.tot_req) *J.tot_req = tot;
-    if (J.tot_clamped) {
-      *J.tot_clamped = tot < J.cap ? tot : J.cap;
-      if (tot > J.cap) atomicOr(w.ctr + C_STATUS, (int)ST_CAPACITY);
+    if (base + kScanTile > n && threadIdx.x == 0) {
+      const int tot = run;  // every item of the later tiles is past n
+      if (J.tot_req) *J.tot_req = tot;
+      if (J.tot_clamped) {
+        *J.tot_clamped = tot < J.cap ? tot : J.cap;
+        if (tot > J.cap) atomicOr(w.ctr + C_STATUS, (int)ST_CAPACITY);
+      }
     }
   }
 }
@@ -177,7 +181,11 @@ static inline int grid_waves(long n, int block = kBlock) {
 }
 
 // Waves per launch that grid-stride kernels share among the launch's events: eight
-// per wave slot of the chip (256 CUs x 32).
+// per wave slot of the chip (256 CUs x 32); the searches whose work is a large
+// fraction of their capacity (segments, triplets, quintuplets and their
+// duplicate removal, MDs) take four times that, since waves with more work
+// left than the others hide each other's latency (measured: two per slot made
+// the segment count 1.24x slower than eight).
 constexpr long kLaunchWaves = 8L * 256 * 32;
 
 static inline int grid_for(long n, int block = kBlock) {
@@ -189,9 +197,10 @@ static inline int grid_for(long n, int block = kBlock) {
 
 // Scan job `job` of every event of the batch; n_cap bounds the item count.
 static void scan(const Ws *wb, int B, int job, long n_cap, hipStream_t st) {
-  // tiles covering n_cap + 1 outputs; capacities are checked on the host so that every scan's
-  // count stays below kMaxScanBlocks tiles, and the grid never exceeds the tile-sum array
-  const int nb = (int)std::min<long>((n_cap + kScanTile) / kScanTile, kMaxScanBlocks);
+  // tiles covering n_cap + 1 outputs (capacities are checked on the host so that every scan's
+  // count stays below kMaxScanBlocks tiles), at most an equal share of kLaunchWaves per event
+  const long share = std::max(64L, kLaunchWaves / B / kWaves);
+  const int nb = (int)std::min<long>(std::min<long>((n_cap + kScanTile) / kScanTile, kMaxScanBlocks), share);
   k_scan_reduce<<<dim3(nb, B), kBlock, 0, st>>>(wb, job);
   k_scan_apply<<<dim3(nb, B), kBlock, 0, st>>>(wb, job);
 }
@@ -2811,9 +2820,13 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   auto share = [&](int blocks, int threads) {
     return (unsigned)std::max(1L, std::min((long)blocks, ev_waves / (threads / 64)));
   };
+  auto share_big = [&](int blocks, int threads) {
+    return (unsigned)std::max(1L, std::min((long)blocks, 4 * ev_waves / (threads / 64)));
+  };
   auto grid = [&](long n) { return dim3(share(grid_for(n), kBlock), B); };
   auto gridt = [&](long n) { return dim3(share(grid_for(n, tb), tb), B); };    // tuned thread-per-item sites
   auto gridwt = [&](long n) { return dim3(share(grid_waves(n, tb), tb), B); }; // tuned wave-per-item sites
+  auto gridwb = [&](long n) { return dim3(share_big(grid_waves(n, tb), tb), B); }; // the heavy searches
   // one wave per seed, every seed its own wave (the seed search does not stride)
   auto seedwaves = [&] { return dim3((unsigned)((S + tb / 64 - 1) / (tb / 64) > 0 ? (S + tb / 64 - 1) / (tb / 64) : 1), B); };
   const dim3 one(1, B);
@@ -2832,17 +2845,17 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   // a1: MD
   run([&] {
     k_md_big<false><<<dim3(share(1024, kBlock), B), kBlock, 0, st>>>(wb, g);
-    k_md<false><<<gridwt(M), tb, 0, st>>>(wb, g);
+    k_md<false><<<gridwb(M), tb, 0, st>>>(wb, g);
   });
   run([&] { scan(wb, B, SC_MD, M, st); });
   run([&] {
     k_md_big<true><<<dim3(share(1024, kBlock), B), kBlock, 0, st>>>(wb, g);
-    k_md<true><<<gridwt(M), tb, 0, st>>>(wb, g);
+    k_md<true><<<gridwb(M), tb, 0, st>>>(wb, g);
   });
   // a2: LS
   run([&] {
     const int lg = ls_group_for(g.tiles, B, b.cap_md);
-    k_ls_count<<<gridwt((b.cap_md + lg - 1) / lg), tb, 0, st>>>(wb, g, lg);
+    k_ls_count<<<gridwb((b.cap_md + lg - 1) / lg), tb, 0, st>>>(wb, g, lg);
   });
   run([&] { scan(wb, B, SC_LS, b.cap_md, st); });
   run([&] {
@@ -2851,13 +2864,13 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
     k_ls_fill<<<gridwt(b.cap_md < 16384 ? b.cap_md : 16384), tb, 0, st>>>(wb, g);  // the overflow MDs
   });
   // a3: T3
-  run([&] { k_t3<false><<<gridwt((b.cap_ls + 63) / 64), tb, 0, st>>>(wb, g); });
+  run([&] { k_t3<false><<<gridwb((b.cap_ls + 63) / 64), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_T3, b.cap_ls, st); });
-  run([&] { k_t3<true><<<gridwt((b.cap_ls + 63) / 64), tb, 0, st>>>(wb, g); });
+  run([&] { k_t3<true><<<gridwb((b.cap_ls + 63) / 64), tb, 0, st>>>(wb, g); });
   // a4: T5
-  run([&] { k_t5<false><<<gridwt((b.cap_t3 + 63) / 64), tb, 0, st>>>(wb, g); });
+  run([&] { k_t5<false><<<gridwb((b.cap_t3 + 63) / 64), tb, 0, st>>>(wb, g); });
   run([&] { scan(wb, B, SC_T5, b.cap_t3, st); });
-  run([&] { k_t5<true><<<gridwt((b.cap_t3 + 63) / 64), tb, 0, st>>>(wb, g); });
+  run([&] { k_t5<true><<<gridwb((b.cap_t3 + 63) / 64), tb, 0, st>>>(wb, g); });
   // a5: T5 duplicate removal through per-MD incidence lists
   run([&] {
     k_clear<<<grid((long)b.cap_md + 1), kBlock, 0, st>>>(wb, FL_INC_CNT, FL_INC_CUR + 1);
@@ -2865,7 +2878,7 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   });
   run([&] { scan(wb, B, SC_INC, b.cap_md, st); });
   run([&] { k_t5_inc_scatter<<<grid(b.cap_t5), kBlock, 0, st>>>(wb); });
-  run([&] { k_t5_dedup<<<gridwt((4L * b.cap_t5 + 63) / 64), tb, 0, st>>>(wb); });
+  run([&] { k_t5_dedup<<<gridwb((4L * b.cap_t5 + 63) / 64), tb, 0, st>>>(wb); });
   // a6: pLS
   run([&] {
     k_clear<<<grid(N + 1), kBlock, 0, st>>>(wb, FL_PH_CNT, FL_PH_CUR + 1);
