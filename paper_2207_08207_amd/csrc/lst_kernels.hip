@@ -320,21 +320,24 @@ __device__ __forceinline__ bool wave_coarse_counts(const Ws &w, int tb, int n_mo
   return any_bad;
 }
 
+// The four waves' rows of coarse counts live in dynamic LDS (kWaves x nc ints,
+// sized at launch from the geometry), so small geometries keep more blocks
+// resident.
 __global__ __launch_bounds__(kBlock) void k_hits_count(const Ws *__restrict__ wb, int n_mod) {
-  __shared__ int s_h[kWaves][kMaxCoarse];
+  extern __shared__ int s_rows[];
   const Ws &w = wb[blockIdx.y];
   const int wv = wave_id();
   const int nc = n_coarse(n_mod), ntb = n_hit_tiles(w.n_hits);
   const int tb = blockIdx.x;
   if (tb < ntb) {
-    for (int c = threadIdx.x; c < kWaves * kMaxCoarse; c += blockDim.x) (&s_h[0][0])[c] = 0;
+    for (int c = threadIdx.x; c < kWaves * nc; c += blockDim.x) s_rows[c] = 0;
     __syncthreads();
-    if (wave_coarse_counts(w, tb, n_mod, s_h[wv])) atomicOr(&w.ctr[C_STATUS], (int)ST_BAD_HIT);
+    if (wave_coarse_counts(w, tb, n_mod, s_rows + wv * nc)) atomicOr(&w.ctr[C_STATUS], (int)ST_BAD_HIT);
     __syncthreads();
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
       int t = 0;
 #pragma unroll
-      for (int q = 0; q < kWaves; ++q) t += s_h[q][c];
+      for (int q = 0; q < kWaves; ++q) t += s_rows[q * nc + c];
       gp(w.tile_hist)[(long)c * ntb + tb] = t;
     }
   }
@@ -357,26 +360,27 @@ __global__ __launch_bounds__(kBlock) void k_hits_count(const Ws *__restrict__ wb
 // coordinates and input index travel with it (one 16-byte store), so the
 // per-bucket sort reads them contiguously.
 __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ wb, int n_mod) {
-  __shared__ int s_h[kWaves][kMaxCoarse];
+  extern __shared__ int s_rows[];  // kWaves x nc, as in k_hits_count
   const Ws &w = wb[blockIdx.y];
   const int wv = wave_id(), lane = lane_id();
   const int nc = n_coarse(n_mod), ntb = n_hit_tiles(w.n_hits);
   const int tb = blockIdx.x;
   if (tb >= ntb) return;  // the whole block
-  for (int c = threadIdx.x; c < kWaves * kMaxCoarse; c += blockDim.x) (&s_h[0][0])[c] = 0;
+  for (int c = threadIdx.x; c < kWaves * nc; c += blockDim.x) s_rows[c] = 0;
   __syncthreads();
-  (void)wave_coarse_counts(w, tb, n_mod, s_h[wv]);
+  (void)wave_coarse_counts(w, tb, n_mod, s_rows + wv * nc);
   __syncthreads();
   for (int c = threadIdx.x; c < nc; c += blockDim.x) {
     int run = gp(w.tile_off)[(long)c * ntb + tb];
 #pragma unroll
     for (int q = 0; q < kWaves; ++q) {
-      const int v = s_h[q][c];
-      s_h[q][c] = run;
+      const int v = s_rows[q * nc + c];
+      s_rows[q * nc + c] = run;
       run += v;
     }
   }
   __syncthreads();
+  int *s_run = s_rows + wv * nc;
   const int nbits = bits_for(nc);
   const int i0 = tb * kHitTile + wv * 1024, i1 = min(w.n_hits, i0 + 1024);
   for (int r0 = i0; r0 < i1; r0 += 64) {
@@ -388,14 +392,14 @@ __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ 
     const unsigned long long peers = match_value(c, nbits, act);
     int base = 0;
     if (act) {
-      base = s_h[wv][c];
+      base = s_run[c];
       const int pos = base + lanes_below(peers);
       gp(w.hkey)[pos] = key;
       gstore(w.hcp, pos, make_float4(w.x[i], gp(w.y)[i], gp(w.z)[i], __int_as_float(i)));
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    if (act && lanes_below(peers) == 0) s_h[wv][c] = base + __popcll(peers);  // the bucket's first lane
+    if (act && lanes_below(peers) == 0) s_run[c] = base + __popcll(peers);  // the bucket's first lane
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
@@ -2837,10 +2841,10 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   const long n_tiles = n_hit_tiles(N), n_co = n_coarse(M);
   run([&] {  // one block per hit tile, and enough threads for the seeds' validation
     const long blocks = std::max(n_tiles, (S + kBlock - 1) / kBlock);
-    k_hits_count<<<dim3((unsigned)std::max(1L, std::min(blocks, 65535L)), B), kBlock, 0, st>>>(wb, M);
+    k_hits_count<<<dim3((unsigned)std::max(1L, std::min(blocks, 65535L)), B), kBlock, kWaves * n_co * sizeof(int), st>>>(wb, M);
   });
   run([&] { scan(wb, B, SC_HITS, n_co * n_tiles, st); });
-  run([&] { k_hits_scatter<<<dim3((unsigned)std::max(1L, n_tiles), B), kBlock, 0, st>>>(wb, M); });
+  run([&] { k_hits_scatter<<<dim3((unsigned)std::max(1L, n_tiles), B), kBlock, kWaves * n_co * sizeof(int), st>>>(wb, M); });
   run([&] { k_bucket_sort<<<dim3((unsigned)n_co, B), 64 * kSortWaves, 0, st>>>(wb, M); });
   // a1: MD
   run([&] {
