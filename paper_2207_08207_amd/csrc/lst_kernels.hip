@@ -931,29 +931,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 }
 
 
-// Count pass of the segment search: one wave per group of kLsGroup
-// consecutive inner MDs.  Each inner MD's candidates go through the pre-tests
-// as in k_ls_fill, but the queue of candidates past them is shared by the
-// group, so the full selection runs on full waves of (inner MD, candidate)
-// pairs rather than on the ~15 a single MD queues.  The pairs of one inner MD
+// Count pass of the segment search: one wave per group of up to kLsGroup
+// consecutive inner MDs, taken in chunks of MDs of one module whose (inner MD,
+// linked module) pairs are flattened over the lanes.  Each candidate goes
+// through the pre-tests as in k_ls_fill, but the queue of candidates past them
+// is shared by the group, so the full selection runs on full waves of (inner
+// MD, candidate) pairs rather than on the ~15 a single MD queues.  The pairs of one inner MD
 // are consecutive in the queue; a passing pair's rank among its MD's passing
 // pairs is the MD's count from earlier flushes plus the passing lanes of its
 // run below it.  Writes each MD's count and caches up to tiles.ls_cache
 // partners in candidate order.  The group size trades the fuller selection
 // waves against the number of waves in flight (tiles.ls_group; see
 // ls_group_for).
+constexpr int kLsPairs = kMaxEdges;  // (inner MD, linked module) pairs of a chunk in LDS
 
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_ls_count(
     const Ws *__restrict__ wb, DevGeom g, int group) {
   const Ws &w = wb[blockIdx.y];
-  // linked modules left with candidates, in map order: first MD, candidates before it,
-  // module info, window bound (bits)
-  __shared__ int4 s_edge[kWaves][kMaxEdges];
-  __shared__ int s_mark[kWaves][64];            // a linked module's candidates start here
+  // (inner MD, linked module) pairs left with candidates, in (MD, map) order: first MD of
+  // the linked module, candidates before it, module info, window bound (bits); and the
+  // pair's inner MD (its slot in the group)
+  __shared__ int4 s_edge[kWaves][kLsPairs];
+  __shared__ int s_ek[kWaves][kLsPairs];
+  __shared__ int s_mark[kWaves][64];            // a pair's candidates start here
   __shared__ int s_q[kWaves][128], s_qi[kWaves][128], s_qg[kWaves][128];  // queued pairs, in order
   __shared__ float4 s_A[kWaves][kLsGroup];      // the group's inner MDs
   __shared__ float2 s_sa[kWaves][kLsGroup];
-  __shared__ int s_mia[kWaves][kLsGroup], s_cnt[kWaves][kLsGroup];
+  __shared__ int s_mia[kWaves][kLsGroup], s_cnt[kWaves][kLsGroup], s_mm[kWaves][kLsGroup];
   const int n_md = uload(w.ctr + C_NMD);
   const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;
@@ -965,9 +969,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     const int na = min(group, n_md - a0);
     if (lane < na) {
       const int a = a0 + lane;
+      const int ma = gp(w.md_mod)[a];
       s_A[wv][lane] = gload(w.md_pos, a);
       s_sa[wv][lane] = get_stub(w, g, a);
-      s_mia[wv][lane] = gp(g.info)[gp(w.md_mod)[a]];
+      s_mia[wv][lane] = gp(g.info)[ma];
+      s_mm[wv][lane] = ma;
       s_cnt[wv][lane] = 0;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1012,36 +1018,48 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       info = gp(g.info)[mb];
       disc = gload(w.mod_disc, mb);
     };
-    for (int k = 0; k < na; ++k) {
-      // the inner MD's data are read from LDS where they are used, after each round's
-      // fence, so that they are not held in registers across the selection
-      const int ma = uload(w.md_mod + a0 + k);
+    // Chunks of consecutive inner MDs of one module, at most kLsPairs / ne of them, so
+    // that every (inner MD, linked module) pair of the chunk fits the LDS list: the
+    // prologue and the candidate rounds run over the chunk's pairs flattened, which
+    // fills the lanes that one MD's ~27 linked modules and ~90 candidates leave idle.
+    for (int k0 = 0; k0 < na;) {
+      const int ma = __builtin_amdgcn_readfirstlane(s_mm[wv][k0]);
       if (ma != cur_ma) {
         cur_ma = ma;
         e0 = uload(g.map_off + ma);
-        ne = uload(g.map_off + ma + 1) - e0;  // <= kMaxEdges, checked when the geometry is loaded
+        ne = uload(g.map_off + ma + 1) - e0;  // <= kMaxEdges = kLsPairs, checked when the geometry is loaded
         if (ne <= 64 && lane < ne) linked(lane, r_first, r_cnt, r_info, r_disc);
       }
+      const int cap_k = ne > 0 ? kLsPairs / ne : na;
+      int k1 = k0 + 1;
+      while (k1 < na && k1 - k0 < cap_k && __builtin_amdgcn_readfirstlane(s_mm[wv][k1]) == ma) ++k1;
+      const int npair = (k1 - k0) * ne;
+      const float rne = ne > 0 ? 1.0f / (float)ne : 0.0f;
       int run = 0, n_ne = 0;
-      for (int k0 = 0; k0 < ne; k0 += 64) {
-        const int kk = k0 + lane;
+      for (int p0 = 0; p0 < npair; p0 += 64) {
+        const int p = p0 + lane;
+        const int2 ke = divmod22(p < npair ? p : 0, ne > 0 ? ne : 1, rne);  // (MD of the chunk, link)
         int first = 0, cnt = 0, info = 0;
+        float4 disc = r_disc;
+        if (ne <= 64) {  // the links' data from the lanes that hold them
+          first = __shfl(r_first, ke.y, 64);
+          cnt = __shfl(r_cnt, ke.y, 64);
+          info = __shfl(r_info, ke.y, 64);
+          disc = make_float4(__shfl(r_disc.x, ke.y, 64), __shfl(r_disc.y, ke.y, 64), __shfl(r_disc.z, ke.y, 64),
+                             __shfl(r_disc.w, ke.y, 64));
+        }
         float wm = 0.0f;
-        const float4 A = s_A[wv][k];
-        const ModInfo mia{s_mia[wv][k]};
-        if (kk < ne) {
-          float4 disc = r_disc;
-          if (ne <= 64) {
-            first = r_first;
-            cnt = r_cnt;
-            info = r_info;
-          } else {
-            linked(kk, first, cnt, info, disc);
-          }
+        const int kk = k0 + ke.x;
+        if (p < npair) {
+          if (ne > 64) linked(ke.y, first, cnt, info, disc);
           if (cnt > 0) {
+            const float4 A = s_A[wv][kk];
+            const ModInfo mia{s_mia[wv][kk]};
             wm = ls_window_bound(A, mia, disc, ModInfo{info}, g.d0max);
             if (!ls_module_may_pass(A, disc, wm)) cnt = 0;
           }
+        } else {
+          cnt = 0;
         }
         int x = cnt;
         for (int o = 1; o < 64; o <<= 1) {
@@ -1049,19 +1067,23 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
           if (lane >= o) x += y;
         }
         const unsigned long long live = __ballot(cnt > 0);
-        if (cnt > 0) s_edge[wv][n_ne + lanes_below(live)] = make_int4(first, run + x - cnt, info, __float_as_int(wm));
+        if (cnt > 0) {
+          const int q = n_ne + lanes_below(live);
+          s_edge[wv][q] = make_int4(first, run + x - cnt, info, __float_as_int(wm));
+          s_ek[wv][q] = kk;
+        }
         n_ne += __popcll(live);
         run += __builtin_amdgcn_readfirstlane(__shfl(x, 63, 64));
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
       const int total = run;
-      // Candidates go 64 per round.  The candidate c of lane L lies in the last module
-      // whose candidates start at or before c: the modules starting before the round
-      // (jlo of them) plus those starting at or below L in it, found by marking the
-      // round's starts (distinct, as every listed module has candidates) and a ballot.
+      // Candidates go 64 per round.  The candidate c of lane L lies in the last pair whose
+      // candidates start at or before c: the pairs starting before the round (jlo of
+      // them) plus those starting at or below L in it, found by marking the round's
+      // starts (distinct, as every listed pair has candidates) and a ballot.
       int jlo = 0;
-      // at least one round, so that the group's last MD flushes the queue
+      // at least one round, so that the group's last chunk flushes the queue
       for (int c0 = 0; c0 < (total > 0 ? total : 1); c0 += 64) {
         s_mark[wv][lane] = 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
@@ -1075,13 +1097,15 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         const unsigned long long starts = __ballot(s_mark[wv][lane] != 0);
         const int c = c0 + lane;
         bool keep_c = false;
-        int b = 0, info = 0;
+        int b = 0, info = 0, kk = 0;
         if (c < total) {
-          const float4 A = s_A[wv][k];
-          const float2 sa = s_sa[wv][k];
-          const ModInfo mia{s_mia[wv][k]};
           const unsigned long long upto = lane == 63 ? ~0ull : ((2ull << lane) - 1ull);
-          const int4 E = s_edge[wv][jlo - 1 + __popcll(starts & upto)];
+          const int j = jlo - 1 + __popcll(starts & upto);
+          const int4 E = s_edge[wv][j];
+          kk = s_ek[wv][j];
+          const float4 A = s_A[wv][kk];
+          const float2 sa = s_sa[wv][kk];
+          const ModInfo mia{s_mia[wv][kk]};
           b = E.x + (c - E.y);
           const float4 Bp = gload(w.md_pos, b);
           info = E.z;
@@ -1094,12 +1118,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
           const int pos = nq + lanes_below(m);
           s_q[wv][pos] = b;
           s_qi[wv][pos] = info;
-          s_qg[wv][pos] = k;
+          s_qg[wv][pos] = kk;
         }
         nq += __popcll(m);
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
-        const bool fin = k == na - 1 && c0 + 64 >= total;
+        const bool fin = k1 == na && c0 + 64 >= total;
         while (nq >= 64 || (fin && nq > 0)) {
           select(nq < 64 ? nq : 64);
           const int rest = nq > 64 ? nq - 64 : 0;  // < 64: move the tail of the queue to its front
@@ -1121,6 +1145,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
           nq = rest;
         }
       }
+      k0 = k1;
     }
     if (lane < na) {
       const int c = s_cnt[wv][lane];
