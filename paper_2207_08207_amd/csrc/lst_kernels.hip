@@ -265,8 +265,8 @@ void launch_tc_export(const Ws *d_ws, int max_tc, int max_hits, int *type, int *
 //  3. k_hits_scatter: each wave walks its quarter of the tile again in input
 //     order, 64 hits at a time, after the waves before it; hits of one coarse
 //     bucket in a round find each other with ballots and take consecutive
-//     positions after the bucket's running position (stable), writing the key
-//     and (x, y, z, input index);
+//     positions after the bucket's running position (stable), writing one
+//     16-byte record (x, y, z, input index and key within the bucket);
 //  4. k_bucket_sort: one block per coarse bucket counts its keys, writes their
 //     offsets and moves every hit (input index; x, y, z, r) to its key's
 //     running position, again 64 hits at a time in order.
@@ -285,6 +285,14 @@ __device__ __forceinline__ int hit_key(const Ws &w, int i, int n_mod, bool *bad)
   *bad = b;
   return key;
 }
+
+// A hit's input index (below 2^23: events hold at most 8,000,000 hits) and its
+// key's position in its coarse bucket, packed into the fourth word of its
+// coarse-order record.
+__device__ __forceinline__ int hit_tag(int i, int key) { return i | ((key & (kFineKeys - 1)) << 23); }
+__device__ __forceinline__ int tag_index(float t) { return __float_as_int(t) & 0x7fffff; }
+__device__ __forceinline__ int tag_fine(float t) { return (int)((unsigned)__float_as_int(t) >> 23); }
+static_assert(kFineBits + 23 <= 32, "index and fine key in one word");
 
 // Lanes (of the active ones) whose `nbits`-bit value v equals this lane's.
 __device__ __forceinline__ unsigned long long match_value(int v, int nbits, bool active) {
@@ -357,8 +365,8 @@ __global__ __launch_bounds__(kBlock) void k_hits_count(const Ws *__restrict__ wb
 // slot in bucket c is the tile's offset (the scan of the tile counts) plus the
 // rows of the waves before it; in each round of 64 hits, a hit's rank among
 // the round's hits of its bucket (match_value) places it.  The hit's
-// coordinates and input index travel with it (one 16-byte store), so the
-// per-bucket sort reads them contiguously.
+// coordinates, input index and key within its bucket travel with it (one
+// 16-byte store), so the per-bucket sort reads them contiguously.
 __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ wb, int n_mod) {
   extern __shared__ int s_rows[];  // kWaves x nc, as in k_hits_count
   const Ws &w = wb[blockIdx.y];
@@ -394,8 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_hits_scatter(const Ws *__restrict__ 
     if (act) {
       base = s_run[c];
       const int pos = base + lanes_below(peers);
-      gp(w.hkey)[pos] = key;
-      gstore(w.hcp, pos, make_float4(w.x[i], gp(w.y)[i], gp(w.z)[i], __int_as_float(i)));
+      gstore(w.hcp, pos, make_float4(gp(w.x)[i], gp(w.y)[i], gp(w.z)[i], __int_as_float(hit_tag(i, key))));
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -425,7 +432,7 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__res
   for (int f = lane; f < kFineKeys; f += 64) s_cnt[wv][f] = 0;
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  for (int j = a + lane; j < b; j += 64) atomicAdd(&s_cnt[wv][gp(w.hkey)[j] & (kFineKeys - 1)], 1);  // LDS
+  for (int j = a + lane; j < b; j += 64) atomicAdd(&s_cnt[wv][tag_fine(gload(w.hcp, j).w)], 1);  // LDS
   __syncthreads();
   // each key's total over the waves, then the keys' first positions (wave 0: one key per lane)
   int tot = 0;
@@ -463,14 +470,14 @@ __global__ __launch_bounds__(64 * kSortWaves) void k_bucket_sort(const Ws *__res
   for (int r0 = a; r0 < b; r0 += 64) {
     const int j = r0 + lane;
     const bool act = j < b;
-    const int f = act ? (w.hkey[j] & (kFineKeys - 1)) : 0;
+    const float4 h = act ? gload(w.hcp, j) : make_float4(0.f, 0.f, 0.f, 0.f);
+    const int f = act ? tag_fine(h.w) : 0;
     const unsigned long long peers = match_value(f, kFineBits, act);
     int base = 0;
     if (act) {
       base = s_cnt[wv][f];
       const int pos = base + lanes_below(peers);
-      const float4 h = gload(w.hcp, j);
-      gp(w.hidx)[pos] = __float_as_int(h.w);
+      gp(w.hidx)[pos] = tag_index(h.w);
       gstore(w.hpos, pos, make_float4(h.x, h.y, h.z, sqrtf(h.x * h.x + h.y * h.y)));
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");

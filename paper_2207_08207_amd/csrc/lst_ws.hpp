@@ -119,8 +119,7 @@ struct Ws {
   // hit buckets by (module, sensor)
   int *boff, *hidx;  // (module, sensor) buckets: offsets (2 n_mod + 1), input index per bucketed hit
   int *tile_hist, *tile_off;  // hits per (coarse bucket, wave tile), coarse-bucket major, and their scan
-  int *hkey;    // hits in coarse-bucket order (stable): bucket key
-  float4 *hcp;  // and x, y, z, input index (bits)
+  float4 *hcp;  // hits in coarse-bucket order (stable): x, y, z, input index | key within the bucket << 23 (bits)
   float4 *hpos;
   // mini-doublets
   int *md_cnt, *md_off;
