@@ -144,7 +144,7 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   t.hcp = F4(N + 1); t.hidx = I(N + 1); t.hpos = F4(N + 1);
   t.md_cnt = I(M + 1); t.md_off = I(M + 1); t.md_cache = I(kMdCache * M); t.md_part = I(4 * M);
   t.md_hits = I2(md); t.md_mod = I(md); t.md_pos = F4(md); t.md_stub = F2(md); t.mod_disc = F4(M);
-  t.ls_cnt = I(md + 1); t.ls_off = I(md + 1); t.ls_md = I2(ls); t.ls_beta = F2(ls);
+  t.ls_cnt = I(md + 1); t.ls_off = I(md + 1); t.ls_md = I2(ls); t.ls_beta = F2(ls); t.ls_opos = F4(ls); t.ls_oinf = I(ls);
   t.ls_cache = I(kLsCache * md);
   t.ls_ovf_flag = I(md + 1); t.ls_ovf_off = I(md + 1); t.ls_ovf = I(md);
   t.t3_cnt = I(ls + 1); t.t3_off = I(ls + 1); t.t3_md = I4(t3); t.t3_attr = F4(t3); t.t3_first = F2(t3);
@@ -298,7 +298,7 @@ lst_status lst_load_geometry(const lst_geometry_desc *d, lst_geometry *out) {
   auto *g = new (std::nothrow) lst_geometry_s();
   if (!g) return fail(LST_E_NOMEM, "host allocation failed");
   std::vector<int> info(M);
-  for (int m = 0; m < M; ++m) info[m] = (d->type[m] & 1) | ((d->subdet[m] & 1) << 1);
+  for (int m = 0; m < M; ++m) info[m] = (d->type[m] & 1) | ((d->subdet[m] & 1) << 1);  // 2 bits (packed with MD indices)
   auto cleanup = [&]() {
     drop(hipFree(g->d_off)); drop(hipFree(g->d_tgt)); drop(hipFree(g->d_info)); drop(hipFree(g->d_win));
     drop(hipFree(g->d_pos)); drop(hipFree(g->d_t5cut));

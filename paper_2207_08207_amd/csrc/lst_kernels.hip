@@ -881,6 +881,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       if (pass && pos < w.cap_ls) {
         gstore(w.ls_md, pos, make_int2(a, b));
         gstore(w.ls_beta, pos, beta);
+        gstore(w.ls_opos, pos, gload(w.md_pos, b));
+        gp(w.ls_oinf)[pos] = s_qi[wv][lane];
       }
       out += __popcll(m);
     };
@@ -1006,7 +1008,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       if (lane < n) before = s_cnt[wv][q];
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      if (pass && before + below < keep) gp(w.ls_cache)[(long)(a0 + q) * kLsCache + before + below] = b;
+      if (pass && before + below < keep)  // the partner and its module's info word (2 bits) in one int
+        gp(w.ls_cache)[(long)(a0 + q) * kLsCache + before + below] = b | (s_qi[wv][lane] << 30);
       if (lane < n && (lane == n - 1 || qn != q)) s_cnt[wv][q] = before + below + (pass ? 1 : 0);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -1235,9 +1238,13 @@ __global__ void k_ls_copy(const Ws *__restrict__ wb, int keep) {
     for (int k = k0; k < cnt; k += kLsCopyLanes) {
       const int pos = gp(w.ls_off)[a] + k;
       if (pos >= w.cap_ls) break;
-      const int b = gp(w.ls_cache)[(long)a * kLsCache + k];
+      const int e = gp(w.ls_cache)[(long)a * kLsCache + k];
+      const int b = e & 0x3fffffff;
+      const float4 B = gload(w.md_pos, b);
       gstore(w.ls_md, pos, make_int2(a, b));
-      gstore(w.ls_beta, pos, ls_beta(gload(w.md_pos, a), gload(w.md_pos, b)));
+      gstore(w.ls_beta, pos, ls_beta(gload(w.md_pos, a), B));
+      gstore(w.ls_opos, pos, B);
+      gp(w.ls_oinf)[pos] = (int)((unsigned)e >> 30);
     }
   }
 }
@@ -1300,8 +1307,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
     if (l1 < n_ls && (!FILL || gp(w.t3_cnt)[l1] > 0)) {
       const int2 ab = gload(w.ls_md, l1);
       s_a[wv][lane] = gload(w.md_pos, ab.x);
-      s_b[wv][lane] = gload(w.md_pos, ab.y);
-      s_mi[wv][lane] = gp(g.info)[gp(w.md_mod)[ab.x]] | (gp(g.info)[gp(w.md_mod)[ab.y]] << 8);
+      s_b[wv][lane] = gload(w.ls_opos, l1);
+      s_mi[wv][lane] = gp(g.info)[gp(w.md_mod)[ab.x]] | (gp(w.ls_oinf)[l1] << 8);
       const int lo = gp(w.ls_off)[ab.y], hi = min(gp(w.ls_off)[ab.y + 1], n_ls);
       s_lo[wv][lane] = lo;
       n = hi > lo ? hi - lo : 0;
@@ -1325,10 +1332,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
       if (lane < nb) {
         e = s_qe[wv][lane];
         cand = s_qc[wv][lane];
-        cmd = gload(w.ls_md, cand).y;
+        if (FILL) cmd = gload(w.ls_md, cand).y;
         const int mi = s_mi[wv][e];
-        pass = t3_pass(s_a[wv][e], s_b[wv][e], gload(w.md_pos, cmd), ModInfo{mi & 0xff}, ModInfo{mi >> 8},
-                       ModInfo{gp(g.info)[gp(w.md_mod)[cmd]]}, &attr, g.d0max);
+        pass = t3_pass(s_a[wv][e], s_b[wv][e], gload(w.ls_opos, cand), ModInfo{mi & 0xff}, ModInfo{mi >> 8},
+                       ModInfo{gp(w.ls_oinf)[cand]}, &attr, g.d0max);
       }
       const int first = run_first_lane(e, nb);
       const unsigned long long m = __ballot(pass);
@@ -1363,10 +1370,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(7))) voi
       if (c < total) {
         const int idx = c - s_seg[wv][e];
         cand = s_cached[wv][e] ? gp(w.t3_cache)[(long)((int)p0 + e) * kT3Cache + idx] : s_lo[wv][e] + idx;
-        const int cmd = gload(w.ls_md, cand).y;
         const int mi = s_mi[wv][e];
-        keep = t3_may_pass(s_a[wv][e], s_b[wv][e], gload(w.md_pos, cmd), ModInfo{mi & 0xff}, ModInfo{mi >> 8},
-                           ModInfo{gp(g.info)[gp(w.md_mod)[cmd]]}, g.d0max);
+        keep = t3_may_pass(s_a[wv][e], s_b[wv][e], gload(w.ls_opos, cand), ModInfo{mi & 0xff}, ModInfo{mi >> 8},
+                           ModInfo{gp(w.ls_oinf)[cand]}, g.d0max);
       }
       const unsigned long long m = __ballot(keep);
       if (keep) {

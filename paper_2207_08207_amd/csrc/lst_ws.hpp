@@ -132,10 +132,12 @@ struct Ws {
   float4 *mod_disc;  // per module with MDs: x-y disc (cx, cy, radius, |c|) around its anchors
   // segments
   int *ls_cnt, *ls_off;
-  int *ls_cache;    // per MD: up to 16 passing partners found by the count pass
+  int *ls_cache;    // per MD: up to kLsCache passing partners found by the count pass (| info << 30)
   int *ls_ovf_flag, *ls_ovf_off, *ls_ovf;  // MDs with more: flag, its scan, the dense list
   int2 *ls_md;
   float2 *ls_beta;
+  float4 *ls_opos;  // the outer MD's anchor (a copy, read by the triplet search)
+  int *ls_oinf;      // and its module's info word
   // triplets
   int *t3_cnt, *t3_off;
   int4 *t3_md;      // a, b, c, -
