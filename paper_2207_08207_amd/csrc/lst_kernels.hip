@@ -1619,13 +1619,21 @@ __device__ __forceinline__ bool better(float su, const int *hu, float st, const 
 // their MDs in LDS and strides all (item, candidate) pairs with its lanes.
 // t5_keep starts at 1 (written by the fill); a strictly better duplicate
 // clears it (every writer writes 0).
+// Its LDS is dynamic, kT5DedupLds bytes per wave of the block, so that a tuned
+// launch of one-wave blocks does not hold four waves' worth.
+struct T5DedupLds {
+  int mt[5][64], lo[64], seg[65], mark[64];
+  float st[64];
+};
+constexpr size_t kT5DedupLds = sizeof(T5DedupLds);
+
 __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) {
+  extern __shared__ T5DedupLds s_dd[];
   const Ws &w = wb[blockIdx.y];
-  __shared__ int s_mt[kWaves][5][64], s_lo[kWaves][64], s_seg[kWaves][65], s_mark[kWaves][64];
-  __shared__ float s_st[kWaves][64];
   const int n = uload(w.ctr + C_NT5);
   const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;
+  auto &S = s_dd[wv];
   for (long p0 = ((long)blockIdx.x * wpb + wv) * 64; p0 < 4L * n; p0 += (long)gridDim.x * wpb * 64) {
     const long item = p0 + lane;
     int cnt = 0;
@@ -1635,28 +1643,28 @@ __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) 
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
         mt[j] = gp(w.t5_md)[5 * (long)t + j];
-        s_mt[wv][j][lane] = mt[j];
+        S.mt[j][lane] = mt[j];
       }
       if (k == 0) gstore(w.t5_first, t, make_float2(w.md_pos[mt[0]].x, w.md_pos[mt[0]].y));
       const int lo = gp(w.inc_off)[mt[k]];
-      s_lo[wv][lane] = lo;
+      S.lo[lane] = lo;
       cnt = gp(w.inc_off)[mt[k] + 1] - lo;
-      s_st[wv][lane] = gp(w.t5_attr)[8 * (long)t + 1];
+      S.st[lane] = gp(w.t5_attr)[8 * (long)t + 1];
     }
-    const int total = wave_segments(cnt, s_seg[wv]);
-    const int start = s_seg[wv][lane];
+    const int total = wave_segments(cnt, S.seg);
+    const int start = S.seg[lane];
     int carry = 0;
     for (int c0 = 0; c0 < total; c0 += 64) {
       const int c = c0 + lane;
-      const int e = round_parent(start, cnt, c0, s_mark[wv], carry);  // item of this lane's pair
+      const int e = round_parent(start, cnt, c0, S.mark, carry);  // item of this lane's pair
       if (c >= total) continue;
       const int t = (int)((p0 + e) >> 2), k = (int)((p0 + e) & 3);
-      const int2 ue = w.inc_list[s_lo[wv][e] + (c - s_seg[wv][e])];
+      const int2 ue = w.inc_list[S.lo[e] + (c - S.seg[e])];
       const int u = ue.x;
       if (u == t) continue;
       // only a u that is not worse can drop t: the score first (kept in the list entry),
       // then sharing, then on a tie of scores the hit tuples (the decision of better<10>)
-      const float su = __int_as_float(ue.y), st = s_st[wv][e];
+      const float su = __int_as_float(ue.y), st = S.st[e];
       if (st < su) continue;
       int mu[5];
 #pragma unroll
@@ -1664,7 +1672,7 @@ __global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) 
       int shared = 0, first = 5;
 #pragma unroll
       for (int j = 0; j < 5; ++j) {
-        const int v = s_mt[wv][j][e];
+        const int v = S.mt[j][e];
         const bool in = v == mu[0] || v == mu[1] || v == mu[2] || v == mu[3] || v == mu[4];
         shared += in ? 1 : 0;
         first = (in && first == 5) ? j : first;
@@ -2920,7 +2928,7 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   });
   run([&] { scan(wb, B, SC_INC, b.cap_md, st); });
   run([&] { k_t5_inc_scatter<<<grid(b.cap_t5), kBlock, 0, st>>>(wb); });
-  run([&] { k_t5_dedup<<<gridwb((4L * b.cap_t5 + 63) / 64), tb, 0, st>>>(wb); });
+  run([&] { k_t5_dedup<<<gridwb((4L * b.cap_t5 + 63) / 64), tb, (tb / 64) * kT5DedupLds, st>>>(wb); });
   // a6: pLS
   run([&] {
     k_clear<<<grid(N + 1), kBlock, 0, st>>>(wb, FL_PH_CNT, FL_PH_CUR + 1);
