@@ -761,14 +761,35 @@ __device__ __forceinline__ bool ls_module_may_pass(const float4 &A, float4 disc,
   return dn - disc.z <= (wmax * (disc.w + disc.z)) * 1.001f + 1e-4f;
 }
 
-// The inner MD's stub check of ls_pass (ls_stub_ok with its chord quantities),
-// evaluated with the fast operations: every quantity is within 2e-6 relative
-// of the exact one (a chain of at most six operations of <= 2 ulp), except
-// that 1 - s^2 loses relative precision as s^2 -> 1: chords within
-// asin(sqrt(0.9)) of the tangent skip the pre-test (the exact test decides),
-// which bounds the error of the predicted displacement at 4e-5 relative.  The
-// margins (1e-4 of the prediction and of the error) exceed those bounds, so
-// whatever passes the exact check passes this one.
+// One MD's stub check of ls_pass (ls_stub_ok) evaluated with the fast
+// operations, from the chord (sx, sy) = B - A, its inverse length il, dz = zB -
+// zA, the chord's sine sn against the radial direction the check uses, eang
+// and the MD's radius rp: every quantity is within 2e-6 relative of the exact
+// one (a chain of at most six operations of <= 2 ulp), except that 1 - s^2
+// loses relative precision as s^2 -> 1: chords within asin(sqrt(0.9)) of the
+// tangent skip the pre-test (the exact test decides), which bounds the error of
+// the predicted displacement at 4e-5 relative.  The margins (1e-4 of the
+// prediction and of the error) exceed those bounds, so whatever passes the
+// exact check passes this one.
+__device__ __forceinline__ bool ls_stub_may_pass(float2 st, ModInfo m, float sn, float sx, float sy, float il, float dz,
+                                                 float eang, float rp, float d0) {
+  float pred, err;
+  if (!m.endcap()) {
+    const float sn2 = sn * sn;
+    if (!(sn2 < 0.9f)) return true;
+    pred = (st.y * sn) * frsq(1.0f - sn2);
+    err = 2.0f * m.hphi() + (2.0f * st.y) * (eang + d0 * frcp(rp));
+  } else {
+    const float adz = fabsf(dz);
+    if (!(adz > 0.0f)) return false;  // the exact check's own rejection, on the same operands
+    const float ds = st.y * (sx * sx + sy * sy) * il * frcp(adz);
+    pred = ds * sn;
+    err = (2.0f * m.hphi() + (float)0.03 * fabsf(pred)) + ds * (eang + d0 * frcp(rp));
+  }
+  return fabsf(st.x - pred) <= (err * kMargin) * 1.0001f + kEps + 1e-4f * fabsf(pred);
+}
+
+// The inner MD's stub check (its chord sine taken at the outer anchor B).
 __device__ __forceinline__ bool ls_inner_stub_may_pass(const float4 &A, const float4 &B, float2 st, ModInfo ma,
                                                        ModInfo mb, float d0) {
   const float sx = B.x - A.x, sy = B.y - A.y;
@@ -776,26 +797,40 @@ __device__ __forceinline__ bool ls_inner_stub_may_pass(const float4 &A, const fl
   const float sn = (B.x * sy - B.y * sx) * frcp(B.w) * il;
   const float ea2 = ma.endcap() ? ma.hlong() : ma.hphi();
   const float eb2 = mb.endcap() ? mb.hlong() : mb.hphi();
-  const float eang = (ea2 + eb2) * il;
-  float pred, err;
-  if (!ma.endcap()) {
-    const float sn2 = sn * sn;
-    if (!(sn2 < 0.9f)) return true;
-    pred = (st.y * sn) * frsq(1.0f - sn2);
-    err = 2.0f * ma.hphi() + (2.0f * st.y) * (eang + d0 * frcp(A.w));
-  } else {
-    const float adz = fabsf(B.z - A.z);
-    if (!(adz > 0.0f)) return false;  // the exact check's own rejection, on the same operands
-    const float ds = st.y * (sx * sx + sy * sy) * il * frcp(adz);
-    pred = ds * sn;
-    err = (2.0f * ma.hphi() + (float)0.03 * fabsf(pred)) + ds * (eang + d0 * frcp(A.w));
-  }
-  return fabsf(st.x - pred) <= (err * kMargin) * 1.0001f + kEps + 1e-4f * fabsf(pred);
+  return ls_stub_may_pass(st, ma, sn, sx, sy, il, B.z - A.z, (ea2 + eb2) * il, A.w, d0);
 }
 
 __device__ __forceinline__ bool ls_window_may_pass(const float4 &A, const float4 &B, float wmax) {
   const float c = A.x * B.y - A.y * B.x;
   return fabsf(c) <= wmax * (A.w * B.w);
+}
+
+// The checks of ls_pass that a pair past the two pre-tests above still fails
+// most often, on the pair itself: the signs of dr and of A.B (the same
+// operations as ls_pass), the x-y window with the outer radius of this B
+// instead of the module's (all terms of w are positive for dr > 0, so the fast
+// operations' few-ulp errors stay far inside the 1e-4 margin; ub >= 0.99
+// leaves the decision to the exact test), and the outer MD's stub check, its
+// chord sine taken at the inner anchor A.
+__device__ __forceinline__ bool ls_pair_may_pass(const float4 &A, const float4 &B, float2 sb, ModInfo ma, ModInfo mb,
+                                                 float d0) {
+  const float dr = B.w - A.w;
+  if (!(dr > 0.0f)) return false;
+  if (!(A.x * B.x + A.y * B.y > 0.0f)) return false;
+  const float ub = kHalfKmax * (B.w + mb.er());
+  if (ub < 0.99f) {
+    const float ua = kHalfKmax * (A.w - ma.er());
+    const float ra = frcp(A.w), rb = frcp(B.w);
+    const float wv = (ub - ua) * frsq(1.0f - ub * ub) + (d0 * dr) * (ra * rb) + ma.hphi() * ra + mb.hphi() * rb;
+    const float c = A.x * B.y - A.y * B.x;
+    if (!(fabsf(c) <= ((wv * kMargin + kEps) * (A.w * B.w)) * 1.0001f + 1e-6f)) return false;
+  }
+  const float sx = B.x - A.x, sy = B.y - A.y;
+  const float il = frsq(sx * sx + sy * sy);
+  const float sn = (A.x * sy - A.y * sx) * frcp(A.w) * il;
+  const float ea2 = ma.endcap() ? ma.hlong() : ma.hphi();
+  const float eb2 = mb.endcap() ? mb.hlong() : mb.hphi();
+  return ls_stub_may_pass(sb, mb, sn, sx, sy, il, B.z - A.z, (ea2 + eb2) * il, B.w, d0);
 }
 
 constexpr int kMaxEdges = 128;  // module-map targets per module (checked when the geometry is loaded)
@@ -944,15 +979,38 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 // consecutive inner MDs, taken in chunks of MDs of one module whose (inner MD,
 // linked module) pairs are flattened over the lanes.  Each candidate goes
 // through the pre-tests as in k_ls_fill, but the queue of candidates past them
-// is shared by the group, so the full selection runs on full waves of (inner
-// MD, candidate) pairs rather than on the ~15 a single MD queues.  The pairs of one inner MD
-// are consecutive in the queue; a passing pair's rank among its MD's passing
-// pairs is the MD's count from earlier flushes plus the passing lanes of its
-// run below it.  Writes each MD's count and caches up to tiles.ls_cache
+// is shared by the group.  Full waves of queued pairs then go through a second,
+// pair-level pre-test (ls_pair_may_pass: about a third of them pass on PU200
+// events), and its survivors, queued the same way, through the full selection,
+// which thus runs on full waves of likely pairs rather than on the ~15 a single
+// MD queues.  The pairs of one inner MD are consecutive in both queues; a
+// passing pair's rank among its MD's passing pairs is the MD's count from
+// earlier flushes plus the passing lanes of its run below it.  Writes each MD's count and caches up to tiles.ls_cache
 // partners in candidate order.  The group size trades the fuller selection
 // waves against the number of waves in flight (tiles.ls_group; see
 // ls_group_for).
 constexpr int kLsPairs = kMaxEdges;  // (inner MD, linked module) pairs of a chunk in LDS
+
+// Drops the first 64 entries of a wave's queue (two arrays of 128): the rest (< 64)
+// entries behind them move to its front.
+template <class T>
+__device__ __forceinline__ void queue_pop64(int *qa, T *qb, int rest) {
+  const int lane = lane_id();
+  int va = 0;
+  T vb = 0;
+  if (lane < rest) {
+    va = qa[64 + lane];
+    vb = qb[64 + lane];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane < rest) {
+    qa[lane] = va;
+    qb[lane] = vb;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
 
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_ls_count(
     const Ws *__restrict__ wb, DevGeom g, int group) {
@@ -963,7 +1021,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
   __shared__ int4 s_edge[kWaves][kLsPairs];
   __shared__ int s_ek[kWaves][kLsPairs];
   __shared__ int s_mark[kWaves][64];            // a pair's candidates start here
-  __shared__ int s_q[kWaves][128], s_qi[kWaves][128], s_qg[kWaves][128];  // queued pairs, in order
+  // (inner MD, candidate) pairs in order, as partner | module info << 30 and the inner
+  // MD's slot in the group: past the candidate pre-tests (s_q) and past the pair
+  // pre-test as well (s_r)
+  __shared__ int s_q[kWaves][128], s_r[kWaves][128];
+  __shared__ unsigned char s_qg[kWaves][128], s_rg[kWaves][128];
   __shared__ float4 s_A[kWaves][kLsGroup];      // the group's inner MDs
   __shared__ float2 s_sa[kWaves][kLsGroup];
   __shared__ int s_mia[kWaves][kLsGroup], s_cnt[kWaves][kLsGroup], s_mm[kWaves][kLsGroup];
@@ -987,16 +1049,39 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    // the full selection on the first n queued pairs (n <= 64)
+    // the pair pre-test on the first n pairs of s_q (n <= 64); the passing ones join s_r
+    int nr = 0;
+    auto sift = [&](int n) {
+      bool ok = false;
+      int e = 0, q = 0;
+      if (lane < n) {
+        e = s_q[wv][lane];
+        q = s_qg[wv][lane];
+        const int b = e & 0x3fffffff;
+        ok = ls_pair_may_pass(s_A[wv][q], gload(w.md_pos, b), get_stub(w, g, b), ModInfo{s_mia[wv][q]},
+                              ModInfo{(int)((unsigned)e >> 30)}, g.d0max);
+      }
+      const unsigned long long m = __ballot(ok);
+      if (ok) {
+        const int pos = nr + lanes_below(m);
+        s_r[wv][pos] = e;
+        s_rg[wv][pos] = (unsigned char)q;
+      }
+      nr += __popcll(m);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    };
+    // the full selection on the first n pairs of s_r (n <= 64)
     auto select = [&](int n) {
       bool pass = false;
-      int b = 0, q = -1;
+      int e = 0, q = -1;
       if (lane < n) {
-        b = s_q[wv][lane];
-        q = s_qg[wv][lane];
+        e = s_r[wv][lane];
+        q = s_rg[wv][lane];
+        const int b = e & 0x3fffffff;
         float2 beta;
         pass = ls_pass(s_A[wv][q], gload(w.md_pos, b), s_sa[wv][q], get_stub(w, g, b), ModInfo{s_mia[wv][q]},
-                       ModInfo{s_qi[wv][lane]}, &beta, g.d0max);
+                       ModInfo{(int)((unsigned)e >> 30)}, &beta, g.d0max);
       }
       const unsigned long long m = __ballot(pass);
       const int qp = __shfl_up(q, 1, 64), qn = __shfl_down(q, 1, 64);
@@ -1009,7 +1094,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
       if (pass && before + below < keep)  // the partner and its module's info word (2 bits) in one int
-        gp(w.ls_cache)[(long)(a0 + q) * kLsCache + before + below] = b | (s_qi[wv][lane] << 30);
+        gp(w.ls_cache)[(long)(a0 + q) * kLsCache + before + below] = e;
       if (lane < n && (lane == n - 1 || qn != q)) s_cnt[wv][q] = before + below + (pass ? 1 : 0);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -1126,33 +1211,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         const unsigned long long m = __ballot(keep_c);
         if (keep_c) {
           const int pos = nq + lanes_below(m);
-          s_q[wv][pos] = b;
-          s_qi[wv][pos] = info;
-          s_qg[wv][pos] = kk;
+          s_q[wv][pos] = b | (info << 30);
+          s_qg[wv][pos] = (unsigned char)kk;
         }
         nq += __popcll(m);
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
+        // each queue holds < 64 entries before a round adds at most 64, and is drained
+        // 64 at a time; the group's last round drains both completely
         const bool fin = k1 == na && c0 + 64 >= total;
         while (nq >= 64 || (fin && nq > 0)) {
-          select(nq < 64 ? nq : 64);
-          const int rest = nq > 64 ? nq - 64 : 0;  // < 64: move the tail of the queue to its front
-          int vb = 0, vi = 0, vg = 0;
-          if (lane < rest) {
-            vb = s_q[wv][64 + lane];
-            vi = s_qi[wv][64 + lane];
-            vg = s_qg[wv][64 + lane];
+          const int n1 = nq < 64 ? nq : 64;
+          sift(n1);
+          queue_pop64(s_q[wv], s_qg[wv], nq - n1);
+          nq -= n1;
+          while (nr >= 64) {
+            select(64);
+            queue_pop64(s_r[wv], s_rg[wv], nr - 64);
+            nr -= 64;
           }
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          if (lane < rest) {
-            s_q[wv][lane] = vb;
-            s_qi[wv][lane] = vi;
-            s_qg[wv][lane] = vg;
-          }
-          __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-          __builtin_amdgcn_wave_barrier();
-          nq = rest;
+        }
+        if (fin && nr > 0) {
+          select(nr);
+          nr = 0;
         }
       }
       k0 = k1;
