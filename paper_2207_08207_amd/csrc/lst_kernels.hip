@@ -835,14 +835,46 @@ __device__ __forceinline__ bool ls_pair_may_pass(const float4 &A, const float4 &
 
 constexpr int kMaxEdges = 128;  // module-map targets per module (checked when the geometry is loaded)
 
+// Drops the first 64 entries of a wave's queue (two arrays of 128): the rest (< 64)
+// entries behind them move to its front.
+template <class T>
+__device__ __forceinline__ void queue_pop64(int *qa, T *qb, int rest) {
+  const int lane = lane_id();
+  int va = 0;
+  T vb = 0;
+  if (lane < rest) {
+    va = qa[64 + lane];
+    vb = qb[64 + lane];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane < rest) {
+    qa[lane] = va;
+    qb[lane] = vb;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void queue_pop64(int *qa, int rest) {
+  const int lane = lane_id();
+  const int va = lane < rest ? qa[64 + lane] : 0;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  if (lane < rest) qa[lane] = va;
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Fill pass of the segment search for the inner MDs with more segments than
 // the count pass cached (k_ls_copy writes the others and lists these densely):
 // one wave per inner MD a.  Its candidates -- the MDs of every module linked
 // to a's module, edge by edge -- are flattened into one list that the 64
 // lanes stride over, so a wave stays full even though each linked module
-// holds few MDs; passing candidates are compacted in list order with ballot
-// and mbcnt.
-// Eight waves per SIMD (64 VGPRs; two spill): the segment search is bound by
+// holds few MDs; candidates past the pre-tests, then past the pair pre-test,
+// are compacted in list order with ballot and mbcnt into two LDS queues, and
+// the full selection runs on full waves of the second.
+// Eight waves per SIMD (64 VGPRs; a few spill): the segment search is bound by
 // the latency of its dependent gathers, and more resident waves hide more of
 // it (measured 9% faster than the 77-VGPR, six-wave build; the same for the
 // triplet and quintuplet searches made them slower).
@@ -853,7 +885,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
   __shared__ int s_first[kWaves][kMaxEdges];    // first MD of each linked module
   __shared__ int s_info[kWaves][kMaxEdges];
   __shared__ float s_wmax[kWaves][kMaxEdges];   // window bound of each linked module
-  __shared__ int s_q[kWaves][128], s_qi[kWaves][128];  // candidates past the pre-tests, in order
+  // candidates in order, as partner | module info << 30: past the candidate pre-tests
+  // (s_q) and past the pair pre-test as well (s_r)
+  __shared__ int s_q[kWaves][128], s_r[kWaves][128];
   const int n_md = uload(w.ctr + C_NMD);
   const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;  // waves per block (a tuned launch may run fewer than kWaves)
@@ -901,14 +935,33 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
     __builtin_amdgcn_wave_barrier();
     const int total = run;
     int out = gp(w.ls_off)[a];
-    // the full selection on the first n queued candidates (n <= 64), in candidate order
+    // the pair pre-test on the first n candidates of s_q (n <= 64); the passing ones join s_r
+    int nr = 0;
+    auto sift = [&](int n) {
+      bool ok = false;
+      int e = 0;
+      if (lane < n) {
+        e = s_q[wv][lane];
+        const int b = e & 0x3fffffff;
+        ok = ls_pair_may_pass(A, gload(w.md_pos, b), get_stub(w, g, b), mia, ModInfo{(int)((unsigned)e >> 30)},
+                              g.d0max);
+      }
+      const unsigned long long m = __ballot(ok);
+      if (ok) s_r[wv][nr + lanes_below(m)] = e;
+      nr += __popcll(m);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    };
+    // the full selection on the first n candidates of s_r (n <= 64), in candidate order
     auto select = [&](int n) {
       bool pass = false;
-      int b = 0;
+      int b = 0, info = 0;
       float2 beta = make_float2(0.f, 0.f);
       if (lane < n) {
-        b = s_q[wv][lane];
-        pass = ls_pass(A, gload(w.md_pos, b), sa, get_stub(w, g, b), mia, ModInfo{s_qi[wv][lane]}, &beta, g.d0max);
+        const int e = s_r[wv][lane];
+        b = e & 0x3fffffff;
+        info = (int)((unsigned)e >> 30);
+        pass = ls_pass(A, gload(w.md_pos, b), sa, get_stub(w, g, b), mia, ModInfo{info}, &beta, g.d0max);
       }
       const unsigned long long m = __ballot(pass);
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
@@ -917,9 +970,11 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
         gstore(w.ls_md, pos, make_int2(a, b));
         gstore(w.ls_beta, pos, beta);
         gstore(w.ls_opos, pos, gload(w.md_pos, b));
-        gp(w.ls_oinf)[pos] = s_qi[wv][lane];
+        gp(w.ls_oinf)[pos] = info;
       }
       out += __popcll(m);
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     };
     // candidates past the azimuth pre-tests and the inner MD's own stub check (both
     // necessary conditions of ls_pass) are queued in LDS, and the full selection runs
@@ -940,35 +995,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
       }
       const unsigned long long m = __ballot(keep);
       const int pre = __builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
-      if (keep) {
-        s_q[wv][nq + pre] = b;
-        s_qi[wv][nq + pre] = info;
-      }
+      if (keep) s_q[wv][nq + pre] = b | (info << 30);
       nq += __popcll(m);
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
+      // each queue holds < 64 entries before a round adds at most 64
       if (nq >= 64) {
-        select(64);
-        const int rest = nq - 64;  // < 64: move the tail of the queue to its front
-        int vb = 0, vi = 0;
-        if (lane < rest) {
-          vb = s_q[wv][64 + lane];
-          vi = s_qi[wv][64 + lane];
+        sift(64);
+        queue_pop64(s_q[wv], nq - 64);
+        nq -= 64;
+        if (nr >= 64) {
+          select(64);
+          queue_pop64(s_r[wv], nr - 64);
+          nr -= 64;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (lane < rest) {
-          s_q[wv][lane] = vb;
-          s_qi[wv][lane] = vi;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        nq = rest;
       }
     }
-    if (nq > 0) select(nq);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    if (nq > 0) sift(nq);
+    while (nr > 0) {
+      const int n2 = nr < 64 ? nr : 64;
+      select(n2);
+      queue_pop64(s_r[wv], nr - n2);
+      nr -= n2;
+    }
   };
   const int n_ovf = uload(w.ctr + C_NLSOVF);
   for (int k = blockIdx.x * wpb + wv; k < n_ovf; k += waves_total) process(w.ls_ovf[k]);
@@ -990,27 +1039,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) voi
 // waves against the number of waves in flight (tiles.ls_group; see
 // ls_group_for).
 constexpr int kLsPairs = kMaxEdges;  // (inner MD, linked module) pairs of a chunk in LDS
-
-// Drops the first 64 entries of a wave's queue (two arrays of 128): the rest (< 64)
-// entries behind them move to its front.
-template <class T>
-__device__ __forceinline__ void queue_pop64(int *qa, T *qb, int rest) {
-  const int lane = lane_id();
-  int va = 0;
-  T vb = 0;
-  if (lane < rest) {
-    va = qa[64 + lane];
-    vb = qb[64 + lane];
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  if (lane < rest) {
-    qa[lane] = va;
-    qb[lane] = vb;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
 
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_ls_count(
     const Ws *__restrict__ wb, DevGeom g, int group) {

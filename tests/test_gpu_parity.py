@@ -70,6 +70,25 @@ def test_parity_tiny_seeded_ragged(seed, lst, gbarrel, obarrel, barrel):
     assert compare_tc(r, o) > 0
 
 
+def test_parity_unsorted_module_map(lst, full):
+    """A module map whose targets are not in increasing module order (each module's list
+    reversed): the segment search finds partners linked module by linked module and must
+    still report them in map order, as the oracle does."""
+    import copy
+    geom = copy.copy(full)
+    mo, mt = full.map_offsets, full.map_targets.copy()
+    for m in range(full.n_modules):
+        mt[mo[m]:mo[m + 1]] = mt[mo[m]:mo[m + 1]][::-1].copy()
+    geom.map_targets = mt
+    assert any(mo[m + 1] - mo[m] > 1 for m in range(full.n_modules))
+    ev = make_event("pu200_seeded", 2)
+    r = _run(lst, lst.Geometry(geom), ev)
+    o = oracle.run(oracle.OracleGeometry(geom), ev)
+    stats = compare_event(r, o, stages=range(3))
+    assert stats["LS"]["oracle"] > 100000
+    compare_tc(r, o)
+
+
 def test_parity_pu200_seeded_full_event(lst, gfull, ofull):
     """The full-size PU200-like event with pixel seeds, all stages, every object."""
     ev = make_event("pu200_seeded", 0)
