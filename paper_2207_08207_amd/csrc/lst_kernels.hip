@@ -638,7 +638,9 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
 // quarter of the module's row-major pairs on its own (no block barrier per
 // round).  The count pass writes each quarter's count (md_part), from which
 // the fill starts each quarter at the module's offset plus the counts of the
-// quarters before it, so the module's MDs stay in row-major order.
+// quarters before it, so the module's MDs stay in row-major order; it also
+// keeps each quarter's first kMdQCache passing pairs, so the fill of a quarter
+// with no more than that copies them instead of testing every pair again.
 template <bool FILL>
 __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, DevGeom g) {
   static_assert(kWaves == 4, "one quarter of the pairs per wave");
@@ -661,12 +663,32 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
     const float rnup = 1.0f / (float)nup;
     const bool small = npair < (1L << 22);  // divmod22's range (always, below 2,048 hits per sensor)
     const long q0 = npair * wid / kWaves, q1 = npair * (wid + 1) / kWaves;  // this wave's quarter
-    int base = 0;
+    // the count pass keeps a quarter's first kMdQCache passing pairs (indices < 2^16)
+    const bool packable = nlo <= 0xffff && nup <= 0xffff;
+    unsigned *qcache = reinterpret_cast<unsigned *>(w.md_bcache) + ((long)m * kWaves + wid) * kMdQCache;
+    int base = 0, qn = 0;
     if (FILL) {
       base = gp(w.md_off)[m];
       for (int q = 0; q < wid; ++q) base += gp(w.md_part)[4 * m + q];
+      qn = gp(w.md_part)[4 * m + wid];
     }
-    for (long p0 = q0; p0 < q1; p0 += 64) {
+    const bool cached = FILL && packable && qn <= kMdQCache;
+    if (cached) {  // the quarter's MDs from the count pass's pairs, in the same order
+      for (int k = lane; k < qn; k += 64) {
+        const unsigned e = gp(qcache)[k];
+        const int i = (int)(e >> 16), j = (int)(e & 0xffffu);
+        const float4 hi = i < kMdStageBig ? s_lo[i] : gload(w.hpos, lo0 + i);
+        const float4 hj = j < kMdStageBig ? s_up[j] : gload(w.hpos, up0 + j);
+        const int pos = base + k;
+        if (pos < w.cap_md) {
+          gstore(w.md_hits, pos, make_int2(gp(w.hidx)[lo0 + i], gp(w.hidx)[up0 + j]));
+          gp(w.md_mod)[pos] = m;
+          gstore(w.md_pos, pos, hi);
+          put_stub(w, g, pos, md_stub(hi, hj, mi));
+        }
+      }
+    }
+    for (long p0 = q0; p0 < (cached ? q0 : q1); p0 += 64) {
       const long p = p0 + lane;
       bool pass = false;
       int i = 0, j = 0;
@@ -685,6 +707,10 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
         pass = md_pass(hi, hj, win, mi);
       }
       const unsigned long long bm = __ballot(pass);
+      if (!FILL && pass && packable) {
+        const int r = base + lanes_below(bm);
+        if (r < kMdQCache) gp(qcache)[r] = ((unsigned)i << 16) | (unsigned)j;
+      }
       if (FILL && pass) {
         const int pos = base + lanes_below(bm);
         if (pos < w.cap_md) {
@@ -1724,8 +1750,10 @@ __device__ __forceinline__ bool better(float su, const int *hu, float st, const 
 // MD, and u is judged there only if it shares at least two MDs with t and its
 // first MD in common with t's first four is that k-th one (so each pair is
 // judged once; a duplicate shares two of the five MDs, hence one of the first
-// four).  Flattened as in the T3/T5 searches: a wave takes 64 items, stages
-// their MDs in LDS and strides all (item, candidate) pairs with its lanes.
+// four).  Flattened as in the T3/T5 searches: a wave takes ipw items (64, or
+// 16 when one event alone leaves too few waves to hide the gathers' latency),
+// stages their MDs in LDS and strides all (item, candidate) pairs with its
+// lanes.
 // t5_keep starts at 1 (written by the fill); a strictly better duplicate
 // clears it (every writer writes 0).
 // Its LDS is dynamic, kT5DedupLds bytes per wave of the block, so that a tuned
@@ -1736,17 +1764,17 @@ struct T5DedupLds {
 };
 constexpr size_t kT5DedupLds = sizeof(T5DedupLds);
 
-__global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb) {
+__global__ __launch_bounds__(kBlock) void k_t5_dedup(const Ws *__restrict__ wb, int ipw) {
   extern __shared__ T5DedupLds s_dd[];
   const Ws &w = wb[blockIdx.y];
   const int n = uload(w.ctr + C_NT5);
   const int wv = wave_id(), lane = lane_id();
   const int wpb = blockDim.x >> 6;
   auto &S = s_dd[wv];
-  for (long p0 = ((long)blockIdx.x * wpb + wv) * 64; p0 < 4L * n; p0 += (long)gridDim.x * wpb * 64) {
+  for (long p0 = ((long)blockIdx.x * wpb + wv) * ipw; p0 < 4L * n; p0 += (long)gridDim.x * wpb * ipw) {
     const long item = p0 + lane;
     int cnt = 0;
-    if (item < 4L * n) {
+    if (lane < ipw && item < 4L * n) {
       const int t = (int)(item >> 2), k = (int)(item & 3);
       int mt[5];
 #pragma unroll
@@ -3037,7 +3065,10 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   });
   run([&] { scan(wb, B, SC_INC, b.cap_md, st); });
   run([&] { k_t5_inc_scatter<<<grid(b.cap_t5), kBlock, 0, st>>>(wb); });
-  run([&] { k_t5_dedup<<<gridwb((4L * b.cap_t5 + 63) / 64), tb, (tb / 64) * kT5DedupLds, st>>>(wb); });
+  run([&] {
+    const int ipw = B == 1 ? 16 : 64;
+    k_t5_dedup<<<gridwb((4L * b.cap_t5 + ipw - 1) / ipw), tb, (tb / 64) * kT5DedupLds, st>>>(wb, ipw);
+  });
   // a6: pLS
   run([&] {
     k_clear<<<grid(N + 1), kBlock, 0, st>>>(wb, FL_PH_CNT, FL_PH_CUR + 1);
