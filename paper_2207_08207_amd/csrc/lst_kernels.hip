@@ -549,7 +549,10 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
     const int lo0 = gp(w.boff)[2 * m], nlo = gp(w.boff)[2 * m + 1] - lo0;
     const int up0 = gp(w.boff)[2 * m + 1], nup = gp(w.boff)[2 * m + 2] - up0;
     const long npair = (long)nlo * nup;
-    if (npair > kMdBig) continue;  // k_md_big's
+    if (npair > kMdBig) {  // k_md_big's, listed for it (the list's order does not matter)
+      if (!FILL && lane == 0) gp(w.md_dense)[atomicAdd(w.ctr + C_NDENSE, 1)] = m;
+      continue;
+    }
     if (npair == 0) {
       if (!FILL && lane == 0) gp(w.md_cnt)[m] = 0;
       continue;
@@ -632,8 +635,9 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
   }
 }
 
-// The same for the modules with more than kMdBig pairs, one block (kBlock
-// threads) each, so that no single wave carries a dense module: the block
+// The same for the modules with more than kMdBig pairs (listed by the count
+// pass of k_md), one block (kBlock threads) each, so that no single wave
+// carries a dense module and no block walks the modules that are not dense: the block
 // stages both sensors' hits, and each of its four waves takes one consecutive
 // quarter of the module's row-major pairs on its own (no block barrier per
 // round).  The count pass writes each quarter's count (md_part), from which
@@ -649,7 +653,9 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
   __shared__ int s_part[kWaves];
   __shared__ float4 s_box[kWaves];
   const int wid = wave_id(), lane = lane_id();
-  for (int m = blockIdx.x; m < g.n_mod; m += gridDim.x) {
+  const int n_dense = uload(w.ctr + C_NDENSE);
+  for (int kd = blockIdx.x; kd < n_dense; kd += gridDim.x) {
+    const int m = uload(w.md_dense + kd);
     const int lo0 = gp(w.boff)[2 * m], nlo = gp(w.boff)[2 * m + 1] - lo0;
     const int up0 = gp(w.boff)[2 * m + 1], nup = gp(w.boff)[2 * m + 2] - up0;
     const long npair = (long)nlo * nup;
@@ -3030,9 +3036,9 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { k_hits_scatter<<<dim3((unsigned)std::max(1L, n_tiles), B), kBlock, kWaves * n_co * sizeof(int), st>>>(wb, M); });
   run([&] { k_bucket_sort<<<dim3((unsigned)n_co, B), 64 * kSortWaves, 0, st>>>(wb, M); });
   // a1: MD
-  run([&] {
-    k_md_big<false><<<dim3(share(1024, kBlock), B), kBlock, 0, st>>>(wb, g);
+  run([&] {  // the small modules' count lists the dense ones for k_md_big
     k_md<false><<<gridwb(M), tb, 0, st>>>(wb, g);
+    k_md_big<false><<<dim3(share(1024, kBlock), B), kBlock, 0, st>>>(wb, g);
   });
   run([&] { scan(wb, B, SC_MD, M, st); });
   run([&] {

@@ -17,6 +17,7 @@ enum Ctr : int {
   C_NLSOVF = 27,                 // MDs with more segments than the count pass caches
   C_NEXTHITS = 28,               // hits of the extended track-candidate collection
   C_EXT = 29,                    // 1 once the track extensions of the event are written
+  C_NDENSE = 30,                 // modules with more than kMdBig hit pairs (listed in md_dense)
   C_COUNT = 64
 };
 enum : int { ST_BAD_HIT = 1, ST_BAD_SEED = 2, ST_CAPACITY = 4 };
@@ -127,6 +128,7 @@ struct Ws {
   int *md_cache;     // per module: up to kMdCache passing pairs (lower << 16 | upper) of the count pass
   int *md_part;      // per dense module: MDs of each wave's quarter of its pairs (count pass)
   int *md_bcache;    // per dense module and quarter: up to kMdQCache passing pairs (lower << 16 | upper)
+  int *md_dense;     // the dense modules, listed (in any order) by the small-module MD count pass
   int2 *md_hits;    // input indices of the lower and upper hit
   int *md_mod;
   float4 *md_pos;   // anchor (lower hit) x, y, z, r
