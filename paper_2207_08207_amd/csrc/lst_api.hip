@@ -211,16 +211,20 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
     sj(SC_B5, t.b5_cnt, t.b5_off, nullptr, nbins, nbins, ct + C_NB5, nullptr, 0);
     sj(SC_LSOVF, t.ls_ovf_flag, t.ls_ovf_off, ct + C_NMD, 0, md, ct + C_NLSOVF, nullptr, 0);
     sj(SC_EXT, t.ext_cnt, t.ext_off, ct + C_NTC, 0, p5 + p3 + t5 + S, ct + C_NEXTHITS, nullptr, 0);
-    auto fj = [&](int id, int *p, long n) { t.fills[id] = FillJob{p, n}; };
+    // arrays indexed by MDs, triplets or quintuplets are cleared up to the built count
+    // (the clears run after it is known), not the capacity
+    auto fj = [&](int id, int *p, long n, const int *n_dev = nullptr, int mul = 1) {
+      t.fills[id] = FillJob{p, n, n_dev, mul};
+    };
     fj(FL_CTR, ct, C_COUNT);
-    fj(FL_INC_CNT, t.inc_cnt, md + 1);
-    fj(FL_INC_CUR, t.inc_cur, md + 1);
+    fj(FL_INC_CNT, t.inc_cnt, md + 1, ct + C_NMD);
+    fj(FL_INC_CUR, t.inc_cur, md + 1, ct + C_NMD);
     fj(FL_PH_CNT, t.ph_cnt, N + 1);
     fj(FL_PH_CUR, t.ph_cur, N + 1);
-    fj(FL_O3_BEST, reinterpret_cast<int *>(t.o3_best), 2 * (t3 + 1));
-    fj(FL_O5_BEST, reinterpret_cast<int *>(t.o5_best), 2 * (t5 + 1));
+    fj(FL_O3_BEST, reinterpret_cast<int *>(t.o3_best), 2 * (t3 + 1), ct + C_NT3, 2);
+    fj(FL_O5_BEST, reinterpret_cast<int *>(t.o5_best), 2 * (t5 + 1), ct + C_NT5, 2);
     fj(FL_SEED_USED, t.seed_used, S + 1);
-    fj(FL_T5_USED, t.t5_used, t5 + 1);
+    fj(FL_T5_USED, t.t5_used, t5 + 1, ct + C_NT5);
     fj(FL_B3_CNT, t.b3_cnt, nbins + 1);
     fj(FL_B3_CUR, t.b3_cur, nbins + 1);
     fj(FL_B5_CNT, t.b5_cnt, nbins + 1);

@@ -92,7 +92,8 @@ __global__ void k_clear(const Ws *__restrict__ wb, int j0, int j1) {
   const Ws &w = wb[blockIdx.y];
   for (int j = j0; j < j1; ++j) {
     int *p = w.fills[j].p;
-    const long n = w.fills[j].n;
+    long n = w.fills[j].n;
+    if (w.fills[j].n_dev) n = min(n, (long)w.fills[j].mul * ((long)uload(w.fills[j].n_dev) + 1));
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) p[i] = 0;
   }
 }

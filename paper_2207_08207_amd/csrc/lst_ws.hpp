@@ -69,9 +69,14 @@ enum ScanId : int {
   SC_F5, SC_F3, SC_FT5, SC_FPLS, SC_B3, SC_B5, SC_LSOVF, SC_EXT, SC_COUNT
 };
 // One array cleared to zero at the start of the chain.
+// n: the array's length; with n_dev, only its first mul * (*n_dev + 1)
+// entries (the device-side count of what it is indexed by, plus one) when
+// that is fewer.
 struct FillJob {
   int *p;
   long n;
+  const int *n_dev;
+  int mul;
 };
 enum FillId : int {
   FL_CTR, FL_INC_CNT, FL_INC_CUR, FL_PH_CNT, FL_PH_CUR, FL_O3_BEST,
