@@ -142,8 +142,8 @@ size_t workspace_layout(int n_mod, int n_hits, int n_seeds, const Caps &c, Ws *w
   const long tiles = (long)n_coarse((int)M) * n_hit_tiles(N);
   t.boff = I(2 * M + 1); t.tile_hist = I(tiles + 1); t.tile_off = I(tiles + 1);
   t.hcp = F4(N + 1); t.hidx = I(N + 1); t.hpos = F4(N + 1);
-  t.md_cnt = I(M + 1); t.md_off = I(M + 1); t.md_cache = I(kMdCache * M); t.md_part = I(4 * M);
-  t.md_bcache = I(4L * kMdQCache * M); t.md_dense = I(M + 1);
+  t.md_cnt = I(M + 1); t.md_off = I(M + 1); t.md_cache = I(kMdCache * M); t.md_part = I((long)kMdParts * M);
+  t.md_bcache = I((long)kMdParts * kMdQCache * M); t.md_dense = I(M + 1);
   t.md_hits = I2(md); t.md_mod = I(md); t.md_pos = F4(md); t.md_stub = F2(md); t.mod_disc = F4(M);
   t.ls_cnt = I(md + 1); t.ls_off = I(md + 1); t.ls_md = I2(ls); t.ls_beta = F2(ls); t.ls_opos = F4(ls); t.ls_oinf = I(ls);
   t.ls_cache = I(kLsCache * md);

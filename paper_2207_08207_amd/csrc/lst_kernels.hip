@@ -639,20 +639,24 @@ __global__ __launch_bounds__(kBlock) void k_md(const Ws *__restrict__ wb, DevGeo
 // The same for the modules with more than kMdBig pairs (listed by the count
 // pass of k_md), one block (kBlock threads) each, so that no single wave
 // carries a dense module and no block walks the modules that are not dense: the block
-// stages both sensors' hits, and each of its four waves takes one consecutive
-// quarter of the module's row-major pairs on its own (no block barrier per
-// round).  The count pass writes each quarter's count (md_part), from which
-// the fill starts each quarter at the module's offset plus the counts of the
-// quarters before it, so the module's MDs stay in row-major order; it also
-// keeps each quarter's first kMdQCache passing pairs, so the fill of a quarter
-// with no more than that copies them instead of testing every pair again.
+// (one wave per part: `parts` = blockDim.x / 64 <= kMdParts) stages both
+// sensors' hits, and each of its waves takes one consecutive part of the
+// module's row-major pairs on its own (no block barrier per round).  Sixteen
+// parts keep the densest module (~24,000 pairs on PU200) from setting the
+// kernel's end when a launch holds one event; over many events four parts
+// run faster.  The count pass writes each part's count (md_part), from which
+// the fill starts each part at the module's offset plus the counts of the
+// parts before it, so the module's MDs stay in row-major order; it also keeps
+// each part's first kMdParts * kMdQCache / parts passing pairs, so the fill of
+// a part with no more than that copies them instead of testing every pair
+// again.
 template <bool FILL>
-__global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, DevGeom g) {
-  static_assert(kWaves == 4, "one quarter of the pairs per wave");
+__global__ __launch_bounds__(64 * kMdParts) void k_md_big(const Ws *__restrict__ wb, DevGeom g) {
   const Ws &w = wb[blockIdx.y];
   __shared__ float4 s_lo[kMdStageBig], s_up[kMdStageBig];
-  __shared__ int s_part[kWaves];
-  __shared__ float4 s_box[kWaves];
+  __shared__ int s_part[kMdParts];
+  __shared__ float4 s_box[kMdParts];
+  const int parts = blockDim.x >> 6, qcap = kMdParts * kMdQCache / parts;
   const int wid = wave_id(), lane = lane_id();
   const int n_dense = uload(w.ctr + C_NDENSE);
   for (int kd = blockIdx.x; kd < n_dense; kd += gridDim.x) {
@@ -662,25 +666,25 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
     const long npair = (long)nlo * nup;
     if (npair <= kMdBig) continue;
     __syncthreads();  // the previous module's LDS reads are done
-    for (int k = threadIdx.x; k < nlo && k < kMdStageBig; k += kBlock) s_lo[k] = gload(w.hpos, lo0 + k);
-    for (int k = threadIdx.x; k < nup && k < kMdStageBig; k += kBlock) s_up[k] = gload(w.hpos, up0 + k);
+    for (int k = threadIdx.x; k < nlo && k < kMdStageBig; k += blockDim.x) s_lo[k] = gload(w.hpos, lo0 + k);
+    for (int k = threadIdx.x; k < nup && k < kMdStageBig; k += blockDim.x) s_up[k] = gload(w.hpos, up0 + k);
     __syncthreads();
     const float4 win = gload(g.win, m);
     const ModInfo mi{gp(g.info)[m]};
     const float rnup = 1.0f / (float)nup;
     const bool small = npair < (1L << 22);  // divmod22's range (always, below 2,048 hits per sensor)
-    const long q0 = npair * wid / kWaves, q1 = npair * (wid + 1) / kWaves;  // this wave's quarter
-    // the count pass keeps a quarter's first kMdQCache passing pairs (indices < 2^16)
+    const long q0 = npair * wid / parts, q1 = npair * (wid + 1) / parts;  // this wave's part
+    // the count pass keeps a part's first qcap passing pairs (indices < 2^16)
     const bool packable = nlo <= 0xffff && nup <= 0xffff;
-    unsigned *qcache = reinterpret_cast<unsigned *>(w.md_bcache) + ((long)m * kWaves + wid) * kMdQCache;
+    unsigned *qcache = reinterpret_cast<unsigned *>(w.md_bcache) + (long)m * kMdParts * kMdQCache + wid * qcap;
     int base = 0, qn = 0;
     if (FILL) {
       base = gp(w.md_off)[m];
-      for (int q = 0; q < wid; ++q) base += gp(w.md_part)[4 * m + q];
-      qn = gp(w.md_part)[4 * m + wid];
+      for (int q = 0; q < wid; ++q) base += gp(w.md_part)[(long)kMdParts * m + q];
+      qn = gp(w.md_part)[(long)kMdParts * m + wid];
     }
-    const bool cached = FILL && packable && qn <= kMdQCache;
-    if (cached) {  // the quarter's MDs from the count pass's pairs, in the same order
+    const bool cached = FILL && packable && qn <= qcap;
+    if (cached) {  // the part's MDs from the count pass's pairs, in the same order
       for (int k = lane; k < qn; k += 64) {
         const unsigned e = gp(qcache)[k];
         const int i = (int)(e >> 16), j = (int)(e & 0xffffu);
@@ -716,7 +720,7 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
       const unsigned long long bm = __ballot(pass);
       if (!FILL && pass && packable) {
         const int r = base + lanes_below(bm);
-        if (r < kMdQCache) gp(qcache)[r] = ((unsigned)i << 16) | (unsigned)j;
+        if (r < qcap) gp(qcache)[r] = ((unsigned)i << 16) | (unsigned)j;
       }
       if (FILL && pass) {
         const int pos = base + lanes_below(bm);
@@ -731,14 +735,18 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
     }
     if (!FILL) {
       if (lane == 0) {
-        gp(w.md_part)[4 * m + wid] = base;
+        gp(w.md_part)[(long)kMdParts * m + wid] = base;
         s_part[wid] = base;
       }
       __syncthreads();
-      if (threadIdx.x == 0) gp(w.md_cnt)[m] = s_part[0] + s_part[1] + s_part[2] + s_part[3];
+      if (threadIdx.x == 0) {
+        int c = 0;
+        for (int q = 0; q < parts; ++q) c += s_part[q];
+        gp(w.md_cnt)[m] = c;
+      }
     } else {
       float x0 = 3.0e38f, x1 = -3.0e38f, y0 = 3.0e38f, y1 = -3.0e38f;
-      for (int k = threadIdx.x; k < nlo; k += kBlock) {
+      for (int k = threadIdx.x; k < nlo; k += blockDim.x) {
         const float4 h = k < kMdStageBig ? s_lo[k] : gload(w.hpos, lo0 + k);
         x0 = fminf(x0, h.x); x1 = fmaxf(x1, h.x);
         y0 = fminf(y0, h.y); y1 = fmaxf(y1, h.y);
@@ -750,7 +758,7 @@ __global__ __launch_bounds__(kBlock) void k_md_big(const Ws *__restrict__ wb, De
       if (lane == 0) s_box[wid] = make_float4(x0, x1, y0, y1);
       __syncthreads();
       if (threadIdx.x == 0) {
-        for (int q = 1; q < kWaves; ++q) {
+        for (int q = 1; q < parts; ++q) {
           x0 = fminf(x0, s_box[q].x); x1 = fmaxf(x1, s_box[q].y);
           y0 = fminf(y0, s_box[q].z); y1 = fmaxf(y1, s_box[q].w);
         }
@@ -3036,14 +3044,15 @@ void enqueue_chain(const DevGeom &g, const Ws *wb, int B, const Ws &b, hipStream
   run([&] { scan(wb, B, SC_HITS, n_co * n_tiles, st); });
   run([&] { k_hits_scatter<<<dim3((unsigned)std::max(1L, n_tiles), B), kBlock, kWaves * n_co * sizeof(int), st>>>(wb, M); });
   run([&] { k_bucket_sort<<<dim3((unsigned)n_co, B), 64 * kSortWaves, 0, st>>>(wb, M); });
-  // a1: MD
+  // a1: MD (a dense module's block: kMdParts waves for a launch of one event, else 4)
+  const int md_big_threads = 64 * (B == 1 ? kMdParts : 4);
   run([&] {  // the small modules' count lists the dense ones for k_md_big
     k_md<false><<<gridwb(M), tb, 0, st>>>(wb, g);
-    k_md_big<false><<<dim3(share(1024, kBlock), B), kBlock, 0, st>>>(wb, g);
+    k_md_big<false><<<dim3(share(1024, md_big_threads), B), md_big_threads, 0, st>>>(wb, g);
   });
   run([&] { scan(wb, B, SC_MD, M, st); });
   run([&] {
-    k_md_big<true><<<dim3(share(1024, kBlock), B), kBlock, 0, st>>>(wb, g);
+    k_md_big<true><<<dim3(share(1024, md_big_threads), B), md_big_threads, 0, st>>>(wb, g);
     k_md<true><<<gridwb(M), tb, 0, st>>>(wb, g);
   });
   // a2: LS

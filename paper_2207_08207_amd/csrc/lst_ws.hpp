@@ -89,7 +89,8 @@ enum FillId : int {
 constexpr int kLsCache = 32;
 constexpr int kLsGroup = 16;  // most inner MDs per wave of the segment count pass
 constexpr int kMdCache = 32;  // MDs per module whose (lower, upper) pair the MD count pass keeps
-constexpr int kMdQCache = 32;  // the same per quarter of a dense module (k_md_big)
+constexpr int kMdParts = 16;   // waves of a dense module's block (k_md_big), one part of its pairs each
+constexpr int kMdQCache = 16;  // MDs per part of a dense module whose pair the MD count pass keeps
 constexpr int kT3Cache = 2;   // triplets per parent segment whose candidate the T3 count pass keeps
 constexpr int kT5Cache = 2;   // quintuplets per parent triplet whose candidate the T5 count pass keeps
 constexpr int kPt3Cache = 256;  // pT3 per seed (PU200 maximum ~190)
@@ -131,8 +132,8 @@ struct Ws {
   // mini-doublets
   int *md_cnt, *md_off;
   int *md_cache;     // per module: up to kMdCache passing pairs (lower << 16 | upper) of the count pass
-  int *md_part;      // per dense module: MDs of each wave's quarter of its pairs (count pass)
-  int *md_bcache;    // per dense module and quarter: up to kMdQCache passing pairs (lower << 16 | upper)
+  int *md_part;      // per dense module: MDs of each wave's part of its pairs (count pass)
+  int *md_bcache;    // per dense module and part: up to kMdQCache passing pairs (lower << 16 | upper)
   int *md_dense;     // the dense modules, listed (in any order) by the small-module MD count pass
   int2 *md_hits;    // input indices of the lower and upper hit
   int *md_mod;
