@@ -2077,10 +2077,13 @@ __device__ void mark_seed_bins(const Seed &sd, unsigned *mask, int *s_lo, int *s
       b0 = 0;
       b1 = kPhiBins - 1;
     } else {
+      // an anchor within d of the sample, at radius >= rin, is within asin(d / rin) of
+      // its azimuth; 2e-4 rad (1% of a bin) covers the rounding of these bin edges
+      // against phibin_of's
       const float hw = asinf(d / rin);
       const float ph = atan2f(y, x);
-      b0 = (int)floorf((ph - hw + (float)M_PI) / bw) - 1;
-      b1 = (int)floorf((ph + hw + (float)M_PI) / bw) + 1;
+      b0 = (int)floorf((ph - hw - 2e-4f + (float)M_PI) / bw);
+      b1 = (int)floorf((ph + hw + 2e-4f + (float)M_PI) / bw);
       if (b1 - b0 >= kPhiBins) { b0 = 0; b1 = kPhiBins - 1; }
     }
     // bins b0..b1 (fewer than kPhiBins, may wrap round) as at most two runs of
