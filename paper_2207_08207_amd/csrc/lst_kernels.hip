@@ -2004,14 +2004,21 @@ __device__ __forceinline__ int seed_key(const Ws &w, int s) {
   const int lb = (int)floorf((p[3] + 6.0f) * (1.0f / 1.5f));
   return (ph == ph ? phibin_of(ph) : 0) * 8 + (lb < 0 ? 0 : (lb > 7 ? 7 : lb));
 }
+constexpr int kSeedKeyLds = 10240;  // seeds whose key the ordering keeps in LDS (the rest recompute it)
 __global__ __launch_bounds__(1024) void k_seed_order(const Ws *__restrict__ wb) {
   __shared__ int s_cnt[kSeedKeys];
+  __shared__ unsigned short s_key[kSeedKeyLds];
   __shared__ int s_wave[16];
+  static_assert(kSeedKeys <= 65536, "a key fits 16 bits");
   const Ws &w = wb[blockIdx.y];
   const int S = w.n_seeds, t = threadIdx.x, lane = lane_id(), wv = t >> 6;
   for (int k = t; k < kSeedKeys; k += 1024) s_cnt[k] = 0;
   __syncthreads();
-  for (int s = t; s < S; s += 1024) atomicAdd(&s_cnt[seed_key(w, s)], 1);  // LDS
+  for (int s = t; s < S; s += 1024) {
+    const int key = seed_key(w, s);
+    if (s < kSeedKeyLds) s_key[s] = (unsigned short)key;
+    atomicAdd(&s_cnt[key], 1);  // LDS
+  }
   __syncthreads();
   // exclusive scan of the key counts: two keys per thread, then over the block
   static_assert(kSeedKeys == 2 * 1024, "two keys per thread");
@@ -2029,7 +2036,10 @@ __global__ __launch_bounds__(1024) void k_seed_order(const Ws *__restrict__ wb) 
   s_cnt[2 * t] = ex;
   s_cnt[2 * t + 1] = ex + c0;
   __syncthreads();
-  for (int s = t; s < S; s += 1024) gp(w.seed_order)[atomicAdd(&s_cnt[seed_key(w, s)], 1)] = s;  // LDS rank
+  for (int s = t; s < S; s += 1024) {
+    const int key = s < kSeedKeyLds ? (int)s_key[s] : seed_key(w, s);
+    gp(w.seed_order)[atomicAdd(&s_cnt[key], 1)] = s;  // LDS rank
+  }
 }
 
 // Marks, in the wave's bin mask, every (ring, azimuth) bin that can hold the
