@@ -4,8 +4,8 @@
 Every event goes through the whole chain (hit bucketing, MD, LS, T3, T5, T5
 duplicate removal, pLS, pT3/pT5, duplicate removal and cross-cleaning into
 track candidates), inputs already resident in HBM.  One step = one full
-round of the server: streams x max-batch events (8 x 16 = 128 by default),
-so K steps time 128 K events.  Forms measured:
+round of the server: streams x max-batch events (8 x 32 = 256 by default),
+so K steps time 256 K events.  Forms measured:
 
 * served (the headline `value`): the library's serving loop (streams x
   batches) with the K rounds' PU200-like seeded events available at once;
@@ -69,8 +69,9 @@ def parse():
     p.add_argument("--warmup", type=int, default=2, help="untimed server rounds before the timed ones")
     p.add_argument("--pool", type=int, default=12, help="distinct events cycled through")
     p.add_argument("--streams", type=int, default=8,
-                   help="server streams (8 x 16 measured 2,731 ev/s against 2,684 for 4 x 32 and ~2,560 for 4 x 16)")
-    p.add_argument("--max-batch", type=int, default=16, help="events per server launch sequence")
+                   help="server streams (8 x 32 measured 3,259 ev/s on one box against 3,060-3,138 for 8 x 16, "
+                        "3,095 for 12 x 16 and 3,028 for 16 x 8)")
+    p.add_argument("--max-batch", type=int, default=32, help="events per server launch sequence")
     p.add_argument("--rate", type=float, default=500.0, help="Poisson arrival rate of the trace [events/s]")
     p.add_argument("--trace", type=int, default=1000, help="requests in the open-loop trace (0: skip)")
     p.add_argument("--sweep", default="100,200,500,1000,2000",
@@ -362,6 +363,8 @@ def main():
     elapsed = time.perf_counter() - t0
     lst.lst_set_timed_site(-1)
     srv.close()
+    del srv  # its pool (a whole round of workspaces) goes back to the device before the other forms
+    torch.cuda.empty_cache()
     value = n_served / elapsed
     served_lat, launches, chain_served = [], {}, []
     for rid, arr, adm, done, ms, c in results:
