@@ -666,7 +666,11 @@ def main():
                 "launches": len(launches), "bytes_per_launch": int(tot_b / len(launches)),
                 "launch_ms": round(tot_s * 1e3 / len(launches), 4),
                 "events_per_launch": round(ev_per_launch, 2),
-                "traffic_source": None if tr is None else tr["profile"]}
+                "traffic_source": None if tr is None else tr["profile"],
+                # the kernel's VALU issue rate over the 2.0 per CU per clock of the FP32 peak, from
+                # the same recorded counter run (it is issue-bound, not HBM-bound)
+                "valu_issue_frac": None if tr is None else tr.get("valu_issue_frac"),
+                "valu_issue_source": None if tr is None else tr.get("counters_profile")}
     out = {
         "metric": "events/s + p50/p99 event latency, PU200-like synthetic, served vs plain, 1 GPU",
         "value": round(value, 3), "unit": "events/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
