@@ -1,0 +1,92 @@
+"""The triplet and quintuplet searches queue only the pairs that pass a pre-test
+in fast arithmetic: for a triplet, the curvature cut and the azimuth-z test of
+its three anchors (Section 2.3); for a quintuplet, the azimuth-z test of
+anchors 1, 3 and 5.  Both must let through every object the exact selection
+accepts.  This replays the pre-tests' formulas in IEEE float32 on the host
+(correctly rounded operations where the kernels use the hardware reciprocal
+and reciprocal square root, within a few ulp of them) and checks on a
+PU200-like event that every triplet and quintuplet of the oracle passes them;
+a dropped error term or a wrong factor rejects thousands of them.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from lstgen.events import make_event, geometry_for
+
+f32 = np.float32
+K_CURV_D = 0.299792458 * 3.8 / 100.0
+K_KMAX_CUT = f32(K_CURV_D / 0.8 * 1.01)
+K_TAU = f32(0.8)
+K_MARGIN, K_EPS = f32(1.001), f32(1e-6)
+K_THIRD = f32(1.0 / 3.0)
+D0 = f32(0.1)
+
+
+@pytest.fixture(scope="module")
+def objs():
+    geom = geometry_for("pu200_seeded")
+    ev = make_event("pu200_seeded", 5)
+    r = oracle.run(oracle.OracleGeometry(geom), ev, last=3)
+    t3, _, _ = r.stage(2)
+    t5, _, _ = r.stage(3)
+    x, y, z = ev.x.astype(f32), ev.y.astype(f32), ev.z.astype(f32)
+    endcap, is2s = geom.subdet == 1, geom.type == 1
+
+    def anchors(hits):  # anchors = the lower hit of each MD (even positions of the hit tuple)
+        h = hits[:, ::2]
+        P = np.stack([x[h], y[h], z[h], np.sqrt(x[h] * x[h] + y[h] * y[h])], -1)
+        m = ev.module[h]
+        ec, t2 = endcap[m], is2s[m]
+        hphi = np.where(t2, f32(0.0045), f32(0.005)).astype(f32)
+        hlong = np.where(t2, f32(2.5), f32(0.075)).astype(f32)
+        return P, dict(hphi=hphi, sig_t=np.where(ec, hphi + K_TAU * hlong, hphi).astype(f32),
+                       ez=np.where(ec, f32(0), hlong).astype(f32))
+    return anchors(t3), anchors(t5)
+
+
+def phiz_may_pass(P, Q, R, mp, mq, mr):
+    su = (P[:, 0] * Q[:, 1] - P[:, 1] * Q[:, 0]) / (P[:, 3] * Q[:, 3])
+    sv = (Q[:, 0] * R[:, 1] - Q[:, 1] * R[:, 0]) / (Q[:, 3] * R[:, 3])
+    dzpq, dzqr = Q[:, 2] - P[:, 2], R[:, 2] - Q[:, 2]
+    t1, t2 = su * dzqr, sv * dzpq
+    iP, iQ, iR = f32(1) / P[:, 3], f32(1) / Q[:, 3], f32(1) / R[:, 3]
+    ePQ = (mp["hphi"] * iP + mq["hphi"] * iQ) + D0 * np.abs(iP - iQ)
+    eQR = (mq["hphi"] * iQ + mr["hphi"] * iR) + D0 * np.abs(iQ - iR)
+    au, av, adpq, adqr = np.abs(su), np.abs(sv), np.abs(dzpq), np.abs(dzqr)
+    nl = (au * au + av * av) * K_THIRD
+    tol = ((adqr * ePQ + adpq * eQR) + (au * (mq["ez"] + mr["ez"]) + av * (mp["ez"] + mq["ez"]))) + \
+        nl * (au * adqr + av * adpq)
+    return np.abs(t1 - t2) <= (tol * K_MARGIN + K_EPS) * f32(1.00001) + f32(1e-5) * (np.abs(t1) + np.abs(t2))
+
+
+def curvature_may_pass(A, B, C, mA, mB, mC):
+    ux, uy = B[:, 0] - A[:, 0], B[:, 1] - A[:, 1]
+    wx, wy = C[:, 0] - A[:, 0], C[:, 1] - A[:, 1]
+    tx, ty = C[:, 0] - B[:, 0], C[:, 1] - B[:, 1]
+    k = ux * wy - uy * wx
+    lw2 = wx * wx + wy * wy
+    kap = (f32(2) * k) / (np.sqrt(ux * ux + uy * uy) * np.sqrt(lw2) * np.sqrt(tx * tx + ty * ty))
+    dk = (f32(4) * ((mA["sig_t"] + f32(2) * mB["sig_t"]) + mC["sig_t"])) / lw2
+    return np.abs(kap) <= (K_KMAX_CUT + dk) * f32(1.00001)
+
+
+def _pick(m, i):
+    return {k: v[:, i] for k, v in m.items()}
+
+
+def test_every_triplet_passes_its_pretest(objs):
+    (P, m), _ = objs
+    assert len(P) > 50000
+    A, B, C = P[:, 0], P[:, 1], P[:, 2]
+    mA, mB, mC = _pick(m, 0), _pick(m, 1), _pick(m, 2)
+    for name, ok in (("curvature", curvature_may_pass(A, B, C, mA, mB, mC)),
+                     ("azimuth-z", phiz_may_pass(A, B, C, mA, mB, mC))):
+        assert ok.all(), f"{name}: {np.count_nonzero(~ok)} of {len(ok)} triplets rejected"
+
+
+def test_every_quintuplet_passes_its_pretest(objs):
+    _, (P, m) = objs
+    assert len(P) > 5000
+    ok = phiz_may_pass(P[:, 0], P[:, 2], P[:, 4], _pick(m, 0), _pick(m, 2), _pick(m, 4))
+    assert ok.all(), f"{np.count_nonzero(~ok)} of {len(ok)} quintuplets rejected"
