@@ -6,7 +6,9 @@ accepts.  This replays the pre-tests' formulas in IEEE float32 on the host
 (correctly rounded operations where the kernels use the hardware reciprocal
 and reciprocal square root, within a few ulp of them) and checks on a
 PU200-like event that every triplet and quintuplet of the oracle passes them;
-a dropped error term or a wrong factor rejects thousands of them.
+a dropped error term or a wrong factor rejects thousands of them.  It also
+checks that the tests prune: of all (segment, segment) and (triplet, triplet)
+pairs sharing an MD, few pass.
 """
 import numpy as np
 import pytest
@@ -28,6 +30,8 @@ def objs():
     geom = geometry_for("pu200_seeded")
     ev = make_event("pu200_seeded", 5)
     r = oracle.run(oracle.OracleGeometry(geom), ev, last=3)
+    md, _, _ = r.stage(0)
+    ls, _, _ = r.stage(1)
     t3, _, _ = r.stage(2)
     t5, _, _ = r.stage(3)
     x, y, z = ev.x.astype(f32), ev.y.astype(f32), ev.z.astype(f32)
@@ -42,7 +46,27 @@ def objs():
         hlong = np.where(t2, f32(2.5), f32(0.075)).astype(f32)
         return P, dict(hphi=hphi, sig_t=np.where(ec, hphi + K_TAU * hlong, hphi).astype(f32),
                        ez=np.where(ec, f32(0), hlong).astype(f32))
-    return anchors(t3), anchors(t5)
+    # candidates of the searches: every pair of objects where the outer MD of the first
+    # is the inner MD of the second (two segments for a triplet, two triplets for a quintuplet)
+    key = {(int(a), int(b)): i for i, (a, b) in enumerate(md)}
+    seg = np.array([[key[(int(t[0]), int(t[1]))], key[(int(t[2]), int(t[3]))]] for t in ls])
+    tri = np.array([[key[(int(t[0]), int(t[1]))], key[(int(t[4]), int(t[5]))]] for t in t3])
+
+    def chained(first, last):
+        order = np.argsort(first, kind="stable")
+        cnt = np.bincount(first, minlength=len(md))
+        off = np.concatenate([[0], np.cumsum(cnt)])
+        ne = cnt[last]
+        i = np.repeat(np.arange(len(last)), ne)
+        j = order[np.repeat(off[last], ne) + np.arange(ne.sum()) - np.repeat(np.cumsum(ne) - ne, ne)]
+        return i, j
+
+    si, sj = chained(seg[:, 0], seg[:, 1])
+    ti, tj = chained(tri[:, 0], tri[:, 1])
+    lo = md[:, 0]
+    cands = dict(t3=(anchors(np.stack([lo[seg[si, 0]], lo[seg[si, 1]], lo[seg[sj, 1]]], 1).repeat(2, 1)), len(t3)),
+                 t5=(anchors(np.stack([lo[tri[ti, 0]], lo[tri[ti, 1]], lo[tri[tj, 1]]], 1).repeat(2, 1)), len(t5)))
+    return anchors(t3), anchors(t5), cands
 
 
 def phiz_may_pass(P, Q, R, mp, mq, mr):
@@ -76,7 +100,7 @@ def _pick(m, i):
 
 
 def test_every_triplet_passes_its_pretest(objs):
-    (P, m), _ = objs
+    (P, m), _, _ = objs
     assert len(P) > 50000
     A, B, C = P[:, 0], P[:, 1], P[:, 2]
     mA, mB, mC = _pick(m, 0), _pick(m, 1), _pick(m, 2)
@@ -86,7 +110,21 @@ def test_every_triplet_passes_its_pretest(objs):
 
 
 def test_every_quintuplet_passes_its_pretest(objs):
-    _, (P, m) = objs
+    _, (P, m), _ = objs
     assert len(P) > 5000
     ok = phiz_may_pass(P[:, 0], P[:, 2], P[:, 4], _pick(m, 0), _pick(m, 2), _pick(m, 4))
     assert ok.all(), f"{np.count_nonzero(~ok)} of {len(ok)} quintuplets rejected"
+
+
+def test_pretests_prune(objs):
+    """The triplet pre-test keeps under 5% of the segment pairs, the quintuplet's azimuth-z
+    test under half of the triplet pairs, and neither keeps fewer than the objects found."""
+    _, _, cands = objs
+    (P, m), n_t3 = cands["t3"]
+    assert len(P) > 20 * n_t3
+    A, B, C, mA, mB, mC = P[:, 0], P[:, 1], P[:, 2], _pick(m, 0), _pick(m, 1), _pick(m, 2)
+    kept = np.count_nonzero(curvature_may_pass(A, B, C, mA, mB, mC) & phiz_may_pass(A, B, C, mA, mB, mC))
+    assert n_t3 <= kept <= 0.05 * len(P), (kept, len(P), n_t3)
+    (P, m), n_t5 = cands["t5"]
+    kept = np.count_nonzero(phiz_may_pass(P[:, 0], P[:, 1], P[:, 2], _pick(m, 0), _pick(m, 1), _pick(m, 2)))
+    assert n_t5 <= kept <= 0.5 * len(P), (kept, len(P), n_t5)
