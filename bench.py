@@ -262,7 +262,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         log(f"bench.py: measures one GPU only; --gpus {args.gpus} is not supported "
-            "(events are independent; multi-GPU sharding by event is described in DESIGN.md)")
+            "(events are independent: several GPUs would each serve their own share of the events)")
         sys.exit(2)
     import numpy as np
     import torch
