@@ -2,11 +2,11 @@
 window, the inner MD's stub check and the pair pre-test before the exact
 selection) must let through every segment the exact selection accepts.  The
 kernels evaluate them with the hardware reciprocal and reciprocal square root
-(within a few ulp of the correctly rounded operations) and margins of about
-1e-4; this replays their formulas in IEEE float32 on the host, with correctly
-rounded operations, and checks on a PU200-like event that every segment of the
-oracle passes all of them, so a dropped term, a wrong sign or a margin on the
-wrong side fails here.  It also checks that the pair pre-test prunes: most pairs
+(within about 1 ulp of the correctly rounded operations) and margins of about
+1e-4; this replays their formulas in IEEE float32 on the host, with those
+operations correctly rounded, 4 ulp high and 4 ulp low, and checks on a
+PU200-like event that every segment of the oracle passes all of them, so a
+dropped term, a wrong sign or a margin on the wrong side fails here.  It also checks that the pair pre-test prunes: most pairs
 past the first two tests fail it (Section 2.2's stub and window cuts).
 """
 import numpy as np
@@ -19,6 +19,18 @@ f32 = np.float32
 K_HALF_KMAX = f32(0.299792458 * 3.8 / 100.0 / 0.8 / 2.0)
 K_MARGIN, K_EPS = f32(1.001), f32(1e-6)
 D0 = f32(0.1)
+# The hardware reciprocal and reciprocal square root are within about 1 ulp of the
+# correctly rounded results; the superset check runs with them exact and with each
+# of them 4 ulp high, then 4 ulp low.
+SCALES = (f32(1), f32(1 + 2.0 ** -21), f32(1 - 2.0 ** -21))
+
+
+def rcp(x, sc):
+    return (f32(1) / x) * sc
+
+
+def rsq(x, sc):
+    return (f32(1) / np.sqrt(x)) * sc
 
 
 @pytest.fixture(scope="module")
@@ -63,18 +75,18 @@ def _info(s, m):
     return ec, hphi, hlong, er
 
 
-def window_bound(A, ma, disc, mb, s):
+def window_bound(A, ma, disc, mb, s, sc=SCALES[0]):
     _, hphi_a, _, er_a = _info(s, ma)
     _, _, _, er_b = _info(s, mb)
     ub = K_HALF_KMAX * ((disc[:, 3] + disc[:, 2]) + er_b)
     ua = K_HALF_KMAX * (A[:, 3] - er_a)
     with np.errstate(invalid="ignore", divide="ignore"):
-        w = (ub - ua) / np.sqrt(f32(1) - ub * ub) + (D0 + hphi_a + f32(0.005)) / A[:, 3]
+        w = (ub - ua) * rsq(f32(1) - ub * ub, sc) + (D0 + hphi_a + f32(0.005)) * rcp(A[:, 3], sc)
     return np.where(ub < f32(0.99), (w * K_MARGIN + K_EPS) * f32(1.01) + f32(1e-6), f32(3e38)).astype(f32)
 
 
-def module_may_pass(A, disc, wm):
-    dn = np.abs(A[:, 0] * disc[:, 1] - A[:, 1] * disc[:, 0]) / A[:, 3]
+def module_may_pass(A, disc, wm, sc=SCALES[0]):
+    dn = np.abs(A[:, 0] * disc[:, 1] - A[:, 1] * disc[:, 0]) * rcp(A[:, 3], sc)
     return dn - disc[:, 2] <= (wm * (disc[:, 3] + disc[:, 2])) * f32(1.001) + f32(1e-4)
 
 
@@ -82,15 +94,15 @@ def window_may_pass(A, B, wm):
     return np.abs(A[:, 0] * B[:, 1] - A[:, 1] * B[:, 0]) <= wm * (A[:, 3] * B[:, 3])
 
 
-def stub_may_pass(st, ec, hphi, sn, sx, sy, il, dz, eang, rp):
+def stub_may_pass(st, ec, hphi, sn, sx, sy, il, dz, eang, rp, sc):
     sn2 = sn * sn
     with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
-        pred_b = (st[:, 1] * sn) / np.sqrt(f32(1) - sn2)
-        err_b = f32(2) * hphi + (f32(2) * st[:, 1]) * (eang + D0 / rp)
+        pred_b = (st[:, 1] * sn) * rsq(f32(1) - sn2, sc)
+        err_b = f32(2) * hphi + (f32(2) * st[:, 1]) * (eang + D0 * rcp(rp, sc))
         adz = np.abs(dz)
-        ds = st[:, 1] * (sx * sx + sy * sy) * il / adz
+        ds = st[:, 1] * (sx * sx + sy * sy) * il * rcp(adz, sc)
         pred_e = ds * sn
-        err_e = (f32(2) * hphi + f32(0.03) * np.abs(pred_e)) + ds * (eang + D0 / rp)
+        err_e = (f32(2) * hphi + f32(0.03) * np.abs(pred_e)) + ds * (eang + D0 * rcp(rp, sc))
     pred = np.where(ec, pred_e, pred_b)
     err = np.where(ec, err_e, err_b)
     ok = np.abs(st[:, 0] - pred) <= (err * K_MARGIN) * f32(1.0001) + K_EPS + f32(1e-4) * np.abs(pred)
@@ -98,49 +110,50 @@ def stub_may_pass(st, ec, hphi, sn, sx, sy, il, dz, eang, rp):
     return np.where(ec & ~(adz > 0), False, ok)
 
 
-def inner_stub_may_pass(A, B, sa, ma, mb, s):
+def inner_stub_may_pass(A, B, sa, ma, mb, s, sc=SCALES[0]):
     ec_a, hphi_a, hlong_a, _ = _info(s, ma)
     ec_b, hphi_b, hlong_b, _ = _info(s, mb)
     sx, sy = B[:, 0] - A[:, 0], B[:, 1] - A[:, 1]
-    il = f32(1) / np.sqrt(sx * sx + sy * sy)
-    sn = (B[:, 0] * sy - B[:, 1] * sx) / B[:, 3] * il
+    il = rsq(sx * sx + sy * sy, sc)
+    sn = (B[:, 0] * sy - B[:, 1] * sx) * rcp(B[:, 3], sc) * il
     eang = (np.where(ec_a, hlong_a, hphi_a) + np.where(ec_b, hlong_b, hphi_b)) * il
-    return stub_may_pass(sa, ec_a, hphi_a, sn, sx, sy, il, B[:, 2] - A[:, 2], eang, A[:, 3])
+    return stub_may_pass(sa, ec_a, hphi_a, sn, sx, sy, il, B[:, 2] - A[:, 2], eang, A[:, 3], sc)
 
 
-def pair_may_pass(A, B, sb, ma, mb, s):
+def pair_may_pass(A, B, sb, ma, mb, s, sc=SCALES[0]):
     ec_a, hphi_a, hlong_a, er_a = _info(s, ma)
     ec_b, hphi_b, hlong_b, er_b = _info(s, mb)
     dr = B[:, 3] - A[:, 3]
     ok = (dr > 0) & (A[:, 0] * B[:, 0] + A[:, 1] * B[:, 1] > 0)
     ub = K_HALF_KMAX * (B[:, 3] + er_b)
     ua = K_HALF_KMAX * (A[:, 3] - er_a)
-    ra, rb = f32(1) / A[:, 3], f32(1) / B[:, 3]
+    ra, rb = rcp(A[:, 3], sc), rcp(B[:, 3], sc)
     with np.errstate(invalid="ignore"):
-        wv = (ub - ua) / np.sqrt(f32(1) - ub * ub) + (D0 * dr) * (ra * rb) + hphi_a * ra + hphi_b * rb
+        wv = (ub - ua) * rsq(f32(1) - ub * ub, sc) + (D0 * dr) * (ra * rb) + hphi_a * ra + hphi_b * rb
     c = A[:, 0] * B[:, 1] - A[:, 1] * B[:, 0]
     win = np.abs(c) <= ((wv * K_MARGIN + K_EPS) * (A[:, 3] * B[:, 3])) * f32(1.0001) + f32(1e-6)
     ok &= np.where(ub < f32(0.99), win, True)
     sx, sy = B[:, 0] - A[:, 0], B[:, 1] - A[:, 1]
-    il = f32(1) / np.sqrt(sx * sx + sy * sy)
-    sn = (A[:, 0] * sy - A[:, 1] * sx) / A[:, 3] * il
+    il = rsq(sx * sx + sy * sy, sc)
+    sn = (A[:, 0] * sy - A[:, 1] * sx) * rcp(A[:, 3], sc) * il
     eang = (np.where(ec_a, hlong_a, hphi_a) + np.where(ec_b, hlong_b, hphi_b)) * il
-    return ok & stub_may_pass(sb, ec_b, hphi_b, sn, sx, sy, il, B[:, 2] - A[:, 2], eang, B[:, 3])
+    return ok & stub_may_pass(sb, ec_b, hphi_b, sn, sx, sy, il, B[:, 2] - A[:, 2], eang, B[:, 3], sc)
 
 
-def test_every_segment_passes_every_pretest(seg):
+@pytest.mark.parametrize("sc", SCALES)
+def test_every_segment_passes_every_pretest(seg, sc):
     s = seg
     a, b = s["la"], s["lb"]
     A, B = s["A"][a], s["A"][b]
     ma, mb = s["mod"][a], s["mod"][b]
     disc = s["disc"][mb]
     assert len(a) > 400000
-    wm = window_bound(A, ma, disc, mb, s)
+    wm = window_bound(A, ma, disc, mb, s, sc)
     checks = {
-        "module window bound": module_may_pass(A, disc, wm),
+        "module window bound": module_may_pass(A, disc, wm, sc),
         "candidate window": window_may_pass(A, B, wm),
-        "inner stub": inner_stub_may_pass(A, B, s["st"][a], ma, mb, s),
-        "pair": pair_may_pass(A, B, s["st"][b], ma, mb, s),
+        "inner stub": inner_stub_may_pass(A, B, s["st"][a], ma, mb, s, sc),
+        "pair": pair_may_pass(A, B, s["st"][b], ma, mb, s, sc),
     }
     for name, ok in checks.items():
         assert ok.all(), f"{name}: {np.count_nonzero(~ok)} of {len(ok)} segments rejected"

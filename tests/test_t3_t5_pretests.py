@@ -3,8 +3,8 @@ in fast arithmetic: for a triplet, the curvature cut and the azimuth-z test of
 its three anchors (Section 2.3); for a quintuplet, the azimuth-z test of
 anchors 1, 3 and 5.  Both must let through every object the exact selection
 accepts.  This replays the pre-tests' formulas in IEEE float32 on the host
-(correctly rounded operations where the kernels use the hardware reciprocal
-and reciprocal square root, within a few ulp of them) and checks on a
+(the hardware reciprocal and reciprocal square root of the kernels taken
+correctly rounded, 4 ulp high and 4 ulp low) and checks on a
 PU200-like event that every triplet and quintuplet of the oracle passes them;
 a dropped error term or a wrong factor rejects thousands of them.  It also
 checks that the tests prune: of all (segment, segment) and (triplet, triplet)
@@ -69,12 +69,26 @@ def objs():
     return anchors(t3), anchors(t5), cands
 
 
-def phiz_may_pass(P, Q, R, mp, mq, mr):
-    su = (P[:, 0] * Q[:, 1] - P[:, 1] * Q[:, 0]) / (P[:, 3] * Q[:, 3])
-    sv = (Q[:, 0] * R[:, 1] - Q[:, 1] * R[:, 0]) / (Q[:, 3] * R[:, 3])
+# The hardware reciprocal and reciprocal square root are within about 1 ulp of the
+# correctly rounded results; every replay runs with them exact and with each of them
+# 4 ulp high, then 4 ulp low.
+SCALES = (f32(1), f32(1 + 2.0 ** -21), f32(1 - 2.0 ** -21))
+
+
+def rcp(x, sc):
+    return (f32(1) / x) * sc
+
+
+def rsq(x, sc):
+    return (f32(1) / np.sqrt(x)) * sc
+
+
+def phiz_may_pass(P, Q, R, mp, mq, mr, sc=SCALES[0]):
+    su = (P[:, 0] * Q[:, 1] - P[:, 1] * Q[:, 0]) * rcp(P[:, 3] * Q[:, 3], sc)
+    sv = (Q[:, 0] * R[:, 1] - Q[:, 1] * R[:, 0]) * rcp(Q[:, 3] * R[:, 3], sc)
     dzpq, dzqr = Q[:, 2] - P[:, 2], R[:, 2] - Q[:, 2]
     t1, t2 = su * dzqr, sv * dzpq
-    iP, iQ, iR = f32(1) / P[:, 3], f32(1) / Q[:, 3], f32(1) / R[:, 3]
+    iP, iQ, iR = rcp(P[:, 3], sc), rcp(Q[:, 3], sc), rcp(R[:, 3], sc)
     ePQ = (mp["hphi"] * iP + mq["hphi"] * iQ) + D0 * np.abs(iP - iQ)
     eQR = (mq["hphi"] * iQ + mr["hphi"] * iR) + D0 * np.abs(iQ - iR)
     au, av, adpq, adqr = np.abs(su), np.abs(sv), np.abs(dzpq), np.abs(dzqr)
@@ -84,14 +98,14 @@ def phiz_may_pass(P, Q, R, mp, mq, mr):
     return np.abs(t1 - t2) <= (tol * K_MARGIN + K_EPS) * f32(1.00001) + f32(1e-5) * (np.abs(t1) + np.abs(t2))
 
 
-def curvature_may_pass(A, B, C, mA, mB, mC):
+def curvature_may_pass(A, B, C, mA, mB, mC, sc=SCALES[0]):
     ux, uy = B[:, 0] - A[:, 0], B[:, 1] - A[:, 1]
     wx, wy = C[:, 0] - A[:, 0], C[:, 1] - A[:, 1]
     tx, ty = C[:, 0] - B[:, 0], C[:, 1] - B[:, 1]
     k = ux * wy - uy * wx
     lw2 = wx * wx + wy * wy
-    kap = (f32(2) * k) / (np.sqrt(ux * ux + uy * uy) * np.sqrt(lw2) * np.sqrt(tx * tx + ty * ty))
-    dk = (f32(4) * ((mA["sig_t"] + f32(2) * mB["sig_t"]) + mC["sig_t"])) / lw2
+    kap = (f32(2) * k) * (rsq(ux * ux + uy * uy, sc) * rsq(lw2, sc) * rsq(tx * tx + ty * ty, sc))
+    dk = (f32(4) * ((mA["sig_t"] + f32(2) * mB["sig_t"]) + mC["sig_t"])) * rcp(lw2, sc)
     return np.abs(kap) <= (K_KMAX_CUT + dk) * f32(1.00001)
 
 
@@ -99,20 +113,22 @@ def _pick(m, i):
     return {k: v[:, i] for k, v in m.items()}
 
 
-def test_every_triplet_passes_its_pretest(objs):
+@pytest.mark.parametrize("sc", SCALES)
+def test_every_triplet_passes_its_pretest(objs, sc):
     (P, m), _, _ = objs
     assert len(P) > 50000
     A, B, C = P[:, 0], P[:, 1], P[:, 2]
     mA, mB, mC = _pick(m, 0), _pick(m, 1), _pick(m, 2)
-    for name, ok in (("curvature", curvature_may_pass(A, B, C, mA, mB, mC)),
-                     ("azimuth-z", phiz_may_pass(A, B, C, mA, mB, mC))):
+    for name, ok in (("curvature", curvature_may_pass(A, B, C, mA, mB, mC, sc)),
+                     ("azimuth-z", phiz_may_pass(A, B, C, mA, mB, mC, sc))):
         assert ok.all(), f"{name}: {np.count_nonzero(~ok)} of {len(ok)} triplets rejected"
 
 
-def test_every_quintuplet_passes_its_pretest(objs):
+@pytest.mark.parametrize("sc", SCALES)
+def test_every_quintuplet_passes_its_pretest(objs, sc):
     _, (P, m), _ = objs
     assert len(P) > 5000
-    ok = phiz_may_pass(P[:, 0], P[:, 2], P[:, 4], _pick(m, 0), _pick(m, 2), _pick(m, 4))
+    ok = phiz_may_pass(P[:, 0], P[:, 2], P[:, 4], _pick(m, 0), _pick(m, 2), _pick(m, 4), sc)
     assert ok.all(), f"{np.count_nonzero(~ok)} of {len(ok)} quintuplets rejected"
 
 
