@@ -19,7 +19,7 @@ f32 = np.float32
 K_HALF_KMAX = f32(0.299792458 * 3.8 / 100.0 / 0.8 / 2.0)
 K_MARGIN, K_EPS = f32(1.001), f32(1e-6)
 D0 = f32(0.1)
-# The hardware reciprocal and reciprocal square root are within about 1 ulp of the
+# The hardware reciprocal and reciprocal square root are within 1 ulp of the
 # correctly rounded results; the superset check runs with them exact and with each
 # of them 4 ulp high, then 4 ulp low.
 SCALES = (f32(1), f32(1 + 2.0 ** -21), f32(1 - 2.0 ** -21))

@@ -69,7 +69,7 @@ def objs():
     return anchors(t3), anchors(t5), cands
 
 
-# The hardware reciprocal and reciprocal square root are within about 1 ulp of the
+# The hardware reciprocal and reciprocal square root are within 1 ulp of the
 # correctly rounded results; every replay runs with them exact and with each of them
 # 4 ulp high, then 4 ulp low.
 SCALES = (f32(1), f32(1 + 2.0 ** -21), f32(1 - 2.0 ** -21))
